@@ -1,0 +1,546 @@
+/*
+ * lb_oracle.c -- FP64 CPU oracle of the hybrid lattice-Boltzmann scheme with
+ * the integral nonlinear Maxwell (nlM) constitutive equation of
+ * Papenkort & Voigtmann, "Lattice Boltzmann simulations of a viscoelastic
+ * shear-thinning fluid" (arXiv:1504.06123).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU path.  Only
+ * the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * load it; the product path never does.  It shares no source, header, table
+ * or helper with the GPU path.
+ *
+ * Style: plain loops, doubles everywhere, one function per step of the
+ * scheme, in the order the paper describes them.  Nothing is fused, blocked
+ * or reordered.  The readings taken where the paper is silent or ambiguous
+ * are stated next to the code they affect.
+ *
+ * Per time step t (state: populations n(t) after streaming, the stress of
+ * the previous step sigma^{t-1}, the history ring, the strain prefix
+ * Gamma_t):
+ *   1. density and momentum  rho = sum n_i,  j = sum c_i n_i
+ *   2. force density  f = rho*g + div sigma^{t-1}
+ *   3. velocity  u = (j + f/2)/rho                        (Eq. hydrofields)
+ *   4. velocity gradient kappa_ab = d_b u_a by 2nd-order differences, shear
+ *      rate s = kappa_xy and r = sqrt(II_D)              (Sec. II, Sec. III)
+ *   5. push (s_t, r_t, Gamma_t) into the ring, Gamma_{t+1} = Gamma_t + s_t
+ *   6. history integral (Eq. gitt with Eq. nlmax) -> sigma^t
+ *   7. BGK collision with the forcing term (Eq. bodyforce, f^ex part)
+ *   8. streaming with halfway bounce-back walls at y = -1/2 and y = ly-1/2.
+ *
+ * Parity status: every function below is pinned by the CPU test suite
+ * (closed forms, moment identities, polynomial exactness, recursion
+ * equivalence, conservation, symmetry, the Newtonian Poiseuille solution).
+ * The coupled nonlinear transient as a whole has no closed form; it is
+ * pinned only through its components and invariants.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* D2Q9 lattice (Sec. III): c_0 = 0, c_1..4 = (+-1,0),(0,+-1), c_5..8 the     */
+/* diagonals; weights 4/9, 1/9, 1/36; c_s^2 = 1/3 in lattice units.          */
+/* The numbering of the directions is not given in the paper; this one is    */
+/* the oracle's own.                                                          */
+/* ------------------------------------------------------------------------ */
+static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double WT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                             1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const double CS2 = 1.0 / 3.0;
+
+void orc_lattice(int *cx, int *cy, double *w, int *opp)
+{
+    for (int i = 0; i < 9; ++i) {
+        cx[i] = CX[i];
+        cy[i] = CY[i];
+        w[i] = WT[i];
+        opp[i] = OPP[i];
+    }
+}
+
+/* Node index: x fastest. */
+static int idx(int lx, int x, int y) { return y * lx + x; }
+static int wrap(int x, int lx) { return ((x % lx) + lx) % lx; }
+
+/* ------------------------------------------------------------------------ */
+/* Step 7a: equilibrium (Sec. III, second-order D2Q9 form).  The printed      */
+/* formula is garbled (a stray parenthesis, u_{i alpha}); the reading is the  */
+/* standard                                                                   */
+/*   n_i^eq = a_i rho [1 + c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2)].        */
+/* ------------------------------------------------------------------------ */
+void orc_equilibrium(double rho, double ux, double uy, double *neq)
+{
+    double uu = ux * ux + uy * uy;
+    for (int i = 0; i < 9; ++i) {
+        double cu = CX[i] * ux + CY[i] * uy;
+        neq[i] = WT[i] * rho *
+                 (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 7b: forcing term, the f^ex part of Eq. (bodyforce) with             */
+/* d_t(delta rho) = 0:                                                        */
+/*   F_i = a_i (1 - 1/(2 tau_LB)) [ c_a f_a / cs2                             */
+/*          + (c_a c_b - cs2 delta_ab)(u_b f_a + u_a f_b) / (2 cs2^2) ].      */
+/* Written with the tensor contraction exactly as printed.                   */
+/* ------------------------------------------------------------------------ */
+void orc_force_term(double tau_lb, double ux, double uy, double fx, double fy,
+                    double *F)
+{
+    double u[2] = {ux, uy};
+    double f[2] = {fx, fy};
+    double pre = 1.0 - 1.0 / (2.0 * tau_lb);
+    for (int i = 0; i < 9; ++i) {
+        double c[2] = {(double)CX[i], (double)CY[i]};
+        double lin = (c[0] * f[0] + c[1] * f[1]) / CS2;
+        double quad = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                double q = c[a] * c[b] - (a == b ? CS2 : 0.0);
+                quad += q * (u[b] * f[a] + u[a] * f[b]);
+            }
+        F[i] = WT[i] * pre * (lin + quad / (2.0 * CS2 * CS2));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 7: BGK collision plus forcing (Sec. III):                             */
+/*   n*_i = n_i - (n_i - n_i^eq(rho,u)) / tau_LB + F_i.                      */
+/* ------------------------------------------------------------------------ */
+void orc_collide(double tau_lb, const double *n, double rho, double ux,
+                 double uy, double fx, double fy, double *nstar)
+{
+    double neq[9], F[9];
+    orc_equilibrium(rho, ux, uy, neq);
+    orc_force_term(tau_lb, ux, uy, fx, fy, F);
+    for (int i = 0; i < 9; ++i)
+        nstar[i] = n[i] - (n[i] - neq[i]) / tau_lb + F[i];
+}
+
+/* Step 1: zeroth and first moments of the populations at one node. */
+void orc_density_momentum(const double *n, double *rho, double *jx, double *jy)
+{
+    double r = 0.0, a = 0.0, b = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        r += n[i];
+        a += CX[i] * n[i];
+        b += CY[i] * n[i];
+    }
+    *rho = r;
+    *jx = a;
+    *jy = b;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 4: velocity gradient kappa_ab = d_b u_a (kappa = (grad v)^T, Sec. I)  */
+/* with second-order finite differences (Sec. III).  d/dx: periodic central.  */
+/* d/dy: central in the interior; at the wall-adjacent rows the 3-point       */
+/* second-order stencil through the no-slip wall value u = 0 at y = -1/2      */
+/* (resp. y = ly - 1/2):                                                      */
+/*   d_y u(0) = u(0) + u(1)/3,   d_y u(ly-1) = -u(ly-1) - u(ly-2)/3.         */
+/* The paper says only "second-order finite difference"; the wall stencil is  */
+/* the oracle's reading.  Arrays are [ly][lx].                               */
+/* ------------------------------------------------------------------------ */
+static double ddy(const double *u, int lx, int ly, int x, int y)
+{
+    if (y == 0)
+        return u[idx(lx, x, 0)] + u[idx(lx, x, 1)] / 3.0;
+    if (y == ly - 1)
+        return -u[idx(lx, x, ly - 1)] - u[idx(lx, x, ly - 2)] / 3.0;
+    return 0.5 * (u[idx(lx, x, y + 1)] - u[idx(lx, x, y - 1)]);
+}
+
+static double ddx(const double *u, int lx, int x, int y)
+{
+    return 0.5 * (u[idx(lx, wrap(x + 1, lx), y)] - u[idx(lx, wrap(x - 1, lx), y)]);
+}
+
+void orc_velocity_gradient(int lx, int ly, const double *ux, const double *uy,
+                           double *kxx, double *kxy, double *kyx, double *kyy)
+{
+    for (int y = 0; y < ly; ++y)
+        for (int x = 0; x < lx; ++x) {
+            int k = idx(lx, x, y);
+            kxx[k] = ddx(ux, lx, x, y);
+            kxy[k] = ddy(ux, lx, ly, x, y);
+            kyx[k] = ddx(uy, lx, x, y);
+            kyy[k] = ddy(uy, lx, ly, x, y);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local shear rate (Sec. II): gamma_dot^2 = II_D = (1/2) tr D^2 with         */
+/* D = kappa + kappa^T (no factor 1/2 in D, as printed).                     */
+/* ------------------------------------------------------------------------ */
+double orc_shear_rate(double kxx, double kxy, double kyx, double kyy)
+{
+    double D[2][2] = {{kxx + kxx, kxy + kyx}, {kyx + kxy, kyy + kyy}};
+    double tr = 0.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            tr += D[a][b] * D[b][a];
+    return sqrt(0.5 * tr);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 2: divergence of the stress, f_a = d_b sigma_ab, entering the force   */
+/* density of Eq. (ns).  d/dx periodic central; d/dy central in the interior  */
+/* and the one-sided 3-point second-order stencil at the first and last rows  */
+/*   d_y s(0) = (-3 s0 + 4 s1 - s2)/2,  d_y s(L-1) = (3 s_{L-1} - 4 s_{L-2}   */
+/*   + s_{L-3})/2.                                                            */
+/* syy may be NULL (zero).                                                    */
+/* ------------------------------------------------------------------------ */
+static double ddy_onesided(const double *s, int lx, int ly, int x, int y)
+{
+    if (y == 0)
+        return 0.5 * (-3.0 * s[idx(lx, x, 0)] + 4.0 * s[idx(lx, x, 1)] -
+                      s[idx(lx, x, 2)]);
+    if (y == ly - 1)
+        return 0.5 * (3.0 * s[idx(lx, x, ly - 1)] - 4.0 * s[idx(lx, x, ly - 2)] +
+                      s[idx(lx, x, ly - 3)]);
+    return 0.5 * (s[idx(lx, x, y + 1)] - s[idx(lx, x, y - 1)]);
+}
+
+void orc_stress_divergence(int lx, int ly, const double *sxx, const double *sxy,
+                           const double *syy, double *fx, double *fy)
+{
+    for (int y = 0; y < ly; ++y)
+        for (int x = 0; x < lx; ++x) {
+            int k = idx(lx, x, y);
+            fx[k] = ddx(sxx, lx, x, y) + ddy_onesided(sxy, lx, ly, x, y);
+            fy[k] = ddx(sxy, lx, x, y) +
+                    (syy ? ddy_onesided(syy, lx, ly, x, y) : 0.0);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 8: streaming n_i(r + c_i, t+1) = n*_i(r, t) (Sec. III collision-and-  */
+/* streaming rule), x periodic.  A population that would leave through a     */
+/* wall (y < 0 or y >= ly) is reflected into the opposite direction at the   */
+/* node it left (halfway bounce-back).  Arrays are [9][ly][lx].              */
+/* ------------------------------------------------------------------------ */
+void orc_stream(int lx, int ly, const double *nstar, double *nout)
+{
+    int N = lx * ly;
+    for (int y = 0; y < ly; ++y)
+        for (int x = 0; x < lx; ++x)
+            for (int i = 0; i < 9; ++i) {
+                double v = nstar[i * N + idx(lx, x, y)];
+                int yy = y + CY[i];
+                if (yy < 0 || yy >= ly)
+                    nout[OPP[i] * N + idx(lx, x, y)] = v;
+                else
+                    nout[i * N + idx(lx, wrap(x + CX[i], lx), yy)] = v;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 6: the history integral of Eq. (gitt) with the modulus of           */
+/* Eq. (nlmax), reduced to simple shear.                                      */
+/*                                                                            */
+/* For unidirectional flow kappa = [[0,s],[0,0]] is nilpotent, so the         */
+/* time-ordered product of Eq. (eeval) collapses to E = [[1,g],[0,1]] with    */
+/* the accumulated strain g = Gamma_t - Gamma_t', and the Finger-tensor rate  */
+/* of Sec. III, -d_t' B = E kappa(t') E^T + (E kappa(t') E^T)^T, becomes      */
+/* s(t') [[2 g, 1], [1, 0]].  Hence                                           */
+/*   sigma_xy = sum_k w_k s G_k,  sigma_xx = sum_k w_k 2 s g G_k,            */
+/*   sigma_yy = 0,  with  G_k = G_inf exp(-k/tau) exp(-k r(t')/gamma_c).      */
+/* The damping rate uses the shear rate at the past time t' (Eq. nlmax; the  */
+/* stray "dt'" inside the printed modulus is read as a typo).  The          */
+/* trapezoidal rule (Sec. III) is applied with fixed weights over the full    */
+/* window of n_hist entries: w = 1/2 at the newest (k = 0) and oldest        */
+/* (k = n_hist - 1) entry, 1 elsewhere; entries older than the start of the  */
+/* run are zero (stress-free rest state before t = 0, Eq. maxwell).          */
+/*                                                                            */
+/* Inputs are by age k = t - t' for k < n_live (n_live <= n_hist): s, r and   */
+/* the accumulated strain dgam_k = Gamma_t - Gamma_{t-k}.                    */
+/* ------------------------------------------------------------------------ */
+void orc_history_sum(int n_hist, int n_live, const double *s_age,
+                     const double *r_age, const double *dgam_age, double g_inf,
+                     double tau_m, double gamma_c, double *sxy, double *sxx)
+{
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < n_live && k < n_hist; ++k) {
+        double w = (k == 0 || k == n_hist - 1) ? 0.5 : 1.0;
+        double G = g_inf * exp(-(double)k / tau_m) *
+                   exp(-(double)k * r_age[k] / gamma_c);
+        a += w * s_age[k] * G;
+        b += w * 2.0 * s_age[k] * dgam_age[k] * G;
+    }
+    *sxy = a;
+    *sxx = b;
+}
+
+/* Same sum from the shear history alone (all n_hist ages given, zeros for   */
+/* times before the run).  The strain prefix is built the way the scheme      */
+/* keeps it: Gamma grows from the oldest entry forward, Gamma_{t'+1} =        */
+/* Gamma_{t'} + s(t') (exclusive prefix, Eq. eeval: the newest factor of E    */
+/* is exp(kappa(t - dt) dt), the oldest exp(kappa(t') dt)).                  */
+void orc_history_sum_ages(int n_hist, const double *s_age, const double *r_age,
+                          double g_inf, double tau_m, double gamma_c,
+                          double *sxy, double *sxx)
+{
+    double *gam = (double *)malloc(sizeof(double) * (size_t)n_hist);
+    double *dg = (double *)malloc(sizeof(double) * (size_t)n_hist);
+    /* gam[k] = Gamma at time t - k, taking Gamma = 0 at the oldest entry. */
+    gam[n_hist - 1] = 0.0;
+    for (int k = n_hist - 1; k > 0; --k)
+        gam[k - 1] = gam[k] + s_age[k];
+    for (int k = 0; k < n_hist; ++k)
+        dg[k] = gam[0] - gam[k];
+    orc_history_sum(n_hist, n_hist, s_age, r_age, dg, g_inf, tau_m, gamma_c,
+                    sxy, sxx);
+    free(gam);
+    free(dg);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One channel: state and time loop.                                          */
+/* ------------------------------------------------------------------------ */
+typedef struct orc_channel {
+    int lx, ly, N, n_hist;
+    double tau_lb, g_inf, tau_m, gamma_c, gx, gy;
+    long t;          /* completed steps */
+    int has_out;     /* outputs below belong to step t-1 */
+    double *n;       /* [9][N] populations n(t), after streaming */
+    double *sig_xy;  /* [N] sigma_xy of the last completed step (sigma^{t-1}) */
+    double *sig_xx;  /* [N] sigma_xx of the last completed step */
+    double *ring_s;  /* [n_hist][N] shear rate s(t'), slot t' mod n_hist */
+    double *ring_r;  /* [n_hist][N] r(t') = sqrt(II_D(t')) */
+    double *ring_g;  /* [n_hist][N] Gamma_{t'} */
+    double *gam;     /* [N] Gamma_t */
+    /* outputs of the last completed step */
+    double *rho_o, *ux_o, *uy_o, *kap_o; /* kap_o: [4][N] kxx,kxy,kyx,kyy */
+    /* scratch */
+    double *nstar, *fx, *fy, *jx, *jy, *sxx_div, *new_xy, *new_xx;
+    double *s_age, *r_age, *dg_age;
+} orc_channel;
+
+static double *zalloc(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
+
+orc_channel *orc_create(int lx, int ly, double tau_lb, double g_inf,
+                        double tau_m, double gamma_c, int n_hist, double gx,
+                        double gy, const double *u0)
+{
+    if (lx < 1 || ly < 3 || n_hist < 2 || !(tau_lb > 0.5))
+        return NULL;
+    orc_channel *c = (orc_channel *)calloc(1, sizeof(orc_channel));
+    size_t N = (size_t)lx * (size_t)ly;
+    c->lx = lx;
+    c->ly = ly;
+    c->N = (int)N;
+    c->n_hist = n_hist;
+    c->tau_lb = tau_lb;
+    c->g_inf = g_inf;
+    c->tau_m = tau_m;
+    c->gamma_c = gamma_c;
+    c->gx = gx;
+    c->gy = gy;
+    c->t = 0;
+    c->n = zalloc(9 * N);
+    c->sig_xy = zalloc(N);
+    c->sig_xx = zalloc(N);
+    c->ring_s = zalloc((size_t)n_hist * N);
+    c->ring_r = zalloc((size_t)n_hist * N);
+    c->ring_g = zalloc((size_t)n_hist * N);
+    c->gam = zalloc(N);
+    c->rho_o = zalloc(N);
+    c->ux_o = zalloc(N);
+    c->uy_o = zalloc(N);
+    c->kap_o = zalloc(4 * N);
+    c->nstar = zalloc(9 * N);
+    c->fx = zalloc(N);
+    c->fy = zalloc(N);
+    c->jx = zalloc(N);
+    c->jy = zalloc(N);
+    c->sxx_div = zalloc(N);
+    c->new_xy = zalloc(N);
+    c->new_xx = zalloc(N);
+    c->s_age = zalloc((size_t)n_hist);
+    c->r_age = zalloc((size_t)n_hist);
+    c->dg_age = zalloc((size_t)n_hist);
+    /* Initial state: n_i = n_i^eq(rho = 1, u0), i.e. a_i at rest. */
+    for (size_t k = 0; k < N; ++k) {
+        double neq[9];
+        double ux = u0 ? u0[k] : 0.0;
+        double uy = u0 ? u0[N + k] : 0.0;
+        orc_equilibrium(1.0, ux, uy, neq);
+        for (int i = 0; i < 9; ++i)
+            c->n[i * N + k] = neq[i];
+    }
+    return c;
+}
+
+void orc_destroy(orc_channel *c)
+{
+    if (!c)
+        return;
+    double *bufs[] = {c->n,      c->sig_xy, c->sig_xx, c->ring_s, c->ring_r,
+                      c->ring_g, c->gam,    c->rho_o,  c->ux_o,   c->uy_o,
+                      c->kap_o,  c->nstar,  c->fx,     c->fy,     c->jx,
+                      c->jy,     c->sxx_div, c->new_xy, c->new_xx, c->s_age,
+                      c->r_age,  c->dg_age};
+    for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i)
+        free(bufs[i]);
+    free(c);
+}
+
+void orc_set_force(orc_channel *c, double gx, double gy)
+{
+    c->gx = gx;
+    c->gy = gy;
+}
+
+long orc_time(const orc_channel *c) { return c->t; }
+
+static void one_step(orc_channel *c)
+{
+    const int lx = c->lx, ly = c->ly, N = c->N, H = c->n_hist;
+    const long t = c->t;
+    double *kxx = c->kap_o, *kxy = c->kap_o + N, *kyx = c->kap_o + 2 * N,
+           *kyy = c->kap_o + 3 * N;
+
+    /* 1. density and momentum */
+    for (int k = 0; k < N; ++k) {
+        double nk[9];
+        for (int i = 0; i < 9; ++i)
+            nk[i] = c->n[i * N + k];
+        orc_density_momentum(nk, &c->rho_o[k], &c->jx[k], &c->jy[k]);
+    }
+    /* 2. force density: rho g + div sigma^{t-1} (sigma_yy = 0) */
+    orc_stress_divergence(lx, ly, c->sig_xx, c->sig_xy, NULL, c->fx, c->fy);
+    for (int k = 0; k < N; ++k) {
+        c->fx[k] += c->rho_o[k] * c->gx;
+        c->fy[k] += c->rho_o[k] * c->gy;
+    }
+    /* 3. velocity with the half-force shift */
+    for (int k = 0; k < N; ++k) {
+        c->ux_o[k] = (c->jx[k] + 0.5 * c->fx[k]) / c->rho_o[k];
+        c->uy_o[k] = (c->jy[k] + 0.5 * c->fy[k]) / c->rho_o[k];
+    }
+    /* 4. velocity gradient and shear rates */
+    orc_velocity_gradient(lx, ly, c->ux_o, c->uy_o, kxx, kxy, kyx, kyy);
+    /* 5. push entry t = (s_t, r_t, Gamma_t) */
+    long slot = t % H;
+    for (int k = 0; k < N; ++k) {
+        c->ring_s[slot * N + k] = kxy[k];
+        c->ring_r[slot * N + k] = orc_shear_rate(kxx[k], kxy[k], kyx[k], kyy[k]);
+        c->ring_g[slot * N + k] = c->gam[k];
+    }
+    /* 6. history integral at every node */
+    int n_live = (t + 1 < H) ? (int)(t + 1) : H;
+    for (int k = 0; k < N; ++k) {
+        for (int a = 0; a < n_live; ++a) {
+            long sl = (t - a) % H;
+            c->s_age[a] = c->ring_s[sl * N + k];
+            c->r_age[a] = c->ring_r[sl * N + k];
+            c->dg_age[a] = c->gam[k] - c->ring_g[sl * N + k];
+        }
+        orc_history_sum(H, n_live, c->s_age, c->r_age, c->dg_age, c->g_inf,
+                        c->tau_m, c->gamma_c, &c->new_xy[k], &c->new_xx[k]);
+    }
+    for (int k = 0; k < N; ++k)
+        c->gam[k] += kxy[k];
+    /* 7. collision */
+    for (int k = 0; k < N; ++k) {
+        double nk[9], ns[9];
+        for (int i = 0; i < 9; ++i)
+            nk[i] = c->n[i * N + k];
+        orc_collide(c->tau_lb, nk, c->rho_o[k], c->ux_o[k], c->uy_o[k],
+                    c->fx[k], c->fy[k], ns);
+        for (int i = 0; i < 9; ++i)
+            c->nstar[i * N + k] = ns[i];
+    }
+    /* 8. streaming */
+    orc_stream(lx, ly, c->nstar, c->n);
+    memcpy(c->sig_xy, c->new_xy, sizeof(double) * (size_t)N);
+    memcpy(c->sig_xx, c->new_xx, sizeof(double) * (size_t)N);
+    c->t = t + 1;
+    c->has_out = 1;
+}
+
+void orc_step(orc_channel *c, long n_steps)
+{
+    for (long i = 0; i < n_steps; ++i)
+        one_step(c);
+}
+
+/* Readouts refer to the last completed step; -1 before the first step and
+ * after a state load (the loaded state carries no step outputs). */
+int orc_fields(const orc_channel *c, double *rho, double *ux, double *uy)
+{
+    if (!c->has_out)
+        return -1;
+    size_t b = sizeof(double) * (size_t)c->N;
+    if (rho) memcpy(rho, c->rho_o, b);
+    if (ux) memcpy(ux, c->ux_o, b);
+    if (uy) memcpy(uy, c->uy_o, b);
+    return 0;
+}
+
+/* sigma_xy and the first normal-stress difference N1 = sigma_xx - sigma_yy. */
+int orc_stress(const orc_channel *c, double *sxy, double *n1)
+{
+    if (!c->has_out)
+        return -1;
+    size_t b = sizeof(double) * (size_t)c->N;
+    if (sxy) memcpy(sxy, c->sig_xy, b);
+    if (n1) memcpy(n1, c->sig_xx, b); /* sigma_yy = 0 in simple shear */
+    return 0;
+}
+
+int orc_grad(const orc_channel *c, double *kappa)
+{
+    if (!c->has_out)
+        return -1;
+    memcpy(kappa, c->kap_o, sizeof(double) * 4 * (size_t)c->N);
+    return 0;
+}
+
+/* Total mass sum_i n_i over the lattice for the current populations. */
+double orc_mass(const orc_channel *c)
+{
+    double m = 0.0;
+    for (long k = 0; k < 9L * c->N; ++k)
+        m += c->n[k];
+    return m;
+}
+
+/* State exchange.  Populations are n(t) after streaming, [9][ly][lx];      */
+/* sig_* is sigma^{t-1}; the ring is slot-major [n_hist][N] with slot        */
+/* t' mod n_hist; gam is Gamma_t.  Any pointer may be NULL (left unchanged). */
+void orc_get_state(const orc_channel *c, double *n, double *sig_xy,
+                   double *sig_xx, double *ring_s, double *ring_r,
+                   double *ring_g, double *gam, long *t)
+{
+    size_t N = (size_t)c->N, R = (size_t)c->n_hist * N;
+    if (n) memcpy(n, c->n, sizeof(double) * 9 * N);
+    if (sig_xy) memcpy(sig_xy, c->sig_xy, sizeof(double) * N);
+    if (sig_xx) memcpy(sig_xx, c->sig_xx, sizeof(double) * N);
+    if (ring_s) memcpy(ring_s, c->ring_s, sizeof(double) * R);
+    if (ring_r) memcpy(ring_r, c->ring_r, sizeof(double) * R);
+    if (ring_g) memcpy(ring_g, c->ring_g, sizeof(double) * R);
+    if (gam) memcpy(gam, c->gam, sizeof(double) * N);
+    if (t) *t = c->t;
+}
+
+void orc_set_state(orc_channel *c, const double *n, const double *sig_xy,
+                   const double *sig_xx, const double *ring_s,
+                   const double *ring_r, const double *ring_g,
+                   const double *gam, long t)
+{
+    size_t N = (size_t)c->N, R = (size_t)c->n_hist * N;
+    if (n) memcpy(c->n, n, sizeof(double) * 9 * N);
+    if (sig_xy) memcpy(c->sig_xy, sig_xy, sizeof(double) * N);
+    if (sig_xx) memcpy(c->sig_xx, sig_xx, sizeof(double) * N);
+    if (ring_s) memcpy(c->ring_s, ring_s, sizeof(double) * R);
+    if (ring_r) memcpy(c->ring_r, ring_r, sizeof(double) * R);
+    if (ring_g) memcpy(c->ring_g, ring_g, sizeof(double) * R);
+    if (gam) memcpy(c->gam, gam, sizeof(double) * N);
+    c->t = t;
+    c->has_out = 0;
+}

@@ -1,0 +1,490 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks one step of the oracle against something other than the
+oracle itself: constants the paper prints, defining moment identities,
+polynomial exactness of the stencils, closed forms of the history integral,
+an independent recursion, conservation laws, symmetries, and the Newtonian
+channel solution.  A plausible mistake in any step (dropped term, wrong sign
+or index, transposed operand) fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _paper():
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# Lattice constants (Sec. III)
+# --------------------------------------------------------------------------
+
+def test_lattice_matches_printed_d2q9():
+    p = _paper()
+    cx, cy, w, opp = oracle.lattice()
+    vel = p["d2q9_velocities"]["value"]
+    wts = p["d2q9_weights"]["value"]
+    got = {(int(a), int(b)): float(c) for a, b, c in zip(cx, cy, w)}
+    for cls in ("rest", "axis", "diagonal"):
+        for v in vel[cls]:
+            assert got[tuple(v)] == pytest.approx(wts[cls], abs=1e-16)
+    assert len(got) == 9
+    for i in range(9):
+        assert cx[opp[i]] == -cx[i] and cy[opp[i]] == -cy[i]
+    # second moment of the weights fixes c_s^2 (isotropy of D2Q9)
+    cs2 = p["sound_speed_squared"]["value"]
+    assert np.sum(w * cx * cx) == pytest.approx(cs2, abs=1e-16)
+    assert np.sum(w * cx * cy) == pytest.approx(0.0, abs=1e-16)
+    assert np.sum(w) == pytest.approx(1.0, abs=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Equilibrium and forcing (Sec. III): defining moments
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(5))
+def test_equilibrium_moments(seed):
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + 0.1 * rng.standard_normal()
+    u = 0.05 * rng.standard_normal(2)
+    cx, cy, _, _ = oracle.lattice()
+    neq = oracle.equilibrium(rho, u[0], u[1])
+    cs2 = 1.0 / 3.0
+    assert neq.sum() == pytest.approx(rho, rel=1e-14)
+    assert (cx * neq).sum() == pytest.approx(rho * u[0], abs=1e-15)
+    assert (cy * neq).sum() == pytest.approx(rho * u[1], abs=1e-15)
+    c = np.stack([cx, cy])
+    for a in range(2):
+        for b in range(2):
+            pi = (c[a] * c[b] * neq).sum()
+            want = rho * cs2 * (a == b) + rho * u[a] * u[b]
+            assert pi == pytest.approx(want, abs=1e-15)
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.9, 1.0, 1.7])
+def test_force_term_moments(tau):
+    rng = np.random.default_rng(7)
+    u = 0.05 * rng.standard_normal(2)
+    f = 1e-4 * rng.standard_normal(2)
+    cx, cy, _, _ = oracle.lattice()
+    F = oracle.force_term(tau, u[0], u[1], f[0], f[1])
+    pre = 1.0 - 1.0 / (2.0 * tau)
+    c = np.stack([cx, cy])
+    assert abs(F.sum()) < 1e-19
+    for a in range(2):
+        assert (c[a] * F).sum() == pytest.approx(pre * f[a], rel=1e-13)
+        for b in range(2):
+            want = pre * (u[a] * f[b] + u[b] * f[a])
+            assert (c[a] * c[b] * F).sum() == pytest.approx(want, abs=1e-20)
+
+
+def test_collision_conserves_mass_and_adds_force_momentum():
+    """With u = (j + f/2)/rho (Eq. hydrofields) one collision changes the
+    momentum by exactly f and leaves the mass unchanged."""
+    rng = np.random.default_rng(3)
+    cx, cy, w, _ = oracle.lattice()
+    for tau in (0.7, 1.0, 1.4):
+        n = w * (1.0 + 0.05 * rng.standard_normal(9))
+        f = 1e-3 * rng.standard_normal(2)
+        rho, jx, jy = oracle.density_momentum(n)
+        ux, uy = (jx + f[0] / 2) / rho, (jy + f[1] / 2) / rho
+        ns = oracle.collide(tau, n, rho, ux, uy, f[0], f[1])
+        assert ns.sum() == pytest.approx(rho, rel=1e-15)
+        assert (cx * ns).sum() == pytest.approx(jx + f[0], abs=1e-16)
+        assert (cy * ns).sum() == pytest.approx(jy + f[1], abs=1e-16)
+
+
+# --------------------------------------------------------------------------
+# Streaming with bounce-back walls
+# --------------------------------------------------------------------------
+
+def test_stream_moves_and_reflects():
+    lx, ly = 5, 4
+    cx, cy, _, opp = oracle.lattice()
+    for i in range(9):
+        for (x, y) in [(0, 0), (2, 1), (4, 3), (3, 2)]:
+            ns = np.zeros((9, ly, lx))
+            ns[i, y, x] = 1.0
+            out = oracle.stream(ns)
+            yy = y + cy[i]
+            if 0 <= yy < ly:
+                assert out[i, yy, (x + cx[i]) % lx] == 1.0
+            else:
+                assert out[opp[i], y, x] == 1.0
+            assert out.sum() == 1.0
+
+
+def test_stream_is_a_permutation():
+    rng = np.random.default_rng(0)
+    ns = rng.permutation(9 * 3 * 7).astype(float).reshape(9, 3, 7)
+    out = oracle.stream(ns)
+    assert np.array_equal(np.sort(out.ravel()), np.sort(ns.ravel()))
+
+
+# --------------------------------------------------------------------------
+# Finite-difference stencils: exact on quadratics
+# --------------------------------------------------------------------------
+
+def test_velocity_gradient_exact_on_wall_quadratics():
+    """A quadratic vanishing at both halfway walls y = -1/2, ly - 1/2 is
+    differentiated exactly at every row, including the wall rows."""
+    lx, ly = 6, 9
+    y = np.arange(ly)[:, None] * np.ones((1, lx))
+    a, b = 1.7e-3, -0.6e-3
+    ux = a * (y + 0.5) * (ly - 0.5 - y)
+    uy = b * (y + 0.5) * (ly - 0.5 - y)
+    kxx, kxy, kyx, kyy = oracle.velocity_gradient(ux, uy)
+    d = (ly - 1 - 2 * y)
+    np.testing.assert_allclose(kxy, a * d, rtol=0, atol=1e-17)
+    np.testing.assert_allclose(kyy, b * d, rtol=0, atol=1e-17)
+    assert np.abs(kxx).max() == 0 and np.abs(kyx).max() == 0
+
+
+def test_velocity_gradient_x_is_periodic_central():
+    lx, ly = 8, 5
+    x = np.arange(lx)[None, :] * np.ones((ly, 1))
+    k = 2 * math.pi / lx
+    ux = np.sin(k * x)
+    uy = 0.3 * np.cos(k * x)
+    kxx, kxy, kyx, kyy = oracle.velocity_gradient(ux, uy)
+    np.testing.assert_allclose(kxx, math.sin(k) * np.cos(k * x), atol=1e-15)
+    np.testing.assert_allclose(kyx, -0.3 * math.sin(k) * np.sin(k * x), atol=1e-15)
+    # y-constant field: zero interior y-derivative; at the wall rows the
+    # quadratic through the wall value 0 gives +-4/3 of the field value
+    assert np.abs(kxy[1:-1]).max() == 0 and np.abs(kyy[1:-1]).max() == 0
+    np.testing.assert_allclose(kxy[0], 4.0 / 3.0 * ux[0], atol=1e-15)
+    np.testing.assert_allclose(kxy[-1], -4.0 / 3.0 * ux[-1], atol=1e-15)
+
+
+def test_stress_divergence_exact_on_quadratics():
+    lx, ly = 4, 7
+    y = np.arange(ly)[:, None] * np.ones((1, lx))
+    sxy = 2e-4 + 3e-5 * y - 7e-6 * y * y
+    sxx = np.zeros((ly, lx))
+    fx, fy = oracle.stress_divergence(sxx, sxy)
+    np.testing.assert_allclose(fx, 3e-5 - 14e-6 * y, rtol=0, atol=1e-18)
+    assert np.abs(fy).max() == 0.0
+    # x-dependence enters f_x through sigma_xx and f_y through sigma_xy
+    x = np.arange(lx)[None, :] * np.ones((ly, 1))
+    k = 2 * math.pi / lx
+    fx, fy = oracle.stress_divergence(np.cos(k * x), np.sin(k * x))
+    np.testing.assert_allclose(fx, -math.sin(k) * np.sin(k * x), atol=1e-15)
+    np.testing.assert_allclose(fy, math.sin(k) * np.cos(k * x), atol=1e-15)
+
+
+def test_shear_rate_invariants():
+    """II_D = (1/2) tr D^2 with D = kappa + kappa^T (Sec. II)."""
+    assert oracle.shear_rate(0, 3e-3, 0, 0) == pytest.approx(3e-3, rel=1e-15)
+    assert oracle.shear_rate(0, -3e-3, 0, 0) == pytest.approx(3e-3, rel=1e-15)
+    # planar extension diag(e, -e): II_D = 4 e^2
+    assert oracle.shear_rate(2e-3, 0, 0, -2e-3) == pytest.approx(4e-3, rel=1e-15)
+    # rigid rotation carries no shear rate (frame indifference)
+    assert oracle.shear_rate(0, 5e-3, -5e-3, 0) == 0.0
+
+
+# --------------------------------------------------------------------------
+# History integral: closed forms, limits, recursion
+# --------------------------------------------------------------------------
+
+G, TAU, GC = 1e-3, 100.0, 0.1
+
+
+def _const_history(n_hist, t, s):
+    """Age arrays for constant shear s switched on at t' = 0."""
+    live = min(t + 1, n_hist)
+    s_age = np.zeros(n_hist)
+    s_age[:live] = s
+    r_age = np.abs(s_age)
+    return s_age, r_age
+
+
+@pytest.mark.parametrize("s", [1e-4, -2e-3, 5e-2])
+@pytest.mark.parametrize("t", [0, 1, 7, 300])
+def test_history_constant_shear_untruncated(s, t):
+    """t < N_h - 1: sigma_xy = G s [(1 - q^{t+1})/(1 - q) - 1/2],
+    N1 = 2 G s^2 q (1 - (t+1) q^t + t q^{t+1}) / (1 - q)^2."""
+    n_hist = 1000
+    s_age, r_age = _const_history(n_hist, t, s)
+    sxy, n1 = oracle.history_sum_ages(s_age, r_age, G, TAU, GC)
+    lam = 1.0 / TAU + abs(s) / GC
+    q = math.exp(-lam)
+    want_xy = G * s * ((1 - q ** (t + 1)) / (1 - q) - 0.5)
+    want_n1 = 2 * G * s * s * q * (1 - (t + 1) * q ** t + t * q ** (t + 1)) / (1 - q) ** 2
+    assert sxy == pytest.approx(want_xy, rel=1e-12)
+    assert n1 == pytest.approx(want_n1, rel=1e-10, abs=1e-30)
+
+
+@pytest.mark.parametrize("n_hist", [2, 3, 50, 1000])
+def test_history_constant_shear_truncated(n_hist):
+    """t >= N_h - 1, n = N_h - 1: sigma_xy = G s (1+q)(1-q^n) / (2(1-q)),
+    N1 = 2 G s^2 [sum_{k<=n} k q^k - n q^n / 2]."""
+    s = 3e-3
+    s_age = np.full(n_hist, s)
+    sxy, n1 = oracle.history_sum_ages(s_age, np.abs(s_age), G, TAU, GC)
+    lam = 1.0 / TAU + s / GC
+    q = math.exp(-lam)
+    n = n_hist - 1
+    want_xy = G * s * (1 + q) * (1 - q ** n) / (2 * (1 - q))
+    # sum_{k=1}^{n} k q^k in closed form
+    skq = q * (1 - (n + 1) * q ** n + n * q ** (n + 1)) / (1 - q) ** 2
+    want_n1 = 2 * G * s * s * (skq - 0.5 * n * q ** n)
+    assert sxy == pytest.approx(want_xy, rel=1e-12)
+    assert n1 == pytest.approx(want_n1, rel=1e-11)
+
+
+def test_history_steady_state_matches_instantaneous_nlm():
+    """Long-time constant shear reproduces the steady nlM of Eq. (inlM):
+    sigma_xy = G tau_M s and N1 = 2 G tau_M^2 s^2 with
+    tau_M = 1/(1/tau + |s|/gamma_c), up to the trapezoid factors
+    (lam/2)coth(lam/2) and (lam/2)^2/sinh^2(lam/2) (both 1 + O(lam^2))."""
+    n_hist = 20000
+    for s in (1e-5, 1e-4, 1e-3):
+        s_age = np.full(n_hist, s)
+        sxy, n1 = oracle.history_sum_ages(s_age, np.abs(s_age), G, TAU, GC)
+        lam = 1.0 / TAU + s / GC
+        tau_m = 1.0 / lam
+        fac_xy = (lam / 2) / math.tanh(lam / 2)
+        fac_n1 = (lam / 2) ** 2 / math.sinh(lam / 2) ** 2
+        assert sxy == pytest.approx(G * tau_m * s * fac_xy, rel=1e-12)
+        assert n1 == pytest.approx(2 * G * tau_m ** 2 * s * s * fac_n1, rel=1e-9)
+        assert abs(fac_xy - 1) < lam ** 2 / 11 and abs(fac_n1 - 1) < lam ** 2 / 11
+
+
+def test_history_maxwell_relation_and_yield_stress():
+    """Small shear: sigma/s -> eta = G tau (Maxwell relation, Sec. I).
+    Glassy limit tau -> infinity, s >> gamma_c/tau: sigma_xy -> G gamma_c
+    (yield stress of the model, Sec. IV.A)."""
+    p = _paper()
+    n_hist = 30000
+    s = 1e-7
+    s_age = np.full(n_hist, s)
+    sxy, _ = oracle.history_sum_ages(s_age, np.abs(s_age), G, TAU, GC)
+    assert sxy / s == pytest.approx(G * TAU, rel=1e-4)
+    gc = p["gamma_c"]["value"]
+    s = 1e-3   # lam = s/gamma_c = 0.01, trapezoid factor 1 + lam^2/12
+    s_age = np.full(n_hist, s)
+    sxy, _ = oracle.history_sum_ages(s_age, np.abs(s_age), G, 1e9, gc)
+    assert sxy == pytest.approx(G * gc, rel=2e-5)
+
+
+def test_history_linear_maxwell_startup():
+    """Linear Maxwell model, Eq. (maxwell), at constant shear from t = 0:
+    sigma(t) = G tau s (1 - exp(-t/tau)).  The discrete sum differs by the
+    endpoint weight at t' = 0 (at most G s/2 exp(-t/tau)) and by the
+    trapezoid factor (1/2tau) coth(1/2tau) = 1 + O(1/tau^2)."""
+    n_hist = 5000
+    s = 1e-3
+    tau = 100.0
+    for t in (10, 100, 400, 2000):
+        s_age, _ = _const_history(n_hist, t, s)
+        sxy, _ = oracle.history_sum_ages(s_age, np.zeros(n_hist), G, tau, math.inf)
+        cont = G * tau * s * (1 - math.exp(-t / tau))
+        bound = 0.5 * G * s * math.exp(-t / tau) + 0.5 * G * s + G * tau * s / (12 * tau ** 2)
+        assert abs(sxy - cont) <= bound
+    # t -> infinity: sigma = G s (1/2) coth(1/(2 tau)); relative to G tau s
+    s_age = np.full(n_hist, s)
+    sxy, _ = oracle.history_sum_ages(s_age, np.zeros(n_hist), G, tau, math.inf)
+    want = G * tau * s * (0.5 / tau) / math.tanh(0.5 / tau) * (1 - math.exp(-(n_hist - 1) / tau))
+    assert sxy == pytest.approx(want, rel=1e-6)
+    assert sxy / (G * tau * s) - 1 == pytest.approx(1.0 / (12 * tau ** 2), rel=1e-2)
+
+
+def _recursive_ucm(s_seq, q, n_hist):
+    """Independent O(1)-per-step recursions for the linear (UCM) case:
+    R_t = sum_{k<N} q^k s_{t-k} = q R_{t-1} + s_t - q^N s_{t-N},
+    P_t = sum_{k<N} q^k s_{t-k} gamma_{t,t-k}
+        = q (P_{t-1} + s_{t-1} R_{t-1}) - q^N s_{t-N} gamma_{t,t-N}.
+    The half weights at k = 0 and k = N - 1 are applied afterwards."""
+    T = len(s_seq)
+    R = P = 0.0
+    Gam = np.concatenate([[0.0], np.cumsum(s_seq)])  # Gamma_t = sum_{j<t} s_j
+    out = []
+    qN = q ** n_hist
+    for t in range(T):
+        s_prev = s_seq[t - 1] if t >= 1 else 0.0
+        old = s_seq[t - n_hist] if t - n_hist >= 0 else 0.0
+        g_old = Gam[t] - Gam[t - n_hist] if t - n_hist >= 0 else 0.0
+        P = q * (P + s_prev * R) - qN * old * g_old
+        R = q * R + s_seq[t] - qN * old
+        k_last = n_hist - 1
+        s_last = s_seq[t - k_last] if t - k_last >= 0 else 0.0
+        g_last = Gam[t] - Gam[t - k_last] if t - k_last >= 0 else 0.0
+        sxy = R - 0.5 * s_seq[t] - 0.5 * q ** k_last * s_last
+        sxx = 2 * (P - 0.5 * q ** k_last * s_last * g_last)
+        out.append((sxy, sxx))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n_hist", [2, 5, 64])
+def test_history_brute_force_equals_recursion(n_hist):
+    """Linear case (gamma_c = inf): the brute-force window sum with the
+    accumulated strain from the Gamma prefix equals the recursions."""
+    rng = np.random.default_rng(11)
+    T = 3 * n_hist + 17
+    s_seq = 1e-3 * rng.standard_normal(T)
+    tau = 7.0
+    q = math.exp(-1.0 / tau)
+    rec = _recursive_ucm(s_seq, q, n_hist)
+    for t in range(T):
+        s_age = np.zeros(n_hist)
+        for k in range(n_hist):
+            if t - k >= 0:
+                s_age[k] = s_seq[t - k]
+        sxy, sxx = oracle.history_sum_ages(s_age, np.abs(s_age), 1.0, tau, math.inf)
+        assert sxy == pytest.approx(rec[t, 0], rel=1e-12, abs=1e-18)
+        assert sxx == pytest.approx(rec[t, 1], rel=1e-9, abs=1e-18)
+
+
+def test_history_damping_uses_past_shear_rate():
+    """Eq. (nlmax): the damping exp(-(t-t')|gamma_dot(t')|/gamma_c) takes the
+    shear rate at the past time t', not the current one."""
+    n_hist = 40
+    s_age = np.zeros(n_hist)
+    r_age = np.zeros(n_hist)
+    s_age[10] = 1e-3
+    r_age[10] = 0.0        # the past entry was unsheared
+    r_age[0] = 1e3         # a huge current shear rate must not damp it
+    sxy, _ = oracle.history_sum_ages(s_age, r_age, 1.0, 50.0, 0.1)
+    assert sxy == pytest.approx(1e-3 * math.exp(-10 / 50.0), rel=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Whole channel: conservation, Newtonian solution, symmetries, LTI identity
+# --------------------------------------------------------------------------
+
+def test_mass_conserved_2d_nlm():
+    ch = workloads.large_2d(lx=8, ly=12, n_hist=64).channels[0]
+    ch = ch.replace(tau_m=30.0)
+    oc = oracle.OracleChannel(ch)
+    m0 = oc.mass()
+    oc.step(300)
+    assert abs(oc.mass() - m0) / m0 < 1e-13
+
+
+def test_newtonian_poiseuille_exact():
+    """G_inf = 0: the steady BGK channel flow with the half-force velocity and
+    halfway bounce-back is the parabola (viscosity (tau_LB - 1/2)/3, Sec. III)
+    plus the uniform slip g (16 tau^2 - 16 tau + 1) / (24 nu)."""
+    p = _paper()
+    assert "tau_LB - 1/2" in p["newtonian_viscosity"]["value"]
+    for tau in (0.8, 1.0):
+        ly, g = 12, 1e-6
+        ch = workloads.Channel(lx=1, ly=ly, tau_lb=tau, g_inf=0.0, n_hist=2, gx=g)
+        oc = oracle.OracleChannel(ch)
+        oc.step(20000)
+        _, ux, uy = oc.fields()
+        nu = (tau - 0.5) / 3.0
+        y = np.arange(ly)
+        want = g / (2 * nu) * (y + 0.5) * (ly - 0.5 - y) + g * (16 * tau ** 2 - 16 * tau + 1) / (24 * nu)
+        np.testing.assert_allclose(ux[:, 0], want, rtol=1e-9)
+        assert np.abs(uy).max() < 1e-9 * np.abs(ux).max()  # rounding level
+
+
+def test_newtonian_momentum_diffusion_time():
+    """Cessation of Newtonian channel flow decays with the slowest diffusive
+    mode, rate 1/t_wall = pi^2 nu / (2H)^2 (Sec. IV.B, with eta_inf the BGK
+    viscosity and 2H = ly); the lattice value converges at O(ly^-2)."""
+    errs = []
+    for ly in (16, 32):
+        ch = workloads.Channel(lx=1, ly=ly, tau_lb=1.0, g_inf=0.0, n_hist=2, gx=1e-6)
+        oc = oracle.OracleChannel(ch)
+        nu = 0.5 / 3.0
+        t_wall = ly * ly / (math.pi ** 2 * nu)
+        oc.step(int(2 * t_wall))
+        oc.set_force(0.0)
+        oc.step(int(1.5 * t_wall))
+        u1 = oc.fields()[1][ly // 2, 0]
+        dt = int(0.5 * t_wall)
+        oc.step(dt)
+        u2 = oc.fields()[1][ly // 2, 0]
+        rate = -math.log(u2 / u1) / dt
+        errs.append(abs(rate * t_wall - 1))
+    assert errs[0] < 0.05 and errs[1] < errs[0] / 3
+
+
+@pytest.mark.parametrize("model", ["newtonian", "ucm"])
+def test_startup_cessation_symmetry_linear_models(model):
+    """Linear models (Newtonian, UCM) obey u_off(T0 + t) = u_on(T0 + t) - u_on(t)
+    (Sec. IV.B, startup/cessation symmetry)."""
+    g_inf = 0.0 if model == "newtonian" else 1e-3
+    ch = workloads.Channel(lx=1, ly=16, tau_lb=1.0, g_inf=g_inf, tau_m=50.0,
+                           gamma_c=math.inf, n_hist=300, gx=1e-6)
+    T0, T1 = 400, 300
+    on = oracle.OracleChannel(ch)
+    u_on = []
+    for _ in range(T0 + T1):
+        on.step(1)
+        u_on.append(on.fields()[1][:, 0].copy())
+    off = oracle.OracleChannel(ch)
+    off.step(T0)
+    off.set_force(0.0)
+    scale = np.abs(u_on).max()
+    for t in range(T1):
+        off.step(1)
+        u_off = off.fields()[1][:, 0]
+        want = u_on[T0 + t] - u_on[t]
+        assert np.abs(u_off - want).max() / scale < 1e-11
+
+
+def test_channel_symmetries():
+    """Mirror symmetry about the channel centre, odd symmetry under g -> -g,
+    and exact x-invariance for an x-invariant start."""
+    base = workloads.Channel(lx=4, ly=10, tau_lb=1.0, g_inf=1e-3, tau_m=40.0,
+                             gamma_c=0.1, n_hist=120, gx=2e-5)
+    a = oracle.OracleChannel(base)
+    b = oracle.OracleChannel(base.replace(gx=-2e-5))
+    a.step(250)
+    b.step(250)
+    _, ua, va = a.fields()
+    sa, na = a.stress()
+    _, ub, _ = b.fields()
+    sb, nb = b.stress()
+    # x-invariance: all columns identical
+    for arr in (ua, sa, na):
+        assert np.array_equal(arr, arr[:, :1] * np.ones((1, 4)))
+    # mirror: u even, sigma_xy odd, N1 even about the centre line
+    sc = np.abs(ua).max()
+    assert np.abs(ua - ua[::-1]).max() / sc < 1e-12
+    assert np.abs(sa + sa[::-1]).max() / np.abs(sa).max() < 1e-10
+    assert np.abs(na - na[::-1]).max() / np.abs(na).max() < 1e-10
+    # sign: u and sigma_xy flip, N1 unchanged
+    np.testing.assert_allclose(ub, -ua, rtol=1e-13, atol=1e-22)
+    np.testing.assert_allclose(sb, -sa, rtol=1e-12, atol=1e-24)
+    np.testing.assert_allclose(nb, na, rtol=1e-12, atol=1e-28)
+    # the paper's claim N1 = sigma_xx - sigma_yy >= 0 in channel flow (Sec. IV.B)
+    assert na.min() >= 0.0
+
+
+def test_ucm_steady_centreline_maxwell_relation():
+    """UCM steady channel flow has the effective viscosity nu + eta_s with the
+    discrete Maxwell viscosity eta_s = G (1/2) coth(1/(2 tau)) (Sec. I relation
+    eta = G tau up to O(tau^-2)); the centreline velocity approaches
+    g ly^2 / (8 nu_eff) at second order in 1/ly."""
+    errs = []
+    for ly in (12, 24):
+        g, tau, Gm = 1e-6, 15.0, 5e-3
+        ch = workloads.Channel(lx=1, ly=ly, tau_lb=1.0, g_inf=Gm, tau_m=tau,
+                               gamma_c=math.inf, n_hist=600, gx=g)
+        oc = oracle.OracleChannel(ch)
+        nu = 0.5 / 3
+        eta_s = Gm * 0.5 / math.tanh(0.5 / tau) * (1 - math.exp(-599 / tau))
+        nu_eff = nu + eta_s
+        t_wall = ly * ly / (math.pi ** 2 * nu_eff)
+        oc.step(int(25 * t_wall) + 1000)
+        _, ux, _ = oc.fields()
+        uc = 0.5 * (ux[ly // 2, 0] + ux[ly // 2 - 1, 0])
+        y = ly / 2 - 0.5
+        want = g / (2 * nu_eff) * (y + 0.5) * (ly - 0.5 - y)
+        errs.append(abs(uc / want - 1))
+    assert errs[0] < 0.05
+    assert errs[1] < errs[0] / 3
