@@ -1,0 +1,192 @@
+/*
+ * lbmax.h -- C interface of the MI355X hybrid lattice-Boltzmann engine with
+ * the integral nonlinear Maxwell (nlM) constitutive equation
+ * (Papenkort & Voigtmann, arXiv:1504.06123).
+ *
+ * Problem statement the calls follow (Sec. I Eq. ns, Sec. II Eqs. gitt,
+ * nlmax, nlM, Sec. III): an incompressible fluid in a planar channel --
+ * x periodic, no-slip walls at y = -1/2 and y = ly - 1/2 -- driven by a body
+ * force rho*g that is switched on (startup) or off (cessation), starting
+ * from a stress-free rest state.  The Newtonian background viscosity
+ * eta_inf is the BGK viscosity rho c_s^2 (tau_LB - 1/2); the structural
+ * stress is the history integral of Eq. (gitt) with the modulus of
+ * Eq. (nlmax), G_inf exp(-(t-t')/tau) exp(-(t-t')|gamma_dot(t')|/gamma_c),
+ * evaluated in the simple-shear reduction (sigma_xy, N1 = sigma_xx -
+ * sigma_yy, sigma_yy = 0) over a window of the last n_hist steps.  The
+ * stress enters the lattice-Boltzmann update as the body force div(sigma),
+ * lagged by one step.  Results returned: density, velocity, velocity
+ * gradient kappa, sigma_xy and N1.
+ *
+ * Conventions shared by every call:
+ *  - Lattice units: dt = dx = 1, rho_0 = 1.  Node index = y*lx + x; every
+ *    host output array is FP64, [ly][lx] (x fastest), caller-owned.
+ *  - Device memory is borrowed, never allocated: the caller allocates the
+ *    workspace (lb_workspace_bytes) and state buffers (lb_state_bytes) and
+ *    keeps them alive until lb_destroy.  The library never calls hipMalloc.
+ *  - Work is ordered on the HIP stream given to lb_init.  lb_step only
+ *    enqueues; readout calls (lb_fields, lb_stress, lb_grad) synchronise
+ *    that stream before returning.  A handle is not thread-safe.
+ *  - Readouts refer to the last completed step.  Before the first step they
+ *    return LB_ESTATE.
+ *  - Every call returns lb_status; no C++ exception crosses this boundary.
+ *    lb_last_error() gives a thread-local message for the last failure.
+ *    Invalid arguments are reported before any device work is enqueued and
+ *    leave the handle unchanged.  After LB_EDEVICE the handle is poisoned:
+ *    every later call except lb_destroy returns LB_ESTATE.
+ */
+#ifndef LBMAX_H
+#define LBMAX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,     /* invalid argument; nothing was enqueued            */
+    LB_ENOMEM = -2,     /* workspace or buffer too small / misaligned        */
+    LB_EDEVICE = -3,    /* a HIP call failed; the handle is now poisoned     */
+    LB_ESTATE = -4,     /* call not valid in the handle's current state      */
+    LB_ENONFINITE = -5  /* reserved: non-finite values detected              */
+} lb_status;
+
+/*
+ * Arithmetic of the whole path.
+ *  LB_F64: populations, velocities, history ring and sums in FP64.
+ *  LB_F32: populations stored as deviations n_i - a_i in FP32, history ring
+ *          in FP32, history sums in FP32 with Kahan compensation; the
+ *          accumulated strain (prefix sum of the shear rate, Sec. III
+ *          Eq. eeval) and the combination of partial sums in FP64.
+ */
+typedef enum { LB_F64 = 0, LB_F32 = 1 } lb_precision;
+
+/*
+ * One channel.  Requirements (checked, LB_EINVAL otherwise):
+ *   lx >= 1, ly >= 3, tau_lb > 1/2, n_hist >= 2, g_inf >= 0, tau_m > 0,
+ *   gamma_c > 0 (may be +INFINITY: the linear / UCM limit of Sec. II),
+ *   all numbers finite except gamma_c = +INF.
+ * g_inf = 0 gives a Newtonian fluid.  (gx, gy) is the body-force
+ * acceleration; the force density is rho*g (Eq. ns).  u0, when not NULL,
+ * is a host array [2][ly][lx] of initial velocities; the initial
+ * populations are the equilibrium n^eq(rho = 1, u0) (NULL: rest).
+ * A channel with lx == 1, gy == 0 and u0_y == 0 everywhere is
+ * unidirectional: u_y stays zero, |gamma_dot| = |kappa_xy|, and its history
+ * ring stores the shear rate only; lb_set_force rejects gy != 0 for it.
+ */
+typedef struct {
+    int32_t lx, ly;
+    double tau_lb;
+    double g_inf, tau_m, gamma_c;
+    int32_t n_hist;
+    double gx, gy;
+    const double *u0;
+} lb_channel_desc;
+
+typedef struct lb_handle lb_handle;
+
+/* Bytes of device workspace needed for these channels (0 if the
+ * description is invalid; lb_last_error says why).  Pure host call. */
+size_t lb_workspace_bytes(const lb_channel_desc *ch, int32_t n_ch,
+                          lb_precision prec);
+
+/*
+ * Create a handle for n_ch >= 1 channels advanced together (one launch per
+ * phase covers every channel).  d_ws: device pointer, 256-byte aligned, at
+ * least lb_workspace_bytes(...) bytes, owned by the caller.  stream: a
+ * hipStream_t (NULL = default stream).  Enqueues the initialisation: the
+ * initial populations, a zero history (rest before t = 0, Eq. maxwell),
+ * zero stress.  On success *out receives the handle.
+ */
+lb_status lb_init(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec,
+                  void *d_ws, size_t ws_bytes, void *stream, lb_handle **out);
+
+/* Change the body force of channel ch from the next step on (startup /
+ * cessation, Sec. IV.B).  Stream-ordered. */
+lb_status lb_set_force(lb_handle *h, int32_t ch, double gx, double gy);
+
+/* Enqueue n_steps >= 0 time steps of every channel.  One step is: stream
+ * and collide (BGK + forcing with rho*g + div sigma of the previous step,
+ * Sec. III Eqs. bodyforce, hydrofields), velocity gradient, history push,
+ * history integral (Eqs. gitt, nlmax) -> sigma. */
+lb_status lb_step(lb_handle *h, int64_t n_steps);
+
+/* Number of completed steps (host-side counter). */
+int64_t lb_time(const lb_handle *h);
+
+/* Density, velocity u = (j + f/2)/rho of the last completed step.  Any
+ * pointer may be NULL.  Synchronises the stream. */
+lb_status lb_fields(lb_handle *h, int32_t ch, double *rho, double *ux,
+                    double *uy);
+
+/* sigma_xy and N1 = sigma_xx - sigma_yy of the last completed step. */
+lb_status lb_stress(lb_handle *h, int32_t ch, double *sxy, double *n1);
+
+/* Velocity gradient kappa_ab = d_b u_a (kappa = (grad v)^T, Sec. I) of the
+ * last completed step by second-order differences (Sec. III); out is
+ * [4][ly][lx] ordered kxx, kxy, kyx, kyy. */
+lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
+
+/*
+ * State snapshot (checkpoint / resume).  lb_state_bytes gives the size of a
+ * device buffer holding the full state; lb_save_state copies the state into
+ * it (stream-ordered), lb_load_state restores it.  Layout (all sections
+ * 256-byte aligned, R = double for LB_F64, float for LB_F32):
+ *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 1,
+ *     uint32 precision, int64 t (completed steps), int32 n_ch,
+ *     int32 reserved, uint64 total bytes;
+ *   then per channel, in order, N = lx*ly:
+ *     pop  [9][N] R  post-collision populations of step t-1 minus the
+ *                    weights a_i (before the first step: the initial state
+ *                    shifted back by one streaming step).  Direction order
+ *                    q = 0..8: (0,0), (1,0), (-1,0), (0,1), (0,-1), (1,1),
+ *                    (-1,-1), (1,-1), (-1,1).
+ *     sig  [2][N] R  sigma_xy, sigma_xx of step t-1
+ *     vel  [2][N] R  u_x, u_y of step t-1
+ *     drho [N]    R  rho - 1 of step t-1
+ *     ring_s [n_hist][N] R  shear rate s(t') = kappa_xy, row t' mod n_hist
+ *     ring_r [n_hist][N] R  |gamma_dot(t')| (absent for unidirectional
+ *                           channels)
+ *     force  2 doubles: gx, gy.
+ * Ring rows of times before t = 0 are zero.
+ */
+size_t lb_state_bytes(const lb_handle *h);
+lb_status lb_save_state(lb_handle *h, void *d_dst);
+lb_status lb_load_state(lb_handle *h, const void *d_src);
+
+/*
+ * Launch shaping (used by the autotuner).  lb_set_chunks splits channel
+ * ch's history window into n_chunks >= 1 age ranges reduced by separate
+ * workgroups and combined in FP64 in fixed order; it must not exceed
+ * lb_max_chunks(h, ch).  lb_set_graph(h, s) replays s steps per hipGraph
+ * launch inside lb_step (0 = plain launches).  Both take effect at the next
+ * lb_step and change rounding only through the chunk split.
+ */
+int32_t lb_max_chunks(const lb_handle *h, int32_t ch);
+lb_status lb_set_chunks(lb_handle *h, int32_t ch, int32_t n_chunks);
+lb_status lb_set_graph(lb_handle *h, int32_t steps_per_graph);
+
+/*
+ * Per-kernel timing with HIP events recorded on the handle's stream around
+ * every launch of the history kernel (which = 0) and the lattice kernel
+ * (which = 1).  Enabled by lb_profile(h, 1) for plain launches;
+ * lb_kernel_time returns the accumulated milliseconds and launch count and
+ * synchronises the stream.
+ */
+lb_status lb_profile(lb_handle *h, int32_t enable);
+lb_status lb_kernel_time(lb_handle *h, int32_t which, double *total_ms,
+                         int64_t *launches);
+
+/* Release host-side handle memory.  Device memory stays the caller's. */
+lb_status lb_destroy(lb_handle *h);
+
+/* Thread-local message of the last failed call ("" if none). */
+const char *lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMAX_H */

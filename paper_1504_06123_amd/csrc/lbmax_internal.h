@@ -1,0 +1,70 @@
+// lbmax_internal.h -- device-side data layout shared by the kernels and the
+// host runtime of liblbmax.  Not part of the public interface (include/lbmax.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbmax {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kNodeAlign = 64;     // node-plane stride is a multiple of this
+constexpr int kMinChunkLen = 128;  // shortest age range of one history chunk
+constexpr int kMaxChunks = 64;     // most age ranges per channel
+constexpr int64_t kPartialBudget = int64_t(1) << 22;  // chunks * stride cap
+
+// Per-channel parameters and workspace offsets, read by every kernel.
+// 256 bytes so a table row never straddles two scalar cache lines twice.
+struct alignas(256) ChanDev {
+    int32_t lx, ly, n, np;          // nodes n = lx*ly, plane stride np
+    int32_t n_hist, has_r, nchunks, max_chunks;
+    double omega;                   // 1/tau_LB
+    double g_inf;
+    double inv_tau, inv_gc;         // 1/tau, 1/gamma_c (0 for gamma_c = inf)
+    double l2_tau, l2_gc;           // log2(e)/tau, log2(e)/gamma_c
+    double gx, gy;                  // body-force acceleration
+    int64_t off_pop;                // [2][9][np] populations minus a_i
+    int64_t off_sig;                // [2][np]  sigma_xy, sigma_xx
+    int64_t off_vel;                // [2][np]  u_x, u_y
+    int64_t off_rho;                // [np]     rho - 1
+    int64_t off_ring_s;             // [n_hist][np] shear rate
+    int64_t off_ring_r;             // [n_hist][np] |gamma_dot| (has_r only)
+    int64_t off_part;               // [3][max_chunks][np] doubles A, B, T
+};
+static_assert(sizeof(ChanDev) == 256, "ChanDev layout");
+
+// One workgroup of the lattice / combine / readout kernels: 256 nodes.
+struct NodeTile {
+    int32_t ch, n0;
+};
+
+// One workgroup of the history kernel: 256 nodes x ages [k0, k1).
+struct HistTile {
+    int32_t ch, n0, k0, k1, chunk, pad;
+};
+
+// Kernel launchers (lbmax_kernels.hip).  All launches go on `st`.
+// `tcount` is the device step counter; a kernel works on step
+// t = *tcount + trel.
+void launch_init(bool f64, char *ws, const ChanDev *chans, int ch,
+                 const NodeTile *tiles, int n_tiles, const double *u0_dev,
+                 hipStream_t st);
+void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+void launch_lb(bool f64, char *ws, const ChanDev *chans, const NodeTile *tiles,
+               int n_tiles, const int64_t *tcount, int trel, hipStream_t st);
+void launch_hist(bool f64, char *ws, const ChanDev *chans,
+                 const HistTile *tiles, int n_tiles, const int64_t *tcount,
+                 int trel, hipStream_t st);
+void launch_combine(bool f64, char *ws, const ChanDev *chans,
+                    const NodeTile *tiles, int n_tiles, hipStream_t st);
+void launch_tick(int64_t *tcount, int64_t add, hipStream_t st);
+void launch_set_force(ChanDev *chans, int ch, double gx, double gy,
+                      hipStream_t st);
+// Readouts into FP64 staging (nodes of one channel): which = 0 fields
+// (rho, ux, uy), 1 stress (sxy, n1), 2 gradient (kxx, kxy, kyx, kyy).
+void launch_readout(bool f64, int which, char *ws, const ChanDev *chans,
+                    int ch, int n_nodes, double *stage, hipStream_t st);
+
+}  // namespace lbmax

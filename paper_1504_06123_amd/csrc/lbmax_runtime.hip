@@ -1,0 +1,808 @@
+// lbmax_runtime.hip -- host side of liblbmax: the C interface declared in
+// include/lbmax.h.  Validates descriptions, lays out the caller-owned
+// workspace, builds the launch tile lists, enqueues steps (plain launches or
+// hipGraph replays), and implements readouts and state snapshots.
+#include "lbmax.h"
+#include "lbmax_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace lbmax;
+
+namespace {
+
+thread_local std::string g_err;
+
+lb_status fail(lb_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr uint64_t kStateMagic = 0x4C424D4158535431ull;  // "LBMAXST1"
+constexpr uint32_t kStateVersion = 1;
+constexpr size_t kStateHeader = 256;
+constexpr int64_t kMaxStepsPerBatch = int64_t(1) << 20;
+
+struct StateHeader {
+    uint64_t magic;
+    uint32_t version;
+    uint32_t precision;
+    int64_t t;
+    int32_t n_ch;
+    int32_t reserved;
+    uint64_t bytes;
+};
+
+bool unidirectional(const lb_channel_desc &d)
+{
+    if (d.lx != 1 || d.gy != 0.0)
+        return false;
+    if (d.u0)
+        for (int y = 0; y < d.ly; ++y)
+            if (d.u0[(size_t)d.ly + y] != 0.0)
+                return false;
+    return true;
+}
+
+std::string check_desc(const lb_channel_desc *ch, int32_t n_ch)
+{
+    if (!ch)
+        return "channel array is NULL";
+    if (n_ch < 1)
+        return "n_ch must be >= 1";
+    for (int i = 0; i < n_ch; ++i) {
+        const lb_channel_desc &d = ch[i];
+        char buf[160];
+        auto bad = [&](const char *what) {
+            snprintf(buf, sizeof buf, "channel %d: %s", i, what);
+            return std::string(buf);
+        };
+        if (d.lx < 1)
+            return bad("lx must be >= 1");
+        if (d.ly < 3)
+            return bad("ly must be >= 3");
+        if ((int64_t)d.lx * d.ly > (int64_t)1 << 30)
+            return bad("too many nodes");
+        if (d.n_hist < 2)
+            return bad("n_hist must be >= 2");
+        if (!std::isfinite(d.tau_lb) || !(d.tau_lb > 0.5))
+            return bad("tau_lb must be finite and > 1/2");
+        if (!std::isfinite(d.g_inf) || d.g_inf < 0.0)
+            return bad("g_inf must be finite and >= 0");
+        if (!std::isfinite(d.tau_m) || !(d.tau_m > 0.0))
+            return bad("tau_m must be finite and > 0");
+        if (std::isnan(d.gamma_c) || !(d.gamma_c > 0.0))
+            return bad("gamma_c must be > 0 (or +inf)");
+        if (!std::isfinite(d.gx) || !std::isfinite(d.gy))
+            return bad("body force must be finite");
+        if (d.u0) {
+            const size_t cnt = 2 * (size_t)d.lx * d.ly;
+            for (size_t k = 0; k < cnt; ++k)
+                if (!std::isfinite(d.u0[k]))
+                    return bad("u0 has a non-finite entry");
+        }
+    }
+    return "";
+}
+
+// Workspace plan: header | channel table | node tiles | history tiles |
+// readout staging | per-channel planes.  Everything 256-byte aligned.
+struct Plan {
+    size_t total = 0;
+    size_t off_tcount = 0, off_chans = 0, off_node_tiles = 0, off_hist_tiles = 0,
+           off_stage = 0, stage_bytes = 0;
+    int n_node_tiles = 0, n_hist_tiles_max = 0;
+    std::vector<ChanDev> chans;
+};
+
+int max_chunks_for(int n_hist, int np)
+{
+    int m = std::min(kMaxChunks, std::max(1, n_hist / kMinChunkLen));
+    const int64_t cap = std::max<int64_t>(1, kPartialBudget / np);
+    return (int)std::min<int64_t>(m, cap);
+}
+
+Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
+{
+    const size_t R = prec == LB_F64 ? 8 : 4;
+    Plan P;
+    size_t off = 0;
+    P.off_tcount = off;
+    off += 256;
+    P.off_chans = off;
+    off = align_up(off + (size_t)n_ch * sizeof(ChanDev), 256);
+    size_t stage = 0;
+    P.chans.resize(n_ch);
+    for (int i = 0; i < n_ch; ++i) {
+        const lb_channel_desc &d = ch[i];
+        ChanDev &c = P.chans[i];
+        std::memset(&c, 0, sizeof c);
+        c.lx = d.lx;
+        c.ly = d.ly;
+        c.n = d.lx * d.ly;
+        c.np = (int)align_up((size_t)c.n, kNodeAlign);
+        c.n_hist = d.n_hist;
+        c.has_r = unidirectional(d) ? 0 : 1;
+        c.max_chunks = max_chunks_for(d.n_hist, c.np);
+        c.nchunks = 1;
+        c.omega = 1.0 / d.tau_lb;
+        c.g_inf = d.g_inf;
+        c.inv_tau = 1.0 / d.tau_m;
+        c.inv_gc = std::isinf(d.gamma_c) ? 0.0 : 1.0 / d.gamma_c;
+        c.l2_tau = M_LOG2E * c.inv_tau;
+        c.l2_gc = M_LOG2E * c.inv_gc;
+        c.gx = d.gx;
+        c.gy = d.gy;
+        const int blocks = (c.n + kBlock - 1) / kBlock;
+        P.n_node_tiles += blocks;
+        P.n_hist_tiles_max += blocks * c.max_chunks;
+        stage = std::max(stage, (size_t)4 * c.n);
+    }
+    P.off_node_tiles = off;
+    off = align_up(off + (size_t)P.n_node_tiles * sizeof(NodeTile), 256);
+    P.off_hist_tiles = off;
+    off = align_up(off + (size_t)P.n_hist_tiles_max * sizeof(HistTile), 256);
+    P.off_stage = off;
+    P.stage_bytes = align_up(stage * sizeof(double), 256);
+    off += P.stage_bytes;
+    for (int i = 0; i < n_ch; ++i) {
+        ChanDev &c = P.chans[i];
+        const size_t plane = (size_t)c.np * R;
+        c.off_pop = (int64_t)off;
+        off = align_up(off + 18 * plane, 256);
+        c.off_sig = (int64_t)off;
+        off = align_up(off + 2 * plane, 256);
+        c.off_vel = (int64_t)off;
+        off = align_up(off + 2 * plane, 256);
+        c.off_rho = (int64_t)off;
+        off = align_up(off + plane, 256);
+        c.off_ring_s = (int64_t)off;
+        off = align_up(off + (size_t)c.n_hist * plane, 256);
+        c.off_ring_r = (int64_t)off;
+        if (c.has_r)
+            off = align_up(off + (size_t)c.n_hist * plane, 256);
+        c.off_part = (int64_t)off;
+        if (c.max_chunks > 1)
+            off = align_up(off + 3 * (size_t)c.max_chunks * c.np * sizeof(double), 256);
+    }
+    P.total = off;
+    return P;
+}
+
+}  // namespace
+
+struct lb_handle {
+    int n_ch = 0;
+    lb_precision prec = LB_F32;
+    bool f64 = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    Plan plan;
+    std::vector<int> ly, lx, n_hist;
+    int64_t t = 0;          // completed steps
+    bool has_out = false;   // readout planes belong to step t-1
+    bool poisoned = false;
+    // device pointers into the workspace
+    int64_t *d_tcount = nullptr;
+    ChanDev *d_chans = nullptr;
+    NodeTile *d_node_tiles = nullptr;
+    HistTile *d_hist_tiles = nullptr;
+    double *d_stage = nullptr;
+    int n_node_tiles = 0, n_hist_tiles = 0;
+    bool any_chunked = false;
+    // host mirrors kept alive for asynchronous uploads
+    std::vector<NodeTile> node_tiles;
+    std::vector<HistTile> hist_tiles;
+    std::vector<char> upload;
+    // graph replay
+    int graph_steps = 0;
+    bool graph_dirty = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    // timing: event pairs recorded around launches, resolved on demand
+    bool profile = false;
+    std::vector<hipEvent_t> free_events;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
+    double kernel_ms[2] = {0.0, 0.0};
+    int64_t kernel_launches[2] = {0, 0};
+};
+
+namespace {
+
+#define HIP_TRY(h, call)                                                        \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess) {                                                 \
+            if (h)                                                              \
+                (h)->poisoned = true;                                           \
+            return fail(LB_EDEVICE, std::string(#call) + ": " +                 \
+                                        hipGetErrorString(e_));                 \
+        }                                                                       \
+    } while (0)
+
+lb_status check_launch(lb_handle *h, const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        h->poisoned = true;
+        return fail(LB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+    return LB_OK;
+}
+
+lb_status usable(lb_handle *h)
+{
+    if (!h)
+        return fail(LB_EINVAL, "handle is NULL");
+    if (h->poisoned)
+        return fail(LB_ESTATE, "handle is poisoned by an earlier device error");
+    return LB_OK;
+}
+
+// Split every channel's window into its chunks and list the workgroups,
+// longest age range first so uneven channels finish together.
+void build_tiles(lb_handle *h)
+{
+    h->node_tiles.clear();
+    h->hist_tiles.clear();
+    h->any_chunked = false;
+    for (int ci = 0; ci < h->n_ch; ++ci) {
+        const ChanDev &c = h->plan.chans[ci];
+        for (int n0 = 0; n0 < c.n; n0 += kBlock)
+            h->node_tiles.push_back({ci, n0});
+        if (c.nchunks > 1)
+            h->any_chunked = true;
+        for (int k = 0; k < c.nchunks; ++k) {
+            const int k0 = (int)((int64_t)c.n_hist * k / c.nchunks);
+            const int k1 = (int)((int64_t)c.n_hist * (k + 1) / c.nchunks);
+            for (int n0 = 0; n0 < c.n; n0 += kBlock)
+                h->hist_tiles.push_back({ci, n0, k0, k1, k, 0});
+        }
+    }
+    std::stable_sort(h->hist_tiles.begin(), h->hist_tiles.end(),
+                     [](const HistTile &a, const HistTile &b) {
+                         return (a.k1 - a.k0) > (b.k1 - b.k0);
+                     });
+    h->n_node_tiles = (int)h->node_tiles.size();
+    h->n_hist_tiles = (int)h->hist_tiles.size();
+}
+
+lb_status upload_tables(lb_handle *h)
+{
+    HIP_TRY(h, hipMemcpyAsync(h->d_chans, h->plan.chans.data(),
+                              h->plan.chans.size() * sizeof(ChanDev),
+                              hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->d_node_tiles, h->node_tiles.data(),
+                              h->node_tiles.size() * sizeof(NodeTile),
+                              hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->d_hist_tiles, h->hist_tiles.data(),
+                              h->hist_tiles.size() * sizeof(HistTile),
+                              hipMemcpyHostToDevice, h->stream));
+    // The host vectors are reused only after this synchronisation.
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->graph_dirty = true;
+    return LB_OK;
+}
+
+lb_status take_event(lb_handle *h, hipEvent_t *ev)
+{
+    if (!h->free_events.empty()) {
+        *ev = h->free_events.back();
+        h->free_events.pop_back();
+        return LB_OK;
+    }
+    HIP_TRY(h, hipEventCreate(ev));
+    return LB_OK;
+}
+
+// Add up the elapsed time of every recorded pair (the stream must be idle).
+lb_status resolve_timing(lb_handle *h)
+{
+    for (int w = 0; w < 2; ++w) {
+        for (auto &pr : h->pending[w]) {
+            float ms = 0.f;
+            HIP_TRY(h, hipEventElapsedTime(&ms, pr.first, pr.second));
+            h->kernel_ms[w] += ms;
+            h->kernel_launches[w] += 1;
+            h->free_events.push_back(pr.first);
+            h->free_events.push_back(pr.second);
+        }
+        h->pending[w].clear();
+    }
+    return LB_OK;
+}
+
+// One step's launches, step t = *tcount + trel.  With `timed`, a HIP event
+// pair brackets the lattice (slot 1) and history (slot 0) launches.
+lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, bool timed)
+{
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (timed) {
+        for (int i = 0; i < 4; ++i) {
+            lb_status s = take_event(h, &e[i]);
+            if (s != LB_OK)
+                return s;
+        }
+        HIP_TRY(h, hipEventRecord(e[0], st));
+    }
+    launch_lb(h->f64, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
+              h->d_tcount, trel, st);
+    if (timed) {
+        HIP_TRY(h, hipEventRecord(e[1], st));
+        HIP_TRY(h, hipEventRecord(e[2], st));
+    }
+    launch_hist(h->f64, h->ws, h->d_chans, h->d_hist_tiles, h->n_hist_tiles,
+                h->d_tcount, trel, st);
+    if (timed) {
+        HIP_TRY(h, hipEventRecord(e[3], st));
+        h->pending[1].push_back({e[0], e[1]});
+        h->pending[0].push_back({e[2], e[3]});
+    }
+    if (h->any_chunked)
+        launch_combine(h->f64, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, st);
+    return check_launch(h, "step launch");
+}
+
+lb_status capture_graph(lb_handle *h)
+{
+    if (h->graph_exec) {
+        (void)hipGraphExecDestroy(h->graph_exec);
+        h->graph_exec = nullptr;
+    }
+    if (h->graph) {
+        (void)hipGraphDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    if (!h->cap_stream)
+        HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < h->graph_steps; ++i) {
+        lb_status s = enqueue_step(h, h->cap_stream, i, false);
+        if (s != LB_OK) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(h->cap_stream, &g);
+            if (g)
+                (void)hipGraphDestroy(g);
+            return s;
+        }
+    }
+    launch_tick(h->d_tcount, h->graph_steps, h->cap_stream);
+    HIP_TRY(h, hipStreamEndCapture(h->cap_stream, &h->graph));
+    HIP_TRY(h, hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+    h->graph_dirty = false;
+    return LB_OK;
+}
+
+lb_status readout(lb_handle *h, int32_t ch, int which, int comps,
+                  double **outs)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (ch < 0 || ch >= h->n_ch)
+        return fail(LB_EINVAL, "channel index out of range");
+    if (!h->has_out)
+        return fail(LB_ESTATE, "no completed step to read");
+    const int N = h->plan.chans[ch].n;
+    launch_readout(h->f64, which, h->ws, h->d_chans, ch, N, h->d_stage, h->stream);
+    s = check_launch(h, "readout");
+    if (s != LB_OK)
+        return s;
+    std::vector<double> host((size_t)comps * N);
+    HIP_TRY(h, hipMemcpyAsync(host.data(), h->d_stage, host.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (int k = 0; k < comps; ++k)
+        if (outs[k])
+            std::memcpy(outs[k], host.data() + (size_t)k * N, N * sizeof(double));
+    return LB_OK;
+}
+
+// Per-channel state sections: (workspace offset, rows, bytes per row) in
+// the order of the state layout.
+struct Section {
+    int64_t ws_off;
+    size_t rows, row_bytes, ws_pitch;
+};
+
+std::vector<Section> state_sections(const lb_handle *h, int ci, int64_t t)
+{
+    const ChanDev &c = h->plan.chans[ci];
+    const size_t R = h->f64 ? 8 : 4;
+    const size_t rowb = (size_t)c.n * R, pitch = (size_t)c.np * R;
+    const int64_t cur = c.off_pop + (int64_t)(((t + 1) & 1) * 9 * pitch);
+    std::vector<Section> v;
+    v.push_back({cur, 9, rowb, pitch});
+    v.push_back({c.off_sig, 2, rowb, pitch});
+    v.push_back({c.off_vel, 2, rowb, pitch});
+    v.push_back({c.off_rho, 1, rowb, pitch});
+    v.push_back({c.off_ring_s, (size_t)c.n_hist, rowb, pitch});
+    if (c.has_r)
+        v.push_back({c.off_ring_r, (size_t)c.n_hist, rowb, pitch});
+    return v;
+}
+
+size_t state_size(const lb_handle *h)
+{
+    size_t off = kStateHeader;
+    for (int ci = 0; ci < h->n_ch; ++ci) {
+        for (const Section &s : state_sections(h, ci, 0))
+            off = align_up(off + s.rows * s.row_bytes, 256);
+        off = align_up(off + 2 * sizeof(double), 256);
+    }
+    return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lb_last_error(void) { return g_err.c_str(); }
+
+size_t lb_workspace_bytes(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
+{
+    if (prec != LB_F64 && prec != LB_F32) {
+        g_err = "unknown precision";
+        return 0;
+    }
+    std::string why = check_desc(ch, n_ch);
+    if (!why.empty()) {
+        g_err = why;
+        return 0;
+    }
+    return make_plan(ch, n_ch, prec).total;
+}
+
+lb_status lb_init(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec, void *d_ws,
+                  size_t ws_bytes, void *stream, lb_handle **out)
+{
+    if (!out)
+        return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (prec != LB_F64 && prec != LB_F32)
+        return fail(LB_EINVAL, "unknown precision");
+    std::string why = check_desc(ch, n_ch);
+    if (!why.empty())
+        return fail(LB_EINVAL, why);
+    if (!d_ws)
+        return fail(LB_EINVAL, "workspace pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0)
+        return fail(LB_ENOMEM, "workspace must be 256-byte aligned");
+    Plan plan = make_plan(ch, n_ch, prec);
+    if (ws_bytes < plan.total)
+        return fail(LB_ENOMEM, "workspace too small: need " + std::to_string(plan.total) +
+                                   " bytes, got " + std::to_string(ws_bytes));
+
+    lb_handle *h = new lb_handle();
+    h->n_ch = n_ch;
+    h->prec = prec;
+    h->f64 = prec == LB_F64;
+    h->ws = static_cast<char *>(d_ws);
+    h->ws_bytes = ws_bytes;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->plan = std::move(plan);
+    h->d_tcount = reinterpret_cast<int64_t *>(h->ws + h->plan.off_tcount);
+    h->d_chans = reinterpret_cast<ChanDev *>(h->ws + h->plan.off_chans);
+    h->d_node_tiles = reinterpret_cast<NodeTile *>(h->ws + h->plan.off_node_tiles);
+    h->d_hist_tiles = reinterpret_cast<HistTile *>(h->ws + h->plan.off_hist_tiles);
+    h->d_stage = reinterpret_cast<double *>(h->ws + h->plan.off_stage);
+    for (int i = 0; i < n_ch; ++i) {
+        h->lx.push_back(ch[i].lx);
+        h->ly.push_back(ch[i].ly);
+        h->n_hist.push_back(ch[i].n_hist);
+    }
+
+    // Default split: enough workgroups to cover the chip (about 2048), never
+    // below kMinChunkLen ages per chunk.
+    int total_blocks = 0;
+    for (const ChanDev &c : h->plan.chans)
+        total_blocks += (c.n + kBlock - 1) / kBlock;
+    const int want = std::max(1, (2048 + total_blocks - 1) / total_blocks);
+    for (ChanDev &c : h->plan.chans)
+        c.nchunks = std::max(1, std::min(want, c.max_chunks));
+    build_tiles(h);
+
+    auto bail = [&](lb_status s) {
+        delete h;
+        return s;
+    };
+
+    // Zero the whole workspace (step counter, rings, partials), then upload
+    // the tables and initialise each channel.
+    launch_fill_zero(h->ws, h->plan.total, h->stream);
+    lb_status s = check_launch(h, "zero fill");
+    if (s != LB_OK)
+        return bail(s);
+    s = upload_tables(h);
+    if (s != LB_OK)
+        return bail(s);
+    for (int i = 0; i < n_ch; ++i) {
+        const ChanDev &c = h->plan.chans[i];
+        const double *u0_dev = nullptr;
+        if (ch[i].u0) {
+            const size_t bytes = 2 * (size_t)c.n * sizeof(double);
+            if (bytes > h->plan.stage_bytes)
+                return bail(fail(LB_ENOMEM, "staging too small for u0"));
+            if (hipMemcpyAsync(h->d_stage, ch[i].u0, bytes, hipMemcpyHostToDevice,
+                               h->stream) != hipSuccess)
+                return bail(fail(LB_EDEVICE, "u0 upload failed"));
+            u0_dev = h->d_stage;
+        }
+        launch_init(h->f64, h->ws, h->d_chans, i, nullptr, (c.n + kBlock - 1) / kBlock,
+                    u0_dev, h->stream);
+        s = check_launch(h, "init");
+        if (s != LB_OK)
+            return bail(s);
+        // The staging area is reused by the next channel: wait for this one.
+        if (ch[i].u0 && hipStreamSynchronize(h->stream) != hipSuccess)
+            return bail(fail(LB_EDEVICE, "init synchronisation failed"));
+    }
+    *out = h;
+    return LB_OK;
+}
+
+lb_status lb_set_force(lb_handle *h, int32_t ch, double gx, double gy)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (ch < 0 || ch >= h->n_ch)
+        return fail(LB_EINVAL, "channel index out of range");
+    if (!std::isfinite(gx) || !std::isfinite(gy))
+        return fail(LB_EINVAL, "body force must be finite");
+    if (!h->plan.chans[ch].has_r && gy != 0.0)
+        return fail(LB_EINVAL, "unidirectional channel: gy must stay 0");
+    h->plan.chans[ch].gx = gx;
+    h->plan.chans[ch].gy = gy;
+    launch_set_force(h->d_chans, ch, gx, gy, h->stream);
+    return check_launch(h, "set_force");
+}
+
+lb_status lb_step(lb_handle *h, int64_t n_steps)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (n_steps < 0)
+        return fail(LB_EINVAL, "n_steps must be >= 0");
+    int64_t left = n_steps;
+    if (h->graph_steps > 0 && !h->profile && left >= h->graph_steps) {
+        if (h->graph_dirty) {
+            s = capture_graph(h);
+            if (s != LB_OK)
+                return s;
+        }
+        while (left >= h->graph_steps) {
+            HIP_TRY(h, hipGraphLaunch(h->graph_exec, h->stream));
+            left -= h->graph_steps;
+        }
+    }
+    while (left > 0) {
+        const int batch = (int)std::min(left, kMaxStepsPerBatch);
+        for (int i = 0; i < batch; ++i) {
+            s = enqueue_step(h, h->stream, i, h->profile);
+            if (s != LB_OK)
+                return s;
+        }
+        launch_tick(h->d_tcount, batch, h->stream);
+        s = check_launch(h, "tick");
+        if (s != LB_OK)
+            return s;
+        left -= batch;
+    }
+    h->t += n_steps;
+    if (n_steps > 0)
+        h->has_out = true;
+    return LB_OK;
+}
+
+int64_t lb_time(const lb_handle *h) { return h ? h->t : -1; }
+
+lb_status lb_fields(lb_handle *h, int32_t ch, double *rho, double *ux, double *uy)
+{
+    double *o[3] = {rho, ux, uy};
+    return readout(h, ch, 0, 3, o);
+}
+
+lb_status lb_stress(lb_handle *h, int32_t ch, double *sxy, double *n1)
+{
+    double *o[2] = {sxy, n1};
+    return readout(h, ch, 1, 2, o);
+}
+
+lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa)
+{
+    if (h && ch >= 0 && ch < h->n_ch && !kappa)
+        return fail(LB_EINVAL, "kappa is NULL");
+    const int N = (h && ch >= 0 && ch < h->n_ch) ? h->plan.chans[ch].n : 0;
+    double *o[4] = {kappa, kappa ? kappa + N : nullptr, kappa ? kappa + 2 * (size_t)N : nullptr,
+                    kappa ? kappa + 3 * (size_t)N : nullptr};
+    return readout(h, ch, 2, 4, o);
+}
+
+size_t lb_state_bytes(const lb_handle *h) { return h ? state_size(h) : 0; }
+
+lb_status lb_save_state(lb_handle *h, void *d_dst)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (!d_dst || reinterpret_cast<uintptr_t>(d_dst) % 256 != 0)
+        return fail(LB_EINVAL, "state buffer must be non-NULL and 256-byte aligned");
+    char *dst = static_cast<char *>(d_dst);
+    size_t off = kStateHeader;
+    h->upload.assign(state_size(h) > 0 ? kStateHeader + 16 * (size_t)h->n_ch : 0, 0);
+    StateHeader hd{kStateMagic, kStateVersion, (uint32_t)h->prec, h->t, h->n_ch, 0,
+                   state_size(h)};
+    std::memcpy(h->upload.data(), &hd, sizeof hd);
+    for (int ci = 0; ci < h->n_ch; ++ci) {
+        for (const Section &sec : state_sections(h, ci, h->t)) {
+            HIP_TRY(h, hipMemcpy2DAsync(dst + off, sec.row_bytes, h->ws + sec.ws_off,
+                                        sec.ws_pitch, sec.row_bytes, sec.rows,
+                                        hipMemcpyDeviceToDevice, h->stream));
+            off = align_up(off + sec.rows * sec.row_bytes, 256);
+        }
+        double g[2] = {h->plan.chans[ci].gx, h->plan.chans[ci].gy};
+        std::memcpy(h->upload.data() + kStateHeader + 16 * (size_t)ci, g, 16);
+        HIP_TRY(h, hipMemcpyAsync(dst + off, h->upload.data() + kStateHeader + 16 * (size_t)ci,
+                                  16, hipMemcpyHostToDevice, h->stream));
+        off = align_up(off + 2 * sizeof(double), 256);
+    }
+    HIP_TRY(h, hipMemcpyAsync(dst, h->upload.data(), sizeof hd, hipMemcpyHostToDevice,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+lb_status lb_load_state(lb_handle *h, const void *d_src)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (!d_src || reinterpret_cast<uintptr_t>(d_src) % 256 != 0)
+        return fail(LB_EINVAL, "state buffer must be non-NULL and 256-byte aligned");
+    const char *src = static_cast<const char *>(d_src);
+    StateHeader hd{};
+    HIP_TRY(h, hipMemcpyAsync(&hd, src, sizeof hd, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (hd.magic != kStateMagic || hd.version != kStateVersion)
+        return fail(LB_EINVAL, "not a state buffer of this library version");
+    if (hd.precision != (uint32_t)h->prec || hd.n_ch != h->n_ch || hd.bytes != state_size(h))
+        return fail(LB_EINVAL, "state buffer belongs to a different configuration");
+    if (hd.t < 0)
+        return fail(LB_EINVAL, "negative step count in state");
+    std::vector<double> forces(2 * (size_t)h->n_ch);
+    size_t off = kStateHeader;
+    for (int ci = 0; ci < h->n_ch; ++ci) {
+        for (const Section &sec : state_sections(h, ci, hd.t)) {
+            HIP_TRY(h, hipMemcpy2DAsync(h->ws + sec.ws_off, sec.ws_pitch, src + off,
+                                        sec.row_bytes, sec.row_bytes, sec.rows,
+                                        hipMemcpyDeviceToDevice, h->stream));
+            off = align_up(off + sec.rows * sec.row_bytes, 256);
+        }
+        HIP_TRY(h, hipMemcpyAsync(&forces[2 * ci], src + off, 16, hipMemcpyDeviceToHost,
+                                  h->stream));
+        off = align_up(off + 2 * sizeof(double), 256);
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (int ci = 0; ci < h->n_ch; ++ci) {
+        if (!std::isfinite(forces[2 * ci]) || !std::isfinite(forces[2 * ci + 1]) ||
+            (!h->plan.chans[ci].has_r && forces[2 * ci + 1] != 0.0)) {
+            h->poisoned = true;
+            return fail(LB_ESTATE, "state buffer carries an invalid force; handle poisoned");
+        }
+        h->plan.chans[ci].gx = forces[2 * ci];
+        h->plan.chans[ci].gy = forces[2 * ci + 1];
+        launch_set_force(h->d_chans, ci, forces[2 * ci], forces[2 * ci + 1], h->stream);
+    }
+    launch_tick(h->d_tcount, hd.t - h->t, h->stream);
+    s = check_launch(h, "load_state");
+    if (s != LB_OK)
+        return s;
+    h->t = hd.t;
+    h->has_out = hd.t > 0;
+    return LB_OK;
+}
+
+int32_t lb_max_chunks(const lb_handle *h, int32_t ch)
+{
+    if (!h || ch < 0 || ch >= h->n_ch)
+        return 0;
+    return h->plan.chans[ch].max_chunks;
+}
+
+lb_status lb_set_chunks(lb_handle *h, int32_t ch, int32_t n_chunks)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (ch < 0 || ch >= h->n_ch)
+        return fail(LB_EINVAL, "channel index out of range");
+    ChanDev &c = h->plan.chans[ch];
+    if (n_chunks < 1 || n_chunks > c.max_chunks)
+        return fail(LB_EINVAL, "n_chunks must be in [1, lb_max_chunks]");
+    c.nchunks = n_chunks;
+    build_tiles(h);
+    return upload_tables(h);
+}
+
+lb_status lb_set_graph(lb_handle *h, int32_t steps_per_graph)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (steps_per_graph < 0 || steps_per_graph > 4096)
+        return fail(LB_EINVAL, "steps_per_graph must be in [0, 4096]");
+    h->graph_steps = steps_per_graph;
+    h->graph_dirty = true;
+    return LB_OK;
+}
+
+lb_status lb_profile(lb_handle *h, int32_t enable)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    h->profile = enable != 0;
+    // Enabling starts a fresh measurement.
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    s = resolve_timing(h);
+    if (s != LB_OK)
+        return s;
+    h->kernel_ms[0] = h->kernel_ms[1] = 0.0;
+    h->kernel_launches[0] = h->kernel_launches[1] = 0;
+    return LB_OK;
+}
+
+lb_status lb_kernel_time(lb_handle *h, int32_t which, double *total_ms, int64_t *launches)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (which < 0 || which > 1)
+        return fail(LB_EINVAL, "which must be 0 (history) or 1 (lattice)");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    s = resolve_timing(h);
+    if (s != LB_OK)
+        return s;
+    if (total_ms)
+        *total_ms = h->kernel_ms[which];
+    if (launches)
+        *launches = h->kernel_launches[which];
+    return LB_OK;
+}
+
+lb_status lb_destroy(lb_handle *h)
+{
+    if (!h)
+        return fail(LB_EINVAL, "handle is NULL");
+    if (h->graph_exec)
+        (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph)
+        (void)hipGraphDestroy(h->graph);
+    if (h->cap_stream)
+        (void)hipStreamDestroy(h->cap_stream);
+    for (int w = 0; w < 2; ++w)
+        for (auto &pr : h->pending[w]) {
+            h->free_events.push_back(pr.first);
+            h->free_events.push_back(pr.second);
+        }
+    for (hipEvent_t e : h->free_events)
+        (void)hipEventDestroy(e);
+    delete h;
+    return LB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+"""Python handle over liblbmax: torch owns the device memory and the stream.
+
+Every step of the computation runs in the library's HIP kernels; this class
+only allocates the workspace, forwards calls and converts outputs to numpy.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+
+
+def _precision_code(precision: str) -> int:
+    p = precision.lower()
+    if p in ("f64", "fp64", "float64", "double"):
+        return _lib.LB_F64
+    if p in ("f32", "fp32", "float32", "float"):
+        return _lib.LB_F32
+    raise ValueError(f"unknown precision {precision!r}")
+
+
+def make_descs(channels: Sequence) -> tuple:
+    """Fill lb_channel_desc records from objects with the channel attributes
+    (lx, ly, tau_lb, g_inf, tau_m, gamma_c, n_hist, gx, gy, u0).  Returns the
+    ctypes array and the list of u0 buffers it points into (keep alive)."""
+    n = len(channels)
+    arr = (_lib.ChannelDesc * n)()
+    keep = []
+    for i, ch in enumerate(channels):
+        d = arr[i]
+        d.lx, d.ly = int(ch.lx), int(ch.ly)
+        d.tau_lb = float(ch.tau_lb)
+        d.g_inf, d.tau_m, d.gamma_c = float(ch.g_inf), float(ch.tau_m), float(ch.gamma_c)
+        d.n_hist = int(ch.n_hist)
+        d.gx, d.gy = float(ch.gx), float(getattr(ch, "gy", 0.0))
+        u0 = getattr(ch, "u0", None)
+        if u0 is not None:
+            buf = np.ascontiguousarray(np.asarray(u0, dtype=np.float64).reshape(2, ch.ly, ch.lx))
+            keep.append(buf)
+            d.u0 = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            d.u0 = None
+    return arr, keep
+
+
+def workspace_bytes(channels: Sequence, precision: str = "f32") -> int:
+    lib = _lib.load()
+    arr, _keep = make_descs(channels)
+    nbytes = lib.lb_workspace_bytes(arr, len(channels), _precision_code(precision))
+    if nbytes == 0:
+        raise _lib.LBError(_lib.LB_EINVAL, "lb_workspace_bytes", _lib.last_error())
+    return int(nbytes)
+
+
+class Solver:
+    """A set of channels advanced together on one GPU.
+
+    channels: sequence of channel descriptions (see make_descs).
+    precision: "f32" (FP32 populations and Kahan history sums, FP64 strain)
+    or "f64".
+    """
+
+    def __init__(self, channels: Sequence, precision: str = "f32",
+                 device: str = "cuda:0", stream=None):
+        import torch
+
+        self.lib = _lib.load()
+        self.channels = list(channels)
+        self.precision = precision
+        self.prec_code = _precision_code(precision)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        arr, keep = make_descs(self.channels)
+        nbytes = self.lib.lb_workspace_bytes(arr, len(self.channels), self.prec_code)
+        if nbytes == 0:
+            raise _lib.LBError(_lib.LB_EINVAL, "lb_workspace_bytes", _lib.last_error())
+        self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self.lib.lb_init(arr, len(self.channels), self.prec_code,
+                                  ctypes.c_void_p(self.ws.data_ptr()), int(nbytes),
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        del keep
+        _lib.check(st, "lb_init")
+        self.h = h
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- stepping ----------------------------------------------------------
+    @property
+    def t(self) -> int:
+        return int(self.lib.lb_time(self.h))
+
+    def step(self, n: int = 1):
+        _lib.check(self.lib.lb_step(self.h, int(n)), "lb_step")
+
+    def set_force(self, ch: int, gx: float, gy: float = 0.0):
+        _lib.check(self.lib.lb_set_force(self.h, int(ch), float(gx), float(gy)), "lb_set_force")
+
+    def set_graph(self, steps_per_graph: int):
+        _lib.check(self.lib.lb_set_graph(self.h, int(steps_per_graph)), "lb_set_graph")
+
+    def max_chunks(self, ch: int) -> int:
+        return int(self.lib.lb_max_chunks(self.h, int(ch)))
+
+    def set_chunks(self, ch: int, n_chunks: int):
+        _lib.check(self.lib.lb_set_chunks(self.h, int(ch), int(n_chunks)), "lb_set_chunks")
+
+    # -- readouts (FP64 numpy, [ly][lx]) -------------------------------------
+    def _shape(self, ch):
+        c = self.channels[ch]
+        return (int(c.ly), int(c.lx))
+
+    def fields(self, ch: int = 0):
+        sh = self._shape(ch)
+        rho, ux, uy = (np.empty(sh) for _ in range(3))
+        P = ctypes.POINTER(ctypes.c_double)
+        _lib.check(self.lib.lb_fields(self.h, int(ch), rho.ctypes.data_as(P),
+                                      ux.ctypes.data_as(P), uy.ctypes.data_as(P)), "lb_fields")
+        return rho, ux, uy
+
+    def stress(self, ch: int = 0):
+        sh = self._shape(ch)
+        sxy, n1 = np.empty(sh), np.empty(sh)
+        P = ctypes.POINTER(ctypes.c_double)
+        _lib.check(self.lib.lb_stress(self.h, int(ch), sxy.ctypes.data_as(P),
+                                      n1.ctypes.data_as(P)), "lb_stress")
+        return sxy, n1
+
+    def grad(self, ch: int = 0):
+        k = np.empty((4,) + self._shape(ch))
+        P = ctypes.POINTER(ctypes.c_double)
+        _lib.check(self.lib.lb_grad(self.h, int(ch), k.ctypes.data_as(P)), "lb_grad")
+        return k
+
+    # -- state ---------------------------------------------------------------
+    def state_bytes(self) -> int:
+        return int(self.lib.lb_state_bytes(self.h))
+
+    def save_state(self, buf=None):
+        import torch
+        if buf is None:
+            buf = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        _lib.check(self.lib.lb_save_state(self.h, ctypes.c_void_p(buf.data_ptr())), "lb_save_state")
+        return buf
+
+    def load_state(self, buf):
+        _lib.check(self.lib.lb_load_state(self.h, ctypes.c_void_p(buf.data_ptr())), "lb_load_state")
+
+    # -- timing ---------------------------------------------------------------
+    def profile(self, enable: bool = True):
+        _lib.check(self.lib.lb_profile(self.h, 1 if enable else 0), "lb_profile")
+
+    def kernel_time(self, which: int = 0):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _lib.check(self.lib.lb_kernel_time(self.h, int(which), ctypes.byref(ms),
+                                           ctypes.byref(cnt)), "lb_kernel_time")
+        return ms.value, cnt.value
+
+
+def state_layout(channels: Sequence, precision: str = "f32"):
+    """Byte offsets of the sections of a state buffer (include/lbmax.h)."""
+    R = 8 if _precision_code(precision) == _lib.LB_F64 else 4
+
+    def up(x):
+        return (x + 255) // 256 * 256
+
+    off = 256
+    out = []
+    for ch in channels:
+        N = int(ch.lx) * int(ch.ly)
+        uni = (int(ch.lx) == 1 and float(getattr(ch, "gy", 0.0)) == 0.0 and
+               (getattr(ch, "u0", None) is None or
+                not np.any(np.asarray(ch.u0, dtype=np.float64).reshape(2, -1)[1])))
+        sec = {}
+        for name, rows in (("pop", 9), ("sig", 2), ("vel", 2), ("drho", 1),
+                           ("ring_s", int(ch.n_hist))) + ((() if uni else (("ring_r", int(ch.n_hist)),))):
+            sec[name] = (off, rows, N)
+            off = up(off + rows * N * R)
+        sec["force"] = (off, 1, 2)
+        off = up(off + 16)
+        out.append(sec)
+    return out, off

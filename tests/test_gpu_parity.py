@@ -1,0 +1,302 @@
+"""GPU parity: the HIP path (through the C interface) against the FP64 oracle
+on identical seeded inputs.
+
+Error metric per output X: max over samples and nodes of |X_gpu - X_ref|,
+divided by max over samples and nodes of |X_ref| (normalised max-norm; it
+stays meaningful through zero crossings of the velocity during cessation).
+Tolerances: FP64 path 1e-12 (rounding-order differences only); FP32 path
+1e-5 for velocity and 1e-4 for sigma_xy and N1.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = {"ux": 1e-5, "uy": 1e-5, "sxy": 1e-4, "n1": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_06123_amd import Solver as S, _lib
+    assert os.path.exists(_lib.LIB_PATH), "liblbmax.so not built"
+    return S
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def nerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a).max())
+
+
+def run_gpu(Solver, chans, precision, steps, every, steps_on=None, chunks=None, graph=0):
+    """Advance all channels together; sample every `every` steps.  The force
+    goes to zero after steps_on steps (cessation)."""
+    steps_on = steps if steps_on is None else steps_on
+    out = [{k: [] for k in ("ux", "uy", "rho", "sxy", "n1")} for _ in chans]
+    with Solver(chans, precision=precision) as s:
+        if chunks is not None:
+            for ci, nc in enumerate(chunks):
+                s.set_chunks(ci, nc)
+        if graph:
+            s.set_graph(graph)
+        marks = sorted({m for m in list(range(every, steps + 1, every)) + [steps_on, steps]
+                        if 0 < m <= steps})
+        done = 0
+        for m in marks:
+            if done >= steps_on:
+                for ci in range(len(chans)):
+                    s.set_force(ci, 0.0, 0.0)
+            s.step(m - done)
+            done = m
+            if done % every == 0:
+                for ci in range(len(chans)):
+                    rho, ux, uy = s.fields(ci)
+                    sxy, n1 = s.stress(ci)
+                    for k, v in (("ux", ux), ("uy", uy), ("rho", rho), ("sxy", sxy), ("n1", n1)):
+                        out[ci][k].append(v)
+    return [{k: np.array(v) for k, v in o.items()} for o in out]
+
+
+def run_oracle(chans, steps, every, steps_on=None):
+    wl = workloads.Workload("t", list(chans), "f64", steps_on=steps if steps_on is None else steps_on,
+                            steps_off=0 if steps_on is None else steps - steps_on,
+                            sample_every=every)
+    return oracle.run_workload(wl, steps=steps, sample_every=every)
+
+
+def compare(gpu, ref, tol, keys=("ux", "sxy", "n1"), label=""):
+    errs = {k: nerr(gpu[k], ref[k]) for k in keys}
+    say(f"  {label} errors: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        t = tol[k] if isinstance(tol, dict) else tol
+        assert v <= t, f"{label} {k}: {v:.3e} > {t:.1e}"
+    return errs
+
+
+# ---------------------------------------------------------------------------
+# FP64 path
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("chunks", [None, 1])
+def test_plain_f64_channel(Solver, chunks):
+    """4 x 16 channel, FP64, tau = 100, window 1000, startup, 2000 steps."""
+    wl = workloads.plain_f64()
+    say(f"case plain_f64 chunks={chunks}")
+    gpu = run_gpu(Solver, wl.channels, "f64", 2000, 100,
+                  chunks=None if chunks is None else [chunks])[0]
+    ref = run_oracle(wl.channels, 2000, 100)[0]
+    compare(gpu, ref, TOL64, keys=("ux", "uy", "rho", "sxy", "n1"), label="plain_f64")
+
+
+def test_f64_gradient_readout(Solver):
+    ch = workloads.large_2d(lx=6, ly=9, n_hist=64).channels[0]
+    say("case f64 gradient 6x9")
+    with Solver([ch], precision="f64") as s:
+        s.step(37)
+        k = s.grad(0)
+    oc = oracle.OracleChannel(ch)
+    oc.step(37)
+    kr = oc.grad()
+    for i in range(4):
+        assert nerr(k[i], kr[i]) < TOL64
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("min_width_ly3", dict(lx=1, ly=3, n_hist=2)),
+    ("ragged_3x37", dict(lx=3, ly=37, n_hist=300)),
+    ("newtonian", dict(lx=2, ly=20, g_inf=0.0, n_hist=50)),
+    ("ucm", dict(lx=1, ly=24, gamma_c=math.inf, n_hist=400, tau_m=60.0)),
+    ("ragged_window_1000", dict(lx=5, ly=70, n_hist=1000, tau_m=80.0)),
+])
+def test_f64_edge_cases(Solver, name, kw):
+    ch = workloads.plain_f64().channels[0].replace(gx=2e-5, **kw)
+    say(f"case f64 edge {name}")
+    gpu = run_gpu(Solver, [ch], "f64", 700, 100, steps_on=450)[0]
+    ref = run_oracle([ch], 700, 100, steps_on=450)[0]
+    keys = ("ux", "uy", "rho") if ch.g_inf == 0 else ("ux", "uy", "rho", "sxy", "n1")
+    compare(gpu, ref, TOL64, keys=keys, label=name)
+
+
+def test_f64_2d_perturbed(Solver):
+    ch = workloads.large_2d(lx=24, ly=16, n_hist=256).channels[0].replace(tau_m=60.0)
+    say("case f64 2d perturbed 24x16")
+    gpu = run_gpu(Solver, [ch], "f64", 600, 100)[0]
+    ref = run_oracle([ch], 600, 100)[0]
+    compare(gpu, ref, TOL64, keys=("ux", "uy", "rho", "sxy", "n1"), label="f64_2d")
+
+
+# ---------------------------------------------------------------------------
+# FP32 path (Kahan history sums, FP64 strain)
+# ---------------------------------------------------------------------------
+
+def test_f32_startup_cessation_reduced(Solver):
+    """Quasi-1D startup then cessation, FP32 vs FP64 oracle."""
+    ch = workloads.startup_cessation().channels[0].replace(ly=64, n_hist=1024, tau_m=250.0, gx=5e-6)
+    say("case f32 startup/cessation 1x64")
+    gpu = run_gpu(Solver, [ch], "f32", 3000, 100, steps_on=1500)[0]
+    ref = run_oracle([ch], 3000, 100, steps_on=1500)[0]
+    compare(gpu, ref, TOL32, label="f32_startcess")
+
+
+def test_f32_2d_perturbed(Solver):
+    ch = workloads.large_2d(lx=32, ly=24, n_hist=512).channels[0].replace(tau_m=100.0)
+    say("case f32 2d perturbed 32x24")
+    gpu = run_gpu(Solver, [ch], "f32", 800, 100)[0]
+    ref = run_oracle([ch], 800, 100)[0]
+    compare(gpu, ref, TOL32, keys=("ux", "uy", "sxy", "n1"), label="f32_2d")
+
+
+def test_f32_batched_uneven_channels(Solver):
+    """Several channels of uneven width and window in one handle: each must
+    match its own oracle run."""
+    wl = workloads.batched()
+    chans = [c.replace(n_hist=min(c.n_hist, 2048), tau_m=min(c.tau_m, 200.0))
+             for c in sorted(wl.channels, key=lambda c: c.ly)[::9]]
+    say(f"case f32 batched {[c.ly for c in chans]}")
+    gpu = run_gpu(Solver, chans, "f32", 600, 200)
+    ref = run_oracle(chans, 600, 200)
+    for ci in range(len(chans)):
+        compare(gpu[ci], ref[ci], TOL32, label=f"batched ch{ci} ly={chans[ci].ly}")
+
+
+# ---------------------------------------------------------------------------
+# Launch-shape invariance, determinism, graphs, state
+# ---------------------------------------------------------------------------
+
+def test_chunk_split_invariance(Solver):
+    ch = workloads.startup_cessation().channels[0].replace(ly=40, n_hist=2048, tau_m=300.0, gx=5e-6)
+    say("case chunk invariance")
+    a = run_gpu(Solver, [ch], "f64", 500, 250, chunks=[1])[0]
+    for nc in (2, 7, 16):
+        b = run_gpu(Solver, [ch], "f64", 500, 250, chunks=[nc])[0]
+        for k in ("ux", "sxy", "n1"):
+            assert nerr(b[k], a[k]) < 1e-13, (nc, k)
+
+
+def test_bitwise_determinism_and_graph_replay(Solver):
+    ch = workloads.large_2d(lx=16, ly=20, n_hist=300).channels[0].replace(tau_m=50.0)
+    say("case determinism + graph")
+    a = run_gpu(Solver, [ch], "f32", 400, 100)[0]
+    b = run_gpu(Solver, [ch], "f32", 400, 100)[0]
+    c = run_gpu(Solver, [ch], "f32", 400, 100, graph=32)[0]
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
+
+
+def test_save_load_resume_bitwise(Solver):
+    ch = workloads.large_2d(lx=8, ly=12, n_hist=200).channels[0].replace(tau_m=40.0)
+    say("case save/load")
+    with Solver([ch], precision="f32") as s:
+        s.step(150)
+        buf = s.save_state()
+        s.step(77)
+        want = s.fields(0), s.stress(0)
+        s.step(5)
+        s.load_state(buf)
+        assert s.t == 150
+        s.step(77)
+        got = s.fields(0), s.stress(0)
+    for a, b in zip(want, got):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_readout_before_first_step_is_state_error(Solver):
+    from paper_1504_06123_amd import LBError
+    ch = workloads.plain_f64().channels[0]
+    with Solver([ch], precision="f64") as s:
+        with pytest.raises(LBError) as ei:
+            s.fields(0)
+        assert ei.value.status == -4
+        with pytest.raises(LBError):
+            s.set_force(3, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Full-size 2D channel 1024 x 512, window 4096, in the benchmark's launch
+# configuration
+# ---------------------------------------------------------------------------
+
+def test_large_2d_full_size_first_steps(Solver):
+    """First 12 steps of the full-size perturbed channel, every node."""
+    wl = workloads.large_2d()
+    ch = wl.channels[0]
+    say("case large_2d full size, 12 steps")
+    with Solver([ch], precision="f32") as s:
+        s.step(12)
+        _, ux, uy = s.fields(0)
+        sxy, n1 = s.stress(0)
+    oc = oracle.OracleChannel(ch)
+    oc.step(12)
+    _, rux, ruy = oc.fields()
+    rsxy, rn1 = oc.stress()
+    errs = dict(ux=nerr(ux, rux), uy=nerr(uy, ruy), sxy=nerr(sxy, rsxy), n1=nerr(n1, rn1))
+    say(f"  errors {errs}")
+    for k, v in errs.items():
+        assert v <= TOL32[k], (k, v)
+
+
+def test_large_2d_full_size_synthetic_window(Solver):
+    """Full-size ring with seeded random history at an arbitrary step (the
+    window wraps): sigma at sampled nodes against the oracle's history sum
+    of the same inputs.  Fluid at rest, so the pushed entry is zero."""
+    import torch
+    from paper_1504_06123_amd import state_layout
+    ch = workloads.large_2d(perturb=False).channels[0].replace(gx=0.0)
+    H, N = ch.n_hist, ch.nodes
+    t_now = 3 * H + 1234
+    say("case large_2d full size synthetic window")
+    secs, total = state_layout([ch], "f32")
+    sec = secs[0]
+    gen = torch.Generator(device="cuda").manual_seed(1504)
+    with Solver([ch], precision="f32") as s:
+        assert s.state_bytes() == total
+        st = torch.zeros(total, dtype=torch.uint8, device="cuda")
+        hdr = np.zeros(32, dtype=np.uint8)
+        hdr[:8] = np.frombuffer(np.uint64(0x4C424D4158535431).tobytes(), np.uint8)
+        hdr[8:12] = np.frombuffer(np.uint32(1).tobytes(), np.uint8)
+        hdr[12:16] = np.frombuffer(np.uint32(1).tobytes(), np.uint8)
+        hdr[16:24] = np.frombuffer(np.int64(t_now).tobytes(), np.uint8)
+        hdr[24:28] = np.frombuffer(np.int32(1).tobytes(), np.uint8)
+        hdr_full = np.concatenate([hdr, np.frombuffer(np.uint64(total).tobytes(), np.uint8)])
+        st[:40] = torch.from_numpy(hdr_full).cuda()
+        off, rows, n = sec["ring_s"]
+        ring_s = st[off:off + rows * n * 4].view(torch.float32).view(rows, n)
+        ring_s.uniform_(-1e-3, 1e-3, generator=gen)
+        off, rows, n = sec["ring_r"]
+        ring_r = st[off:off + rows * n * 4].view(torch.float32).view(rows, n)
+        ring_r.uniform_(0.0, 2e-3, generator=gen)
+        s.load_state(st)
+        s.step(1)
+        sxy, n1 = s.stress(0)
+        rng = np.random.default_rng(7)
+        nodes = rng.choice(N, size=24, replace=False)
+        cols_s = ring_s[:, torch.from_numpy(nodes).cuda()].double().cpu().numpy()
+        cols_r = ring_r[:, torch.from_numpy(nodes).cuda()].double().cpu().numpy()
+    t = t_now  # the step just taken
+    for j, node in enumerate(nodes):
+        s_age = np.zeros(H)
+        r_age = np.zeros(H)
+        for k in range(1, H):
+            slot = (t - k) % H
+            s_age[k] = cols_s[slot, j]
+            r_age[k] = cols_r[slot, j]
+        rxy, rxx = oracle.history_sum_ages(s_age, r_age, ch.g_inf, ch.tau_m, ch.gamma_c)
+        y, x = divmod(int(node), ch.lx)
+        assert abs(sxy[y, x] - rxy) <= 1e-4 * abs(rxy) + 1e-12 * ch.g_inf, (node, sxy[y, x], rxy)
+        assert abs(n1[y, x] - rxx) <= 1e-4 * abs(rxx) + 1e-12 * ch.g_inf, (node, n1[y, x], rxx)
