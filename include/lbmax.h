@@ -157,15 +157,21 @@ lb_status lb_save_state(lb_handle *h, void *d_dst);
 lb_status lb_load_state(lb_handle *h, const void *d_src);
 
 /*
- * Launch shaping (used by the autotuner).  lb_set_chunks splits channel
- * ch's history window into n_chunks >= 1 age ranges reduced by separate
- * workgroups and combined in FP64 in fixed order; it must not exceed
- * lb_max_chunks(h, ch).  lb_set_graph(h, s) replays s steps per hipGraph
- * launch inside lb_step (0 = plain launches).  Both take effect at the next
- * lb_step and change rounding only through the chunk split.
+ * Launch shaping (used by the autotuner).  lb_set_tiling sets, for channel
+ * ch, the number of age ranges its history window is split into
+ * (n_chunks in [1, lb_max_chunks(h, ch)]; the ranges are reduced by separate
+ * workgroups and combined in FP64 in a fixed order) and the nodes each lane
+ * of the history kernel owns (nodes_per_lane in {1, 2, 4}; one ring row is
+ * then read as a 1-, 2- or 4-wide vector).  lb_get_tiling reads the current
+ * choice.  lb_set_graph(h, s) replays s steps per hipGraph launch inside
+ * lb_step (0 = plain launches).  All take effect at the next lb_step; only
+ * the chunk split changes results, and only through rounding order.
  */
 int32_t lb_max_chunks(const lb_handle *h, int32_t ch);
-lb_status lb_set_chunks(lb_handle *h, int32_t ch, int32_t n_chunks);
+lb_status lb_set_tiling(lb_handle *h, int32_t ch, int32_t n_chunks,
+                        int32_t nodes_per_lane);
+lb_status lb_get_tiling(const lb_handle *h, int32_t ch, int32_t *n_chunks,
+                        int32_t *nodes_per_lane);
 lb_status lb_set_graph(lb_handle *h, int32_t steps_per_graph);
 
 /*

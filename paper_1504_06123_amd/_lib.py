@@ -53,7 +53,9 @@ SIGNATURES = {
     "lb_save_state": (ctypes.c_int, [_H, ctypes.c_void_p]),
     "lb_load_state": (ctypes.c_int, [_H, ctypes.c_void_p]),
     "lb_max_chunks": (ctypes.c_int32, [_H, ctypes.c_int32]),
-    "lb_set_chunks": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_int32]),
+    "lb_set_tiling": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "lb_get_tiling": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]),
     "lb_set_graph": (ctypes.c_int, [_H, ctypes.c_int32]),
     "lb_profile": (ctypes.c_int, [_H, ctypes.c_int32]),
     "lb_kernel_time": (ctypes.c_int, [_H, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64)]),

@@ -20,6 +20,7 @@ constexpr int64_t kPartialBudget = int64_t(1) << 22;  // chunks * stride cap
 struct alignas(256) ChanDev {
     int32_t lx, ly, n, np;          // nodes n = lx*ly, plane stride np
     int32_t n_hist, has_r, nchunks, max_chunks;
+    int32_t vec, pad_[3];           // history kernel: nodes per lane (1, 2, 4)
     double omega;                   // 1/tau_LB
     double g_inf;
     double inv_tau, inv_gc;         // 1/tau, 1/gamma_c (0 for gamma_c = inf)
@@ -40,7 +41,7 @@ struct NodeTile {
     int32_t ch, n0;
 };
 
-// One workgroup of the history kernel: 256 nodes x ages [k0, k1).
+// One workgroup of the history kernel: 256*vec nodes x ages [k0, k1).
 struct HistTile {
     int32_t ch, n0, k0, k1, chunk, pad;
 };
@@ -54,7 +55,8 @@ void launch_init(bool f64, char *ws, const ChanDev *chans, int ch,
 void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 void launch_lb(bool f64, char *ws, const ChanDev *chans, const NodeTile *tiles,
                int n_tiles, const int64_t *tcount, int trel, hipStream_t st);
-void launch_hist(bool f64, char *ws, const ChanDev *chans,
+// History kernel for the tiles of the channels whose lane width is `vec`.
+void launch_hist(bool f64, int vec, char *ws, const ChanDev *chans,
                  const HistTile *tiles, int n_tiles, const int64_t *tcount,
                  int trel, hipStream_t st);
 void launch_combine(bool f64, char *ws, const ChanDev *chans,

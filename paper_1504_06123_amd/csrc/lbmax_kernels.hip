@@ -281,125 +281,185 @@ __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
 }
 
 // ---------------------------------------------------------------------------
-// History integral over one age range, ages k = k0 .. k1-1 (slot p-k mod H),
-// for the lane's node.  8 ages are loaded before any is used so each wave
-// keeps 8 (16 with r) row reads in flight.
-//   A += s E,  B += 2 s gamma E,  gamma = running FP64 strain (loc),
-// with the trapezoid weight 1 (end weights are handled by the caller).
+// History integral.
+//
+// A workgroup owns kBlock*V consecutive nodes of one channel and one age
+// range [k0, k1) of their window; lane l owns nodes n0 + V*l .. n0 + V*l + V-1
+// and reads them as one V-wide vector per ring row.  Ages are walked newest
+// to oldest; U rows are loaded before any is used so each wavefront keeps U
+// (2U with |gamma_dot|) vector reads in flight.  Row addresses are uniform
+// across the workgroup, so a load is a scalar row base plus the lane's
+// 32-bit node offset.
+//   A += w s E,  B += w 2 s gamma E,  gamma = FP64 running strain (loc),
+// w = 1 inside the window; the end weights 1/2 are applied by the caller's
+// peeled first (age 0) and last (age n_hist-1) entries.
 // ---------------------------------------------------------------------------
-template <typename R, bool HAS_R>
+template <typename R, int V>
+struct alignas(sizeof(R) * V) Pack {
+    R v[V];
+};
+
+// row: uniform row base; off: the lane's byte offset within the row (32-bit,
+// so the load is a scalar base plus an unsigned vector offset).
+template <typename R, int V>
+__device__ __forceinline__ Pack<R, V> load_pack(const R *row, uint32_t off)
+{
+    return *reinterpret_cast<const Pack<R, V> *>(reinterpret_cast<const char *>(row) + off);
+}
+
+template <typename R>
+__device__ __forceinline__ void accumulate(R s, R r, R k, const Decay<R> &dec,
+                                           Acc<R> &A, Acc<R> &B, double &loc)
+{
+    loc += (double)s;
+    const R se = s * dec(k, r);
+    A.add(se);
+    B.add(R(2) * se * (R)loc);
+}
+
+template <typename R, int V, int U, bool HAS_R>
 __device__ __forceinline__ void hist_range(const R *__restrict__ ring_s,
                                            const R *__restrict__ ring_r,
-                                           size_t np, int node, int H, int p,
+                                           size_t np, uint32_t lane_off, int H, int p,
                                            int k0, int k1, const Decay<R> &dec,
-                                           Acc<R> &A, Acc<R> &B, double &loc)
+                                           Acc<R> (&A)[V], Acc<R> (&B)[V],
+                                           double (&loc)[V])
 {
     int k = k0;
     int slot = p - k;
     if (slot < 0)
         slot += H;
     while (k < k1) {
-        // contiguous run of slots going down without wrapping
+        // contiguous run of rows going down without wrapping
         const int run = min(k1 - k, slot + 1);
-        const R *ps = ring_s + (size_t)slot * np + node;
-        const R *pr = HAS_R ? ring_r + (size_t)slot * np + node : nullptr;
         int j = 0;
-        for (; j + 8 <= run; j += 8) {
-            R sv[8], rv[8];
+        for (; j + U <= run; j += U) {
+            Pack<R, V> sv[U], rv[U];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                sv[u] = ps[-(ptrdiff_t)(j + u) * (ptrdiff_t)np];
+            for (int u = 0; u < U; ++u) {
+                const size_t row = (size_t)(slot - j - u) * np;
+                sv[u] = load_pack<R, V>(ring_s + row, lane_off);
                 if (HAS_R)
-                    rv[u] = pr[-(ptrdiff_t)(j + u) * (ptrdiff_t)np];
+                    rv[u] = load_pack<R, V>(ring_r + row, lane_off);
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const R s = sv[u];
-                const R r = HAS_R ? rv[u] : fabs(s);
-                loc += (double)s;
-                const R e = dec(R(k + j + u), r);
-                const R se = s * e;
-                A.add(se);
-                B.add(R(2) * se * (R)loc);
+            for (int u = 0; u < U; ++u) {
+                const R kf = R(k + j + u);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const R s = sv[u].v[v];
+                    accumulate<R>(s, HAS_R ? rv[u].v[v] : fabs(s), kf, dec, A[v], B[v],
+                                  loc[v]);
+                }
             }
         }
         for (; j < run; ++j) {
-            const R s = ps[-(ptrdiff_t)j * (ptrdiff_t)np];
-            const R r = HAS_R ? pr[-(ptrdiff_t)j * (ptrdiff_t)np] : fabs(s);
-            loc += (double)s;
-            const R e = dec(R(k + j), r);
-            const R se = s * e;
-            A.add(se);
-            B.add(R(2) * se * (R)loc);
+            const size_t row = (size_t)(slot - j) * np;
+            const Pack<R, V> sv = load_pack<R, V>(ring_s + row, lane_off);
+            Pack<R, V> rv;
+            if (HAS_R)
+                rv = load_pack<R, V>(ring_r + row, lane_off);
+            const R kf = R(k + j);
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                accumulate<R>(sv.v[v], HAS_R ? rv.v[v] : fabs(sv.v[v]), kf, dec, A[v],
+                              B[v], loc[v]);
         }
         k += run;
         slot = H - 1;
     }
 }
 
-template <typename R, bool HAS_R>
+template <typename R, int V, int U, bool HAS_R>
 __device__ __forceinline__ void hist_tile(char *__restrict__ ws, const ChanDev *c,
                                           const HistTile &tl, int64_t t)
 {
     const int H = c->n_hist;
     const size_t np = (size_t)c->np;
-    const int n = tl.n0 + (int)threadIdx.x;
-    const bool live = n < c->n;
-    const int node = live ? n : c->n - 1;  // dead lanes shadow a live node
+    const int first = tl.n0 + (int)threadIdx.x * V;  // lane's first node
+    // A lane past the channel end shadows the last vector of the channel (in
+    // bounds, results discarded); nodes past the end inside a vector read the
+    // zero padding of the ring.
+    const int lane_node = first < c->n ? first : ((c->n - 1) / V) * V;
+    const uint32_t lane_off = (uint32_t)lane_node * (uint32_t)sizeof(R);
     const int p = (int)(t % H);
     R *ring_s = reinterpret_cast<R *>(ws + c->off_ring_s);
     R *ring_r = reinterpret_cast<R *>(ws + c->off_ring_r);
     const Decay<R> dec(c);
-    Acc<R> A, B;
-    double loc = 0.0;
+    Acc<R> A[V], B[V];
+    double loc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        loc[v] = 0.0;
     int k = tl.k0;
     if (k == 0) {
-        // Newest entry, age 0: gradient of this step's velocity, push it,
-        // and add it with the trapezoid weight 1/2 (E = 1, gamma = 0).
+        // Newest entry, age 0: gradient of this step's velocity, push it, and
+        // add it with the trapezoid weight 1/2 (E = 1, gamma = 0).
         const R *vel = reinterpret_cast<const R *>(ws + c->off_vel);
-        const int y = node / c->lx, x = node - y * c->lx;
-        R kxx, kxy, kyx, kyy;
-        velocity_gradient<R>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
-        const R s = kxy;
-        if (live) {
-            ring_s[(size_t)p * np + n] = s;
-            if (HAS_R)
-                ring_r[(size_t)p * np + n] = shear_rate<R>(kxx, kxy, kyx, kyy);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int node = first + v;
+            R s = R(0);
+            if (node < c->n) {
+                const int y = node / c->lx, x = node - y * c->lx;
+                R kxx, kxy, kyx, kyy;
+                velocity_gradient<R>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx,
+                                     kyy);
+                s = kxy;
+                ring_s[(size_t)p * np + node] = s;
+                if (HAS_R)
+                    ring_r[(size_t)p * np + node] = shear_rate<R>(kxx, kxy, kyx, kyy);
+            }
+            A[v].add(R(0.5) * s);
         }
-        A.add(R(0.5) * s);
         k = 1;
     }
     const bool oldest = tl.k1 == H;
-    hist_range<R, HAS_R>(ring_s, ring_r, np, node, H, p, k, oldest ? H - 1 : tl.k1,
-                         dec, A, B, loc);
+    hist_range<R, V, U, HAS_R>(ring_s, ring_r, np, lane_off, H, p, k,
+                               oldest ? H - 1 : tl.k1, dec, A, B, loc);
     if (oldest) {
         // Oldest entry, age H-1, trapezoid weight 1/2.
         int slot = p + 1;
         if (slot >= H)
             slot -= H;
-        const R s = ring_s[(size_t)slot * np + node];
-        const R r = HAS_R ? ring_r[(size_t)slot * np + node] : fabs(s);
-        loc += (double)s;
-        const R se = R(0.5) * s * dec(R(H - 1), r);
-        A.add(se);
-        B.add(R(2) * se * (R)loc);
+        const size_t row = (size_t)slot * np;
+        const Pack<R, V> sv = load_pack<R, V>(ring_s + row, lane_off);
+        Pack<R, V> rv;
+        if (HAS_R)
+            rv = load_pack<R, V>(ring_r + row, lane_off);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const R s = sv.v[v];
+            loc[v] += (double)s;
+            const R se = R(0.5) * s * dec(R(H - 1), HAS_R ? rv.v[v] : fabs(s));
+            A[v].add(se);
+            B[v].add(R(2) * se * (R)loc[v]);
+        }
     }
-    if (!live)
+    if (first >= c->n)
         return;
-    if (c->nchunks == 1) {
-        R *sig = reinterpret_cast<R *>(ws + c->off_sig);
-        sig[n] = (R)(c->g_inf * A.value());
-        sig[np + n] = (R)(c->g_inf * B.value());
-    } else {
-        double *part = reinterpret_cast<double *>(ws + c->off_part);
-        const size_t plane = (size_t)c->max_chunks * np;
-        part[(size_t)tl.chunk * np + n] = A.value();
-        part[plane + (size_t)tl.chunk * np + n] = B.value();
-        part[2 * plane + (size_t)tl.chunk * np + n] = loc;
+    R *sig = reinterpret_cast<R *>(ws + c->off_sig);
+    double *part = reinterpret_cast<double *>(ws + c->off_part);
+    const size_t plane = (size_t)c->max_chunks * np;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int node = first + v;
+        if (node >= c->n)
+            break;
+        if (c->nchunks == 1) {
+            sig[node] = (R)(c->g_inf * A[v].value());
+            sig[np + node] = (R)(c->g_inf * B[v].value());
+        } else {
+            const size_t at = (size_t)tl.chunk * np + node;
+            part[at] = A[v].value();
+            part[plane + at] = B[v].value();
+            part[2 * plane + at] = loc[v];
+        }
     }
 }
 
-template <typename R>
+// One launch per lane width V: the tiles of channels with c->vec == V.
+template <typename R, int V, int U>
 __global__ __launch_bounds__(kBlock) void k_hist(char *__restrict__ ws,
                                                  const ChanDev *__restrict__ chans,
                                                  const HistTile *__restrict__ tiles,
@@ -409,13 +469,13 @@ __global__ __launch_bounds__(kBlock) void k_hist(char *__restrict__ ws,
     const HistTile tl = tiles[blockIdx.x];
     const ChanDev *c = chans + tl.ch;
     // A wavefront whose nodes all lie past the channel has nothing to do.
-    if (tl.n0 + (int)(threadIdx.x & ~63u) >= c->n)
+    if (tl.n0 + (int)(threadIdx.x & ~63u) * V >= c->n)
         return;
     const int64_t t = *tcount + trel;
     if (c->has_r)
-        hist_tile<R, true>(ws, c, tl, t);
+        hist_tile<R, V, U, true>(ws, c, tl, t);
     else
-        hist_tile<R, false>(ws, c, tl, t);
+        hist_tile<R, V, U, false>(ws, c, tl, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -538,15 +598,31 @@ void launch_lb(bool f64, char *ws, const ChanDev *chans, const NodeTile *tiles,
                            chans, tiles, tcount, trel);
 }
 
-void launch_hist(bool f64, char *ws, const ChanDev *chans, const HistTile *tiles,
-                 int n_tiles, const int64_t *tcount, int trel, hipStream_t st)
+void launch_hist(bool f64, int vec, char *ws, const ChanDev *chans,
+                 const HistTile *tiles, int n_tiles, const int64_t *tcount, int trel,
+                 hipStream_t st)
 {
-    if (f64)
-        hipLaunchKernelGGL(k_hist<double>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
-                           chans, tiles, tcount, trel);
-    else
-        hipLaunchKernelGGL(k_hist<float>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
-                           chans, tiles, tcount, trel);
+    if (n_tiles <= 0)
+        return;
+#define LBMAX_HIST(R, V, U)                                                     \
+    hipLaunchKernelGGL((k_hist<R, V, U>), dim3(n_tiles), dim3(kBlock), 0, st, ws, \
+                       chans, tiles, tcount, trel)
+    if (f64) {
+        if (vec == 4)
+            LBMAX_HIST(double, 4, 4);
+        else if (vec == 2)
+            LBMAX_HIST(double, 2, 8);
+        else
+            LBMAX_HIST(double, 1, 8);
+    } else {
+        if (vec == 4)
+            LBMAX_HIST(float, 4, 4);
+        else if (vec == 2)
+            LBMAX_HIST(float, 2, 8);
+        else
+            LBMAX_HIST(float, 1, 8);
+    }
+#undef LBMAX_HIST
 }
 
 void launch_combine(bool f64, char *ws, const ChanDev *chans, const NodeTile *tiles,

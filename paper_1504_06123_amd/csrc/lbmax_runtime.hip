@@ -135,6 +135,7 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         c.has_r = unidirectional(d) ? 0 : 1;
         c.max_chunks = max_chunks_for(d.n_hist, c.np);
         c.nchunks = 1;
+        c.vec = 1;
         c.omega = 1.0 / d.tau_lb;
         c.g_inf = d.g_inf;
         c.inv_tau = 1.0 / d.tau_m;
@@ -200,6 +201,7 @@ struct lb_handle {
     HistTile *d_hist_tiles = nullptr;
     double *d_stage = nullptr;
     int n_node_tiles = 0, n_hist_tiles = 0;
+    int hist_group_begin[3] = {0, 0, 0}, hist_group_count[3] = {0, 0, 0};  // vec 1, 2, 4
     bool any_chunked = false;
     // host mirrors kept alive for asynchronous uploads
     std::vector<NodeTile> node_tiles;
@@ -252,7 +254,8 @@ lb_status usable(lb_handle *h)
 }
 
 // Split every channel's window into its chunks and list the workgroups,
-// longest age range first so uneven channels finish together.
+// longest age range first so uneven channels finish together.  A history
+// workgroup covers kBlock*vec nodes.
 void build_tiles(lb_handle *h)
 {
     h->node_tiles.clear();
@@ -264,19 +267,49 @@ void build_tiles(lb_handle *h)
             h->node_tiles.push_back({ci, n0});
         if (c.nchunks > 1)
             h->any_chunked = true;
+        const int span = kBlock * c.vec;
         for (int k = 0; k < c.nchunks; ++k) {
             const int k0 = (int)((int64_t)c.n_hist * k / c.nchunks);
             const int k1 = (int)((int64_t)c.n_hist * (k + 1) / c.nchunks);
-            for (int n0 = 0; n0 < c.n; n0 += kBlock)
+            for (int n0 = 0; n0 < c.n; n0 += span)
                 h->hist_tiles.push_back({ci, n0, k0, k1, k, 0});
         }
     }
+    // Group by lane width (one launch each), longest age range first inside
+    // a group.
+    auto group = [h](const HistTile &a) {
+        const int v = h->plan.chans[a.ch].vec;
+        return v == 4 ? 2 : (v == 2 ? 1 : 0);
+    };
     std::stable_sort(h->hist_tiles.begin(), h->hist_tiles.end(),
-                     [](const HistTile &a, const HistTile &b) {
+                     [&](const HistTile &a, const HistTile &b) {
+                         if (group(a) != group(b))
+                             return group(a) < group(b);
                          return (a.k1 - a.k0) > (b.k1 - b.k0);
                      });
+    for (int g = 0; g < 3; ++g)
+        h->hist_group_count[g] = 0;
+    for (const HistTile &tl : h->hist_tiles)
+        h->hist_group_count[group(tl)] += 1;
+    h->hist_group_begin[0] = 0;
+    h->hist_group_begin[1] = h->hist_group_count[0];
+    h->hist_group_begin[2] = h->hist_group_count[0] + h->hist_group_count[1];
     h->n_node_tiles = (int)h->node_tiles.size();
     h->n_hist_tiles = (int)h->hist_tiles.size();
+}
+
+// Default launch shape: wide lanes for large channels, and enough age chunks
+// that the history launch has about 2048 workgroups.
+void default_tiling(lb_handle *h)
+{
+    int total = 0;
+    for (ChanDev &c : h->plan.chans) {
+        c.vec = c.n >= (1 << 16) ? 4 : (c.n >= (1 << 12) ? 2 : 1);
+        total += (c.n + kBlock * c.vec - 1) / (kBlock * c.vec);
+    }
+    const int want = std::max(1, (2048 + total - 1) / total);
+    for (ChanDev &c : h->plan.chans)
+        c.nchunks = std::max(1, std::min(want, c.max_chunks));
 }
 
 lb_status upload_tables(lb_handle *h)
@@ -343,8 +376,11 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, bool timed)
         HIP_TRY(h, hipEventRecord(e[1], st));
         HIP_TRY(h, hipEventRecord(e[2], st));
     }
-    launch_hist(h->f64, h->ws, h->d_chans, h->d_hist_tiles, h->n_hist_tiles,
-                h->d_tcount, trel, st);
+    static const int kVec[3] = {1, 2, 4};
+    for (int g = 0; g < 3; ++g)
+        launch_hist(h->f64, kVec[g], h->ws, h->d_chans,
+                    h->d_hist_tiles + h->hist_group_begin[g], h->hist_group_count[g],
+                    h->d_tcount, trel, st);
     if (timed) {
         HIP_TRY(h, hipEventRecord(e[3], st));
         h->pending[1].push_back({e[0], e[1]});
@@ -504,14 +540,7 @@ lb_status lb_init(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec, vo
         h->n_hist.push_back(ch[i].n_hist);
     }
 
-    // Default split: enough workgroups to cover the chip (about 2048), never
-    // below kMinChunkLen ages per chunk.
-    int total_blocks = 0;
-    for (const ChanDev &c : h->plan.chans)
-        total_blocks += (c.n + kBlock - 1) / kBlock;
-    const int want = std::max(1, (2048 + total_blocks - 1) / total_blocks);
-    for (ChanDev &c : h->plan.chans)
-        c.nchunks = std::max(1, std::min(want, c.max_chunks));
+    default_tiling(h);
     build_tiles(h);
 
     auto bail = [&](lb_status s) {
@@ -723,7 +752,7 @@ int32_t lb_max_chunks(const lb_handle *h, int32_t ch)
     return h->plan.chans[ch].max_chunks;
 }
 
-lb_status lb_set_chunks(lb_handle *h, int32_t ch, int32_t n_chunks)
+lb_status lb_set_tiling(lb_handle *h, int32_t ch, int32_t n_chunks, int32_t nodes_per_lane)
 {
     lb_status s = usable(h);
     if (s != LB_OK)
@@ -733,9 +762,24 @@ lb_status lb_set_chunks(lb_handle *h, int32_t ch, int32_t n_chunks)
     ChanDev &c = h->plan.chans[ch];
     if (n_chunks < 1 || n_chunks > c.max_chunks)
         return fail(LB_EINVAL, "n_chunks must be in [1, lb_max_chunks]");
+    if (nodes_per_lane != 1 && nodes_per_lane != 2 && nodes_per_lane != 4)
+        return fail(LB_EINVAL, "nodes_per_lane must be 1, 2 or 4");
     c.nchunks = n_chunks;
+    c.vec = nodes_per_lane;
     build_tiles(h);
     return upload_tables(h);
+}
+
+lb_status lb_get_tiling(const lb_handle *h, int32_t ch, int32_t *n_chunks,
+                        int32_t *nodes_per_lane)
+{
+    if (!h || ch < 0 || ch >= h->n_ch)
+        return fail(LB_EINVAL, "bad handle or channel index");
+    if (n_chunks)
+        *n_chunks = h->plan.chans[ch].nchunks;
+    if (nodes_per_lane)
+        *nodes_per_lane = h->plan.chans[ch].vec;
+    return LB_OK;
 }
 
 lb_status lb_set_graph(lb_handle *h, int32_t steps_per_graph)

@@ -123,8 +123,18 @@ class Solver:
     def max_chunks(self, ch: int) -> int:
         return int(self.lib.lb_max_chunks(self.h, int(ch)))
 
-    def set_chunks(self, ch: int, n_chunks: int):
-        _lib.check(self.lib.lb_set_chunks(self.h, int(ch), int(n_chunks)), "lb_set_chunks")
+    def set_tiling(self, ch: int, n_chunks: int, nodes_per_lane: int = None):
+        """History-kernel launch shape of channel ch (age chunks, nodes per lane)."""
+        if nodes_per_lane is None:
+            nodes_per_lane = self.tiling(ch)[1]
+        _lib.check(self.lib.lb_set_tiling(self.h, int(ch), int(n_chunks), int(nodes_per_lane)),
+                   "lb_set_tiling")
+
+    def tiling(self, ch: int):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(self.lib.lb_get_tiling(self.h, int(ch), ctypes.byref(a), ctypes.byref(b)),
+                   "lb_get_tiling")
+        return a.value, b.value
 
     # -- readouts (FP64 numpy, [ly][lx]) -------------------------------------
     def _shape(self, ch):

@@ -47,15 +47,17 @@ def nerr(a, b):
     return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a).max())
 
 
-def run_gpu(Solver, chans, precision, steps, every, steps_on=None, chunks=None, graph=0):
+def run_gpu(Solver, chans, precision, steps, every, steps_on=None, chunks=None, graph=0,
+            vec=None):
     """Advance all channels together; sample every `every` steps.  The force
     goes to zero after steps_on steps (cessation)."""
     steps_on = steps if steps_on is None else steps_on
     out = [{k: [] for k in ("ux", "uy", "rho", "sxy", "n1")} for _ in chans]
     with Solver(chans, precision=precision) as s:
-        if chunks is not None:
-            for ci, nc in enumerate(chunks):
-                s.set_chunks(ci, nc)
+        for ci in range(len(chans)):
+            nc = s.tiling(ci)[0] if chunks is None else chunks[ci]
+            v = s.tiling(ci)[1] if vec is None else vec[ci]
+            s.set_tiling(ci, nc, v)
         if graph:
             s.set_graph(graph)
         marks = sorted({m for m in list(range(every, steps + 1, every)) + [steps_on, steps]
@@ -199,6 +201,19 @@ def test_chunk_split_invariance(Solver):
         b = run_gpu(Solver, [ch], "f64", 500, 250, chunks=[nc])[0]
         for k in ("ux", "sxy", "n1"):
             assert nerr(b[k], a[k]) < 1e-12, (nc, k)
+
+
+def test_lane_width_invariance_bitwise(Solver):
+    """Nodes per lane only changes which lane owns which node: the per-node
+    arithmetic and its order are the same, so results agree bit for bit."""
+    ch = workloads.large_2d(lx=40, ly=30, n_hist=700).channels[0].replace(tau_m=90.0)
+    say("case lane width invariance")
+    for prec in ("f32", "f64"):
+        a = run_gpu(Solver, [ch], prec, 300, 100, chunks=[3], vec=[1])[0]
+        for v in (2, 4):
+            b = run_gpu(Solver, [ch], prec, 300, 100, chunks=[3], vec=[v])[0]
+            for k in a:
+                assert np.array_equal(a[k], b[k]), (prec, v, k)
 
 
 def test_bitwise_determinism_and_graph_replay(Solver):
