@@ -134,9 +134,10 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  * device buffer holding the full state; lb_save_state copies the state into
  * it (stream-ordered), lb_load_state restores it.  Layout (all sections
  * 256-byte aligned, R = double for LB_F64, float for LB_F32):
- *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 1,
+ *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 2,
  *     uint32 precision, int64 t (completed steps), int32 n_ch,
- *     int32 reserved, uint64 total bytes;
+ *     int32 reserved, uint64 total bytes, int32 block length,
+ *     int32 block position (steps of the current block already done);
  *   then per channel, in order, N = lx*ly:
  *     pop  [9][N] R  post-collision populations of step t-1 minus the
  *                    weights a_i (before the first step: the initial state
@@ -149,6 +150,9 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  *     ring_s [n_hist][N] R  shear rate s(t') = kappa_xy, row t' mod n_hist
  *     ring_r [n_hist][N] R  |gamma_dot(t')| (absent for unidirectional
  *                           channels)
+ *     blk  [32][N] double   window sums of the block in progress (see
+ *                           lb_set_block); read only when the block
+ *                           position is not 0
  *     force  2 doubles: gx, gy.
  * Ring rows of times before t = 0 are zero.
  */
@@ -162,8 +166,9 @@ lb_status lb_load_state(lb_handle *h, const void *d_src);
  * (n_chunks in [1, lb_max_chunks(h, ch)]; the ranges are reduced by separate
  * workgroups and combined in FP64 in a fixed order) and the nodes each lane
  * of the history kernel owns (nodes_per_lane in {1, 2, 4}; one ring row is
- * then read as a 1-, 2- or 4-wide vector).  lb_get_tiling reads the current
- * choice.  lb_set_graph(h, s) replays s steps per hipGraph launch inside
+ * then read as a 1-, 2- or 4-wide vector; with temporal blocking of 2 or 4
+ * steps at most 2 are used, with 8 or 16 steps 1).  lb_get_tiling reads the
+ * lane width in use and the chunk count.  lb_set_graph(h, s) replays s steps per hipGraph launch inside
  * lb_step (0 = plain launches).  All take effect at the next lb_step; only
  * the chunk split changes results, and only through rounding order.
  */
@@ -175,9 +180,24 @@ lb_status lb_get_tiling(const lb_handle *h, int32_t ch, int32_t *n_chunks,
 lb_status lb_set_graph(lb_handle *h, int32_t steps_per_graph);
 
 /*
+ * Temporal blocking of the history integral.  Every history entry except
+ * the newest is known one step ahead, so one pass over the history ring can
+ * form the window sums of steps_per_pass (1, 2, 4, 8 or 16) consecutive steps;
+ * the following steps of the block add only the entries pushed since the
+ * pass and shift the accumulated strain by the strain since the pass, which
+ * enters the normal-stress sum affinely (Sec. III Eq. eeval: gamma(t,t') is a
+ * sum of the shear rate over [t', t)).  Results differ from unblocked
+ * stepping only by rounding order.  A change takes effect at the next step
+ * (which starts a new block); the graph length (lb_set_graph) must be a
+ * multiple of it.  Default 1.
+ */
+lb_status lb_set_block(lb_handle *h, int32_t steps_per_pass);
+int32_t lb_get_block(const lb_handle *h);
+
+/*
  * Per-kernel timing with HIP events recorded on the handle's stream around
- * every launch of the history kernel (which = 0) and the lattice kernel
- * (which = 1).  Enabled by lb_profile(h, 1) for plain launches;
+ * every history pass (which = 0, including the chunk combine), every lattice
+ * launch (which = 1) and every in-block history step (which = 2).  Enabled by lb_profile(h, 1) for plain launches;
  * lb_kernel_time returns the accumulated milliseconds and launch count and
  * synchronises the stream.
  */

@@ -13,7 +13,13 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kNodeAlign = 64;     // node-plane stride is a multiple of this
 constexpr int kMinChunkLen = 128;  // shortest age range of one history chunk
 constexpr int kMaxChunks = 64;     // most age ranges per channel
-constexpr int64_t kPartialBudget = int64_t(1) << 22;  // chunks * stride cap
+constexpr int64_t kPartialBudget = int64_t(1) << 21;  // chunks * stride cap
+constexpr int kMaxBlock = 16;      // most steps served by one history pass
+// Planes of the per-chunk partials and of the block sums (doubles, [plane][np]
+// per chunk): A_m at m, B_m at kMaxBlock + m, chunk strain total at kPlaneT.
+constexpr int kPlaneB = kMaxBlock;
+constexpr int kPlaneT = 2 * kMaxBlock;
+constexpr int kPartPlanes = 2 * kMaxBlock + 1;
 
 // Per-channel parameters and workspace offsets, read by every kernel.
 // 256 bytes so a table row never straddles two scalar cache lines twice.
@@ -32,7 +38,8 @@ struct alignas(256) ChanDev {
     int64_t off_rho;                // [np]     rho - 1
     int64_t off_ring_s;             // [n_hist][np] shear rate
     int64_t off_ring_r;             // [n_hist][np] |gamma_dot| (has_r only)
-    int64_t off_part;               // [3][max_chunks][np] doubles A, B, T
+    int64_t off_part;               // [kPartPlanes][max_chunks][np] doubles
+    int64_t off_blk;                // [2*kMaxBlock][np] doubles: block sums
 };
 static_assert(sizeof(ChanDev) == 256, "ChanDev layout");
 
@@ -55,12 +62,18 @@ void launch_init(bool f64, char *ws, const ChanDev *chans, int ch,
 void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 void launch_lb(bool f64, char *ws, const ChanDev *chans, const NodeTile *tiles,
                int n_tiles, const int64_t *tcount, int trel, hipStream_t st);
-// History kernel for the tiles of the channels whose lane width is `vec`.
-void launch_hist(bool f64, int vec, char *ws, const ChanDev *chans,
-                 const HistTile *tiles, int n_tiles, const int64_t *tcount,
-                 int trel, hipStream_t st);
-void launch_combine(bool f64, char *ws, const ChanDev *chans,
+// History pass (first step of a block of `block` steps) for the tiles of the
+// channels whose lane width is `vec`.
+void launch_hist_pass(bool f64, int vec, int block, char *ws, const ChanDev *chans,
+                      const HistTile *tiles, int n_tiles, const int64_t *tcount,
+                      int trel, hipStream_t st);
+// FP64 combine of chunk partials into sigma and the block sums.
+void launch_combine(bool f64, int block, char *ws, const ChanDev *chans,
                     const NodeTile *tiles, int n_tiles, hipStream_t st);
+// Step m (1 <= m < block) of a block: gradient, push, sigma from the block sums.
+void launch_hist_step(bool f64, int m, char *ws, const ChanDev *chans,
+                      const NodeTile *tiles, int n_tiles, const int64_t *tcount,
+                      int trel, hipStream_t st);
 void launch_tick(int64_t *tcount, int64_t add, hipStream_t st);
 void launch_set_force(ChanDev *chans, int ch, double gx, double gy,
                       hipStream_t st);

@@ -5,9 +5,11 @@
 //   k_lb      pull-stream + bounce-back, moments, force rho*g + div sigma^{t-1},
 //             half-force velocity, BGK collision with the forcing term
 //             (Sec. III: collision-streaming rule, Eqs. bodyforce, hydrofields)
-//   k_hist    velocity gradient, push of the shear history entry, and the
+//   history   velocity gradient, push of the shear history entry, and the
 //             history integral of Eq. (gitt) with the modulus of Eq. (nlmax)
-//             over the window of the last n_hist steps -> sigma^t
+//             over the window of the last n_hist steps -> sigma^t:
+//   k_hist_pass / k_hist_step: the history integral blocked in time (one
+//             ring pass serves a block of steps, see below)
 //   k_combine FP64 affine combination of per-chunk partial sums when a
 //             channel's window is split across workgroups.
 //
@@ -281,57 +283,99 @@ __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
 }
 
 // ---------------------------------------------------------------------------
-// History integral.
+// History integral, blocked in time.
 //
-// A workgroup owns kBlock*V consecutive nodes of one channel and one age
-// range [k0, k1) of their window; lane l owns nodes n0 + V*l .. n0 + V*l + V-1
-// and reads them as one V-wide vector per ring row.  Ages are walked newest
-// to oldest; U rows are loaded before any is used so each wavefront keeps U
-// (2U with |gamma_dot|) vector reads in flight.  Row addresses are uniform
-// across the workgroup, so a load is a scalar row base plus the lane's
-// 32-bit node offset.
-//   A += w s E,  B += w 2 s gamma E,  gamma = FP64 running strain (loc),
-// w = 1 inside the window; the end weights 1/2 are applied by the caller's
-// peeled first (age 0) and last (age n_hist-1) entries.
+// Sums over the window at step t (Eq. gitt with Eq. nlmax, trapezoid weights
+// w(a) = 1/2 at ages a = 0 and a = n_hist - 1, 1 inside):
+//   sigma_xy(t) = G sum_e w(a) s_e E(a, r_e),
+//   sigma_xx(t) = G sum_e w(a) 2 s_e gamma(t, e) E(a, r_e),
+// a = t - e, E(a, r) = exp(-a (1/tau + r/gamma_c)),
+// gamma(t, e) = s_e + ... + s_{t-1} (accumulated strain, Eq. eeval).
+//
+// Every entry but the newest is known before the step, so a pass over the
+// ring at the first step t0 of a block of M steps serves all M steps: for
+// m = 0..M-1 it forms, over the entries e <= t0 still in step t0+m's window,
+//   A_m = sum w(k+m) s_e E(k+m, r_e),  B_m = sum w(k+m) 2 s_e gamma(t0, e) E(k+m, r_e)
+// (k = t0 - e), with E(k+m) = E(k) q^m, q = exp(-(1/tau + r/gamma_c)).  At step
+// t0 + m the entries pushed since t0 are added directly and, because
+// gamma(t0+m, e) = gamma(t0, e) + Delta_m for every old entry with
+// Delta_m = s_{t0} + ... + s_{t0+m-1},
+//   sigma_xy = G (A_m + new),  sigma_xx = G (B_m + 2 Delta_m A_m + new).
+//
+// Pass layout: a workgroup owns kBlock*V consecutive nodes of one channel and
+// one age range [k0, k1); lane l owns nodes n0 + V*l .. n0 + V*l + V-1 and
+// reads them as one V-wide vector per ring row.  Ages are walked newest to
+// oldest (the running FP64 strain gamma is a sum over the rows already
+// read); U rows are loaded before any is used so each wavefront keeps U (2U
+// with |gamma_dot|) vector reads in flight.  In FP32 the U terms of a row
+// group are added plainly and the group sum enters the Kahan accumulator.
 // ---------------------------------------------------------------------------
 template <typename R, int V>
 struct alignas(sizeof(R) * V) Pack {
     R v[V];
 };
 
-// row: uniform row base; off: the lane's byte offset within the row (32-bit,
-// so the load is a scalar base plus an unsigned vector offset).
+// row: uniform row base; off: the lane's byte offset within the row.
 template <typename R, int V>
 __device__ __forceinline__ Pack<R, V> load_pack(const R *row, uint32_t off)
 {
     return *reinterpret_cast<const Pack<R, V> *>(reinterpret_cast<const char *>(row) + off);
 }
 
+__device__ __forceinline__ float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename R>
-__device__ __forceinline__ void accumulate(R s, R r, R k, const Decay<R> &dec,
-                                           Acc<R> &A, Acc<R> &B, double &loc)
+__device__ __forceinline__ R decay_rate(const Decay<R> &dec, R r)
 {
-    loc += (double)s;
-    const R se = s * dec(k, r);
-    A.add(se);
-    B.add(R(2) * se * (R)loc);
+    return dec.b * r + dec.a;
 }
 
-template <typename R, int V, int U, bool HAS_R>
-__device__ __forceinline__ void hist_range(const R *__restrict__ ring_s,
-                                           const R *__restrict__ ring_r,
-                                           size_t np, uint32_t lane_off, int H, int p,
-                                           int k0, int k1, const Decay<R> &dec,
-                                           Acc<R> (&A)[V], Acc<R> (&B)[V],
-                                           double (&loc)[V])
+// exp(-k * rate) in the precision's form (rate pre-scaled by log2(e) in FP32).
+__device__ __forceinline__ float decay_pow(float k, float rate)
 {
-    int k = k0;
+    return __builtin_amdgcn_exp2f(-k * rate);
+}
+__device__ __forceinline__ double decay_pow(double k, double rate)
+{
+    return exp(-k * rate);
+}
+
+// An entry whose ages touch a window end (age 0 at t0, or age k + m at the
+// far end for some m): per-m weight and window membership, direct exp.
+template <typename R, int M>
+__device__ __forceinline__ void edge_entry(R s, R r, int k, int H, double loc,
+                                           const Decay<R> &dec, Acc<R> (&A)[M],
+                                           Acc<R> (&B)[M])
+{
+    const R rate = decay_rate<R>(dec, r);
+    const R g2 = R(2) * (R)loc;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int a = k + m;
+        if (a <= H - 1) {
+            const R w = (a == 0 || a == H - 1) ? R(0.5) : R(1);
+            const R se = w * s * decay_pow(R(a), rate);
+            A[m].add(se);
+            B[m].add(se * g2);
+        }
+    }
+}
+
+// Interior ages [k, kend) of one chunk: every m has weight 1 and is in the
+// window.  Rows are visited newest to oldest, wrapping at row 0.
+template <typename R, int V, int M, int U, bool HAS_R>
+__device__ __forceinline__ void pass_bulk(const R *__restrict__ ring_s,
+                                          const R *__restrict__ ring_r, size_t np,
+                                          uint32_t lane_off, int H, int p, int k, int kend,
+                                          const Decay<R> &dec, Acc<R> (&A)[M][V],
+                                          Acc<R> (&B)[M][V], double (&loc)[V])
+{
     int slot = p - k;
     if (slot < 0)
         slot += H;
-    while (k < k1) {
-        // contiguous run of rows going down without wrapping
-        const int run = min(k1 - k, slot + 1);
+    while (k < kend) {
+        const int run = min(kend - k, slot + 1);  // rows down to 0 without wrap
         int j = 0;
         for (; j + U <= run; j += U) {
             Pack<R, V> sv[U], rv[U];
@@ -342,16 +386,43 @@ __device__ __forceinline__ void hist_range(const R *__restrict__ ring_s,
                 if (HAS_R)
                     rv[u] = load_pack<R, V>(ring_r + row, lane_off);
             }
+            // Plain partial sums of the U rows, started from the first row;
+            // x = s E(k+m) is carried along m by the factor q.
+            R pa[M][V], pb[M][V];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const R kf = R(k + j + u);
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const R s = sv[u].v[v];
-                    accumulate<R>(s, HAS_R ? rv[u].v[v] : fabs(s), kf, dec, A[v], B[v],
-                                  loc[v]);
+                    const R rate = decay_rate<R>(dec, HAS_R ? rv[u].v[v] : fabs(s));
+                    loc[v] += (double)s;
+                    const R g2 = R(2) * (R)loc[v];
+                    R x = s * decay_pow(kf, rate);
+                    R q = R(1);
+                    if (M > 1)
+                        q = decay_pow(R(1), rate);
+#pragma unroll
+                    for (int m = 0; m < M; ++m) {
+                        if (u == 0) {
+                            pa[m][v] = x;
+                            pb[m][v] = x * g2;
+                        } else {
+                            pa[m][v] += x;
+                            pb[m][v] = fused(x, g2, pb[m][v]);
+                        }
+                        if (m + 1 < M)
+                            x *= q;
+                    }
                 }
             }
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    A[m][v].add(pa[m][v]);
+                    B[m][v].add(pb[m][v]);
+                }
         }
         for (; j < run; ++j) {
             const size_t row = (size_t)(slot - j) * np;
@@ -361,17 +432,29 @@ __device__ __forceinline__ void hist_range(const R *__restrict__ ring_s,
                 rv = load_pack<R, V>(ring_r + row, lane_off);
             const R kf = R(k + j);
 #pragma unroll
-            for (int v = 0; v < V; ++v)
-                accumulate<R>(sv.v[v], HAS_R ? rv.v[v] : fabs(sv.v[v]), kf, dec, A[v],
-                              B[v], loc[v]);
+            for (int v = 0; v < V; ++v) {
+                const R s = sv.v[v];
+                const R rate = decay_rate<R>(dec, HAS_R ? rv.v[v] : fabs(s));
+                loc[v] += (double)s;
+                const R g2 = R(2) * (R)loc[v];
+                R x = s * decay_pow(kf, rate);
+                const R q = M > 1 ? decay_pow(R(1), rate) : R(1);
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    A[m][v].add(x);
+                    B[m][v].add(x * g2);
+                    if (m + 1 < M)
+                        x *= q;
+                }
+            }
         }
         k += run;
         slot = H - 1;
     }
 }
 
-template <typename R, int V, int U, bool HAS_R>
-__device__ __forceinline__ void hist_tile(char *__restrict__ ws, const ChanDev *c,
+template <typename R, int V, int M, int U, bool HAS_R>
+__device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *c,
                                           const HistTile &tl, int64_t t)
 {
     const int H = c->n_hist;
@@ -386,42 +469,53 @@ __device__ __forceinline__ void hist_tile(char *__restrict__ ws, const ChanDev *
     R *ring_s = reinterpret_cast<R *>(ws + c->off_ring_s);
     R *ring_r = reinterpret_cast<R *>(ws + c->off_ring_r);
     const Decay<R> dec(c);
-    Acc<R> A[V], B[V];
+    Acc<R> A[M][V], B[M][V];
     double loc[V];
 #pragma unroll
     for (int v = 0; v < V; ++v)
         loc[v] = 0.0;
     int k = tl.k0;
     if (k == 0) {
-        // Newest entry, age 0: gradient of this step's velocity, push it, and
-        // add it with the trapezoid weight 1/2 (E = 1, gamma = 0).
+        // Newest entry, age 0: gradient of this step's velocity, push it.
         const R *vel = reinterpret_cast<const R *>(ws + c->off_vel);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const int node = first + v;
-            R s = R(0);
+            R s = R(0), r = R(0);
             if (node < c->n) {
                 const int y = node / c->lx, x = node - y * c->lx;
                 R kxx, kxy, kyx, kyy;
                 velocity_gradient<R>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx,
                                      kyy);
                 s = kxy;
+                r = HAS_R ? shear_rate<R>(kxx, kxy, kyx, kyy) : fabs(s);
                 ring_s[(size_t)p * np + node] = s;
                 if (HAS_R)
-                    ring_r[(size_t)p * np + node] = shear_rate<R>(kxx, kxy, kyx, kyy);
+                    ring_r[(size_t)p * np + node] = r;
             }
-            A[v].add(R(0.5) * s);
+            Acc<R> a1[M], b1[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                a1[m] = A[m][v];
+                b1[m] = B[m][v];
+            }
+            edge_entry<R, M>(s, r, 0, H, 0.0, dec, a1, b1);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                A[m][v] = a1[m];
+                B[m][v] = b1[m];
+            }
         }
         k = 1;
     }
-    const bool oldest = tl.k1 == H;
-    hist_range<R, V, U, HAS_R>(ring_s, ring_r, np, lane_off, H, p, k,
-                               oldest ? H - 1 : tl.k1, dec, A, B, loc);
-    if (oldest) {
-        // Oldest entry, age H-1, trapezoid weight 1/2.
-        int slot = p + 1;
-        if (slot >= H)
-            slot -= H;
+    // Interior ages, then the ages whose k + m reaches the window end.
+    const int tail0 = max(k, H - M);
+    pass_bulk<R, V, M, U, HAS_R>(ring_s, ring_r, np, lane_off, H, p, k, min(tl.k1, tail0),
+                                 dec, A, B, loc);
+    for (int kk = max(k, tail0); kk < tl.k1; ++kk) {
+        int slot = p - kk;
+        if (slot < 0)
+            slot += H;
         const size_t row = (size_t)slot * np;
         const Pack<R, V> sv = load_pack<R, V>(ring_s + row, lane_off);
         Pack<R, V> rv;
@@ -431,40 +525,59 @@ __device__ __forceinline__ void hist_tile(char *__restrict__ ws, const ChanDev *
         for (int v = 0; v < V; ++v) {
             const R s = sv.v[v];
             loc[v] += (double)s;
-            const R se = R(0.5) * s * dec(R(H - 1), HAS_R ? rv.v[v] : fabs(s));
-            A[v].add(se);
-            B[v].add(R(2) * se * (R)loc[v]);
+            Acc<R> a1[M], b1[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                a1[m] = A[m][v];
+                b1[m] = B[m][v];
+            }
+            edge_entry<R, M>(s, HAS_R ? rv.v[v] : fabs(s), kk, H, loc[v], dec, a1, b1);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                A[m][v] = a1[m];
+                B[m][v] = b1[m];
+            }
         }
     }
     if (first >= c->n)
         return;
     R *sig = reinterpret_cast<R *>(ws + c->off_sig);
     double *part = reinterpret_cast<double *>(ws + c->off_part);
-    const size_t plane = (size_t)c->max_chunks * np;
+    double *blk = reinterpret_cast<double *>(ws + c->off_blk);
+    const size_t pplane = (size_t)c->max_chunks * np;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const int node = first + v;
         if (node >= c->n)
             break;
         if (c->nchunks == 1) {
-            sig[node] = (R)(c->g_inf * A[v].value());
-            sig[np + node] = (R)(c->g_inf * B[v].value());
+            sig[node] = (R)(c->g_inf * A[0][v].value());
+            sig[np + node] = (R)(c->g_inf * B[0][v].value());
+#pragma unroll
+            for (int m = 1; m < M; ++m) {
+                blk[m * np + node] = A[m][v].value();
+                blk[(kPlaneB + m) * np + node] = B[m][v].value();
+            }
         } else {
             const size_t at = (size_t)tl.chunk * np + node;
-            part[at] = A[v].value();
-            part[plane + at] = B[v].value();
-            part[2 * plane + at] = loc[v];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                part[m * pplane + at] = A[m][v].value();
+                part[(kPlaneB + m) * pplane + at] = B[m][v].value();
+            }
+            part[kPlaneT * pplane + at] = loc[v];
         }
     }
 }
 
-// One launch per lane width V: the tiles of channels with c->vec == V.
-template <typename R, int V, int U>
-__global__ __launch_bounds__(kBlock) void k_hist(char *__restrict__ ws,
-                                                 const ChanDev *__restrict__ chans,
-                                                 const HistTile *__restrict__ tiles,
-                                                 const int64_t *__restrict__ tcount,
-                                                 int trel)
+// One launch per (lane width V, block length M): the tiles of the channels
+// whose lane width is V.
+template <typename R, int V, int M, int U>
+__global__ __launch_bounds__(kBlock) void k_hist_pass(char *__restrict__ ws,
+                                                      const ChanDev *__restrict__ chans,
+                                                      const HistTile *__restrict__ tiles,
+                                                      const int64_t *__restrict__ tcount,
+                                                      int trel)
 {
     const HistTile tl = tiles[blockIdx.x];
     const ChanDev *c = chans + tl.ch;
@@ -473,21 +586,23 @@ __global__ __launch_bounds__(kBlock) void k_hist(char *__restrict__ ws,
         return;
     const int64_t t = *tcount + trel;
     if (c->has_r)
-        hist_tile<R, V, U, true>(ws, c, tl, t);
+        pass_tile<R, V, M, U, true>(ws, c, tl, t);
     else
-        hist_tile<R, V, U, false>(ws, c, tl, t);
+        pass_tile<R, V, M, U, false>(ws, c, tl, t);
 }
 
 // ---------------------------------------------------------------------------
 // FP64 combine of the per-chunk partials of a split window, newest chunk
-// first: sigma_xy = G sum_c A_c, sigma_xx = G sum_c (2 O_c A_c + B_c), where
+// first: A_m = sum_c A_{m,c}, B_m = sum_c (2 O_c A_{m,c} + B_{m,c}), where
 // O_c = sum of the strain totals T of the newer chunks (the accumulated
-// strain at the chunk's start).
+// strain at the chunk's start).  Writes sigma of the pass step and the block
+// sums for the following steps.
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_combine(char *__restrict__ ws,
                                                     const ChanDev *__restrict__ chans,
-                                                    const NodeTile *__restrict__ tiles)
+                                                    const NodeTile *__restrict__ tiles,
+                                                    int block)
 {
     const NodeTile tl = tiles[blockIdx.x];
     const ChanDev *c = chans + tl.ch;
@@ -495,20 +610,85 @@ __global__ __launch_bounds__(kBlock) void k_combine(char *__restrict__ ws,
     if (c->nchunks == 1 || n >= c->n)
         return;
     const size_t np = (size_t)c->np;
-    const size_t plane = (size_t)c->max_chunks * np;
+    const size_t pplane = (size_t)c->max_chunks * np;
     const double *part = reinterpret_cast<const double *>(ws + c->off_part);
-    double O = 0.0, sxy = 0.0, sxx = 0.0;
+    double A[kMaxBlock], B[kMaxBlock];
+    for (int m = 0; m < block; ++m)
+        A[m] = B[m] = 0.0;
+    double O = 0.0;
     for (int k = 0; k < c->nchunks; ++k) {
-        const double A = part[k * np + n];
-        const double B = part[plane + k * np + n];
-        const double T = part[2 * plane + k * np + n];
-        sxy += A;
-        sxx += 2.0 * O * A + B;
-        O += T;
+        const size_t at = (size_t)k * np + n;
+        for (int m = 0; m < block; ++m) {
+            const double a = part[m * pplane + at];
+            A[m] += a;
+            B[m] += 2.0 * O * a + part[(kPlaneB + m) * pplane + at];
+        }
+        O += part[kPlaneT * pplane + at];
     }
     R *sig = reinterpret_cast<R *>(ws + c->off_sig);
-    sig[n] = (R)(c->g_inf * sxy);
-    sig[np + n] = (R)(c->g_inf * sxx);
+    sig[n] = (R)(c->g_inf * A[0]);
+    sig[np + n] = (R)(c->g_inf * B[0]);
+    double *blk = reinterpret_cast<double *>(ws + c->off_blk);
+    for (int m = 1; m < block; ++m) {
+        blk[m * np + n] = A[m];
+        blk[(kPlaneB + m) * np + n] = B[m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step t = t0 + m of a block (1 <= m < M): gradient and push of entry t, then
+// sigma from the block sums plus the entries t0+1 .. t pushed since the pass.
+// Walking ages a = 0..m from the new entry back to entry t0 accumulates the
+// strain gamma(t, t - a); at a = m it is Delta_m.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
+                                                      const ChanDev *__restrict__ chans,
+                                                      const NodeTile *__restrict__ tiles,
+                                                      const int64_t *__restrict__ tcount,
+                                                      int trel, int m)
+{
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const int n = tl.n0 + threadIdx.x;
+    if (n >= c->n)
+        return;
+    const int64_t t = *tcount + trel;
+    const int H = c->n_hist;
+    const size_t np = (size_t)c->np;
+    const int p = (int)(t % H);
+    R *ring_s = reinterpret_cast<R *>(ws + c->off_ring_s);
+    R *ring_r = reinterpret_cast<R *>(ws + c->off_ring_r);
+    const R *vel = reinterpret_cast<const R *>(ws + c->off_vel);
+    const int y = n / c->lx, x = n - y * c->lx;
+    R kxx, kxy, kyx, kyy;
+    velocity_gradient<R>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
+    const R s_new = kxy;
+    ring_s[(size_t)p * np + n] = s_new;
+    if (c->has_r)
+        ring_r[(size_t)p * np + n] = shear_rate<R>(kxx, kxy, kyx, kyy);
+
+    const double *blk = reinterpret_cast<const double *>(ws + c->off_blk);
+    const double A = blk[m * np + n];
+    const double B = blk[(kPlaneB + m) * np + n];
+    // newest entry: age 0, weight 1/2, E = 1, gamma = 0
+    double sxy = 0.5 * (double)s_new, sxx = 0.0, gam = 0.0;
+    int slot = p;
+    for (int a = 1; a <= m; ++a) {
+        slot = slot == 0 ? H - 1 : slot - 1;
+        const double s = (double)ring_s[(size_t)slot * np + n];
+        gam += s;
+        if (a < m && a <= H - 1) {
+            const double r = c->has_r ? (double)ring_r[(size_t)slot * np + n] : fabs(s);
+            const double w = (a == H - 1) ? 0.5 : 1.0;
+            const double e = exp(-(double)a * (c->inv_tau + c->inv_gc * r));
+            sxy += w * s * e;
+            sxx += w * 2.0 * s * gam * e;
+        }
+    }
+    R *sig = reinterpret_cast<R *>(ws + c->off_sig);
+    sig[n] = (R)(c->g_inf * (A + sxy));
+    sig[np + n] = (R)(c->g_inf * (B + 2.0 * gam * A + sxx));
 }
 
 __global__ void k_tick(int64_t *tcount, int64_t add)
@@ -598,42 +778,68 @@ void launch_lb(bool f64, char *ws, const ChanDev *chans, const NodeTile *tiles,
                            chans, tiles, tcount, trel);
 }
 
-void launch_hist(bool f64, int vec, char *ws, const ChanDev *chans,
-                 const HistTile *tiles, int n_tiles, const int64_t *tcount, int trel,
-                 hipStream_t st)
+void launch_hist_pass(bool f64, int vec, int block, char *ws, const ChanDev *chans,
+                      const HistTile *tiles, int n_tiles, const int64_t *tcount, int trel,
+                      hipStream_t st)
 {
     if (n_tiles <= 0)
         return;
-#define LBMAX_HIST(R, V, U)                                                     \
-    hipLaunchKernelGGL((k_hist<R, V, U>), dim3(n_tiles), dim3(kBlock), 0, st, ws, \
-                       chans, tiles, tcount, trel)
-    if (f64) {
-        if (vec == 4)
-            LBMAX_HIST(double, 4, 4);
-        else if (vec == 2)
-            LBMAX_HIST(double, 2, 8);
-        else
-            LBMAX_HIST(double, 1, 8);
-    } else {
-        if (vec == 4)
-            LBMAX_HIST(float, 4, 4);
-        else if (vec == 2)
-            LBMAX_HIST(float, 2, 8);
-        else
-            LBMAX_HIST(float, 1, 8);
-    }
-#undef LBMAX_HIST
+#define LBMAX_PASS(R, V, M, U)                                                   \
+    hipLaunchKernelGGL((k_hist_pass<R, V, M, U>), dim3(n_tiles), dim3(kBlock), 0, st, \
+                       ws, chans, tiles, tcount, trel)
+#define LBMAX_PASS_V(R)                                                          \
+    do {                                                                         \
+        if (block == 1) {                                                        \
+            if (vec == 4)                                                        \
+                LBMAX_PASS(R, 4, 1, 4);                                          \
+            else if (vec == 2)                                                   \
+                LBMAX_PASS(R, 2, 1, 8);                                          \
+            else                                                                 \
+                LBMAX_PASS(R, 1, 1, 8);                                          \
+        } else if (block == 2) {                                                 \
+            if (vec == 1)                                                        \
+                LBMAX_PASS(R, 1, 2, 8);                                          \
+            else                                                                 \
+                LBMAX_PASS(R, 2, 2, 4);                                          \
+        } else if (block == 4) {                                                 \
+            if (vec == 1)                                                        \
+                LBMAX_PASS(R, 1, 4, 8);                                          \
+            else                                                                 \
+                LBMAX_PASS(R, 2, 4, 4);                                          \
+        } else if (block == 8) {                                                 \
+            LBMAX_PASS(R, 1, 8, 8);                                              \
+        } else {                                                                 \
+            LBMAX_PASS(R, 1, 16, 8);                                             \
+        }                                                                        \
+    } while (0)
+    if (f64)
+        LBMAX_PASS_V(double);
+    else
+        LBMAX_PASS_V(float);
+#undef LBMAX_PASS_V
+#undef LBMAX_PASS
 }
 
-void launch_combine(bool f64, char *ws, const ChanDev *chans, const NodeTile *tiles,
-                    int n_tiles, hipStream_t st)
+void launch_combine(bool f64, int block, char *ws, const ChanDev *chans,
+                    const NodeTile *tiles, int n_tiles, hipStream_t st)
 {
     if (f64)
-        hipLaunchKernelGGL(k_combine<double>, dim3(n_tiles), dim3(kBlock), 0, st,
-                           ws, chans, tiles);
+        hipLaunchKernelGGL(k_combine<double>, dim3(n_tiles), dim3(kBlock), 0, st, ws, chans,
+                           tiles, block);
     else
-        hipLaunchKernelGGL(k_combine<float>, dim3(n_tiles), dim3(kBlock), 0, st,
-                           ws, chans, tiles);
+        hipLaunchKernelGGL(k_combine<float>, dim3(n_tiles), dim3(kBlock), 0, st, ws, chans,
+                           tiles, block);
+}
+
+void launch_hist_step(bool f64, int m, char *ws, const ChanDev *chans, const NodeTile *tiles,
+                      int n_tiles, const int64_t *tcount, int trel, hipStream_t st)
+{
+    if (f64)
+        hipLaunchKernelGGL(k_hist_step<double>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
+                           chans, tiles, tcount, trel, m);
+    else
+        hipLaunchKernelGGL(k_hist_step<float>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
+                           chans, tiles, tcount, trel, m);
 }
 
 void launch_tick(int64_t *tcount, int64_t add, hipStream_t st)

@@ -29,7 +29,7 @@ lb_status fail(lb_status s, const std::string &msg)
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr uint64_t kStateMagic = 0x4C424D4158535431ull;  // "LBMAXST1"
-constexpr uint32_t kStateVersion = 1;
+constexpr uint32_t kStateVersion = 2;
 constexpr size_t kStateHeader = 256;
 constexpr int64_t kMaxStepsPerBatch = int64_t(1) << 20;
 
@@ -41,6 +41,8 @@ struct StateHeader {
     int32_t n_ch;
     int32_t reserved;
     uint64_t bytes;
+    int32_t block_len;
+    int32_t block_pos;
 };
 
 bool unidirectional(const lb_channel_desc &d)
@@ -174,7 +176,10 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
             off = align_up(off + (size_t)c.n_hist * plane, 256);
         c.off_part = (int64_t)off;
         if (c.max_chunks > 1)
-            off = align_up(off + 3 * (size_t)c.max_chunks * c.np * sizeof(double), 256);
+            off = align_up(off + (size_t)kPartPlanes * c.max_chunks * c.np * sizeof(double),
+                           256);
+        c.off_blk = (int64_t)off;
+        off = align_up(off + (size_t)2 * kMaxBlock * c.np * sizeof(double), 256);
     }
     P.total = off;
     return P;
@@ -192,6 +197,8 @@ struct lb_handle {
     Plan plan;
     std::vector<int> ly, lx, n_hist;
     int64_t t = 0;          // completed steps
+    int block = 1;          // steps served by one history pass
+    int block_pos = 0;      // steps done in the current block (0: next is a pass)
     bool has_out = false;   // readout planes belong to step t-1
     bool poisoned = false;
     // device pointers into the workspace
@@ -216,9 +223,9 @@ struct lb_handle {
     // timing: event pairs recorded around launches, resolved on demand
     bool profile = false;
     std::vector<hipEvent_t> free_events;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
-    double kernel_ms[2] = {0.0, 0.0};
-    int64_t kernel_launches[2] = {0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
+    double kernel_ms[3] = {0.0, 0.0, 0.0};
+    int64_t kernel_launches[3] = {0, 0, 0};
 };
 
 namespace {
@@ -253,6 +260,16 @@ lb_status usable(lb_handle *h)
     return LB_OK;
 }
 
+// Lane widths with a history-pass instantiation for a block length.
+int effective_vec(int vec, int block)
+{
+    if (block >= 8)
+        return 1;
+    if (block > 1)
+        return std::min(vec, 2);
+    return vec;
+}
+
 // Split every channel's window into its chunks and list the workgroups,
 // longest age range first so uneven channels finish together.  A history
 // workgroup covers kBlock*vec nodes.
@@ -267,7 +284,7 @@ void build_tiles(lb_handle *h)
             h->node_tiles.push_back({ci, n0});
         if (c.nchunks > 1)
             h->any_chunked = true;
-        const int span = kBlock * c.vec;
+        const int span = kBlock * effective_vec(c.vec, h->block);
         for (int k = 0; k < c.nchunks; ++k) {
             const int k0 = (int)((int64_t)c.n_hist * k / c.nchunks);
             const int k1 = (int)((int64_t)c.n_hist * (k + 1) / c.nchunks);
@@ -278,7 +295,7 @@ void build_tiles(lb_handle *h)
     // Group by lane width (one launch each), longest age range first inside
     // a group.
     auto group = [h](const HistTile &a) {
-        const int v = h->plan.chans[a.ch].vec;
+        const int v = effective_vec(h->plan.chans[a.ch].vec, h->block);
         return v == 4 ? 2 : (v == 2 ? 1 : 0);
     };
     std::stable_sort(h->hist_tiles.begin(), h->hist_tiles.end(),
@@ -343,7 +360,7 @@ lb_status take_event(lb_handle *h, hipEvent_t *ev)
 // Add up the elapsed time of every recorded pair (the stream must be idle).
 lb_status resolve_timing(lb_handle *h)
 {
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < 3; ++w) {
         for (auto &pr : h->pending[w]) {
             float ms = 0.f;
             HIP_TRY(h, hipEventElapsedTime(&ms, pr.first, pr.second));
@@ -357,9 +374,10 @@ lb_status resolve_timing(lb_handle *h)
     return LB_OK;
 }
 
-// One step's launches, step t = *tcount + trel.  With `timed`, a HIP event
-// pair brackets the lattice (slot 1) and history (slot 0) launches.
-lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, bool timed)
+// One step's launches, step t = *tcount + trel, position m in its block (0:
+// the history pass).  With `timed`, HIP event pairs bracket the lattice launch
+// (slot 1) and the history work (slot 0 for a pass, slot 2 for a block step).
+lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed)
 {
     hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
     if (timed) {
@@ -376,18 +394,24 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, bool timed)
         HIP_TRY(h, hipEventRecord(e[1], st));
         HIP_TRY(h, hipEventRecord(e[2], st));
     }
-    static const int kVec[3] = {1, 2, 4};
-    for (int g = 0; g < 3; ++g)
-        launch_hist(h->f64, kVec[g], h->ws, h->d_chans,
-                    h->d_hist_tiles + h->hist_group_begin[g], h->hist_group_count[g],
-                    h->d_tcount, trel, st);
+    if (m == 0) {
+        static const int kVec[3] = {1, 2, 4};
+        for (int g = 0; g < 3; ++g)
+            launch_hist_pass(h->f64, kVec[g], h->block, h->ws, h->d_chans,
+                             h->d_hist_tiles + h->hist_group_begin[g], h->hist_group_count[g],
+                             h->d_tcount, trel, st);
+        if (h->any_chunked)
+            launch_combine(h->f64, h->block, h->ws, h->d_chans, h->d_node_tiles,
+                           h->n_node_tiles, st);
+    } else {
+        launch_hist_step(h->f64, m, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
+                         h->d_tcount, trel, st);
+    }
     if (timed) {
         HIP_TRY(h, hipEventRecord(e[3], st));
         h->pending[1].push_back({e[0], e[1]});
-        h->pending[0].push_back({e[2], e[3]});
+        h->pending[m == 0 ? 0 : 2].push_back({e[2], e[3]});
     }
-    if (h->any_chunked)
-        launch_combine(h->f64, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, st);
     return check_launch(h, "step launch");
 }
 
@@ -405,7 +429,7 @@ lb_status capture_graph(lb_handle *h)
         HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < h->graph_steps; ++i) {
-        lb_status s = enqueue_step(h, h->cap_stream, i, false);
+        lb_status s = enqueue_step(h, h->cap_stream, i, i % h->block, false);
         if (s != LB_OK) {
             hipGraph_t g = nullptr;
             (void)hipStreamEndCapture(h->cap_stream, &g);
@@ -467,6 +491,8 @@ std::vector<Section> state_sections(const lb_handle *h, int ci, int64_t t)
     v.push_back({c.off_ring_s, (size_t)c.n_hist, rowb, pitch});
     if (c.has_r)
         v.push_back({c.off_ring_r, (size_t)c.n_hist, rowb, pitch});
+    v.push_back({c.off_blk, (size_t)2 * kMaxBlock, (size_t)c.n * sizeof(double),
+                 (size_t)c.np * sizeof(double)});
     return v;
 }
 
@@ -607,30 +633,47 @@ lb_status lb_step(lb_handle *h, int64_t n_steps)
     if (n_steps < 0)
         return fail(LB_EINVAL, "n_steps must be >= 0");
     int64_t left = n_steps;
-    if (h->graph_steps > 0 && !h->profile && left >= h->graph_steps) {
-        if (h->graph_dirty) {
-            s = capture_graph(h);
-            if (s != LB_OK)
-                return s;
+    // Plain launches of a batch of steps starting at the current block
+    // position; the device counter advances once per batch.
+    auto eager = [&](int64_t count) -> lb_status {
+        while (count > 0) {
+            const int batch = (int)std::min(count, kMaxStepsPerBatch);
+            for (int i = 0; i < batch; ++i) {
+                lb_status e = enqueue_step(h, h->stream, i, h->block_pos, h->profile);
+                if (e != LB_OK)
+                    return e;
+                h->block_pos = (h->block_pos + 1) % h->block;
+            }
+            launch_tick(h->d_tcount, batch, h->stream);
+            lb_status e = check_launch(h, "tick");
+            if (e != LB_OK)
+                return e;
+            count -= batch;
         }
-        while (left >= h->graph_steps) {
-            HIP_TRY(h, hipGraphLaunch(h->graph_exec, h->stream));
-            left -= h->graph_steps;
-        }
-    }
-    while (left > 0) {
-        const int batch = (int)std::min(left, kMaxStepsPerBatch);
-        for (int i = 0; i < batch; ++i) {
-            s = enqueue_step(h, h->stream, i, h->profile);
-            if (s != LB_OK)
-                return s;
-        }
-        launch_tick(h->d_tcount, batch, h->stream);
-        s = check_launch(h, "tick");
+        return LB_OK;
+    };
+    if (h->graph_steps > 0 && !h->profile) {
+        // finish the current block, then replay whole graphs
+        const int64_t head = h->block_pos == 0 ? 0 : std::min<int64_t>(left, h->block - h->block_pos);
+        s = eager(head);
         if (s != LB_OK)
             return s;
-        left -= batch;
+        left -= head;
+        if (left >= h->graph_steps) {
+            if (h->graph_dirty) {
+                s = capture_graph(h);
+                if (s != LB_OK)
+                    return s;
+            }
+            while (left >= h->graph_steps) {
+                HIP_TRY(h, hipGraphLaunch(h->graph_exec, h->stream));
+                left -= h->graph_steps;
+            }
+        }
     }
+    s = eager(left);
+    if (s != LB_OK)
+        return s;
     h->t += n_steps;
     if (n_steps > 0)
         h->has_out = true;
@@ -674,7 +717,7 @@ lb_status lb_save_state(lb_handle *h, void *d_dst)
     size_t off = kStateHeader;
     h->upload.assign(state_size(h) > 0 ? kStateHeader + 16 * (size_t)h->n_ch : 0, 0);
     StateHeader hd{kStateMagic, kStateVersion, (uint32_t)h->prec, h->t, h->n_ch, 0,
-                   state_size(h)};
+                   state_size(h), h->block, h->block_pos};
     std::memcpy(h->upload.data(), &hd, sizeof hd);
     for (int ci = 0; ci < h->n_ch; ++ci) {
         for (const Section &sec : state_sections(h, ci, h->t)) {
@@ -712,6 +755,9 @@ lb_status lb_load_state(lb_handle *h, const void *d_src)
         return fail(LB_EINVAL, "state buffer belongs to a different configuration");
     if (hd.t < 0)
         return fail(LB_EINVAL, "negative step count in state");
+    if (hd.block_pos < 0 || hd.block_pos >= std::max(1, hd.block_len) ||
+        (hd.block_pos != 0 && hd.block_len != h->block))
+        return fail(LB_EINVAL, "state is inside a block of a different length");
     std::vector<double> forces(2 * (size_t)h->n_ch);
     size_t off = kStateHeader;
     for (int ci = 0; ci < h->n_ch; ++ci) {
@@ -742,6 +788,7 @@ lb_status lb_load_state(lb_handle *h, const void *d_src)
         return s;
     h->t = hd.t;
     h->has_out = hd.t > 0;
+    h->block_pos = hd.block_pos;
     return LB_OK;
 }
 
@@ -778,7 +825,7 @@ lb_status lb_get_tiling(const lb_handle *h, int32_t ch, int32_t *n_chunks,
     if (n_chunks)
         *n_chunks = h->plan.chans[ch].nchunks;
     if (nodes_per_lane)
-        *nodes_per_lane = h->plan.chans[ch].vec;
+        *nodes_per_lane = effective_vec(h->plan.chans[ch].vec, h->block);
     return LB_OK;
 }
 
@@ -789,10 +836,31 @@ lb_status lb_set_graph(lb_handle *h, int32_t steps_per_graph)
         return s;
     if (steps_per_graph < 0 || steps_per_graph > 4096)
         return fail(LB_EINVAL, "steps_per_graph must be in [0, 4096]");
+    if (steps_per_graph % h->block != 0)
+        return fail(LB_EINVAL, "steps_per_graph must be a multiple of the block length");
     h->graph_steps = steps_per_graph;
     h->graph_dirty = true;
     return LB_OK;
 }
+
+lb_status lb_set_block(lb_handle *h, int32_t steps_per_pass)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (steps_per_pass != 1 && steps_per_pass != 2 && steps_per_pass != 4 &&
+        steps_per_pass != 8 && steps_per_pass != 16)
+        return fail(LB_EINVAL, "steps_per_pass must be 1, 2, 4, 8 or 16");
+    if (h->graph_steps % steps_per_pass != 0)
+        return fail(LB_EINVAL, "the graph length must stay a multiple of the block length");
+    h->block = steps_per_pass;
+    h->block_pos = 0;  // the next step starts a block with a fresh pass
+    h->graph_dirty = true;
+    build_tiles(h);  // lane widths depend on the block length
+    return upload_tables(h);
+}
+
+int32_t lb_get_block(const lb_handle *h) { return h ? h->block : 0; }
 
 lb_status lb_profile(lb_handle *h, int32_t enable)
 {
@@ -805,8 +873,10 @@ lb_status lb_profile(lb_handle *h, int32_t enable)
     s = resolve_timing(h);
     if (s != LB_OK)
         return s;
-    h->kernel_ms[0] = h->kernel_ms[1] = 0.0;
-    h->kernel_launches[0] = h->kernel_launches[1] = 0;
+    for (int w = 0; w < 3; ++w) {
+        h->kernel_ms[w] = 0.0;
+        h->kernel_launches[w] = 0;
+    }
     return LB_OK;
 }
 
@@ -815,8 +885,8 @@ lb_status lb_kernel_time(lb_handle *h, int32_t which, double *total_ms, int64_t 
     lb_status s = usable(h);
     if (s != LB_OK)
         return s;
-    if (which < 0 || which > 1)
-        return fail(LB_EINVAL, "which must be 0 (history) or 1 (lattice)");
+    if (which < 0 || which > 2)
+        return fail(LB_EINVAL, "which must be 0 (history pass), 1 (lattice) or 2 (block step)");
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     s = resolve_timing(h);
     if (s != LB_OK)
@@ -838,7 +908,7 @@ lb_status lb_destroy(lb_handle *h)
         (void)hipGraphDestroy(h->graph);
     if (h->cap_stream)
         (void)hipStreamDestroy(h->cap_stream);
-    for (int w = 0; w < 2; ++w)
+    for (int w = 0; w < 3; ++w)
         for (auto &pr : h->pending[w]) {
             h->free_events.push_back(pr.first);
             h->free_events.push_back(pr.second);

@@ -120,6 +120,14 @@ class Solver:
     def set_graph(self, steps_per_graph: int):
         _lib.check(self.lib.lb_set_graph(self.h, int(steps_per_graph)), "lb_set_graph")
 
+    def set_block(self, steps_per_pass: int):
+        """Steps served by one history pass (temporal blocking: 1, 2, 4, 8, 16)."""
+        _lib.check(self.lib.lb_set_block(self.h, int(steps_per_pass)), "lb_set_block")
+
+    @property
+    def block(self) -> int:
+        return int(self.lib.lb_get_block(self.h))
+
     def max_chunks(self, ch: int) -> int:
         return int(self.lib.lb_max_chunks(self.h, int(ch)))
 
@@ -189,6 +197,19 @@ class Solver:
         return ms.value, cnt.value
 
 
+STATE_MAGIC = 0x4C424D4158535431
+STATE_VERSION = 2
+
+
+def pack_state_header(t: int, n_ch: int, precision: str, total_bytes: int,
+                      block_len: int = 1, block_pos: int = 0) -> bytes:
+    """The 256-byte state header (include/lbmax.h)."""
+    import struct
+    hdr = struct.pack("<QIIqiiQii", STATE_MAGIC, STATE_VERSION, _precision_code(precision),
+                      int(t), int(n_ch), 0, int(total_bytes), int(block_len), int(block_pos))
+    return hdr + bytes(256 - len(hdr))
+
+
 def state_layout(channels: Sequence, precision: str = "f32"):
     """Byte offsets of the sections of a state buffer (include/lbmax.h)."""
     R = 8 if _precision_code(precision) == _lib.LB_F64 else 4
@@ -208,6 +229,8 @@ def state_layout(channels: Sequence, precision: str = "f32"):
                            ("ring_s", int(ch.n_hist))) + ((() if uni else (("ring_r", int(ch.n_hist)),))):
             sec[name] = (off, rows, N)
             off = up(off + rows * N * R)
+        sec["blk"] = (off, 32, N)   # doubles
+        off = up(off + 32 * N * 8)
         sec["force"] = (off, 1, 2)
         off = up(off + 16)
         out.append(sec)

@@ -67,9 +67,10 @@ def test_workspace_bytes_large_2d_fits(lib):
     wl = workloads.large_2d(perturb=False)
     arr, _ = make_descs(wl.channels)
     nb = lib.lb_workspace_bytes(arr, 1, 1)
-    # two FP32 rings (s, r) of 4096 x 524288 plus small planes and partials
+    # two FP32 rings (s, r) of 4096 x 524288 plus small planes, chunk
+    # partials and block sums
     ring = 2 * 4096 * 524288 * 4
-    assert ring <= nb < ring * 1.02
+    assert ring <= nb < ring * 1.05
 
 
 @pytest.mark.parametrize("field,value,msg", [
