@@ -1,12 +1,18 @@
 """Throughput benchmark: lattice node-steps/s of the hybrid LB / integral
-nonlinear-Maxwell step at history window N_h, with the HBM roofline of the
+nonlinear-Maxwell step at history window N_h, with the roofline of the
 history kernel and the FP64 oracle timed on the host beside it.
 
 Workload: the large 2D channel, 1024 x 512 nodes, window N_h = 4096, FP32
 populations and history (Kahan sums, FP64 strain), tau = 1000, g = 5e-6,
 1 % seeded velocity perturbation.  One step = the whole path for every node:
 pull-stream + collide with the stress-divergence force, velocity gradient,
-history push and the N_h-entry history integral.
+history push and the N_h-entry history integral.  The launch shape (steps
+per history pass, lanes, chunks, persistent pass) is chosen by the
+autotuner before the timed region.
+
+Beside it ("batched"): the 64-channel batched workload (uneven widths and
+windows, FP32, one launch per phase) against the plain per-channel FP64
+path (one handle per channel, no blocking, no graphs) on the same GPU.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 Prints one JSON line.
@@ -23,18 +29,68 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# FP32 vector arithmetic without packed instructions (the build disables
+# them): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# wave64 VALU instruction issue: 1024 SIMDs, 4 cycles per instruction
+VALU_WAVE_INSTR_PER_S = 1024 * 2.4e9 / 4
+
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernels.hip")
+# rocprofv3 counter results for the history pass on this workload (see
+# profiles/history_pass_large_2d_1024x512_nh4096.md), keyed by
+# (steps per pass, nodes per lane).  Valid only for the kernel source they
+# were taken from; otherwise reported as null.
+MEASURED = {
+    "source_sha256": "6c527575ddc1198d0190757a622459bad4993b7a9f119d5c4d42458f929c0db4",
+    # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated)
+    "traffic_bytes": {(16, 1): 17319683980.0, (1, 4): 17258171597.0},
+    # SQ_INSTS_VALU x 64 / history entries
+    "valu_instr_per_entry": {(16, 1): 77.6, (1, 4): 13.06},
+}
+
+
+def measured(kind: str, key):
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != MEASURED["source_sha256"]:
+            return None
+    return MEASURED[kind].get(key)
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def unidirectional(ch) -> bool:
+    return ch.lx == 1 and ch.gy == 0.0 and ch.u0 is None
+
+
 def hist_bytes_per_entry(ch) -> int:
-    """Algorithmic bytes per history entry-update: the FP32 shear rate and,
-    for channels that are not unidirectional, the FP32 |gamma_dot|."""
-    uni = ch.lx == 1 and ch.gy == 0.0 and (ch.u0 is None)
-    return 4 if uni else 8
+    """Algorithmic bytes per history entry read by a pass: the FP32 shear
+    rate and, unless the channel is unidirectional, the FP32 |gamma_dot|."""
+    return 4 if unidirectional(ch) else 8
+
+
+def pass_flops_per_entry(block: int) -> int:
+    """Algorithmic FP32 operations per history entry of one pass serving
+    `block` steps: decay rate (fma 2), exponent (1), two exponentials (2),
+    s*E (1), FP64 strain add (1), 2*strain (1); per step of the block: decay
+    factor (1), sigma_xy add (1), sigma_xx fma (2)."""
+    return 8 + 4 * block
+
+
+def time_steps(solver, steps: int):
+    import torch
+    torch.cuda.synchronize()
+    solver.profile(True)
+    t0 = time.perf_counter()
+    solver.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = {w: solver.kernel_time(w) for w in (0, 1, 2)}
+    solver.profile(False)
+    return el, kt
 
 
 def cpu_baseline(seconds: float = 12.0):
@@ -67,26 +123,86 @@ def cpu_baseline(seconds: float = 12.0):
                       f"{steps} steps in {el:.1f} s, single thread"}
 
 
+def bench_batched(steps: int = 2000):
+    """64 uneven channels: tuned FP32 batched path vs plain per-channel FP64."""
+    import torch
+    import workloads
+    from paper_1504_06123_amd import Solver, autotune
+
+    wl = workloads.batched()
+    nodes = wl.nodes
+    s = Solver(wl.channels, precision="f32")
+    s.step(64)
+    best = autotune.tune(s, autotune.candidates(s, blocks=(1, 4, 8, 16),
+                                                chunk_lens=(256, 1024, 4096),
+                                                graphs=(0, 64)), min_steps=64)
+    s.step(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.close()
+    batched = nodes * steps / el
+    # plain per-channel FP64: one handle per channel, one step at a time
+    handles = [Solver([c], precision="f64") for c in wl.channels]
+    for h in handles:
+        h.step(2)
+    base_steps = 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(base_steps):
+        for h in handles:
+            h.step(1)
+    torch.cuda.synchronize()
+    el64 = time.perf_counter() - t0
+    for h in handles:
+        h.close()
+    plain = nodes * base_steps / el64
+    cfg = {k: best[k] for k in ("block", "vec", "chunk_len", "persistent", "graph")}
+    return {"workload": "64 channels, lx=1, ly log-uniform [16,1024], tau U[50,2000], "
+                        "window 10*tau rounded to a power of two",
+            "nodes": nodes, "history_entries_per_step": wl.entries_per_step,
+            "value": batched, "unit": "node-steps/s", "dtype": "f32", "config": cfg,
+            "ms_per_step": el / steps * 1e3,
+            "plain_per_channel_f64": plain, "speedup_vs_plain_f64": batched / plain}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=800)
+    ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--block", type=int, default=16, help="steps per pass without tuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note only)"}))
         sys.exit(2)
 
+    import numpy as np
     import torch
     import workloads
-    from paper_1504_06123_amd import Solver, _lib
+    from paper_1504_06123_amd import Solver, _lib, autotune
 
     if not os.path.exists(_lib.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib << 18  # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy probe of {args.copy_probe_mib} MiB done")
+        del src, dst
 
     wl = workloads.large_2d()
     ch = wl.channels[0]
@@ -94,30 +210,61 @@ def main():
     log(f"bench: {wl.name} nodes={nodes} N_h={H} precision=f32")
     s = Solver(wl.channels, precision="f32", device="cuda:0")
     s.step(args.warmup)
-    torch.cuda.synchronize()
-    s.profile(True)  # HIP events around every launch on the solver's stream
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(args.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    hist_ms, hist_n = s.kernel_time(0)
-    lb_ms, lb_n = s.kernel_time(1)
-    s.profile(False)
-    # the run must still be physical: finite, near-unit density
+    if args.no_tune:
+        cfg = dict(block=args.block, vec=1, chunk_len=1 << 30, persistent=False, graph=0)
+        autotune.apply(s, cfg)
+    else:
+        best = autotune.tune(s, autotune.candidates(s, blocks=(1, 4, 8, 16),
+                                                    chunk_lens=(1024, 1 << 30)),
+                             min_steps=32)
+        cfg = {k: best[k] for k in ("block", "vec", "chunk_len", "persistent", "graph")}
+        log(f"bench: tuned {cfg} ({best['ms_per_step']:.4f} ms/step in tuning)")
+    M = cfg["block"]
+    steps = max(M, args.steps // M * M)
+    s.step(2 * M)
+    el, kt = time_steps(s, steps)
     rho, ux, _ = s.fields(0)
-    import numpy as np
     assert np.isfinite(ux).all() and abs(rho.mean() - 1) < 1e-3
     s.close()
+    del s
+    torch.cuda.empty_cache()
 
-    node_steps = nodes * args.steps / el
+    node_steps = nodes * steps / el
+    pass_ms, n_pass = kt[0]
+    pass_s = pass_ms / n_pass / 1e3
     entries = nodes * H
-    hist_avg_s = hist_ms / hist_n / 1e3
     alg_bytes = entries * hist_bytes_per_entry(ch)
-    achieved = alg_bytes / hist_avg_s / 1e9
-    log(f"bench: {args.steps} steps in {el:.3f} s; history kernel {hist_avg_s*1e3:.3f} ms avg, "
-        f"lattice kernel {lb_ms/lb_n:.3f} ms avg")
+    alg_flops = entries * pass_flops_per_entry(M)
+    gbs = alg_bytes / pass_s / 1e9
+    tflops = alg_flops / pass_s / 1e12
+    hbm_frac = gbs / HBM_PEAK_GBS
+    alu_frac = tflops / VALU_PEAK_TFLOPS
+    log(f"bench: {steps} steps in {el:.3f} s ({el/steps*1e3:.4f} ms/step); history pass "
+        f"{pass_s*1e3:.3f} ms x {n_pass} ({gbs:.0f} GB/s, {tflops:.1f} TFLOP/s); "
+        f"lattice {kt[1][0]/max(kt[1][1],1):.4f} ms; block step "
+        f"{(kt[2][0]/kt[2][1]) if kt[2][1] else 0:.4f} ms")
+    key = (M, cfg["vec"])
+    traffic = measured("traffic_bytes", key)
+    vpe = measured("valu_instr_per_entry", key)
+    issue_frac = (vpe * entries / 64 / pass_s / VALU_WAVE_INSTR_PER_S) if vpe else None
+    if issue_frac is not None and issue_frac > hbm_frac:
+        roof = {"bound": "alu", "achieved": tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": alu_frac}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm_frac}
+    roof.update({"traffic": traffic, "kernel": f"k_hist_pass (float, {M} steps per pass)",
+                 "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg_bytes,
+                 "alg_flops_per_launch": alg_flops, "hbm_GBs": gbs, "hbm_frac": hbm_frac,
+                 "valu_TFLOPs": tflops, "valu_frac": alu_frac,
+                 "valu_issue_frac": issue_frac})
 
+    batched = None
+    if not args.no_batched:
+        log("bench: batched 64-channel workload")
+        batched = bench_batched()
+        log(f"bench: batched {batched['value']:.3e} node-steps/s, plain per-channel FP64 "
+            f"{batched['plain_per_channel_f64']:.3e}")
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")
@@ -128,9 +275,9 @@ def main():
         "value": node_steps,
         "unit": "node-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
+        "ms_per_step": el / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -139,13 +286,10 @@ def main():
         "config": {"workload": "large 2D channel 1024x512, N_h=4096, tau=1000 steps, "
                                "g=5e-6, 1% seeded velocity perturbation",
                    "lx": ch.lx, "ly": ch.ly, "n_hist": H, "nodes": nodes,
-                   "history_entries_per_step": entries},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_hist<float>",
-                     "kernel_avg_ms": hist_avg_s * 1e3,
-                     "alg_bytes_per_launch": alg_bytes},
-        "entry_updates_per_s": entries * args.steps / el,
+                   "history_entries_per_step": entries, "launch": cfg},
+        "roofline": roof,
+        "entry_updates_per_s": entries * steps / el,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -195,6 +195,15 @@ lb_status lb_set_block(lb_handle *h, int32_t steps_per_pass);
 int32_t lb_get_block(const lb_handle *h);
 
 /*
+ * Persistent history pass (enable != 0): instead of one workgroup per tile,
+ * as many workgroups as are resident on the chip at once claim tiles from a
+ * device counter, longest age range first, until all channels' tiles are
+ * done -- one launch balances many uneven channels.  Results are identical
+ * to the plain launch.  Default off.
+ */
+lb_status lb_set_persistent(lb_handle *h, int32_t enable);
+
+/*
  * Per-kernel timing with HIP events recorded on the handle's stream around
  * every history pass (which = 0, including the chunk combine), every lattice
  * launch (which = 1) and every in-block history step (which = 2).  Enabled by lb_profile(h, 1) for plain launches;

@@ -20,6 +20,7 @@ constexpr int kMaxBlock = 16;      // most steps served by one history pass
 constexpr int kPlaneB = kMaxBlock;
 constexpr int kPlaneT = 2 * kMaxBlock;
 constexpr int kPartPlanes = 2 * kMaxBlock + 1;
+constexpr int kTileCounters = 4;   // persistent-pass tile counters (one per lane width)
 
 // Per-channel parameters and workspace offsets, read by every kernel.
 // 256 bytes so a table row never straddles two scalar cache lines twice.
@@ -60,13 +61,17 @@ void launch_init(bool f64, char *ws, const ChanDev *chans, int ch,
                  const NodeTile *tiles, int n_tiles, const double *u0_dev,
                  hipStream_t st);
 void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+// The lattice kernel also zeroes the persistent-pass tile counters.
 void launch_lb(bool f64, char *ws, const ChanDev *chans, const NodeTile *tiles,
-               int n_tiles, const int64_t *tcount, int trel, hipStream_t st);
+               int n_tiles, const int64_t *tcount, int trel, int *tile_counters,
+               hipStream_t st);
 // History pass (first step of a block of `block` steps) for the tiles of the
-// channels whose lane width is `vec`.
+// channels whose lane width is `vec`.  persistent_grid > 0 launches that many
+// persistent workgroups claiming tiles from *counter.
 void launch_hist_pass(bool f64, int vec, int block, char *ws, const ChanDev *chans,
                       const HistTile *tiles, int n_tiles, const int64_t *tcount,
-                      int trel, hipStream_t st);
+                      int trel, int persistent_grid, int *counter, hipStream_t st);
+int hist_pass_blocks_per_cu(bool f64, int vec, int block);
 // FP64 combine of chunk partials into sigma and the block sums.
 void launch_combine(bool f64, int block, char *ws, const ChanDev *chans,
                     const NodeTile *tiles, int n_tiles, hipStream_t st);

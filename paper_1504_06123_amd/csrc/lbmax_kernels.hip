@@ -26,6 +26,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 namespace lbmax {
@@ -202,11 +203,15 @@ __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
                                                const ChanDev *__restrict__ chans,
                                                const NodeTile *__restrict__ tiles,
                                                const int64_t *__restrict__ tcount,
-                                               int trel)
+                                               int trel, int *__restrict__ tile_counters)
 {
     const NodeTile tl = tiles[blockIdx.x];
     const ChanDev *c = chans + tl.ch;
     const int n = tl.n0 + threadIdx.x;
+    // The history pass of this step (if any) claims its tiles from these
+    // counters; it runs after this kernel on the same stream.
+    if (blockIdx.x == 0 && threadIdx.x < kTileCounters)
+        tile_counters[threadIdx.x] = 0;
     if (n >= c->n)
         return;
     const int lx = c->lx, ly = c->ly;
@@ -571,7 +576,7 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
 }
 
 // One launch per (lane width V, block length M): the tiles of the channels
-// whose lane width is V.
+// whose lane width is V.  Plain form: one workgroup per tile.
 template <typename R, int V, int M, int U>
 __global__ __launch_bounds__(kBlock) void k_hist_pass(char *__restrict__ ws,
                                                       const ChanDev *__restrict__ chans,
@@ -589,6 +594,36 @@ __global__ __launch_bounds__(kBlock) void k_hist_pass(char *__restrict__ ws,
         pass_tile<R, V, M, U, true>(ws, c, tl, t);
     else
         pass_tile<R, V, M, U, false>(ws, c, tl, t);
+}
+
+// Persistent form: as many workgroups as fit on the chip at once; each claims
+// the next tile of the list (longest first) from a counter until the list
+// is exhausted.  The counter was zeroed by the lattice kernel of this step.
+template <typename R, int V, int M, int U>
+__global__ __launch_bounds__(kBlock) void k_hist_pass_persistent(
+    char *__restrict__ ws, const ChanDev *__restrict__ chans,
+    const HistTile *__restrict__ tiles, int n_tiles, const int64_t *__restrict__ tcount,
+    int trel, int *__restrict__ counter)
+{
+    __shared__ int claimed;
+    const int64_t t = *tcount + trel;
+    for (;;) {
+        if (threadIdx.x == 0)
+            claimed = atomicAdd(counter, 1);
+        __syncthreads();
+        const int i = claimed;
+        __syncthreads();  // every lane has read `claimed` before it changes
+        if (i >= n_tiles)
+            break;  // uniform across the workgroup: all waves leave together
+        const HistTile tl = tiles[i];
+        const ChanDev *c = chans + tl.ch;
+        if (tl.n0 + (int)(threadIdx.x & ~63u) * V < c->n) {
+            if (c->has_r)
+                pass_tile<R, V, M, U, true>(ws, c, tl, t);
+            else
+                pass_tile<R, V, M, U, false>(ws, c, tl, t);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -768,25 +803,35 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st)
 }
 
 void launch_lb(bool f64, char *ws, const ChanDev *chans, const NodeTile *tiles,
-               int n_tiles, const int64_t *tcount, int trel, hipStream_t st)
+               int n_tiles, const int64_t *tcount, int trel, int *tile_counters,
+               hipStream_t st)
 {
     if (f64)
         hipLaunchKernelGGL(k_lb<double>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
-                           chans, tiles, tcount, trel);
+                           chans, tiles, tcount, trel, tile_counters);
     else
         hipLaunchKernelGGL(k_lb<float>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
-                           chans, tiles, tcount, trel);
+                           chans, tiles, tcount, trel, tile_counters);
 }
 
 void launch_hist_pass(bool f64, int vec, int block, char *ws, const ChanDev *chans,
                       const HistTile *tiles, int n_tiles, const int64_t *tcount, int trel,
-                      hipStream_t st)
+                      int persistent_grid, int *counter, hipStream_t st)
 {
     if (n_tiles <= 0)
         return;
+    const int grid = persistent_grid > 0 ? std::min(persistent_grid, n_tiles) : n_tiles;
 #define LBMAX_PASS(R, V, M, U)                                                   \
-    hipLaunchKernelGGL((k_hist_pass<R, V, M, U>), dim3(n_tiles), dim3(kBlock), 0, st, \
-                       ws, chans, tiles, tcount, trel)
+    do {                                                                         \
+        if (persistent_grid > 0)                                                 \
+            hipLaunchKernelGGL((k_hist_pass_persistent<R, V, M, U>), dim3(grid), \
+                               dim3(kBlock), 0, st, ws, chans, tiles, n_tiles,   \
+                               tcount, trel, counter);                           \
+        else                                                                     \
+            hipLaunchKernelGGL((k_hist_pass<R, V, M, U>), dim3(grid),            \
+                               dim3(kBlock), 0, st, ws, chans, tiles, tcount,    \
+                               trel);                                            \
+    } while (0)
 #define LBMAX_PASS_V(R)                                                          \
     do {                                                                         \
         if (block == 1) {                                                        \
@@ -818,6 +863,38 @@ void launch_hist_pass(bool f64, int vec, int block, char *ws, const ChanDev *cha
         LBMAX_PASS_V(float);
 #undef LBMAX_PASS_V
 #undef LBMAX_PASS
+}
+
+// Workgroups of the persistent pass that are resident on one compute unit.
+int hist_pass_blocks_per_cu(bool f64, int vec, int block)
+{
+    int n = 0;
+    hipError_t e = hipSuccess;
+#define LBMAX_OCC(R, V, M, U)                                                        \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
+        &n, reinterpret_cast<const void *>(&k_hist_pass_persistent<R, V, M, U>), kBlock, 0)
+#define LBMAX_OCC_V(R)                                                               \
+    do {                                                                             \
+        if (block == 1)                                                              \
+            (vec == 4 ? (void)(LBMAX_OCC(R, 4, 1, 4))                                \
+                      : (vec == 2 ? (void)(LBMAX_OCC(R, 2, 1, 8))                    \
+                                  : (void)(LBMAX_OCC(R, 1, 1, 8))));                 \
+        else if (block == 2)                                                         \
+            (vec == 1 ? (void)(LBMAX_OCC(R, 1, 2, 8)) : (void)(LBMAX_OCC(R, 2, 2, 4)));  \
+        else if (block == 4)                                                         \
+            (vec == 1 ? (void)(LBMAX_OCC(R, 1, 4, 8)) : (void)(LBMAX_OCC(R, 2, 4, 4)));  \
+        else if (block == 8)                                                         \
+            (void)(LBMAX_OCC(R, 1, 8, 8));                                           \
+        else                                                                         \
+            (void)(LBMAX_OCC(R, 1, 16, 8));                                          \
+    } while (0)
+    if (f64)
+        LBMAX_OCC_V(double);
+    else
+        LBMAX_OCC_V(float);
+#undef LBMAX_OCC_V
+#undef LBMAX_OCC
+    return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 void launch_combine(bool f64, int block, char *ws, const ChanDev *chans,

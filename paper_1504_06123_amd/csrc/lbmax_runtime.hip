@@ -203,6 +203,9 @@ struct lb_handle {
     bool poisoned = false;
     // device pointers into the workspace
     int64_t *d_tcount = nullptr;
+    int *d_tile_counters = nullptr;  // in the header block after the step counter
+    bool persistent = false;
+    int num_cus = 0;
     ChanDev *d_chans = nullptr;
     NodeTile *d_node_tiles = nullptr;
     HistTile *d_hist_tiles = nullptr;
@@ -389,17 +392,21 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
         HIP_TRY(h, hipEventRecord(e[0], st));
     }
     launch_lb(h->f64, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
-              h->d_tcount, trel, st);
+              h->d_tcount, trel, h->d_tile_counters, st);
     if (timed) {
         HIP_TRY(h, hipEventRecord(e[1], st));
         HIP_TRY(h, hipEventRecord(e[2], st));
     }
     if (m == 0) {
         static const int kVec[3] = {1, 2, 4};
-        for (int g = 0; g < 3; ++g)
+        for (int g = 0; g < 3; ++g) {
+            const int pgrid =
+                h->persistent ? h->num_cus * hist_pass_blocks_per_cu(h->f64, kVec[g], h->block)
+                              : 0;
             launch_hist_pass(h->f64, kVec[g], h->block, h->ws, h->d_chans,
                              h->d_hist_tiles + h->hist_group_begin[g], h->hist_group_count[g],
-                             h->d_tcount, trel, st);
+                             h->d_tcount, trel, pgrid, h->d_tile_counters + g, st);
+        }
         if (h->any_chunked)
             launch_combine(h->f64, h->block, h->ws, h->d_chans, h->d_node_tiles,
                            h->n_node_tiles, st);
@@ -556,6 +563,7 @@ lb_status lb_init(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec, vo
     h->stream = static_cast<hipStream_t>(stream);
     h->plan = std::move(plan);
     h->d_tcount = reinterpret_cast<int64_t *>(h->ws + h->plan.off_tcount);
+    h->d_tile_counters = reinterpret_cast<int *>(h->ws + h->plan.off_tcount + 64);
     h->d_chans = reinterpret_cast<ChanDev *>(h->ws + h->plan.off_chans);
     h->d_node_tiles = reinterpret_cast<NodeTile *>(h->ws + h->plan.off_node_tiles);
     h->d_hist_tiles = reinterpret_cast<HistTile *>(h->ws + h->plan.off_hist_tiles);
@@ -568,6 +576,15 @@ lb_status lb_init(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec, vo
 
     default_tiling(h);
     build_tiles(h);
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess || h->num_cus <= 0) {
+            delete h;
+            return fail(LB_EDEVICE, "cannot query the compute-unit count");
+        }
+    }
 
     auto bail = [&](lb_status s) {
         delete h;
@@ -861,6 +878,16 @@ lb_status lb_set_block(lb_handle *h, int32_t steps_per_pass)
 }
 
 int32_t lb_get_block(const lb_handle *h) { return h ? h->block : 0; }
+
+lb_status lb_set_persistent(lb_handle *h, int32_t enable)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    h->persistent = enable != 0;
+    h->graph_dirty = true;
+    return LB_OK;
+}
 
 lb_status lb_profile(lb_handle *h, int32_t enable)
 {

@@ -124,6 +124,10 @@ class Solver:
         """Steps served by one history pass (temporal blocking: 1, 2, 4, 8, 16)."""
         _lib.check(self.lib.lb_set_block(self.h, int(steps_per_pass)), "lb_set_block")
 
+    def set_persistent(self, enable: bool = True):
+        """Persistent history pass: resident workgroups claim tiles from a counter."""
+        _lib.check(self.lib.lb_set_persistent(self.h, 1 if enable else 0), "lb_set_persistent")
+
     @property
     def block(self) -> int:
         return int(self.lib.lb_get_block(self.h))

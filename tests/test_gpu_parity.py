@@ -48,7 +48,7 @@ def nerr(a, b):
 
 
 def run_gpu(Solver, chans, precision, steps, every, steps_on=None, chunks=None, graph=0,
-            vec=None, block=1):
+            vec=None, block=1, persistent=False):
     """Advance all channels together; sample every `every` steps.  The force
     goes to zero after steps_on steps (cessation)."""
     steps_on = steps if steps_on is None else steps_on
@@ -60,6 +60,8 @@ def run_gpu(Solver, chans, precision, steps, every, steps_on=None, chunks=None, 
             s.set_tiling(ci, nc, v)
         if block != 1:
             s.set_block(block)
+        if persistent:
+            s.set_persistent(True)
         if graph:
             s.set_graph(graph)
         marks = sorted({m for m in list(range(every, steps + 1, every)) + [steps_on, steps]
@@ -275,6 +277,42 @@ def test_blocking_save_load_mid_block_and_graph(Solver):
     b = run_gpu(Solver, [ch], "f32", 400, 100, block=4, graph=32)[0]
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_persistent_pass_bitwise(Solver):
+    """The persistent pass computes the same tiles as the plain launch, only
+    scheduled differently: identical bits, also for many uneven channels."""
+    wl = workloads.batched()
+    chans = [c.replace(n_hist=min(c.n_hist, 1024)) for c in wl.channels[:12]]
+    say("case persistent pass")
+    for block in (1, 4):
+        a = run_gpu(Solver, chans, "f32", 200, 100, block=block)
+        b = run_gpu(Solver, chans, "f32", 200, 100, block=block, persistent=True)
+        for ca, cb in zip(a, b):
+            for k in ca:
+                assert np.array_equal(ca[k], cb[k]), (block, k)
+
+
+def test_autotune_restores_state(Solver):
+    from paper_1504_06123_amd import autotune
+    ch = workloads.large_2d(lx=16, ly=40, n_hist=512).channels[0].replace(tau_m=60.0)
+    say("case autotune")
+    with Solver([ch], precision="f32") as s:
+        s.step(123)
+        before = s.fields(0), s.stress(0)
+        best = autotune.tune(s, autotune.candidates(s, blocks=(1, 8), chunk_lens=(128, 1 << 30)),
+                             min_steps=16)
+        assert s.t == 123 and best["ms_per_step"] > 0
+        after = s.fields(0), s.stress(0)
+        for a, b in zip(before, after):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+        s.step(200)
+        _, ux, _ = s.fields(0)
+    oc = oracle.OracleChannel(ch)
+    oc.step(323)
+    _, rux, _ = oc.fields()
+    assert nerr(ux, rux) < TOL32["ux"]
 
 
 def test_bitwise_determinism_and_graph_replay(Solver):
