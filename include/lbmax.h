@@ -60,8 +60,14 @@ typedef enum {
  *          in FP32, history sums in FP32 with Kahan compensation; the
  *          accumulated strain (prefix sum of the shear rate, Sec. III
  *          Eq. eeval) and the combination of partial sums in FP64.
+ *  LB_F32_P64: the lattice state (populations as deviations, moments,
+ *          stress planes) in FP64, the history ring and its window sums as
+ *          in LB_F32.  The ring carries nearly all the bytes, so this costs
+ *          little over LB_F32 and removes the drift of FP32 populations over
+ *          long runs (a velocity that grows by a small amount per step loses
+ *          part of each increment to FP32 rounding, coherently).
  */
-typedef enum { LB_F64 = 0, LB_F32 = 1 } lb_precision;
+typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F32_P64 = 2 } lb_precision;
 
 /*
  * One channel.  Requirements (checked, LB_EINVAL otherwise):
@@ -133,7 +139,9 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  * State snapshot (checkpoint / resume).  lb_state_bytes gives the size of a
  * device buffer holding the full state; lb_save_state copies the state into
  * it (stream-ordered), lb_load_state restores it.  Layout (all sections
- * 256-byte aligned, R = double for LB_F64, float for LB_F32):
+ * 256-byte aligned, R = the lattice type: double for LB_F64 and LB_F32_P64,
+ * float for LB_F32; RH = the history type: double for LB_F64, float
+ * otherwise):
  *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 2,
  *     uint32 precision, int64 t (completed steps), int32 n_ch,
  *     int32 reserved, uint64 total bytes, int32 block length,
@@ -147,8 +155,8 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  *     sig  [2][N] R  sigma_xy, sigma_xx of step t-1
  *     vel  [2][N] R  u_x, u_y of step t-1
  *     drho [N]    R  rho - 1 of step t-1
- *     ring_s [n_hist][N] R  shear rate s(t') = kappa_xy, row t' mod n_hist
- *     ring_r [n_hist][N] R  |gamma_dot(t')| (absent for unidirectional
+ *     ring_s [n_hist][N] RH shear rate s(t') = kappa_xy, row t' mod n_hist
+ *     ring_r [n_hist][N] RH |gamma_dot(t')| (absent for unidirectional
  *                           channels)
  *     blk  [32][N] double   window sums of the block in progress (see
  *                           lb_set_block); read only when the block
@@ -213,6 +221,51 @@ lb_status lb_set_persistent(lb_handle *h, int32_t enable);
 lb_status lb_profile(lb_handle *h, int32_t enable);
 lb_status lb_kernel_time(lb_handle *h, int32_t which, double *total_ms,
                          int64_t *launches);
+
+/*
+ * Material parameters of channel ch from the next step on (G_inf, tau,
+ * gamma_c of Eq. nlmax; same validity rules as lb_channel_desc).
+ */
+lb_status lb_set_params(lb_handle *h, int32_t ch, double g_inf, double tau_m,
+                        double gamma_c);
+
+/*
+ * Discrete adjoint of the stepping, for gradients of a loss of the sampled
+ * velocities with respect to (G_inf, tau, gamma_c, g_x) of every channel.
+ * Supported for unidirectional channels (lx = 1, gy = 0, u0_y = 0): there
+ * d/dx vanishes, sigma_xx never reaches the force and |gamma_dot| = |s|, so
+ * the transpose involves sigma_xy only (Sec. IV.C: normal stresses do not
+ * feed back in translation-invariant flow).  The transpose of every step of
+ * lb_step is applied in reverse time: collision, forcing and moments, the
+ * stress divergence, the velocity gradient, and the history integral, whose
+ * transpose gathers, for each history entry, the adjoint stresses of the
+ * n_hist steps that saw it.
+ *
+ * Protocol (checkpointing): during the forward run save a state with
+ * lb_save_state every seg_len steps (at most n_hist; the force must stay
+ * constant inside a segment).  After the last step, call
+ *   lb_adjoint_begin(h, aws, bytes, seg_len)   -- aws: caller-owned device
+ *       buffer of lb_adjoint_workspace_bytes(h, seg_len) bytes, 256-aligned;
+ *       the sweep will cover the steps before the current step count;
+ * then, for the segments from last to first,
+ *   lb_adjoint_segment(h, ckpt, dL_dux, n_steps)  -- ckpt: the state saved
+ *       at the segment's first step; the segment must end where the previous
+ *       call began; dL_dux: host array [n_steps][sum of lx*ly over channels]
+ *       of dL/du_x for each step of the segment (zero where the loss does
+ *       not sample), channels concatenated in order.  The segment is
+ *       replayed from ckpt (overwriting the forward state) and swept back;
+ * and finally
+ *   lb_adjoint_end(h, dL_dtheta)  -- host [n_ch][4]: dL/dG_inf, dL/dtau,
+ *       dL/dgamma_c, dL/dg_x, summed over the covered steps.
+ * Accumulation is per node in FP64 and reduced in node order (bitwise
+ * reproducible).  Arithmetic of the transposes: the handle's precision, with
+ * the history gather in FP64.
+ */
+size_t lb_adjoint_workspace_bytes(const lb_handle *h, int32_t seg_len);
+lb_status lb_adjoint_begin(lb_handle *h, void *d_aws, size_t bytes, int32_t seg_len);
+lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_dux,
+                             int32_t n_steps);
+lb_status lb_adjoint_end(lb_handle *h, double *dL_dtheta);
 
 /* Release host-side handle memory.  Device memory stays the caller's. */
 lb_status lb_destroy(lb_handle *h);

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbmax.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_ENONFINITE = 0, -1, -2, -3, -4, -5
-LB_F64, LB_F32 = 0, 1
+LB_F64, LB_F32, LB_F32_P64 = 0, 1, 2
 STATUS_NAMES = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EDEVICE",
                 -4: "LB_ESTATE", -5: "LB_ENONFINITE"}
 
@@ -62,6 +62,12 @@ SIGNATURES = {
     "lb_set_persistent": (ctypes.c_int, [_H, ctypes.c_int32]),
     "lb_profile": (ctypes.c_int, [_H, ctypes.c_int32]),
     "lb_kernel_time": (ctypes.c_int, [_H, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64)]),
+    "lb_set_params": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double]),
+    "lb_adjoint_workspace_bytes": (ctypes.c_size_t, [_H, ctypes.c_int32]),
+    "lb_adjoint_begin": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32]),
+    "lb_adjoint_segment": (ctypes.c_int, [_H, ctypes.c_void_p, _D, ctypes.c_int32]),
+    "lb_adjoint_end": (ctypes.c_int, [_H, _D]),
     "lb_destroy": (ctypes.c_int, [_H]),
     "lb_last_error": (ctypes.c_char_p, []),
 }

@@ -54,29 +54,31 @@ struct HistTile {
     int32_t ch, n0, k0, k1, chunk, pad;
 };
 
-// Kernel launchers (lbmax_kernels.hip).  All launches go on `st`.
+// Kernel launchers (lbmax_kernels.hip).  All launches go on `st`.  `prec`:
+// 0 = FP64 lattice and history, 1 = FP32 both, 2 = FP64 lattice (populations,
+// moments, stress planes) with FP32 history (ring and window sums).
 // `tcount` is the device step counter; a kernel works on step
 // t = *tcount + trel.
-void launch_init(bool f64, char *ws, const ChanDev *chans, int ch,
+void launch_init(int prec, char *ws, const ChanDev *chans, int ch,
                  const NodeTile *tiles, int n_tiles, const double *u0_dev,
                  hipStream_t st);
 void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 // The lattice kernel also zeroes the persistent-pass tile counters.
-void launch_lb(bool f64, char *ws, const ChanDev *chans, const NodeTile *tiles,
+void launch_lb(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
                int n_tiles, const int64_t *tcount, int trel, int *tile_counters,
                hipStream_t st);
 // History pass (first step of a block of `block` steps) for the tiles of the
 // channels whose lane width is `vec`.  persistent_grid > 0 launches that many
 // persistent workgroups claiming tiles from *counter.
-void launch_hist_pass(bool f64, int vec, int block, char *ws, const ChanDev *chans,
+void launch_hist_pass(int prec, int vec, int block, char *ws, const ChanDev *chans,
                       const HistTile *tiles, int n_tiles, const int64_t *tcount,
                       int trel, int persistent_grid, int *counter, hipStream_t st);
-int hist_pass_blocks_per_cu(bool f64, int vec, int block);
+int hist_pass_blocks_per_cu(int prec, int vec, int block);
 // FP64 combine of chunk partials into sigma and the block sums.
-void launch_combine(bool f64, int block, char *ws, const ChanDev *chans,
+void launch_combine(int prec, int block, char *ws, const ChanDev *chans,
                     const NodeTile *tiles, int n_tiles, hipStream_t st);
 // Step m (1 <= m < block) of a block: gradient, push, sigma from the block sums.
-void launch_hist_step(bool f64, int m, char *ws, const ChanDev *chans,
+void launch_hist_step(int prec, int m, char *ws, const ChanDev *chans,
                       const NodeTile *tiles, int n_tiles, const int64_t *tcount,
                       int trel, hipStream_t st);
 void launch_tick(int64_t *tcount, int64_t add, hipStream_t st);
@@ -84,7 +86,35 @@ void launch_set_force(ChanDev *chans, int ch, double gx, double gy,
                       hipStream_t st);
 // Readouts into FP64 staging (nodes of one channel): which = 0 fields
 // (rho, ux, uy), 1 stress (sxy, n1), 2 gradient (kxx, kxy, kyx, kyy).
-void launch_readout(bool f64, int which, char *ws, const ChanDev *chans,
+void launch_readout(int prec, int which, char *ws, const ChanDev *chans,
                     int ch, int n_nodes, double *stage, hipStream_t st);
+
+}  // namespace lbmax
+
+namespace lbmax {
+
+// Adjoint workspace of one channel (byte offsets into the adjoint workspace).
+struct alignas(64) AdjChan {
+    int64_t off_sbar_ring;  // [n_hist][np] R  adjoint of sigma_xy, row t mod n_hist
+    int64_t off_nbar;       // [9][np] R  adjoint of the post-collision populations
+    int64_t off_dbar;       // [9][np] R  adjoint of the pulled populations
+    int64_t off_fbar;       // [np] R     adjoint of the force f_x
+    int64_t off_shbar;      // [np] R     adjoint of the pushed shear rate
+    int64_t off_acc;        // [4][np] double  per-node parameter gradients
+    int64_t off_rec;        // [seg_len][10][np] R  n*(t-1) (9 planes), sigma_xy^{t-1}
+    int64_t off_dldu;       // [seg_len][np] double  dL/du_x of each step
+};
+
+void launch_adj_record(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
+                       int n_tiles, const int64_t *tcount, char *aws, const AdjChan *achans,
+                       int slot, hipStream_t st);
+void launch_adj_a(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
+                  int n_tiles, char *aws, const AdjChan *achans, int64_t t, hipStream_t st);
+void launch_adj_b(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
+                  int n_tiles, char *aws, const AdjChan *achans, int slot, hipStream_t st);
+void launch_adj_reduce(const ChanDev *chans, int n_ch, char *aws, const AdjChan *achans,
+                       double *out, hipStream_t st);
+void launch_set_params(ChanDev *chans, int ch, double g_inf, double tau_m, double gamma_c,
+                       hipStream_t st);
 
 }  // namespace lbmax

@@ -458,7 +458,7 @@ __device__ __forceinline__ void pass_bulk(const R *__restrict__ ring_s,
     }
 }
 
-template <typename R, int V, int M, int U, bool HAS_R>
+template <typename P, typename R, int V, int M, int U, bool HAS_R>
 __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *c,
                                           const HistTile &tl, int64_t t)
 {
@@ -482,18 +482,18 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
     int k = tl.k0;
     if (k == 0) {
         // Newest entry, age 0: gradient of this step's velocity, push it.
-        const R *vel = reinterpret_cast<const R *>(ws + c->off_vel);
+        const P *vel = reinterpret_cast<const P *>(ws + c->off_vel);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const int node = first + v;
             R s = R(0), r = R(0);
             if (node < c->n) {
                 const int y = node / c->lx, x = node - y * c->lx;
-                R kxx, kxy, kyx, kyy;
-                velocity_gradient<R>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx,
+                P kxx, kxy, kyx, kyy;
+                velocity_gradient<P>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx,
                                      kyy);
-                s = kxy;
-                r = HAS_R ? shear_rate<R>(kxx, kxy, kyx, kyy) : fabs(s);
+                s = (R)kxy;
+                r = HAS_R ? (R)shear_rate<P>(kxx, kxy, kyx, kyy) : fabs(s);
                 ring_s[(size_t)p * np + node] = s;
                 if (HAS_R)
                     ring_r[(size_t)p * np + node] = r;
@@ -546,7 +546,7 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
     }
     if (first >= c->n)
         return;
-    R *sig = reinterpret_cast<R *>(ws + c->off_sig);
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
     double *part = reinterpret_cast<double *>(ws + c->off_part);
     double *blk = reinterpret_cast<double *>(ws + c->off_blk);
     const size_t pplane = (size_t)c->max_chunks * np;
@@ -556,8 +556,8 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
         if (node >= c->n)
             break;
         if (c->nchunks == 1) {
-            sig[node] = (R)(c->g_inf * A[0][v].value());
-            sig[np + node] = (R)(c->g_inf * B[0][v].value());
+            sig[node] = (P)(c->g_inf * A[0][v].value());
+            sig[np + node] = (P)(c->g_inf * B[0][v].value());
 #pragma unroll
             for (int m = 1; m < M; ++m) {
                 blk[m * np + node] = A[m][v].value();
@@ -577,7 +577,7 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
 
 // One launch per (lane width V, block length M): the tiles of the channels
 // whose lane width is V.  Plain form: one workgroup per tile.
-template <typename R, int V, int M, int U>
+template <typename P, typename R, int V, int M, int U>
 __global__ __launch_bounds__(kBlock) void k_hist_pass(char *__restrict__ ws,
                                                       const ChanDev *__restrict__ chans,
                                                       const HistTile *__restrict__ tiles,
@@ -591,15 +591,15 @@ __global__ __launch_bounds__(kBlock) void k_hist_pass(char *__restrict__ ws,
         return;
     const int64_t t = *tcount + trel;
     if (c->has_r)
-        pass_tile<R, V, M, U, true>(ws, c, tl, t);
+        pass_tile<P, R, V, M, U, true>(ws, c, tl, t);
     else
-        pass_tile<R, V, M, U, false>(ws, c, tl, t);
+        pass_tile<P, R, V, M, U, false>(ws, c, tl, t);
 }
 
 // Persistent form: as many workgroups as fit on the chip at once; each claims
 // the next tile of the list (longest first) from a counter until the list
 // is exhausted.  The counter was zeroed by the lattice kernel of this step.
-template <typename R, int V, int M, int U>
+template <typename P, typename R, int V, int M, int U>
 __global__ __launch_bounds__(kBlock) void k_hist_pass_persistent(
     char *__restrict__ ws, const ChanDev *__restrict__ chans,
     const HistTile *__restrict__ tiles, int n_tiles, const int64_t *__restrict__ tcount,
@@ -619,9 +619,9 @@ __global__ __launch_bounds__(kBlock) void k_hist_pass_persistent(
         const ChanDev *c = chans + tl.ch;
         if (tl.n0 + (int)(threadIdx.x & ~63u) * V < c->n) {
             if (c->has_r)
-                pass_tile<R, V, M, U, true>(ws, c, tl, t);
+                pass_tile<P, R, V, M, U, true>(ws, c, tl, t);
             else
-                pass_tile<R, V, M, U, false>(ws, c, tl, t);
+                pass_tile<P, R, V, M, U, false>(ws, c, tl, t);
         }
     }
 }
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(kBlock) void k_hist_pass_persistent(
 // strain at the chunk's start).  Writes sigma of the pass step and the block
 // sums for the following steps.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename P>
 __global__ __launch_bounds__(kBlock) void k_combine(char *__restrict__ ws,
                                                     const ChanDev *__restrict__ chans,
                                                     const NodeTile *__restrict__ tiles,
@@ -660,9 +660,9 @@ __global__ __launch_bounds__(kBlock) void k_combine(char *__restrict__ ws,
         }
         O += part[kPlaneT * pplane + at];
     }
-    R *sig = reinterpret_cast<R *>(ws + c->off_sig);
-    sig[n] = (R)(c->g_inf * A[0]);
-    sig[np + n] = (R)(c->g_inf * B[0]);
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    sig[n] = (P)(c->g_inf * A[0]);
+    sig[np + n] = (P)(c->g_inf * B[0]);
     double *blk = reinterpret_cast<double *>(ws + c->off_blk);
     for (int m = 1; m < block; ++m) {
         blk[m * np + n] = A[m];
@@ -676,7 +676,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(char *__restrict__ ws,
 // Walking ages a = 0..m from the new entry back to entry t0 accumulates the
 // strain gamma(t, t - a); at a = m it is Delta_m.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename P, typename R>
 __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
                                                       const ChanDev *__restrict__ chans,
                                                       const NodeTile *__restrict__ tiles,
@@ -694,14 +694,14 @@ __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
     const int p = (int)(t % H);
     R *ring_s = reinterpret_cast<R *>(ws + c->off_ring_s);
     R *ring_r = reinterpret_cast<R *>(ws + c->off_ring_r);
-    const R *vel = reinterpret_cast<const R *>(ws + c->off_vel);
+    const P *vel = reinterpret_cast<const P *>(ws + c->off_vel);
     const int y = n / c->lx, x = n - y * c->lx;
-    R kxx, kxy, kyx, kyy;
-    velocity_gradient<R>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
-    const R s_new = kxy;
+    P kxx, kxy, kyx, kyy;
+    velocity_gradient<P>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
+    const R s_new = (R)kxy;
     ring_s[(size_t)p * np + n] = s_new;
     if (c->has_r)
-        ring_r[(size_t)p * np + n] = shear_rate<R>(kxx, kxy, kyx, kyy);
+        ring_r[(size_t)p * np + n] = (R)shear_rate<P>(kxx, kxy, kyx, kyy);
 
     const double *blk = reinterpret_cast<const double *>(ws + c->off_blk);
     const double A = blk[m * np + n];
@@ -721,9 +721,9 @@ __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
             sxx += w * 2.0 * s * gam * e;
         }
     }
-    R *sig = reinterpret_cast<R *>(ws + c->off_sig);
-    sig[n] = (R)(c->g_inf * (A + sxy));
-    sig[np + n] = (R)(c->g_inf * (B + 2.0 * gam * A + sxx));
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    sig[n] = (P)(c->g_inf * (A + sxy));
+    sig[np + n] = (P)(c->g_inf * (B + 2.0 * gam * A + sxx));
 }
 
 __global__ void k_tick(int64_t *tcount, int64_t add)
@@ -778,16 +778,30 @@ __global__ __launch_bounds__(kBlock) void k_readout(int which, const char *__res
 // ---------------------------------------------------------------------------
 static inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
-void launch_init(bool f64, char *ws, const ChanDev *chans, int ch,
-                 const NodeTile *, int n_tiles, const double *u0_dev,
-                 hipStream_t st)
+// Precision codes: 0 FP64 lattice + FP64 history, 1 FP32 + FP32,
+// 2 FP64 lattice + FP32 history.  P is the lattice type, H the history type.
+#define LBMAX_BY_PREC(prec, BODY)                                                \
+    do {                                                                         \
+        if ((prec) == 0) {                                                       \
+            typedef double P;                                                    \
+            typedef double H;                                                    \
+            BODY;                                                                \
+        } else if ((prec) == 1) {                                                \
+            typedef float P;                                                     \
+            typedef float H;                                                     \
+            BODY;                                                                \
+        } else {                                                                 \
+            typedef double P;                                                    \
+            typedef float H;                                                     \
+            BODY;                                                                \
+        }                                                                        \
+    } while (0)
+
+void launch_init(int prec, char *ws, const ChanDev *chans, int ch, const NodeTile *,
+                 int n_tiles, const double *u0_dev, hipStream_t st)
 {
-    if (f64)
-        hipLaunchKernelGGL(k_init<double>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
-                           chans, ch, u0_dev);
-    else
-        hipLaunchKernelGGL(k_init<float>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
-                           chans, ch, u0_dev);
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_init<P>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
+                                           chans, ch, u0_dev));
 }
 
 void launch_fill_zero(void *p, size_t bytes, hipStream_t st)
@@ -802,121 +816,101 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st)
                        reinterpret_cast<uint4 *>(p), n16);
 }
 
-void launch_lb(bool f64, char *ws, const ChanDev *chans, const NodeTile *tiles,
-               int n_tiles, const int64_t *tcount, int trel, int *tile_counters,
-               hipStream_t st)
+void launch_lb(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
+               const int64_t *tcount, int trel, int *tile_counters, hipStream_t st)
 {
-    if (f64)
-        hipLaunchKernelGGL(k_lb<double>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
-                           chans, tiles, tcount, trel, tile_counters);
-    else
-        hipLaunchKernelGGL(k_lb<float>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
-                           chans, tiles, tcount, trel, tile_counters);
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_lb<P>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
+                                           chans, tiles, tcount, trel, tile_counters));
 }
 
-void launch_hist_pass(bool f64, int vec, int block, char *ws, const ChanDev *chans,
+void launch_hist_pass(int prec, int vec, int block, char *ws, const ChanDev *chans,
                       const HistTile *tiles, int n_tiles, const int64_t *tcount, int trel,
                       int persistent_grid, int *counter, hipStream_t st)
 {
     if (n_tiles <= 0)
         return;
     const int grid = persistent_grid > 0 ? std::min(persistent_grid, n_tiles) : n_tiles;
-#define LBMAX_PASS(R, V, M, U)                                                   \
+#define LBMAX_PASS(V, M, U)                                                      \
     do {                                                                         \
         if (persistent_grid > 0)                                                 \
-            hipLaunchKernelGGL((k_hist_pass_persistent<R, V, M, U>), dim3(grid), \
+            hipLaunchKernelGGL((k_hist_pass_persistent<P, H, V, M, U>), dim3(grid), \
                                dim3(kBlock), 0, st, ws, chans, tiles, n_tiles,   \
                                tcount, trel, counter);                           \
         else                                                                     \
-            hipLaunchKernelGGL((k_hist_pass<R, V, M, U>), dim3(grid),            \
+            hipLaunchKernelGGL((k_hist_pass<P, H, V, M, U>), dim3(grid),         \
                                dim3(kBlock), 0, st, ws, chans, tiles, tcount,    \
                                trel);                                            \
     } while (0)
-#define LBMAX_PASS_V(R)                                                          \
+#define LBMAX_PASS_SHAPES                                                        \
     do {                                                                         \
         if (block == 1) {                                                        \
             if (vec == 4)                                                        \
-                LBMAX_PASS(R, 4, 1, 4);                                          \
+                LBMAX_PASS(4, 1, 4);                                             \
             else if (vec == 2)                                                   \
-                LBMAX_PASS(R, 2, 1, 8);                                          \
+                LBMAX_PASS(2, 1, 8);                                             \
             else                                                                 \
-                LBMAX_PASS(R, 1, 1, 8);                                          \
+                LBMAX_PASS(1, 1, 8);                                             \
         } else if (block == 2) {                                                 \
             if (vec == 1)                                                        \
-                LBMAX_PASS(R, 1, 2, 8);                                          \
+                LBMAX_PASS(1, 2, 8);                                             \
             else                                                                 \
-                LBMAX_PASS(R, 2, 2, 4);                                          \
+                LBMAX_PASS(2, 2, 4);                                             \
         } else if (block == 4) {                                                 \
             if (vec == 1)                                                        \
-                LBMAX_PASS(R, 1, 4, 8);                                          \
+                LBMAX_PASS(1, 4, 8);                                             \
             else                                                                 \
-                LBMAX_PASS(R, 2, 4, 4);                                          \
+                LBMAX_PASS(2, 4, 4);                                             \
         } else if (block == 8) {                                                 \
-            LBMAX_PASS(R, 1, 8, 8);                                              \
+            LBMAX_PASS(1, 8, 8);                                                 \
         } else {                                                                 \
-            LBMAX_PASS(R, 1, 16, 8);                                             \
+            LBMAX_PASS(1, 16, 8);                                                \
         }                                                                        \
     } while (0)
-    if (f64)
-        LBMAX_PASS_V(double);
-    else
-        LBMAX_PASS_V(float);
-#undef LBMAX_PASS_V
+    LBMAX_BY_PREC(prec, LBMAX_PASS_SHAPES);
+#undef LBMAX_PASS_SHAPES
 #undef LBMAX_PASS
 }
 
 // Workgroups of the persistent pass that are resident on one compute unit.
-int hist_pass_blocks_per_cu(bool f64, int vec, int block)
+int hist_pass_blocks_per_cu(int prec, int vec, int block)
 {
     int n = 0;
     hipError_t e = hipSuccess;
-#define LBMAX_OCC(R, V, M, U)                                                        \
+#define LBMAX_OCC(V, M, U)                                                           \
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-        &n, reinterpret_cast<const void *>(&k_hist_pass_persistent<R, V, M, U>), kBlock, 0)
-#define LBMAX_OCC_V(R)                                                               \
+        &n, reinterpret_cast<const void *>(&k_hist_pass_persistent<P, H, V, M, U>), kBlock, 0)
+#define LBMAX_OCC_SHAPES                                                             \
     do {                                                                             \
         if (block == 1)                                                              \
-            (vec == 4 ? (void)(LBMAX_OCC(R, 4, 1, 4))                                \
-                      : (vec == 2 ? (void)(LBMAX_OCC(R, 2, 1, 8))                    \
-                                  : (void)(LBMAX_OCC(R, 1, 1, 8))));                 \
+            (vec == 4 ? (void)(LBMAX_OCC(4, 1, 4))                                   \
+                      : (vec == 2 ? (void)(LBMAX_OCC(2, 1, 8)) : (void)(LBMAX_OCC(1, 1, 8)))); \
         else if (block == 2)                                                         \
-            (vec == 1 ? (void)(LBMAX_OCC(R, 1, 2, 8)) : (void)(LBMAX_OCC(R, 2, 2, 4)));  \
+            (vec == 1 ? (void)(LBMAX_OCC(1, 2, 8)) : (void)(LBMAX_OCC(2, 2, 4)));    \
         else if (block == 4)                                                         \
-            (vec == 1 ? (void)(LBMAX_OCC(R, 1, 4, 8)) : (void)(LBMAX_OCC(R, 2, 4, 4)));  \
+            (vec == 1 ? (void)(LBMAX_OCC(1, 4, 8)) : (void)(LBMAX_OCC(2, 4, 4)));    \
         else if (block == 8)                                                         \
-            (void)(LBMAX_OCC(R, 1, 8, 8));                                           \
+            (void)(LBMAX_OCC(1, 8, 8));                                              \
         else                                                                         \
-            (void)(LBMAX_OCC(R, 1, 16, 8));                                          \
+            (void)(LBMAX_OCC(1, 16, 8));                                             \
     } while (0)
-    if (f64)
-        LBMAX_OCC_V(double);
-    else
-        LBMAX_OCC_V(float);
-#undef LBMAX_OCC_V
+    LBMAX_BY_PREC(prec, LBMAX_OCC_SHAPES);
+#undef LBMAX_OCC_SHAPES
 #undef LBMAX_OCC
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-void launch_combine(bool f64, int block, char *ws, const ChanDev *chans,
-                    const NodeTile *tiles, int n_tiles, hipStream_t st)
+void launch_combine(int prec, int block, char *ws, const ChanDev *chans, const NodeTile *tiles,
+                    int n_tiles, hipStream_t st)
 {
-    if (f64)
-        hipLaunchKernelGGL(k_combine<double>, dim3(n_tiles), dim3(kBlock), 0, st, ws, chans,
-                           tiles, block);
-    else
-        hipLaunchKernelGGL(k_combine<float>, dim3(n_tiles), dim3(kBlock), 0, st, ws, chans,
-                           tiles, block);
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_combine<P>, dim3(n_tiles), dim3(kBlock), 0, st,
+                                           ws, chans, tiles, block));
 }
 
-void launch_hist_step(bool f64, int m, char *ws, const ChanDev *chans, const NodeTile *tiles,
+void launch_hist_step(int prec, int m, char *ws, const ChanDev *chans, const NodeTile *tiles,
                       int n_tiles, const int64_t *tcount, int trel, hipStream_t st)
 {
-    if (f64)
-        hipLaunchKernelGGL(k_hist_step<double>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
-                           chans, tiles, tcount, trel, m);
-    else
-        hipLaunchKernelGGL(k_hist_step<float>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
-                           chans, tiles, tcount, trel, m);
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_hist_step<P, H>), dim3(n_tiles), dim3(kBlock), 0,
+                                           st, ws, chans, tiles, tcount, trel, m));
 }
 
 void launch_tick(int64_t *tcount, int64_t add, hipStream_t st)
@@ -929,15 +923,285 @@ void launch_set_force(ChanDev *chans, int ch, double gx, double gy, hipStream_t 
     hipLaunchKernelGGL(k_set_force, dim3(1), dim3(64), 0, st, chans, ch, gx, gy);
 }
 
-void launch_readout(bool f64, int which, char *ws, const ChanDev *chans, int ch,
+void launch_readout(int prec, int which, char *ws, const ChanDev *chans, int ch,
                     int n_nodes, double *stage, hipStream_t st)
 {
-    if (f64)
-        hipLaunchKernelGGL(k_readout<double>, dim3(blocks_for(n_nodes)), dim3(kBlock),
-                           0, st, which, ws, chans, ch, stage);
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_readout<P>, dim3(blocks_for(n_nodes)),
+                                           dim3(kBlock), 0, st, which, ws, chans, ch, stage));
+}
+
+
+// ===========================================================================
+// Discrete adjoint of the step for unidirectional channels (lx = 1: d/dx
+// vanishes, sigma_xx never reaches the force, |gamma_dot| = |s|).  The
+// reverse sweep runs t = T-1 .. 0; per step two kernels:
+//   k_adj_a(t): sigma_bar^t = Dy^T fbar(t+1) pushed into the adjoint ring,
+//     nbar(t) = streaming^T dbar(t+1), and the history transpose, a gather
+//     over the future adjoint stresses:
+//       S0 = sum_j w_j sigma_bar^{t+j} E_j,  S1 = sum_j w_j sigma_bar^{t+j} E_j j,
+//       E_j = exp(-j (1/tau + |s_t|/gamma_c)),
+//       sbar_t = G (S0 - |s_t| S1 / gamma_c)
+//     (d/ds of s E_j(|s|) is E_j (1 - j |s| / gamma_c)), plus the parameter
+//     terms dL/dG += s_t S0, dL/dtau += G s_t S1 / tau^2,
+//     dL/dgamma_c += G s_t |s_t| S1 / gamma_c^2.
+//   k_adj_b(t): the step's collision, moments and force recomputed from the
+//     recorded n*(t-1), sigma^{t-1}; their transposes give dbar(t), fbar(t),
+//     and dL/dg_x += fbar_x rho.
+// Per-node FP64 accumulators; no atomics, fixed order.
+// ===========================================================================
+
+// d s(y) / d u(yp) of the velocity-gradient stencil in y.
+template <typename R>
+__device__ __forceinline__ R coef_grad(int y, int yp, int ly)
+{
+    if (y == 0)
+        return yp == 0 ? R(1) : (yp == 1 ? R(1) / R(3) : R(0));
+    if (y == ly - 1)
+        return yp == ly - 1 ? R(-1) : (yp == ly - 2 ? R(-1) / R(3) : R(0));
+    return yp == y + 1 ? R(0.5) : (yp == y - 1 ? R(-0.5) : R(0));
+}
+
+// d f(y) / d sigma(yp) of the stress-divergence stencil in y.
+template <typename R>
+__device__ __forceinline__ R coef_div(int y, int yp, int ly)
+{
+    if (y == 0)
+        return yp == 0 ? R(-1.5) : (yp == 1 ? R(2) : (yp == 2 ? R(-0.5) : R(0)));
+    if (y == ly - 1)
+        return yp == ly - 1 ? R(1.5) : (yp == ly - 2 ? R(-2) : (yp == ly - 3 ? R(0.5) : R(0)));
+    return yp == y + 1 ? R(0.5) : (yp == y - 1 ? R(-0.5) : R(0));
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_adj_record(char *__restrict__ ws,
+                                                       const ChanDev *__restrict__ chans,
+                                                       const NodeTile *__restrict__ tiles,
+                                                       const int64_t *__restrict__ tcount,
+                                                       char *__restrict__ aws,
+                                                       const AdjChan *__restrict__ achans,
+                                                       int slot)
+{
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const AdjChan *a = achans + tl.ch;
+    const int n = tl.n0 + threadIdx.x;
+    if (n >= c->n)
+        return;
+    const size_t np = (size_t)c->np;
+    const int64_t t = *tcount;
+    const R *pop = reinterpret_cast<const R *>(ws + c->off_pop) + ((t + 1) & 1) * 9 * np;
+    R *rec = reinterpret_cast<R *>(aws + a->off_rec) + (size_t)slot * 10 * np;
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        rec[q * np + n] = pop[q * np + n];
+    rec[9 * np + n] = reinterpret_cast<const R *>(ws + c->off_sig)[n];
+}
+
+template <typename R, typename RH>
+__global__ __launch_bounds__(kBlock) void k_adj_a(char *__restrict__ ws,
+                                                  const ChanDev *__restrict__ chans,
+                                                  const NodeTile *__restrict__ tiles,
+                                                  char *__restrict__ aws,
+                                                  const AdjChan *__restrict__ achans,
+                                                  int64_t t)
+{
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const AdjChan *a = achans + tl.ch;
+    const int y = tl.n0 + threadIdx.x;  // lx = 1: node index = y
+    const int ly = c->ly;
+    if (y >= ly)
+        return;
+    const size_t np = (size_t)c->np;
+    const int H = c->n_hist;
+    const int p = (int)(t % H);
+    R *sring = reinterpret_cast<R *>(aws + a->off_sbar_ring);
+    const R *fbar = reinterpret_cast<const R *>(aws + a->off_fbar);
+    const R *dbar = reinterpret_cast<const R *>(aws + a->off_dbar);
+    R *nbar = reinterpret_cast<R *>(aws + a->off_nbar);
+
+    // sigma_bar^t: transpose of the divergence stencil applied to fbar(t+1)
+    R sb = R(0);
+    for (int yy = max(0, y - 2); yy <= min(ly - 1, y + 2); ++yy)
+        sb += coef_div<R>(yy, y, ly) * fbar[yy];
+    sring[(size_t)p * np + y] = sb;
+
+    // nbar(t): transpose of the pull-stream (the push map) applied to dbar(t+1)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int yt = y + QY[q];
+        nbar[q * np + y] = (yt >= 0 && yt < ly) ? dbar[q * np + yt] : dbar[QOPP[q] * np + y];
+    }
+
+    // history transpose for the entry of step t
+    const R s = (R)reinterpret_cast<const RH *>(ws + c->off_ring_s)[(size_t)p * np + y];
+    const R as = fabs(s);
+    const double rate = c->inv_tau + c->inv_gc * (double)as;
+    double S0 = 0.0, S1 = 0.0;
+    int slot = p;
+    for (int j = 0; j < H; ++j) {
+        const double w = (j == 0 || j == H - 1) ? 0.5 : 1.0;
+        const double e = exp(-(double)j * rate);
+        const double v = w * (double)sring[(size_t)slot * np + y] * e;
+        S0 += v;
+        S1 += v * (double)j;
+        slot = slot + 1 == H ? 0 : slot + 1;
+    }
+    const double G = c->g_inf;
+    reinterpret_cast<R *>(aws + a->off_shbar)[y] = (R)(G * (S0 - (double)as * S1 * c->inv_gc));
+    double *acc = reinterpret_cast<double *>(aws + a->off_acc);
+    acc[y] += (double)s * S0;
+    acc[np + y] += G * (double)s * S1 * c->inv_tau * c->inv_tau;
+    acc[2 * np + y] += G * (double)s * (double)as * S1 * c->inv_gc * c->inv_gc;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_adj_b(char *__restrict__ ws,
+                                                  const ChanDev *__restrict__ chans,
+                                                  const NodeTile *__restrict__ tiles,
+                                                  char *__restrict__ aws,
+                                                  const AdjChan *__restrict__ achans,
+                                                  int slot)
+{
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const AdjChan *a = achans + tl.ch;
+    const int y = tl.n0 + threadIdx.x;
+    const int ly = c->ly;
+    if (y >= ly)
+        return;
+    const size_t np = (size_t)c->np;
+    const R *rec = reinterpret_cast<const R *>(aws + a->off_rec) + (size_t)slot * 10 * np;
+    const R *sig = rec + 9 * np;
+
+    // forward quantities of the step, in the order and arithmetic of k_lb
+    R d[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int ys = y - QY[q];
+        d[q] = (ys >= 0 && ys < ly) ? rec[q * np + ys] : rec[QOPP[q] * np + y];
+    }
+    const R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    const R jx = (d[1] - d[2]) + (d[5] - d[6]) + (d[7] - d[8]);
+    const R jy = (d[3] - d[4]) + (d[5] - d[6]) + (d[8] - d[7]);
+    const R rho = R(1) + drho;
+    R dys;
+    if (y == 0)
+        dys = R(0.5) * (R(-3) * sig[0] + R(4) * sig[1] - sig[2]);
+    else if (y == ly - 1)
+        dys = R(0.5) * (R(3) * sig[y] - R(4) * sig[y - 1] + sig[y - 2]);
     else
-        hipLaunchKernelGGL(k_readout<float>, dim3(blocks_for(n_nodes)), dim3(kBlock),
-                           0, st, which, ws, chans, ch, stage);
+        dys = R(0.5) * (sig[y + 1] - sig[y - 1]);
+    const R gx = (R)c->gx;
+    const R fx = dys + rho * gx;
+    const R ux = (jx + R(0.5) * fx) / rho;
+    const R uy = jy / rho;
+    const R om = (R)c->omega;
+    const R pf = R(1) - R(0.5) * om;
+
+    // collision + forcing transpose
+    const R *nbar = reinterpret_cast<const R *>(aws + a->off_nbar);
+    R A[9];
+    R drho_b = R(0), ux_b = R(0), uy_b = R(0), fx_b = R(0);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        A[q] = nbar[q * np + y];
+        const R cx = R(QX[q]), cy = R(QY[q]);
+        const R w = qweight<R>(q);
+        const R cu = cx * ux + cy * uy;
+        const R P = R(3) * cu + R(4.5) * cu * cu - R(1.5) * (ux * ux + uy * uy);
+        drho_b += om * A[q] * w * (R(1) + P);
+        ux_b += om * A[q] * w * rho * (R(3) * cx + R(9) * cu * cx - R(3) * ux) +
+                A[q] * w * pf * (R(-3) * fx + R(9) * cx * cx * fx);
+        uy_b += om * A[q] * w * rho * (R(3) * cy + R(9) * cu * cy - R(3) * uy) +
+                A[q] * w * pf * R(9) * cy * cx * fx;
+        fx_b += A[q] * w * pf * (R(3) * (cx - ux) + R(9) * cu * cx);
+    }
+    // the loss and the velocity-gradient transpose
+    ux_b += (R)reinterpret_cast<const double *>(aws + a->off_dldu)[(size_t)slot * np + y];
+    const R *shbar = reinterpret_cast<const R *>(aws + a->off_shbar);
+    for (int yy = max(0, y - 1); yy <= min(ly - 1, y + 1); ++yy)
+        ux_b += coef_grad<R>(yy, y, ly) * shbar[yy];
+    // u = (j + f/2) / rho
+    const R jx_b = ux_b / rho;
+    const R jy_b = uy_b / rho;
+    fx_b += ux_b / (R(2) * rho);
+    drho_b -= (ux * ux_b + uy * uy_b) / rho;
+    // f_x = Dy sigma + rho g_x
+    drho_b += fx_b * gx;
+    double *acc = reinterpret_cast<double *>(aws + a->off_acc);
+    acc[3 * np + y] += (double)fx_b * (double)rho;
+    // moments of the pulled populations
+    R *dbar = reinterpret_cast<R *>(aws + a->off_dbar);
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        dbar[q * np + y] = (R(1) - om) * A[q] + drho_b + R(QX[q]) * jx_b + R(QY[q]) * jy_b;
+    reinterpret_cast<R *>(aws + a->off_fbar)[y] = fx_b;
+}
+
+// Sum the per-node parameter gradients of every channel in node order.
+__global__ void k_adj_reduce(const ChanDev *__restrict__ chans, int n_ch,
+                             const char *__restrict__ aws, const AdjChan *__restrict__ achans,
+                             double *__restrict__ out)
+{
+    const int ch = blockIdx.x;
+    if (ch >= n_ch || threadIdx.x >= 4)
+        return;
+    const ChanDev *c = chans + ch;
+    const double *acc = reinterpret_cast<const double *>(aws + achans[ch].off_acc) +
+                        (size_t)threadIdx.x * c->np;
+    double sum = 0.0;
+    for (int n = 0; n < c->n; ++n)
+        sum += acc[n];
+    out[ch * 4 + threadIdx.x] = sum;
+}
+
+__global__ void k_set_params(ChanDev *chans, int ch, double g_inf, double tau_m, double gamma_c)
+{
+    if (threadIdx.x == 0) {
+        ChanDev *c = chans + ch;
+        c->g_inf = g_inf;
+        c->inv_tau = 1.0 / tau_m;
+        c->inv_gc = isinf(gamma_c) ? 0.0 : 1.0 / gamma_c;
+        c->l2_tau = 1.4426950408889634 * c->inv_tau;
+        c->l2_gc = 1.4426950408889634 * c->inv_gc;
+    }
+}
+
+void launch_adj_record(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
+                       int n_tiles, const int64_t *tcount, char *aws, const AdjChan *achans,
+                       int slot, hipStream_t st)
+{
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_adj_record<P>, dim3(n_tiles), dim3(kBlock), 0, st,
+                                           ws, chans, tiles, tcount, aws, achans, slot));
+}
+
+void launch_adj_a(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
+                  char *aws, const AdjChan *achans, int64_t t, hipStream_t st)
+{
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_a<P, H>), dim3(n_tiles), dim3(kBlock), 0, st,
+                                           ws, chans, tiles, aws, achans, t));
+}
+
+void launch_adj_b(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
+                  char *aws, const AdjChan *achans, int slot, hipStream_t st)
+{
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_adj_b<P>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
+                                           chans, tiles, aws, achans, slot));
+}
+
+void launch_adj_reduce(const ChanDev *chans, int n_ch, char *aws, const AdjChan *achans,
+                       double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adj_reduce, dim3(n_ch), dim3(64), 0, st, chans, n_ch, aws, achans,
+                       out);
+}
+
+void launch_set_params(ChanDev *chans, int ch, double g_inf, double tau_m, double gamma_c,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_params, dim3(1), dim3(64), 0, st, chans, ch, g_inf, tau_m,
+                       gamma_c);
 }
 
 }  // namespace lbmax

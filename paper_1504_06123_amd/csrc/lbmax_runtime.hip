@@ -114,9 +114,14 @@ int max_chunks_for(int n_hist, int np)
     return (int)std::min<int64_t>(m, cap);
 }
 
+// Element sizes of the lattice planes and of the history ring.
+size_t lattice_bytes(lb_precision prec) { return prec == LB_F32 ? 4 : 8; }
+size_t history_bytes(lb_precision prec) { return prec == LB_F64 ? 8 : 4; }
+int prec_code(lb_precision prec) { return prec == LB_F64 ? 0 : (prec == LB_F32 ? 1 : 2); }
+
 Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
 {
-    const size_t R = prec == LB_F64 ? 8 : 4;
+    const size_t R = lattice_bytes(prec), RH = history_bytes(prec);
     Plan P;
     size_t off = 0;
     P.off_tcount = off;
@@ -169,11 +174,12 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         off = align_up(off + 2 * plane, 256);
         c.off_rho = (int64_t)off;
         off = align_up(off + plane, 256);
+        const size_t hplane = (size_t)c.np * RH;
         c.off_ring_s = (int64_t)off;
-        off = align_up(off + (size_t)c.n_hist * plane, 256);
+        off = align_up(off + (size_t)c.n_hist * hplane, 256);
         c.off_ring_r = (int64_t)off;
         if (c.has_r)
-            off = align_up(off + (size_t)c.n_hist * plane, 256);
+            off = align_up(off + (size_t)c.n_hist * hplane, 256);
         c.off_part = (int64_t)off;
         if (c.max_chunks > 1)
             off = align_up(off + (size_t)kPartPlanes * c.max_chunks * c.np * sizeof(double),
@@ -190,7 +196,7 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
 struct lb_handle {
     int n_ch = 0;
     lb_precision prec = LB_F32;
-    bool f64 = false;
+    int pc = 1;  // kernel precision code
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
@@ -223,6 +229,14 @@ struct lb_handle {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // adjoint sweep
+    char *aws = nullptr;
+    size_t aws_bytes = 0;
+    AdjChan *d_achans = nullptr;
+    double *d_adj_out = nullptr;
+    std::vector<AdjChan> achans;
+    int adj_seg_len = 0;
+    int64_t adj_next = -1;  // the next segment must end at this step (-1: no sweep)
     // timing: event pairs recorded around launches, resolved on demand
     bool profile = false;
     std::vector<hipEvent_t> free_events;
@@ -391,7 +405,7 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
         }
         HIP_TRY(h, hipEventRecord(e[0], st));
     }
-    launch_lb(h->f64, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
+    launch_lb(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
               h->d_tcount, trel, h->d_tile_counters, st);
     if (timed) {
         HIP_TRY(h, hipEventRecord(e[1], st));
@@ -401,17 +415,17 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
         static const int kVec[3] = {1, 2, 4};
         for (int g = 0; g < 3; ++g) {
             const int pgrid =
-                h->persistent ? h->num_cus * hist_pass_blocks_per_cu(h->f64, kVec[g], h->block)
+                h->persistent ? h->num_cus * hist_pass_blocks_per_cu(h->pc, kVec[g], h->block)
                               : 0;
-            launch_hist_pass(h->f64, kVec[g], h->block, h->ws, h->d_chans,
+            launch_hist_pass(h->pc, kVec[g], h->block, h->ws, h->d_chans,
                              h->d_hist_tiles + h->hist_group_begin[g], h->hist_group_count[g],
                              h->d_tcount, trel, pgrid, h->d_tile_counters + g, st);
         }
         if (h->any_chunked)
-            launch_combine(h->f64, h->block, h->ws, h->d_chans, h->d_node_tiles,
+            launch_combine(h->pc, h->block, h->ws, h->d_chans, h->d_node_tiles,
                            h->n_node_tiles, st);
     } else {
-        launch_hist_step(h->f64, m, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
+        launch_hist_step(h->pc, m, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
                          h->d_tcount, trel, st);
     }
     if (timed) {
@@ -463,7 +477,7 @@ lb_status readout(lb_handle *h, int32_t ch, int which, int comps,
     if (!h->has_out)
         return fail(LB_ESTATE, "no completed step to read");
     const int N = h->plan.chans[ch].n;
-    launch_readout(h->f64, which, h->ws, h->d_chans, ch, N, h->d_stage, h->stream);
+    launch_readout(h->pc, which, h->ws, h->d_chans, ch, N, h->d_stage, h->stream);
     s = check_launch(h, "readout");
     if (s != LB_OK)
         return s;
@@ -487,17 +501,18 @@ struct Section {
 std::vector<Section> state_sections(const lb_handle *h, int ci, int64_t t)
 {
     const ChanDev &c = h->plan.chans[ci];
-    const size_t R = h->f64 ? 8 : 4;
+    const size_t R = lattice_bytes(h->prec), RH = history_bytes(h->prec);
     const size_t rowb = (size_t)c.n * R, pitch = (size_t)c.np * R;
+    const size_t hrowb = (size_t)c.n * RH, hpitch = (size_t)c.np * RH;
     const int64_t cur = c.off_pop + (int64_t)(((t + 1) & 1) * 9 * pitch);
     std::vector<Section> v;
     v.push_back({cur, 9, rowb, pitch});
     v.push_back({c.off_sig, 2, rowb, pitch});
     v.push_back({c.off_vel, 2, rowb, pitch});
     v.push_back({c.off_rho, 1, rowb, pitch});
-    v.push_back({c.off_ring_s, (size_t)c.n_hist, rowb, pitch});
+    v.push_back({c.off_ring_s, (size_t)c.n_hist, hrowb, hpitch});
     if (c.has_r)
-        v.push_back({c.off_ring_r, (size_t)c.n_hist, rowb, pitch});
+        v.push_back({c.off_ring_r, (size_t)c.n_hist, hrowb, hpitch});
     v.push_back({c.off_blk, (size_t)2 * kMaxBlock, (size_t)c.n * sizeof(double),
                  (size_t)c.np * sizeof(double)});
     return v;
@@ -514,6 +529,64 @@ size_t state_size(const lb_handle *h)
     return off;
 }
 
+
+// ---------------------------------------------------------------------------
+// Adjoint sweep
+// ---------------------------------------------------------------------------
+struct AdjPlan {
+    size_t total = 0, off_table = 0, off_out = 0;
+    std::vector<AdjChan> chans;
+};
+
+AdjPlan make_adj_plan(const lb_handle *h, int seg_len)
+{
+    const size_t R = lattice_bytes(h->prec);
+    AdjPlan P;
+    size_t off = 0;
+    P.off_table = off;
+    off = align_up(off + (size_t)h->n_ch * sizeof(AdjChan), 256);
+    P.off_out = off;
+    off = align_up(off + (size_t)h->n_ch * 4 * sizeof(double), 256);
+    P.chans.resize(h->n_ch);
+    for (int ci = 0; ci < h->n_ch; ++ci) {
+        const ChanDev &c = h->plan.chans[ci];
+        const size_t plane = (size_t)c.np * R;
+        AdjChan &a = P.chans[ci];
+        a.off_sbar_ring = (int64_t)off;
+        off = align_up(off + (size_t)c.n_hist * plane, 256);
+        a.off_nbar = (int64_t)off;
+        off = align_up(off + 9 * plane, 256);
+        a.off_dbar = (int64_t)off;
+        off = align_up(off + 9 * plane, 256);
+        a.off_fbar = (int64_t)off;
+        off = align_up(off + plane, 256);
+        a.off_shbar = (int64_t)off;
+        off = align_up(off + plane, 256);
+        a.off_acc = (int64_t)off;
+        off = align_up(off + 4 * (size_t)c.np * sizeof(double), 256);
+        a.off_rec = (int64_t)off;
+        off = align_up(off + (size_t)seg_len * 10 * plane, 256);
+        a.off_dldu = (int64_t)off;
+        off = align_up(off + (size_t)seg_len * c.np * sizeof(double), 256);
+    }
+    P.total = off;
+    return P;
+}
+
+std::string adjoint_unsupported(const lb_handle *h, int seg_len)
+{
+    for (int ci = 0; ci < h->n_ch; ++ci) {
+        const ChanDev &c = h->plan.chans[ci];
+        if (c.lx != 1 || c.has_r)
+            return "the adjoint covers unidirectional channels (lx = 1, gy = 0, u0_y = 0); "
+                   "channel " + std::to_string(ci) + " is not";
+        if (seg_len > c.n_hist)
+            return "seg_len must not exceed the history window of every channel";
+    }
+    if (seg_len < 1)
+        return "seg_len must be >= 1";
+    return "";
+}
 }  // namespace
 
 extern "C" {
@@ -522,7 +595,7 @@ const char *lb_last_error(void) { return g_err.c_str(); }
 
 size_t lb_workspace_bytes(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
 {
-    if (prec != LB_F64 && prec != LB_F32) {
+    if (prec != LB_F64 && prec != LB_F32 && prec != LB_F32_P64) {
         g_err = "unknown precision";
         return 0;
     }
@@ -540,7 +613,7 @@ lb_status lb_init(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec, vo
     if (!out)
         return fail(LB_EINVAL, "out is NULL");
     *out = nullptr;
-    if (prec != LB_F64 && prec != LB_F32)
+    if (prec != LB_F64 && prec != LB_F32 && prec != LB_F32_P64)
         return fail(LB_EINVAL, "unknown precision");
     std::string why = check_desc(ch, n_ch);
     if (!why.empty())
@@ -557,7 +630,7 @@ lb_status lb_init(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec, vo
     lb_handle *h = new lb_handle();
     h->n_ch = n_ch;
     h->prec = prec;
-    h->f64 = prec == LB_F64;
+    h->pc = prec_code(prec);
     h->ws = static_cast<char *>(d_ws);
     h->ws_bytes = ws_bytes;
     h->stream = static_cast<hipStream_t>(stream);
@@ -612,7 +685,7 @@ lb_status lb_init(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec, vo
                 return bail(fail(LB_EDEVICE, "u0 upload failed"));
             u0_dev = h->d_stage;
         }
-        launch_init(h->f64, h->ws, h->d_chans, i, nullptr, (c.n + kBlock - 1) / kBlock,
+        launch_init(h->pc, h->ws, h->d_chans, i, nullptr, (c.n + kBlock - 1) / kBlock,
                     u0_dev, h->stream);
         s = check_launch(h, "init");
         if (s != LB_OK)
@@ -922,6 +995,151 @@ lb_status lb_kernel_time(lb_handle *h, int32_t which, double *total_ms, int64_t 
         *total_ms = h->kernel_ms[which];
     if (launches)
         *launches = h->kernel_launches[which];
+    return LB_OK;
+}
+
+
+lb_status lb_set_params(lb_handle *h, int32_t ch, double g_inf, double tau_m, double gamma_c)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (ch < 0 || ch >= h->n_ch)
+        return fail(LB_EINVAL, "channel index out of range");
+    if (!std::isfinite(g_inf) || g_inf < 0.0 || !std::isfinite(tau_m) || !(tau_m > 0.0) ||
+        std::isnan(gamma_c) || !(gamma_c > 0.0))
+        return fail(LB_EINVAL, "need g_inf >= 0, tau_m > 0 finite, gamma_c > 0 (or +inf)");
+    ChanDev &c = h->plan.chans[ch];
+    c.g_inf = g_inf;
+    c.inv_tau = 1.0 / tau_m;
+    c.inv_gc = std::isinf(gamma_c) ? 0.0 : 1.0 / gamma_c;
+    c.l2_tau = M_LOG2E * c.inv_tau;
+    c.l2_gc = M_LOG2E * c.inv_gc;
+    launch_set_params(h->d_chans, ch, g_inf, tau_m, gamma_c, h->stream);
+    return check_launch(h, "set_params");
+}
+
+size_t lb_adjoint_workspace_bytes(const lb_handle *h, int32_t seg_len)
+{
+    if (!h)
+        return 0;
+    std::string why = adjoint_unsupported(h, seg_len);
+    if (!why.empty()) {
+        g_err = why;
+        return 0;
+    }
+    return make_adj_plan(h, seg_len).total;
+}
+
+lb_status lb_adjoint_begin(lb_handle *h, void *d_aws, size_t bytes, int32_t seg_len)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    std::string why = adjoint_unsupported(h, seg_len);
+    if (!why.empty())
+        return fail(LB_EINVAL, why);
+    if (!d_aws || reinterpret_cast<uintptr_t>(d_aws) % 256 != 0)
+        return fail(LB_ENOMEM, "adjoint workspace must be non-NULL and 256-byte aligned");
+    AdjPlan P = make_adj_plan(h, seg_len);
+    if (bytes < P.total)
+        return fail(LB_ENOMEM, "adjoint workspace too small: need " + std::to_string(P.total));
+    h->aws = static_cast<char *>(d_aws);
+    h->aws_bytes = bytes;
+    h->achans = P.chans;
+    h->d_achans = reinterpret_cast<AdjChan *>(h->aws + P.off_table);
+    h->d_adj_out = reinterpret_cast<double *>(h->aws + P.off_out);
+    h->adj_seg_len = seg_len;
+    launch_fill_zero(h->aws, P.total, h->stream);
+    s = check_launch(h, "adjoint zero fill");
+    if (s != LB_OK)
+        return s;
+    HIP_TRY(h, hipMemcpyAsync(h->d_achans, h->achans.data(), h->achans.size() * sizeof(AdjChan),
+                              hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->adj_next = h->t;
+    return LB_OK;
+}
+
+lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_dux,
+                             int32_t n_steps)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (h->adj_next < 0)
+        return fail(LB_ESTATE, "no adjoint sweep in progress (call lb_adjoint_begin)");
+    if (n_steps < 1 || n_steps > h->adj_seg_len)
+        return fail(LB_EINVAL, "n_steps must be in [1, seg_len]");
+    if (!dL_dux)
+        return fail(LB_EINVAL, "dL_dux is NULL");
+    const int64_t want_end = h->adj_next;
+    s = lb_load_state(h, d_ckpt);
+    if (s != LB_OK)
+        return s;
+    const int64_t t0 = h->t;
+    if (t0 + n_steps != want_end) {
+        h->poisoned = true;
+        return fail(LB_ESTATE, "segment does not end where the previous one began; handle "
+                               "poisoned");
+    }
+    // replay the segment, recording each step's input populations and stress
+    for (int i = 0; i < n_steps; ++i) {
+        launch_adj_record(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
+                          h->d_tcount, h->aws, h->d_achans, i, h->stream);
+        s = check_launch(h, "adjoint record");
+        if (s != LB_OK)
+            return s;
+        s = lb_step(h, 1);
+        if (s != LB_OK)
+            return s;
+    }
+    // dL/du_x of the segment: host [n_steps][sum of nodes]
+    size_t total_nodes = 0;
+    for (const ChanDev &c : h->plan.chans)
+        total_nodes += (size_t)c.n;
+    size_t col = 0;
+    for (int ci = 0; ci < h->n_ch; ++ci) {
+        const ChanDev &c = h->plan.chans[ci];
+        HIP_TRY(h, hipMemcpy2DAsync(h->aws + h->achans[ci].off_dldu, (size_t)c.np * sizeof(double),
+                                    dL_dux + col, total_nodes * sizeof(double),
+                                    (size_t)c.n * sizeof(double), (size_t)n_steps,
+                                    hipMemcpyHostToDevice, h->stream));
+        col += (size_t)c.n;
+    }
+    // reverse sweep over the segment
+    for (int64_t t = t0 + n_steps - 1; t >= t0; --t) {
+        launch_adj_a(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
+                     h->d_achans, t, h->stream);
+        launch_adj_b(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
+                     h->d_achans, (int)(t - t0), h->stream);
+        s = check_launch(h, "adjoint step");
+        if (s != LB_OK)
+            return s;
+    }
+    // the host buffer may be reused once this returns
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->adj_next = t0;
+    return LB_OK;
+}
+
+lb_status lb_adjoint_end(lb_handle *h, double *dL_dtheta)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (h->adj_next < 0)
+        return fail(LB_ESTATE, "no adjoint sweep in progress");
+    if (!dL_dtheta)
+        return fail(LB_EINVAL, "dL_dtheta is NULL");
+    launch_adj_reduce(h->d_chans, h->n_ch, h->aws, h->d_achans, h->d_adj_out, h->stream);
+    s = check_launch(h, "adjoint reduce");
+    if (s != LB_OK)
+        return s;
+    HIP_TRY(h, hipMemcpyAsync(dL_dtheta, h->d_adj_out, (size_t)h->n_ch * 4 * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->adj_next = -1;
     return LB_OK;
 }
 

@@ -20,6 +20,8 @@ def _precision_code(precision: str) -> int:
         return _lib.LB_F64
     if p in ("f32", "fp32", "float32", "float"):
         return _lib.LB_F32
+    if p in ("f32p64", "f32_p64", "mixed"):
+        return _lib.LB_F32_P64
     raise ValueError(f"unknown precision {precision!r}")
 
 
@@ -60,8 +62,8 @@ class Solver:
     """A set of channels advanced together on one GPU.
 
     channels: sequence of channel descriptions (see make_descs).
-    precision: "f32" (FP32 populations and Kahan history sums, FP64 strain)
-    or "f64".
+    precision: "f32" (FP32 populations and Kahan history sums, FP64 strain),
+    "f32p64" (FP64 lattice state, FP32 Kahan history) or "f64".
     """
 
     def __init__(self, channels: Sequence, precision: str = "f32",
@@ -216,7 +218,9 @@ def pack_state_header(t: int, n_ch: int, precision: str, total_bytes: int,
 
 def state_layout(channels: Sequence, precision: str = "f32"):
     """Byte offsets of the sections of a state buffer (include/lbmax.h)."""
-    R = 8 if _precision_code(precision) == _lib.LB_F64 else 4
+    code = _precision_code(precision)
+    R = 4 if code == _lib.LB_F32 else 8          # lattice planes
+    RH = 8 if code == _lib.LB_F64 else 4         # history ring
 
     def up(x):
         return (x + 255) // 256 * 256
@@ -229,10 +233,12 @@ def state_layout(channels: Sequence, precision: str = "f32"):
                (getattr(ch, "u0", None) is None or
                 not np.any(np.asarray(ch.u0, dtype=np.float64).reshape(2, -1)[1])))
         sec = {}
-        for name, rows in (("pop", 9), ("sig", 2), ("vel", 2), ("drho", 1),
-                           ("ring_s", int(ch.n_hist))) + ((() if uni else (("ring_r", int(ch.n_hist)),))):
+        for name, rows in (("pop", 9), ("sig", 2), ("vel", 2), ("drho", 1)):
             sec[name] = (off, rows, N)
             off = up(off + rows * N * R)
+        for name in ("ring_s",) + (() if uni else ("ring_r",)):
+            sec[name] = (off, int(ch.n_hist), N)
+            off = up(off + int(ch.n_hist) * N * RH)
         sec["blk"] = (off, 32, N)   # doubles
         off = up(off + 32 * N * 8)
         sec["force"] = (off, 1, 2)

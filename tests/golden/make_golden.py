@@ -5,7 +5,8 @@ seeded inputs of ``workloads``; nothing is read from the GPU path.  Usage:
 
     python tests/golden/make_golden.py NAME [NAME ...]     (or "all")
 
-Names and the runs they store (sampled u_x, u_y, sigma_xy, N1, rho):
+Names and the runs they store (sampled u_x, sigma_xy, N1; u_y and rho as
+well for the 2D runs):
   startup_cessation   1 x 256, window 8192, 20000 steps on + 20000 off,
                       every 1000 steps
   large_2d_64x32      the large 2D channel recipe on a 64 x 32 grid with the
@@ -16,7 +17,13 @@ Names and the runs they store (sampled u_x, u_y, sigma_xy, N1, rho):
                       every column
   batched_cheap8      the 8 batched channels of smallest ly*window, full
                       10000 steps, every 1000
-  batched_all_1000    all 64 batched channels, 1000 steps, every 100
+  batched_all_1000    all 64 batched channels, 1000 steps, every 250
+  differentiation     the 1 x 128 differentiation run: u_x samples (every 200
+                      steps) at the true parameters (the target) and at the
+                      evaluation point p0, the loss
+                      L = sum over samples and nodes of (u_x(p0) - u_x(true))^2,
+                      and dL/dp by central differences with relative step
+                      1e-6 for p = (G_inf, tau, gamma_c, g_x)
 """
 from __future__ import annotations
 
@@ -47,11 +54,44 @@ def runs():
         "large_2d_column": lambda: (workloads.large_2d(lx=1, perturb=False), None, None, None),
         "batched_cheap8": lambda: (workloads.batched(), None, None,
                                    cheap8_indices(workloads.batched())),
-        "batched_all_1000": lambda: (workloads.batched(), 1000, 100, None),
+        "batched_all_1000": lambda: (workloads.batched(), 1000, 250, None),
     }
 
 
+def differentiation_fd(h_rel: float = 1e-6):
+    wl = workloads.differentiation()
+    ch0 = wl.channels[0]
+    true = workloads.true_channel(ch0)
+
+    def samples(ch):
+        r = oracle.run_workload(workloads.Workload("d", [ch], "f64", steps_on=wl.steps_on,
+                                                   sample_every=wl.sample_every))[0]
+        return r["t"], r["ux"][:, :, 0]
+
+    t, target = samples(true)
+    _, u0 = samples(ch0)
+    loss0 = float(np.sum((u0 - target) ** 2))
+    grad = np.zeros(4)
+    for i, name in enumerate(workloads.ADJOINT_PARAMS):
+        p = getattr(ch0, name)
+        hp = h_rel * p
+        lp = float(np.sum((samples(ch0.replace(**{name: p + hp}))[1] - target) ** 2))
+        lm = float(np.sum((samples(ch0.replace(**{name: p - hp}))[1] - target) ** 2))
+        grad[i] = (lp - lm) / (2 * hp)
+        print(f"differentiation: dL/d{name} = {grad[i]:.10e}", flush=True)
+    return {"t": t, "target": target, "u_p0": u0, "loss": loss0, "grad_fd": grad,
+            "params": np.array([getattr(ch0, n) for n in workloads.ADJOINT_PARAMS]),
+            "h_rel": h_rel}
+
+
 def make(name):
+    if name == "differentiation":
+        t0 = time.time()
+        out = differentiation_fd()
+        path = os.path.join(HERE, f"{name}.npz")
+        np.savez_compressed(path, **out)
+        print(f"{name}: {time.time() - t0:.0f} s -> {path}", flush=True)
+        return
     wl, steps, every, chans = runs()[name]()
     t0 = time.time()
     res = oracle.run_workload(wl, steps=steps, sample_every=every, channels=chans)
@@ -59,9 +99,10 @@ def make(name):
     out = {"channels": np.array(idx), "steps": wl.steps if steps is None else steps,
            "sample_every": wl.sample_every if every is None else every,
            "steps_on": wl.steps_on}
+    keep = ("t", "ux", "sxy", "n1") + (("uy", "rho") if wl.channels[0].lx > 1 else ())
     for j, r in enumerate(res):
-        for k, v in r.items():
-            out[f"c{idx[j]}_{k}"] = v
+        for k in keep:
+            out[f"c{idx[j]}_{k}"] = r[k]
     path = os.path.join(HERE, f"{name}.npz")
     np.savez_compressed(path, **out)
     print(f"{name}: {time.time() - t0:.0f} s -> {path}", flush=True)
@@ -70,6 +111,6 @@ def make(name):
 if __name__ == "__main__":
     names = sys.argv[1:] or ["all"]
     if names == ["all"]:
-        names = list(runs())
+        names = list(runs()) + ["differentiation"]
     for n in names:
         make(n)

@@ -1,0 +1,152 @@
+"""GPU adjoint (lb_adjoint_*) against central finite differences of the FP64
+oracle's loss, at the same parameters and with the same target.
+
+Loss: L = sum over sampled steps and nodes of (u_x - u_x_target)^2.
+Gradients with respect to (G_inf, tau, gamma_c, g_x).  Tolerances: FP32
+adjoint 1e-4 relative per component (the stated bar); FP64 adjoint 1e-5,
+set by the finite differences themselves: with a relative step of 1e-6 the
+oracle's loss changes by ~1e-7 of itself for the least sensitive parameter,
+and the rounding pattern of the whole FP64 trajectory changes with the
+parameter, which leaves ~1e-6 of noise in that difference.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1504_06123_amd as lb
+    from paper_1504_06123_amd import _lib
+    assert os.path.exists(_lib.LIB_PATH), "liblbmax.so not built"
+    return lb
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def oracle_samples(ch, steps, every):
+    wl = workloads.Workload("a", [ch], "f64", steps_on=steps, sample_every=every)
+    return oracle.run_workload(wl)[0]["ux"][:, :, 0]
+
+
+def oracle_fd(ch, target, steps, every, h_rel=1e-6):
+    grad = []
+    for name in workloads.ADJOINT_PARAMS:
+        p = getattr(ch, name)
+        hp = h_rel * p
+        lp = np.sum((oracle_samples(ch.replace(**{name: p + hp}), steps, every) - target) ** 2)
+        lm = np.sum((oracle_samples(ch.replace(**{name: p - hp}), steps, every) - target) ** 2)
+        grad.append((lp - lm) / (2 * hp))
+    return np.array(grad)
+
+
+def gpu_gradient(lb, ch, precision, steps, every, seg_len, target, block=1):
+    from paper_1504_06123_amd import adjoint
+    with lb.Solver([ch], precision=precision) as s:
+        if block != 1:
+            s.set_block(block)
+        u, ckpts = adjoint.forward(s, steps, every, seg_len)
+        g = adjoint.backward(s, ckpts, steps, every, seg_len, 2 * (u - target))
+    return u, g[0]
+
+
+def small_channel():
+    return workloads.Channel(lx=1, ly=16, tau_lb=1.0, g_inf=2e-3, tau_m=40.0, gamma_c=0.05,
+                             n_hist=64, gx=2e-5)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-5), ("f32", 1e-4), ("f32p64", 1e-4)])
+def test_adjoint_small_against_oracle_fd(lb, precision, tol):
+    ch = small_channel()
+    steps, every, seg = 300, 25, 64
+    say(f"case adjoint small {precision}")
+    target = oracle_samples(ch.replace(g_inf=1.6e-3, tau_m=50.0, gamma_c=0.06, gx=1.7e-5),
+                            steps, every)
+    fd = oracle_fd(ch, target, steps, every)
+    _, g = gpu_gradient(lb, ch, precision, steps, every, seg, target)
+    rel = np.abs(g - fd) / np.abs(fd)
+    say(f"  fd {fd}\n  adjoint {g}\n  rel {rel}")
+    assert np.all(rel < tol), rel
+
+
+def test_adjoint_f64_tight(lb):
+    """With a relative step of 1e-4 the oracle's central differences are
+    accurate to ~1e-8 (truncation O(h^2), rounding noise 100x below the 1e-6
+    step); the FP64 adjoint must agree to 1e-6 on every parameter."""
+    ch = small_channel()
+    steps, every, seg = 300, 25, 64
+    say("case adjoint small f64, tight")
+    target = oracle_samples(ch.replace(g_inf=1.6e-3, tau_m=50.0, gamma_c=0.06, gx=1.7e-5),
+                            steps, every)
+    fd = oracle_fd(ch, target, steps, every, h_rel=1e-4)
+    _, g = gpu_gradient(lb, ch, "f64", steps, every, seg, target)
+    rel = np.abs(g - fd) / np.abs(fd)
+    say(f"  rel {rel}")
+    assert np.all(rel < 1e-6), rel
+
+
+def test_adjoint_segment_length_and_blocking_invariance(lb):
+    ch = small_channel()
+    steps, every = 300, 25
+    say("case adjoint segment invariance")
+    target = oracle_samples(ch.replace(gx=1.5e-5), steps, every)
+    _, g1 = gpu_gradient(lb, ch, "f64", steps, every, 64, target)
+    _, g2 = gpu_gradient(lb, ch, "f64", steps, every, 37, target)
+    assert np.array_equal(g1, g2)
+    _, g3 = gpu_gradient(lb, ch, "f64", steps, every, 64, target, block=4)
+    assert np.all(np.abs(g3 - g1) <= 1e-10 * np.abs(g1))
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-5), ("f32", 1e-4), ("f32p64", 1e-4)])
+def test_adjoint_differentiation_run(lb, precision, tol):
+    """1 x 128 channel, window 2048, 4000 steps, samples every 200, checkpoints
+    every 256 steps, against the oracle's central differences (golden)."""
+    path = os.path.join(GOLDEN, "differentiation.npz")
+    if not os.path.exists(path):
+        pytest.skip("differentiation.npz not generated")
+    gold = np.load(path)
+    wl = workloads.differentiation()
+    ch = wl.channels[0]
+    say(f"case adjoint differentiation run {precision}")
+    u, g = gpu_gradient(lb, ch, precision, wl.steps, wl.sample_every, 256, gold["target"],
+                        block=1 if precision == "f64" else 8)
+    fd = gold["grad_fd"]
+    rel = np.abs(g - fd) / np.abs(fd)
+    uerr = np.abs(u - gold["u_p0"]).max() / np.abs(gold["u_p0"]).max()
+    say(f"  u err {uerr:.2e}\n  fd {fd}\n  adjoint {g}\n  rel {rel}")
+    assert np.all(rel < tol), rel
+    assert uerr < {"f64": 1e-10, "f32p64": 1e-5, "f32": 1e-4}[precision], uerr
+
+
+def test_lbfunction_autograd(lb):
+    import torch
+    from paper_1504_06123_amd import adjoint
+    ch = small_channel()
+    steps, every, seg = 200, 20, 50
+    target = torch.from_numpy(oracle_samples(ch.replace(gx=1.5e-5), steps, every))
+    say("case LBFunction")
+    with lb.Solver([ch], precision="f64") as s:
+        init = s.save_state()
+        theta = torch.tensor([[ch.g_inf, ch.tau_m, ch.gamma_c, ch.gx]], dtype=torch.float64,
+                             requires_grad=True)
+        u = adjoint.LBFunction.apply(theta, s, init, steps, every, seg)
+        loss = ((u - target) ** 2).sum()
+        loss.backward()
+        g_auto = theta.grad.numpy()[0]
+    fd = oracle_fd(ch, target.numpy(), steps, every)
+    rel = np.abs(g_auto - fd) / np.abs(fd)
+    say(f"  rel {rel}")
+    assert np.all(rel < 1e-5)

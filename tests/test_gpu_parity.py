@@ -163,19 +163,21 @@ def test_f64_2d_perturbed(Solver):
 # FP32 path (Kahan history sums, FP64 strain)
 # ---------------------------------------------------------------------------
 
-def test_f32_startup_cessation_reduced(Solver):
-    """Quasi-1D startup then cessation, FP32 vs FP64 oracle."""
+@pytest.mark.parametrize("precision", ["f32", "f32p64"])
+def test_f32_startup_cessation_reduced(Solver, precision):
+    """Quasi-1D startup then cessation, FP32 history vs FP64 oracle."""
     ch = workloads.startup_cessation().channels[0].replace(ly=64, n_hist=1024, tau_m=250.0, gx=5e-6)
-    say("case f32 startup/cessation 1x64")
-    gpu = run_gpu(Solver, [ch], "f32", 3000, 100, steps_on=1500)[0]
+    say(f"case {precision} startup/cessation 1x64")
+    gpu = run_gpu(Solver, [ch], precision, 3000, 100, steps_on=1500)[0]
     ref = run_oracle([ch], 3000, 100, steps_on=1500)[0]
     compare(gpu, ref, TOL32, label="f32_startcess")
 
 
-def test_f32_2d_perturbed(Solver):
+@pytest.mark.parametrize("precision", ["f32", "f32p64"])
+def test_f32_2d_perturbed(Solver, precision):
     ch = workloads.large_2d(lx=32, ly=24, n_hist=512).channels[0].replace(tau_m=100.0)
-    say("case f32 2d perturbed 32x24")
-    gpu = run_gpu(Solver, [ch], "f32", 800, 100)[0]
+    say(f"case {precision} 2d perturbed 32x24")
+    gpu = run_gpu(Solver, [ch], precision, 800, 100)[0]
     ref = run_oracle([ch], 800, 100)[0]
     compare(gpu, ref, TOL32, keys=("ux", "uy", "sxy", "n1"), label="f32_2d")
 
@@ -326,10 +328,11 @@ def test_bitwise_determinism_and_graph_replay(Solver):
         assert np.array_equal(a[k], c[k]), k
 
 
-def test_save_load_resume_bitwise(Solver):
+@pytest.mark.parametrize("precision", ["f32", "f32p64", "f64"])
+def test_save_load_resume_bitwise(Solver, precision):
     ch = workloads.large_2d(lx=8, ly=12, n_hist=200).channels[0].replace(tau_m=40.0)
-    say("case save/load")
-    with Solver([ch], precision="f32") as s:
+    say(f"case save/load {precision}")
+    with Solver([ch], precision=precision) as s:
         s.step(150)
         buf = s.save_state()
         s.step(77)
