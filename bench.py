@@ -2,9 +2,12 @@
 nonlinear-Maxwell step at history window N_h, with the roofline of the
 history kernel and the FP64 oracle timed on the host beside it.
 
-Workload: the large 2D channel, 1024 x 512 nodes, window N_h = 4096, FP32
-populations and history (Kahan sums, FP64 strain), tau = 1000, g = 5e-6,
-1 % seeded velocity perturbation.  One step = the whole path for every node:
+Workload: the large 2D channel, 1024 x 512 nodes, window N_h = 4096, tau =
+1000, g = 5e-6, 1 % seeded velocity perturbation.  Precision of the headline
+number: FP32 history ring with Kahan-compensated FP32 window sums and FP64
+accumulated strain, FP64 lattice state (the mode that holds the velocity to
+1e-5 of the FP64 oracle over full-length runs); the all-FP32 mode is timed
+beside it.  One step = the whole path for every node:
 pull-stream + collide with the stress-divergence force, velocity gradient,
 history push and the N_h-entry history integral.  The launch shape (steps
 per history pass, lanes, chunks, persistent pass) is chosen by the
@@ -44,9 +47,9 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernel
 MEASURED = {
     "source_sha256": "6c527575ddc1198d0190757a622459bad4993b7a9f119d5c4d42458f929c0db4",
     # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated)
-    "traffic_bytes": {(16, 1): 17319683980.0, (1, 4): 17258171597.0},
+    "traffic_bytes": {("f32", 16, 1): 17319683980.0, ("f32", 1, 4): 17258171597.0},
     # SQ_INSTS_VALU x 64 / history entries
-    "valu_instr_per_entry": {(16, 1): 77.6, (1, 4): 13.06},
+    "valu_instr_per_entry": {("f32", 16, 1): 77.6, ("f32", 1, 4): 13.06},
 }
 
 
@@ -93,6 +96,70 @@ def time_steps(solver, steps: int):
     return el, kt
 
 
+def bench_large_2d(wl, args, precision: str):
+    """Tune and time the large 2D channel in one precision; roofline of the
+    history pass."""
+    import numpy as np
+    import torch
+    from paper_1504_06123_amd import Solver, autotune
+
+    ch = wl.channels[0]
+    nodes, H = ch.nodes, ch.n_hist
+    log(f"bench: {wl.name} nodes={nodes} N_h={H} precision={precision}")
+    s = Solver(wl.channels, precision=precision, device="cuda:0")
+    s.step(args.warmup)
+    if args.no_tune:
+        cfg = dict(block=args.block, vec=1, chunk_len=1 << 30, persistent=False, graph=0)
+        autotune.apply(s, cfg)
+    else:
+        best = autotune.tune(s, autotune.candidates(s, blocks=(1, 8, 16, 32),
+                                                    chunk_lens=(1024, 1 << 30)),
+                             min_steps=32)
+        cfg = {k: best[k] for k in ("block", "vec", "chunk_len", "persistent", "graph")}
+        log(f"bench: tuned {cfg} ({best['ms_per_step']:.4f} ms/step in tuning)")
+    M = cfg["block"]
+    steps = max(M, args.steps // M * M)
+    s.step(2 * M)
+    el, kt = time_steps(s, steps)
+    rho, ux, _ = s.fields(0)
+    assert np.isfinite(ux).all() and abs(rho.mean() - 1) < 1e-3
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+
+    pass_ms, n_pass = kt[0]
+    pass_s = pass_ms / n_pass / 1e3
+    entries = nodes * H
+    alg_bytes = entries * hist_bytes_per_entry(ch)
+    alg_flops = entries * pass_flops_per_entry(M)
+    gbs = alg_bytes / pass_s / 1e9
+    tflops = alg_flops / pass_s / 1e12
+    hbm_frac = gbs / HBM_PEAK_GBS
+    alu_frac = tflops / VALU_PEAK_TFLOPS
+    log(f"bench: {precision}: {steps} steps in {el:.3f} s ({el/steps*1e3:.4f} ms/step); "
+        f"history pass {pass_s*1e3:.3f} ms x {n_pass} ({gbs:.0f} GB/s, {tflops:.1f} TFLOP/s); "
+        f"lattice {kt[1][0]/max(kt[1][1],1):.4f} ms; block step "
+        f"{(kt[2][0]/kt[2][1]) if kt[2][1] else 0:.4f} ms")
+    key = (precision, M, cfg["vec"])
+    traffic = measured("traffic_bytes", key)
+    vpe = measured("valu_instr_per_entry", key)
+    issue_frac = (vpe * entries / 64 / pass_s / VALU_WAVE_INSTR_PER_S) if vpe else None
+    if issue_frac is not None and issue_frac > hbm_frac:
+        roof = {"bound": "alu", "achieved": tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": alu_frac}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm_frac}
+    roof.update({"traffic": traffic,
+                 "kernel": f"k_hist_pass ({precision}, {M} steps per pass)",
+                 "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg_bytes,
+                 "alg_flops_per_launch": alg_flops, "hbm_GBs": gbs, "hbm_frac": hbm_frac,
+                 "valu_TFLOPs": tflops, "valu_frac": alu_frac,
+                 "valu_issue_frac": issue_frac})
+    return {"el": el, "steps": steps, "cfg": cfg, "roof": roof,
+            "node_steps_per_s": nodes * steps / el, "ms_per_step": el / steps * 1e3}
+
+
 def cpu_baseline(seconds: float = 12.0):
     """The FP64 oracle on a bounded sample of the same workload: a 16 x 512
     strip of the channel with the full 4096-entry window (seeded synthetic
@@ -133,7 +200,7 @@ def bench_batched(steps: int = 2000):
     nodes = wl.nodes
     s = Solver(wl.channels, precision="f32")
     s.step(64)
-    best = autotune.tune(s, autotune.candidates(s, blocks=(1, 4, 8, 16),
+    best = autotune.tune(s, autotune.candidates(s, blocks=(1, 4, 8, 16, 32),
                                                 chunk_lens=(256, 1024, 4096),
                                                 graphs=(0, 64)), min_steps=64)
     s.step(64)
@@ -207,57 +274,11 @@ def main():
     wl = workloads.large_2d()
     ch = wl.channels[0]
     nodes, H = ch.nodes, ch.n_hist
-    log(f"bench: {wl.name} nodes={nodes} N_h={H} precision=f32")
-    s = Solver(wl.channels, precision="f32", device="cuda:0")
-    s.step(args.warmup)
-    if args.no_tune:
-        cfg = dict(block=args.block, vec=1, chunk_len=1 << 30, persistent=False, graph=0)
-        autotune.apply(s, cfg)
-    else:
-        best = autotune.tune(s, autotune.candidates(s, blocks=(1, 4, 8, 16),
-                                                    chunk_lens=(1024, 1 << 30)),
-                             min_steps=32)
-        cfg = {k: best[k] for k in ("block", "vec", "chunk_len", "persistent", "graph")}
-        log(f"bench: tuned {cfg} ({best['ms_per_step']:.4f} ms/step in tuning)")
-    M = cfg["block"]
-    steps = max(M, args.steps // M * M)
-    s.step(2 * M)
-    el, kt = time_steps(s, steps)
-    rho, ux, _ = s.fields(0)
-    assert np.isfinite(ux).all() and abs(rho.mean() - 1) < 1e-3
-    s.close()
-    del s
-    torch.cuda.empty_cache()
-
+    main = bench_large_2d(wl, args, "f32p64")
+    side = bench_large_2d(wl, args, "f32")
+    el, steps, cfg, roof = main["el"], main["steps"], main["cfg"], main["roof"]
     node_steps = nodes * steps / el
-    pass_ms, n_pass = kt[0]
-    pass_s = pass_ms / n_pass / 1e3
     entries = nodes * H
-    alg_bytes = entries * hist_bytes_per_entry(ch)
-    alg_flops = entries * pass_flops_per_entry(M)
-    gbs = alg_bytes / pass_s / 1e9
-    tflops = alg_flops / pass_s / 1e12
-    hbm_frac = gbs / HBM_PEAK_GBS
-    alu_frac = tflops / VALU_PEAK_TFLOPS
-    log(f"bench: {steps} steps in {el:.3f} s ({el/steps*1e3:.4f} ms/step); history pass "
-        f"{pass_s*1e3:.3f} ms x {n_pass} ({gbs:.0f} GB/s, {tflops:.1f} TFLOP/s); "
-        f"lattice {kt[1][0]/max(kt[1][1],1):.4f} ms; block step "
-        f"{(kt[2][0]/kt[2][1]) if kt[2][1] else 0:.4f} ms")
-    key = (M, cfg["vec"])
-    traffic = measured("traffic_bytes", key)
-    vpe = measured("valu_instr_per_entry", key)
-    issue_frac = (vpe * entries / 64 / pass_s / VALU_WAVE_INSTR_PER_S) if vpe else None
-    if issue_frac is not None and issue_frac > hbm_frac:
-        roof = {"bound": "alu", "achieved": tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": alu_frac}
-    else:
-        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": hbm_frac}
-    roof.update({"traffic": traffic, "kernel": f"k_hist_pass (float, {M} steps per pass)",
-                 "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg_bytes,
-                 "alg_flops_per_launch": alg_flops, "hbm_GBs": gbs, "hbm_frac": hbm_frac,
-                 "valu_TFLOPs": tflops, "valu_frac": alu_frac,
-                 "valu_issue_frac": issue_frac})
 
     batched = None
     if not args.no_batched:
@@ -281,14 +302,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32 history (Kahan sums, f64 strain) + f64 lattice state",
         "data": "synthetic",
         "config": {"workload": "large 2D channel 1024x512, N_h=4096, tau=1000 steps, "
                                "g=5e-6, 1% seeded velocity perturbation",
                    "lx": ch.lx, "ly": ch.ly, "n_hist": H, "nodes": nodes,
-                   "history_entries_per_step": entries, "launch": cfg},
+                   "history_entries_per_step": entries, "launch": cfg,
+                   "precision": "f32p64"},
         "roofline": roof,
         "entry_updates_per_s": entries * steps / el,
+        "all_f32": {"value": side["node_steps_per_s"], "ms_per_step": side["ms_per_step"],
+                    "launch": side["cfg"], "roofline": side["roof"]},
         "batched": batched,
         "cpu_baseline": cpu,
     }

@@ -158,7 +158,7 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  *     ring_s [n_hist][N] RH shear rate s(t') = kappa_xy, row t' mod n_hist
  *     ring_r [n_hist][N] RH |gamma_dot(t')| (absent for unidirectional
  *                           channels)
- *     blk  [32][N] double   window sums of the block in progress (see
+ *     blk  [64][N] double   window sums of the block in progress (see
  *                           lb_set_block); read only when the block
  *                           position is not 0
  *     force  2 doubles: gx, gy.
@@ -175,7 +175,7 @@ lb_status lb_load_state(lb_handle *h, const void *d_src);
  * workgroups and combined in FP64 in a fixed order) and the nodes each lane
  * of the history kernel owns (nodes_per_lane in {1, 2, 4}; one ring row is
  * then read as a 1-, 2- or 4-wide vector; with temporal blocking of 2 or 4
- * steps at most 2 are used, with 8 or 16 steps 1).  lb_get_tiling reads the
+ * steps at most 2 are used, with 8 or more steps 1).  lb_get_tiling reads the
  * lane width in use and the chunk count.  lb_set_graph(h, s) replays s steps per hipGraph launch inside
  * lb_step (0 = plain launches).  All take effect at the next lb_step; only
  * the chunk split changes results, and only through rounding order.
@@ -190,7 +190,7 @@ lb_status lb_set_graph(lb_handle *h, int32_t steps_per_graph);
 /*
  * Temporal blocking of the history integral.  Every history entry except
  * the newest is known one step ahead, so one pass over the history ring can
- * form the window sums of steps_per_pass (1, 2, 4, 8 or 16) consecutive steps;
+ * form the window sums of steps_per_pass (1, 2, 4, 8, 16 or 32) consecutive steps;
  * the following steps of the block add only the entries pushed since the
  * pass and shift the accumulated strain by the strain since the pass, which
  * enters the normal-stress sum affinely (Sec. III Eq. eeval: gamma(t,t') is a

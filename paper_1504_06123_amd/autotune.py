@@ -15,7 +15,7 @@ import math
 import time
 from typing import Dict, Iterable, List, Optional
 
-LANES_FOR_BLOCK = {1: (1, 2, 4), 2: (1, 2), 4: (1, 2), 8: (1,), 16: (1,)}
+LANES_FOR_BLOCK = {1: (1, 2, 4), 2: (1, 2), 4: (1, 2), 8: (1,), 16: (1,), 32: (1,)}
 
 
 def chunks_for(solver, ch: int, chunk_len: int) -> int:

@@ -13,8 +13,8 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kNodeAlign = 64;     // node-plane stride is a multiple of this
 constexpr int kMinChunkLen = 128;  // shortest age range of one history chunk
 constexpr int kMaxChunks = 64;     // most age ranges per channel
-constexpr int64_t kPartialBudget = int64_t(1) << 21;  // chunks * stride cap
-constexpr int kMaxBlock = 16;      // most steps served by one history pass
+constexpr int64_t kPartialBudget = int64_t(1) << 20;  // chunks * stride cap
+constexpr int kMaxBlock = 32;      // most steps served by one history pass
 // Planes of the per-chunk partials and of the block sums (doubles, [plane][np]
 // per chunk): A_m at m, B_m at kMaxBlock + m, chunk strain total at kPlaneT.
 constexpr int kPlaneB = kMaxBlock;

@@ -862,8 +862,10 @@ void launch_hist_pass(int prec, int vec, int block, char *ws, const ChanDev *cha
                 LBMAX_PASS(2, 4, 4);                                             \
         } else if (block == 8) {                                                 \
             LBMAX_PASS(1, 8, 8);                                                 \
+        } else if (block == 16) {                                                \
+            LBMAX_PASS(1, 16, 16);                                               \
         } else {                                                                 \
-            LBMAX_PASS(1, 16, 8);                                                \
+            LBMAX_PASS(1, 32, 8);                                                \
         }                                                                        \
     } while (0)
     LBMAX_BY_PREC(prec, LBMAX_PASS_SHAPES);
@@ -890,8 +892,10 @@ int hist_pass_blocks_per_cu(int prec, int vec, int block)
             (vec == 1 ? (void)(LBMAX_OCC(1, 4, 8)) : (void)(LBMAX_OCC(2, 4, 4)));    \
         else if (block == 8)                                                         \
             (void)(LBMAX_OCC(1, 8, 8));                                              \
+        else if (block == 16)                                                        \
+            (void)(LBMAX_OCC(1, 16, 16));                                            \
         else                                                                         \
-            (void)(LBMAX_OCC(1, 16, 8));                                             \
+            (void)(LBMAX_OCC(1, 32, 8));                                             \
     } while (0)
     LBMAX_BY_PREC(prec, LBMAX_OCC_SHAPES);
 #undef LBMAX_OCC_SHAPES

@@ -939,8 +939,8 @@ lb_status lb_set_block(lb_handle *h, int32_t steps_per_pass)
     if (s != LB_OK)
         return s;
     if (steps_per_pass != 1 && steps_per_pass != 2 && steps_per_pass != 4 &&
-        steps_per_pass != 8 && steps_per_pass != 16)
-        return fail(LB_EINVAL, "steps_per_pass must be 1, 2, 4, 8 or 16");
+        steps_per_pass != 8 && steps_per_pass != 16 && steps_per_pass != 32)
+        return fail(LB_EINVAL, "steps_per_pass must be 1, 2, 4, 8, 16 or 32");
     if (h->graph_steps % steps_per_pass != 0)
         return fail(LB_EINVAL, "the graph length must stay a multiple of the block length");
     h->block = steps_per_pass;

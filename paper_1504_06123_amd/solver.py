@@ -123,7 +123,7 @@ class Solver:
         _lib.check(self.lib.lb_set_graph(self.h, int(steps_per_graph)), "lb_set_graph")
 
     def set_block(self, steps_per_pass: int):
-        """Steps served by one history pass (temporal blocking: 1, 2, 4, 8, 16)."""
+        """Steps served by one history pass (temporal blocking: 1, 2, 4, 8, 16, 32)."""
         _lib.check(self.lib.lb_set_block(self.h, int(steps_per_pass)), "lb_set_block")
 
     def set_persistent(self, enable: bool = True):
@@ -239,8 +239,8 @@ def state_layout(channels: Sequence, precision: str = "f32"):
         for name in ("ring_s",) + (() if uni else ("ring_r",)):
             sec[name] = (off, int(ch.n_hist), N)
             off = up(off + int(ch.n_hist) * N * RH)
-        sec["blk"] = (off, 32, N)   # doubles
-        off = up(off + 32 * N * 8)
+        sec["blk"] = (off, 64, N)   # doubles
+        off = up(off + 64 * N * 8)
         sec["force"] = (off, 1, 2)
         off = up(off + 16)
         out.append(sec)

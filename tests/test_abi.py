@@ -70,7 +70,7 @@ def test_workspace_bytes_large_2d_fits(lib):
     # two FP32 rings (s, r) of 4096 x 524288 plus small planes, chunk
     # partials and block sums
     ring = 2 * 4096 * 524288 * 4
-    assert ring <= nb < ring * 1.05
+    assert ring <= nb < ring * 1.06
 
 
 @pytest.mark.parametrize("field,value,msg", [

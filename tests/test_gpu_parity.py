@@ -243,7 +243,7 @@ def test_temporal_blocking_f64(Solver, name, kw, chunks):
     say(f"case blocking f64 {name}")
     ref = run_oracle([ch], 420, 35, steps_on=300)[0]
     base = run_gpu(Solver, [ch], "f64", 420, 35, steps_on=300, chunks=chunks)[0]
-    for M in (2, 4, 8, 16):
+    for M in (2, 4, 8, 16, 32):
         got = run_gpu(Solver, [ch], "f64", 420, 35, steps_on=300, chunks=chunks, block=M)[0]
         compare(got, ref, TOL64, keys=("ux", "uy", "sxy", "n1"), label=f"{name} M={M}")
         for k in ("ux", "sxy", "n1"):
@@ -254,7 +254,7 @@ def test_temporal_blocking_f32_2d(Solver):
     ch = workloads.large_2d(lx=32, ly=24, n_hist=512).channels[0].replace(tau_m=100.0)
     say("case blocking f32 2d")
     ref = run_oracle([ch], 800, 100)[0]
-    for M in (4, 8, 16):
+    for M in (4, 8, 16, 32):
         got = run_gpu(Solver, [ch], "f32", 800, 100, block=M)[0]
         compare(got, ref, TOL32, keys=("ux", "uy", "sxy", "n1"), label=f"f32_2d M={M}")
 
