@@ -46,30 +46,16 @@ __device__ __forceinline__ R qweight(int q)
 }
 
 // ---------------------------------------------------------------------------
-// Compensated accumulation.  FP32 sums use Kahan's compensation; FP64 sums
-// are plain.  value() returns the compensated sum in FP64.
+// Window-sum accumulators.  FP32 entries are summed in plain FP32 partial
+// groups that are flushed into an FP64 sum (one conversion and one FP64 add
+// per flush: cheaper than a Kahan-compensated FP32 pair and no less
+// accurate); FP64 entries are summed plainly.  value() returns the sum.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Acc {
-    R s = R(0);
-    __device__ __forceinline__ void add(R x) { s += x; }
-    __device__ __forceinline__ double value() const { return (double)s; }
-};
-
-template <>
-struct Acc<float> {
-    float s = 0.0f, c = 0.0f;
-    __device__ __forceinline__ void add(float x)
-    {
-        float y = x - c;
-        float t = s + y;
-        c = (t - s) - y;
-        s = t;
-    }
-    __device__ __forceinline__ double value() const
-    {
-        return (double)s - (double)c;
-    }
+    double s = 0.0;
+    __device__ __forceinline__ void add(R x) { s += (double)x; }
+    __device__ __forceinline__ double value() const { return s; }
 };
 
 // Memory decay exp(-k (1/tau + r/gamma_c)) of Eq. (nlmax).  FP32: hardware
@@ -707,18 +693,21 @@ __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
     const double A = blk[m * np + n];
     const double B = blk[(kPlaneB + m) * np + n];
     // newest entry: age 0, weight 1/2, E = 1, gamma = 0
+    // The decay of these few entries is taken in the history precision, as
+    // in the pass.
+    const Decay<R> dec(c);
     double sxy = 0.5 * (double)s_new, sxx = 0.0, gam = 0.0;
     int slot = p;
     for (int a = 1; a <= m; ++a) {
         slot = slot == 0 ? H - 1 : slot - 1;
-        const double s = (double)ring_s[(size_t)slot * np + n];
-        gam += s;
+        const R s = ring_s[(size_t)slot * np + n];
+        gam += (double)s;
         if (a < m && a <= H - 1) {
-            const double r = c->has_r ? (double)ring_r[(size_t)slot * np + n] : fabs(s);
+            const R r = c->has_r ? ring_r[(size_t)slot * np + n] : fabs(s);
             const double w = (a == H - 1) ? 0.5 : 1.0;
-            const double e = exp(-(double)a * (c->inv_tau + c->inv_gc * r));
-            sxy += w * s * e;
-            sxx += w * 2.0 * s * gam * e;
+            const double se = w * (double)(s * decay_pow(R(a), decay_rate<R>(dec, r)));
+            sxy += se;
+            sxx += 2.0 * gam * se;
         }
     }
     P *sig = reinterpret_cast<P *>(ws + c->off_sig);
@@ -823,6 +812,38 @@ void launch_lb(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, 
                                            chans, tiles, tcount, trel, tile_counters));
 }
 
+// Shapes of the history pass: (nodes per lane V, steps per pass M, rows per
+// plain partial group U) for each block length and requested lane width.
+// Blocked passes use one node per lane (the M accumulator pairs fill the
+// registers); the group size trades FP64 flushes against registers.
+#define LBMAX_PASS_SHAPE_TABLE(block, vec, X)                                    \
+    do {                                                                         \
+        if (block == 1) {                                                        \
+            if (vec == 4)                                                        \
+                X(4, 1, 4);                                                      \
+            else if (vec == 2)                                                   \
+                X(2, 1, 8);                                                      \
+            else                                                                 \
+                X(1, 1, 8);                                                      \
+        } else if (block == 2) {                                                 \
+            if (vec == 1)                                                        \
+                X(1, 2, 8);                                                      \
+            else                                                                 \
+                X(2, 2, 4);                                                      \
+        } else if (block == 4) {                                                 \
+            if (vec == 1)                                                        \
+                X(1, 4, 8);                                                      \
+            else                                                                 \
+                X(2, 4, 4);                                                      \
+        } else if (block == 8) {                                                 \
+            X(1, 8, 8);                                                          \
+        } else if (block == 16) {                                                \
+            X(1, 16, 16);                                                        \
+        } else {                                                                 \
+            X(1, 32, 8);                                                         \
+        }                                                                        \
+    } while (0)
+
 void launch_hist_pass(int prec, int vec, int block, char *ws, const ChanDev *chans,
                       const HistTile *tiles, int n_tiles, const int64_t *tcount, int trel,
                       int persistent_grid, int *counter, hipStream_t st)
@@ -841,33 +862,7 @@ void launch_hist_pass(int prec, int vec, int block, char *ws, const ChanDev *cha
                                dim3(kBlock), 0, st, ws, chans, tiles, tcount,    \
                                trel);                                            \
     } while (0)
-#define LBMAX_PASS_SHAPES                                                        \
-    do {                                                                         \
-        if (block == 1) {                                                        \
-            if (vec == 4)                                                        \
-                LBMAX_PASS(4, 1, 4);                                             \
-            else if (vec == 2)                                                   \
-                LBMAX_PASS(2, 1, 8);                                             \
-            else                                                                 \
-                LBMAX_PASS(1, 1, 8);                                             \
-        } else if (block == 2) {                                                 \
-            if (vec == 1)                                                        \
-                LBMAX_PASS(1, 2, 8);                                             \
-            else                                                                 \
-                LBMAX_PASS(2, 2, 4);                                             \
-        } else if (block == 4) {                                                 \
-            if (vec == 1)                                                        \
-                LBMAX_PASS(1, 4, 8);                                             \
-            else                                                                 \
-                LBMAX_PASS(2, 4, 4);                                             \
-        } else if (block == 8) {                                                 \
-            LBMAX_PASS(1, 8, 8);                                                 \
-        } else if (block == 16) {                                                \
-            LBMAX_PASS(1, 16, 16);                                               \
-        } else {                                                                 \
-            LBMAX_PASS(1, 32, 8);                                                \
-        }                                                                        \
-    } while (0)
+#define LBMAX_PASS_SHAPES LBMAX_PASS_SHAPE_TABLE(block, vec, LBMAX_PASS)
     LBMAX_BY_PREC(prec, LBMAX_PASS_SHAPES);
 #undef LBMAX_PASS_SHAPES
 #undef LBMAX_PASS
@@ -879,24 +874,12 @@ int hist_pass_blocks_per_cu(int prec, int vec, int block)
     int n = 0;
     hipError_t e = hipSuccess;
 #define LBMAX_OCC(V, M, U)                                                           \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-        &n, reinterpret_cast<const void *>(&k_hist_pass_persistent<P, H, V, M, U>), kBlock, 0)
-#define LBMAX_OCC_SHAPES                                                             \
     do {                                                                             \
-        if (block == 1)                                                              \
-            (vec == 4 ? (void)(LBMAX_OCC(4, 1, 4))                                   \
-                      : (vec == 2 ? (void)(LBMAX_OCC(2, 1, 8)) : (void)(LBMAX_OCC(1, 1, 8)))); \
-        else if (block == 2)                                                         \
-            (vec == 1 ? (void)(LBMAX_OCC(1, 2, 8)) : (void)(LBMAX_OCC(2, 2, 4)));    \
-        else if (block == 4)                                                         \
-            (vec == 1 ? (void)(LBMAX_OCC(1, 4, 8)) : (void)(LBMAX_OCC(2, 4, 4)));    \
-        else if (block == 8)                                                         \
-            (void)(LBMAX_OCC(1, 8, 8));                                              \
-        else if (block == 16)                                                        \
-            (void)(LBMAX_OCC(1, 16, 16));                                            \
-        else                                                                         \
-            (void)(LBMAX_OCC(1, 32, 8));                                             \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                            \
+            &n, reinterpret_cast<const void *>(&k_hist_pass_persistent<P, H, V, M, U>), \
+            kBlock, 0);                                                              \
     } while (0)
+#define LBMAX_OCC_SHAPES LBMAX_PASS_SHAPE_TABLE(block, vec, LBMAX_OCC)
     LBMAX_BY_PREC(prec, LBMAX_OCC_SHAPES);
 #undef LBMAX_OCC_SHAPES
 #undef LBMAX_OCC
