@@ -42,14 +42,15 @@ VALU_WAVE_INSTR_PER_S = 1024 * 2.4e9 / 4
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernels.hip")
 # rocprofv3 counter results for the history pass on this workload (see
 # profiles/history_pass_large_2d_1024x512_nh4096.md), keyed by
-# (steps per pass, nodes per lane).  Valid only for the kernel source they
+# (precision, steps per pass, nodes per lane).  Valid only for the kernel source they
 # were taken from; otherwise reported as null.
 MEASURED = {
-    "source_sha256": "6c527575ddc1198d0190757a622459bad4993b7a9f119d5c4d42458f929c0db4",
+    "source_sha256": "d3ffe78a1d04066172bf0c3caba23d5aadcd6bb0dcf99b6c6d465d55f0417efa",
     # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated)
-    "traffic_bytes": {("f32", 16, 1): 17319683980.0, ("f32", 1, 4): 17258171597.0},
+    "traffic_bytes": {("f32p64", 32, 1): 8394636.0 * 1024 * 2 + 266320 * 1024,
+                      ("f32p64", 1, 4): 8411090.0 * 1024 * 2 + 52458.2 * 1024},
     # SQ_INSTS_VALU x 64 / history entries
-    "valu_instr_per_entry": {("f32", 16, 1): 77.6, ("f32", 1, 4): 13.06},
+    "valu_instr_per_entry": {("f32p64", 32, 1): 112.06, ("f32p64", 1, 4): 11.54},
 }
 
 
@@ -109,12 +110,14 @@ def bench_large_2d(wl, args, precision: str):
     s = Solver(wl.channels, precision=precision, device="cuda:0")
     s.step(args.warmup)
     if args.no_tune:
-        cfg = dict(block=args.block, vec=1, chunk_len=1 << 30, persistent=False, graph=0)
+        cfg = dict(block=args.block, vec=1, chunk_len=1 << 30, persistent=args.persistent,
+                   graph=args.graph)
         autotune.apply(s, cfg)
     else:
         best = autotune.tune(s, autotune.candidates(s, blocks=(1, 8, 16, 32),
-                                                    chunk_lens=(1024, 1 << 30)),
-                             min_steps=32)
+                                                    chunk_lens=(1024, 1 << 30),
+                                                    graphs=(0, 64)),
+                             min_steps=64)
         cfg = {k: best[k] for k in ("block", "vec", "chunk_len", "persistent", "graph")}
         log(f"bench: tuned {cfg} ({best['ms_per_step']:.4f} ms/step in tuning)")
     M = cfg["block"]
@@ -143,8 +146,18 @@ def bench_large_2d(wl, args, precision: str):
     key = (precision, M, cfg["vec"])
     traffic = measured("traffic_bytes", key)
     vpe = measured("valu_instr_per_entry", key)
-    issue_frac = (vpe * entries / 64 / pass_s / VALU_WAVE_INSTR_PER_S) if vpe else None
-    if issue_frac is not None and issue_frac > hbm_frac:
+    vpe_src = "rocprofv3 SQ_INSTS_VALU" if vpe else "model 3.5 M + 10"
+    if not vpe:
+        # three FP32 instructions per entry and step of the block plus the
+        # per-entry decay, strain and flush work (the counted 32-step pass
+        # has 112)
+        vpe = 3.5 * M + 10
+    # Cycles each SIMD spends per wave-level VALU instruction; 4 is the
+    # nominal wave64 issue interval (dependence-free FP32 chains measure 4.1).
+    wave_instr = vpe * entries / 64
+    cycles_per_instr = 1024 * 2.4e9 * pass_s / wave_instr
+    valu_bound = wave_instr / VALU_WAVE_INSTR_PER_S > alg_bytes / (HBM_PEAK_GBS * 1e9)
+    if valu_bound:
         roof = {"bound": "alu", "achieved": tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": alu_frac}
     else:
@@ -155,7 +168,8 @@ def bench_large_2d(wl, args, precision: str):
                  "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg_bytes,
                  "alg_flops_per_launch": alg_flops, "hbm_GBs": gbs, "hbm_frac": hbm_frac,
                  "valu_TFLOPs": tflops, "valu_frac": alu_frac,
-                 "valu_issue_frac": issue_frac})
+                 "valu_instr_per_entry": vpe, "valu_instr_source": vpe_src,
+                 "valu_cycles_per_instr": cycles_per_instr})
     return {"el": el, "steps": steps, "cfg": cfg, "roof": roof,
             "node_steps_per_s": nodes * steps / el, "ms_per_step": el / steps * 1e3}
 
@@ -243,8 +257,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--block", type=int, default=16, help="steps per pass without tuning")
+    ap.add_argument("--block", type=int, default=32, help="steps per pass without tuning")
+    ap.add_argument("--persistent", action="store_true", help="persistent pass without tuning")
+    ap.add_argument("--graph", type=int, default=0, help="graph replay length without tuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--all-f32", dest="all_f32", action="store_true", default=True,
+                    help="also time the all-FP32 mode (default)")
+    ap.add_argument("--no-all-f32", dest="all_f32", action="store_false")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -275,7 +294,7 @@ def main():
     ch = wl.channels[0]
     nodes, H = ch.nodes, ch.n_hist
     main = bench_large_2d(wl, args, "f32p64")
-    side = bench_large_2d(wl, args, "f32")
+    side = bench_large_2d(wl, args, "f32") if args.all_f32 else None
     el, steps, cfg, roof = main["el"], main["steps"], main["cfg"], main["roof"]
     node_steps = nodes * steps / el
     entries = nodes * H
@@ -311,8 +330,9 @@ def main():
                    "precision": "f32p64"},
         "roofline": roof,
         "entry_updates_per_s": entries * steps / el,
-        "all_f32": {"value": side["node_steps_per_s"], "ms_per_step": side["ms_per_step"],
-                    "launch": side["cfg"], "roofline": side["roof"]},
+        "all_f32": side and {"value": side["node_steps_per_s"],
+                             "ms_per_step": side["ms_per_step"],
+                             "launch": side["cfg"], "roofline": side["roof"]},
         "batched": batched,
         "cpu_baseline": cpu,
     }

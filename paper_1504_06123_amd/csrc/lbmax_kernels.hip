@@ -58,8 +58,9 @@ struct Acc {
     __device__ __forceinline__ double value() const { return s; }
 };
 
-// Memory decay exp(-k (1/tau + r/gamma_c)) of Eq. (nlmax).  FP32: hardware
-// exp2 with the log2(e)-scaled rates; FP64: libm-grade exp.
+// Rate constants of the memory decay exp(-k (1/tau + r/gamma_c)) of
+// Eq. (nlmax).  FP32 keeps them scaled by log2(e) for the hardware exp2;
+// FP64 keeps them plain for exp.
 template <typename R>
 struct Decay;
 
@@ -68,10 +69,6 @@ struct Decay<float> {
     float a, b;  // log2(e)/tau, log2(e)/gamma_c
     __device__ __forceinline__ explicit Decay(const ChanDev *c)
         : a((float)c->l2_tau), b((float)c->l2_gc) {}
-    __device__ __forceinline__ float operator()(float k, float r) const
-    {
-        return __builtin_amdgcn_exp2f(-k * __builtin_fmaf(b, r, a));
-    }
 };
 
 template <>
@@ -79,10 +76,6 @@ struct Decay<double> {
     double a, b;  // 1/tau, 1/gamma_c
     __device__ __forceinline__ explicit Decay(const ChanDev *c)
         : a(c->inv_tau), b(c->inv_gc) {}
-    __device__ __forceinline__ double operator()(double k, double r) const
-    {
-        return exp(-k * (a + b * r));
-    }
 };
 
 // ---------------------------------------------------------------------------
@@ -319,7 +312,7 @@ __device__ __forceinline__ double fused(double a, double b, double c) { return _
 template <typename R>
 __device__ __forceinline__ R decay_rate(const Decay<R> &dec, R r)
 {
-    return dec.b * r + dec.a;
+    return fused(dec.b, r, dec.a);
 }
 
 // exp(-k * rate) in the precision's form (rate pre-scaled by log2(e) in FP32).
@@ -339,6 +332,7 @@ __device__ __forceinline__ void edge_entry(R s, R r, int k, int H, double loc,
                                            const Decay<R> &dec, Acc<R> (&A)[M],
                                            Acc<R> (&B)[M])
 {
+#pragma clang fp contract(off)
     const R rate = decay_rate<R>(dec, r);
     const R g2 = R(2) * (R)loc;
 #pragma unroll
@@ -353,98 +347,116 @@ __device__ __forceinline__ void edge_entry(R s, R r, int k, int H, double loc,
     }
 }
 
+// U rows of interior ages: entry k + j0 + u sits at ring slot `slot - j0 - u`.
+// The plain partial sums pa, pb take x = s E(k+m) (carried along m by the
+// per-entry factor q) and x * 2 gamma; FIRST starts them from these rows.
+template <typename R, int V, int M, int U, bool HAS_R, bool FIRST>
+__device__ __forceinline__ void pass_rows(const R *__restrict__ ring_s,
+                                          const R *__restrict__ ring_r, size_t np,
+                                          uint32_t lane_off, int slot, int kf0,
+                                          const Decay<R> &dec, R (&pa)[M][V], R (&pb)[M][V],
+                                          double (&loc)[V])
+{
+    // No implicit contraction: every lane width and group size rounds the
+    // same operations the same way (the FMAs are written out).
+#pragma clang fp contract(off)
+    Pack<R, V> sv[U], rv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const size_t row = (size_t)(slot - u) * np;
+        sv[u] = load_pack<R, V>(ring_s + row, lane_off);
+        if (HAS_R)
+            rv[u] = load_pack<R, V>(ring_r + row, lane_off);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const R kf = R(kf0 + u);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const R s = sv[u].v[v];
+            const R rate = decay_rate<R>(dec, HAS_R ? rv[u].v[v] : fabs(s));
+            loc[v] += (double)s;
+            const R g2 = R(2) * (R)loc[v];
+            R x = s * decay_pow(kf, rate);
+            R q = R(1);
+            if (M > 1)
+                q = decay_pow(R(1), rate);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (FIRST && u == 0) {
+                    pa[m][v] = x;
+                    pb[m][v] = x * g2;
+                } else {
+                    pa[m][v] += x;
+                    pb[m][v] = fused(x, g2, pb[m][v]);
+                }
+                if (m + 1 < M)
+                    x *= q;
+            }
+        }
+    }
+}
+
+template <typename R, int V, int M>
+__device__ __forceinline__ void flush(const R (&pa)[M][V], const R (&pb)[M][V],
+                                      Acc<R> (&A)[M][V], Acc<R> (&B)[M][V])
+{
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            A[m][v].add(pa[m][v]);
+            B[m][v].add(pb[m][v]);
+        }
+}
+
 // Interior ages [k, kend) of one chunk: every m has weight 1 and is in the
-// window.  Rows are visited newest to oldest, wrapping at row 0.
-template <typename R, int V, int M, int U, bool HAS_R>
+// window.  Rows are visited newest to oldest, wrapping at row 0.  Rows are
+// loaded U at a time; the plain partial sums are flushed into the FP64
+// accumulators every F rows (F a multiple of U), then every U rows near the
+// end of a run, then row by row.
+template <typename R, int V, int M, int U, int F, bool HAS_R>
 __device__ __forceinline__ void pass_bulk(const R *__restrict__ ring_s,
                                           const R *__restrict__ ring_r, size_t np,
                                           uint32_t lane_off, int H, int p, int k, int kend,
                                           const Decay<R> &dec, Acc<R> (&A)[M][V],
                                           Acc<R> (&B)[M][V], double (&loc)[V])
 {
+    static_assert(F % U == 0, "flush length must be a multiple of the row group");
     int slot = p - k;
     if (slot < 0)
         slot += H;
     while (k < kend) {
         const int run = min(kend - k, slot + 1);  // rows down to 0 without wrap
         int j = 0;
+        R pa[M][V], pb[M][V];
+        if (F > U) {
+            for (; j + F <= run; j += F) {
+                pass_rows<R, V, M, U, HAS_R, true>(ring_s, ring_r, np, lane_off, slot - j,
+                                                   k + j, dec, pa, pb, loc);
+                for (int g = U; g < F; g += U)
+                    pass_rows<R, V, M, U, HAS_R, false>(ring_s, ring_r, np, lane_off,
+                                                        slot - j - g, k + j + g, dec, pa, pb,
+                                                        loc);
+                flush<R, V, M>(pa, pb, A, B);
+            }
+        }
         for (; j + U <= run; j += U) {
-            Pack<R, V> sv[U], rv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const size_t row = (size_t)(slot - j - u) * np;
-                sv[u] = load_pack<R, V>(ring_s + row, lane_off);
-                if (HAS_R)
-                    rv[u] = load_pack<R, V>(ring_r + row, lane_off);
-            }
-            // Plain partial sums of the U rows, started from the first row;
-            // x = s E(k+m) is carried along m by the factor q.
-            R pa[M][V], pb[M][V];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const R kf = R(k + j + u);
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const R s = sv[u].v[v];
-                    const R rate = decay_rate<R>(dec, HAS_R ? rv[u].v[v] : fabs(s));
-                    loc[v] += (double)s;
-                    const R g2 = R(2) * (R)loc[v];
-                    R x = s * decay_pow(kf, rate);
-                    R q = R(1);
-                    if (M > 1)
-                        q = decay_pow(R(1), rate);
-#pragma unroll
-                    for (int m = 0; m < M; ++m) {
-                        if (u == 0) {
-                            pa[m][v] = x;
-                            pb[m][v] = x * g2;
-                        } else {
-                            pa[m][v] += x;
-                            pb[m][v] = fused(x, g2, pb[m][v]);
-                        }
-                        if (m + 1 < M)
-                            x *= q;
-                    }
-                }
-            }
-#pragma unroll
-            for (int m = 0; m < M; ++m)
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    A[m][v].add(pa[m][v]);
-                    B[m][v].add(pb[m][v]);
-                }
+            pass_rows<R, V, M, U, HAS_R, true>(ring_s, ring_r, np, lane_off, slot - j, k + j,
+                                               dec, pa, pb, loc);
+            flush<R, V, M>(pa, pb, A, B);
         }
         for (; j < run; ++j) {
-            const size_t row = (size_t)(slot - j) * np;
-            const Pack<R, V> sv = load_pack<R, V>(ring_s + row, lane_off);
-            Pack<R, V> rv;
-            if (HAS_R)
-                rv = load_pack<R, V>(ring_r + row, lane_off);
-            const R kf = R(k + j);
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const R s = sv.v[v];
-                const R rate = decay_rate<R>(dec, HAS_R ? rv.v[v] : fabs(s));
-                loc[v] += (double)s;
-                const R g2 = R(2) * (R)loc[v];
-                R x = s * decay_pow(kf, rate);
-                const R q = M > 1 ? decay_pow(R(1), rate) : R(1);
-#pragma unroll
-                for (int m = 0; m < M; ++m) {
-                    A[m][v].add(x);
-                    B[m][v].add(x * g2);
-                    if (m + 1 < M)
-                        x *= q;
-                }
-            }
+            pass_rows<R, V, M, 1, HAS_R, true>(ring_s, ring_r, np, lane_off, slot - j, k + j,
+                                               dec, pa, pb, loc);
+            flush<R, V, M>(pa, pb, A, B);
         }
         k += run;
         slot = H - 1;
     }
 }
 
-template <typename P, typename R, int V, int M, int U, bool HAS_R>
+template <typename P, typename R, int V, int M, int U, int F, bool HAS_R>
 __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *c,
                                           const HistTile &tl, int64_t t)
 {
@@ -501,7 +513,7 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
     }
     // Interior ages, then the ages whose k + m reaches the window end.
     const int tail0 = max(k, H - M);
-    pass_bulk<R, V, M, U, HAS_R>(ring_s, ring_r, np, lane_off, H, p, k, min(tl.k1, tail0),
+    pass_bulk<R, V, M, U, F, HAS_R>(ring_s, ring_r, np, lane_off, H, p, k, min(tl.k1, tail0),
                                  dec, A, B, loc);
     for (int kk = max(k, tail0); kk < tl.k1; ++kk) {
         int slot = p - kk;
@@ -563,7 +575,7 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
 
 // One launch per (lane width V, block length M): the tiles of the channels
 // whose lane width is V.  Plain form: one workgroup per tile.
-template <typename P, typename R, int V, int M, int U>
+template <typename P, typename R, int V, int M, int U, int F>
 __global__ __launch_bounds__(kBlock) void k_hist_pass(char *__restrict__ ws,
                                                       const ChanDev *__restrict__ chans,
                                                       const HistTile *__restrict__ tiles,
@@ -577,15 +589,15 @@ __global__ __launch_bounds__(kBlock) void k_hist_pass(char *__restrict__ ws,
         return;
     const int64_t t = *tcount + trel;
     if (c->has_r)
-        pass_tile<P, R, V, M, U, true>(ws, c, tl, t);
+        pass_tile<P, R, V, M, U, F, true>(ws, c, tl, t);
     else
-        pass_tile<P, R, V, M, U, false>(ws, c, tl, t);
+        pass_tile<P, R, V, M, U, F, false>(ws, c, tl, t);
 }
 
 // Persistent form: as many workgroups as fit on the chip at once; each claims
 // the next tile of the list (longest first) from a counter until the list
 // is exhausted.  The counter was zeroed by the lattice kernel of this step.
-template <typename P, typename R, int V, int M, int U>
+template <typename P, typename R, int V, int M, int U, int F>
 __global__ __launch_bounds__(kBlock) void k_hist_pass_persistent(
     char *__restrict__ ws, const ChanDev *__restrict__ chans,
     const HistTile *__restrict__ tiles, int n_tiles, const int64_t *__restrict__ tcount,
@@ -605,9 +617,9 @@ __global__ __launch_bounds__(kBlock) void k_hist_pass_persistent(
         const ChanDev *c = chans + tl.ch;
         if (tl.n0 + (int)(threadIdx.x & ~63u) * V < c->n) {
             if (c->has_r)
-                pass_tile<P, R, V, M, U, true>(ws, c, tl, t);
+                pass_tile<P, R, V, M, U, F, true>(ws, c, tl, t);
             else
-                pass_tile<P, R, V, M, U, false>(ws, c, tl, t);
+                pass_tile<P, R, V, M, U, F, false>(ws, c, tl, t);
         }
     }
 }
@@ -812,35 +824,36 @@ void launch_lb(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, 
                                            chans, tiles, tcount, trel, tile_counters));
 }
 
-// Shapes of the history pass: (nodes per lane V, steps per pass M, rows per
-// plain partial group U) for each block length and requested lane width.
-// Blocked passes use one node per lane (the M accumulator pairs fill the
-// registers); the group size trades FP64 flushes against registers.
+// Shapes of the history pass: (nodes per lane V, steps per pass M, rows
+// loaded per group U, rows per FP64 flush F) for each block length and
+// requested lane width.  Blocked passes use one node per lane (the M
+// accumulator pairs fill the registers); longer flush intervals save FP64
+// adds where the pass is bound by vector-ALU issue.
 #define LBMAX_PASS_SHAPE_TABLE(block, vec, X)                                    \
     do {                                                                         \
         if (block == 1) {                                                        \
             if (vec == 4)                                                        \
-                X(4, 1, 4);                                                      \
+                X(4, 1, 4, 4);                                                    \
             else if (vec == 2)                                                   \
-                X(2, 1, 8);                                                      \
+                X(2, 1, 8, 8);                                                    \
             else                                                                 \
-                X(1, 1, 8);                                                      \
+                X(1, 1, 8, 8);                                                    \
         } else if (block == 2) {                                                 \
             if (vec == 1)                                                        \
-                X(1, 2, 8);                                                      \
+                X(1, 2, 8, 8);                                                    \
             else                                                                 \
-                X(2, 2, 4);                                                      \
+                X(2, 2, 4, 4);                                                    \
         } else if (block == 4) {                                                 \
             if (vec == 1)                                                        \
-                X(1, 4, 8);                                                      \
+                X(1, 4, 8, 8);                                                    \
             else                                                                 \
-                X(2, 4, 4);                                                      \
+                X(2, 4, 4, 4);                                                    \
         } else if (block == 8) {                                                 \
-            X(1, 8, 8);                                                          \
+            X(1, 8, 8, 8);                                                      \
         } else if (block == 16) {                                                \
-            X(1, 16, 16);                                                        \
+            X(1, 16, 8, 32);                                                     \
         } else {                                                                 \
-            X(1, 32, 8);                                                         \
+            X(1, 32, 8, 64);                                                       \
         }                                                                        \
     } while (0)
 
@@ -851,14 +864,14 @@ void launch_hist_pass(int prec, int vec, int block, char *ws, const ChanDev *cha
     if (n_tiles <= 0)
         return;
     const int grid = persistent_grid > 0 ? std::min(persistent_grid, n_tiles) : n_tiles;
-#define LBMAX_PASS(V, M, U)                                                      \
+#define LBMAX_PASS(V, M, U, F)                                                    \
     do {                                                                         \
         if (persistent_grid > 0)                                                 \
-            hipLaunchKernelGGL((k_hist_pass_persistent<P, H, V, M, U>), dim3(grid), \
+            hipLaunchKernelGGL((k_hist_pass_persistent<P, H, V, M, U, F>), dim3(grid), \
                                dim3(kBlock), 0, st, ws, chans, tiles, n_tiles,   \
                                tcount, trel, counter);                           \
         else                                                                     \
-            hipLaunchKernelGGL((k_hist_pass<P, H, V, M, U>), dim3(grid),         \
+            hipLaunchKernelGGL((k_hist_pass<P, H, V, M, U, F>), dim3(grid),         \
                                dim3(kBlock), 0, st, ws, chans, tiles, tcount,    \
                                trel);                                            \
     } while (0)
@@ -873,10 +886,10 @@ int hist_pass_blocks_per_cu(int prec, int vec, int block)
 {
     int n = 0;
     hipError_t e = hipSuccess;
-#define LBMAX_OCC(V, M, U)                                                           \
+#define LBMAX_OCC(V, M, U, F)                                                         \
     do {                                                                             \
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                            \
-            &n, reinterpret_cast<const void *>(&k_hist_pass_persistent<P, H, V, M, U>), \
+            &n, reinterpret_cast<const void *>(&k_hist_pass_persistent<P, H, V, M, U, F>), \
             kBlock, 0);                                                              \
     } while (0)
 #define LBMAX_OCC_SHAPES LBMAX_PASS_SHAPE_TABLE(block, vec, LBMAX_OCC)
