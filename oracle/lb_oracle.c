@@ -27,6 +27,14 @@
  *   7. BGK collision with the forcing term (Eq. bodyforce, f^ex part)
  *   8. streaming with halfway bounce-back walls at y = -1/2 and y = ly-1/2.
  *
+ * Steps 5-6 use either the uniform window of the last n_hist steps or, when
+ * orc_set_history_grid() was called, the quasi-logarithmic grid of Sec. III
+ * (blocks whose step doubles going back; the two oldest entries of a full
+ * block are combined into the next block).  The grid keeps kappa and the
+ * deformation factors exactly as the paper describes and multiplies the
+ * factors to obtain the strain.  State exchange (orc_get/set_state) covers
+ * the uniform window only.
+ *
  * Parity status: every function below is pinned by the CPU test suite
  * (closed forms, moment identities, polynomial exactness, recursion
  * equivalence, conservation, symmetry, the Newtonian Poiseuille solution).
@@ -299,6 +307,204 @@ void orc_history_sum_ages(int n_hist, const double *s_age, const double *r_age,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Quasi-logarithmic history grid (Sec. III).                                 */
+/*                                                                            */
+/* B blocks of equidistant entries; block b = 1..B has the step               */
+/* dt_b = 2^(B-b) (block B, the newest, has the LB step 1).  Each entry keeps */
+/* its start time t0, its duration dt, the velocity gradient kappa averaged   */
+/* over [t0, t0 + dt) and its factor of the deformation tensor, which in the  */
+/* simple-shear reduction is F = [[1, kappa_xy dt], [0, 1]].  A new entry     */
+/* enters block B every step.  When a block then holds more than C entries,   */
+/* its two oldest are combined -- factors multiplied, kappa averaged,         */
+/* durations added -- into the newest entry of block b - 1; what block 1      */
+/* combines falls off the grid.  Readings where the paper is silent: a block  */
+/* holds at most C entries and combines when a push makes it C + 1; before    */
+/* t = 0 every block is full of zero entries of its own step, contiguous in   */
+/* time (the rest state); the time integral uses the trapezoid rule on the    */
+/* entries' start times, and the damping uses sqrt(II_D) of the averaged      */
+/* kappa.                                                                     */
+/* ------------------------------------------------------------------------ */
+static double *zalloc_q(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
+
+typedef struct {
+    double t0, dt;
+    double k[4];   /* kxx, kxy, kyx, kyy averaged over the entry */
+    double F[4];   /* deformation factor, row-major 2x2 */
+} orc_qentry;
+
+typedef struct orc_qgrid {
+    int B, C;
+    int *count;          /* [B] entries in each block */
+    orc_qentry *e;       /* [B][C + 1], oldest first within a block */
+} orc_qgrid;
+
+static void qgrid_init(orc_qgrid *g, int B, int C)
+{
+    g->B = B;
+    g->C = C;
+    g->count = (int *)calloc((size_t)B, sizeof(int));
+    g->e = (orc_qentry *)calloc((size_t)B * (size_t)(C + 1), sizeof(orc_qentry));
+    /* zero prefill, newest block first, walking back in time from t' = 0 */
+    double t_end = 0.0;
+    for (int b = B; b >= 1; --b) {
+        double dt = ldexp(1.0, B - b);
+        orc_qentry *blk = g->e + (size_t)(b - 1) * (C + 1);
+        for (int i = C - 1; i >= 0; --i) {
+            orc_qentry *q = &blk[i];
+            t_end -= dt;
+            q->t0 = t_end;
+            q->dt = dt;
+            q->F[0] = 1.0;
+            q->F[3] = 1.0;
+        }
+        g->count[b - 1] = C;
+    }
+}
+
+static void qgrid_free(orc_qgrid *g)
+{
+    free(g->count);
+    free(g->e);
+}
+
+/* Push the entry of step t with velocity gradient k[4], then let every full  */
+/* block pass its two oldest entries on, newest block first.                  */
+static void qgrid_push(orc_qgrid *g, long t, const double *k)
+{
+    const int B = g->B, C = g->C;
+    orc_qentry in;
+    memset(&in, 0, sizeof in);
+    in.t0 = (double)t;
+    in.dt = 1.0;
+    for (int a = 0; a < 4; ++a)
+        in.k[a] = k[a];
+    in.F[0] = 1.0;
+    in.F[1] = k[1] * 1.0;  /* exp(kappa dt) of simple shear */
+    in.F[3] = 1.0;
+    for (int b = B; b >= 1; --b) {
+        orc_qentry *blk = g->e + (size_t)(b - 1) * (C + 1);
+        blk[g->count[b - 1]] = in;
+        g->count[b - 1] += 1;
+        if (g->count[b - 1] <= C)
+            return;
+        /* the two oldest: blk[0] (older) and blk[1] */
+        orc_qentry m;
+        memset(&m, 0, sizeof m);
+        m.t0 = blk[0].t0;
+        m.dt = blk[0].dt + blk[1].dt;
+        for (int a = 0; a < 4; ++a)
+            m.k[a] = 0.5 * (blk[0].k[a] + blk[1].k[a]);
+        /* E accumulates newer factors on the left: F(newer) F(older) */
+        m.F[0] = blk[1].F[0] * blk[0].F[0] + blk[1].F[1] * blk[0].F[2];
+        m.F[1] = blk[1].F[0] * blk[0].F[1] + blk[1].F[1] * blk[0].F[3];
+        m.F[2] = blk[1].F[2] * blk[0].F[0] + blk[1].F[3] * blk[0].F[2];
+        m.F[3] = blk[1].F[2] * blk[0].F[1] + blk[1].F[3] * blk[0].F[3];
+        memmove(blk, blk + 2, sizeof(orc_qentry) * (size_t)(g->count[b - 1] - 2));
+        g->count[b - 1] -= 2;
+        in = m;  /* moves to block b - 1 (dropped after block 1) */
+    }
+}
+
+/* Number of live entries, newest first: fills t0[], dt[], kxy[] and the      */
+/* strain gamma(t, t0) = E_xy of the ordered product of the factors from the  */
+/* newest-but-one entry down to the entry itself (Eq. eeval).                  */
+static int qgrid_walk(const orc_qgrid *g, double *t0, double *dt, double *k4,
+                      double *strain)
+{
+    int n = 0;
+    double E[4] = {1.0, 0.0, 0.0, 1.0};
+    for (int b = g->B; b >= 1; --b) {
+        const orc_qentry *blk = g->e + (size_t)(b - 1) * (g->C + 1);
+        for (int i = g->count[b - 1] - 1; i >= 0; --i) {
+            const orc_qentry *q = &blk[i];
+            if (n > 0) {
+                /* E(t, t0) = E(t, t0 + dt) F(entry) */
+                double e0 = E[0] * q->F[0] + E[1] * q->F[2];
+                double e1 = E[0] * q->F[1] + E[1] * q->F[3];
+                double e2 = E[2] * q->F[0] + E[3] * q->F[2];
+                double e3 = E[2] * q->F[1] + E[3] * q->F[3];
+                E[0] = e0; E[1] = e1; E[2] = e2; E[3] = e3;
+            }
+            t0[n] = q->t0;
+            dt[n] = q->dt;
+            for (int a = 0; a < 4; ++a)
+                k4[4 * n + a] = q->k[a];
+            strain[n] = E[1];
+            ++n;
+        }
+    }
+    return n;
+}
+
+/* Eq. gitt with Eq. nlmax on the grid's entries: trapezoid weights from the  */
+/* start times, w_e = (t0_{e-1} - t0_{e+1})/2 with the end intervals halved.   */
+static void qgrid_sum(int n, long t, const double *t0, const double *k4,
+                      const double *strain, double g_inf, double tau_m,
+                      double gamma_c, double *sxy, double *sxx)
+{
+    double a = 0.0, b = 0.0;
+    for (int e = 0; e < n; ++e) {
+        double newer = e > 0 ? t0[e - 1] : t0[e];
+        double older = e + 1 < n ? t0[e + 1] : t0[e];
+        double w = 0.5 * (newer - older);
+        double age = (double)t - t0[e];
+        double s = k4[4 * e + 1];
+        double r = orc_shear_rate(k4[4 * e], k4[4 * e + 1], k4[4 * e + 2], k4[4 * e + 3]);
+        double G = g_inf * exp(-age / tau_m) * exp(-age * r / gamma_c);
+        a += w * s * G;
+        b += w * 2.0 * s * strain[e] * G;
+    }
+    *sxy = a;
+    *sxx = b;
+}
+
+/* Standalone grid for the pins: create, push a step, read the entries, sum. */
+orc_qgrid *orc_qgrid_create(int B, int C)
+{
+    if (B < 1 || C < 2)
+        return NULL;
+    orc_qgrid *g = (orc_qgrid *)calloc(1, sizeof(orc_qgrid));
+    qgrid_init(g, B, C);
+    return g;
+}
+
+void orc_qgrid_destroy(orc_qgrid *g)
+{
+    if (!g)
+        return;
+    qgrid_free(g);
+    free(g);
+}
+
+void orc_qgrid_push(orc_qgrid *g, long t, double kxx, double kxy, double kyx, double kyy)
+{
+    double k[4] = {kxx, kxy, kyx, kyy};
+    qgrid_push(g, t, k);
+}
+
+int orc_qgrid_capacity(const orc_qgrid *g) { return g->B * (g->C + 1); }
+
+int orc_qgrid_entries(const orc_qgrid *g, double *t0, double *dt, double *k4,
+                      double *strain)
+{
+    return qgrid_walk(g, t0, dt, k4, strain);
+}
+
+void orc_qgrid_sum(const orc_qgrid *g, long t, double g_inf, double tau_m,
+                   double gamma_c, double *sxy, double *sxx)
+{
+    int cap = orc_qgrid_capacity(g);
+    double *t0 = zalloc_q(cap), *dt = zalloc_q(cap), *k4 = zalloc_q(4 * (size_t)cap),
+           *st = zalloc_q(cap);
+    int n = qgrid_walk(g, t0, dt, k4, st);
+    qgrid_sum(n, t, t0, k4, st, g_inf, tau_m, gamma_c, sxy, sxx);
+    free(t0);
+    free(dt);
+    free(k4);
+    free(st);
+}
+
+/* ------------------------------------------------------------------------ */
 /* One channel: state and time loop.                                          */
 /* ------------------------------------------------------------------------ */
 typedef struct orc_channel {
@@ -313,6 +519,7 @@ typedef struct orc_channel {
     double *ring_r;  /* [n_hist][N] r(t') = sqrt(II_D(t')) */
     double *ring_g;  /* [n_hist][N] Gamma_{t'} */
     double *gam;     /* [N] Gamma_t */
+    struct orc_qgrid *qg; /* [N] quasi-logarithmic history grids, or NULL */
     /* outputs of the last completed step */
     double *rho_o, *ux_o, *uy_o, *kap_o; /* kap_o: [4][N] kxx,kxy,kyx,kyy */
     /* scratch */
@@ -386,6 +593,11 @@ void orc_destroy(orc_channel *c)
                       c->r_age,  c->dg_age};
     for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i)
         free(bufs[i]);
+    if (c->qg) {
+        for (int k = 0; k < c->N; ++k)
+            qgrid_free(&c->qg[k]);
+        free(c->qg);
+    }
     free(c);
 }
 
@@ -393,6 +605,18 @@ void orc_set_force(orc_channel *c, double gx, double gy)
 {
     c->gx = gx;
     c->gy = gy;
+}
+
+/* Switch the channel to the quasi-logarithmic history grid of B blocks of   */
+/* C entries (before its first step); the uniform window is then unused.      */
+int orc_set_history_grid(orc_channel *c, int B, int C)
+{
+    if (c->t != 0 || c->qg || B < 1 || C < 2)
+        return -1;
+    c->qg = (orc_qgrid *)calloc((size_t)c->N, sizeof(orc_qgrid));
+    for (int k = 0; k < c->N; ++k)
+        qgrid_init(&c->qg[k], B, C);
+    return 0;
 }
 
 long orc_time(const orc_channel *c) { return c->t; }
@@ -424,6 +648,24 @@ static void one_step(orc_channel *c)
     }
     /* 4. velocity gradient and shear rates */
     orc_velocity_gradient(lx, ly, c->ux_o, c->uy_o, kxx, kxy, kyx, kyy);
+    if (c->qg) {
+        /* 5-6 on the quasi-logarithmic grid: push, combine, integrate */
+        int cap = orc_qgrid_capacity(&c->qg[0]);
+        double *t0 = zalloc(cap), *dt = zalloc(cap), *k4 = zalloc(4 * (size_t)cap),
+               *st = zalloc(cap);
+        for (int k = 0; k < N; ++k) {
+            double kk[4] = {kxx[k], kxy[k], kyx[k], kyy[k]};
+            qgrid_push(&c->qg[k], t, kk);
+            int n = qgrid_walk(&c->qg[k], t0, dt, k4, st);
+            qgrid_sum(n, t, t0, k4, st, c->g_inf, c->tau_m, c->gamma_c, &c->new_xy[k],
+                      &c->new_xx[k]);
+        }
+        free(t0);
+        free(dt);
+        free(k4);
+        free(st);
+        goto collide;
+    }
     /* 5. push entry t = (s_t, r_t, Gamma_t) */
     long slot = t % H;
     for (int k = 0; k < N; ++k) {
@@ -445,6 +687,7 @@ static void one_step(orc_channel *c)
     }
     for (int k = 0; k < N; ++k)
         c->gam[k] += kxy[k];
+collide:
     /* 7. collision */
     for (int k = 0; k < N; ++k) {
         double nk[9], ns[9];

@@ -56,6 +56,14 @@ def load():
         "orc_get_state": (None, [ctypes.c_void_p, _D, _D, _D, _D, _D, _D, _D,
                                  ctypes.POINTER(ctypes.c_long)]),
         "orc_set_state": (None, [ctypes.c_void_p, _D, _D, _D, _D, _D, _D, _D, ctypes.c_long]),
+        "orc_set_history_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+        "orc_qgrid_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_int]),
+        "orc_qgrid_destroy": (None, [ctypes.c_void_p]),
+        "orc_qgrid_push": (None, [ctypes.c_void_p, ctypes.c_long] + [ctypes.c_double] * 4),
+        "orc_qgrid_capacity": (ctypes.c_int, [ctypes.c_void_p]),
+        "orc_qgrid_entries": (ctypes.c_int, [ctypes.c_void_p, _D, _D, _D, _D]),
+        "orc_qgrid_sum": (None, [ctypes.c_void_p, ctypes.c_long] + [ctypes.c_double] * 3
+                          + [_D, _D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -166,6 +174,52 @@ def history_sum_ages(s_age, r_age, g_inf, tau_m, gamma_c):
     return a.value, b.value
 
 
+class QGrid:
+    """The quasi-logarithmic history grid of one node (B blocks of C entries),
+    driven directly: push velocity gradients step by step, read the entries
+    newest first, evaluate the history integral."""
+
+    def __init__(self, B: int, C: int):
+        self.lib = load()
+        self.B, self.C = B, C
+        self.h = self.lib.orc_qgrid_create(B, C)
+        if not self.h:
+            raise ValueError("oracle rejected the grid")
+        self.t = 0
+
+    def close(self):
+        if self.h:
+            self.lib.orc_qgrid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, kxx=0.0, kxy=0.0, kyx=0.0, kyy=0.0):
+        """The entry of step self.t; then the step counter advances."""
+        self.lib.orc_qgrid_push(self.h, self.t, kxx, kxy, kyx, kyy)
+        self.t += 1
+
+    def entries(self):
+        """Live entries newest first: start time, duration, kappa [n][4] and
+        the strain gamma(t, t0) for the last pushed step t."""
+        cap = self.lib.orc_qgrid_capacity(self.h)
+        t0, dt, st = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+        k4 = np.zeros((cap, 4))
+        n = self.lib.orc_qgrid_entries(self.h, _p(t0), _p(dt), _p(k4), _p(st))
+        return t0[:n], dt[:n], k4[:n], st[:n]
+
+    def sum(self, g_inf, tau_m, gamma_c):
+        """(sigma_xy, sigma_xx) at the last pushed step."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self.lib.orc_qgrid_sum(self.h, self.t - 1, g_inf, tau_m, gamma_c, ctypes.byref(a),
+                               ctypes.byref(b))
+        return a.value, b.value
+
+
 # --------------------------------------------------------------------------
 # Channel object
 # --------------------------------------------------------------------------
@@ -182,6 +236,9 @@ class OracleChannel:
                                      ch.gamma_c, ch.n_hist, ch.gx, ch.gy, _p(u0))
         if not self.h:
             raise ValueError("oracle rejected the channel description")
+        if getattr(ch, "hist_blocks", 0):
+            if self.lib.orc_set_history_grid(self.h, ch.hist_blocks, ch.hist_block_len) != 0:
+                raise ValueError("oracle rejected the history grid")
 
     def close(self):
         if self.h:

@@ -488,3 +488,131 @@ def test_ucm_steady_centreline_maxwell_relation():
         errs.append(abs(uc / want - 1))
     assert errs[0] < 0.05
     assert errs[1] < errs[0] / 3
+
+
+# --------------------------------------------------------------------------
+# Quasi-logarithmic history grid (Sec. III)
+# --------------------------------------------------------------------------
+
+def _drive(grid, kappa_hist):
+    for k in kappa_hist:
+        grid.push(*k)
+
+
+def _seeded_kappa(n, seed, scale=1e-3):
+    rng = np.random.default_rng(workloads.BASE_SEED + seed)
+    return rng.uniform(-scale, scale, size=(n, 4))
+
+
+@pytest.mark.parametrize("B,C,t", [(1, 5, 17), (3, 4, 19), (3, 4, 64), (4, 6, 101),
+                                   (5, 128, 1000)])
+def test_qgrid_structure(B, C, t):
+    """Block steps double going back, entries tile time without gaps, the
+    newest is the current step, and every block holds C or C - 1 entries."""
+    g = oracle.QGrid(B, C)
+    _drive(g, np.zeros((t + 1, 4)))
+    t0, dt, _, _ = g.entries()
+    assert t0[0] == t and dt[0] == 1
+    assert np.all(t0[:-1] == t0[1:] + dt[1:])          # contiguous, newest first
+    assert set(np.unique(dt)) == {2.0 ** k for k in range(B)}
+    assert np.all(np.diff(dt) >= 0)                      # steps only grow with age
+    for k in range(B):
+        assert np.sum(dt == 2.0 ** k) in (C - 1, C)
+    # the grid reaches back about C (2^B - 1) steps
+    span = t0[0] + dt[0] - t0[-1]
+    assert C * (2 ** B - 1) - 2 ** B <= span <= C * (2 ** B - 1) + 1
+
+
+@pytest.mark.parametrize("B,C", [(3, 4), (4, 8), (6, 16)])
+def test_qgrid_entries_hold_interval_means_and_exact_strain(B, C):
+    """Each entry's kappa is the mean of the step kappas over its interval
+    (zero before t = 0), and its strain is the exact sum of the step shear
+    rates from its start to t - 1: combining two entries averages kappa and
+    multiplies the deformation factors."""
+    T = C * 2 ** B + 37
+    kap = _seeded_kappa(T, 40 + B)
+    g = oracle.QGrid(B, C)
+    _drive(g, kap)
+    t = T - 1
+    t0, dt, k4, strain = g.entries()
+
+    def raw(a, b):  # rows for steps a .. b-1, zeros before 0
+        out = np.zeros((b - a, 4))
+        for i, tt in enumerate(range(a, b)):
+            if tt >= 0:
+                out[i] = kap[tt]
+        return out
+
+    for e in range(len(t0)):
+        a, b = int(t0[e]), int(t0[e] + dt[e])
+        np.testing.assert_allclose(k4[e], raw(a, b).mean(axis=0), rtol=0, atol=1e-18)
+        want = raw(a, t)[:, 1].sum() if e > 0 else 0.0
+        assert abs(strain[e] - want) <= 1e-15, (e, strain[e], want)
+
+
+@pytest.mark.parametrize("C,t", [(8, 30), (9, 31), (64, 500)])
+def test_qgrid_single_block_is_the_uniform_window(C, t):
+    """With one block the grid is a uniform window of the last C (or C - 1)
+    steps, and its integral equals the uniform-window history sum of that
+    length."""
+    kap = _seeded_kappa(t + 1, 50 + C, scale=2e-2)
+    g = oracle.QGrid(1, C)
+    _drive(g, kap)
+    t0, dt, _, _ = g.entries()
+    n = len(t0)
+    assert n in (C, C - 1) and np.all(dt == 1) and t0[-1] == t - n + 1
+    s_age = kap[::-1][:n, 1]
+    r_age = np.array([oracle.shear_rate(*kap[t - a]) for a in range(n)])
+    for G, tau, gc in ((1e-3, 7.0, 0.1), (2e-3, 40.0, math.inf)):
+        want = oracle.history_sum_ages(s_age, r_age, G, tau, gc)
+        got = g.sum(G, tau, gc)
+        np.testing.assert_allclose(got, want, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("B,C,tau", [(4, 128, 200.0), (6, 128, 1000.0), (3, 64, 50.0)])
+def test_qgrid_constant_shear_continuum_limit(B, C, tau):
+    """Constant shear rate s for longer than the grid reaches back (UCM, no
+    damping): the non-uniform trapezoid rule gives the continuum integrals
+    sigma_xy = G s tau (1 - e^{-A/tau}) and N1 = 2 G s^2 tau^2 (1 - e^{-A/tau}
+    (1 + A/tau)) over the grid's reach A, within the trapezoid error bound
+    h^2 / (12 tau^2) of the widest step h."""
+    s, G = 3e-4, 1e-3
+    T = C * 2 ** (B + 1)
+    g = oracle.QGrid(B, C)
+    _drive(g, np.tile([0.0, s, 0.0, 0.0], (T, 1)))
+    t0, dt, _, _ = g.entries()
+    assert t0[-1] >= 0                    # only sheared entries left
+    A = (T - 1) - t0[-1]
+    sxy, sxx = g.sum(G, tau, math.inf)
+    want_xy = G * s * tau * (1 - math.exp(-A / tau))
+    want_n1 = 2 * G * s * s * tau * tau * (1 - math.exp(-A / tau) * (1 + A / tau))
+    bound = dt.max() ** 2 / (12 * tau ** 2)
+    assert abs(sxy / want_xy - 1) <= 1.5 * bound, (sxy, want_xy, bound)
+    assert abs(sxx / want_n1 - 1) <= 3.0 * bound, (sxx, want_n1, bound)
+
+
+def test_qgrid_damping_uses_the_averaged_gradient():
+    """The damping of a combined entry is sqrt(II_D) of its averaged kappa.
+    Grid X sees kappa_xx = +b, -b, +b, ... and grid Y kappa_xx = +b always,
+    both with kappa_xy = a: every single step has the same shear rate and the
+    same |gamma_dot| in both, so they differ only where entries were combined
+    -- X's averaged kappa_xx is 0 there (damping |a|), Y's is b.  Averaging
+    the rates instead would make the two sums equal."""
+    B, C, T = 3, 8, 200
+    a, b = 2e-3, 4e-2
+    gx, gy = oracle.QGrid(B, C), oracle.QGrid(B, C)
+    for t in range(T):
+        gx.push(b * (-1) ** t, a, 0.0, 0.0)
+        gy.push(b, a, 0.0, 0.0)
+    tx, dx, kx, _ = gx.entries()
+    ty, dy, ky, _ = gy.entries()
+    assert np.array_equal(tx, ty) and np.array_equal(dx, dy)
+    merged = dx > 1
+    assert np.allclose(kx[merged, 0], 0.0, atol=1e-18) and np.allclose(ky[merged, 0], b)
+    G, tau, gc = 1e-3, 60.0, 5e-3
+    sx, _ = gx.sum(G, tau, gc)
+    sy, _ = gy.sum(G, tau, gc)
+    # X's combined entries are damped by |a| instead of sqrt(2 b^2 + a^2)
+    assert sx > sy * (1 + 1e-3), (sx, sy)
+    # without damping the two grids carry the same shear history
+    assert abs(gx.sum(G, tau, math.inf)[0] - gy.sum(G, tau, math.inf)[0]) <= 1e-18

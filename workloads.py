@@ -45,6 +45,11 @@ class Channel:
     gx: float = 1e-6
     gy: float = 0.0
     u0: Optional[np.ndarray] = None
+    # History grid: hist_blocks = 0 keeps the uniform window of n_hist steps;
+    # hist_blocks = B >= 1 uses the quasi-logarithmic grid of B blocks of
+    # hist_block_len entries whose step doubles from block to block.
+    hist_blocks: int = 0
+    hist_block_len: int = 128
 
     @property
     def nodes(self) -> int:
