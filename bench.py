@@ -13,7 +13,8 @@ history push and the N_h-entry history integral.  The launch shape (steps
 per history pass, lanes, chunks, persistent pass) is chosen by the
 autotuner before the timed region.
 
-Beside it ("batched"): the 64-channel batched workload (uneven widths and
+Beside it ("grid"): the same channel on the quasi-logarithmic history grid
+of Sec. III.  And ("batched"): the 64-channel batched workload (uneven widths and
 windows, FP32, one launch per phase) against the plain per-channel FP64
 path (one handle per channel, no blocking, no graphs) on the same GPU.
 
@@ -204,6 +205,38 @@ def cpu_baseline(seconds: float = 12.0):
                       f"{steps} steps in {el:.1f} s, single thread"}
 
 
+def bench_grid(steps: int = 200, B: int = 6, C: int = 128):
+    """The large 2D channel on the quasi-logarithmic history grid of Sec. III
+    (B blocks of C entries; reach C (2^B - 1) = 8064 steps), FP64 lattice and
+    FP32 history.  One grid kernel per step (no temporal blocking)."""
+    import torch
+    import workloads
+    from paper_1504_06123_amd import Solver
+
+    ch = workloads.large_2d().channels[0].replace(hist_blocks=B, hist_block_len=C)
+    s = Solver([ch], precision="f32p64")
+    s.step(2 * C)
+    el, kt = time_steps(s, steps)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    grid_s = kt[0][0] / kt[0][1] / 1e3
+    # each block alternates between C - 1 and C live entries; 8 B per entry
+    # (FP32 averaged shear rate + FP32 |gamma_dot|)
+    alg_bytes = ch.nodes * B * (C - 0.5) * 8
+    gbs = alg_bytes / grid_s / 1e9
+    log(f"bench: grid B={B} C={C}: {el/steps*1e3:.4f} ms/step, grid kernel "
+        f"{grid_s*1e3:.4f} ms ({gbs:.0f} GB/s)")
+    return {"workload": f"large 2D channel 1024x512 on the quasi-logarithmic history grid, "
+                        f"B={B} blocks of C={C} (reach {C * (2 ** B - 1)} steps)",
+            "value": ch.nodes * steps / el, "unit": "node-steps/s", "ms_per_step": el / steps * 1e3,
+            "dtype": "f32 history + f64 lattice",
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_grid_step", "kernel_avg_ms": grid_s * 1e3,
+                         "alg_bytes_per_launch": alg_bytes}}
+
+
 def bench_batched(steps: int = 2000):
     """64 uneven channels: tuned FP32 batched path vs plain per-channel FP64."""
     import torch
@@ -256,6 +289,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--block", type=int, default=32, help="steps per pass without tuning")
     ap.add_argument("--persistent", action="store_true", help="persistent pass without tuning")
@@ -299,6 +333,10 @@ def main():
     node_steps = nodes * steps / el
     entries = nodes * H
 
+    grid = None
+    if not args.no_grid:
+        log("bench: large 2D channel on the quasi-logarithmic grid")
+        grid = bench_grid()
     batched = None
     if not args.no_batched:
         log("bench: batched 64-channel workload")
@@ -333,6 +371,7 @@ def main():
         "all_f32": side and {"value": side["node_steps_per_s"],
                              "ms_per_step": side["ms_per_step"],
                              "launch": side["cfg"], "roofline": side["roof"]},
+        "grid": grid,
         "batched": batched,
         "cpu_baseline": cpu,
     }

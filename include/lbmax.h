@@ -57,9 +57,10 @@ typedef enum {
  * Arithmetic of the whole path.
  *  LB_F64: populations, velocities, history ring and sums in FP64.
  *  LB_F32: populations stored as deviations n_i - a_i in FP32, history ring
- *          in FP32, history sums in FP32 with Kahan compensation; the
- *          accumulated strain (prefix sum of the shear rate, Sec. III
- *          Eq. eeval) and the combination of partial sums in FP64.
+ *          in FP32, history sums as FP32 partial sums over groups of rows
+ *          added into FP64 accumulators; the accumulated strain (prefix sum
+ *          of the shear rate, Sec. III Eq. eeval) and the combination of
+ *          partial sums in FP64.
  *  LB_F32_P64: the lattice state (populations as deviations, moments,
  *          stress planes) in FP64, the history ring and its window sums as
  *          in LB_F32.  The ring carries nearly all the bytes, so this costs
@@ -81,6 +82,20 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F32_P64 = 2 } lb_precision;
  * A channel with lx == 1, gy == 0 and u0_y == 0 everywhere is
  * unidirectional: u_y stays zero, |gamma_dot| = |kappa_xy|, and its history
  * ring stores the shear rate only; lb_set_force rejects gy != 0 for it.
+ *
+ * History grid.  hist_blocks == 0: the history integral runs over a uniform
+ * window of the last n_hist steps.  hist_blocks = B >= 1: it runs over the
+ * quasi-logarithmic grid of Sec. III instead, B blocks of
+ * C = hist_block_len entries (2 <= C, B <= 20, C * 2^B <= 2^30; n_hist is
+ * then ignored).  Block b = 1..B has the time step 2^(B-b) (block B, the
+ * newest, the LB step).  Each step a new entry enters block B; when a block
+ * then holds C + 1 entries, its two oldest are combined (strains added,
+ * velocity gradient averaged, |gamma_dot| taken from the averaged gradient)
+ * into the newest entry of block b - 1, and block 1's combined entries are
+ * dropped.  Before t = 0 every block is full of zero entries (rest).  The
+ * integral uses the trapezoid rule on the entries' start times.  Such a
+ * channel takes no temporal blocking (lb_set_block applies to the other
+ * channels), no window split, and no adjoint.
  */
 typedef struct {
     int32_t lx, ly;
@@ -89,6 +104,7 @@ typedef struct {
     int32_t n_hist;
     double gx, gy;
     const double *u0;
+    int32_t hist_blocks, hist_block_len;
 } lb_channel_desc;
 
 typedef struct lb_handle lb_handle;
@@ -158,6 +174,15 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  *     ring_s [n_hist][N] RH shear rate s(t') = kappa_xy, row t' mod n_hist
  *     ring_r [n_hist][N] RH |gamma_dot(t')| (absent for unidirectional
  *                           channels)
+ *   (a channel on the quasi-logarithmic grid has, instead of the two rings:
+ *     grid_s [B][C][N] RH   averaged shear rate of each entry; block b-1
+ *                           first, row (b-1)*C + (i mod C) for the i-th
+ *                           entry the block ever held, counting its C
+ *                           initial zero entries
+ *     grid_r [B][C][N] RH   |gamma_dot| of the averaged gradient, and
+ *     grid_d [3][B][C][N] RH  averaged 2 kappa_xx, kappa_xy + kappa_yx,
+ *                           2 kappa_yy (both absent for unidirectional
+ *                           channels))
  *     blk  [64][N] double   window sums of the block in progress (see
  *                           lb_set_block); read only when the block
  *                           position is not 0

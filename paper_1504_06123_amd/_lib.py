@@ -25,6 +25,7 @@ class ChannelDesc(ctypes.Structure):
         ("n_hist", ctypes.c_int32),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double),
         ("u0", ctypes.POINTER(ctypes.c_double)),
+        ("hist_blocks", ctypes.c_int32), ("hist_block_len", ctypes.c_int32),
     ]
 
 

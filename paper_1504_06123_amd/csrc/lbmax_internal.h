@@ -27,7 +27,9 @@ constexpr int kTileCounters = 4;   // persistent-pass tile counters (one per lan
 struct alignas(256) ChanDev {
     int32_t lx, ly, n, np;          // nodes n = lx*ly, plane stride np
     int32_t n_hist, has_r, nchunks, max_chunks;
-    int32_t vec, pad_[3];           // history kernel: nodes per lane (1, 2, 4)
+    int32_t vec;                    // history kernel: nodes per lane (1, 2, 4)
+    int32_t qb, qc;                 // quasi-logarithmic grid: blocks B, entries C (qb = 0: none)
+    int32_t pad_;
     double omega;                   // 1/tau_LB
     double g_inf;
     double inv_tau, inv_gc;         // 1/tau, 1/gamma_c (0 for gamma_c = inf)
@@ -41,6 +43,9 @@ struct alignas(256) ChanDev {
     int64_t off_ring_r;             // [n_hist][np] |gamma_dot| (has_r only)
     int64_t off_part;               // [kPartPlanes][max_chunks][np] doubles
     int64_t off_blk;                // [2*kMaxBlock][np] doubles: block sums
+    int64_t off_grid_s;             // [qb][qc][np] averaged shear rate of each grid entry
+    int64_t off_grid_r;             // [qb][qc][np] |gamma_dot| of the averaged gradient (has_r)
+    int64_t off_grid_d;             // [3][qb][qc][np] averaged D components (has_r)
 };
 static_assert(sizeof(ChanDev) == 256, "ChanDev layout");
 
@@ -81,6 +86,10 @@ void launch_combine(int prec, int block, char *ws, const ChanDev *chans,
 void launch_hist_step(int prec, int m, char *ws, const ChanDev *chans,
                       const NodeTile *tiles, int n_tiles, const int64_t *tcount,
                       int trel, hipStream_t st);
+// Quasi-logarithmic grid channels, every step: gradient, push, combination of
+// full blocks, history integral -> sigma (other channels' tiles return).
+void launch_grid_step(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
+                      int n_tiles, const int64_t *tcount, int trel, hipStream_t st);
 void launch_tick(int64_t *tcount, int64_t add, hipStream_t st);
 void launch_set_force(ChanDev *chans, int ch, double gx, double gy,
                       hipStream_t st);

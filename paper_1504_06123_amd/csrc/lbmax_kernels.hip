@@ -684,8 +684,8 @@ __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
     const NodeTile tl = tiles[blockIdx.x];
     const ChanDev *c = chans + tl.ch;
     const int n = tl.n0 + threadIdx.x;
-    if (n >= c->n)
-        return;
+    if (c->qb != 0 || n >= c->n)
+        return;  // grid channels step in k_grid_step
     const int64_t t = *tcount + trel;
     const int H = c->n_hist;
     const size_t np = (size_t)c->np;
@@ -725,6 +725,128 @@ __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
     P *sig = reinterpret_cast<P *>(ws + c->off_sig);
     sig[n] = (P)(c->g_inf * (A + sxy));
     sig[np + n] = (P)(c->g_inf * (B + 2.0 * gam * A + sxx));
+}
+
+// ---------------------------------------------------------------------------
+// Quasi-logarithmic history grid (Sec. III), one node per thread, every step.
+//
+// Block b = 1..B (index bi = b - 1, 0 the oldest) has the step 2^(B-b).  Its
+// i-th entry (i counts the C zero entries it starts with) lives in row
+// bi*C + (i mod C) and starts at t0 = 2^(B-b) i - (2^(B-b+1) - 1) C.  With
+// the C zero entries present before t = 0, block b has received
+// floor(t / 2^(B-b)) + 1 entries after step t (one per step for block B,
+// one per combination of block b + 1 otherwise) and combined
+// floor(t / 2^(B-b+1)) + 1 pairs, so at step t it combines its pair j = t /
+// 2^(B-b+1) -- entries 2j, 2j+1 -- exactly when 2^(B-b+1) divides t, into
+// entry C + j of block b - 1.  Blocks are combined oldest first, each before
+// it receives, so a block never holds more than C entries.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R rate_of_d(R dxx, R dxy, R dyy)
+{
+    // sqrt(II_D), II_D = tr(D^2) / 2 for D = kappa + kappa^T (Sec. II)
+    return sqrt(R(0.5) * (dxx * dxx + R(2) * dxy * dxy + dyy * dyy));
+}
+
+template <typename P, typename R>
+__global__ __launch_bounds__(kBlock) void k_grid_step(char *__restrict__ ws,
+                                                      const ChanDev *__restrict__ chans,
+                                                      const NodeTile *__restrict__ tiles,
+                                                      const int64_t *__restrict__ tcount,
+                                                      int trel)
+{
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const int n = tl.n0 + threadIdx.x;
+    if (c->qb == 0 || n >= c->n)
+        return;
+    const int64_t t = *tcount + trel;
+    const int B = c->qb, C = c->qc;
+    const size_t np = (size_t)c->np;
+    const size_t dplane = (size_t)B * C * np;
+    const bool has_r = c->has_r != 0;
+    R *gs = reinterpret_cast<R *>(ws + c->off_grid_s);
+    R *gr = reinterpret_cast<R *>(ws + c->off_grid_r);
+    R *gd = reinterpret_cast<R *>(ws + c->off_grid_d);
+    auto row = [&](int bi, int slot) { return ((size_t)bi * C + slot) * np + n; };
+
+    // gradient of this step's velocity
+    const P *vel = reinterpret_cast<const P *>(ws + c->off_vel);
+    const int y = n / c->lx, x = n - y * c->lx;
+    P kxx, kxy, kyx, kyy;
+    velocity_gradient<P>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
+
+    // combine the blocks whose pair is due, oldest block first
+    for (int bi = 0; bi < B; ++bi) {
+        const int sh = B - bi;  // log2 of the block's combination period
+        if ((t & ((int64_t(1) << sh) - 1)) != 0)
+            continue;
+        const int64_t j = t >> sh;
+        const int s0 = (int)((2 * j) % C), s1 = s0 + 1 == C ? 0 : s0 + 1;
+        const size_t o0 = row(bi, s0), o1 = row(bi, s1);
+        const R ms = R(0.5) * (gs[o0] + gs[o1]);
+        R md[3] = {R(0), R(0), R(0)}, mr = R(0);
+        if (has_r) {
+            for (int q = 0; q < 3; ++q)
+                md[q] = R(0.5) * (gd[q * dplane + o0] + gd[q * dplane + o1]);
+            mr = rate_of_d<R>(md[0], md[1], md[2]);
+        }
+        if (bi > 0) {
+            const size_t d = row(bi - 1, (int)(j % C));
+            gs[d] = ms;
+            if (has_r) {
+                gr[d] = mr;
+                for (int q = 0; q < 3; ++q)
+                    gd[q * dplane + d] = md[q];
+            }
+        }
+    }
+    // push the entry of step t: entry C + t of the newest block
+    {
+        const size_t d = row(B - 1, (int)(t % C));
+        gs[d] = (R)kxy;
+        if (has_r) {
+            const R dd[3] = {(R)(P(2) * kxx), (R)(kxy + kyx), (R)(P(2) * kyy)};
+            for (int q = 0; q < 3; ++q)
+                gd[q * dplane + d] = dd[q];
+            gr[d] = (R)shear_rate<P>(kxx, kxy, kyx, kyy);
+        }
+    }
+
+    // Eq. gitt on the grid, newest entry first: trapezoid weights from the
+    // neighbours' ages, strain gamma(t, t0) = sum of (mean s) x (step) over
+    // the entries from the newest-but-one down to this one.
+    const Decay<R> dec(c);
+    double sxy = 0.0, sxx = 0.0, gam = 0.0;
+    int64_t a_prev = 0;
+    bool first = true;
+    for (int bi = B - 1; bi >= 0; --bi) {
+        const int lg = B - 1 - bi;  // log2 of the block's step
+        const int64_t step = int64_t(1) << lg;
+        const int64_t i_new = C + (t >> lg);
+        const int64_t i_old = 2 * ((t >> (lg + 1)) + 1);
+        int64_t age = t - (step * i_new - (2 * step - 1) * (int64_t)C);
+        int slot = (int)(i_new % C);
+        for (int64_t i = i_new; i >= i_old; --i) {
+            const int64_t a_next = i > i_old ? age + step : (bi > 0 ? age + 2 * step : age);
+            const size_t o = row(bi, slot);
+            const R sv = gs[o];
+            const R rv = has_r ? gr[o] : fabs(sv);
+            if (!first)
+                gam += (double)sv * (double)step;
+            const R e = decay_pow((R)age, decay_rate<R>(dec, rv));
+            const double xw = 0.5 * (double)(a_next - a_prev) * (double)(sv * e);
+            sxy += xw;
+            sxx += 2.0 * gam * xw;
+            a_prev = age;
+            first = false;
+            age += step;
+            slot = slot == 0 ? C - 1 : slot - 1;
+        }
+    }
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    sig[n] = (P)(c->g_inf * sxy);
+    sig[np + n] = (P)(c->g_inf * sxx);
 }
 
 __global__ void k_tick(int64_t *tcount, int64_t add)
@@ -911,6 +1033,13 @@ void launch_hist_step(int prec, int m, char *ws, const ChanDev *chans, const Nod
 {
     LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_hist_step<P, H>), dim3(n_tiles), dim3(kBlock), 0,
                                            st, ws, chans, tiles, tcount, trel, m));
+}
+
+void launch_grid_step(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
+                      int n_tiles, const int64_t *tcount, int trel, hipStream_t st)
+{
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_grid_step<P, H>), dim3(n_tiles), dim3(kBlock),
+                                           0, st, ws, chans, tiles, tcount, trel));
 }
 
 void launch_tick(int64_t *tcount, int64_t add, hipStream_t st)

@@ -75,8 +75,18 @@ std::string check_desc(const lb_channel_desc *ch, int32_t n_ch)
             return bad("ly must be >= 3");
         if ((int64_t)d.lx * d.ly > (int64_t)1 << 30)
             return bad("too many nodes");
-        if (d.n_hist < 2)
+        if (d.hist_blocks < 0)
+            return bad("hist_blocks must be >= 0");
+        if (d.hist_blocks == 0 && d.n_hist < 2)
             return bad("n_hist must be >= 2");
+        if (d.hist_blocks > 0) {
+            if (d.hist_blocks > 20)
+                return bad("hist_blocks must be <= 20");
+            if (d.hist_block_len < 2)
+                return bad("hist_block_len must be >= 2");
+            if (((int64_t)d.hist_block_len << d.hist_blocks) > ((int64_t)1 << 30))
+                return bad("hist_block_len * 2^hist_blocks must be <= 2^30");
+        }
         if (!std::isfinite(d.tau_lb) || !(d.tau_lb > 0.5))
             return bad("tau_lb must be finite and > 1/2");
         if (!std::isfinite(d.g_inf) || d.g_inf < 0.0)
@@ -138,9 +148,11 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         c.ly = d.ly;
         c.n = d.lx * d.ly;
         c.np = (int)align_up((size_t)c.n, kNodeAlign);
-        c.n_hist = d.n_hist;
+        c.qb = d.hist_blocks;
+        c.qc = d.hist_blocks > 0 ? d.hist_block_len : 0;
+        c.n_hist = d.hist_blocks > 0 ? 0 : d.n_hist;
         c.has_r = unidirectional(d) ? 0 : 1;
-        c.max_chunks = max_chunks_for(d.n_hist, c.np);
+        c.max_chunks = d.hist_blocks > 0 ? 1 : max_chunks_for(d.n_hist, c.np);
         c.nchunks = 1;
         c.vec = 1;
         c.omega = 1.0 / d.tau_lb;
@@ -153,7 +165,8 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         c.gy = d.gy;
         const int blocks = (c.n + kBlock - 1) / kBlock;
         P.n_node_tiles += blocks;
-        P.n_hist_tiles_max += blocks * c.max_chunks;
+        if (c.qb == 0)
+            P.n_hist_tiles_max += blocks * c.max_chunks;
         stage = std::max(stage, (size_t)4 * c.n);
     }
     P.off_node_tiles = off;
@@ -186,6 +199,15 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
                            256);
         c.off_blk = (int64_t)off;
         off = align_up(off + (size_t)2 * kMaxBlock * c.np * sizeof(double), 256);
+        const size_t grows = (size_t)c.qb * c.qc;  // 0 without a grid
+        c.off_grid_s = (int64_t)off;
+        off = align_up(off + grows * hplane, 256);
+        c.off_grid_r = (int64_t)off;
+        if (c.has_r)
+            off = align_up(off + grows * hplane, 256);
+        c.off_grid_d = (int64_t)off;
+        if (c.has_r)
+            off = align_up(off + 3 * grows * hplane, 256);
     }
     P.total = off;
     return P;
@@ -219,6 +241,7 @@ struct lb_handle {
     int n_node_tiles = 0, n_hist_tiles = 0;
     int hist_group_begin[3] = {0, 0, 0}, hist_group_count[3] = {0, 0, 0};  // vec 1, 2, 4
     bool any_chunked = false;
+    bool any_grid = false, any_window = false;  // channels on the grid / the uniform window
     // host mirrors kept alive for asynchronous uploads
     std::vector<NodeTile> node_tiles;
     std::vector<HistTile> hist_tiles;
@@ -295,10 +318,16 @@ void build_tiles(lb_handle *h)
     h->node_tiles.clear();
     h->hist_tiles.clear();
     h->any_chunked = false;
+    h->any_grid = h->any_window = false;
     for (int ci = 0; ci < h->n_ch; ++ci) {
         const ChanDev &c = h->plan.chans[ci];
         for (int n0 = 0; n0 < c.n; n0 += kBlock)
             h->node_tiles.push_back({ci, n0});
+        if (c.qb > 0) {
+            h->any_grid = true;  // stepped by k_grid_step, no history tiles
+            continue;
+        }
+        h->any_window = true;
         if (c.nchunks > 1)
             h->any_chunked = true;
         const int span = kBlock * effective_vec(c.vec, h->block);
@@ -338,9 +367,11 @@ void default_tiling(lb_handle *h)
 {
     int total = 0;
     for (ChanDev &c : h->plan.chans) {
-        c.vec = c.n >= (1 << 16) ? 4 : (c.n >= (1 << 12) ? 2 : 1);
-        total += (c.n + kBlock * c.vec - 1) / (kBlock * c.vec);
+        c.vec = c.qb > 0 ? 1 : (c.n >= (1 << 16) ? 4 : (c.n >= (1 << 12) ? 2 : 1));
+        if (c.qb == 0)
+            total += (c.n + kBlock * c.vec - 1) / (kBlock * c.vec);
     }
+    total = std::max(total, 1);
     const int want = std::max(1, (2048 + total - 1) / total);
     for (ChanDev &c : h->plan.chans)
         c.nchunks = std::max(1, std::min(want, c.max_chunks));
@@ -411,6 +442,9 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
         HIP_TRY(h, hipEventRecord(e[1], st));
         HIP_TRY(h, hipEventRecord(e[2], st));
     }
+    if (h->any_grid)
+        launch_grid_step(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
+                         h->d_tcount, trel, st);
     if (m == 0) {
         static const int kVec[3] = {1, 2, 4};
         for (int g = 0; g < 3; ++g) {
@@ -424,7 +458,7 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
         if (h->any_chunked)
             launch_combine(h->pc, h->block, h->ws, h->d_chans, h->d_node_tiles,
                            h->n_node_tiles, st);
-    } else {
+    } else if (h->any_window) {
         launch_hist_step(h->pc, m, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
                          h->d_tcount, trel, st);
     }
@@ -510,9 +544,18 @@ std::vector<Section> state_sections(const lb_handle *h, int ci, int64_t t)
     v.push_back({c.off_sig, 2, rowb, pitch});
     v.push_back({c.off_vel, 2, rowb, pitch});
     v.push_back({c.off_rho, 1, rowb, pitch});
-    v.push_back({c.off_ring_s, (size_t)c.n_hist, hrowb, hpitch});
-    if (c.has_r)
-        v.push_back({c.off_ring_r, (size_t)c.n_hist, hrowb, hpitch});
+    if (c.qb > 0) {
+        const size_t grows = (size_t)c.qb * c.qc;
+        v.push_back({c.off_grid_s, grows, hrowb, hpitch});
+        if (c.has_r) {
+            v.push_back({c.off_grid_r, grows, hrowb, hpitch});
+            v.push_back({c.off_grid_d, 3 * grows, hrowb, hpitch});
+        }
+    } else {
+        v.push_back({c.off_ring_s, (size_t)c.n_hist, hrowb, hpitch});
+        if (c.has_r)
+            v.push_back({c.off_ring_r, (size_t)c.n_hist, hrowb, hpitch});
+    }
     v.push_back({c.off_blk, (size_t)2 * kMaxBlock, (size_t)c.n * sizeof(double),
                  (size_t)c.np * sizeof(double)});
     return v;
@@ -577,6 +620,9 @@ std::string adjoint_unsupported(const lb_handle *h, int seg_len)
 {
     for (int ci = 0; ci < h->n_ch; ++ci) {
         const ChanDev &c = h->plan.chans[ci];
+        if (c.qb > 0)
+            return "the adjoint covers the uniform history window; channel " +
+                   std::to_string(ci) + " uses the quasi-logarithmic grid";
         if (c.lx != 1 || c.has_r)
             return "the adjoint covers unidirectional channels (lx = 1, gy = 0, u0_y = 0); "
                    "channel " + std::to_string(ci) + " is not";

@@ -27,7 +27,8 @@ def _precision_code(precision: str) -> int:
 
 def make_descs(channels: Sequence) -> tuple:
     """Fill lb_channel_desc records from objects with the channel attributes
-    (lx, ly, tau_lb, g_inf, tau_m, gamma_c, n_hist, gx, gy, u0).  Returns the
+    (lx, ly, tau_lb, g_inf, tau_m, gamma_c, n_hist, gx, gy, u0, and optionally
+    hist_blocks, hist_block_len for the quasi-logarithmic grid).  Returns the
     ctypes array and the list of u0 buffers it points into (keep alive)."""
     n = len(channels)
     arr = (_lib.ChannelDesc * n)()
@@ -39,6 +40,8 @@ def make_descs(channels: Sequence) -> tuple:
         d.g_inf, d.tau_m, d.gamma_c = float(ch.g_inf), float(ch.tau_m), float(ch.gamma_c)
         d.n_hist = int(ch.n_hist)
         d.gx, d.gy = float(ch.gx), float(getattr(ch, "gy", 0.0))
+        d.hist_blocks = int(getattr(ch, "hist_blocks", 0))
+        d.hist_block_len = int(getattr(ch, "hist_block_len", 0)) if d.hist_blocks else 0
         u0 = getattr(ch, "u0", None)
         if u0 is not None:
             buf = np.ascontiguousarray(np.asarray(u0, dtype=np.float64).reshape(2, ch.ly, ch.lx))
@@ -236,9 +239,16 @@ def state_layout(channels: Sequence, precision: str = "f32"):
         for name, rows in (("pop", 9), ("sig", 2), ("vel", 2), ("drho", 1)):
             sec[name] = (off, rows, N)
             off = up(off + rows * N * R)
-        for name in ("ring_s",) + (() if uni else ("ring_r",)):
-            sec[name] = (off, int(ch.n_hist), N)
-            off = up(off + int(ch.n_hist) * N * RH)
+        B = int(getattr(ch, "hist_blocks", 0))
+        if B:
+            rows = B * int(ch.hist_block_len)
+            for name, k in (("grid_s", 1),) + (() if uni else (("grid_r", 1), ("grid_d", 3))):
+                sec[name] = (off, k * rows, N)
+                off = up(off + k * rows * N * RH)
+        else:
+            for name in ("ring_s",) + (() if uni else ("ring_r",)):
+                sec[name] = (off, int(ch.n_hist), N)
+                off = up(off + int(ch.n_hist) * N * RH)
         sec["blk"] = (off, 64, N)   # doubles
         off = up(off + 64 * N * 8)
         sec["force"] = (off, 1, 2)

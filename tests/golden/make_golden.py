@@ -15,6 +15,9 @@ well for the 2D runs):
                       unperturbed large 2D channel, 5000 steps, every 500;
                       an x-invariant 1024 x 512 run must reproduce it in
                       every column
+  startup_cessation_grid  the startup/cessation channel on the
+                      quasi-logarithmic grid of Sec. III with C = 128 and
+                      B = 7 (reach 16256 steps), same run and sampling
   batched_cheap8      the 8 batched channels of smallest ly*window, full
                       10000 steps, every 1000
   batched_all_1000    all 64 batched channels, 1000 steps, every 250
@@ -50,6 +53,8 @@ def cheap8_indices(wl):
 def runs():
     return {
         "startup_cessation": lambda: (workloads.startup_cessation(), None, None, None),
+        "startup_cessation_grid": lambda: (workloads.startup_cessation(grid=(7, 128)), None,
+                                           None, None),
         "large_2d_64x32": lambda: (workloads.large_2d(lx=64, ly=32), None, None, None),
         "large_2d_column": lambda: (workloads.large_2d(lx=1, perturb=False), None, None, None),
         "batched_cheap8": lambda: (workloads.batched(), None, None,

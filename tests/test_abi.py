@@ -142,3 +142,58 @@ def test_state_layout_sections_are_aligned():
     secs, _ = state_layout(workloads.plain_f64().channels, "f64")
     assert "ring_r" in secs[0]
     assert total % 256 == 0
+
+
+def test_descriptor_layout_matches_the_header(tmp_path):
+    """The ctypes record has the layout a C compiler gives lb_channel_desc."""
+    import subprocess
+    from paper_1504_06123_amd import _lib
+    src = tmp_path / "layout.c"
+    fields = [f for f, _ in _lib.ChannelDesc._fields_]
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "lbmax.h"\n'
+                   "int main(void) {\n"
+                   '  printf("%zu\\n", sizeof(lb_channel_desc));\n' +
+                   "".join(f'  printf("%zu\\n", offsetof(lb_channel_desc, {f}));\n'
+                           for f in fields) + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                           text=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(_lib.ChannelDesc)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(_lib.ChannelDesc, f).offset == off, f
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(hist_blocks=-1), "hist_blocks"), (dict(hist_blocks=21), "hist_blocks"),
+    (dict(hist_blocks=3, hist_block_len=1), "hist_block_len"),
+    (dict(hist_blocks=20, hist_block_len=4096), "2^hist_blocks"),
+])
+def test_invalid_history_grids_rejected(lib, kw, msg):
+    arr, _ = _desc(**kw)
+    assert lib.lb_workspace_bytes(arr, 1, 1) == 0
+    assert msg in lib.lb_last_error().decode()
+
+
+def test_grid_channel_workspace_replaces_the_window(lib):
+    """A grid channel holds B*C entries per node (s, |gamma_dot| and three
+    gradient components in 2D) and no uniform window: n_hist is ignored."""
+    from paper_1504_06123_amd import make_descs
+    ch = workloads.large_2d(lx=64, ly=32, n_hist=4096).channels[0]
+    a_win, _ = make_descs([ch])
+    a_grid, _ = make_descs([ch.replace(hist_blocks=6, hist_block_len=128)])
+    a_grid2, _ = make_descs([ch.replace(hist_blocks=6, hist_block_len=128, n_hist=1)])
+    w, g = lib.lb_workspace_bytes(a_win, 1, 1), lib.lb_workspace_bytes(a_grid, 1, 1)
+    assert g == lib.lb_workspace_bytes(a_grid2, 1, 1) > 0
+    N = 64 * 32
+    assert w - g >= 2 * 4096 * N * 4 - 5 * 6 * 128 * N * 4 - 4096
+
+
+def test_state_layout_of_grid_channels():
+    from paper_1504_06123_amd import state_layout
+    uni = workloads.plain_f64().channels[0].replace(lx=1, hist_blocks=3, hist_block_len=8)
+    twod = workloads.plain_f64().channels[0].replace(hist_blocks=2, hist_block_len=5)
+    secs, _ = state_layout([uni, twod], "f32p64")
+    assert secs[0]["grid_s"][1] == 24 and "grid_r" not in secs[0] and "ring_s" not in secs[0]
+    assert secs[1]["grid_s"][1] == 10 and secs[1]["grid_d"][1] == 30

@@ -111,15 +111,19 @@ def plain_f64() -> Workload:
                     sample_every=1, seed=BASE_SEED)
 
 
-def startup_cessation(seed: int = BASE_SEED + 1) -> Workload:
+def startup_cessation(seed: int = BASE_SEED + 1, grid=None) -> Workload:
     """Quasi-1D channel 1 x 256, tau = 2000, window 8192, on 20000 then off 20000.
 
     The body force is drawn log-uniform in [1e-7, 1e-5] from the seed.
+    ``grid=(B, C)`` replaces the window by the quasi-logarithmic grid of B
+    blocks of C entries.
     """
     rng = np.random.default_rng(seed)
     gx = float(_log_uniform(rng, 1e-7, 1e-5))
     ch = Channel(lx=1, ly=256, tau_lb=1.0, g_inf=1e-3, tau_m=2000.0,
                  gamma_c=0.1, n_hist=8192, gx=gx)
+    if grid is not None:
+        ch = ch.replace(hist_blocks=int(grid[0]), hist_block_len=int(grid[1]))
     return Workload("startup_cessation_1x256", [ch], "f32", steps_on=20000,
                     steps_off=20000, sample_every=1000, seed=seed)
 
