@@ -9,5 +9,5 @@ with the GPU path; the only common import is the seeded input module
 from .oracle import (  # noqa: F401
     OracleChannel, QGrid, lattice, equilibrium, force_term, collide,
     density_momentum, velocity_gradient, shear_rate, stress_divergence,
-    stream, history_sum, history_sum_ages, run_workload, load,
+    stream, history_sum, history_sum_ages, run_workload, load, expm2, finger_sum,
 )

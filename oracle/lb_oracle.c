@@ -32,8 +32,12 @@
  * (blocks whose step doubles going back; the two oldest entries of a full
  * block are combined into the next block).  The grid keeps kappa and the
  * deformation factors exactly as the paper describes and multiplies the
- * factors to obtain the strain.  State exchange (orc_get/set_state) covers
- * the uniform window only.
+ * factors to obtain the strain.  With orc_set_finger() the stress is taken
+ * from the full Finger tensor instead of its simple-shear reduction: the
+ * window keeps kappa(t') and exp(kappa(t') dt), E(t, t') is their ordered
+ * product (Eq. eeval) and -d_t' B = E kappa E^T + (E kappa E^T)^T; then
+ * sigma_yy enters the force and N1 = sigma_xx - sigma_yy.  State exchange
+ * (orc_get/set_state) covers the uniform window of the reduced path only.
  *
  * Parity status: every function below is pinned by the CPU test suite
  * (closed forms, moment identities, polynomial exactness, recursion
@@ -505,6 +509,80 @@ void orc_qgrid_sum(const orc_qgrid *g, long t, double g_inf, double tau_m,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Full-tensor Finger path (Sec. I Eq. gitt, Sec. III Eq. eeval and the       */
+/* relation for -d_t' B).                                                     */
+/*                                                                            */
+/* exp of a 2x2 matrix: scaling and squaring of the Taylor series (the norm  */
+/* is halved until it is at most 1/4, 24 Taylor terms, then squared back).   */
+/* ------------------------------------------------------------------------ */
+static void mat2_mul(const double *a, const double *b, double *out)
+{
+    double r0 = a[0] * b[0] + a[1] * b[2];
+    double r1 = a[0] * b[1] + a[1] * b[3];
+    double r2 = a[2] * b[0] + a[3] * b[2];
+    double r3 = a[2] * b[1] + a[3] * b[3];
+    out[0] = r0;
+    out[1] = r1;
+    out[2] = r2;
+    out[3] = r3;
+}
+
+void orc_expm2(const double *A, double *out)
+{
+    double nrm = fabs(A[0]) + fabs(A[1]) + fabs(A[2]) + fabs(A[3]);
+    int sq = 0;
+    while (nrm > 0.25) {
+        nrm *= 0.5;
+        ++sq;
+    }
+    double sc = ldexp(1.0, -sq);
+    double B[4] = {A[0] * sc, A[1] * sc, A[2] * sc, A[3] * sc};
+    double T[4] = {1.0, 0.0, 0.0, 1.0}, term[4] = {1.0, 0.0, 0.0, 1.0};
+    for (int n = 1; n <= 24; ++n) {
+        mat2_mul(term, B, term);
+        for (int i = 0; i < 4; ++i) {
+            term[i] /= (double)n;
+            T[i] += term[i];
+        }
+    }
+    for (int i = 0; i < sq; ++i)
+        mat2_mul(T, T, T);
+    for (int i = 0; i < 4; ++i)
+        out[i] = T[i];
+}
+
+/* Eq. gitt over a window given by age k = 0..n_live-1 (n_live <= n_hist):  */
+/* kappa_k[4] and the factors F_k = exp(kappa_k dt).  The deformation tensor */
+/* E(t, t - k) = F_1 F_2 ... F_k (Eq. eeval: newest factor on the left; the */
+/* entry at age 0 contributes no factor), -d_t' B = E kappa E^T + (E kappa  */
+/* E^T)^T, weights and modulus as in the simple-shear sum.  Output: sigma   */
+/* xx, xy, yy.                                                                */
+void orc_finger_sum(int n_hist, int n_live, const double *k_age, const double *f_age,
+                    double g_inf, double tau_m, double gamma_c, double *sig3)
+{
+    double E[4] = {1.0, 0.0, 0.0, 1.0};
+    double sxx = 0.0, sxy = 0.0, syy = 0.0;
+    for (int k = 0; k < n_live && k < n_hist; ++k) {
+        const double *kap = k_age + 4 * (size_t)k;
+        if (k > 0)
+            mat2_mul(E, f_age + 4 * (size_t)k, E);
+        double Et[4] = {E[0], E[2], E[1], E[3]};
+        double M[4];
+        mat2_mul(E, kap, M);
+        mat2_mul(M, Et, M);
+        double w = (k == 0 || k == n_hist - 1) ? 0.5 : 1.0;
+        double r = orc_shear_rate(kap[0], kap[1], kap[2], kap[3]);
+        double G = g_inf * exp(-(double)k / tau_m) * exp(-(double)k * r / gamma_c);
+        sxx += w * 2.0 * M[0] * G;
+        sxy += w * (M[1] + M[2]) * G;
+        syy += w * 2.0 * M[3] * G;
+    }
+    sig3[0] = sxx;
+    sig3[1] = sxy;
+    sig3[2] = syy;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One channel: state and time loop.                                          */
 /* ------------------------------------------------------------------------ */
 typedef struct orc_channel {
@@ -520,6 +598,12 @@ typedef struct orc_channel {
     double *ring_g;  /* [n_hist][N] Gamma_{t'} */
     double *gam;     /* [N] Gamma_t */
     struct orc_qgrid *qg; /* [N] quasi-logarithmic history grids, or NULL */
+    /* full-tensor Finger path (NULL unless enabled): per entry the velocity   */
+    /* gradient and its factor exp(kappa dt) of the deformation tensor         */
+    double *ring_k;  /* [n_hist][4][N] kxx, kxy, kyx, kyy of t' */
+    double *ring_f;  /* [n_hist][4][N] exp(kappa(t') dt), row-major 2x2 */
+    double *sig_yy;  /* [N] sigma_yy of the last completed step (full tensor) */
+    double *new_yy;
     /* outputs of the last completed step */
     double *rho_o, *ux_o, *uy_o, *kap_o; /* kap_o: [4][N] kxx,kxy,kyx,kyy */
     /* scratch */
@@ -598,6 +682,10 @@ void orc_destroy(orc_channel *c)
             qgrid_free(&c->qg[k]);
         free(c->qg);
     }
+    free(c->ring_k);
+    free(c->ring_f);
+    free(c->sig_yy);
+    free(c->new_yy);
     free(c);
 }
 
@@ -611,11 +699,30 @@ void orc_set_force(orc_channel *c, double gx, double gy)
 /* C entries (before its first step); the uniform window is then unused.      */
 int orc_set_history_grid(orc_channel *c, int B, int C)
 {
-    if (c->t != 0 || c->qg || B < 1 || C < 2)
+    if (c->t != 0 || c->qg || c->ring_k || B < 1 || C < 2)
         return -1;
     c->qg = (orc_qgrid *)calloc((size_t)c->N, sizeof(orc_qgrid));
     for (int k = 0; k < c->N; ++k)
         qgrid_init(&c->qg[k], B, C);
+    return 0;
+}
+
+/* Switch the channel to the full Finger tensor on its uniform window (before */
+/* its first step): sigma_yy no longer vanishes and enters the force.         */
+int orc_set_finger(orc_channel *c)
+{
+    if (c->t != 0 || c->qg || c->ring_k)
+        return -1;
+    size_t N = (size_t)c->N, H = (size_t)c->n_hist;
+    c->ring_k = zalloc(4 * H * N);
+    c->ring_f = zalloc(4 * H * N);
+    for (size_t sl = 0; sl < H; ++sl)
+        for (size_t k = 0; k < N; ++k) {
+            c->ring_f[(sl * 4 + 0) * N + k] = 1.0;  /* zero gradient: identity */
+            c->ring_f[(sl * 4 + 3) * N + k] = 1.0;
+        }
+    c->sig_yy = zalloc(N);
+    c->new_yy = zalloc(N);
     return 0;
 }
 
@@ -636,7 +743,7 @@ static void one_step(orc_channel *c)
         orc_density_momentum(nk, &c->rho_o[k], &c->jx[k], &c->jy[k]);
     }
     /* 2. force density: rho g + div sigma^{t-1} (sigma_yy = 0) */
-    orc_stress_divergence(lx, ly, c->sig_xx, c->sig_xy, NULL, c->fx, c->fy);
+    orc_stress_divergence(lx, ly, c->sig_xx, c->sig_xy, c->sig_yy, c->fx, c->fy);
     for (int k = 0; k < N; ++k) {
         c->fx[k] += c->rho_o[k] * c->gx;
         c->fy[k] += c->rho_o[k] * c->gy;
@@ -664,6 +771,38 @@ static void one_step(orc_channel *c)
         free(dt);
         free(k4);
         free(st);
+        goto collide;
+    }
+    if (c->ring_k) {
+        /* 5-6 with the full Finger tensor: push kappa and exp(kappa dt),    */
+        /* integrate over the window                                          */
+        long sl = t % H;
+        for (int k = 0; k < N; ++k) {
+            double kk[4] = {kxx[k], kxy[k], kyx[k], kyy[k]}, f[4];
+            orc_expm2(kk, f);
+            for (int a = 0; a < 4; ++a) {
+                c->ring_k[(sl * 4 + a) * N + k] = kk[a];
+                c->ring_f[(sl * 4 + a) * N + k] = f[a];
+            }
+        }
+        int live = (t + 1 < H) ? (int)(t + 1) : H;
+        double *ka = zalloc(4 * (size_t)H), *fa = zalloc(4 * (size_t)H);
+        for (int k = 0; k < N; ++k) {
+            for (int a = 0; a < live; ++a) {
+                long sa = (t - a) % H;
+                for (int q = 0; q < 4; ++q) {
+                    ka[4 * a + q] = c->ring_k[(sa * 4 + q) * N + k];
+                    fa[4 * a + q] = c->ring_f[(sa * 4 + q) * N + k];
+                }
+            }
+            double s3[3];
+            orc_finger_sum(H, live, ka, fa, c->g_inf, c->tau_m, c->gamma_c, s3);
+            c->new_xx[k] = s3[0];
+            c->new_xy[k] = s3[1];
+            c->new_yy[k] = s3[2];
+        }
+        free(ka);
+        free(fa);
         goto collide;
     }
     /* 5. push entry t = (s_t, r_t, Gamma_t) */
@@ -702,6 +841,8 @@ collide:
     orc_stream(lx, ly, c->nstar, c->n);
     memcpy(c->sig_xy, c->new_xy, sizeof(double) * (size_t)N);
     memcpy(c->sig_xx, c->new_xx, sizeof(double) * (size_t)N);
+    if (c->sig_yy)
+        memcpy(c->sig_yy, c->new_yy, sizeof(double) * (size_t)N);
     c->t = t + 1;
     c->has_out = 1;
 }
@@ -732,7 +873,12 @@ int orc_stress(const orc_channel *c, double *sxy, double *n1)
         return -1;
     size_t b = sizeof(double) * (size_t)c->N;
     if (sxy) memcpy(sxy, c->sig_xy, b);
-    if (n1) memcpy(n1, c->sig_xx, b); /* sigma_yy = 0 in simple shear */
+    if (n1) {
+        memcpy(n1, c->sig_xx, b); /* sigma_yy = 0 in simple shear */
+        if (c->sig_yy)
+            for (int k = 0; k < c->N; ++k)
+                n1[k] -= c->sig_yy[k];
+    }
     return 0;
 }
 

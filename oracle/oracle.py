@@ -57,6 +57,10 @@ def load():
                                  ctypes.POINTER(ctypes.c_long)]),
         "orc_set_state": (None, [ctypes.c_void_p, _D, _D, _D, _D, _D, _D, _D, ctypes.c_long]),
         "orc_set_history_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+        "orc_set_finger": (ctypes.c_int, [ctypes.c_void_p]),
+        "orc_expm2": (None, [_D, _D]),
+        "orc_finger_sum": (None, [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, _D]),
         "orc_qgrid_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_int]),
         "orc_qgrid_destroy": (None, [ctypes.c_void_p]),
         "orc_qgrid_push": (None, [ctypes.c_void_p, ctypes.c_long] + [ctypes.c_double] * 4),
@@ -174,6 +178,28 @@ def history_sum_ages(s_age, r_age, g_inf, tau_m, gamma_c):
     return a.value, b.value
 
 
+def expm2(a) -> np.ndarray:
+    """exp of a 2x2 matrix (row-major [2][2])."""
+    a = _f64(a).reshape(4)
+    out = np.zeros(4)
+    load().orc_expm2(_p(a), _p(out))
+    return out.reshape(2, 2)
+
+
+def finger_sum(n_hist, k_age, g_inf, tau_m, gamma_c, f_age=None):
+    """Full-tensor history integral over a window given by age: k_age
+    [n_live][2][2] velocity gradients (kappa_ab = d_b u_a); f_age the factors
+    exp(kappa dt) (computed with expm2 when None).  Returns (sxx, sxy, syy)."""
+    k_age = _f64(k_age).reshape(-1, 4)
+    if f_age is None:
+        f_age = np.array([expm2(k.reshape(2, 2)).reshape(4) for k in k_age])
+    f_age = _f64(f_age).reshape(-1, 4)
+    out = np.zeros(3)
+    load().orc_finger_sum(int(n_hist), len(k_age), _p(np.ascontiguousarray(k_age)),
+                          _p(np.ascontiguousarray(f_age)), g_inf, tau_m, gamma_c, _p(out))
+    return tuple(out)
+
+
 class QGrid:
     """The quasi-logarithmic history grid of one node (B blocks of C entries),
     driven directly: push velocity gradients step by step, read the entries
@@ -236,6 +262,9 @@ class OracleChannel:
                                      ch.gamma_c, ch.n_hist, ch.gx, ch.gy, _p(u0))
         if not self.h:
             raise ValueError("oracle rejected the channel description")
+        if getattr(ch, "finger", False):
+            if self.lib.orc_set_finger(self.h) != 0:
+                raise ValueError("oracle rejected the full-tensor path")
         if getattr(ch, "hist_blocks", 0):
             if self.lib.orc_set_history_grid(self.h, ch.hist_blocks, ch.hist_block_len) != 0:
                 raise ValueError("oracle rejected the history grid")

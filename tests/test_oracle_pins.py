@@ -616,3 +616,138 @@ def test_qgrid_damping_uses_the_averaged_gradient():
     assert sx > sy * (1 + 1e-3), (sx, sy)
     # without damping the two grids carry the same shear history
     assert abs(gx.sum(G, tau, math.inf)[0] - gy.sum(G, tau, math.inf)[0]) <= 1e-18
+
+
+# --------------------------------------------------------------------------
+# Full-tensor Finger path (Eq. gitt, -d_t'B = E kappa E^T + transpose,
+# Eq. eeval)
+# --------------------------------------------------------------------------
+
+def test_expm2_matches_scipy():
+    import scipy.linalg as sla
+    rng = np.random.default_rng(workloads.BASE_SEED + 60)
+    for scale in (1e-6, 1e-3, 0.1, 1.0, 7.0):
+        for _ in range(20):
+            a = rng.normal(size=(2, 2)) * scale
+            want = sla.expm(a)
+            got = oracle.expm2(a)
+            # forward error of scaling and squaring: rounding relative to
+            # e^{|A|}, doubled by each squaring
+            nrm = np.abs(a).sum()
+            sq = max(0, math.ceil(math.log2(max(nrm / 0.25, 1.0))))
+            assert np.abs(got - want).max() <= 4e-15 * 2 ** sq * math.exp(nrm)
+
+
+def _shear_history(n, seed, scale=2e-3):
+    rng = np.random.default_rng(workloads.BASE_SEED + seed)
+    return rng.uniform(-scale, scale, size=n)
+
+
+@pytest.mark.parametrize("n_hist,live", [(50, 50), (64, 20)])
+def test_finger_reduces_to_simple_shear(n_hist, live):
+    """For unidirectional flow (kappa = [[0, s], [0, 0]], nilpotent) the full
+    tensor gives the simple-shear reduction: sigma_xy = int s G,
+    sigma_xx = int 2 s gamma G, sigma_yy = 0."""
+    s = _shear_history(live, 61)
+    k = np.zeros((live, 2, 2))
+    k[:, 0, 1] = s
+    r = np.abs(s)
+    G, tau, gc = 1e-3, 30.0, 0.05
+    sxx, sxy, syy = oracle.finger_sum(n_hist, k, G, tau, gc)
+    # reduced path: strain gamma_k = sum of s over ages 1..k
+    dg = np.concatenate([[0.0], np.cumsum(s[1:])])
+    want_xy, want_xx = oracle.history_sum(n_hist, s, r, dg, G, tau, gc, n_live=live)
+    assert abs(sxy - want_xy) <= 1e-15 * abs(want_xy) + 1e-22
+    assert abs(sxx - want_xx) <= 1e-13 * abs(want_xx) + 1e-24
+    assert abs(syy) <= 1e-24
+
+
+@pytest.mark.parametrize("eps", [3e-4, -2e-3])
+def test_finger_planar_extension_closed_form(eps):
+    """Constant planar extension kappa = diag(eps, -eps): E_k = diag(e^{eps k},
+    e^{-eps k}), so sigma_xx = G sum_k w_k 2 eps e^{2 eps k} D_k and
+    sigma_yy = -G sum_k w_k 2 eps e^{-2 eps k} D_k with the damping
+    D_k = e^{-k (1/tau + 2|eps|/gamma_c)} -- geometric sums in closed form
+    (trapezoid weights 1/2 at both ends of the window)."""
+    n_hist, G, tau, gc = 80, 1e-3, 25.0, 0.1
+    k = np.tile(np.diag([eps, -eps]), (n_hist, 1, 1))
+    sxx, sxy, syy = oracle.finger_sum(n_hist, k, G, tau, gc)
+    lam = 1 / tau + 2 * abs(eps) / gc
+    n = n_hist - 1
+
+    def trap(x):  # sum_{k=0}^{n} w_k x^k
+        return (1 - x ** (n + 1)) / (1 - x) - 0.5 - 0.5 * x ** n
+
+    want_xx = G * 2 * eps * trap(math.exp(2 * eps - lam))
+    want_yy = -G * 2 * eps * trap(math.exp(-2 * eps - lam))
+    assert abs(sxx / want_xx - 1) <= 1e-13
+    assert abs(syy / want_yy - 1) <= 1e-13
+    assert abs(sxy) <= 1e-22
+
+
+def test_finger_rigid_rotation_is_stress_free():
+    """kappa = [[0, w], [-w, 0]] is a rigid rotation: E is a rotation that
+    commutes with kappa, E kappa E^T = kappa is antisymmetric, and the
+    stress vanishes (frame indifference)."""
+    w = 3e-3
+    k = np.tile(np.array([[0.0, w], [-w, 0.0]]), (60, 1, 1))
+    out = oracle.finger_sum(60, k, 1e-3, 40.0, 0.1)
+    assert max(abs(v) for v in out) <= 1e-20
+
+
+def test_finger_rotates_with_the_frame():
+    """Rotating every velocity gradient by a fixed Q rotates the stress:
+    sigma' = Q sigma Q^T (|gamma_dot| is invariant)."""
+    rng = np.random.default_rng(workloads.BASE_SEED + 62)
+    k = rng.uniform(-2e-3, 2e-3, size=(70, 2, 2))
+    th = 0.7
+    Q = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    kq = np.einsum("ab,kbc,dc->kad", Q, k, Q)
+    a = oracle.finger_sum(70, k, 1e-3, 30.0, 0.08)
+    b = oracle.finger_sum(70, kq, 1e-3, 30.0, 0.08)
+    S = np.array([[a[0], a[1]], [a[1], a[2]]])
+    Sq = Q @ S @ Q.T
+    np.testing.assert_allclose([b[0], b[1], b[2]], [Sq[0, 0], Sq[0, 1], Sq[1, 1]],
+                               rtol=0, atol=1e-13 * np.abs(S).max())
+
+
+def test_finger_channel_equals_reduced_channel_in_unidirectional_flow():
+    """A unidirectional channel gives the same run with the full tensor and
+    with the simple-shear reduction (sigma_yy stays zero)."""
+    ch = workloads.plain_f64().channels[0].replace(lx=1, ly=12, n_hist=120, tau_m=30.0,
+                                                   gx=5e-5)
+    wl = workloads.Workload("u", [ch], "f64", steps_on=300, steps_off=100, sample_every=50)
+    a = oracle.run_workload(wl)[0]
+    b = oracle.run_workload(workloads.Workload("u", [ch.replace(finger=True)], "f64",
+                                               steps_on=300, steps_off=100,
+                                               sample_every=50))[0]
+    # the reduced path takes strains as differences of the growing prefix
+    # Gamma, the full tensor as products: N1 (second order in the strain)
+    # differs by the prefix's cancellation, ~1e-12
+    for key, tol in (("ux", 1e-13), ("sxy", 1e-13), ("n1", 1e-11)):
+        assert np.abs(a[key] - b[key]).max() <= tol * np.abs(a[key]).max(), key
+
+
+def test_finger_product_order_rotation_after_shear():
+    """Order of the factors in Eq. eeval (newest on the left): shear for the
+    older ages, then a rigid rotation for the K - 1 newest.  The rotation
+    adds no stress of its own and turns the shear's stress with it:
+    sigma = R sigma_shear R^T, R = exp(kappa_rot (K - 1)), where sigma_shear
+    is the same history with zero gradient in place of the rotation.  The
+    reversed product order would instead rotate the shear rate before it
+    is deformed."""
+    K, H, w = 15, 90, 0.02
+    s = _shear_history(H, 63, scale=3e-3) + 4e-3
+    hist = np.zeros((H, 2, 2))
+    hist[K:, 0, 1] = s[K:]
+    rot = hist.copy()
+    rot[1:K] = np.array([[0.0, w], [-w, 0.0]])
+    G, tau, gc = 1e-3, 40.0, 0.1
+    a = oracle.finger_sum(H, hist, G, tau, gc)
+    b = oracle.finger_sum(H, rot, G, tau, gc)
+    R = oracle.expm2(np.array([[0.0, w], [-w, 0.0]]) * (K - 1))
+    S = np.array([[a[0], a[1]], [a[1], a[2]]])
+    want = R @ S @ R.T
+    got = np.array([[b[0], b[1]], [b[1], b[2]]])
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(S).max()
+    assert np.abs(got - S).max() > 1e-3 * np.abs(S).max()   # the rotation matters

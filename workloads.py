@@ -50,6 +50,10 @@ class Channel:
     # hist_block_len entries whose step doubles from block to block.
     hist_blocks: int = 0
     hist_block_len: int = 128
+    # Stress from the full Finger tensor (Eq. gitt with -d_t'B = E k E^T +
+    # (E k E^T)^T, E the ordered product of exp(kappa dt)) instead of the
+    # simple-shear reduction; sigma_yy then enters the force.
+    finger: bool = False
 
     @property
     def nodes(self) -> int:
