@@ -14,7 +14,9 @@ per history pass, lanes, chunks, persistent pass) is chosen by the
 autotuner before the timed region.
 
 Beside it ("grid"): the same channel on the quasi-logarithmic history grid
-of Sec. III.  And ("batched"): the 64-channel batched workload (uneven widths and
+of Sec. III; ("full_tensor"): the same channel with the full Finger tensor
+instead of its simple-shear reduction; and ("batched"): the 64-channel
+batched workload (uneven widths and
 windows, FP32, one launch per phase) against the plain per-channel FP64
 path (one handle per channel, no blocking, no graphs) on the same GPU.
 
@@ -237,6 +239,40 @@ def bench_grid(steps: int = 200, B: int = 6, C: int = 128):
                          "alg_bytes_per_launch": alg_bytes}}
 
 
+def bench_finger(steps: int = 128):
+    """The perturbed large 2D channel with the full Finger tensor (the exact
+    model for non-unidirectional flow), FP64 lattice and FP32 history,
+    16 steps per pass, persistent pass."""
+    import torch
+    import workloads
+    from paper_1504_06123_amd import Solver, autotune
+
+    ch = workloads.large_2d().channels[0].replace(finger=True)
+    s = Solver([ch], precision="f32p64")
+    s.step(16)
+    cfg = dict(block=16, vec=1, chunk_len=1 << 30, persistent=True, graph=0)
+    autotune.apply(s, cfg)
+    s.step(32)
+    el, kt = time_steps(s, steps)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    pass_s = kt[0][0] / kt[0][1] / 1e3
+    # 32 B per entry: kappa (4 x FP32) and exp(kappa dt) - I (4 x FP32)
+    alg_bytes = ch.nodes * ch.n_hist * 32
+    gbs = alg_bytes / pass_s / 1e9
+    log(f"bench: full tensor: {el/steps*1e3:.4f} ms/step, pass {pass_s*1e3:.3f} ms "
+        f"({gbs:.0f} GB/s)")
+    return {"workload": "large 2D channel 1024x512, N_h=4096, full Finger tensor",
+            "value": ch.nodes * steps / el, "unit": "node-steps/s",
+            "ms_per_step": el / steps * 1e3, "dtype": "f32 history + f64 lattice",
+            "config": cfg,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_finger_pass_persistent (16 steps per pass)",
+                         "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg_bytes}}
+
+
 def bench_batched(steps: int = 2000):
     """64 uneven channels: tuned FP32 batched path vs plain per-channel FP64."""
     import torch
@@ -290,6 +326,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--no-finger", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--block", type=int, default=32, help="steps per pass without tuning")
     ap.add_argument("--persistent", action="store_true", help="persistent pass without tuning")
@@ -337,6 +374,10 @@ def main():
     if not args.no_grid:
         log("bench: large 2D channel on the quasi-logarithmic grid")
         grid = bench_grid()
+    finger = None
+    if not args.no_finger:
+        log("bench: large 2D channel with the full Finger tensor")
+        finger = bench_finger()
     batched = None
     if not args.no_batched:
         log("bench: batched 64-channel workload")
@@ -359,7 +400,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 history (Kahan sums, f64 strain) + f64 lattice state",
+        "dtype": "f32 history (FP32 partial sums into FP64, f64 strain) + f64 lattice state",
         "data": "synthetic",
         "config": {"workload": "large 2D channel 1024x512, N_h=4096, tau=1000 steps, "
                                "g=5e-6, 1% seeded velocity perturbation",
@@ -372,6 +413,7 @@ def main():
                              "ms_per_step": side["ms_per_step"],
                              "launch": side["cfg"], "roofline": side["roof"]},
         "grid": grid,
+        "full_tensor": finger,
         "batched": batched,
         "cpu_baseline": cpu,
     }

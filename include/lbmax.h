@@ -96,6 +96,14 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F32_P64 = 2 } lb_precision;
  * integral uses the trapezoid rule on the entries' start times.  Such a
  * channel takes no temporal blocking (lb_set_block applies to the other
  * channels), no window split, and no adjoint.
+ *
+ * Stress tensor.  finger == 0: the simple-shear reduction of the Finger
+ * tensor (sigma_xy = int s G, sigma_xx = int 2 s gamma G, sigma_yy = 0;
+ * exact for unidirectional flow).  finger == 1: the full tensor of Eq. gitt,
+ * -d_t'B(t, t') = E kappa(t') E^T + transpose with E(t, t') the ordered
+ * product of exp(kappa dt) over the steps from t' to t - 1 (Eq. eeval);
+ * sigma_yy enters the force and N1 = sigma_xx - sigma_yy.  Needs
+ * hist_blocks == 0; blocks of at most 16 steps (lb_set_block); no adjoint.
  */
 typedef struct {
     int32_t lx, ly;
@@ -105,6 +113,7 @@ typedef struct {
     double gx, gy;
     const double *u0;
     int32_t hist_blocks, hist_block_len;
+    int32_t finger;
 } lb_channel_desc;
 
 typedef struct lb_handle lb_handle;
@@ -158,7 +167,7 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  * 256-byte aligned, R = the lattice type: double for LB_F64 and LB_F32_P64,
  * float for LB_F32; RH = the history type: double for LB_F64, float
  * otherwise):
- *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 2,
+ *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 3,
  *     uint32 precision, int64 t (completed steps), int32 n_ch,
  *     int32 reserved, uint64 total bytes, int32 block length,
  *     int32 block position (steps of the current block already done);
@@ -168,13 +177,16 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  *                    shifted back by one streaming step).  Direction order
  *                    q = 0..8: (0,0), (1,0), (-1,0), (0,1), (0,-1), (1,1),
  *                    (-1,-1), (1,-1), (-1,1).
- *     sig  [2][N] R  sigma_xy, sigma_xx of step t-1
+ *     sig  [3][N] R  sigma_xy, sigma_xx, sigma_yy of step t-1
  *     vel  [2][N] R  u_x, u_y of step t-1
  *     drho [N]    R  rho - 1 of step t-1
  *     ring_s [n_hist][N] RH shear rate s(t') = kappa_xy, row t' mod n_hist
  *     ring_r [n_hist][N] RH |gamma_dot(t')| (absent for unidirectional
  *                           channels)
- *   (a channel on the quasi-logarithmic grid has, instead of the two rings:
+ *   (a full-tensor channel has instead ring [8][n_hist][N] RH: kappa_xx,
+ *     kappa_xy, kappa_yx, kappa_yy of t', then exp(kappa(t') dt) - I
+ *     row-major, each plane with row t' mod n_hist;
+ *   a channel on the quasi-logarithmic grid has, instead of the two rings:
  *     grid_s [B][C][N] RH   averaged shear rate of each entry; block b-1
  *                           first, row (b-1)*C + (i mod C) for the i-th
  *                           entry the block ever held, counting its C
@@ -185,7 +197,8 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  *                           channels))
  *     blk  [64][N] double   window sums of the block in progress (see
  *                           lb_set_block); read only when the block
- *                           position is not 0
+ *                           position is not 0 ([96][N] for a full-tensor
+ *                           channel)
  *     force  2 doubles: gx, gy.
  * Ring rows of times before t = 0 are zero.
  */

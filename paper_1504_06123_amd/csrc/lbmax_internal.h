@@ -20,7 +20,11 @@ constexpr int kMaxBlock = 32;      // most steps served by one history pass
 constexpr int kPlaneB = kMaxBlock;
 constexpr int kPlaneT = 2 * kMaxBlock;
 constexpr int kPartPlanes = 2 * kMaxBlock + 1;
-constexpr int kTileCounters = 4;   // persistent-pass tile counters (one per lane width)
+constexpr int kTileCounters = 4;   // persistent-pass tile counters (lane widths, full tensor)
+// Full tensor: S_xx, S_xy, S_yy per step of the block, then the range's
+// total deformation (4 planes).
+constexpr int kFingerPartPlanes = 3 * kMaxBlock + 4;
+constexpr int kMaxFingerBlock = 16;
 
 // Per-channel parameters and workspace offsets, read by every kernel.
 // 256 bytes so a table row never straddles two scalar cache lines twice.
@@ -29,20 +33,20 @@ struct alignas(256) ChanDev {
     int32_t n_hist, has_r, nchunks, max_chunks;
     int32_t vec;                    // history kernel: nodes per lane (1, 2, 4)
     int32_t qb, qc;                 // quasi-logarithmic grid: blocks B, entries C (qb = 0: none)
-    int32_t pad_;
+    int32_t finger;                 // 1: full Finger tensor (8-plane ring: kappa, g; sigma_yy)
     double omega;                   // 1/tau_LB
     double g_inf;
     double inv_tau, inv_gc;         // 1/tau, 1/gamma_c (0 for gamma_c = inf)
     double l2_tau, l2_gc;           // log2(e)/tau, log2(e)/gamma_c
     double gx, gy;                  // body-force acceleration
     int64_t off_pop;                // [2][9][np] populations minus a_i
-    int64_t off_sig;                // [2][np]  sigma_xy, sigma_xx
+    int64_t off_sig;                // [3][np]  sigma_xy, sigma_xx, sigma_yy
     int64_t off_vel;                // [2][np]  u_x, u_y
     int64_t off_rho;                // [np]     rho - 1
-    int64_t off_ring_s;             // [n_hist][np] shear rate
+    int64_t off_ring_s;             // [n_hist][np] shear rate ([8][n_hist][np] full tensor)
     int64_t off_ring_r;             // [n_hist][np] |gamma_dot| (has_r only)
-    int64_t off_part;               // [kPartPlanes][max_chunks][np] doubles
-    int64_t off_blk;                // [2*kMaxBlock][np] doubles: block sums
+    int64_t off_part;               // [kPartPlanes or kFingerPartPlanes][max_chunks][np] doubles
+    int64_t off_blk;                // [2 or 3 * kMaxBlock][np] doubles: block sums
     int64_t off_grid_s;             // [qb][qc][np] averaged shear rate of each grid entry
     int64_t off_grid_r;             // [qb][qc][np] |gamma_dot| of the averaged gradient (has_r)
     int64_t off_grid_d;             // [3][qb][qc][np] averaged D components (has_r)
@@ -79,6 +83,11 @@ void launch_hist_pass(int prec, int vec, int block, char *ws, const ChanDev *cha
                       const HistTile *tiles, int n_tiles, const int64_t *tcount,
                       int trel, int persistent_grid, int *counter, hipStream_t st);
 int hist_pass_blocks_per_cu(int prec, int vec, int block);
+// Full-tensor pass for the tiles of the full-tensor channels (block <= 16).
+void launch_finger_pass(int prec, int block, char *ws, const ChanDev *chans,
+                        const HistTile *tiles, int n_tiles, const int64_t *tcount, int trel,
+                        int persistent_grid, int *counter, hipStream_t st);
+int finger_pass_blocks_per_cu(int prec, int block);
 // FP64 combine of chunk partials into sigma and the block sums.
 void launch_combine(int prec, int block, char *ws, const ChanDev *chans,
                     const NodeTile *tiles, int n_tiles, hipStream_t st);

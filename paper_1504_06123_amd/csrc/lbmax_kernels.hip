@@ -224,19 +224,22 @@ __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
     const R jy = (d[3] - d[4]) + (d[5] - d[6]) + (d[8] - d[7]);
     const R rho = R(1) + drho;
 
-    // Force density rho*g + div sigma^{t-1} (sigma_yy = 0 in simple shear);
-    // d/dx periodic central, d/dy central with one-sided rows at the walls.
+    // Force density rho*g + div sigma^{t-1} (sigma_yy = 0 in the simple-shear
+    // reduction, a third plane with the full tensor); d/dx periodic central,
+    // d/dy central with one-sided rows at the walls.
     const R *__restrict__ sxy = reinterpret_cast<const R *>(ws + c->off_sig);
     const R *__restrict__ sxx = sxy + np;
-    R dys;
-    if (y == 0)
-        dys = R(0.5) * (R(-3) * sxy[n] + R(4) * sxy[n + lx] - sxy[n + 2 * lx]);
-    else if (y == ly - 1)
-        dys = R(0.5) * (R(3) * sxy[n] - R(4) * sxy[n - lx] + sxy[n - 2 * lx]);
-    else
-        dys = R(0.5) * (sxy[n + lx] - sxy[n - lx]);
-    R fx = R(0.5) * (sxx[row + xp] - sxx[row + xm]) + dys;
+    auto ddy = [&](const R *__restrict__ f) {
+        if (y == 0)
+            return R(0.5) * (R(-3) * f[n] + R(4) * f[n + lx] - f[n + 2 * lx]);
+        if (y == ly - 1)
+            return R(0.5) * (R(3) * f[n] - R(4) * f[n - lx] + f[n - 2 * lx]);
+        return R(0.5) * (f[n + lx] - f[n - lx]);
+    };
+    R fx = R(0.5) * (sxx[row + xp] - sxx[row + xm]) + ddy(sxy);
     R fy = R(0.5) * (sxy[row + xp] - sxy[row + xm]);
+    if (c->finger)
+        fy += ddy(sxy + 2 * np);
     fx += rho * (R)c->gx;
     fy += rho * (R)c->gy;
 
@@ -291,8 +294,8 @@ __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
 // reads them as one V-wide vector per ring row.  Ages are walked newest to
 // oldest (the running FP64 strain gamma is a sum over the rows already
 // read); U rows are loaded before any is used so each wavefront keeps U (2U
-// with |gamma_dot|) vector reads in flight.  In FP32 the U terms of a row
-// group are added plainly and the group sum enters the Kahan accumulator.
+// with |gamma_dot|) vector reads in flight.  In FP32 the terms of F rows
+// are added plainly and their sum enters the FP64 accumulator.
 // ---------------------------------------------------------------------------
 template <typename R, int V>
 struct alignas(sizeof(R) * V) Pack {
@@ -625,6 +628,432 @@ __global__ __launch_bounds__(kBlock) void k_hist_pass_persistent(
 }
 
 // ---------------------------------------------------------------------------
+// Full-tensor Finger path (Eq. gitt with -d_t'B = E kappa E^T + transpose,
+// E(t, t') the ordered product of exp(kappa dt), Eq. eeval).
+//
+// Ring of a full-tensor channel: 8 planes [8][n_hist][np] -- kappa_xx,
+// kappa_xy, kappa_yx, kappa_yy of the entry, then g = exp(kappa dt) - I
+// row-major (formed once, in FP64, when the entry is pushed; kept apart from
+// the identity so FP32 storage keeps its precision).
+// Walking ages newest to oldest, E_k = E_{k-1} (I + g_k) in FP64 (E_0 = I:
+// the newest entry contributes no factor), and the entry's term is
+// P_k = E_k kappa_k E_k^T + transpose (symmetric: xx, xy, yy).  With the
+// damping unchanged, a pass at t0 forms for m = 0..M-1
+//   S_m = sum w(k+m) P_k E(k+m, r_k)
+// (E the damping factor as in the reduced path), and step t0 + m has
+//   sigma = G (E_m S_m E_m^T + terms of the entries pushed since t0),
+// E_m = E(t0 + m, t0): the deformation since the pass is a common left
+// factor of every older entry's deformation, so the blocking carries over.
+// A window split into age ranges keeps, per range, its sums and its total
+// product T_c; the combine forms sum_c O_c S_c O_c^T with O_c = T_0 ... T_{c-1}.
+// ---------------------------------------------------------------------------
+struct Mat2 {
+    double a, b, c, d;  // [[a, b], [c, d]]
+};
+
+__device__ __forceinline__ Mat2 mat_mul(const Mat2 &x, const Mat2 &y)
+{
+    return {fma(x.a, y.a, x.b * y.c), fma(x.a, y.b, x.b * y.d), fma(x.c, y.a, x.d * y.c),
+            fma(x.c, y.b, x.d * y.d)};
+}
+
+// E (I + g) = E + E g
+__device__ __forceinline__ Mat2 step_deformation(const Mat2 &E, double g00, double g01,
+                                                 double g10, double g11)
+{
+    return {fma(E.a, g00, fma(E.b, g10, E.a)), fma(E.a, g01, fma(E.b, g11, E.b)),
+            fma(E.c, g00, fma(E.d, g10, E.c)), fma(E.c, g01, fma(E.d, g11, E.d))};
+}
+
+// P = E k E^T + (E k E^T)^T as (xx, xy, yy)
+__device__ __forceinline__ void finger_term(const Mat2 &E, double kxx, double kxy, double kyx,
+                                            double kyy, double &pxx, double &pxy,
+                                            double &pyy)
+{
+    const double ea = fma(E.a, kxx, E.b * kyx), eb = fma(E.a, kxy, E.b * kyy);
+    const double ec = fma(E.c, kxx, E.d * kyx), ed = fma(E.c, kxy, E.d * kyy);
+    pxx = 2.0 * fma(ea, E.a, eb * E.b);
+    pxy = fma(ea, E.c, eb * E.d) + fma(ec, E.a, ed * E.b);
+    pyy = 2.0 * fma(ec, E.c, ed * E.d);
+}
+
+// S -> O S O^T for symmetric S = (xx, xy, yy)
+__device__ __forceinline__ void congruence(const Mat2 &O, double &sxx, double &sxy,
+                                           double &syy)
+{
+    const double xa = fma(O.a, sxx, O.b * sxy), xb = fma(O.a, sxy, O.b * syy);
+    const double xc = fma(O.c, sxx, O.d * sxy), xd = fma(O.c, sxy, O.d * syy);
+    const double nxx = fma(xa, O.a, xb * O.b);
+    const double nxy = fma(xa, O.c, xb * O.d);
+    const double nyy = fma(xc, O.c, xd * O.d);
+    sxx = nxx;
+    sxy = nxy;
+    syy = nyy;
+}
+
+// g = exp(K) - I for a 2x2 K (the velocity gradient of one step), formed
+// when an entry is pushed.
+// Cayley-Hamilton: with s = tr K / 2, h = (K_xx - K_yy)/2 and
+// q^2 = h^2 + K_xy K_yx (the eigenvalues are s +- q),
+//   exp(K) = e^s [cosh(q) I + sinh(q)/q (K - s I)],
+// so g_xx = e^s (c + S h) - 1, g_yy = e^s (c - S h) - 1, g_xy = e^s S K_xy,
+// g_yx = e^s S K_yx with c = cosh q, S = sinh(q)/q as even series in q^2 and
+// e^s - 1 as a series in s (no cancellation near K = 0).  The series cover
+// |s| <= 1/8 and |q^2| <= 1/64 to the working precision; a larger K is
+// halved j times first and the result squared back, g <- g (2 I + g).
+template <typename R>
+struct ExpTerms;
+template <>
+struct ExpTerms<float> {
+    static constexpr int kS = 7, kQ = 4;
+};
+template <>
+struct ExpTerms<double> {
+    static constexpr int kS = 13, kQ = 7;
+};
+
+template <typename R>
+__device__ __forceinline__ void expm1_2x2(R kxx, R kxy, R kyx, R kyy, R (&g)[4])
+{
+    R s = R(0.5) * (kxx + kyy), h = R(0.5) * (kxx - kyy);
+    R q2 = fused(h, h, kxy * kyx);
+    // halvings j with 64 max(s^2, |q^2|) 4^-j <= 1: with 64 max(..) < 2^e,
+    // j = ceil(e / 2) suffices
+    int j = 0;
+    const R m2 = R(64) * fmax(s * s, fabs(q2));
+    if (m2 > R(1)) {
+        int e;
+        (void)frexp(m2, &e);
+        j = (e + 1) >> 1;
+        const R sc = ldexp(R(1), -j);
+        s *= sc;
+        h *= sc;
+        kxy *= sc;
+        kyx *= sc;
+        q2 *= sc * sc;
+    }
+    // c - 1 = sum_{n>=1} q^{2n}/(2n)!,  S = sum_{n>=0} q^{2n}/(2n+1)!
+    R cm1 = R(0), S = R(1);
+    {
+        R tc = R(1), ts = R(1);
+#pragma unroll
+        for (int n = 1; n <= ExpTerms<R>::kQ; ++n) {
+            tc = tc * q2 * R(1.0 / ((2 * n - 1) * (2 * n)));
+            ts = ts * q2 * R(1.0 / ((2 * n) * (2 * n + 1)));
+            cm1 += tc;
+            S += ts;
+        }
+    }
+    // e^s - 1 = s (1 + s/2 (1 + s/3 (1 + ...)))
+    R em1 = R(1);
+#pragma unroll
+    for (int n = ExpTerms<R>::kS; n >= 2; --n)
+        em1 = fused(em1, s * R(1.0 / n), R(1));
+    em1 *= s;
+    const R es = em1 + R(1), sh = S * h;
+    // e^s (c +- S h) - 1 = em1 (c +- S h) + (c - 1) +- S h
+    g[0] = fused(em1, (cm1 + R(1)) + sh, cm1 + sh);
+    g[3] = fused(em1, (cm1 + R(1)) - sh, cm1 - sh);
+    g[1] = es * S * kxy;
+    g[2] = es * S * kyx;
+    for (; j > 0; --j) {
+        // (I + g)^2 - I = g (2 I + g)
+        const R a = g[0], b = g[1], c = g[2], d = g[3];
+        g[0] = fused(a, a, fused(b, c, R(2) * a));
+        g[1] = fused(b, a + d, R(2) * b);
+        g[2] = fused(c, a + d, R(2) * c);
+        g[3] = fused(d, d, fused(b, c, R(2) * d));
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R finger_rate(R kxx, R kxy, R kyx, R kyy)
+{
+    const R o = kxy + kyx;
+    return sqrt(R(2) * kxx * kxx + o * o + R(2) * kyy * kyy);
+}
+
+// An entry whose ages touch a window end: per-m weight and window membership.
+template <typename R, int M>
+__device__ __forceinline__ void finger_edge(double pxx, double pxy, double pyy, R rate, int k,
+                                            int H, Acc<R> (&X)[M], Acc<R> (&Y)[M],
+                                            Acc<R> (&Z)[M])
+{
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int a = k + m;
+        if (a <= H - 1) {
+            const R w = (a == 0 || a == H - 1) ? R(0.5) : R(1);
+            const R e = w * decay_pow(R(a), rate);
+            X[m].add(e * (R)pxx);
+            Y[m].add(e * (R)pxy);
+            Z[m].add(e * (R)pyy);
+        }
+    }
+}
+
+// U interior rows starting at ring slot `slot`, age kf0: advance E, add the
+// terms into the FP32 partials (FIRST starts them).
+template <typename R, int M, int U, bool FIRST>
+__device__ __forceinline__ void finger_rows(const R *__restrict__ ring, size_t hplane, size_t np,
+                                            int node, int slot, int kf0, const Decay<R> &dec,
+                                            Mat2 &E, R (&px)[M], R (&py)[M], R (&pz)[M])
+{
+#pragma clang fp contract(off)
+    R v[U][8];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const size_t row = (size_t)(slot - u) * np + node;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            v[u][q] = ring[q * hplane + row];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        E = step_deformation(E, (double)v[u][4], (double)v[u][5], (double)v[u][6],
+                             (double)v[u][7]);
+        double pxx, pxy, pyy;
+        finger_term(E, (double)v[u][0], (double)v[u][1], (double)v[u][2], (double)v[u][3], pxx,
+                    pxy, pyy);
+        const R rate = decay_rate<R>(dec, finger_rate<R>(v[u][0], v[u][1], v[u][2], v[u][3]));
+        R x = decay_pow(R(kf0 + u), rate);
+        R q = R(1);
+        if (M > 1)
+            q = decay_pow(R(1), rate);
+        const R fx = (R)pxx, fy = (R)pxy, fz = (R)pyy;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            if (FIRST && u == 0) {
+                px[m] = x * fx;
+                py[m] = x * fy;
+                pz[m] = x * fz;
+            } else {
+                px[m] = fused(x, fx, px[m]);
+                py[m] = fused(x, fy, py[m]);
+                pz[m] = fused(x, fz, pz[m]);
+            }
+            if (m + 1 < M)
+                x *= q;
+        }
+    }
+}
+
+template <typename R, int M>
+__device__ __forceinline__ void finger_flush(const R (&px)[M], const R (&py)[M],
+                                             const R (&pz)[M], Acc<R> (&X)[M], Acc<R> (&Y)[M],
+                                             Acc<R> (&Z)[M])
+{
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        X[m].add(px[m]);
+        Y[m].add(py[m]);
+        Z[m].add(pz[m]);
+    }
+}
+
+// Gradient of this step at a node and its push into the full-tensor ring.
+template <typename P, typename R>
+__device__ __forceinline__ void finger_push(char *__restrict__ ws, const ChanDev *c, int node,
+                                            int slot, P &kxx, P &kxy, P &kyx, P &kyy)
+{
+    const size_t np = (size_t)c->np;
+    const P *vel = reinterpret_cast<const P *>(ws + c->off_vel);
+    const int y = node / c->lx, x = node - y * c->lx;
+    velocity_gradient<P>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
+    R *ring = reinterpret_cast<R *>(ws + c->off_ring_s);
+    const size_t hplane = (size_t)c->n_hist * np, row = (size_t)slot * np + node;
+    double g[4];
+    expm1_2x2<double>((double)kxx, (double)kxy, (double)kyx, (double)kyy, g);
+    ring[0 * hplane + row] = (R)kxx;
+    ring[1 * hplane + row] = (R)kxy;
+    ring[2 * hplane + row] = (R)kyx;
+    ring[3 * hplane + row] = (R)kyy;
+    for (int q = 0; q < 4; ++q)
+        ring[(4 + q) * hplane + row] = (R)g[q];
+}
+
+// One tile of a full-tensor channel: 256 nodes (one per lane), ages [k0, k1).
+template <typename P, typename R, int M, int U, int F>
+__device__ __forceinline__ void finger_tile(char *__restrict__ ws, const ChanDev *c,
+                                            const HistTile &tl, int64_t t)
+{
+    static_assert(F % U == 0, "flush length must be a multiple of the row group");
+    const int H = c->n_hist;
+    const size_t np = (size_t)c->np, hplane = (size_t)H * np;
+    const int first = tl.n0 + (int)threadIdx.x;
+    const int node = first < c->n ? first : c->n - 1;  // shadow lanes past the end
+    const int p = (int)(t % H);
+    const R *ring = reinterpret_cast<const R *>(ws + c->off_ring_s);
+    const Decay<R> dec(c);
+    Acc<R> X[M], Y[M], Z[M];
+    Mat2 E = {1.0, 0.0, 0.0, 1.0};
+    int k = tl.k0;
+    if (k == 0) {
+        P kxx = P(0), kxy = P(0), kyx = P(0), kyy = P(0);
+        if (first < c->n)
+            finger_push<P, R>(ws, c, node, p, kxx, kxy, kyx, kyy);
+        // age 0: E = I, P = kappa + kappa^T
+        const R rate = decay_rate<R>(dec, finger_rate<R>((R)kxx, (R)kxy, (R)kyx, (R)kyy));
+        finger_edge<R, M>(2.0 * (double)(R)kxx, (double)(R)kxy + (double)(R)kyx,
+                          2.0 * (double)(R)kyy, rate, 0, H, X, Y, Z);
+        k = 1;
+    }
+    // interior ages, then those whose k + m reaches the window end
+    const int tail0 = max(k, H - M);
+    const int kend = min(tl.k1, tail0);
+    int slot = p - k;
+    if (slot < 0)
+        slot += H;
+    R px[M], py[M], pz[M];
+    while (k < kend) {
+        const int run = min(kend - k, slot + 1);
+        int j = 0;
+        for (; j + F <= run; j += F) {
+            finger_rows<R, M, U, true>(ring, hplane, np, node, slot - j, k + j, dec, E, px, py,
+                                       pz);
+            for (int gq = U; gq < F; gq += U)
+                finger_rows<R, M, U, false>(ring, hplane, np, node, slot - j - gq, k + j + gq,
+                                            dec, E, px, py, pz);
+            finger_flush<R, M>(px, py, pz, X, Y, Z);
+        }
+        for (; j < run; ++j) {
+            finger_rows<R, M, 1, true>(ring, hplane, np, node, slot - j, k + j, dec, E, px, py,
+                                       pz);
+            finger_flush<R, M>(px, py, pz, X, Y, Z);
+        }
+        k += run;
+        slot = H - 1;
+    }
+    for (int kk = max(k, tail0); kk < tl.k1; ++kk) {
+        int sl = p - kk;
+        if (sl < 0)
+            sl += H;
+        const size_t row = (size_t)sl * np + node;
+        R v[8];
+        for (int q = 0; q < 8; ++q)
+            v[q] = ring[q * hplane + row];
+        E = step_deformation(E, (double)v[4], (double)v[5], (double)v[6], (double)v[7]);
+        double pxx, pxy, pyy;
+        finger_term(E, (double)v[0], (double)v[1], (double)v[2], (double)v[3], pxx, pxy, pyy);
+        const R rate = decay_rate<R>(dec, finger_rate<R>(v[0], v[1], v[2], v[3]));
+        finger_edge<R, M>(pxx, pxy, pyy, rate, kk, H, X, Y, Z);
+    }
+    if (first >= c->n)
+        return;
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    double *part = reinterpret_cast<double *>(ws + c->off_part);
+    double *blk = reinterpret_cast<double *>(ws + c->off_blk);
+    if (c->nchunks == 1) {
+        sig[first] = (P)(c->g_inf * Y[0].value());
+        sig[np + first] = (P)(c->g_inf * X[0].value());
+        sig[2 * np + first] = (P)(c->g_inf * Z[0].value());
+#pragma unroll
+        for (int m = 1; m < M; ++m) {
+            blk[m * np + first] = X[m].value();
+            blk[(kMaxBlock + m) * np + first] = Y[m].value();
+            blk[(2 * kMaxBlock + m) * np + first] = Z[m].value();
+        }
+    } else {
+        const size_t pplane = (size_t)c->max_chunks * np, at = (size_t)tl.chunk * np + first;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            part[m * pplane + at] = X[m].value();
+            part[(kMaxBlock + m) * pplane + at] = Y[m].value();
+            part[(2 * kMaxBlock + m) * pplane + at] = Z[m].value();
+        }
+        part[(3 * kMaxBlock + 0) * pplane + at] = E.a;
+        part[(3 * kMaxBlock + 1) * pplane + at] = E.b;
+        part[(3 * kMaxBlock + 2) * pplane + at] = E.c;
+        part[(3 * kMaxBlock + 3) * pplane + at] = E.d;
+    }
+}
+
+template <typename P, typename R, int M, int U, int F>
+__global__ __launch_bounds__(kBlock) void k_finger_pass(char *__restrict__ ws,
+                                                        const ChanDev *__restrict__ chans,
+                                                        const HistTile *__restrict__ tiles,
+                                                        const int64_t *__restrict__ tcount,
+                                                        int trel)
+{
+    const HistTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    if (tl.n0 + (int)(threadIdx.x & ~63u) >= c->n)
+        return;
+    finger_tile<P, R, M, U, F>(ws, c, tl, *tcount + trel);
+}
+
+template <typename P, typename R, int M, int U, int F>
+__global__ __launch_bounds__(kBlock) void k_finger_pass_persistent(
+    char *__restrict__ ws, const ChanDev *__restrict__ chans,
+    const HistTile *__restrict__ tiles, int n_tiles, const int64_t *__restrict__ tcount,
+    int trel, int *__restrict__ counter)
+{
+    __shared__ int claimed;
+    const int64_t t = *tcount + trel;
+    for (;;) {
+        if (threadIdx.x == 0)
+            claimed = atomicAdd(counter, 1);
+        __syncthreads();
+        const int i = claimed;
+        __syncthreads();
+        if (i >= n_tiles)
+            break;
+        const HistTile tl = tiles[i];
+        const ChanDev *c = chans + tl.ch;
+        if (tl.n0 + (int)(threadIdx.x & ~63u) < c->n)
+            finger_tile<P, R, M, U, F>(ws, c, tl, t);
+    }
+}
+
+// In-block step m of a full-tensor channel (called from k_hist_step).
+template <typename P, typename R>
+__device__ __forceinline__ void finger_step(char *__restrict__ ws, const ChanDev *c, int n,
+                                            int64_t t, int m)
+{
+    const int H = c->n_hist;
+    const size_t np = (size_t)c->np, hplane = (size_t)H * np;
+    const int p = (int)(t % H);
+    P kxx, kxy, kyx, kyy;
+    finger_push<P, R>(ws, c, n, p, kxx, kxy, kyx, kyy);
+    const R *ring = reinterpret_cast<const R *>(ws + c->off_ring_s);
+    const Decay<R> dec(c);
+    // newest entry: age 0, weight 1/2, E = I
+    double sxx = (double)(R)kxx, sxy = 0.5 * ((double)(R)kxy + (double)(R)kyx),
+           syy = (double)(R)kyy;
+    Mat2 E = {1.0, 0.0, 0.0, 1.0};
+    int slot = p;
+    for (int a = 1; a <= m; ++a) {
+        slot = slot == 0 ? H - 1 : slot - 1;
+        const size_t row = (size_t)slot * np + n;
+        R v[8];
+        for (int q = 0; q < 8; ++q)
+            v[q] = ring[q * hplane + row];
+        E = step_deformation(E, (double)v[4], (double)v[5], (double)v[6], (double)v[7]);
+        if (a < m && a <= H - 1) {
+            double pxx, pxy, pyy;
+            finger_term(E, (double)v[0], (double)v[1], (double)v[2], (double)v[3], pxx, pxy,
+                        pyy);
+            const R rate = decay_rate<R>(dec, finger_rate<R>(v[0], v[1], v[2], v[3]));
+            const double w = (a == H - 1) ? 0.5 : 1.0;
+            const double e = w * (double)decay_pow(R(a), rate);
+            sxx += e * pxx;
+            sxy += e * pxy;
+            syy += e * pyy;
+        }
+    }
+    // E is now E(t, t0): carry the pass's sums forward
+    const double *blk = reinterpret_cast<const double *>(ws + c->off_blk);
+    double bxx = blk[m * np + n], bxy = blk[(kMaxBlock + m) * np + n],
+           byy = blk[(2 * kMaxBlock + m) * np + n];
+    congruence(E, bxx, bxy, byy);
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    sig[n] = (P)(c->g_inf * (sxy + bxy));
+    sig[np + n] = (P)(c->g_inf * (sxx + bxx));
+    sig[2 * np + n] = (P)(c->g_inf * (syy + byy));
+}
+
+// ---------------------------------------------------------------------------
 // FP64 combine of the per-chunk partials of a split window, newest chunk
 // first: A_m = sum_c A_{m,c}, B_m = sum_c (2 O_c A_{m,c} + B_{m,c}), where
 // O_c = sum of the strain totals T of the newer chunks (the accumulated
@@ -645,6 +1074,40 @@ __global__ __launch_bounds__(kBlock) void k_combine(char *__restrict__ ws,
     const size_t np = (size_t)c->np;
     const size_t pplane = (size_t)c->max_chunks * np;
     const double *part = reinterpret_cast<const double *>(ws + c->off_part);
+    if (c->finger) {
+        // sum_c O_c S_c O_c^T, O_0 = I, O_{c+1} = O_c T_c
+        double X[kMaxBlock], Y[kMaxBlock], Z[kMaxBlock];
+        for (int m = 0; m < block; ++m)
+            X[m] = Y[m] = Z[m] = 0.0;
+        Mat2 O = {1.0, 0.0, 0.0, 1.0};
+        for (int k = 0; k < c->nchunks; ++k) {
+            const size_t at = (size_t)k * np + n;
+            for (int m = 0; m < block; ++m) {
+                double sx = part[m * pplane + at], sy = part[(kMaxBlock + m) * pplane + at],
+                       sz = part[(2 * kMaxBlock + m) * pplane + at];
+                congruence(O, sx, sy, sz);
+                X[m] += sx;
+                Y[m] += sy;
+                Z[m] += sz;
+            }
+            const Mat2 T = {part[(3 * kMaxBlock + 0) * pplane + at],
+                            part[(3 * kMaxBlock + 1) * pplane + at],
+                            part[(3 * kMaxBlock + 2) * pplane + at],
+                            part[(3 * kMaxBlock + 3) * pplane + at]};
+            O = mat_mul(O, T);
+        }
+        P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+        sig[n] = (P)(c->g_inf * Y[0]);
+        sig[np + n] = (P)(c->g_inf * X[0]);
+        sig[2 * np + n] = (P)(c->g_inf * Z[0]);
+        double *blk = reinterpret_cast<double *>(ws + c->off_blk);
+        for (int m = 1; m < block; ++m) {
+            blk[m * np + n] = X[m];
+            blk[(kMaxBlock + m) * np + n] = Y[m];
+            blk[(2 * kMaxBlock + m) * np + n] = Z[m];
+        }
+        return;
+    }
     double A[kMaxBlock], B[kMaxBlock];
     for (int m = 0; m < block; ++m)
         A[m] = B[m] = 0.0;
@@ -687,6 +1150,10 @@ __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
     if (c->qb != 0 || n >= c->n)
         return;  // grid channels step in k_grid_step
     const int64_t t = *tcount + trel;
+    if (c->finger) {
+        finger_step<P, R>(ws, c, n, t, m);
+        return;
+    }
     const int H = c->n_hist;
     const size_t np = (size_t)c->np;
     const int p = (int)(t % H);
@@ -883,7 +1350,8 @@ __global__ __launch_bounds__(kBlock) void k_readout(int which, const char *__res
     } else if (which == 1) {
         const R *sig = reinterpret_cast<const R *>(ws + c->off_sig);
         out[n] = (double)sig[n];
-        out[N + n] = (double)sig[np + n];  // N1 = sigma_xx - sigma_yy, sigma_yy = 0
+        // N1 = sigma_xx - sigma_yy (sigma_yy = 0 in the simple-shear reduction)
+        out[N + n] = (double)sig[np + n] - (c->finger ? (double)sig[2 * np + n] : 0.0);
     } else {
         const R *vel = reinterpret_cast<const R *>(ws + c->off_vel);
         const int y = n / c->lx, x = n - y * c->lx;
@@ -1018,6 +1486,63 @@ int hist_pass_blocks_per_cu(int prec, int vec, int block)
     LBMAX_BY_PREC(prec, LBMAX_OCC_SHAPES);
 #undef LBMAX_OCC_SHAPES
 #undef LBMAX_OCC
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+// Shapes of the full-tensor pass: (steps per pass M, rows per group U, rows
+// per FP64 flush F); three sums per step limit the block to 16 steps.
+#define LBMAX_FINGER_SHAPE_TABLE(block, X)                                      \
+    do {                                                                         \
+        if (block == 1)                                                          \
+            X(1, 8, 8);                                                          \
+        else if (block == 2)                                                     \
+            X(2, 4, 8);                                                          \
+        else if (block == 4)                                                     \
+            X(4, 4, 8);                                                          \
+        else if (block == 8)                                                     \
+            X(8, 4, 16);                                                         \
+        else                                                                     \
+            X(16, 2, 16);                                                        \
+    } while (0)
+
+void launch_finger_pass(int prec, int block, char *ws, const ChanDev *chans,
+                        const HistTile *tiles, int n_tiles, const int64_t *tcount, int trel,
+                        int persistent_grid, int *counter, hipStream_t st)
+{
+    if (n_tiles <= 0)
+        return;
+    const int grid = persistent_grid > 0 ? std::min(persistent_grid, n_tiles) : n_tiles;
+#define LBMAX_FPASS(M, U, F)                                                     \
+    do {                                                                         \
+        if (persistent_grid > 0)                                                 \
+            hipLaunchKernelGGL((k_finger_pass_persistent<P, H, M, U, F>), dim3(grid), \
+                               dim3(kBlock), 0, st, ws, chans, tiles, n_tiles,   \
+                               tcount, trel, counter);                           \
+        else                                                                     \
+            hipLaunchKernelGGL((k_finger_pass<P, H, M, U, F>), dim3(grid),       \
+                               dim3(kBlock), 0, st, ws, chans, tiles, tcount,    \
+                               trel);                                            \
+    } while (0)
+#define LBMAX_FPASS_SHAPES LBMAX_FINGER_SHAPE_TABLE(block, LBMAX_FPASS)
+    LBMAX_BY_PREC(prec, LBMAX_FPASS_SHAPES);
+#undef LBMAX_FPASS_SHAPES
+#undef LBMAX_FPASS
+}
+
+int finger_pass_blocks_per_cu(int prec, int block)
+{
+    int n = 0;
+    hipError_t e = hipSuccess;
+#define LBMAX_FOCC(M, U, F)                                                          \
+    do {                                                                             \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                            \
+            &n, reinterpret_cast<const void *>(&k_finger_pass_persistent<P, H, M, U, F>), \
+            kBlock, 0);                                                              \
+    } while (0)
+#define LBMAX_FOCC_SHAPES LBMAX_FINGER_SHAPE_TABLE(block, LBMAX_FOCC)
+    LBMAX_BY_PREC(prec, LBMAX_FOCC_SHAPES);
+#undef LBMAX_FOCC_SHAPES
+#undef LBMAX_FOCC
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 

@@ -29,7 +29,7 @@ lb_status fail(lb_status s, const std::string &msg)
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr uint64_t kStateMagic = 0x4C424D4158535431ull;  // "LBMAXST1"
-constexpr uint32_t kStateVersion = 2;
+constexpr uint32_t kStateVersion = 3;
 constexpr size_t kStateHeader = 256;
 constexpr int64_t kMaxStepsPerBatch = int64_t(1) << 20;
 
@@ -79,6 +79,10 @@ std::string check_desc(const lb_channel_desc *ch, int32_t n_ch)
             return bad("hist_blocks must be >= 0");
         if (d.hist_blocks == 0 && d.n_hist < 2)
             return bad("n_hist must be >= 2");
+        if (d.finger != 0 && d.finger != 1)
+            return bad("finger must be 0 or 1");
+        if (d.finger && d.hist_blocks > 0)
+            return bad("the full Finger tensor runs on the uniform window (hist_blocks = 0)");
         if (d.hist_blocks > 0) {
             if (d.hist_blocks > 20)
                 return bad("hist_blocks must be <= 20");
@@ -148,10 +152,11 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         c.ly = d.ly;
         c.n = d.lx * d.ly;
         c.np = (int)align_up((size_t)c.n, kNodeAlign);
+        c.finger = d.finger;
         c.qb = d.hist_blocks;
         c.qc = d.hist_blocks > 0 ? d.hist_block_len : 0;
         c.n_hist = d.hist_blocks > 0 ? 0 : d.n_hist;
-        c.has_r = unidirectional(d) ? 0 : 1;
+        c.has_r = (unidirectional(d) && !d.finger) ? 0 : 1;
         c.max_chunks = d.hist_blocks > 0 ? 1 : max_chunks_for(d.n_hist, c.np);
         c.nchunks = 1;
         c.vec = 1;
@@ -182,23 +187,25 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         c.off_pop = (int64_t)off;
         off = align_up(off + 18 * plane, 256);
         c.off_sig = (int64_t)off;
-        off = align_up(off + 2 * plane, 256);
+        off = align_up(off + 3 * plane, 256);
         c.off_vel = (int64_t)off;
         off = align_up(off + 2 * plane, 256);
         c.off_rho = (int64_t)off;
         off = align_up(off + plane, 256);
         const size_t hplane = (size_t)c.np * RH;
         c.off_ring_s = (int64_t)off;
-        off = align_up(off + (size_t)c.n_hist * hplane, 256);
+        off = align_up(off + (c.finger ? 8 : 1) * (size_t)c.n_hist * hplane, 256);
         c.off_ring_r = (int64_t)off;
-        if (c.has_r)
+        if (c.has_r && !c.finger)
             off = align_up(off + (size_t)c.n_hist * hplane, 256);
         c.off_part = (int64_t)off;
         if (c.max_chunks > 1)
-            off = align_up(off + (size_t)kPartPlanes * c.max_chunks * c.np * sizeof(double),
+            off = align_up(off + (size_t)(c.finger ? kFingerPartPlanes : kPartPlanes) *
+                                     c.max_chunks * c.np * sizeof(double),
                            256);
         c.off_blk = (int64_t)off;
-        off = align_up(off + (size_t)2 * kMaxBlock * c.np * sizeof(double), 256);
+        off = align_up(off + (size_t)(c.finger ? 3 : 2) * kMaxBlock * c.np * sizeof(double),
+                       256);
         const size_t grows = (size_t)c.qb * c.qc;  // 0 without a grid
         c.off_grid_s = (int64_t)off;
         off = align_up(off + grows * hplane, 256);
@@ -239,7 +246,9 @@ struct lb_handle {
     HistTile *d_hist_tiles = nullptr;
     double *d_stage = nullptr;
     int n_node_tiles = 0, n_hist_tiles = 0;
-    int hist_group_begin[3] = {0, 0, 0}, hist_group_count[3] = {0, 0, 0};  // vec 1, 2, 4
+    // history tile groups: lane width 1, 2, 4 (simple-shear pass), full tensor
+    int hist_group_begin[4] = {0, 0, 0, 0}, hist_group_count[4] = {0, 0, 0, 0};
+    bool any_finger = false;
     bool any_chunked = false;
     bool any_grid = false, any_window = false;  // channels on the grid / the uniform window
     // host mirrors kept alive for asynchronous uploads
@@ -330,7 +339,7 @@ void build_tiles(lb_handle *h)
         h->any_window = true;
         if (c.nchunks > 1)
             h->any_chunked = true;
-        const int span = kBlock * effective_vec(c.vec, h->block);
+        const int span = kBlock * (c.finger ? 1 : effective_vec(c.vec, h->block));
         for (int k = 0; k < c.nchunks; ++k) {
             const int k0 = (int)((int64_t)c.n_hist * k / c.nchunks);
             const int k1 = (int)((int64_t)c.n_hist * (k + 1) / c.nchunks);
@@ -341,6 +350,8 @@ void build_tiles(lb_handle *h)
     // Group by lane width (one launch each), longest age range first inside
     // a group.
     auto group = [h](const HistTile &a) {
+        if (h->plan.chans[a.ch].finger)
+            return 3;
         const int v = effective_vec(h->plan.chans[a.ch].vec, h->block);
         return v == 4 ? 2 : (v == 2 ? 1 : 0);
     };
@@ -350,13 +361,15 @@ void build_tiles(lb_handle *h)
                              return group(a) < group(b);
                          return (a.k1 - a.k0) > (b.k1 - b.k0);
                      });
-    for (int g = 0; g < 3; ++g)
+    for (int g = 0; g < 4; ++g)
         h->hist_group_count[g] = 0;
     for (const HistTile &tl : h->hist_tiles)
         h->hist_group_count[group(tl)] += 1;
     h->hist_group_begin[0] = 0;
     h->hist_group_begin[1] = h->hist_group_count[0];
     h->hist_group_begin[2] = h->hist_group_count[0] + h->hist_group_count[1];
+    h->hist_group_begin[3] = h->hist_group_begin[2] + h->hist_group_count[2];
+    h->any_finger = h->hist_group_count[3] > 0;
     h->n_node_tiles = (int)h->node_tiles.size();
     h->n_hist_tiles = (int)h->hist_tiles.size();
 }
@@ -455,6 +468,13 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
                              h->d_hist_tiles + h->hist_group_begin[g], h->hist_group_count[g],
                              h->d_tcount, trel, pgrid, h->d_tile_counters + g, st);
         }
+        if (h->any_finger) {
+            const int pgrid =
+                h->persistent ? h->num_cus * finger_pass_blocks_per_cu(h->pc, h->block) : 0;
+            launch_finger_pass(h->pc, h->block, h->ws, h->d_chans,
+                               h->d_hist_tiles + h->hist_group_begin[3], h->hist_group_count[3],
+                               h->d_tcount, trel, pgrid, h->d_tile_counters + 3, st);
+        }
         if (h->any_chunked)
             launch_combine(h->pc, h->block, h->ws, h->d_chans, h->d_node_tiles,
                            h->n_node_tiles, st);
@@ -541,7 +561,7 @@ std::vector<Section> state_sections(const lb_handle *h, int ci, int64_t t)
     const int64_t cur = c.off_pop + (int64_t)(((t + 1) & 1) * 9 * pitch);
     std::vector<Section> v;
     v.push_back({cur, 9, rowb, pitch});
-    v.push_back({c.off_sig, 2, rowb, pitch});
+    v.push_back({c.off_sig, 3, rowb, pitch});
     v.push_back({c.off_vel, 2, rowb, pitch});
     v.push_back({c.off_rho, 1, rowb, pitch});
     if (c.qb > 0) {
@@ -551,12 +571,14 @@ std::vector<Section> state_sections(const lb_handle *h, int ci, int64_t t)
             v.push_back({c.off_grid_r, grows, hrowb, hpitch});
             v.push_back({c.off_grid_d, 3 * grows, hrowb, hpitch});
         }
+    } else if (c.finger) {
+        v.push_back({c.off_ring_s, 8 * (size_t)c.n_hist, hrowb, hpitch});
     } else {
         v.push_back({c.off_ring_s, (size_t)c.n_hist, hrowb, hpitch});
         if (c.has_r)
             v.push_back({c.off_ring_r, (size_t)c.n_hist, hrowb, hpitch});
     }
-    v.push_back({c.off_blk, (size_t)2 * kMaxBlock, (size_t)c.n * sizeof(double),
+    v.push_back({c.off_blk, (size_t)(c.finger ? 3 : 2) * kMaxBlock, (size_t)c.n * sizeof(double),
                  (size_t)c.np * sizeof(double)});
     return v;
 }
@@ -623,6 +645,9 @@ std::string adjoint_unsupported(const lb_handle *h, int seg_len)
         if (c.qb > 0)
             return "the adjoint covers the uniform history window; channel " +
                    std::to_string(ci) + " uses the quasi-logarithmic grid";
+        if (c.finger)
+            return "the adjoint covers the simple-shear reduction; channel " +
+                   std::to_string(ci) + " uses the full Finger tensor";
         if (c.lx != 1 || c.has_r)
             return "the adjoint covers unidirectional channels (lx = 1, gy = 0, u0_y = 0); "
                    "channel " + std::to_string(ci) + " is not";
@@ -989,6 +1014,9 @@ lb_status lb_set_block(lb_handle *h, int32_t steps_per_pass)
         return fail(LB_EINVAL, "steps_per_pass must be 1, 2, 4, 8, 16 or 32");
     if (h->graph_steps % steps_per_pass != 0)
         return fail(LB_EINVAL, "the graph length must stay a multiple of the block length");
+    for (const ChanDev &c : h->plan.chans)
+        if (c.finger && steps_per_pass > kMaxFingerBlock)
+            return fail(LB_EINVAL, "full-tensor channels take at most 16 steps per pass");
     h->block = steps_per_pass;
     h->block_pos = 0;  // the next step starts a block with a fresh pass
     h->graph_dirty = true;

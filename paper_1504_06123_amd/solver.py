@@ -28,7 +28,8 @@ def _precision_code(precision: str) -> int:
 def make_descs(channels: Sequence) -> tuple:
     """Fill lb_channel_desc records from objects with the channel attributes
     (lx, ly, tau_lb, g_inf, tau_m, gamma_c, n_hist, gx, gy, u0, and optionally
-    hist_blocks, hist_block_len for the quasi-logarithmic grid).  Returns the
+    hist_blocks, hist_block_len for the quasi-logarithmic grid and finger for
+    the full Finger tensor).  Returns the
     ctypes array and the list of u0 buffers it points into (keep alive)."""
     n = len(channels)
     arr = (_lib.ChannelDesc * n)()
@@ -42,6 +43,7 @@ def make_descs(channels: Sequence) -> tuple:
         d.gx, d.gy = float(ch.gx), float(getattr(ch, "gy", 0.0))
         d.hist_blocks = int(getattr(ch, "hist_blocks", 0))
         d.hist_block_len = int(getattr(ch, "hist_block_len", 0)) if d.hist_blocks else 0
+        d.finger = 1 if getattr(ch, "finger", False) else 0
         u0 = getattr(ch, "u0", None)
         if u0 is not None:
             buf = np.ascontiguousarray(np.asarray(u0, dtype=np.float64).reshape(2, ch.ly, ch.lx))
@@ -207,7 +209,7 @@ class Solver:
 
 
 STATE_MAGIC = 0x4C424D4158535431
-STATE_VERSION = 2
+STATE_VERSION = 3
 
 
 def pack_state_header(t: int, n_ch: int, precision: str, total_bytes: int,
@@ -236,7 +238,8 @@ def state_layout(channels: Sequence, precision: str = "f32"):
                (getattr(ch, "u0", None) is None or
                 not np.any(np.asarray(ch.u0, dtype=np.float64).reshape(2, -1)[1])))
         sec = {}
-        for name, rows in (("pop", 9), ("sig", 2), ("vel", 2), ("drho", 1)):
+        finger = bool(getattr(ch, "finger", False))
+        for name, rows in (("pop", 9), ("sig", 3), ("vel", 2), ("drho", 1)):
             sec[name] = (off, rows, N)
             off = up(off + rows * N * R)
         B = int(getattr(ch, "hist_blocks", 0))
@@ -245,12 +248,16 @@ def state_layout(channels: Sequence, precision: str = "f32"):
             for name, k in (("grid_s", 1),) + (() if uni else (("grid_r", 1), ("grid_d", 3))):
                 sec[name] = (off, k * rows, N)
                 off = up(off + k * rows * N * RH)
+        elif finger:
+            sec["ring"] = (off, 8 * int(ch.n_hist), N)
+            off = up(off + 8 * int(ch.n_hist) * N * RH)
         else:
             for name in ("ring_s",) + (() if uni else ("ring_r",)):
                 sec[name] = (off, int(ch.n_hist), N)
                 off = up(off + int(ch.n_hist) * N * RH)
-        sec["blk"] = (off, 64, N)   # doubles
-        off = up(off + 64 * N * 8)
+        nblk = 96 if finger else 64
+        sec["blk"] = (off, nblk, N)   # doubles
+        off = up(off + nblk * N * 8)
         sec["force"] = (off, 1, 2)
         off = up(off + 16)
         out.append(sec)
