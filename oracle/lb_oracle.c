@@ -38,6 +38,11 @@
  * product (Eq. eeval) and -d_t' B = E kappa E^T + (E kappa E^T)^T; then
  * sigma_yy enters the force and N1 = sigma_xx - sigma_yy.  State exchange
  * (orc_get/set_state) covers the uniform window of the reduced path only.
+ * With orc_set_paper_coupling() the stress reaches the fluid through the
+ * paper's own forcing term (Eq. bodyforce in full): the traceless part in the
+ * second moment of F_i, the trace through d_t delta rho = -(tr sigma^{t-1} -
+ * tr sigma^{t-2}) / (2 cs2), rho = sum n + d_t rho / 2 and f = rho g only
+ * (Eq. hydrofields) -- instead of the body force div sigma.
  *
  * Parity status: every function below is pinned by the CPU test suite
  * (closed forms, moment identities, polynomial exactness, recursion
@@ -123,6 +128,34 @@ void orc_force_term(double tau_lb, double ux, double uy, double fx, double fy,
 /* Step 7: BGK collision plus forcing (Sec. III):                             */
 /*   n*_i = n_i - (n_i - n_i^eq(rho,u)) / tau_LB + F_i.                      */
 /* ------------------------------------------------------------------------ */
+/* The paper's own forcing term, Eq. bodyforce in full: the traceless       */
+/* non-Newtonian stress sbar (xx, xy, yy) enters the second moment, the      */
+/* density rate dr = d_t delta rho (with dt = 1) carries its trace:          */
+/*   F_i = a_i { -sbar:(c c - cs2 I) / (2 cs2^2 tau)                          */
+/*         + (1 - 1/(2 tau)) [ dr + c.f / cs2                                 */
+/*           + (c c - cs2 I):(-dr u u + u f + f u) / (2 cs2^2) ] }.           */
+void orc_force_term_paper(double tau_lb, double ux, double uy, double fx,
+                          double fy, const double *sbar, double dr, double *F)
+{
+    double u[2] = {ux, uy};
+    double f[2] = {fx, fy};
+    double S[2][2] = {{sbar[0], sbar[1]}, {sbar[1], sbar[2]}};
+    double pre = 1.0 - 1.0 / (2.0 * tau_lb);
+    for (int i = 0; i < 9; ++i) {
+        double c[2] = {(double)CX[i], (double)CY[i]};
+        double stress = 0.0, quad = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                double q = c[a] * c[b] - (a == b ? CS2 : 0.0);
+                stress += S[a][b] * q;
+                quad += q * (-dr * u[a] * u[b] + u[b] * f[a] + u[a] * f[b]);
+            }
+        double lin = (c[0] * f[0] + c[1] * f[1]) / CS2;
+        F[i] = WT[i] * (-stress / (2.0 * CS2 * CS2 * tau_lb) +
+                        pre * (dr + lin + quad / (2.0 * CS2 * CS2)));
+    }
+}
+
 void orc_collide(double tau_lb, const double *n, double rho, double ux,
                  double uy, double fx, double fy, double *nstar)
 {
@@ -603,6 +636,8 @@ typedef struct orc_channel {
     double *ring_k;  /* [n_hist][4][N] kxx, kxy, kyx, kyy of t' */
     double *ring_f;  /* [n_hist][4][N] exp(kappa(t') dt), row-major 2x2 */
     double *sig_yy;  /* [N] sigma_yy of the last completed step (full tensor) */
+    int paper_coupling; /* 1: stress through Eq. bodyforce instead of div sigma */
+    double *tr_prev; /* [N] trace of sigma two steps back (paper coupling) */
     double *new_yy;
     /* outputs of the last completed step */
     double *rho_o, *ux_o, *uy_o, *kap_o; /* kap_o: [4][N] kxx,kxy,kyx,kyy */
@@ -684,6 +719,7 @@ void orc_destroy(orc_channel *c)
     }
     free(c->ring_k);
     free(c->ring_f);
+    free(c->tr_prev);
     free(c->sig_yy);
     free(c->new_yy);
     free(c);
@@ -726,6 +762,27 @@ int orc_set_finger(orc_channel *c)
     return 0;
 }
 
+/* Enter the stress through the paper's forcing term (Eq. bodyforce:       */
+/* traceless part in the second moment, trace through d_t delta rho)        */
+/* instead of the body force div sigma (before the first step).              */
+int orc_set_paper_coupling(orc_channel *c)
+{
+    if (c->t != 0 || c->paper_coupling)
+        return -1;
+    c->paper_coupling = 1;
+    c->tr_prev = zalloc((size_t)c->N);
+    return 0;
+}
+
+/* Trace of sigma two steps back (the paper coupling's state); n = N.       */
+int orc_trace_prev(const orc_channel *c, double *out)
+{
+    if (!c->paper_coupling)
+        return -1;
+    memcpy(out, c->tr_prev, sizeof(double) * (size_t)c->N);
+    return 0;
+}
+
 long orc_time(const orc_channel *c) { return c->t; }
 
 static void one_step(orc_channel *c)
@@ -742,6 +799,24 @@ static void one_step(orc_channel *c)
             nk[i] = c->n[i * N + k];
         orc_density_momentum(nk, &c->rho_o[k], &c->jx[k], &c->jy[k]);
     }
+    if (c->paper_coupling) {
+        /* The paper's coupling (Sec. III, Eqs. bodyforce and hydrofields):    */
+        /* no stress divergence; d_t delta rho = -(tr sigma^{t-1} - tr         */
+        /* sigma^{t-2}) / (2 cs2) carries the trace, rho = sum n + d_t rho / 2, */
+        /* f = rho g (the external force only).                                */
+        for (int k = 0; k < N; ++k) {
+            double tr1 = c->sig_xx[k] + (c->sig_yy ? c->sig_yy[k] : 0.0);
+            double dr = -(tr1 - c->tr_prev[k]) / (2.0 * CS2);
+            c->tr_prev[k] = tr1;
+            c->rho_o[k] += 0.5 * dr;
+            c->fx[k] = c->rho_o[k] * c->gx;
+            c->fy[k] = c->rho_o[k] * c->gy;
+            c->ux_o[k] = (c->jx[k] + 0.5 * c->fx[k]) / c->rho_o[k];
+            c->uy_o[k] = (c->jy[k] + 0.5 * c->fy[k]) / c->rho_o[k];
+            c->sxx_div[k] = dr; /* kept for the collision below */
+        }
+        goto gradient;
+    }
     /* 2. force density: rho g + div sigma^{t-1} (sigma_yy = 0) */
     orc_stress_divergence(lx, ly, c->sig_xx, c->sig_xy, c->sig_yy, c->fx, c->fy);
     for (int k = 0; k < N; ++k) {
@@ -753,6 +828,7 @@ static void one_step(orc_channel *c)
         c->ux_o[k] = (c->jx[k] + 0.5 * c->fx[k]) / c->rho_o[k];
         c->uy_o[k] = (c->jy[k] + 0.5 * c->fy[k]) / c->rho_o[k];
     }
+gradient:
     /* 4. velocity gradient and shear rates */
     orc_velocity_gradient(lx, ly, c->ux_o, c->uy_o, kxx, kxy, kyx, kyy);
     if (c->qg) {
@@ -832,8 +908,21 @@ collide:
         double nk[9], ns[9];
         for (int i = 0; i < 9; ++i)
             nk[i] = c->n[i * N + k];
-        orc_collide(c->tau_lb, nk, c->rho_o[k], c->ux_o[k], c->uy_o[k],
-                    c->fx[k], c->fy[k], ns);
+        if (c->paper_coupling) {
+            /* traceless part of sigma^{t-1}: sbar = sigma - (tr sigma / 2) I */
+            double syy = c->sig_yy ? c->sig_yy[k] : 0.0;
+            double sbar[3] = {0.5 * (c->sig_xx[k] - syy), c->sig_xy[k],
+                              0.5 * (syy - c->sig_xx[k])};
+            double neq[9], F[9];
+            orc_equilibrium(c->rho_o[k], c->ux_o[k], c->uy_o[k], neq);
+            orc_force_term_paper(c->tau_lb, c->ux_o[k], c->uy_o[k], c->fx[k],
+                                 c->fy[k], sbar, c->sxx_div[k], F);
+            for (int i = 0; i < 9; ++i)
+                ns[i] = nk[i] - (nk[i] - neq[i]) / c->tau_lb + F[i];
+        } else {
+            orc_collide(c->tau_lb, nk, c->rho_o[k], c->ux_o[k], c->uy_o[k],
+                        c->fx[k], c->fy[k], ns);
+        }
         for (int i = 0; i < 9; ++i)
             c->nstar[i * N + k] = ns[i];
     }

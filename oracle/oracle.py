@@ -58,6 +58,9 @@ def load():
         "orc_set_state": (None, [ctypes.c_void_p, _D, _D, _D, _D, _D, _D, _D, ctypes.c_long]),
         "orc_set_history_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
         "orc_set_finger": (ctypes.c_int, [ctypes.c_void_p]),
+        "orc_set_paper_coupling": (ctypes.c_int, [ctypes.c_void_p]),
+        "orc_trace_prev": (ctypes.c_int, [ctypes.c_void_p, _D]),
+        "orc_force_term_paper": (None, [ctypes.c_double] * 5 + [_D, ctypes.c_double, _D]),
         "orc_expm2": (None, [_D, _D]),
         "orc_finger_sum": (None, [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, _D]),
@@ -178,6 +181,15 @@ def history_sum_ages(s_age, r_age, g_inf, tau_m, gamma_c):
     return a.value, b.value
 
 
+def force_term_paper(tau_lb, ux, uy, fx, fy, sbar, dr) -> np.ndarray:
+    """Eq. bodyforce in full: sbar = traceless stress (xx, xy, yy), dr the
+    density rate d_t delta rho."""
+    sbar = _f64(sbar).reshape(3)
+    out = np.zeros(9)
+    load().orc_force_term_paper(tau_lb, ux, uy, fx, fy, _p(sbar), dr, _p(out))
+    return out
+
+
 def expm2(a) -> np.ndarray:
     """exp of a 2x2 matrix (row-major [2][2])."""
     a = _f64(a).reshape(4)
@@ -262,6 +274,9 @@ class OracleChannel:
                                      ch.gamma_c, ch.n_hist, ch.gx, ch.gy, _p(u0))
         if not self.h:
             raise ValueError("oracle rejected the channel description")
+        if getattr(ch, "paper_coupling", False):
+            if self.lib.orc_set_paper_coupling(self.h) != 0:
+                raise ValueError("oracle rejected the paper coupling")
         if getattr(ch, "finger", False):
             if self.lib.orc_set_finger(self.h) != 0:
                 raise ValueError("oracle rejected the full-tensor path")
@@ -313,6 +328,13 @@ class OracleChannel:
 
     def mass(self) -> float:
         return self.lib.orc_mass(self.h)
+
+    def trace_prev(self) -> np.ndarray:
+        """tr sigma two steps back (paper coupling only), [ly][lx]."""
+        out = np.zeros(self._shape())
+        if self.lib.orc_trace_prev(self.h, _p(out)) != 0:
+            raise RuntimeError("not a paper-coupling channel")
+        return out
 
     def get_state(self) -> Dict[str, np.ndarray]:
         N, H = self.lx * self.ly, self.n_hist

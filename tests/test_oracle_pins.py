@@ -751,3 +751,79 @@ def test_finger_product_order_rotation_after_shear():
     got = np.array([[b[0], b[1]], [b[1], b[2]]])
     assert np.abs(got - want).max() <= 1e-13 * np.abs(S).max()
     assert np.abs(got - S).max() > 1e-3 * np.abs(S).max()   # the rotation matters
+
+
+# --------------------------------------------------------------------------
+# The paper's own stress coupling (Eq. bodyforce with d_t delta rho)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_paper_forcing_moments(seed):
+    """Moments of Eq. bodyforce on D2Q9 (4th-order isotropy of the weights):
+    sum F = (1 - 1/2tau) dr, sum c F = (1 - 1/2tau) f,
+    sum c c F = -sbar/tau + (1 - 1/2tau) (cs2 dr I - dr u u + u f + f u)."""
+    rng = np.random.default_rng(workloads.BASE_SEED + 70 + seed)
+    tau = rng.uniform(0.6, 2.0)
+    u, f = rng.uniform(-0.05, 0.05, 2), rng.uniform(-1e-4, 1e-4, 2)
+    a, b = rng.uniform(-1e-3, 1e-3, 2)
+    sbar = np.array([a, b, -a])
+    dr = rng.uniform(-1e-5, 1e-5)
+    F = oracle.force_term_paper(tau, u[0], u[1], f[0], f[1], sbar, dr)
+    cx, cy, _, _ = oracle.lattice()
+    c = np.stack([cx, cy], 1).astype(float)
+    pre = 1 - 1 / (2 * tau)
+    S = np.array([[a, b], [b, -a]])
+    A = -dr * np.outer(u, u) + np.outer(u, f) + np.outer(f, u)
+    assert abs(F.sum() - pre * dr) < 1e-18
+    np.testing.assert_allclose(c.T @ F, pre * f, rtol=0, atol=1e-18)
+    want2 = -S / tau + pre * (dr / 3 * np.eye(2) + A)
+    np.testing.assert_allclose(np.einsum("i,ia,ib->ab", F, c, c), want2, rtol=0, atol=1e-17)
+
+
+def test_paper_coupling_newtonian_equals_body_force():
+    """Without stress (G = 0) both couplings are the same scheme."""
+    ch = workloads.large_2d(lx=6, ly=10, n_hist=16).channels[0].replace(g_inf=0.0, gx=2e-5)
+    wl = lambda c: workloads.Workload("n", [c], "f64", steps_on=200, sample_every=50)
+    a = oracle.run_workload(wl(ch))[0]
+    b = oracle.run_workload(wl(ch.replace(paper_coupling=True)))[0]
+    for key in ("ux", "uy", "rho"):
+        np.testing.assert_allclose(b[key], a[key], rtol=0, atol=1e-15 * np.abs(a[key]).max())
+
+
+@pytest.mark.parametrize("finger", [False, True])
+def test_paper_coupling_mass_and_pressure(finger):
+    """Every node gains d_t delta rho of mass per step, so the total mass
+    plus 1.5 sum tr sigma^{t-2} (the density carrying the non-Newtonian
+    pressure -tr sigma / 2 = cs2 delta rho) is conserved exactly."""
+    ch = workloads.large_2d(lx=8, ly=12, n_hist=64).channels[0]
+    ch = ch.replace(u0=ch.u0 * 50.0, tau_m=30.0, paper_coupling=True, finger=finger)
+    oc = oracle.OracleChannel(ch)
+    m0 = oc.mass()
+    oc.step(300)
+    tr = oc.trace_prev()
+    assert np.abs(tr).max() > 1e-8          # the trace is not trivially zero
+    assert abs(oc.mass() + 1.5 * tr.sum() - m0) / m0 < 1e-13
+
+
+def test_paper_coupling_ucm_steady_centreline():
+    """With the paper's coupling the UCM channel reaches the same steady
+    state as with the body force: centreline g ly^2 / (8 nu_eff) at second
+    order in 1/ly (nu_eff = nu + the discrete Maxwell viscosity)."""
+    errs = []
+    for ly in (12, 24):
+        g, tau, Gm = 1e-6, 15.0, 5e-3
+        ch = workloads.Channel(lx=1, ly=ly, tau_lb=1.0, g_inf=Gm, tau_m=tau,
+                               gamma_c=math.inf, n_hist=600, gx=g, paper_coupling=True)
+        oc = oracle.OracleChannel(ch)
+        nu = 0.5 / 3
+        eta_s = Gm * 0.5 / math.tanh(0.5 / tau) * (1 - math.exp(-599 / tau))
+        nu_eff = nu + eta_s
+        t_wall = ly * ly / (math.pi ** 2 * nu_eff)
+        oc.step(int(25 * t_wall) + 1000)
+        _, ux, _ = oc.fields()
+        uc = 0.5 * (ux[ly // 2, 0] + ux[ly // 2 - 1, 0])
+        y = ly / 2 - 0.5
+        want = g / (2 * nu_eff) * (y + 0.5) * (ly - 0.5 - y)
+        errs.append(abs(uc / want - 1))
+    assert errs[0] < 0.05
+    assert errs[1] < errs[0] / 3

@@ -54,6 +54,10 @@ class Channel:
     # (E k E^T)^T, E the ordered product of exp(kappa dt)) instead of the
     # simple-shear reduction; sigma_yy then enters the force.
     finger: bool = False
+    # Stress coupling: False enters div sigma as a body force (default);
+    # True uses the paper's forcing term (Eq. bodyforce: traceless stress in
+    # the second moment, trace through a density rate).
+    paper_coupling: bool = False
 
     @property
     def nodes(self) -> int:
