@@ -104,6 +104,15 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F32_P64 = 2 } lb_precision;
  * product of exp(kappa dt) over the steps from t' to t - 1 (Eq. eeval);
  * sigma_yy enters the force and N1 = sigma_xx - sigma_yy.  Needs
  * hist_blocks == 0; blocks of at most 16 steps (lb_set_block); no adjoint.
+ *
+ * Stress coupling.  paper_coupling == 0: the stress of the previous step
+ * enters as the body force div sigma (forcing term with the external force
+ * rho*g + div sigma; mass conserved exactly).  paper_coupling == 1: the
+ * paper's own forcing term, Eq. bodyforce in full -- the traceless part of
+ * sigma^{t-1} in the second moment, the trace through the density rate
+ * d_t delta rho = -(tr sigma^{t-1} - tr sigma^{t-2}) / (2 cs2),
+ * rho = sum n + d_t delta rho / 2 and the external force rho*g only
+ * (Eq. hydrofields).  No adjoint.
  */
 typedef struct {
     int32_t lx, ly;
@@ -114,6 +123,7 @@ typedef struct {
     const double *u0;
     int32_t hist_blocks, hist_block_len;
     int32_t finger;
+    int32_t paper_coupling;
 } lb_channel_desc;
 
 typedef struct lb_handle lb_handle;
@@ -167,7 +177,7 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  * 256-byte aligned, R = the lattice type: double for LB_F64 and LB_F32_P64,
  * float for LB_F32; RH = the history type: double for LB_F64, float
  * otherwise):
- *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 3,
+ *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 4,
  *     uint32 precision, int64 t (completed steps), int32 n_ch,
  *     int32 reserved, uint64 total bytes, int32 block length,
  *     int32 block position (steps of the current block already done);
@@ -180,6 +190,7 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  *     sig  [3][N] R  sigma_xy, sigma_xx, sigma_yy of step t-1
  *     vel  [2][N] R  u_x, u_y of step t-1
  *     drho [N]    R  rho - 1 of step t-1
+ *     trp  [N]    R  tr sigma^{t-2} (used by the paper coupling; zero else)
  *     ring_s [n_hist][N] RH shear rate s(t') = kappa_xy, row t' mod n_hist
  *     ring_r [n_hist][N] RH |gamma_dot(t')| (absent for unidirectional
  *                           channels)

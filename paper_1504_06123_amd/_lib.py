@@ -26,7 +26,7 @@ class ChannelDesc(ctypes.Structure):
         ("gx", ctypes.c_double), ("gy", ctypes.c_double),
         ("u0", ctypes.POINTER(ctypes.c_double)),
         ("hist_blocks", ctypes.c_int32), ("hist_block_len", ctypes.c_int32),
-        ("finger", ctypes.c_int32),
+        ("finger", ctypes.c_int32), ("paper_coupling", ctypes.c_int32),
     ]
 
 

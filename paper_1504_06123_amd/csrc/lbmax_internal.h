@@ -34,6 +34,8 @@ struct alignas(256) ChanDev {
     int32_t vec;                    // history kernel: nodes per lane (1, 2, 4)
     int32_t qb, qc;                 // quasi-logarithmic grid: blocks B, entries C (qb = 0: none)
     int32_t finger;                 // 1: full Finger tensor (8-plane ring: kappa, g; sigma_yy)
+    int32_t coupling;               // 0: body force div sigma; 1: the paper's forcing term
+    int32_t pad_;
     double omega;                   // 1/tau_LB
     double g_inf;
     double inv_tau, inv_gc;         // 1/tau, 1/gamma_c (0 for gamma_c = inf)
@@ -50,6 +52,7 @@ struct alignas(256) ChanDev {
     int64_t off_grid_s;             // [qb][qc][np] averaged shear rate of each grid entry
     int64_t off_grid_r;             // [qb][qc][np] |gamma_dot| of the averaged gradient (has_r)
     int64_t off_grid_d;             // [3][qb][qc][np] averaged D components (has_r)
+    int64_t off_trace;              // [np] tr sigma two steps back (paper coupling)
 };
 static_assert(sizeof(ChanDev) == 256, "ChanDev layout");
 

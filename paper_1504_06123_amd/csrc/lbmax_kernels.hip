@@ -175,6 +175,60 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero(uint4 *__restrict__ p,
 }
 
 // ---------------------------------------------------------------------------
+// The paper's own coupling (Sec. III, Eqs. bodyforce and hydrofields): the
+// traceless stress sbar = sigma - (tr sigma / 2) I of step t-1 enters the
+// second moment of the forcing term, its trace through the density rate
+// dr = d_t delta rho = -(tr sigma^{t-1} - tr sigma^{t-2}) / (2 cs2);
+// rho = sum n + dr / 2, the force is the external rho g only, and
+//   F_q = a_q { -sbar:(c c - cs2 I) / (2 cs2^2 tau) + (1 - 1/(2 tau))
+//          [dr + c.f / cs2 + (c c - cs2 I):(-dr u u + u f + f u) / (2 cs2^2)] },
+// which in D2Q9 (cs2 = 1/3, sbar traceless) reads
+//   a_q { -4.5 omega (sbar_xx (cx^2 - cy^2) + 2 sbar_xy cx cy)
+//         + (1 - omega/2) [dr + 3 c.f + 9 (c.u)(c.f) - 3 u.f
+//                          - 4.5 dr (c.u)^2 + 1.5 dr u.u] }.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void lb_collide_paper(char *__restrict__ ws, const ChanDev *c, int n,
+                                                 size_t np, const R (&d)[9], R drho, R jx,
+                                                 R jy, R *__restrict__ dst)
+{
+    const R *__restrict__ sxy = reinterpret_cast<const R *>(ws + c->off_sig);
+    const R *__restrict__ sxx = sxy + np;
+    const R syy = c->finger ? sxy[2 * np + n] : R(0);
+    R *trp = reinterpret_cast<R *>(ws + c->off_trace);
+    const R tr1 = sxx[n] + syy;
+    const R dr = R(-1.5) * (tr1 - trp[n]);
+    trp[n] = tr1;
+    drho += R(0.5) * dr;
+    const R rho = R(1) + drho;
+    const R fx = rho * (R)c->gx, fy = rho * (R)c->gy;
+    const R ux = (jx + R(0.5) * fx) / rho;
+    const R uy = (jy + R(0.5) * fy) / rho;
+    const R bxx = R(0.5) * (sxx[n] - syy), bxy = sxy[n];
+    const R om = (R)c->omega;
+    const R pf = R(1) - R(0.5) * om;
+    const R uu = ux * ux + uy * uy;
+    const R uf = ux * fx + uy * fy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const R cx = R(QX[q]), cy = R(QY[q]);
+        const R cu = cx * ux + cy * uy;
+        const R cf = cx * fx + cy * fy;
+        const R w = qweight<R>(q);
+        const R deq = w * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+        const R st = bxx * (cx * cx - cy * cy) + R(2) * bxy * cx * cy;
+        const R F = w * (R(-4.5) * om * st +
+                         pf * (dr + R(3) * (cf - uf) + R(9) * cu * cf - R(4.5) * dr * cu * cu +
+                               R(1.5) * dr * uu));
+        dst[q * np + n] = d[q] - om * (d[q] - deq) + F;
+    }
+    R *vel = reinterpret_cast<R *>(ws + c->off_vel);
+    vel[n] = ux;
+    vel[np + n] = uy;
+    reinterpret_cast<R *>(ws + c->off_rho)[n] = drho;
+}
+
+// ---------------------------------------------------------------------------
 // Lattice phase of step t.
 // ---------------------------------------------------------------------------
 template <typename R>
@@ -219,9 +273,13 @@ __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
     d[8] = lo ? src[8 * np + rowm + xp] : src[7 * np + n];
 
     // Moments of the deviations n_q - a_q: rho - 1 and j.
-    const R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
     const R jx = (d[1] - d[2]) + (d[5] - d[6]) + (d[7] - d[8]);
     const R jy = (d[3] - d[4]) + (d[5] - d[6]) + (d[8] - d[7]);
+    if (c->coupling) {
+        lb_collide_paper<R>(ws, c, n, np, d, drho, jx, jy, dst);
+        return;
+    }
     const R rho = R(1) + drho;
 
     // Force density rho*g + div sigma^{t-1} (sigma_yy = 0 in the simple-shear

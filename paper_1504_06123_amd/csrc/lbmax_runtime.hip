@@ -29,7 +29,7 @@ lb_status fail(lb_status s, const std::string &msg)
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr uint64_t kStateMagic = 0x4C424D4158535431ull;  // "LBMAXST1"
-constexpr uint32_t kStateVersion = 3;
+constexpr uint32_t kStateVersion = 4;
 constexpr size_t kStateHeader = 256;
 constexpr int64_t kMaxStepsPerBatch = int64_t(1) << 20;
 
@@ -81,6 +81,8 @@ std::string check_desc(const lb_channel_desc *ch, int32_t n_ch)
             return bad("n_hist must be >= 2");
         if (d.finger != 0 && d.finger != 1)
             return bad("finger must be 0 or 1");
+        if (d.paper_coupling != 0 && d.paper_coupling != 1)
+            return bad("paper_coupling must be 0 or 1");
         if (d.finger && d.hist_blocks > 0)
             return bad("the full Finger tensor runs on the uniform window (hist_blocks = 0)");
         if (d.hist_blocks > 0) {
@@ -153,6 +155,7 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         c.n = d.lx * d.ly;
         c.np = (int)align_up((size_t)c.n, kNodeAlign);
         c.finger = d.finger;
+        c.coupling = d.paper_coupling;
         c.qb = d.hist_blocks;
         c.qc = d.hist_blocks > 0 ? d.hist_block_len : 0;
         c.n_hist = d.hist_blocks > 0 ? 0 : d.n_hist;
@@ -191,6 +194,8 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         c.off_vel = (int64_t)off;
         off = align_up(off + 2 * plane, 256);
         c.off_rho = (int64_t)off;
+        off = align_up(off + plane, 256);
+        c.off_trace = (int64_t)off;
         off = align_up(off + plane, 256);
         const size_t hplane = (size_t)c.np * RH;
         c.off_ring_s = (int64_t)off;
@@ -564,6 +569,7 @@ std::vector<Section> state_sections(const lb_handle *h, int ci, int64_t t)
     v.push_back({c.off_sig, 3, rowb, pitch});
     v.push_back({c.off_vel, 2, rowb, pitch});
     v.push_back({c.off_rho, 1, rowb, pitch});
+    v.push_back({c.off_trace, 1, rowb, pitch});
     if (c.qb > 0) {
         const size_t grows = (size_t)c.qb * c.qc;
         v.push_back({c.off_grid_s, grows, hrowb, hpitch});
@@ -648,6 +654,9 @@ std::string adjoint_unsupported(const lb_handle *h, int seg_len)
         if (c.finger)
             return "the adjoint covers the simple-shear reduction; channel " +
                    std::to_string(ci) + " uses the full Finger tensor";
+        if (c.coupling)
+            return "the adjoint covers the body-force coupling; channel " + std::to_string(ci) +
+                   " uses the paper's forcing term";
         if (c.lx != 1 || c.has_r)
             return "the adjoint covers unidirectional channels (lx = 1, gy = 0, u0_y = 0); "
                    "channel " + std::to_string(ci) + " is not";

@@ -44,6 +44,7 @@ def make_descs(channels: Sequence) -> tuple:
         d.hist_blocks = int(getattr(ch, "hist_blocks", 0))
         d.hist_block_len = int(getattr(ch, "hist_block_len", 0)) if d.hist_blocks else 0
         d.finger = 1 if getattr(ch, "finger", False) else 0
+        d.paper_coupling = 1 if getattr(ch, "paper_coupling", False) else 0
         u0 = getattr(ch, "u0", None)
         if u0 is not None:
             buf = np.ascontiguousarray(np.asarray(u0, dtype=np.float64).reshape(2, ch.ly, ch.lx))
@@ -209,7 +210,7 @@ class Solver:
 
 
 STATE_MAGIC = 0x4C424D4158535431
-STATE_VERSION = 3
+STATE_VERSION = 4
 
 
 def pack_state_header(t: int, n_ch: int, precision: str, total_bytes: int,
@@ -239,7 +240,7 @@ def state_layout(channels: Sequence, precision: str = "f32"):
                 not np.any(np.asarray(ch.u0, dtype=np.float64).reshape(2, -1)[1])))
         sec = {}
         finger = bool(getattr(ch, "finger", False))
-        for name, rows in (("pop", 9), ("sig", 3), ("vel", 2), ("drho", 1)):
+        for name, rows in (("pop", 9), ("sig", 3), ("vel", 2), ("drho", 1), ("trp", 1)):
             sec[name] = (off, rows, N)
             off = up(off + rows * N * R)
         B = int(getattr(ch, "hist_blocks", 0))
