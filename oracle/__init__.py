@@ -10,5 +10,5 @@ from .oracle import (  # noqa: F401
     OracleChannel, QGrid, lattice, equilibrium, force_term, collide,
     density_momentum, velocity_gradient, shear_rate, stress_divergence,
     stream, history_sum, history_sum_ages, run_workload, load, expm2, finger_sum,
-    force_term_paper,
+    force_term_paper, history_sum_wm, instantaneous, LAWS,
 )

@@ -42,7 +42,9 @@
  * paper's own forcing term (Eq. bodyforce in full): the traceless part in the
  * second moment of F_i, the trace through d_t delta rho = -(tr sigma^{t-1} -
  * tr sigma^{t-2}) / (2 cs2), rho = sum n + d_t rho / 2 and f = rho g only
- * (Eq. hydrofields) -- instead of the body force div sigma.
+ * (Eq. hydrofields) -- instead of the body force div sigma.  orc_set_law()
+ * selects the accumulated-strain variant of the damping (Sec. II) or the
+ * instantaneous law of Eq. inlM instead of the integral nlM model.
  *
  * Parity status: every function below is pinned by the CPU test suite
  * (closed forms, moment identities, polynomial exactness, recursion
@@ -318,6 +320,42 @@ void orc_history_sum(int n_hist, int n_live, const double *s_age,
     }
     *sxy = a;
     *sxx = b;
+}
+
+/* The White-Metzner-type variant of Sec. II: the rate-dependent second      */
+/* exponential of Eq. nlmax becomes the accumulated strain, here the total    */
+/* shear accumulated from t' to t, R = sum of r(j) over the steps             */
+/* j = t', ..., t - 1 (the same steps as the strain gamma):                    */
+/*   G(t, t') = G exp(-(t - t')/tau) exp(-R(t, t')/gamma_c).                   */
+/* Inputs by age as in orc_history_sum.                                        */
+void orc_history_sum_wm(int n_hist, int n_live, const double *s_age,
+                        const double *r_age, const double *dgam_age, double g_inf,
+                        double tau_m, double gamma_c, double *sxy, double *sxx)
+{
+    double a = 0.0, b = 0.0, R = 0.0;
+    for (int k = 0; k < n_live && k < n_hist; ++k) {
+        if (k > 0)
+            R += r_age[k];
+        double w = (k == 0 || k == n_hist - 1) ? 0.5 : 1.0;
+        double G = g_inf * exp(-(double)k / tau_m) * exp(-R / gamma_c);
+        a += w * s_age[k] * G;
+        b += w * 2.0 * s_age[k] * dgam_age[k] * G;
+    }
+    *sxy = a;
+    *sxx = b;
+}
+
+/* Eq. inlM read at time t (the instantaneous nonlinear Maxwell model of Sec. */
+/* IV): sigma_struc = sum_{n>=1} G tau_M^n d^(n), which for the simple-shear   */
+/* reduction (kappa nilpotent: d^(1) = kappa + kappa^T, d^(2) = 2 kappa        */
+/* kappa^T, d^(n>2) = 0) is sigma_xy = G tau_M s, sigma_xx = 2 G tau_M^2 s^2,   */
+/* with tau_M = 1/(1/tau + r/gamma_c).                                         */
+void orc_instantaneous(double s, double r, double g_inf, double tau_m,
+                       double gamma_c, double *sxy, double *sxx)
+{
+    double taum = 1.0 / (1.0 / tau_m + r / gamma_c);
+    *sxy = g_inf * taum * s;
+    *sxx = 2.0 * g_inf * taum * taum * s * s;
 }
 
 /* Same sum from the shear history alone (all n_hist ages given, zeros for   */
@@ -637,6 +675,7 @@ typedef struct orc_channel {
     double *ring_f;  /* [n_hist][4][N] exp(kappa(t') dt), row-major 2x2 */
     double *sig_yy;  /* [N] sigma_yy of the last completed step (full tensor) */
     int paper_coupling; /* 1: stress through Eq. bodyforce instead of div sigma */
+    int law;         /* 0: Eq. nlmax; 1: accumulated-strain damping; 2: Eq. inlM */
     double *tr_prev; /* [N] trace of sigma two steps back (paper coupling) */
     double *new_yy;
     /* outputs of the last completed step */
@@ -735,7 +774,7 @@ void orc_set_force(orc_channel *c, double gx, double gy)
 /* C entries (before its first step); the uniform window is then unused.      */
 int orc_set_history_grid(orc_channel *c, int B, int C)
 {
-    if (c->t != 0 || c->qg || c->ring_k || B < 1 || C < 2)
+    if (c->t != 0 || c->qg || c->ring_k || c->law || B < 1 || C < 2)
         return -1;
     c->qg = (orc_qgrid *)calloc((size_t)c->N, sizeof(orc_qgrid));
     for (int k = 0; k < c->N; ++k)
@@ -747,7 +786,7 @@ int orc_set_history_grid(orc_channel *c, int B, int C)
 /* its first step): sigma_yy no longer vanishes and enters the force.         */
 int orc_set_finger(orc_channel *c)
 {
-    if (c->t != 0 || c->qg || c->ring_k)
+    if (c->t != 0 || c->qg || c->ring_k || c->law)
         return -1;
     size_t N = (size_t)c->N, H = (size_t)c->n_hist;
     c->ring_k = zalloc(4 * H * N);
@@ -780,6 +819,19 @@ int orc_trace_prev(const orc_channel *c, double *out)
     if (!c->paper_coupling)
         return -1;
     memcpy(out, c->tr_prev, sizeof(double) * (size_t)c->N);
+    return 0;
+}
+
+/* Constitutive law (before the first step): 0 the integral nlM model of    */
+/* Eqs. gitt and nlmax, 1 its accumulated-strain (White-Metzner-type)        */
+/* variant on the uniform window, 2 the instantaneous law of Eq. inlM.        */
+int orc_set_law(orc_channel *c, int law)
+{
+    if (c->t != 0 || law < 0 || law > 2)
+        return -1;
+    if (law != 0 && (c->qg || c->ring_k))
+        return -1;
+    c->law = law;
     return 0;
 }
 
@@ -831,6 +883,13 @@ static void one_step(orc_channel *c)
 gradient:
     /* 4. velocity gradient and shear rates */
     orc_velocity_gradient(lx, ly, c->ux_o, c->uy_o, kxx, kxy, kyx, kyy);
+    if (c->law == 2) {
+        /* 5-6 replaced by the instantaneous law of the current gradient */
+        for (int k = 0; k < N; ++k)
+            orc_instantaneous(kxy[k], orc_shear_rate(kxx[k], kxy[k], kyx[k], kyy[k]),
+                              c->g_inf, c->tau_m, c->gamma_c, &c->new_xy[k], &c->new_xx[k]);
+        goto collide;
+    }
     if (c->qg) {
         /* 5-6 on the quasi-logarithmic grid: push, combine, integrate */
         int cap = orc_qgrid_capacity(&c->qg[0]);
@@ -897,8 +956,12 @@ gradient:
             c->r_age[a] = c->ring_r[sl * N + k];
             c->dg_age[a] = c->gam[k] - c->ring_g[sl * N + k];
         }
-        orc_history_sum(H, n_live, c->s_age, c->r_age, c->dg_age, c->g_inf,
-                        c->tau_m, c->gamma_c, &c->new_xy[k], &c->new_xx[k]);
+        if (c->law == 1)
+            orc_history_sum_wm(H, n_live, c->s_age, c->r_age, c->dg_age, c->g_inf,
+                               c->tau_m, c->gamma_c, &c->new_xy[k], &c->new_xx[k]);
+        else
+            orc_history_sum(H, n_live, c->s_age, c->r_age, c->dg_age, c->g_inf,
+                            c->tau_m, c->gamma_c, &c->new_xy[k], &c->new_xx[k]);
     }
     for (int k = 0; k < N; ++k)
         c->gam[k] += kxy[k];

@@ -16,6 +16,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liblboracle.so")
 _lib = None
 
+# constitutive laws (Channel.law): the integral nlM model, its accumulated-
+# strain damping variant, the instantaneous law
+LAWS = {"nlm": 0, "strain_damping": 1, "instantaneous": 2}
+
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int)
 
@@ -59,6 +63,11 @@ def load():
         "orc_set_history_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
         "orc_set_finger": (ctypes.c_int, [ctypes.c_void_p]),
         "orc_set_paper_coupling": (ctypes.c_int, [ctypes.c_void_p]),
+        "orc_set_law": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+        "orc_history_sum_wm": (None, [ctypes.c_int, ctypes.c_int, _D, _D, _D,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
+                                      _D]),
+        "orc_instantaneous": (None, [ctypes.c_double] * 5 + [_D, _D]),
         "orc_trace_prev": (ctypes.c_int, [ctypes.c_void_p, _D]),
         "orc_force_term_paper": (None, [ctypes.c_double] * 5 + [_D, ctypes.c_double, _D]),
         "orc_expm2": (None, [_D, _D]),
@@ -172,6 +181,23 @@ def history_sum(n_hist, s_age, r_age, dgam_age, g_inf, tau_m, gamma_c, n_live=No
     return a.value, b.value
 
 
+def history_sum_wm(n_hist, s_age, r_age, dgam_age, g_inf, tau_m, gamma_c, n_live=None):
+    """History sum with the accumulated-strain damping (Sec. II variant)."""
+    s_age, r_age, dgam_age = _f64(s_age), _f64(r_age), _f64(dgam_age)
+    if n_live is None:
+        n_live = len(s_age)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    load().orc_history_sum_wm(int(n_hist), int(n_live), _p(s_age), _p(r_age), _p(dgam_age),
+                              g_inf, tau_m, gamma_c, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def instantaneous(s, r, g_inf, tau_m, gamma_c):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    load().orc_instantaneous(s, r, g_inf, tau_m, gamma_c, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
 def history_sum_ages(s_age, r_age, g_inf, tau_m, gamma_c):
     """History integral from a full window of shear history given by age."""
     s_age, r_age = _f64(s_age), _f64(r_age)
@@ -274,6 +300,9 @@ class OracleChannel:
                                      ch.gamma_c, ch.n_hist, ch.gx, ch.gy, _p(u0))
         if not self.h:
             raise ValueError("oracle rejected the channel description")
+        law = LAWS[getattr(ch, "law", "nlm")]
+        if law and self.lib.orc_set_law(self.h, law) != 0:
+            raise ValueError("oracle rejected the constitutive law")
         if getattr(ch, "paper_coupling", False):
             if self.lib.orc_set_paper_coupling(self.h) != 0:
                 raise ValueError("oracle rejected the paper coupling")

@@ -827,3 +827,86 @@ def test_paper_coupling_ucm_steady_centreline():
         errs.append(abs(uc / want - 1))
     assert errs[0] < 0.05
     assert errs[1] < errs[0] / 3
+
+
+# --------------------------------------------------------------------------
+# Alternative laws: accumulated-strain damping (Sec. II) and the
+# instantaneous law (Eq. inlM)
+# --------------------------------------------------------------------------
+
+def test_strain_damping_equals_nlm_for_constant_shear():
+    """Under constant shear the accumulated strain from t' to t is (t - t')|s|,
+    exactly the rate term of Eq. nlmax: both laws give the same sums."""
+    H, t = 300, 180
+    for s in (2e-4, -7e-4):
+        s_age = np.where(np.arange(H) <= t, s, 0.0)
+        r_age = np.abs(s_age)
+        dg = np.concatenate([[0.0], np.cumsum(s_age[1:])])
+        a = oracle.history_sum(H, s_age, r_age, dg, 1e-3, 40.0, 0.05)
+        b = oracle.history_sum_wm(H, s_age, r_age, dg, 1e-3, 40.0, 0.05)
+        np.testing.assert_allclose(b, a, rtol=1e-13)
+
+
+def test_strain_damping_one_step_recursion():
+    """The damping factorises over time, so the shear stress obeys the
+    one-step update A(t+1) = s_{t+1}/2 + l_t (A(t) + s_t/2) with
+    l_t = exp(-1/tau - r_t/gamma_c) while nothing leaves the window
+    (trapezoid weight 1/2 at age 0, 1 beyond)."""
+    rng = np.random.default_rng(workloads.BASE_SEED + 80)
+    T, H, tau, gc, G = 150, 400, 30.0, 0.02, 1.0
+    s = rng.uniform(-1e-3, 1e-3, T)
+    r = np.abs(s) * rng.uniform(0.5, 1.5, T)       # |gamma_dot| from the full II_D
+    A = []
+    for t in range(T):
+        s_age = s[t::-1]
+        r_age = r[t::-1]
+        A.append(oracle.history_sum_wm(H, s_age, r_age, np.zeros(t + 1), G, tau, gc,
+                                       n_live=t + 1)[0])
+    for t in range(T - 1):
+        lam = math.exp(-1 / tau - r[t] / gc)
+        want = 0.5 * s[t + 1] + lam * (A[t] + 0.5 * s[t])
+        assert abs(A[t + 1] - want) <= 1e-13 * max(abs(want), 1e-3)
+
+
+def test_strain_damping_differs_from_nlm_for_varying_shear():
+    rng = np.random.default_rng(workloads.BASE_SEED + 81)
+    H = 200
+    s_age = rng.uniform(-1e-3, 1e-3, H)
+    r_age = np.abs(s_age)
+    dg = np.concatenate([[0.0], np.cumsum(s_age[1:])])
+    a = oracle.history_sum(H, s_age, r_age, dg, 1e-3, 40.0, 0.01)
+    b = oracle.history_sum_wm(H, s_age, r_age, dg, 1e-3, 40.0, 0.01)
+    assert abs(a[0] - b[0]) > 1e-3 * abs(a[0])
+
+
+def test_instantaneous_law_is_the_steady_limit_of_the_history_sum():
+    """Long-time constant shear: the integral model tends to the
+    instantaneous law within its trapezoid factors 1 + O(lam^2)."""
+    n_hist = 20000
+    for s in (1e-5, 3e-4, 2e-3):
+        s_age = np.full(n_hist, s)
+        a = oracle.history_sum_ages(s_age, np.abs(s_age), G, TAU, GC)
+        b = oracle.instantaneous(s, abs(s), G, TAU, GC)
+        lam = 1.0 / TAU + s / GC
+        assert abs(a[0] / b[0] - 1) < lam ** 2 / 11
+        assert abs(a[1] / b[1] - 1) < lam ** 2 / 11
+
+
+def test_instantaneous_channel_reaches_the_integral_steady_state():
+    """Fig. steadystate's claim: the instantaneous and the integral model
+    reach the same steady channel flow (up to the O(lam^2) quadrature factor
+    of the integral model and its truncated window)."""
+    base = workloads.Channel(lx=1, ly=14, tau_lb=1.0, g_inf=4e-3, tau_m=12.0, gamma_c=0.05,
+                             n_hist=500, gx=2e-5)
+    outs = []
+    for law in ("nlm", "instantaneous"):
+        oc = oracle.OracleChannel(base.replace(law=law))
+        oc.step(6000)
+        outs.append(oc.fields()[1][:, 0])
+        sxy, _ = oc.stress()
+    a, b = outs
+    assert np.abs(a).max() > 1e-4
+    # quadrature factor 1 + lam^2/12 at the largest rate lam = 1/tau + |s|/gamma_c
+    s_max = np.abs(np.diff(a)).max() * 1.5
+    lam = 1 / base.tau_m + s_max / base.gamma_c
+    assert np.abs(a - b).max() <= lam ** 2 / 12 * np.abs(a).max()

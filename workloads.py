@@ -58,6 +58,10 @@ class Channel:
     # True uses the paper's forcing term (Eq. bodyforce: traceless stress in
     # the second moment, trace through a density rate).
     paper_coupling: bool = False
+    # Constitutive law: "nlm" the integral nonlinear Maxwell model (Eqs.
+    # gitt, nlmax); "strain_damping" its variant with the accumulated strain
+    # in the damping (Sec. II); "instantaneous" the instantaneous law (Eq. inlM).
+    law: str = "nlm"
 
     @property
     def nodes(self) -> int:
