@@ -72,7 +72,8 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F32_P64 = 2 } lb_precision;
 
 /*
  * One channel.  Requirements (checked, LB_EINVAL otherwise):
- *   lx >= 1, ly >= 3, tau_lb > 1/2, n_hist >= 2, g_inf >= 0, tau_m > 0,
+ *   lx >= 1, ly >= 3, tau_lb > 1/2, n_hist >= 2 (unless the grid or law 2
+ *   is used), g_inf >= 0, tau_m > 0,
  *   gamma_c > 0 (may be +INFINITY: the linear / UCM limit of Sec. II),
  *   all numbers finite except gamma_c = +INF.
  * g_inf = 0 gives a Newtonian fluid.  (gx, gy) is the body-force
@@ -113,6 +114,15 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F32_P64 = 2 } lb_precision;
  * d_t delta rho = -(tr sigma^{t-1} - tr sigma^{t-2}) / (2 cs2),
  * rho = sum n + d_t delta rho / 2 and the external force rho*g only
  * (Eq. hydrofields).  No adjoint.
+ *
+ * Constitutive law.  law == 0: the integral nonlinear Maxwell model
+ * (Eqs. gitt, nlmax).  law == 1: its variant of Sec. II with the
+ * accumulated strain in the damping, G exp(-(t - t')/tau) exp(-R(t, t') /
+ * gamma_c) with R the |gamma_dot| summed over the steps t', ..., t - 1.
+ * law == 2: the instantaneous law, Eq. inlM read at time t: sigma_xy =
+ * G tau_M s, N1 = 2 G tau_M^2 s^2, tau_M = 1/(1/tau + |gamma_dot|/gamma_c)
+ * (no history; n_hist ignored).  Laws 1 and 2 need finger == 0 and
+ * hist_blocks == 0, take no window split and no adjoint.
  */
 typedef struct {
     int32_t lx, ly;
@@ -124,6 +134,7 @@ typedef struct {
     int32_t hist_blocks, hist_block_len;
     int32_t finger;
     int32_t paper_coupling;
+    int32_t law;
 } lb_channel_desc;
 
 typedef struct lb_handle lb_handle;

@@ -27,7 +27,12 @@ class ChannelDesc(ctypes.Structure):
         ("u0", ctypes.POINTER(ctypes.c_double)),
         ("hist_blocks", ctypes.c_int32), ("hist_block_len", ctypes.c_int32),
         ("finger", ctypes.c_int32), ("paper_coupling", ctypes.c_int32),
+        ("law", ctypes.c_int32),
     ]
+
+
+# Channel.law names -> lb_channel_desc.law
+LAWS = {"nlm": 0, "strain_damping": 1, "instantaneous": 2}
 
 
 class LBError(RuntimeError):

@@ -20,7 +20,7 @@ constexpr int kMaxBlock = 32;      // most steps served by one history pass
 constexpr int kPlaneB = kMaxBlock;
 constexpr int kPlaneT = 2 * kMaxBlock;
 constexpr int kPartPlanes = 2 * kMaxBlock + 1;
-constexpr int kTileCounters = 4;   // persistent-pass tile counters (lane widths, full tensor)
+constexpr int kTileCounters = 8;   // persistent-pass tile counters (one per tile group)
 // Full tensor: S_xx, S_xy, S_yy per step of the block, then the range's
 // total deformation (4 planes).
 constexpr int kFingerPartPlanes = 3 * kMaxBlock + 4;
@@ -35,7 +35,7 @@ struct alignas(256) ChanDev {
     int32_t qb, qc;                 // quasi-logarithmic grid: blocks B, entries C (qb = 0: none)
     int32_t finger;                 // 1: full Finger tensor (8-plane ring: kappa, g; sigma_yy)
     int32_t coupling;               // 0: body force div sigma; 1: the paper's forcing term
-    int32_t pad_;
+    int32_t law;                    // 0: Eq. nlmax; 1: accumulated-strain damping; 2: Eq. inlM
     double omega;                   // 1/tau_LB
     double g_inf;
     double inv_tau, inv_gc;         // 1/tau, 1/gamma_c (0 for gamma_c = inf)
@@ -91,6 +91,12 @@ void launch_finger_pass(int prec, int block, char *ws, const ChanDev *chans,
                         const HistTile *tiles, int n_tiles, const int64_t *tcount, int trel,
                         int persistent_grid, int *counter, hipStream_t st);
 int finger_pass_blocks_per_cu(int prec, int block);
+// Accumulated-strain damping: one pass per block, O(1) work per entry.
+void launch_wm_pass(int prec, int block, char *ws, const ChanDev *chans, const HistTile *tiles,
+                    int n_tiles, const int64_t *tcount, int trel, hipStream_t st);
+// Instantaneous law (Eq. inlM), every step, node-local (other channels return).
+void launch_inst_step(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
+                      int n_tiles, const int64_t *tcount, int trel, hipStream_t st);
 // FP64 combine of chunk partials into sigma and the block sums.
 void launch_combine(int prec, int block, char *ws, const ChanDev *chans,
                     const NodeTile *tiles, int n_tiles, hipStream_t st);

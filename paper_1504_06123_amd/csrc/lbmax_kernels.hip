@@ -1112,6 +1112,190 @@ __device__ __forceinline__ void finger_step(char *__restrict__ ws, const ChanDev
 }
 
 // ---------------------------------------------------------------------------
+// Accumulated-strain damping (the White-Metzner-type variant of Sec. II):
+//   G(t, t') = G exp(-(t - t')/tau - R(t, t')/gamma_c),
+// R(t, t') = sum of |gamma_dot| over the steps t', ..., t - 1 (the steps of
+// the strain gamma).  The damping factorises over time: at step t0 + m an
+// entry's factor is its factor at t0 times c_m = exp(-m/tau - dR_m/gamma_c)
+// with dR_m the |gamma_dot| pushed since the pass.  So a pass at t0 needs a
+// single sum over the entries that stay inside the window with weight 1 for
+// the whole block (ages 1 .. H-M-1), plus per-step terms for the few ages at
+// the window's ends; the step t0 + m scales the result by c_m.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R wm_damping(const Decay<R> &dec, R k, double racc)
+{
+    return decay_pow(R(1), fused(dec.b, (R)racc, dec.a * k));
+}
+
+template <typename P, typename R, int M>
+__device__ __forceinline__ void wm_tile(char *__restrict__ ws, const ChanDev *c,
+                                        const HistTile &tl, int64_t t)
+{
+#pragma clang fp contract(off)
+    const int H = c->n_hist;
+    const size_t np = (size_t)c->np;
+    const int first = tl.n0 + (int)threadIdx.x;
+    const int node = first < c->n ? first : c->n - 1;
+    const int p = (int)(t % H);
+    R *ring_s = reinterpret_cast<R *>(ws + c->off_ring_s);
+    R *ring_r = reinterpret_cast<R *>(ws + c->off_ring_r);
+    const bool has_r = c->has_r != 0;
+    const Decay<R> dec(c);
+    Acc<R> A[M], B[M], bulkA, bulkB;
+    // newest entry: gradient, push, age 0
+    R s0 = R(0), r0 = R(0);
+    {
+        const P *vel = reinterpret_cast<const P *>(ws + c->off_vel);
+        if (first < c->n) {
+            const int y = node / c->lx, x = node - y * c->lx;
+            P kxx, kxy, kyx, kyy;
+            velocity_gradient<P>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
+            s0 = (R)kxy;
+            r0 = has_r ? (R)shear_rate<P>(kxx, kxy, kyx, kyy) : fabs(s0);
+            ring_s[(size_t)p * np + node] = s0;
+            if (has_r)
+                ring_r[(size_t)p * np + node] = r0;
+        }
+    }
+    double loc = 0.0, racc = 0.0;  // strain and accumulated |gamma_dot| since age 0
+    auto edge = [&](R s, int k, R e) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int a = k + m;
+            if (a <= H - 1) {
+                const R w = (a == 0 || a == H - 1) ? R(0.5) : R(1);
+                const R x = w * s * e;
+                A[m].add(x);
+                B[m].add(x * R(2) * (R)loc);
+            }
+        }
+    };
+    edge(s0, 0, R(1));
+    const int kb = max(1, H - M);  // ages [1, kb) stay inside with weight 1
+    int slot = p;
+    R pa = R(0), pb = R(0);
+    int cnt = 0;
+    for (int k = 1; k < H; ++k) {
+        slot = slot == 0 ? H - 1 : slot - 1;
+        const size_t row = (size_t)slot * np + node;
+        const R s = ring_s[row];
+        const R r = has_r ? ring_r[row] : fabs(s);
+        loc += (double)s;
+        racc += (double)r;
+        const R e = wm_damping<R>(dec, R(k), racc);
+        if (k < kb) {
+            const R x = s * e;
+            pa = pa + x;
+            pb = fused(x, R(2) * (R)loc, pb);
+            if (++cnt == 32) {
+                bulkA.add(pa);
+                bulkB.add(pb);
+                pa = pb = R(0);
+                cnt = 0;
+            }
+        } else {
+            edge(s, k, e);
+        }
+    }
+    bulkA.add(pa);
+    bulkB.add(pb);
+    if (first >= c->n)
+        return;
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    double *blk = reinterpret_cast<double *>(ws + c->off_blk);
+    sig[first] = (P)(c->g_inf * (bulkA.value() + A[0].value()));
+    sig[np + first] = (P)(c->g_inf * (bulkB.value() + B[0].value()));
+#pragma unroll
+    for (int m = 1; m < M; ++m) {
+        blk[m * np + first] = bulkA.value() + A[m].value();
+        blk[(kPlaneB + m) * np + first] = bulkB.value() + B[m].value();
+    }
+}
+
+template <typename P, typename R, int M>
+__global__ __launch_bounds__(kBlock) void k_wm_pass(char *__restrict__ ws,
+                                                    const ChanDev *__restrict__ chans,
+                                                    const HistTile *__restrict__ tiles,
+                                                    const int64_t *__restrict__ tcount, int trel)
+{
+    const HistTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    if (tl.n0 + (int)(threadIdx.x & ~63u) >= c->n)
+        return;
+    wm_tile<P, R, M>(ws, c, tl, *tcount + trel);
+}
+
+// In-block step m of an accumulated-strain channel (called from k_hist_step).
+template <typename P, typename R>
+__device__ __forceinline__ void wm_step(char *__restrict__ ws, const ChanDev *c, int n,
+                                        int64_t t, int m)
+{
+    const int H = c->n_hist;
+    const size_t np = (size_t)c->np;
+    const int p = (int)(t % H);
+    R *ring_s = reinterpret_cast<R *>(ws + c->off_ring_s);
+    R *ring_r = reinterpret_cast<R *>(ws + c->off_ring_r);
+    const bool has_r = c->has_r != 0;
+    const P *vel = reinterpret_cast<const P *>(ws + c->off_vel);
+    const int y = n / c->lx, x = n - y * c->lx;
+    P kxx, kxy, kyx, kyy;
+    velocity_gradient<P>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
+    const R s_new = (R)kxy;
+    ring_s[(size_t)p * np + n] = s_new;
+    if (has_r)
+        ring_r[(size_t)p * np + n] = (R)shear_rate<P>(kxx, kxy, kyx, kyy);
+    const Decay<R> dec(c);
+    double sxy = 0.5 * (double)s_new, sxx = 0.0, gam = 0.0, racc = 0.0;
+    int slot = p;
+    for (int a = 1; a <= m; ++a) {
+        slot = slot == 0 ? H - 1 : slot - 1;
+        const R s = ring_s[(size_t)slot * np + n];
+        const R r = has_r ? ring_r[(size_t)slot * np + n] : fabs(s);
+        gam += (double)s;
+        racc += (double)r;
+        if (a < m && a <= H - 1) {
+            const double w = (a == H - 1) ? 0.5 : 1.0;
+            const double se = w * (double)(s * wm_damping<R>(dec, R(a), racc));
+            sxy += se;
+            sxx += 2.0 * gam * se;
+        }
+    }
+    // the pass's sums carried to this step: factor c_m
+    const double cm = (double)wm_damping<R>(dec, R(m), racc);
+    const double *blk = reinterpret_cast<const double *>(ws + c->off_blk);
+    const double A = blk[m * np + n], B = blk[(kPlaneB + m) * np + n];
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    sig[n] = (P)(c->g_inf * (sxy + cm * A));
+    sig[np + n] = (P)(c->g_inf * (sxx + cm * (B + 2.0 * gam * A)));
+}
+
+// Instantaneous law (Eq. inlM read at time t): sigma_xy = G tau_M s,
+// sigma_xx = 2 G tau_M^2 s^2, tau_M = 1/(1/tau + |gamma_dot|/gamma_c).
+template <typename P>
+__global__ __launch_bounds__(kBlock) void k_inst_step(char *__restrict__ ws,
+                                                      const ChanDev *__restrict__ chans,
+                                                      const NodeTile *__restrict__ tiles)
+{
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const int n = tl.n0 + threadIdx.x;
+    if (c->law != 2 || n >= c->n)
+        return;
+    const size_t np = (size_t)c->np;
+    const P *vel = reinterpret_cast<const P *>(ws + c->off_vel);
+    const int y = n / c->lx, x = n - y * c->lx;
+    P kxx, kxy, kyx, kyy;
+    velocity_gradient<P>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
+    const double r = (double)shear_rate<P>(kxx, kxy, kyx, kyy);
+    const double taum = 1.0 / (c->inv_tau + c->inv_gc * r);
+    const double s = (double)kxy;
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    sig[n] = (P)(c->g_inf * taum * s);
+    sig[np + n] = (P)(2.0 * c->g_inf * taum * taum * s * s);
+}
+
+// ---------------------------------------------------------------------------
 // FP64 combine of the per-chunk partials of a split window, newest chunk
 // first: A_m = sum_c A_{m,c}, B_m = sum_c (2 O_c A_{m,c} + B_{m,c}), where
 // O_c = sum of the strain totals T of the newer chunks (the accumulated
@@ -1212,6 +1396,12 @@ __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
         finger_step<P, R>(ws, c, n, t, m);
         return;
     }
+    if (c->law == 1) {
+        wm_step<P, R>(ws, c, n, t, m);
+        return;
+    }
+    if (c->law == 2)
+        return;  // instantaneous channels step in k_inst_step
     const int H = c->n_hist;
     const size_t np = (size_t)c->np;
     const int p = (int)(t % H);
@@ -1602,6 +1792,40 @@ int finger_pass_blocks_per_cu(int prec, int block)
 #undef LBMAX_FOCC_SHAPES
 #undef LBMAX_FOCC
     return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+void launch_wm_pass(int prec, int block, char *ws, const ChanDev *chans, const HistTile *tiles,
+                    int n_tiles, const int64_t *tcount, int trel, hipStream_t st)
+{
+    if (n_tiles <= 0)
+        return;
+#define LBMAX_WM(MM) hipLaunchKernelGGL((k_wm_pass<P, H, MM>), dim3(n_tiles), dim3(kBlock), 0, \
+                                        st, ws, chans, tiles, tcount, trel)
+#define LBMAX_WM_SHAPES                                                          \
+    do {                                                                         \
+        if (block == 1)                                                          \
+            LBMAX_WM(1);                                                         \
+        else if (block == 2)                                                     \
+            LBMAX_WM(2);                                                         \
+        else if (block == 4)                                                     \
+            LBMAX_WM(4);                                                         \
+        else if (block == 8)                                                     \
+            LBMAX_WM(8);                                                         \
+        else if (block == 16)                                                    \
+            LBMAX_WM(16);                                                        \
+        else                                                                     \
+            LBMAX_WM(32);                                                        \
+    } while (0)
+    LBMAX_BY_PREC(prec, LBMAX_WM_SHAPES);
+#undef LBMAX_WM_SHAPES
+#undef LBMAX_WM
+}
+
+void launch_inst_step(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
+                      int n_tiles, const int64_t *, int, hipStream_t st)
+{
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_inst_step<P>, dim3(n_tiles), dim3(kBlock), 0, st,
+                                           ws, chans, tiles));
 }
 
 void launch_combine(int prec, int block, char *ws, const ChanDev *chans, const NodeTile *tiles,

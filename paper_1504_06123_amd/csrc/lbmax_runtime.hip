@@ -77,12 +77,18 @@ std::string check_desc(const lb_channel_desc *ch, int32_t n_ch)
             return bad("too many nodes");
         if (d.hist_blocks < 0)
             return bad("hist_blocks must be >= 0");
-        if (d.hist_blocks == 0 && d.n_hist < 2)
+        if (d.hist_blocks == 0 && d.law != 2 && d.n_hist < 2)
             return bad("n_hist must be >= 2");
         if (d.finger != 0 && d.finger != 1)
             return bad("finger must be 0 or 1");
         if (d.paper_coupling != 0 && d.paper_coupling != 1)
             return bad("paper_coupling must be 0 or 1");
+        if (d.law < 0 || d.law > 2)
+            return bad("law must be 0 (nlM), 1 (accumulated-strain damping) or 2 "
+                       "(instantaneous)");
+        if (d.law != 0 && (d.finger || d.hist_blocks > 0))
+            return bad("the alternative laws use the simple-shear reduction on the uniform "
+                       "window (finger = 0, hist_blocks = 0)");
         if (d.finger && d.hist_blocks > 0)
             return bad("the full Finger tensor runs on the uniform window (hist_blocks = 0)");
         if (d.hist_blocks > 0) {
@@ -156,11 +162,12 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         c.np = (int)align_up((size_t)c.n, kNodeAlign);
         c.finger = d.finger;
         c.coupling = d.paper_coupling;
+        c.law = d.law;
         c.qb = d.hist_blocks;
         c.qc = d.hist_blocks > 0 ? d.hist_block_len : 0;
-        c.n_hist = d.hist_blocks > 0 ? 0 : d.n_hist;
+        c.n_hist = (d.hist_blocks > 0 || d.law == 2) ? 0 : d.n_hist;
         c.has_r = (unidirectional(d) && !d.finger) ? 0 : 1;
-        c.max_chunks = d.hist_blocks > 0 ? 1 : max_chunks_for(d.n_hist, c.np);
+        c.max_chunks = (d.hist_blocks > 0 || d.law != 0) ? 1 : max_chunks_for(d.n_hist, c.np);
         c.nchunks = 1;
         c.vec = 1;
         c.omega = 1.0 / d.tau_lb;
@@ -173,7 +180,7 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         c.gy = d.gy;
         const int blocks = (c.n + kBlock - 1) / kBlock;
         P.n_node_tiles += blocks;
-        if (c.qb == 0)
+        if (c.qb == 0 && c.law != 2)
             P.n_hist_tiles_max += blocks * c.max_chunks;
         stage = std::max(stage, (size_t)4 * c.n);
     }
@@ -251,9 +258,10 @@ struct lb_handle {
     HistTile *d_hist_tiles = nullptr;
     double *d_stage = nullptr;
     int n_node_tiles = 0, n_hist_tiles = 0;
-    // history tile groups: lane width 1, 2, 4 (simple-shear pass), full tensor
-    int hist_group_begin[4] = {0, 0, 0, 0}, hist_group_count[4] = {0, 0, 0, 0};
-    bool any_finger = false;
+    // history tile groups: lane width 1, 2, 4 (simple-shear pass), full tensor,
+    // accumulated-strain damping
+    int hist_group_begin[5] = {0, 0, 0, 0, 0}, hist_group_count[5] = {0, 0, 0, 0, 0};
+    bool any_finger = false, any_wm = false, any_inst = false;
     bool any_chunked = false;
     bool any_grid = false, any_window = false;  // channels on the grid / the uniform window
     // host mirrors kept alive for asynchronous uploads
@@ -332,7 +340,7 @@ void build_tiles(lb_handle *h)
     h->node_tiles.clear();
     h->hist_tiles.clear();
     h->any_chunked = false;
-    h->any_grid = h->any_window = false;
+    h->any_grid = h->any_window = h->any_inst = false;
     for (int ci = 0; ci < h->n_ch; ++ci) {
         const ChanDev &c = h->plan.chans[ci];
         for (int n0 = 0; n0 < c.n; n0 += kBlock)
@@ -341,10 +349,14 @@ void build_tiles(lb_handle *h)
             h->any_grid = true;  // stepped by k_grid_step, no history tiles
             continue;
         }
+        if (c.law == 2) {
+            h->any_inst = true;  // stepped by k_inst_step, no history
+            continue;
+        }
         h->any_window = true;
         if (c.nchunks > 1)
             h->any_chunked = true;
-        const int span = kBlock * (c.finger ? 1 : effective_vec(c.vec, h->block));
+        const int span = kBlock * ((c.finger || c.law) ? 1 : effective_vec(c.vec, h->block));
         for (int k = 0; k < c.nchunks; ++k) {
             const int k0 = (int)((int64_t)c.n_hist * k / c.nchunks);
             const int k1 = (int)((int64_t)c.n_hist * (k + 1) / c.nchunks);
@@ -355,6 +367,8 @@ void build_tiles(lb_handle *h)
     // Group by lane width (one launch each), longest age range first inside
     // a group.
     auto group = [h](const HistTile &a) {
+        if (h->plan.chans[a.ch].law == 1)
+            return 4;
         if (h->plan.chans[a.ch].finger)
             return 3;
         const int v = effective_vec(h->plan.chans[a.ch].vec, h->block);
@@ -366,7 +380,7 @@ void build_tiles(lb_handle *h)
                              return group(a) < group(b);
                          return (a.k1 - a.k0) > (b.k1 - b.k0);
                      });
-    for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < 5; ++g)
         h->hist_group_count[g] = 0;
     for (const HistTile &tl : h->hist_tiles)
         h->hist_group_count[group(tl)] += 1;
@@ -374,7 +388,9 @@ void build_tiles(lb_handle *h)
     h->hist_group_begin[1] = h->hist_group_count[0];
     h->hist_group_begin[2] = h->hist_group_count[0] + h->hist_group_count[1];
     h->hist_group_begin[3] = h->hist_group_begin[2] + h->hist_group_count[2];
+    h->hist_group_begin[4] = h->hist_group_begin[3] + h->hist_group_count[3];
     h->any_finger = h->hist_group_count[3] > 0;
+    h->any_wm = h->hist_group_count[4] > 0;
     h->n_node_tiles = (int)h->node_tiles.size();
     h->n_hist_tiles = (int)h->hist_tiles.size();
 }
@@ -385,8 +401,9 @@ void default_tiling(lb_handle *h)
 {
     int total = 0;
     for (ChanDev &c : h->plan.chans) {
-        c.vec = c.qb > 0 ? 1 : (c.n >= (1 << 16) ? 4 : (c.n >= (1 << 12) ? 2 : 1));
-        if (c.qb == 0)
+        const bool plain = c.qb == 0 && c.law == 0 && !c.finger;
+        c.vec = !plain ? 1 : (c.n >= (1 << 16) ? 4 : (c.n >= (1 << 12) ? 2 : 1));
+        if (c.qb == 0 && c.law != 2)
             total += (c.n + kBlock * c.vec - 1) / (kBlock * c.vec);
     }
     total = std::max(total, 1);
@@ -463,6 +480,9 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
     if (h->any_grid)
         launch_grid_step(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
                          h->d_tcount, trel, st);
+    if (h->any_inst)
+        launch_inst_step(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
+                         h->d_tcount, trel, st);
     if (m == 0) {
         static const int kVec[3] = {1, 2, 4};
         for (int g = 0; g < 3; ++g) {
@@ -473,6 +493,10 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
                              h->d_hist_tiles + h->hist_group_begin[g], h->hist_group_count[g],
                              h->d_tcount, trel, pgrid, h->d_tile_counters + g, st);
         }
+        if (h->any_wm)
+            launch_wm_pass(h->pc, h->block, h->ws, h->d_chans,
+                           h->d_hist_tiles + h->hist_group_begin[4], h->hist_group_count[4],
+                           h->d_tcount, trel, st);
         if (h->any_finger) {
             const int pgrid =
                 h->persistent ? h->num_cus * finger_pass_blocks_per_cu(h->pc, h->block) : 0;
@@ -657,6 +681,9 @@ std::string adjoint_unsupported(const lb_handle *h, int seg_len)
         if (c.coupling)
             return "the adjoint covers the body-force coupling; channel " + std::to_string(ci) +
                    " uses the paper's forcing term";
+        if (c.law)
+            return "the adjoint covers the integral nlM law; channel " + std::to_string(ci) +
+                   " uses another constitutive law";
         if (c.lx != 1 || c.has_r)
             return "the adjoint covers unidirectional channels (lx = 1, gy = 0, u0_y = 0); "
                    "channel " + std::to_string(ci) + " is not";

@@ -45,6 +45,7 @@ def make_descs(channels: Sequence) -> tuple:
         d.hist_block_len = int(getattr(ch, "hist_block_len", 0)) if d.hist_blocks else 0
         d.finger = 1 if getattr(ch, "finger", False) else 0
         d.paper_coupling = 1 if getattr(ch, "paper_coupling", False) else 0
+        d.law = _lib.LAWS[getattr(ch, "law", "nlm")]
         u0 = getattr(ch, "u0", None)
         if u0 is not None:
             buf = np.ascontiguousarray(np.asarray(u0, dtype=np.float64).reshape(2, ch.ly, ch.lx))
@@ -249,6 +250,8 @@ def state_layout(channels: Sequence, precision: str = "f32"):
             for name, k in (("grid_s", 1),) + (() if uni else (("grid_r", 1), ("grid_d", 3))):
                 sec[name] = (off, k * rows, N)
                 off = up(off + k * rows * N * RH)
+        elif getattr(ch, "law", "nlm") == "instantaneous":
+            pass
         elif finger:
             sec["ring"] = (off, 8 * int(ch.n_hist), N)
             off = up(off + 8 * int(ch.n_hist) * N * RH)
