@@ -15,8 +15,9 @@ autotuner before the timed region.
 
 Beside it ("grid"): the same channel on the quasi-logarithmic history grid
 of Sec. III; ("full_tensor"): the same channel with the full Finger tensor
-instead of its simple-shear reduction; and ("batched"): the 64-channel
-batched workload (uneven widths and
+instead of its simple-shear reduction; ("laws"): the same channel with the
+accumulated-strain damping variant and with the instantaneous law; and
+("batched"): the 64-channel batched workload (uneven widths and
 windows, FP32, one launch per phase) against the plain per-channel FP64
 path (one handle per channel, no blocking, no graphs) on the same GPU.
 
@@ -273,6 +274,46 @@ def bench_finger(steps: int = 128):
                          "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg_bytes}}
 
 
+def bench_laws(steps: int = 256):
+    """The large 2D channel with the accumulated-strain damping variant
+    (32-step passes, one bulk sum per entry), with the instantaneous law (no
+    history), and with the integral law coupled through the paper's forcing
+    term; FP64 lattice and FP32 history."""
+    import torch
+    import workloads
+    from paper_1504_06123_amd import Solver, autotune
+
+    base = workloads.large_2d().channels[0]
+    out = {}
+    for law, block, coupled in (("strain_damping", 32, False), ("instantaneous", 1, False),
+                                ("nlm", 32, True)):
+        ch = base.replace(law=law, paper_coupling=coupled)
+        s = Solver([ch], precision="f32p64")
+        s.step(32)
+        autotune.apply(s, dict(block=block, vec=1, chunk_len=1 << 30, persistent=False,
+                               graph=0))
+        s.step(2 * block)
+        el, kt = time_steps(s, steps)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        rec = {"value": ch.nodes * steps / el, "unit": "node-steps/s",
+               "ms_per_step": el / steps * 1e3, "steps_per_pass": block,
+               "lattice_kernel_ms": kt[1][0] / max(kt[1][1], 1)}
+        if law == "strain_damping":
+            pass_s = kt[0][0] / kt[0][1] / 1e3
+            alg = ch.nodes * ch.n_hist * 8
+            rec["roofline"] = {"bound": "hbm", "achieved": alg / pass_s / 1e9,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": alg / pass_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                               "kernel": "k_wm_pass (32 steps per pass)",
+                               "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg}
+        name = "nlm_paper_coupling" if coupled else law
+        log(f"bench: {name}: {rec['ms_per_step']:.4f} ms/step")
+        out[name] = rec
+    return out
+
+
 def bench_batched(steps: int = 2000):
     """64 uneven channels: tuned FP32 batched path vs plain per-channel FP64."""
     import torch
@@ -327,6 +368,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-finger", action="store_true")
+    ap.add_argument("--no-laws", action="store_true")
+    ap.add_argument("--only", choices=("grid", "full_tensor", "laws", "batched"),
+                    help="run one side leg alone and print its record")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--block", type=int, default=32, help="steps per pass without tuning")
     ap.add_argument("--persistent", action="store_true", help="persistent pass without tuning")
@@ -361,6 +405,13 @@ def main():
         log(f"bench: copy probe of {args.copy_probe_mib} MiB done")
         del src, dst
 
+    if args.only:
+        # one side leg alone (for profiling); prints that leg's record
+        legs = {"grid": bench_grid, "full_tensor": bench_finger, "laws": bench_laws,
+                "batched": bench_batched}
+        print(json.dumps({args.only: legs[args.only]()}), flush=True)
+        return
+
     wl = workloads.large_2d()
     ch = wl.channels[0]
     nodes, H = ch.nodes, ch.n_hist
@@ -378,6 +429,10 @@ def main():
     if not args.no_finger:
         log("bench: large 2D channel with the full Finger tensor")
         finger = bench_finger()
+    laws = None
+    if not args.no_laws:
+        log("bench: alternative constitutive laws on the large 2D channel")
+        laws = bench_laws()
     batched = None
     if not args.no_batched:
         log("bench: batched 64-channel workload")
@@ -414,6 +469,7 @@ def main():
                              "launch": side["cfg"], "roofline": side["roof"]},
         "grid": grid,
         "full_tensor": finger,
+        "laws": laws,
         "batched": batched,
         "cpu_baseline": cpu,
     }

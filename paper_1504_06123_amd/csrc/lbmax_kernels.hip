@@ -1142,7 +1142,7 @@ __device__ __forceinline__ void wm_tile(char *__restrict__ ws, const ChanDev *c,
     R *ring_r = reinterpret_cast<R *>(ws + c->off_ring_r);
     const bool has_r = c->has_r != 0;
     const Decay<R> dec(c);
-    Acc<R> A[M], B[M], bulkA, bulkB;
+    Acc<R> bulkA, bulkB;
     // newest entry: gradient, push, age 0
     R s0 = R(0), r0 = R(0);
     {
@@ -1159,57 +1159,67 @@ __device__ __forceinline__ void wm_tile(char *__restrict__ ws, const ChanDev *c,
         }
     }
     double loc = 0.0, racc = 0.0;  // strain and accumulated |gamma_dot| since age 0
-    auto edge = [&](R s, int k, R e) {
+    // per-step sums of the few entries at the window's ends (at most M + 1
+    // terms each: plain sums in the history precision)
+    R A[M], B[M];
+    auto edge = [&](R s, int k, R e, double gam) {
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int a = k + m;
             if (a <= H - 1) {
                 const R w = (a == 0 || a == H - 1) ? R(0.5) : R(1);
                 const R x = w * s * e;
-                A[m].add(x);
-                B[m].add(x * R(2) * (R)loc);
+                A[m] = A[m] + x;
+                B[m] = B[m] + x * R(2) * (R)gam;
             }
         }
     };
-    edge(s0, 0, R(1));
     const int kb = max(1, H - M);  // ages [1, kb) stay inside with weight 1
     int slot = p;
-    R pa = R(0), pb = R(0);
-    int cnt = 0;
-    for (int k = 1; k < H; ++k) {
+    // bulk ages: one sum, FP32 partials of 32 rows flushed into FP64
+    int k = 1;
+    while (k < kb) {
+        const int kend = min(kb, k + 32);
+        R pa = R(0), pb = R(0);
+        for (; k < kend; ++k) {
+            slot = slot == 0 ? H - 1 : slot - 1;
+            const size_t row = (size_t)slot * np + node;
+            const R s = ring_s[row];
+            const R r = has_r ? ring_r[row] : fabs(s);
+            loc += (double)s;
+            racc += (double)r;
+            const R x = s * wm_damping<R>(dec, R(k), racc);
+            pa = pa + x;
+            pb = fused(x, R(2) * (R)loc, pb);
+        }
+        bulkA.add(pa);
+        bulkB.add(pb);
+    }
+    // the newest entry (age 0, no strain, no damping), then the ages whose
+    // k + m reaches the window end: per-step weights
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+        A[m] = B[m] = R(0);
+    edge(s0, 0, R(1), 0.0);
+    for (; k < H; ++k) {
         slot = slot == 0 ? H - 1 : slot - 1;
         const size_t row = (size_t)slot * np + node;
         const R s = ring_s[row];
         const R r = has_r ? ring_r[row] : fabs(s);
         loc += (double)s;
         racc += (double)r;
-        const R e = wm_damping<R>(dec, R(k), racc);
-        if (k < kb) {
-            const R x = s * e;
-            pa = pa + x;
-            pb = fused(x, R(2) * (R)loc, pb);
-            if (++cnt == 32) {
-                bulkA.add(pa);
-                bulkB.add(pb);
-                pa = pb = R(0);
-                cnt = 0;
-            }
-        } else {
-            edge(s, k, e);
-        }
+        edge(s, k, wm_damping<R>(dec, R(k), racc), loc);
     }
-    bulkA.add(pa);
-    bulkB.add(pb);
     if (first >= c->n)
         return;
     P *sig = reinterpret_cast<P *>(ws + c->off_sig);
     double *blk = reinterpret_cast<double *>(ws + c->off_blk);
-    sig[first] = (P)(c->g_inf * (bulkA.value() + A[0].value()));
-    sig[np + first] = (P)(c->g_inf * (bulkB.value() + B[0].value()));
+    sig[first] = (P)(c->g_inf * (bulkA.value() + (double)A[0]));
+    sig[np + first] = (P)(c->g_inf * (bulkB.value() + (double)B[0]));
 #pragma unroll
     for (int m = 1; m < M; ++m) {
-        blk[m * np + first] = bulkA.value() + A[m].value();
-        blk[(kPlaneB + m) * np + first] = bulkB.value() + B[m].value();
+        blk[m * np + first] = bulkA.value() + (double)A[m];
+        blk[(kPlaneB + m) * np + first] = bulkB.value() + (double)B[m];
     }
 }
 
