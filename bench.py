@@ -49,12 +49,12 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernel
 # (precision, steps per pass, nodes per lane).  Valid only for the kernel source they
 # were taken from; otherwise reported as null.
 MEASURED = {
-    "source_sha256": "d3ffe78a1d04066172bf0c3caba23d5aadcd6bb0dcf99b6c6d465d55f0417efa",
+    "source_sha256": "ce674621b7e7f4b8d5ddc7b4234ad4b039d5fe51c40d2c2e1c391b1eeade275c",
     # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated)
-    "traffic_bytes": {("f32p64", 32, 1): 8394636.0 * 1024 * 2 + 266320 * 1024,
-                      ("f32p64", 1, 4): 8411090.0 * 1024 * 2 + 52458.2 * 1024},
+    "traffic_bytes": {("f32p64", 32, 1): 8395163.025 * 1024 * 2 + 266320.0 * 1024,
+                      ("f32p64", 1, 4): 8410789.0625 * 1024 * 2 + 52479.85 * 1024},
     # SQ_INSTS_VALU x 64 / history entries
-    "valu_instr_per_entry": {("f32p64", 32, 1): 112.06, ("f32p64", 1, 4): 11.54},
+    "valu_instr_per_entry": {("f32p64", 32, 1): 96.63, ("f32p64", 1, 4): 11.54},
 }
 
 
@@ -150,12 +150,13 @@ def bench_large_2d(wl, args, precision: str):
     key = (precision, M, cfg["vec"])
     traffic = measured("traffic_bytes", key)
     vpe = measured("valu_instr_per_entry", key)
-    vpe_src = "rocprofv3 SQ_INSTS_VALU" if vpe else "model 3.5 M + 10"
+    vpe_src = "rocprofv3 SQ_INSTS_VALU" if vpe else "model"
     if not vpe:
-        # three FP32 instructions per entry and step of the block plus the
-        # per-entry decay, strain and flush work (the counted 32-step pass
-        # has 112)
-        vpe = 3.5 * M + 10
+        # Instruction model.  M >= 16: one FMA per sum and step plus the eight
+        # low and M/8 high powers and the per-entry decay, strain and flush
+        # work (the counted 32-step pass has 97).  Shorter blocks carry the
+        # decay factor along the steps: three instructions per step.
+        vpe = 2.25 * M + 24 if M >= 16 else 3.5 * M + 10
     # Cycles each SIMD spends per wave-level VALU instruction; 4 is the
     # nominal wave64 issue interval (dependence-free FP32 chains measure 4.1).
     wave_instr = vpe * entries / 64

@@ -442,17 +442,50 @@ __device__ __forceinline__ void pass_rows(const R *__restrict__ ring_s,
             R q = R(1);
             if (M > 1)
                 q = decay_pow(R(1), rate);
+            if constexpr (M >= 16 && M % 8 == 0) {
+                // q^m = q^{m mod 8} (q^8)^{m / 8}: eight carried powers lo[],
+                // M/8 high powers hi[] (the second also carries 2 gamma), one
+                // FMA per sum and step
+                constexpr int MH = M / 8;
+                R lo[8], hi[MH], hg[MH];
+                lo[0] = x;
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                if (FIRST && u == 0) {
-                    pa[m][v] = x;
-                    pb[m][v] = x * g2;
-                } else {
-                    pa[m][v] += x;
-                    pb[m][v] = fused(x, g2, pb[m][v]);
+                for (int i = 1; i < 8; ++i)
+                    lo[i] = lo[i - 1] * q;
+                const R q2 = q * q, q4 = q2 * q2, q8 = q4 * q4;
+                hi[0] = R(1);
+                hg[0] = g2;
+#pragma unroll
+                for (int j = 1; j < MH; ++j) {
+                    hi[j] = j == 1 ? q8 : hi[j - 1] * q8;
+                    hg[j] = hi[j] * g2;
                 }
-                if (m + 1 < M)
-                    x *= q;
+#pragma unroll
+                for (int j = 0; j < MH; ++j)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int m = 8 * j + i;
+                        if (FIRST && u == 0) {
+                            pa[m][v] = j == 0 ? lo[i] : lo[i] * hi[j];
+                            pb[m][v] = lo[i] * hg[j];
+                        } else {
+                            pa[m][v] = j == 0 ? pa[m][v] + lo[i] : fused(lo[i], hi[j], pa[m][v]);
+                            pb[m][v] = fused(lo[i], hg[j], pb[m][v]);
+                        }
+                    }
+            } else {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    if (FIRST && u == 0) {
+                        pa[m][v] = x;
+                        pb[m][v] = x * g2;
+                    } else {
+                        pa[m][v] += x;
+                        pb[m][v] = fused(x, g2, pb[m][v]);
+                    }
+                    if (m + 1 < M)
+                        x *= q;
+                }
             }
         }
     }
