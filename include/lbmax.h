@@ -95,8 +95,9 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F32_P64 = 2 } lb_precision;
  * into the newest entry of block b - 1, and block 1's combined entries are
  * dropped.  Before t = 0 every block is full of zero entries (rest).  The
  * integral uses the trapezoid rule on the entries' start times.  Such a
- * channel takes no temporal blocking (lb_set_block applies to the other
- * channels), no window split, and no adjoint.
+ * channel takes temporal blocking (lb_set_block) when C >= steps_per_pass + 2
+ * (shorter blocks visit every entry every step), no window split, and no
+ * adjoint.
  *
  * Stress tensor.  finger == 0: the simple-shear reduction of the Finger
  * tensor (sigma_xy = int s G, sigma_xx = int 2 s gamma G, sigma_yy = 0;
@@ -188,7 +189,7 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  * 256-byte aligned, R = the lattice type: double for LB_F64 and LB_F32_P64,
  * float for LB_F32; RH = the history type: double for LB_F64, float
  * otherwise):
- *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 4,
+ *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 5,
  *     uint32 precision, int64 t (completed steps), int32 n_ch,
  *     int32 reserved, uint64 total bytes, int32 block length,
  *     int32 block position (steps of the current block already done);
@@ -220,7 +221,9 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  *     blk  [64][N] double   window sums of the block in progress (see
  *                           lb_set_block); read only when the block
  *                           position is not 0 ([96][N] for a full-tensor
- *                           channel)
+ *                           channel; [64 + B][N] on the grid, the last B
+ *                           planes the strain of each grid block's entries
+ *                           held through the block, oldest grid block first)
  *     force  2 doubles: gx, gy.
  * Ring rows of times before t = 0 are zero.
  */
@@ -254,7 +257,10 @@ lb_status lb_set_graph(lb_handle *h, int32_t steps_per_graph);
  * the following steps of the block add only the entries pushed since the
  * pass and shift the accumulated strain by the strain since the pass, which
  * enters the normal-stress sum affinely (Sec. III Eq. eeval: gamma(t,t') is a
- * sum of the shear rate over [t', t)).  Results differ from unblocked
+ * sum of the shear rate over [t', t)).  On the quasi-logarithmic grid the
+ * pass covers the entries each grid block holds through the whole block with
+ * unchanged neighbours; the steps of the block visit the rest (the entries
+ * received, combined away, or at a grid block's ends).  Results differ from unblocked
  * stepping only by rounding order.  A change takes effect at the next step
  * (which starts a new block); the graph length (lb_set_graph) must be a
  * multiple of it.  Default 1.
@@ -284,7 +290,8 @@ lb_status lb_kernel_time(lb_handle *h, int32_t which, double *total_ms,
 
 /*
  * Material parameters of channel ch from the next step on (G_inf, tau,
- * gamma_c of Eq. nlmax; same validity rules as lb_channel_desc).
+ * gamma_c of Eq. nlmax; same validity rules as lb_channel_desc).  The next
+ * step starts a new block (see lb_set_block) with a fresh history pass.
  */
 lb_status lb_set_params(lb_handle *h, int32_t ch, double g_inf, double tau_m,
                         double gamma_c);

@@ -20,6 +20,12 @@ constexpr int kMaxBlock = 32;      // most steps served by one history pass
 constexpr int kPlaneB = kMaxBlock;
 constexpr int kPlaneT = 2 * kMaxBlock;
 constexpr int kPartPlanes = 2 * kMaxBlock + 1;
+// Block planes of a channel on the quasi-logarithmic grid: A_m, B_m as
+// above, then the interior strain of each grid block at kPlaneGrid + bi.
+constexpr int kPlaneGrid = 2 * kMaxBlock;
+// Most steps served by one pass over a grid channel (longer blocks of the
+// other channels are served in sub-blocks of this length).
+constexpr int kMaxGridBlock = 16;
 constexpr int kTileCounters = 8;   // persistent-pass tile counters (one per tile group)
 // Full tensor: S_xx, S_xy, S_yy per step of the block, then the range's
 // total deformation (4 planes).
@@ -48,7 +54,7 @@ struct alignas(256) ChanDev {
     int64_t off_ring_s;             // [n_hist][np] shear rate ([8][n_hist][np] full tensor)
     int64_t off_ring_r;             // [n_hist][np] |gamma_dot| (has_r only)
     int64_t off_part;               // [kPartPlanes or kFingerPartPlanes][max_chunks][np] doubles
-    int64_t off_blk;                // [2 or 3 * kMaxBlock][np] doubles: block sums
+    int64_t off_blk;                // [2 or 3 * kMaxBlock (+ qb)][np] doubles: block sums
     int64_t off_grid_s;             // [qb][qc][np] averaged shear rate of each grid entry
     int64_t off_grid_r;             // [qb][qc][np] |gamma_dot| of the averaged gradient (has_r)
     int64_t off_grid_d;             // [3][qb][qc][np] averaged D components (has_r)
@@ -106,8 +112,11 @@ void launch_hist_step(int prec, int m, char *ws, const ChanDev *chans,
                       int trel, hipStream_t st);
 // Quasi-logarithmic grid channels, every step: gradient, push, combination of
 // full blocks, history integral -> sigma (other channels' tiles return).
-void launch_grid_step(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
-                      int n_tiles, const int64_t *tcount, int trel, hipStream_t st);
+// With blocks of block > 1 steps, step m = 0 of a block also forms the
+// interior sums of the block and steps m > 0 visit only the other entries.
+void launch_grid_step(int prec, int block, int m, char *ws, const ChanDev *chans,
+                      const NodeTile *tiles, int n_tiles, const int64_t *tcount, int trel,
+                      hipStream_t st);
 void launch_tick(int64_t *tcount, int64_t add, hipStream_t st);
 void launch_set_force(ChanDev *chans, int ch, double gx, double gy,
                       hipStream_t st);

@@ -408,6 +408,60 @@ __device__ __forceinline__ void edge_entry(R s, R r, int k, int H, double loc,
     }
 }
 
+// One entry's terms for the M steps of a block: x q^m into pa[m][v] and
+// x q^m g2 into pb[m][v], m = 0..M-1 (SET: the first entry of a group sets
+// them).  For M >= 16, q^m = q^{m mod 8} (q^8)^{m / 8}: eight carried low
+// powers, M/8 high powers (the second set also carries g2), one FMA per sum
+// and step; shorter blocks carry x q^m along m.
+template <typename R, int M, int V, bool SET>
+__device__ __forceinline__ void add_powers(R x, R q, R g2, R (&pa)[M][V], R (&pb)[M][V],
+                                           int v)
+{
+#pragma clang fp contract(off)
+    if constexpr (M >= 16 && M % 8 == 0) {
+        constexpr int MH = M / 8;
+        R lo[8], hi[MH], hg[MH];
+        lo[0] = x;
+#pragma unroll
+        for (int i = 1; i < 8; ++i)
+            lo[i] = lo[i - 1] * q;
+        const R q2 = q * q, q4 = q2 * q2, q8 = q4 * q4;
+        hi[0] = R(1);
+        hg[0] = g2;
+#pragma unroll
+        for (int j = 1; j < MH; ++j) {
+            hi[j] = j == 1 ? q8 : hi[j - 1] * q8;
+            hg[j] = hi[j] * g2;
+        }
+#pragma unroll
+        for (int j = 0; j < MH; ++j)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int m = 8 * j + i;
+                if (SET) {
+                    pa[m][v] = j == 0 ? lo[i] : lo[i] * hi[j];
+                    pb[m][v] = lo[i] * hg[j];
+                } else {
+                    pa[m][v] = j == 0 ? pa[m][v] + lo[i] : fused(lo[i], hi[j], pa[m][v]);
+                    pb[m][v] = fused(lo[i], hg[j], pb[m][v]);
+                }
+            }
+    } else {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            if (SET) {
+                pa[m][v] = x;
+                pb[m][v] = x * g2;
+            } else {
+                pa[m][v] += x;
+                pb[m][v] = fused(x, g2, pb[m][v]);
+            }
+            if (m + 1 < M)
+                x *= q;
+        }
+    }
+}
+
 // U rows of interior ages: entry k + j0 + u sits at ring slot `slot - j0 - u`.
 // The plain partial sums pa, pb take x = s E(k+m) (carried along m by the
 // per-entry factor q) and x * 2 gamma; FIRST starts them from these rows.
@@ -442,51 +496,10 @@ __device__ __forceinline__ void pass_rows(const R *__restrict__ ring_s,
             R q = R(1);
             if (M > 1)
                 q = decay_pow(R(1), rate);
-            if constexpr (M >= 16 && M % 8 == 0) {
-                // q^m = q^{m mod 8} (q^8)^{m / 8}: eight carried powers lo[],
-                // M/8 high powers hi[] (the second also carries 2 gamma), one
-                // FMA per sum and step
-                constexpr int MH = M / 8;
-                R lo[8], hi[MH], hg[MH];
-                lo[0] = x;
-#pragma unroll
-                for (int i = 1; i < 8; ++i)
-                    lo[i] = lo[i - 1] * q;
-                const R q2 = q * q, q4 = q2 * q2, q8 = q4 * q4;
-                hi[0] = R(1);
-                hg[0] = g2;
-#pragma unroll
-                for (int j = 1; j < MH; ++j) {
-                    hi[j] = j == 1 ? q8 : hi[j - 1] * q8;
-                    hg[j] = hi[j] * g2;
-                }
-#pragma unroll
-                for (int j = 0; j < MH; ++j)
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        const int m = 8 * j + i;
-                        if (FIRST && u == 0) {
-                            pa[m][v] = j == 0 ? lo[i] : lo[i] * hi[j];
-                            pb[m][v] = lo[i] * hg[j];
-                        } else {
-                            pa[m][v] = j == 0 ? pa[m][v] + lo[i] : fused(lo[i], hi[j], pa[m][v]);
-                            pb[m][v] = fused(lo[i], hg[j], pb[m][v]);
-                        }
-                    }
-            } else {
-#pragma unroll
-                for (int m = 0; m < M; ++m) {
-                    if (FIRST && u == 0) {
-                        pa[m][v] = x;
-                        pb[m][v] = x * g2;
-                    } else {
-                        pa[m][v] += x;
-                        pb[m][v] = fused(x, g2, pb[m][v]);
-                    }
-                    if (m + 1 < M)
-                        x *= q;
-                }
-            }
+            if (FIRST && u == 0)
+                add_powers<R, M, V, true>(x, q, g2, pa, pb, v);
+            else
+                add_powers<R, M, V, false>(x, q, g2, pa, pb, v);
         }
     }
 }
@@ -1506,19 +1519,29 @@ __device__ __forceinline__ R rate_of_d(R dxx, R dxy, R dyy)
     return sqrt(R(0.5) * (dxx * dxx + R(2) * dxy * dxy + dyy * dyy));
 }
 
-template <typename P, typename R>
-__global__ __launch_bounds__(kBlock) void k_grid_step(char *__restrict__ ws,
-                                                      const ChanDev *__restrict__ chans,
-                                                      const NodeTile *__restrict__ tiles,
-                                                      const int64_t *__restrict__ tcount,
-                                                      int trel)
+// Entry bookkeeping of block bi (lg = B - 1 - bi, step 2^lg): the newest
+// and oldest entry it holds after the combinations and the push of step t,
+// and the age at step t of its i-th entry.
+__device__ __forceinline__ int64_t grid_newest(int64_t t, int lg, int C)
 {
-    const NodeTile tl = tiles[blockIdx.x];
-    const ChanDev *c = chans + tl.ch;
-    const int n = tl.n0 + threadIdx.x;
-    if (c->qb == 0 || n >= c->n)
-        return;
-    const int64_t t = *tcount + trel;
+    return C + (t >> lg);
+}
+__device__ __forceinline__ int64_t grid_oldest(int64_t t, int lg)
+{
+    return 2 * ((t >> (lg + 1)) + 1);
+}
+__device__ __forceinline__ int64_t grid_age(int64_t t, int64_t i, int lg, int C)
+{
+    const int64_t step = int64_t(1) << lg;
+    return t - (step * i - (2 * step - 1) * (int64_t)C);
+}
+
+// The combinations due at step t, oldest block first, then the push of step
+// t's entry (node n; the velocity of step t is in place).
+template <typename P, typename R>
+__device__ __forceinline__ void grid_update(char *__restrict__ ws, const ChanDev *c, int n,
+                                            int64_t t)
+{
     const int B = c->qb, C = c->qc;
     const size_t np = (size_t)c->np;
     const size_t dplane = (size_t)B * C * np;
@@ -1528,13 +1551,11 @@ __global__ __launch_bounds__(kBlock) void k_grid_step(char *__restrict__ ws,
     R *gd = reinterpret_cast<R *>(ws + c->off_grid_d);
     auto row = [&](int bi, int slot) { return ((size_t)bi * C + slot) * np + n; };
 
-    // gradient of this step's velocity
     const P *vel = reinterpret_cast<const P *>(ws + c->off_vel);
     const int y = n / c->lx, x = n - y * c->lx;
     P kxx, kxy, kyx, kyy;
     velocity_gradient<P>(vel, vel + np, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
 
-    // combine the blocks whose pair is due, oldest block first
     for (int bi = 0; bi < B; ++bi) {
         const int sh = B - bi;  // log2 of the block's combination period
         if ((t & ((int64_t(1) << sh) - 1)) != 0)
@@ -1559,52 +1580,255 @@ __global__ __launch_bounds__(kBlock) void k_grid_step(char *__restrict__ ws,
             }
         }
     }
-    // push the entry of step t: entry C + t of the newest block
-    {
-        const size_t d = row(B - 1, (int)(t % C));
-        gs[d] = (R)kxy;
-        if (has_r) {
-            const R dd[3] = {(R)(P(2) * kxx), (R)(kxy + kyx), (R)(P(2) * kyy)};
-            for (int q = 0; q < 3; ++q)
-                gd[q * dplane + d] = dd[q];
-            gr[d] = (R)shear_rate<P>(kxx, kxy, kyx, kyy);
-        }
+    const size_t d = row(B - 1, (int)(t % C));
+    gs[d] = (R)kxy;
+    if (has_r) {
+        const R dd[3] = {(R)(P(2) * kxx), (R)(kxy + kyx), (R)(P(2) * kyy)};
+        for (int q = 0; q < 3; ++q)
+            gd[q * dplane + d] = dd[q];
+        gr[d] = (R)shear_rate<P>(kxx, kxy, kyx, kyy);
     }
+}
 
-    // Eq. gitt on the grid, newest entry first: trapezoid weights from the
-    // neighbours' ages, strain gamma(t, t0) = sum of (mean s) x (step) over
-    // the entries from the newest-but-one down to this one.
-    const Decay<R> dec(c);
+// Running state of Eq. gitt on the grid, entries visited newest first:
+// trapezoid weights from the neighbours' ages, strain gamma = sum of (mean
+// s) x (step) over the entries from the newest-but-one down to the current.
+struct GridSums {
     double sxy = 0.0, sxx = 0.0, gam = 0.0;
     int64_t a_prev = 0;
     bool first = true;
+};
+
+// Row of the i-th entry of block bi (node n).
+__device__ __forceinline__ size_t grid_row(const ChanDev *c, int n, int bi, int64_t i)
+{
+    return ((size_t)bi * c->qc + (size_t)(i % c->qc)) * (size_t)c->np + n;
+}
+
+
+// Visit the i-th entry of block bi at step t, with shear rate sv and
+// |gamma_dot| rv; returns its decay rate and E(age) in the history precision.
+template <typename R>
+__device__ __forceinline__ void grid_visit(R sv, R rv, int C, int bi, int lg, int64_t i,
+                                           int64_t i_old, int64_t t, const Decay<R> &dec,
+                                           GridSums &g, R &rate, R &e)
+{
+    const int64_t step = int64_t(1) << lg;
+    const int64_t age = grid_age(t, i, lg, C);
+    // the older neighbour: the next entry of the block, or the newest of
+    // block bi - 1 (2 steps back), or none for the oldest entry of all
+    const int64_t a_next = i > i_old ? age + step : (bi > 0 ? age + 2 * step : age);
+    if (!g.first)
+        g.gam += (double)sv * (double)step;
+    rate = decay_rate<R>(dec, rv);
+    e = decay_pow((R)age, rate);
+    const double xw = 0.5 * (double)(a_next - g.a_prev) * (double)(sv * e);
+    g.sxy += xw;
+    g.sxx += 2.0 * g.gam * xw;
+    g.a_prev = age;
+    g.first = false;
+}
+
+// Visit entries hi, hi - 1, ..., lo of block bi (newest first), loading L
+// entries ahead of their use; fn(i, sv, rate, e) after each visit.
+template <typename R, int L, typename Fn>
+__device__ __forceinline__ void grid_range(const R *__restrict__ gs, const R *__restrict__ gr,
+                                           bool has_r, const ChanDev *c, int n, int bi, int lg,
+                                           int64_t hi, int64_t lo, int64_t i_old, int64_t t,
+                                           const Decay<R> &dec, GridSums &g, Fn &&fn)
+{
+    for (int64_t i = hi; i >= lo; i -= L) {
+        R sv[L], rv[L];
+#pragma unroll
+        for (int u = 0; u < L; ++u)
+            if (i - u >= lo) {
+                const size_t o = grid_row(c, n, bi, i - u);
+                sv[u] = gs[o];
+                rv[u] = has_r ? gr[o] : fabs(sv[u]);
+            }
+#pragma unroll
+        for (int u = 0; u < L; ++u)
+            if (i - u >= lo) {
+                R rate, e;
+                grid_visit<R>(sv[u], rv[u], c->qc, bi, lg, i - u, i_old, t, dec, g, rate, e);
+                fn(i - u, sv[u], rate, e);
+            }
+    }
+}
+
+// Temporal blocking on the grid.  The grid takes blocks of M = min(steps per
+// pass, kMaxGridBlock) steps: per step it reads 1/M of its entries in the
+// pass, plus the entries outside the interior (below), whose count grows
+// with M.  For a block of steps t0..t1 = t0 + M - 1, entry i of block bi
+// with grid_oldest(t1) < i < grid_newest(t0) is held at every step of the
+// block with the same neighbours, so its trapezoid weight
+// stays `step`, its decay is E(age(t0)) q^m at step t0 + m, and its strain
+// grows by the same Delta_m (the strain of the entries pushed since t0) as
+// every older entry: combinations only regroup the strain of newer entries.
+// These interior entries enter the block sums A_m, B_m of the pass at t0
+// exactly as the window entries do; the other entries (the newest ones,
+// received since t0 and the one newest at t0, and the oldest ones, combined
+// away during the block and the oldest kept) are visited every step.  The two
+// sets are disjoint when C >= M + 2.
+__host__ __device__ constexpr bool grid_blockable(int C, int M) { return M > 1 && C >= M + 2; }
+
+// The full walk at step t.  With M > 1 it also forms, for m = 1..M-1, the
+// block sums of the interior entries of the block t..t+M-1 (blk planes m and
+// kPlaneB + m) and, per grid block, their strain (plane kPlaneGrid + bi).
+template <typename P, typename R, int M>
+__device__ __forceinline__ void grid_walk(char *__restrict__ ws, const ChanDev *c, int n,
+                                          int64_t t)
+{
+#pragma clang fp contract(off)
+    constexpr int F = 64;  // FP32 partial sums flushed into FP64 every F entries
+    const int B = c->qb, C = c->qc;
+    const size_t np = (size_t)c->np;
+    const bool has_r = c->has_r != 0;
+    const R *gs = reinterpret_cast<const R *>(ws + c->off_grid_s);
+    const R *gr = reinterpret_cast<const R *>(ws + c->off_grid_r);
+    double *blk = reinterpret_cast<double *>(ws + c->off_blk);
+    const Decay<R> dec(c);
+    GridSums g;
+    R pa[M][1], pb[M][1];
+    Acc<R> A[M][1], Bs[M][1];
+    int cnt = 0;
+    const int64_t t1 = t + M - 1;
     for (int bi = B - 1; bi >= 0; --bi) {
-        const int lg = B - 1 - bi;  // log2 of the block's step
+        const int lg = B - 1 - bi;
         const int64_t step = int64_t(1) << lg;
-        const int64_t i_new = C + (t >> lg);
-        const int64_t i_old = 2 * ((t >> (lg + 1)) + 1);
-        int64_t age = t - (step * i_new - (2 * step - 1) * (int64_t)C);
-        int slot = (int)(i_new % C);
-        for (int64_t i = i_new; i >= i_old; --i) {
-            const int64_t a_next = i > i_old ? age + step : (bi > 0 ? age + 2 * step : age);
-            const size_t o = row(bi, slot);
-            const R sv = gs[o];
-            const R rv = has_r ? gr[o] : fabs(sv);
-            if (!first)
-                gam += (double)sv * (double)step;
-            const R e = decay_pow((R)age, decay_rate<R>(dec, rv));
-            const double xw = 0.5 * (double)(a_next - a_prev) * (double)(sv * e);
-            sxy += xw;
-            sxx += 2.0 * gam * xw;
-            a_prev = age;
-            first = false;
-            age += step;
-            slot = slot == 0 ? C - 1 : slot - 1;
-        }
+        const int64_t i_new = grid_newest(t, lg, C), i_old = grid_oldest(t, lg);
+        const int64_t in_hi = i_new - 1, in_lo = grid_oldest(t1, lg) + 1;
+        double strain = 0.0;
+        constexpr int L = M == 1 ? 4 : 8;  // entries loaded ahead
+        grid_range<R, L>(gs, gr, has_r, c, n, bi, lg, i_new, i_old, i_old, t, dec, g,
+                      [&](int64_t i, R sv, R rate, R e) {
+                          if (M > 1 && i >= in_lo && i <= in_hi) {
+                              strain += (double)sv * (double)step;
+                              const R x = (R)step * (sv * e);
+                              const R q = decay_pow(R(1), rate);
+                              const R g2 = R(2) * (R)g.gam;
+                              if (cnt == 0)
+                                  add_powers<R, M, 1, true>(x, q, g2, pa, pb, 0);
+                              else
+                                  add_powers<R, M, 1, false>(x, q, g2, pa, pb, 0);
+                              if (++cnt == F) {
+                                  flush<R, 1, M>(pa, pb, A, Bs);
+                                  cnt = 0;
+                              }
+                          }
+                      });
+        if (M > 1)
+            blk[(kPlaneGrid + bi) * np + n] = strain;
     }
     P *sig = reinterpret_cast<P *>(ws + c->off_sig);
-    sig[n] = (P)(c->g_inf * sxy);
-    sig[np + n] = (P)(c->g_inf * sxx);
+    sig[n] = (P)(c->g_inf * g.sxy);
+    sig[np + n] = (P)(c->g_inf * g.sxx);
+    if (M > 1) {
+        if (cnt > 0)
+            flush<R, 1, M>(pa, pb, A, Bs);
+#pragma unroll
+        for (int m = 1; m < M; ++m) {
+            blk[m * np + n] = A[m][0].value();
+            blk[(kPlaneB + m) * np + n] = Bs[m][0].value();
+        }
+    }
+}
+
+// Step t0 + m (0 < m < M) of a block: the entries outside the interior
+// directly, the interior through the pass's sums and strains.
+template <typename P, typename R>
+__device__ __forceinline__ void grid_edges(char *__restrict__ ws, const ChanDev *c, int n,
+                                           int64_t t, int m, int M)
+{
+    const int B = c->qb, C = c->qc;
+    const size_t np = (size_t)c->np;
+    const bool has_r = c->has_r != 0;
+    const R *gs = reinterpret_cast<const R *>(ws + c->off_grid_s);
+    const R *gr = reinterpret_cast<const R *>(ws + c->off_grid_r);
+    const double *blk = reinterpret_cast<const double *>(ws + c->off_blk);
+    const Decay<R> dec(c);
+    const int64_t t0 = t - m, t1 = t0 + M - 1;
+    GridSums g;
+    double delta = 0.0;
+    auto none = [](int64_t, R, R, R) {};
+    for (int bi = B - 1; bi >= 0; --bi) {
+        const int lg = B - 1 - bi;
+        const int64_t i_new = grid_newest(t, lg, C), i_new0 = grid_newest(t0, lg, C);
+        const int64_t i_old = grid_oldest(t, lg), i_old1 = grid_oldest(t1, lg);
+        grid_range<R, 4>(gs, gr, has_r, c, n, bi, lg, i_new, i_new0, i_old, t, dec, g, none);
+        if (bi == B - 1)
+            delta = g.gam;  // entries C + t0 .. C + t - 1: the shear rates of steps t0..t-1
+        if (i_old1 + 1 <= i_new0 - 1) {
+            g.gam += blk[(kPlaneGrid + bi) * np + n];
+            g.a_prev = grid_age(t, i_old1 + 1, lg, C);
+        }
+        grid_range<R, 4>(gs, gr, has_r, c, n, bi, lg, i_old1, i_old, i_old, t, dec, g, none);
+    }
+    const double A = blk[m * np + n], Bm = blk[(kPlaneB + m) * np + n];
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    sig[n] = (P)(c->g_inf * (A + g.sxy));
+    sig[np + n] = (P)(c->g_inf * (Bm + 2.0 * delta * A + g.sxx));
+}
+
+// Unblocked grid step (M = 1): update and full walk every step.
+template <typename P, typename R>
+__global__ __launch_bounds__(kBlock) void k_grid_step(char *__restrict__ ws,
+                                                      const ChanDev *__restrict__ chans,
+                                                      const NodeTile *__restrict__ tiles,
+                                                      const int64_t *__restrict__ tcount,
+                                                      int trel)
+{
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const int n = tl.n0 + threadIdx.x;
+    if (c->qb == 0 || n >= c->n)
+        return;
+    const int64_t t = *tcount + trel;
+    grid_update<P, R>(ws, c, n, t);
+    grid_walk<P, R, 1>(ws, c, n, t);
+}
+
+// First step of a block of M: update, full walk and the interior sums.
+// Channels too short for blocking (C < M + 2) take the full walk only.
+template <typename P, typename R, int M>
+__global__ __launch_bounds__(kBlock) void k_grid_pass(char *__restrict__ ws,
+                                                      const ChanDev *__restrict__ chans,
+                                                      const NodeTile *__restrict__ tiles,
+                                                      const int64_t *__restrict__ tcount,
+                                                      int trel)
+{
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const int n = tl.n0 + threadIdx.x;
+    if (c->qb == 0 || n >= c->n)
+        return;
+    const int64_t t = *tcount + trel;
+    grid_update<P, R>(ws, c, n, t);
+    if (grid_blockable(c->qc, M))
+        grid_walk<P, R, M>(ws, c, n, t);
+    else
+        grid_walk<P, R, 1>(ws, c, n, t);
+}
+
+// Step m (0 < m < M) of a block: update and the edge walk.
+template <typename P, typename R>
+__global__ __launch_bounds__(kBlock) void k_grid_edges(char *__restrict__ ws,
+                                                       const ChanDev *__restrict__ chans,
+                                                       const NodeTile *__restrict__ tiles,
+                                                       const int64_t *__restrict__ tcount,
+                                                       int trel, int m, int M)
+{
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const int n = tl.n0 + threadIdx.x;
+    if (c->qb == 0 || n >= c->n)
+        return;
+    const int64_t t = *tcount + trel;
+    grid_update<P, R>(ws, c, n, t);
+    if (grid_blockable(c->qc, M))
+        grid_edges<P, R>(ws, c, n, t, m, M);
+    else
+        grid_walk<P, R, 1>(ws, c, n, t);
 }
 
 __global__ void k_tick(int64_t *tcount, int64_t add)
@@ -1885,11 +2109,32 @@ void launch_hist_step(int prec, int m, char *ws, const ChanDev *chans, const Nod
                                            st, ws, chans, tiles, tcount, trel, m));
 }
 
-void launch_grid_step(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
-                      int n_tiles, const int64_t *tcount, int trel, hipStream_t st)
+void launch_grid_step(int prec, int block, int m, char *ws, const ChanDev *chans,
+                      const NodeTile *tiles, int n_tiles, const int64_t *tcount, int trel,
+                      hipStream_t st)
 {
-    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_grid_step<P, H>), dim3(n_tiles), dim3(kBlock),
-                                           0, st, ws, chans, tiles, tcount, trel));
+    block = block < kMaxGridBlock ? block : kMaxGridBlock;
+    m %= block;
+    if (block <= 1) {
+        LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_grid_step<P, H>), dim3(n_tiles),
+                                               dim3(kBlock), 0, st, ws, chans, tiles, tcount,
+                                               trel));
+    } else if (m > 0) {
+        LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_grid_edges<P, H>), dim3(n_tiles),
+                                               dim3(kBlock), 0, st, ws, chans, tiles, tcount,
+                                               trel, m, block));
+    } else {
+#define LBMAX_GRID_PASS(MM)                                                                   \
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_grid_pass<P, H, MM>), dim3(n_tiles), dim3(kBlock), \
+                                           0, st, ws, chans, tiles, tcount, trel))
+        switch (block) {
+        case 2: LBMAX_GRID_PASS(2); break;
+        case 4: LBMAX_GRID_PASS(4); break;
+        case 8: LBMAX_GRID_PASS(8); break;
+        default: LBMAX_GRID_PASS(16); break;
+        }
+#undef LBMAX_GRID_PASS
+    }
 }
 
 void launch_tick(int64_t *tcount, int64_t add, hipStream_t st)

@@ -28,8 +28,13 @@ lb_status fail(lb_status s, const std::string &msg)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Block-sum planes of a channel, doubles per node: A_m and B_m (and the
+// sigma_yy sums of a full-tensor channel), then one interior strain per
+// block of a grid channel.
+int blk_planes(const ChanDev &c) { return c.finger ? 3 * kMaxBlock : 2 * kMaxBlock + c.qb; }
+
 constexpr uint64_t kStateMagic = 0x4C424D4158535431ull;  // "LBMAXST1"
-constexpr uint32_t kStateVersion = 4;
+constexpr uint32_t kStateVersion = 5;
 constexpr size_t kStateHeader = 256;
 constexpr int64_t kMaxStepsPerBatch = int64_t(1) << 20;
 
@@ -216,8 +221,7 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
                                      c.max_chunks * c.np * sizeof(double),
                            256);
         c.off_blk = (int64_t)off;
-        off = align_up(off + (size_t)(c.finger ? 3 : 2) * kMaxBlock * c.np * sizeof(double),
-                       256);
+        off = align_up(off + (size_t)blk_planes(c) * c.np * sizeof(double), 256);
         const size_t grows = (size_t)c.qb * c.qc;  // 0 without a grid
         c.off_grid_s = (int64_t)off;
         off = align_up(off + grows * hplane, 256);
@@ -478,8 +482,8 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
         HIP_TRY(h, hipEventRecord(e[2], st));
     }
     if (h->any_grid)
-        launch_grid_step(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
-                         h->d_tcount, trel, st);
+        launch_grid_step(h->pc, h->block, m, h->ws, h->d_chans, h->d_node_tiles,
+                         h->n_node_tiles, h->d_tcount, trel, st);
     if (h->any_inst)
         launch_inst_step(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
                          h->d_tcount, trel, st);
@@ -608,7 +612,7 @@ std::vector<Section> state_sections(const lb_handle *h, int ci, int64_t t)
         if (c.has_r)
             v.push_back({c.off_ring_r, (size_t)c.n_hist, hrowb, hpitch});
     }
-    v.push_back({c.off_blk, (size_t)(c.finger ? 3 : 2) * kMaxBlock, (size_t)c.n * sizeof(double),
+    v.push_back({c.off_blk, (size_t)blk_planes(c), (size_t)c.n * sizeof(double),
                  (size_t)c.np * sizeof(double)});
     return v;
 }
@@ -1125,6 +1129,8 @@ lb_status lb_set_params(lb_handle *h, int32_t ch, double g_inf, double tau_m, do
     c.inv_gc = std::isinf(gamma_c) ? 0.0 : 1.0 / gamma_c;
     c.l2_tau = M_LOG2E * c.inv_tau;
     c.l2_gc = M_LOG2E * c.inv_gc;
+    // block sums already formed hold the old decay rates: start a new block
+    h->block_pos = 0;
     launch_set_params(h->d_chans, ch, g_inf, tau_m, gamma_c, h->stream);
     return check_launch(h, "set_params");
 }

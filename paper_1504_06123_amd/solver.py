@@ -211,7 +211,7 @@ class Solver:
 
 
 STATE_MAGIC = 0x4C424D4158535431
-STATE_VERSION = 4
+STATE_VERSION = 5
 
 
 def pack_state_header(t: int, n_ch: int, precision: str, total_bytes: int,
@@ -259,7 +259,7 @@ def state_layout(channels: Sequence, precision: str = "f32"):
             for name in ("ring_s",) + (() if uni else ("ring_r",)):
                 sec[name] = (off, int(ch.n_hist), N)
                 off = up(off + int(ch.n_hist) * N * RH)
-        nblk = 96 if finger else 64
+        nblk = 96 if finger else 64 + B
         sec["blk"] = (off, nblk, N)   # doubles
         off = up(off + nblk * N * 8)
         sec["force"] = (off, 1, 2)
