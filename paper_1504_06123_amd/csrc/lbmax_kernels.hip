@@ -1608,10 +1608,11 @@ __device__ __forceinline__ size_t grid_row(const ChanDev *c, int n, int bi, int6
 
 // Visit the i-th entry of block bi at step t, with shear rate sv and
 // |gamma_dot| rv; returns its decay rate and E(age) in the history precision.
+// Without `direct` the entry's trapezoid terms are left to the caller.
 template <typename R>
 __device__ __forceinline__ void grid_visit(R sv, R rv, int C, int bi, int lg, int64_t i,
                                            int64_t i_old, int64_t t, const Decay<R> &dec,
-                                           GridSums &g, R &rate, R &e)
+                                           GridSums &g, R &rate, R &e, bool direct = true)
 {
     const int64_t step = int64_t(1) << lg;
     const int64_t age = grid_age(t, i, lg, C);
@@ -1622,9 +1623,11 @@ __device__ __forceinline__ void grid_visit(R sv, R rv, int C, int bi, int lg, in
         g.gam += (double)sv * (double)step;
     rate = decay_rate<R>(dec, rv);
     e = decay_pow((R)age, rate);
-    const double xw = 0.5 * (double)(a_next - g.a_prev) * (double)(sv * e);
-    g.sxy += xw;
-    g.sxx += 2.0 * g.gam * xw;
+    if (direct) {
+        const double xw = 0.5 * (double)(a_next - g.a_prev) * (double)(sv * e);
+        g.sxy += xw;
+        g.sxx += 2.0 * g.gam * xw;
+    }
     g.a_prev = age;
     g.first = false;
 }
@@ -1635,7 +1638,8 @@ template <typename R, int L, typename Fn>
 __device__ __forceinline__ void grid_range(const R *__restrict__ gs, const R *__restrict__ gr,
                                            bool has_r, const ChanDev *c, int n, int bi, int lg,
                                            int64_t hi, int64_t lo, int64_t i_old, int64_t t,
-                                           const Decay<R> &dec, GridSums &g, Fn &&fn)
+                                           const Decay<R> &dec, GridSums &g, Fn &&fn,
+                                           int64_t sk_lo = 1, int64_t sk_hi = 0)
 {
     for (int64_t i = hi; i >= lo; i -= L) {
         R sv[L], rv[L];
@@ -1650,7 +1654,8 @@ __device__ __forceinline__ void grid_range(const R *__restrict__ gs, const R *__
         for (int u = 0; u < L; ++u)
             if (i - u >= lo) {
                 R rate, e;
-                grid_visit<R>(sv[u], rv[u], c->qc, bi, lg, i - u, i_old, t, dec, g, rate, e);
+                grid_visit<R>(sv[u], rv[u], c->qc, bi, lg, i - u, i_old, t, dec, g, rate, e,
+                              i - u < sk_lo || i - u > sk_hi);
                 fn(i - u, sv[u], rate, e);
             }
     }
@@ -1716,16 +1721,23 @@ __device__ __forceinline__ void grid_walk(char *__restrict__ ws, const ChanDev *
                                   cnt = 0;
                               }
                           }
-                      });
+                      },
+                      in_lo, M > 1 ? in_hi : in_lo - 1);
         if (M > 1)
             blk[(kPlaneGrid + bi) * np + n] = strain;
     }
-    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
-    sig[n] = (P)(c->g_inf * g.sxy);
-    sig[np + n] = (P)(c->g_inf * g.sxx);
+    // the interior's terms of step t are its m = 0 block sums
+    double a0 = 0.0, b0 = 0.0;
     if (M > 1) {
         if (cnt > 0)
             flush<R, 1, M>(pa, pb, A, Bs);
+        a0 = A[0][0].value();
+        b0 = Bs[0][0].value();
+    }
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    sig[n] = (P)(c->g_inf * (g.sxy + a0));
+    sig[np + n] = (P)(c->g_inf * (g.sxx + b0));
+    if (M > 1) {
 #pragma unroll
         for (int m = 1; m < M; ++m) {
             blk[m * np + n] = A[m][0].value();
