@@ -336,8 +336,8 @@ def bench_batched(steps: int = 2000):
     nodes = wl.nodes
     s = Solver(wl.channels, precision="f32")
     s.step(64)
-    best = autotune.tune(s, autotune.candidates(s, blocks=(1, 4, 8, 16, 32),
-                                                chunk_lens=(256, 1024, 4096),
+    best = autotune.tune(s, autotune.candidates(s, blocks=(8, 16, 32),
+                                                chunk_lens=(256, 512, 1024, 2048, 4096),
                                                 graphs=(0, 64)), min_steps=64)
     s.step(64)
     torch.cuda.synchronize()

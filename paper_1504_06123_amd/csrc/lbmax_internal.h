@@ -10,6 +10,7 @@
 namespace lbmax {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kWave = 64;          // threads per wavefront
 constexpr int kNodeAlign = 64;     // node-plane stride is a multiple of this
 constexpr int kMinChunkLen = 128;  // shortest age range of one history chunk
 constexpr int kMaxChunks = 64;     // most age ranges per channel
@@ -67,7 +68,10 @@ struct NodeTile {
     int32_t ch, n0;
 };
 
-// One workgroup of the history kernel: 256*vec nodes x ages [k0, k1).
+// One unit of history work: nodes [n0, n0 + span) x ages [k0, k1), span =
+// 64*vec for the simple-shear pass (one wavefront per tile, four tiles per
+// workgroup), 256 for the full-tensor and accumulated-strain passes (one
+// workgroup per tile).
 struct HistTile {
     int32_t ch, n0, k0, k1, chunk, pad;
 };

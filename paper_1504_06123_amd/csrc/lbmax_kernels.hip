@@ -569,7 +569,7 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
 {
     const int H = c->n_hist;
     const size_t np = (size_t)c->np;
-    const int first = tl.n0 + (int)threadIdx.x * V;  // lane's first node
+    const int first = tl.n0 + (int)(threadIdx.x % kWave) * V;  // lane's first node
     // A lane past the channel end shadows the last vector of the channel (in
     // bounds, results discarded); nodes past the end inside a vector read the
     // zero padding of the ring.
@@ -681,19 +681,32 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
 }
 
 // One launch per (lane width V, block length M): the tiles of the channels
-// whose lane width is V.  Plain form: one workgroup per tile.
+// whose lane width is V, one wavefront per tile (64 V nodes), so channels
+// narrower than a workgroup leave no wavefront idle.  Plain form: the four
+// wavefronts of workgroup b take tiles 4b .. 4b + 3.
+// FP32 histories fit two wavefronts per SIMD at every block length (the
+// 32-step pass needs the bound to get there); FP64 ones keep the default.
+template <typename R>
+constexpr int pass_waves_per_simd()
+{
+    return sizeof(R) == 4 ? 2 : 1;
+}
+
 template <typename P, typename R, int V, int M, int U, int F>
-__global__ __launch_bounds__(kBlock) void k_hist_pass(char *__restrict__ ws,
+__global__ __launch_bounds__(kBlock, pass_waves_per_simd<R>()) void k_hist_pass(char *__restrict__ ws,
                                                       const ChanDev *__restrict__ chans,
                                                       const HistTile *__restrict__ tiles,
+                                                      int n_tiles,
                                                       const int64_t *__restrict__ tcount,
                                                       int trel)
 {
-    const HistTile tl = tiles[blockIdx.x];
+    // wave-uniform, so the tile and channel fields stay in scalar registers
+    const int i = (int)blockIdx.x * (kBlock / kWave) +
+                  __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (i >= n_tiles)
+        return;  // the last workgroup's spare wavefronts
+    const HistTile tl = tiles[i];
     const ChanDev *c = chans + tl.ch;
-    // A wavefront whose nodes all lie past the channel has nothing to do.
-    if (tl.n0 + (int)(threadIdx.x & ~63u) * V >= c->n)
-        return;
     const int64_t t = *tcount + trel;
     if (c->has_r)
         pass_tile<P, R, V, M, U, F, true>(ws, c, tl, t);
@@ -701,33 +714,31 @@ __global__ __launch_bounds__(kBlock) void k_hist_pass(char *__restrict__ ws,
         pass_tile<P, R, V, M, U, F, false>(ws, c, tl, t);
 }
 
-// Persistent form: as many workgroups as fit on the chip at once; each claims
-// the next tile of the list (longest first) from a counter until the list
-// is exhausted.  The counter was zeroed by the lattice kernel of this step.
+// Persistent form: as many workgroups as fit on the chip at once; each
+// wavefront claims the next tile of the list (longest first) from a counter
+// until the list is exhausted.  The counter was zeroed by the lattice kernel
+// of this step.
 template <typename P, typename R, int V, int M, int U, int F>
-__global__ __launch_bounds__(kBlock) void k_hist_pass_persistent(
+__global__ __launch_bounds__(kBlock, pass_waves_per_simd<R>()) void k_hist_pass_persistent(
     char *__restrict__ ws, const ChanDev *__restrict__ chans,
     const HistTile *__restrict__ tiles, int n_tiles, const int64_t *__restrict__ tcount,
     int trel, int *__restrict__ counter)
 {
-    __shared__ int claimed;
     const int64_t t = *tcount + trel;
+    const bool leader = threadIdx.x % kWave == 0;
     for (;;) {
-        if (threadIdx.x == 0)
-            claimed = atomicAdd(counter, 1);
-        __syncthreads();
-        const int i = claimed;
-        __syncthreads();  // every lane has read `claimed` before it changes
+        int i = 0;
+        if (leader)
+            i = atomicAdd(counter, 1);
+        i = __builtin_amdgcn_readfirstlane(i);  // the claim of the first lane, wave-uniform
         if (i >= n_tiles)
-            break;  // uniform across the workgroup: all waves leave together
+            break;  // uniform across the wavefront
         const HistTile tl = tiles[i];
         const ChanDev *c = chans + tl.ch;
-        if (tl.n0 + (int)(threadIdx.x & ~63u) * V < c->n) {
-            if (c->has_r)
-                pass_tile<P, R, V, M, U, F, true>(ws, c, tl, t);
-            else
-                pass_tile<P, R, V, M, U, F, false>(ws, c, tl, t);
-        }
+        if (c->has_r)
+            pass_tile<P, R, V, M, U, F, true>(ws, c, tl, t);
+        else
+            pass_tile<P, R, V, M, U, F, false>(ws, c, tl, t);
     }
 }
 
@@ -1355,77 +1366,69 @@ __global__ __launch_bounds__(kBlock) void k_inst_step(char *__restrict__ ws,
 // FP64 combine of the per-chunk partials of a split window, newest chunk
 // first: A_m = sum_c A_{m,c}, B_m = sum_c (2 O_c A_{m,c} + B_{m,c}), where
 // O_c = sum of the strain totals T of the newer chunks (the accumulated
-// strain at the chunk's start).  Writes sigma of the pass step and the block
-// sums for the following steps.
+// strain at the chunk's start).  One thread per node and step m of the block
+// (grid: node tiles x block); m = 0 writes sigma of the pass step, m > 0 the
+// block sums for the following steps.
 // ---------------------------------------------------------------------------
 template <typename P>
 __global__ __launch_bounds__(kBlock) void k_combine(char *__restrict__ ws,
                                                     const ChanDev *__restrict__ chans,
-                                                    const NodeTile *__restrict__ tiles,
-                                                    int block)
+                                                    const NodeTile *__restrict__ tiles)
 {
     const NodeTile tl = tiles[blockIdx.x];
     const ChanDev *c = chans + tl.ch;
     const int n = tl.n0 + threadIdx.x;
+    const int m = blockIdx.y;
     if (c->nchunks == 1 || n >= c->n)
         return;
     const size_t np = (size_t)c->np;
     const size_t pplane = (size_t)c->max_chunks * np;
     const double *part = reinterpret_cast<const double *>(ws + c->off_part);
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    double *blk = reinterpret_cast<double *>(ws + c->off_blk);
     if (c->finger) {
         // sum_c O_c S_c O_c^T, O_0 = I, O_{c+1} = O_c T_c
-        double X[kMaxBlock], Y[kMaxBlock], Z[kMaxBlock];
-        for (int m = 0; m < block; ++m)
-            X[m] = Y[m] = Z[m] = 0.0;
+        double X = 0.0, Y = 0.0, Z = 0.0;
         Mat2 O = {1.0, 0.0, 0.0, 1.0};
         for (int k = 0; k < c->nchunks; ++k) {
             const size_t at = (size_t)k * np + n;
-            for (int m = 0; m < block; ++m) {
-                double sx = part[m * pplane + at], sy = part[(kMaxBlock + m) * pplane + at],
-                       sz = part[(2 * kMaxBlock + m) * pplane + at];
-                congruence(O, sx, sy, sz);
-                X[m] += sx;
-                Y[m] += sy;
-                Z[m] += sz;
-            }
+            double sx = part[m * pplane + at], sy = part[(kMaxBlock + m) * pplane + at],
+                   sz = part[(2 * kMaxBlock + m) * pplane + at];
+            congruence(O, sx, sy, sz);
+            X += sx;
+            Y += sy;
+            Z += sz;
             const Mat2 T = {part[(3 * kMaxBlock + 0) * pplane + at],
                             part[(3 * kMaxBlock + 1) * pplane + at],
                             part[(3 * kMaxBlock + 2) * pplane + at],
                             part[(3 * kMaxBlock + 3) * pplane + at]};
             O = mat_mul(O, T);
         }
-        P *sig = reinterpret_cast<P *>(ws + c->off_sig);
-        sig[n] = (P)(c->g_inf * Y[0]);
-        sig[np + n] = (P)(c->g_inf * X[0]);
-        sig[2 * np + n] = (P)(c->g_inf * Z[0]);
-        double *blk = reinterpret_cast<double *>(ws + c->off_blk);
-        for (int m = 1; m < block; ++m) {
-            blk[m * np + n] = X[m];
-            blk[(kMaxBlock + m) * np + n] = Y[m];
-            blk[(2 * kMaxBlock + m) * np + n] = Z[m];
+        if (m == 0) {
+            sig[n] = (P)(c->g_inf * Y);
+            sig[np + n] = (P)(c->g_inf * X);
+            sig[2 * np + n] = (P)(c->g_inf * Z);
+        } else {
+            blk[m * np + n] = X;
+            blk[(kMaxBlock + m) * np + n] = Y;
+            blk[(2 * kMaxBlock + m) * np + n] = Z;
         }
         return;
     }
-    double A[kMaxBlock], B[kMaxBlock];
-    for (int m = 0; m < block; ++m)
-        A[m] = B[m] = 0.0;
-    double O = 0.0;
+    double A = 0.0, B = 0.0, O = 0.0;
     for (int k = 0; k < c->nchunks; ++k) {
         const size_t at = (size_t)k * np + n;
-        for (int m = 0; m < block; ++m) {
-            const double a = part[m * pplane + at];
-            A[m] += a;
-            B[m] += 2.0 * O * a + part[(kPlaneB + m) * pplane + at];
-        }
+        const double a = part[m * pplane + at];
+        A += a;
+        B += 2.0 * O * a + part[(kPlaneB + m) * pplane + at];
         O += part[kPlaneT * pplane + at];
     }
-    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
-    sig[n] = (P)(c->g_inf * A[0]);
-    sig[np + n] = (P)(c->g_inf * B[0]);
-    double *blk = reinterpret_cast<double *>(ws + c->off_blk);
-    for (int m = 1; m < block; ++m) {
-        blk[m * np + n] = A[m];
-        blk[(kPlaneB + m) * np + n] = B[m];
+    if (m == 0) {
+        sig[n] = (P)(c->g_inf * A);
+        sig[np + n] = (P)(c->g_inf * B);
+    } else {
+        blk[m * np + n] = A;
+        blk[(kPlaneB + m) * np + n] = B;
     }
 }
 
@@ -1980,7 +1983,9 @@ void launch_hist_pass(int prec, int vec, int block, char *ws, const ChanDev *cha
 {
     if (n_tiles <= 0)
         return;
-    const int grid = persistent_grid > 0 ? std::min(persistent_grid, n_tiles) : n_tiles;
+    const int per_group = kBlock / kWave;  // one tile per wavefront
+    const int groups = (n_tiles + per_group - 1) / per_group;
+    const int grid = persistent_grid > 0 ? std::min(persistent_grid, groups) : groups;
 #define LBMAX_PASS(V, M, U, F)                                                    \
     do {                                                                         \
         if (persistent_grid > 0)                                                 \
@@ -1989,8 +1994,8 @@ void launch_hist_pass(int prec, int vec, int block, char *ws, const ChanDev *cha
                                tcount, trel, counter);                           \
         else                                                                     \
             hipLaunchKernelGGL((k_hist_pass<P, H, V, M, U, F>), dim3(grid),         \
-                               dim3(kBlock), 0, st, ws, chans, tiles, tcount,    \
-                               trel);                                            \
+                               dim3(kBlock), 0, st, ws, chans, tiles, n_tiles,   \
+                               tcount, trel);                                    \
     } while (0)
 #define LBMAX_PASS_SHAPES LBMAX_PASS_SHAPE_TABLE(block, vec, LBMAX_PASS)
     LBMAX_BY_PREC(prec, LBMAX_PASS_SHAPES);
@@ -2110,8 +2115,10 @@ void launch_inst_step(int prec, char *ws, const ChanDev *chans, const NodeTile *
 void launch_combine(int prec, int block, char *ws, const ChanDev *chans, const NodeTile *tiles,
                     int n_tiles, hipStream_t st)
 {
-    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_combine<P>, dim3(n_tiles), dim3(kBlock), 0, st,
-                                           ws, chans, tiles, block));
+    if (n_tiles <= 0 || block <= 0)
+        return;
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_combine<P>, dim3(n_tiles, block), dim3(kBlock), 0,
+                                           st, ws, chans, tiles));
 }
 
 void launch_hist_step(int prec, int m, char *ws, const ChanDev *chans, const NodeTile *tiles,

@@ -185,8 +185,9 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         c.gy = d.gy;
         const int blocks = (c.n + kBlock - 1) / kBlock;
         P.n_node_tiles += blocks;
+        // history tiles: at most one per wavefront of nodes and age chunk
         if (c.qb == 0 && c.law != 2)
-            P.n_hist_tiles_max += blocks * c.max_chunks;
+            P.n_hist_tiles_max += ((c.n + kWave - 1) / kWave) * c.max_chunks;
         stage = std::max(stage, (size_t)4 * c.n);
     }
     P.off_node_tiles = off;
@@ -336,9 +337,10 @@ int effective_vec(int vec, int block)
     return vec;
 }
 
-// Split every channel's window into its chunks and list the workgroups,
-// longest age range first so uneven channels finish together.  A history
-// workgroup covers kBlock*vec nodes.
+// Split every channel's window into its chunks and list the tiles, longest
+// age range first so uneven channels finish together.  A simple-shear tile
+// covers 64*vec nodes (one wavefront), a full-tensor or accumulated-strain
+// tile 256 (one workgroup).
 void build_tiles(lb_handle *h)
 {
     h->node_tiles.clear();
@@ -360,7 +362,7 @@ void build_tiles(lb_handle *h)
         h->any_window = true;
         if (c.nchunks > 1)
             h->any_chunked = true;
-        const int span = kBlock * ((c.finger || c.law) ? 1 : effective_vec(c.vec, h->block));
+        const int span = (c.finger || c.law) ? kBlock : kWave * effective_vec(c.vec, h->block);
         for (int k = 0; k < c.nchunks; ++k) {
             const int k0 = (int)((int64_t)c.n_hist * k / c.nchunks);
             const int k1 = (int)((int64_t)c.n_hist * (k + 1) / c.nchunks);
@@ -418,6 +420,9 @@ void default_tiling(lb_handle *h)
 
 lb_status upload_tables(lb_handle *h)
 {
+    if ((int)h->hist_tiles.size() > h->plan.n_hist_tiles_max ||
+        (int)h->node_tiles.size() > h->plan.n_node_tiles)
+        return fail(LB_EINVAL, "internal: tile lists exceed their workspace area");
     HIP_TRY(h, hipMemcpyAsync(h->d_chans, h->plan.chans.data(),
                               h->plan.chans.size() * sizeof(ChanDev),
                               hipMemcpyHostToDevice, h->stream));
