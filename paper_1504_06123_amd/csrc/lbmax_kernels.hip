@@ -232,24 +232,11 @@ __device__ __forceinline__ void lb_collide_paper(char *__restrict__ ws, const Ch
 // Lattice phase of step t.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
-                                               const ChanDev *__restrict__ chans,
-                                               const NodeTile *__restrict__ tiles,
-                                               const int64_t *__restrict__ tcount,
-                                               int trel, int *__restrict__ tile_counters)
+__device__ __forceinline__ void lb_node(char *__restrict__ ws, const ChanDev *c, int n,
+                                        int64_t t)
 {
-    const NodeTile tl = tiles[blockIdx.x];
-    const ChanDev *c = chans + tl.ch;
-    const int n = tl.n0 + threadIdx.x;
-    // The history pass of this step (if any) claims its tiles from these
-    // counters; it runs after this kernel on the same stream.
-    if (blockIdx.x == 0 && threadIdx.x < kTileCounters)
-        tile_counters[threadIdx.x] = 0;
-    if (n >= c->n)
-        return;
     const int lx = c->lx, ly = c->ly;
     const size_t np = (size_t)c->np;
-    const int64_t t = *tcount + trel;
     R *pop = reinterpret_cast<R *>(ws + c->off_pop);
     const R *__restrict__ src = pop + ((t + 1) & 1) * 9 * np;  // n*(t-1)
     R *__restrict__ dst = pop + (t & 1) * 9 * np;              // n*(t)
@@ -327,6 +314,25 @@ __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
     reinterpret_cast<R *>(ws + c->off_rho)[n] = drho;
 }
 
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
+                                               const ChanDev *__restrict__ chans,
+                                               const NodeTile *__restrict__ tiles,
+                                               const int64_t *__restrict__ tcount,
+                                               int trel, int *__restrict__ tile_counters)
+{
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const int n = tl.n0 + threadIdx.x;
+    // The history pass of this step (if any) claims its tiles from these
+    // counters; it runs after this kernel on the same stream.
+    if (blockIdx.x == 0 && threadIdx.x < kTileCounters)
+        tile_counters[threadIdx.x] = 0;
+    if (n >= c->n)
+        return;
+    lb_node<R>(ws, c, n, *tcount + trel);
+}
+
 // ---------------------------------------------------------------------------
 // History integral, blocked in time.
 //
@@ -347,9 +353,9 @@ __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
 // Delta_m = s_{t0} + ... + s_{t0+m-1},
 //   sigma_xy = G (A_m + new),  sigma_xx = G (B_m + 2 Delta_m A_m + new).
 //
-// Pass layout: a workgroup owns kBlock*V consecutive nodes of one channel and
-// one age range [k0, k1); lane l owns nodes n0 + V*l .. n0 + V*l + V-1 and
-// reads them as one V-wide vector per ring row.  Ages are walked newest to
+// Pass layout: a wavefront owns 64*V consecutive nodes of one channel and one
+// age range [k0, k1) (a tile; four per workgroup); lane l owns nodes
+// n0 + V*l .. n0 + V*l + V-1 and reads them as one V-wide vector per ring row.  Ages are walked newest to
 // oldest (the running FP64 strain gamma is a sum over the rows already
 // read); U rows are loaded before any is used so each wavefront keeps U (2U
 // with |gamma_dot|) vector reads in flight.  In FP32 the terms of F rows
@@ -1439,18 +1445,9 @@ __global__ __launch_bounds__(kBlock) void k_combine(char *__restrict__ ws,
 // strain gamma(t, t - a); at a = m it is Delta_m.
 // ---------------------------------------------------------------------------
 template <typename P, typename R>
-__global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
-                                                      const ChanDev *__restrict__ chans,
-                                                      const NodeTile *__restrict__ tiles,
-                                                      const int64_t *__restrict__ tcount,
-                                                      int trel, int m)
+__device__ __forceinline__ void hist_step_node(char *__restrict__ ws, const ChanDev *c, int n,
+                                               int64_t t, int m)
 {
-    const NodeTile tl = tiles[blockIdx.x];
-    const ChanDev *c = chans + tl.ch;
-    const int n = tl.n0 + threadIdx.x;
-    if (c->qb != 0 || n >= c->n)
-        return;  // grid channels step in k_grid_step
-    const int64_t t = *tcount + trel;
     if (c->finger) {
         finger_step<P, R>(ws, c, n, t, m);
         return;
@@ -1483,22 +1480,56 @@ __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
     // in the pass.
     const Decay<R> dec(c);
     double sxy = 0.5 * (double)s_new, sxx = 0.0, gam = 0.0;
+    // entries at ages 1..m (the one at age m only adds its strain), read
+    // kLoads rows ahead of their use
+    constexpr int kLoads = 8;
     int slot = p;
-    for (int a = 1; a <= m; ++a) {
-        slot = slot == 0 ? H - 1 : slot - 1;
-        const R s = ring_s[(size_t)slot * np + n];
-        gam += (double)s;
-        if (a < m && a <= H - 1) {
-            const R r = c->has_r ? ring_r[(size_t)slot * np + n] : fabs(s);
-            const double w = (a == H - 1) ? 0.5 : 1.0;
-            const double se = w * (double)(s * decay_pow(R(a), decay_rate<R>(dec, r)));
-            sxy += se;
-            sxx += 2.0 * gam * se;
+    for (int a0 = 1; a0 <= m; a0 += kLoads) {
+        R sv[kLoads], rv[kLoads];
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) {
+            const int a = a0 + u;
+            if (a <= m) {
+                slot = slot == 0 ? H - 1 : slot - 1;
+                const size_t o = (size_t)slot * np + n;
+                sv[u] = ring_s[o];
+                rv[u] = (c->has_r && a < m) ? ring_r[o] : fabs(sv[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) {
+            const int a = a0 + u;
+            if (a <= m) {
+                const R s = sv[u];
+                gam += (double)s;
+                if (a < m && a <= H - 1) {
+                    const double w = (a == H - 1) ? 0.5 : 1.0;
+                    const double se =
+                        w * (double)(s * decay_pow(R(a), decay_rate<R>(dec, rv[u])));
+                    sxy += se;
+                    sxx += 2.0 * gam * se;
+                }
+            }
         }
     }
     P *sig = reinterpret_cast<P *>(ws + c->off_sig);
     sig[n] = (P)(c->g_inf * (A + sxy));
     sig[np + n] = (P)(c->g_inf * (B + 2.0 * gam * A + sxx));
+}
+
+template <typename P, typename R>
+__global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
+                                                      const ChanDev *__restrict__ chans,
+                                                      const NodeTile *__restrict__ tiles,
+                                                      const int64_t *__restrict__ tcount,
+                                                      int trel, int m)
+{
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const int n = tl.n0 + threadIdx.x;
+    if (c->qb != 0 || n >= c->n)
+        return;  // grid channels step in k_grid_step
+    hist_step_node<P, R>(ws, c, n, *tcount + trel, m);
 }
 
 // ---------------------------------------------------------------------------
