@@ -184,17 +184,17 @@ def bench_large_2d(wl, args, precision: str):
             "node_steps_per_s": nodes * steps / el, "ms_per_step": el / steps * 1e3}
 
 
-def cpu_baseline(seconds: float = 12.0):
-    """The FP64 oracle on a bounded sample of the same workload: a 16 x 512
-    strip of the channel with the full 4096-entry window (seeded synthetic
-    history, so every entry is live), stepped until `seconds` have passed."""
+def oracle_strip(seconds: float, seed_offset: int = 10):
+    """Step the FP64 oracle on a 16 x 512 strip of the channel with the full
+    4096-entry window (seeded synthetic history, so every entry is live) until
+    `seconds` have passed; returns (node-steps, seconds, steps)."""
     import numpy as np
     import oracle
     import workloads
 
     ch = workloads.large_2d(lx=16, ly=512, n_hist=4096).channels[0]
     oc = oracle.OracleChannel(ch)
-    rng = np.random.default_rng(workloads.BASE_SEED + 10)
+    rng = np.random.default_rng(workloads.BASE_SEED + seed_offset)
     s, r = workloads.random_history(rng, ch.n_hist, ch.nodes, dtype=np.float64)
     st = oc.get_state()
     oc.set_state(t=2 * ch.n_hist, n=st["n"], ring_s=s, ring_r=r)
@@ -208,10 +208,42 @@ def cpu_baseline(seconds: float = 12.0):
         if el >= seconds:
             break
     oc.close()
-    return {"value": ch.nodes * steps / el, "unit": "node-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"16x512 strip of the 1024x512 channel, N_h=4096 full window, "
-                      f"{steps} steps in {el:.1f} s, single thread"}
+    return ch.nodes * steps, el, steps
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seconds: float = 12.0, max_procs: int = 16):
+    """The FP64 oracle on a bounded sample of the same workload: one 16 x 512
+    strip in this process (single thread: `value`), then one strip per host
+    core in worker processes, each its own seeded strip (`all_cores`; at most
+    16 workers, the CPU share of one GPU)."""
+    import multiprocessing as mp
+
+    ns, el, steps = oracle_strip(seconds)
+    out = {"value": ns / el, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"16x512 strip of the 1024x512 channel, N_h=4096 full window, "
+                     f"{steps} steps in {el:.1f} s, single thread",
+           "cpu_model": _cpu_model(), "host_cores": os.cpu_count()}
+    procs = max(1, min(max_procs, len(os.sched_getaffinity(0))))
+    if procs > 1:
+        # fresh interpreters (spawn): the workers touch no GPU state
+        with mp.get_context("spawn").Pool(procs) as pool:
+            res = pool.starmap(oracle_strip, [(seconds, 10 + i) for i in range(procs)])
+        rate = sum(n / e for n, e, _ in res)
+        out["all_cores"] = {"value": rate, "unit": "node-steps/s", "cores": procs,
+                            "sample": f"{procs} processes, one 16x512 strip each, "
+                                      f"{sum(r[2] for r in res)} steps in total"}
+    return out
 
 
 def bench_grid(steps: int = 256, B: int = 6, C: int = 128, block: int = 16):
