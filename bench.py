@@ -371,14 +371,17 @@ def bench_batched(steps: int = 2000):
     best = autotune.tune(s, autotune.candidates(s, blocks=(8, 16, 32),
                                                 chunk_lens=(256, 512, 1024, 2048, 4096),
                                                 graphs=(0, 64)), min_steps=64)
+    M = best["block"]
     s.step(64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el, kt = time_steps(s, max(M, steps // M * M))
+    steps = max(M, steps // M * M)
     s.close()
     batched = nodes * steps / el
+    # the history pass (with its chunk combine) over the 64 windows
+    pass_s = kt[0][0] / kt[0][1] / 1e3
+    entries = wl.entries_per_step
+    tflops = entries * pass_flops_per_entry(M) / pass_s / 1e12
+    gbs = entries * 4 / pass_s / 1e9  # unidirectional: FP32 shear rate only
     # plain per-channel FP64: one handle per channel, one step at a time
     handles = [Solver([c], precision="f64") for c in wl.channels]
     for h in handles:
@@ -400,6 +403,11 @@ def bench_batched(steps: int = 2000):
             "nodes": nodes, "history_entries_per_step": wl.entries_per_step,
             "value": batched, "unit": "node-steps/s", "dtype": "f32", "config": cfg,
             "ms_per_step": el / steps * 1e3,
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": VALU_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tflops / VALU_PEAK_TFLOPS, "traffic": None,
+                         "kernel": f"k_hist_pass + k_combine ({M} steps per pass)",
+                         "kernel_avg_ms": pass_s * 1e3, "hbm_GBs": gbs,
+                         "hbm_frac": gbs / HBM_PEAK_GBS},
             "plain_per_channel_f64": plain, "speedup_vs_plain_f64": batched / plain}
 
 

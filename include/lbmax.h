@@ -269,6 +269,21 @@ lb_status lb_set_block(lb_handle *h, int32_t steps_per_pass);
 int32_t lb_get_block(const lb_handle *h);
 
 /*
+ * Fused in-block steps (enable != 0, the default).  When every channel of the
+ * handle has a uniform window (hist_blocks == 0, law != 2) and at most 1024
+ * nodes, the steps of a block after its history pass run as one launch: one
+ * workgroup per channel advances the lattice and the history of all those
+ * steps, with workgroup barriers in place of kernel boundaries.  Results are
+ * identical to separate launches.  lb_get_fused returns 1 when the fused
+ * launch is in use for this handle (enabled, every channel qualifies, and
+ * blocks of more than one step).
+ * Takes effect at the next lb_step.  For lb_kernel_time, a fused launch
+ * counts as one in-block launch.
+ */
+lb_status lb_set_fused(lb_handle *h, int32_t enable);
+int32_t lb_get_fused(const lb_handle *h);
+
+/*
  * Persistent history pass (enable != 0): instead of one workgroup per tile,
  * as many workgroups as are resident on the chip at once claim tiles from a
  * device counter, longest age range first, until all channels' tiles are

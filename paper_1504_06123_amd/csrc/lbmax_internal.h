@@ -11,6 +11,8 @@ namespace lbmax {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kWave = 64;          // threads per wavefront
+constexpr int kFuseThreads = 1024; // workgroup of the fused in-block steps
+constexpr int kFuseMaxNodes = 1024; // channels up to this size take them
 constexpr int kNodeAlign = 64;     // node-plane stride is a multiple of this
 constexpr int kMinChunkLen = 128;  // shortest age range of one history chunk
 constexpr int kMaxChunks = 64;     // most age ranges per channel
@@ -121,6 +123,12 @@ void launch_hist_step(int prec, int m, char *ws, const ChanDev *chans,
 void launch_grid_step(int prec, int block, int m, char *ws, const ChanDev *chans,
                       const NodeTile *tiles, int n_tiles, const int64_t *tcount, int trel,
                       hipStream_t st);
+// Steps m0 .. m0 + count - 1 of a block, after its pass, for handles whose
+// channels all fit one workgroup (window histories, n <= kFuseMaxNodes): one
+// workgroup per channel runs the lattice and in-block history phases of
+// every step.
+void launch_fused_steps(int prec, char *ws, const ChanDev *chans, int n_ch,
+                        const int64_t *tcount, int trel, int m0, int count, hipStream_t st);
 void launch_tick(int64_t *tcount, int64_t add, hipStream_t st);
 void launch_set_force(ChanDev *chans, int ch, double gx, double gy,
                       hipStream_t st);

@@ -1532,6 +1532,31 @@ __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
     hist_step_node<P, R>(ws, c, n, *tcount + trel, m);
 }
 
+// Steps m0 .. m0 + count - 1 of a block (all after its pass) for handles whose
+// channels each fit one workgroup: workgroup b runs channel b's lattice phase
+// and in-block history phase for every step, with a workgroup barrier where
+// the unfused path has a kernel boundary (every node a stencil of the channel
+// reads belongs to the workgroup).  Same per-node arithmetic as k_lb and
+// k_hist_step, so results are identical.
+template <typename P, typename R>
+__global__ __launch_bounds__(kFuseThreads) void k_fused_steps(char *__restrict__ ws,
+                                                            const ChanDev *__restrict__ chans,
+                                                            const int64_t *__restrict__ tcount,
+                                                            int trel, int m0, int count)
+{
+    const ChanDev *c = chans + blockIdx.x;
+    const int64_t t0 = *tcount + trel;
+    for (int k = 0; k < count; ++k) {
+        const int64_t t = t0 + k;
+        for (int n = threadIdx.x; n < c->n; n += kFuseThreads)
+            lb_node<P>(ws, c, n, t);
+        __syncthreads();
+        for (int n = threadIdx.x; n < c->n; n += kFuseThreads)
+            hist_step_node<P, R>(ws, c, n, t, m0 + k);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Quasi-logarithmic history grid (Sec. III), one node per thread, every step.
 //
@@ -2150,6 +2175,15 @@ void launch_combine(int prec, int block, char *ws, const ChanDev *chans, const N
         return;
     LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_combine<P>, dim3(n_tiles, block), dim3(kBlock), 0,
                                            st, ws, chans, tiles));
+}
+
+void launch_fused_steps(int prec, char *ws, const ChanDev *chans, int n_ch,
+                        const int64_t *tcount, int trel, int m0, int count, hipStream_t st)
+{
+    if (n_ch <= 0 || count <= 0)
+        return;
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_fused_steps<P, H>), dim3(n_ch), dim3(kFuseThreads),
+                                           0, st, ws, chans, tcount, trel, m0, count));
 }
 
 void launch_hist_step(int prec, int m, char *ws, const ChanDev *chans, const NodeTile *tiles,

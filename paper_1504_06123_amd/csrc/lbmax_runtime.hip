@@ -269,6 +269,8 @@ struct lb_handle {
     bool any_finger = false, any_wm = false, any_inst = false;
     bool any_chunked = false;
     bool any_grid = false, any_window = false;  // channels on the grid / the uniform window
+    bool fuse_ok = false;      // every channel fits the fused in-block steps
+    bool fuse_enabled = true;  // lb_set_fused
     // host mirrors kept alive for asynchronous uploads
     std::vector<NodeTile> node_tiles;
     std::vector<HistTile> hist_tiles;
@@ -399,6 +401,10 @@ void build_tiles(lb_handle *h)
     h->any_wm = h->hist_group_count[4] > 0;
     h->n_node_tiles = (int)h->node_tiles.size();
     h->n_hist_tiles = (int)h->hist_tiles.size();
+    h->fuse_ok = !h->any_grid && !h->any_inst;
+    for (const ChanDev &c : h->plan.chans)
+        if (c.n > kFuseMaxNodes)
+            h->fuse_ok = false;
 }
 
 // Default launch shape: wide lanes for large channels, and enough age chunks
@@ -528,6 +534,35 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
     return check_launch(h, "step launch");
 }
 
+// Enqueue up to `left` steps starting at block position m: a fused launch
+// for the rest of the block when the handle allows it and m > 0, else one
+// step.  Sets *done to the steps enqueued.
+lb_status enqueue_span(lb_handle *h, hipStream_t st, int trel, int m, int64_t left, bool timed,
+                       int *done)
+{
+    if (h->fuse_ok && h->fuse_enabled && h->block > 1 && m > 0) {
+        const int k = (int)std::min<int64_t>(left, h->block - m);
+        hipEvent_t e[2] = {nullptr, nullptr};
+        if (timed) {
+            for (int i = 0; i < 2; ++i) {
+                lb_status s = take_event(h, &e[i]);
+                if (s != LB_OK)
+                    return s;
+            }
+            HIP_TRY(h, hipEventRecord(e[0], st));
+        }
+        launch_fused_steps(h->pc, h->ws, h->d_chans, h->n_ch, h->d_tcount, trel, m, k, st);
+        if (timed) {
+            HIP_TRY(h, hipEventRecord(e[1], st));
+            h->pending[2].push_back({e[0], e[1]});
+        }
+        *done = k;
+        return check_launch(h, "fused steps launch");
+    }
+    *done = 1;
+    return enqueue_step(h, st, trel, m, timed);
+}
+
 lb_status capture_graph(lb_handle *h)
 {
     if (h->graph_exec) {
@@ -541,8 +576,9 @@ lb_status capture_graph(lb_handle *h)
     if (!h->cap_stream)
         HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < h->graph_steps; ++i) {
-        lb_status s = enqueue_step(h, h->cap_stream, i, i % h->block, false);
+    for (int i = 0, k = 0; i < h->graph_steps; i += k) {
+        lb_status s = enqueue_span(h, h->cap_stream, i, i % h->block, h->graph_steps - i, false,
+                                   &k);
         if (s != LB_OK) {
             hipGraph_t g = nullptr;
             (void)hipStreamEndCapture(h->cap_stream, &g);
@@ -844,11 +880,12 @@ lb_status lb_step(lb_handle *h, int64_t n_steps)
     auto eager = [&](int64_t count) -> lb_status {
         while (count > 0) {
             const int batch = (int)std::min(count, kMaxStepsPerBatch);
-            for (int i = 0; i < batch; ++i) {
-                lb_status e = enqueue_step(h, h->stream, i, h->block_pos, h->profile);
+            for (int i = 0, k = 0; i < batch; i += k) {
+                lb_status e = enqueue_span(h, h->stream, i, h->block_pos, batch - i, h->profile,
+                                           &k);
                 if (e != LB_OK)
                     return e;
-                h->block_pos = (h->block_pos + 1) % h->block;
+                h->block_pos = (h->block_pos + k) % h->block;
             }
             launch_tick(h->d_tcount, batch, h->stream);
             lb_status e = check_launch(h, "tick");
@@ -1070,6 +1107,21 @@ lb_status lb_set_block(lb_handle *h, int32_t steps_per_pass)
 }
 
 int32_t lb_get_block(const lb_handle *h) { return h ? h->block : 0; }
+
+lb_status lb_set_fused(lb_handle *h, int32_t enable)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    h->fuse_enabled = enable != 0;
+    h->graph_dirty = true;
+    return LB_OK;
+}
+
+int32_t lb_get_fused(const lb_handle *h)
+{
+    return (h && h->fuse_ok && h->fuse_enabled && h->block > 1) ? 1 : 0;
+}
 
 lb_status lb_set_persistent(lb_handle *h, int32_t enable)
 {
