@@ -269,18 +269,24 @@ lb_status lb_set_block(lb_handle *h, int32_t steps_per_pass);
 int32_t lb_get_block(const lb_handle *h);
 
 /*
- * Fused in-block steps (enable != 0, the default).  When every channel of the
- * handle has a uniform window (hist_blocks == 0, law != 2) and at most 1024
- * nodes, the steps of a block after its history pass run as one launch: one
- * workgroup per channel advances the lattice and the history of all those
- * steps, with workgroup barriers in place of kernel boundaries.  Results are
- * identical to separate launches.  lb_get_fused returns 1 when the fused
- * launch is in use for this handle (enabled, every channel qualifies, and
- * blocks of more than one step).
- * Takes effect at the next lb_step.  For lb_kernel_time, a fused launch
- * counts as one in-block launch.
+ * Fused in-block steps.  When every channel of the handle has a uniform
+ * window (hist_blocks == 0, law != 2) and at most 1024 nodes, the steps of a
+ * block after its history pass run as one launch: one workgroup per channel
+ * advances the lattice and the history of all those steps, with workgroup
+ * barriers in place of kernel boundaries.  If moreover the handle is LB_F32
+ * and every channel takes the simple-shear integral law (law == 0,
+ * finger == 0) with the body-force coupling (paper_coupling == 0), the
+ * workgroup keeps the channel's
+ * populations, stress and velocity in LDS and the history rows pushed since
+ * the pass in registers (the stencils then read no global memory).  mode: 0
+ * separate launches, 1 fused (the LDS form where it applies; the default), 2
+ * fused without the LDS form.  Results are identical in every mode.
+ * lb_get_fused returns 0 when the steps are not fused (mode 0, a channel
+ * that does not qualify, or blocks of one step), 1 for the fused launch, 2
+ * for its LDS form.  Takes effect at the next lb_step.  For lb_kernel_time a
+ * fused launch counts as one in-block launch.
  */
-lb_status lb_set_fused(lb_handle *h, int32_t enable);
+lb_status lb_set_fused(lb_handle *h, int32_t mode);
 int32_t lb_get_fused(const lb_handle *h);
 
 /*

@@ -127,8 +127,15 @@ void launch_grid_step(int prec, int block, int m, char *ws, const ChanDev *chans
 // channels all fit one workgroup (window histories, n <= kFuseMaxNodes): one
 // workgroup per channel runs the lattice and in-block history phases of
 // every step.
-void launch_fused_steps(int prec, char *ws, const ChanDev *chans, int n_ch,
+// With `lds`, the form that keeps each channel's lattice state in LDS and
+// the rows pushed since the pass in registers (FP32 handles whose channels
+// take the simple-shear integral law and the body-force coupling); it needs
+// fused_lds_bytes(prec) of dynamic LDS, allowed by prepare_fused_lds (0 on
+// success, -1 for the other precisions).
+void launch_fused_steps(int prec, bool lds, char *ws, const ChanDev *chans, int n_ch,
                         const int64_t *tcount, int trel, int m0, int count, hipStream_t st);
+size_t fused_lds_bytes(int prec);
+int prepare_fused_lds(int prec);
 void launch_tick(int64_t *tcount, int64_t add, hipStream_t st);
 void launch_set_force(ChanDev *chans, int ch, double gx, double gy,
                       hipStream_t st);

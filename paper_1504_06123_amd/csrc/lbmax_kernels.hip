@@ -231,49 +231,63 @@ __device__ __forceinline__ void lb_collide_paper(char *__restrict__ ws, const Ch
 // ---------------------------------------------------------------------------
 // Lattice phase of step t.
 // ---------------------------------------------------------------------------
+// Pull-stream of node n from the post-collision planes `src` (plane stride
+// ss): n_q(x, y) = n*_q(x - c_q); through a wall, the population that left in
+// the opposite direction comes back (halfway bounce-back).
 template <typename R>
-__device__ __forceinline__ void lb_node(char *__restrict__ ws, const ChanDev *c, int n,
-                                        int64_t t)
+__device__ __forceinline__ void lb_pull(const ChanDev *c, int n, const R *__restrict__ src,
+                                        size_t ss, R (&d)[9])
 {
     const int lx = c->lx, ly = c->ly;
-    const size_t np = (size_t)c->np;
-    R *pop = reinterpret_cast<R *>(ws + c->off_pop);
-    const R *__restrict__ src = pop + ((t + 1) & 1) * 9 * np;  // n*(t-1)
-    R *__restrict__ dst = pop + (t & 1) * 9 * np;              // n*(t)
     const int y = n / lx, x = n - y * lx;
     const int xp = (x + 1 == lx) ? 0 : x + 1;
     const int xm = (x == 0) ? lx - 1 : x - 1;
     const bool lo = y > 0, hi = y < ly - 1;
     const int rowm = (y - 1) * lx, row = y * lx, rowp = (y + 1) * lx;
-
-    // Pull-stream: n_q(x, y) = n*_q(x - c_q); through a wall, the population
-    // that left in the opposite direction comes back (halfway bounce-back).
-    R d[9];
     d[0] = src[n];
-    d[1] = src[1 * np + row + xm];
-    d[2] = src[2 * np + row + xp];
-    d[3] = lo ? src[3 * np + rowm + x] : src[4 * np + n];
-    d[4] = hi ? src[4 * np + rowp + x] : src[3 * np + n];
-    d[5] = lo ? src[5 * np + rowm + xm] : src[6 * np + n];
-    d[6] = hi ? src[6 * np + rowp + xp] : src[5 * np + n];
-    d[7] = hi ? src[7 * np + rowp + xm] : src[8 * np + n];
-    d[8] = lo ? src[8 * np + rowm + xp] : src[7 * np + n];
+    d[1] = src[1 * ss + row + xm];
+    d[2] = src[2 * ss + row + xp];
+    d[3] = lo ? src[3 * ss + rowm + x] : src[4 * ss + n];
+    d[4] = hi ? src[4 * ss + rowp + x] : src[3 * ss + n];
+    d[5] = lo ? src[5 * ss + rowm + xm] : src[6 * ss + n];
+    d[6] = hi ? src[6 * ss + rowp + xp] : src[5 * ss + n];
+    d[7] = hi ? src[7 * ss + rowp + xm] : src[8 * ss + n];
+    d[8] = lo ? src[8 * ss + rowm + xp] : src[7 * ss + n];
+}
 
-    // Moments of the deviations n_q - a_q: rho - 1 and j.
-    R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
-    const R jx = (d[1] - d[2]) + (d[5] - d[6]) + (d[7] - d[8]);
-    const R jy = (d[3] - d[4]) + (d[5] - d[6]) + (d[8] - d[7]);
-    if (c->coupling) {
-        lb_collide_paper<R>(ws, c, n, np, d, drho, jx, jy, dst);
-        return;
-    }
+// Moments of the deviations n_q - a_q: rho - 1 and j.
+template <typename R>
+__device__ __forceinline__ void lb_moments(const R (&d)[9], R &drho, R &jx, R &jy)
+{
+    drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    jx = (d[1] - d[2]) + (d[5] - d[6]) + (d[7] - d[8]);
+    jy = (d[3] - d[4]) + (d[5] - d[6]) + (d[8] - d[7]);
+}
+
+// Body-force collision of node n: moments of the pulled deviations d, force
+// density rho g + div sigma^{t-1} from the stress planes `sg` (plane stride
+// gs: sigma_xy, sigma_xx, and sigma_yy with the full tensor), velocity with
+// the half-force shift, BGK + forcing term.  Post-collision deviations in
+// `out`.
+template <typename R>
+__device__ __forceinline__ void lb_collide_body(const ChanDev *c, int n, const R (&d)[9],
+                                                const R *__restrict__ sg, size_t gs,
+                                                R (&out)[9], R &ux, R &uy, R &drho)
+{
+    const int lx = c->lx, ly = c->ly;
+    const int y = n / lx, x = n - y * lx;
+    const int xp = (x + 1 == lx) ? 0 : x + 1;
+    const int xm = (x == 0) ? lx - 1 : x - 1;
+    const int row = y * lx;
+    R jx, jy;
+    lb_moments<R>(d, drho, jx, jy);
     const R rho = R(1) + drho;
 
     // Force density rho*g + div sigma^{t-1} (sigma_yy = 0 in the simple-shear
     // reduction, a third plane with the full tensor); d/dx periodic central,
     // d/dy central with one-sided rows at the walls.
-    const R *__restrict__ sxy = reinterpret_cast<const R *>(ws + c->off_sig);
-    const R *__restrict__ sxx = sxy + np;
+    const R *__restrict__ sxy = sg;
+    const R *__restrict__ sxx = sg + gs;
     auto ddy = [&](const R *__restrict__ f) {
         if (y == 0)
             return R(0.5) * (R(-3) * f[n] + R(4) * f[n + lx] - f[n + 2 * lx]);
@@ -284,13 +298,13 @@ __device__ __forceinline__ void lb_node(char *__restrict__ ws, const ChanDev *c,
     R fx = R(0.5) * (sxx[row + xp] - sxx[row + xm]) + ddy(sxy);
     R fy = R(0.5) * (sxy[row + xp] - sxy[row + xm]);
     if (c->finger)
-        fy += ddy(sxy + 2 * np);
+        fy += ddy(sg + 2 * gs);
     fx += rho * (R)c->gx;
     fy += rho * (R)c->gy;
 
     // Velocity with the half-force shift (Eq. hydrofields).
-    const R ux = (jx + R(0.5) * fx) / rho;
-    const R uy = (jy + R(0.5) * fy) / rho;
+    ux = (jx + R(0.5) * fx) / rho;
+    uy = (jy + R(0.5) * fy) / rho;
 
     // BGK relaxation to the second-order equilibrium plus the forcing term
     // a_q (1 - 1/(2 tau_LB)) [(c - u).f / cs2 + (c.u)(c.f) / cs2^2]
@@ -306,8 +320,33 @@ __device__ __forceinline__ void lb_node(char *__restrict__ ws, const ChanDev *c,
         const R w = qweight<R>(q);
         const R deq = w * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
         const R F = w * pf * (R(3) * (cf - uf) + R(9) * cu * cf);
-        dst[q * np + n] = d[q] - om * (d[q] - deq) + F;
+        out[q] = d[q] - om * (d[q] - deq) + F;
     }
+}
+
+// Lattice update of node n at step t from and to the workspace.
+template <typename R>
+__device__ __forceinline__ void lb_node(char *__restrict__ ws, const ChanDev *c, int n,
+                                        int64_t t)
+{
+    const size_t np = (size_t)c->np;
+    R *pop = reinterpret_cast<R *>(ws + c->off_pop);
+    const R *__restrict__ src = pop + ((t + 1) & 1) * 9 * np;  // n*(t-1)
+    R *__restrict__ dst = pop + (t & 1) * 9 * np;              // n*(t)
+    R d[9];
+    lb_pull<R>(c, n, src, np, d);
+    if (c->coupling) {
+        R drho, jx, jy;
+        lb_moments<R>(d, drho, jx, jy);
+        lb_collide_paper<R>(ws, c, n, np, d, drho, jx, jy, dst);
+        return;
+    }
+    R out[9], ux, uy, drho;
+    lb_collide_body<R>(c, n, d, reinterpret_cast<const R *>(ws + c->off_sig), np, out, ux, uy,
+                       drho);
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        dst[q * np + n] = out[q];
     R *vel = reinterpret_cast<R *>(ws + c->off_vel);
     vel[n] = ux;
     vel[np + n] = uy;
@@ -1557,6 +1596,163 @@ __global__ __launch_bounds__(kFuseThreads) void k_fused_steps(char *__restrict__
     }
 }
 
+// Steps m0 .. m0 + count - 1 of a block with the channel's lattice state in
+// the workgroup, for handles whose channels all take the simple-shear integral
+// law with the body-force coupling on a uniform window (and fit one
+// workgroup).  LDS holds the post-collision populations, the stress and the
+// velocity of the channel, so the neighbours a stencil reads come from LDS;
+// each thread keeps the history rows of its node pushed since the pass in
+// registers.  Every result still goes to the workspace (populations of both
+// parities, velocity, rho, stress, ring rows) as the separate launches write
+// it, and the arithmetic is the same operations in the same order, so the
+// results are identical.
+//
+// In-block history of one node at step t0 + m from the rows in registers
+// (entry j pushed at t0 + j, s_new this step's): the ring walk of
+// hist_step_node, ages a = 1..m in the same order.
+template <typename R, bool HAS_R>
+__device__ __forceinline__ void hist_regs(const ChanDev *c, const Decay<R> &dec, int m, R s_new,
+                                          const R (&hs)[kMaxBlock], const R (&hr)[kMaxBlock],
+                                          double &sxy_out, double &sxx_out, double &gam_out)
+{
+    const int H = c->n_hist;
+    double sxy = 0.5 * (double)s_new, sxx = 0.0, gam = 0.0;
+#pragma unroll
+    for (int j = kMaxBlock - 1; j >= 0; --j) {
+        if (j < m) {
+            const int a = m - j;
+            const R s = hs[j];
+            gam += (double)s;
+            if (a < m && a <= H - 1) {
+                const double w = (a == H - 1) ? 0.5 : 1.0;
+                const R r = HAS_R ? hr[j] : fabs(s);
+                const double se = w * (double)(s * decay_pow(R(a), decay_rate<R>(dec, r)));
+                sxy += se;
+                sxx += 2.0 * gam * se;
+            }
+        }
+    }
+    sxy_out = sxy;
+    sxx_out = sxx;
+    gam_out = gam;
+}
+
+template <typename P, typename R, bool HAS_R>
+__device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const ChanDev *c,
+                                               int64_t t0s, int m0, int count, P *s_pop,
+                                               P *s_sig, P *s_vel)
+{
+    constexpr int K = kFuseThreads;  // LDS plane stride
+    const int n = threadIdx.x;
+    const bool own = n < c->n;
+    const size_t np = (size_t)c->np;
+    const int H = c->n_hist;
+    const int64_t tb = t0s - m0;  // step of the block's pass
+    P *pop = reinterpret_cast<P *>(ws + c->off_pop);
+    P *vel = reinterpret_cast<P *>(ws + c->off_vel);
+    P *rhop = reinterpret_cast<P *>(ws + c->off_rho);
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    R *ring_s = reinterpret_cast<R *>(ws + c->off_ring_s);
+    R *ring_r = reinterpret_cast<R *>(ws + c->off_ring_r);
+    const double *blk = reinterpret_cast<const double *>(ws + c->off_blk);
+    const Decay<R> dec(c);
+    // state of step t0s - 1, and the rows pushed since the pass
+    R hs[kMaxBlock], hr[kMaxBlock];
+    if (own) {
+        const P *src = pop + ((t0s + 1) & 1) * 9 * np;
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            s_pop[q * K + n] = src[q * np + n];
+        s_sig[n] = sig[n];
+        s_sig[K + n] = sig[np + n];
+#pragma unroll
+        for (int j = 0; j < kMaxBlock; ++j) {
+            hs[j] = hr[j] = R(0);
+            if (j < m0) {
+                const size_t o = (size_t)((tb + j) % H) * np + n;
+                hs[j] = ring_s[o];
+                if (HAS_R)
+                    hr[j] = ring_r[o];
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < count; ++k) {
+        const int64_t t = t0s + k;
+        const int m = m0 + k;
+        double A = 0.0, B = 0.0;
+        P out[9], ux = P(0), uy = P(0), drho = P(0);
+        if (own) {
+            A = blk[m * np + n];  // issued before the lattice phase
+            B = blk[(kPlaneB + m) * np + n];
+            P d[9];
+            lb_pull<P>(c, n, s_pop, K, d);
+            lb_collide_body<P>(c, n, d, s_sig, K, out, ux, uy, drho);
+        }
+        __syncthreads();  // every stencil read of the old populations and stress is done
+        if (own) {
+            P *dst = pop + (t & 1) * 9 * np;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                s_pop[q * K + n] = out[q];
+                dst[q * np + n] = out[q];
+            }
+            s_vel[n] = ux;
+            s_vel[K + n] = uy;
+            vel[n] = ux;
+            vel[np + n] = uy;
+            rhop[n] = drho;
+        }
+        __syncthreads();  // this step's velocities are in LDS
+        if (own) {
+            const int y = n / c->lx, x = n - y * c->lx;
+            P kxx, kxy, kyx, kyy;
+            velocity_gradient<P>(s_vel, s_vel + K, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
+            const R s_new = (R)kxy;
+            const size_t o = (size_t)(t % H) * np + n;
+            ring_s[o] = s_new;
+            R r_new = R(0);
+            if (HAS_R) {
+                r_new = (R)shear_rate<P>(kxx, kxy, kyx, kyy);
+                ring_r[o] = r_new;
+            }
+            double sxy, sxx, gam;
+            hist_regs<R, HAS_R>(c, dec, m, s_new, hs, hr, sxy, sxx, gam);
+#pragma unroll
+            for (int j = 0; j < kMaxBlock; ++j)
+                if (j == m) {
+                    hs[j] = s_new;
+                    if (HAS_R)
+                        hr[j] = r_new;
+                }
+            const P sxy_p = (P)(c->g_inf * (A + sxy));
+            const P sxx_p = (P)(c->g_inf * (B + 2.0 * gam * A + sxx));
+            sig[n] = sxy_p;
+            sig[np + n] = sxx_p;
+            s_sig[n] = sxy_p;
+            s_sig[K + n] = sxx_p;
+        }
+        __syncthreads();  // this step's stress is in LDS
+    }
+}
+
+template <typename P, typename R>
+__global__ __launch_bounds__(kFuseThreads) void k_fused_steps_lds(
+    char *__restrict__ ws, const ChanDev *__restrict__ chans, const int64_t *__restrict__ tcount,
+    int trel, int m0, int count)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    P *s_pop = reinterpret_cast<P *>(lds_raw);  // [9][kFuseThreads]
+    P *s_sig = s_pop + 9 * kFuseThreads;        // [2][kFuseThreads]
+    P *s_vel = s_sig + 2 * kFuseThreads;        // [2][kFuseThreads]
+    const ChanDev *c = chans + blockIdx.x;
+    const int64_t t0s = *tcount + trel;
+    if (c->has_r)
+        fused_span_lds<P, R, true>(ws, c, t0s, m0, count, s_pop, s_sig, s_vel);
+    else
+        fused_span_lds<P, R, false>(ws, c, t0s, m0, count, s_pop, s_sig, s_vel);
+}
+
 // ---------------------------------------------------------------------------
 // Quasi-logarithmic history grid (Sec. III), one node per thread, every step.
 //
@@ -2177,13 +2373,34 @@ void launch_combine(int prec, int block, char *ws, const ChanDev *chans, const N
                                            st, ws, chans, tiles));
 }
 
-void launch_fused_steps(int prec, char *ws, const ChanDev *chans, int n_ch,
+void launch_fused_steps(int prec, bool lds, char *ws, const ChanDev *chans, int n_ch,
                         const int64_t *tcount, int trel, int m0, int count, hipStream_t st)
 {
     if (n_ch <= 0 || count <= 0)
         return;
-    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_fused_steps<P, H>), dim3(n_ch), dim3(kFuseThreads),
-                                           0, st, ws, chans, tcount, trel, m0, count));
+    if (!lds) {
+        LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_fused_steps<P, H>), dim3(n_ch),
+                                               dim3(kFuseThreads), 0, st, ws, chans, tcount,
+                                               trel, m0, count));
+        return;
+    }
+    if (prec == 1)
+        hipLaunchKernelGGL((k_fused_steps_lds<float, float>), dim3(n_ch), dim3(kFuseThreads),
+                           fused_lds_bytes(prec), st, ws, chans, tcount, trel, m0, count);
+}
+
+size_t fused_lds_bytes(int prec) { return prec == 1 ? (size_t)13 * kFuseThreads * sizeof(float) : 0; }
+
+int prepare_fused_lds(int prec)
+{
+    // FP32 only: with FP64 lattice state the form does not fit the 128
+    // registers a 1024-thread workgroup leaves each thread
+    if (prec != 1)
+        return -1;
+    const hipError_t e =
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fused_steps_lds<float, float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_lds_bytes(prec));
+    return e == hipSuccess ? 0 : -1;
 }
 
 void launch_hist_step(int prec, int m, char *ws, const ChanDev *chans, const NodeTile *tiles,

@@ -270,7 +270,9 @@ struct lb_handle {
     bool any_chunked = false;
     bool any_grid = false, any_window = false;  // channels on the grid / the uniform window
     bool fuse_ok = false;      // every channel fits the fused in-block steps
-    bool fuse_enabled = true;  // lb_set_fused
+    bool fuse_lds_ok = false;  // ... and takes the LDS-resident form
+    bool fuse_lds_ready = false;  // its dynamic LDS size is allowed
+    int fuse_mode = 1;         // lb_set_fused
     // host mirrors kept alive for asynchronous uploads
     std::vector<NodeTile> node_tiles;
     std::vector<HistTile> hist_tiles;
@@ -402,9 +404,15 @@ void build_tiles(lb_handle *h)
     h->n_node_tiles = (int)h->node_tiles.size();
     h->n_hist_tiles = (int)h->hist_tiles.size();
     h->fuse_ok = !h->any_grid && !h->any_inst;
-    for (const ChanDev &c : h->plan.chans)
+    h->fuse_lds_ok = h->fuse_ok;
+    for (const ChanDev &c : h->plan.chans) {
         if (c.n > kFuseMaxNodes)
-            h->fuse_ok = false;
+            h->fuse_ok = h->fuse_lds_ok = false;
+        if (c.law != 0 || c.finger || c.coupling)
+            h->fuse_lds_ok = false;
+    }
+    if (h->fuse_lds_ok && !h->fuse_lds_ready)
+        h->fuse_lds_ready = prepare_fused_lds(h->pc) == 0;
 }
 
 // Default launch shape: wide lanes for large channels, and enough age chunks
@@ -540,7 +548,7 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
 lb_status enqueue_span(lb_handle *h, hipStream_t st, int trel, int m, int64_t left, bool timed,
                        int *done)
 {
-    if (h->fuse_ok && h->fuse_enabled && h->block > 1 && m > 0) {
+    if (h->fuse_ok && h->fuse_mode != 0 && h->block > 1 && m > 0) {
         const int k = (int)std::min<int64_t>(left, h->block - m);
         hipEvent_t e[2] = {nullptr, nullptr};
         if (timed) {
@@ -551,7 +559,8 @@ lb_status enqueue_span(lb_handle *h, hipStream_t st, int trel, int m, int64_t le
             }
             HIP_TRY(h, hipEventRecord(e[0], st));
         }
-        launch_fused_steps(h->pc, h->ws, h->d_chans, h->n_ch, h->d_tcount, trel, m, k, st);
+        const bool lds = h->fuse_mode == 1 && h->fuse_lds_ok && h->fuse_lds_ready;
+        launch_fused_steps(h->pc, lds, h->ws, h->d_chans, h->n_ch, h->d_tcount, trel, m, k, st);
         if (timed) {
             HIP_TRY(h, hipEventRecord(e[1], st));
             h->pending[2].push_back({e[0], e[1]});
@@ -1108,19 +1117,23 @@ lb_status lb_set_block(lb_handle *h, int32_t steps_per_pass)
 
 int32_t lb_get_block(const lb_handle *h) { return h ? h->block : 0; }
 
-lb_status lb_set_fused(lb_handle *h, int32_t enable)
+lb_status lb_set_fused(lb_handle *h, int32_t mode)
 {
     lb_status s = usable(h);
     if (s != LB_OK)
         return s;
-    h->fuse_enabled = enable != 0;
+    if (mode < 0 || mode > 2)
+        return fail(LB_EINVAL, "fused mode must be 0, 1 or 2");
+    h->fuse_mode = mode;
     h->graph_dirty = true;
     return LB_OK;
 }
 
 int32_t lb_get_fused(const lb_handle *h)
 {
-    return (h && h->fuse_ok && h->fuse_enabled && h->block > 1) ? 1 : 0;
+    if (!h || !h->fuse_ok || h->fuse_mode == 0 || h->block <= 1)
+        return 0;
+    return (h->fuse_mode == 1 && h->fuse_lds_ok && h->fuse_lds_ready) ? 2 : 1;
 }
 
 lb_status lb_set_persistent(lb_handle *h, int32_t enable)

@@ -133,13 +133,16 @@ class Solver:
         """Steps served by one history pass (temporal blocking: 1, 2, 4, 8, 16, 32)."""
         _lib.check(self.lib.lb_set_block(self.h, int(steps_per_pass)), "lb_set_block")
 
-    def set_fused(self, enable: bool = True):
-        """Fused in-block steps for handles whose channels all fit one workgroup."""
-        _lib.check(self.lib.lb_set_fused(self.h, 1 if enable else 0), "lb_set_fused")
+    def set_fused(self, mode=1):
+        """Fused in-block steps for handles whose channels all fit one
+        workgroup: 0 (or False) separate launches, 1 (or True) fused with the
+        LDS-resident form where it applies, 2 fused without it."""
+        _lib.check(self.lib.lb_set_fused(self.h, int(mode)), "lb_set_fused")
 
     @property
-    def fused(self) -> bool:
-        return bool(self.lib.lb_get_fused(self.h))
+    def fused(self) -> int:
+        """0 not fused, 1 fused launch, 2 its LDS-resident form."""
+        return int(self.lib.lb_get_fused(self.h))
 
     def set_persistent(self, enable: bool = True):
         """Persistent history pass: resident workgroups claim tiles from a counter."""

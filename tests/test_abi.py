@@ -130,6 +130,7 @@ def test_null_handle_calls(lib):
     assert lib.lb_state_bytes(None) == 0
     assert lib.lb_max_chunks(None, 0) == 0
     assert lib.lb_set_fused(None, 1) == -1
+    assert lib.lb_set_fused(None, 3) == -1
     assert lib.lb_get_fused(None) == 0
 
 

@@ -15,13 +15,14 @@ from test_gpu_parity import Solver, say  # noqa: F401
 pytestmark = pytest.mark.gpu
 
 
-def _run(Solver, chans, precision, block, fused, steps, graph=0):
+def _run(Solver, chans, precision, block, mode, steps, graph=0, want=None):
     with Solver(chans, precision=precision) as s:
         s.set_block(block)
-        s.set_fused(fused)
+        s.set_fused(mode)
         if graph:
             s.set_graph(graph)
-        assert s.fused == (fused and block > 1)
+        if want is not None:
+            assert s.fused == want
         out = []
         done = 0
         for k in (steps // 3, steps // 3 + 5, steps):
@@ -41,11 +42,54 @@ def _same(a, b):
 @pytest.mark.parametrize("precision", ["f64", "f32p64", "f32"])
 @pytest.mark.parametrize("block", [2, 8, 32])
 def test_fused_equals_separate_launches_batched(Solver, precision, block):
+    """Separate launches, the fused launch, and (LB_F32) its LDS form."""
     chans = workloads.batched().channels[:12]
     say(f"case fused batched 12 channels {precision} block {block}")
-    a = _run(Solver, chans, precision, block, False, 203)
-    b = _run(Solver, chans, precision, block, True, 203)
+    a = _run(Solver, chans, precision, block, 0, 203, want=0)
+    b = _run(Solver, chans, precision, block, 2, 203, want=1)
+    c = _run(Solver, chans, precision, block, 1, 203, want=2 if precision == "f32" else 1)
     _same(a, b)
+    _same(a, c)
+
+
+@pytest.mark.parametrize("block", [4, 32])
+def test_fused_lds_form_2d_channels_and_short_windows(Solver, block):
+    """The LDS form on 2D channels (|gamma_dot| rows kept too), windows
+    shorter than the block, a chunked window, and a channel at the 1024-node
+    limit."""
+    def twod(lx, ly, n_hist, tau_m):
+        return workloads.large_2d(lx=lx, ly=ly, n_hist=n_hist).channels[0].replace(tau_m=tau_m)
+
+    chans = [twod(8, 16, 300, 20.0),
+             twod(5, 13, 3, 15.0),      # window shorter than the block
+             twod(32, 32, 64, 30.0),    # 1024 nodes
+             workloads.plain_f64().channels[0].replace(lx=1, ly=40, n_hist=2000)]
+    say(f"case fused LDS form 2D + short windows, f32 block {block}")
+    a = _run(Solver, chans, "f32", block, 0, 150, want=0)
+    with Solver(chans, precision="f32") as s:
+        s.set_tiling(3, 4)     # the long window split into 4 age chunks
+        s.set_block(block)
+        out = []
+        done = 0
+        for k in (50, 55, 150):
+            s.step(k - done)
+            done = k
+            for ci in range(len(chans)):
+                out.append(s.fields(ci) + s.stress(ci))
+        assert s.fused == 2
+    with Solver(chans, precision="f32") as s:
+        s.set_tiling(3, 4)
+        s.set_block(block)
+        s.set_fused(0)
+        ref = []
+        done = 0
+        for k in (50, 55, 150):
+            s.step(k - done)
+            done = k
+            for ci in range(len(chans)):
+                ref.append(s.fields(ci) + s.stress(ci))
+    _same(ref, out)
+    assert len(a) == len(out)
 
 
 def test_fused_equals_separate_launches_mixed_kinds(Solver):
@@ -56,10 +100,11 @@ def test_fused_equals_separate_launches_mixed_kinds(Solver):
              base.replace(law="strain_damping", tau_m=25.0),
              base.replace(paper_coupling=True, tau_m=30.0),
              workloads.plain_f64().channels[0].replace(lx=1, ly=40)]
-    say("case fused mixed kinds f32p64 block 8")
-    a = _run(Solver, chans, "f32p64", 8, False, 150)
-    b = _run(Solver, chans, "f32p64", 8, True, 150)
-    _same(a, b)
+    for precision in ("f32p64", "f32"):
+        say(f"case fused mixed kinds {precision} block 8")
+        a = _run(Solver, chans, precision, 8, 0, 150, want=0)
+        b = _run(Solver, chans, precision, 8, 1, 150, want=1)   # no LDS form here
+        _same(a, b)
 
 
 def test_fused_save_load_mid_span_and_graph(Solver):
@@ -67,7 +112,7 @@ def test_fused_save_load_mid_span_and_graph(Solver):
     say("case fused save/load mid-span + graph, f32 block 16")
     with Solver(chans, precision="f32") as s:
         s.set_block(16)
-        assert s.fused
+        assert s.fused == 2
         s.step(53)                     # 5 steps into a block
         buf = s.save_state()
         s.step(40)
@@ -77,8 +122,8 @@ def test_fused_save_load_mid_span_and_graph(Solver):
         s.step(40)
         got = [s.fields(i) + s.stress(i) for i in range(len(chans))]
     _same(want, got)
-    a = _run(Solver, chans, "f32", 16, True, 256)
-    b = _run(Solver, chans, "f32", 16, True, 256, graph=64)
+    a = _run(Solver, chans, "f32", 16, 1, 256)
+    b = _run(Solver, chans, "f32", 16, 1, 256, graph=64)
     _same(a, b)
 
 
@@ -87,13 +132,17 @@ def test_fused_only_when_every_channel_fits(Solver):
     wide = workloads.large_2d(lx=40, ly=30, n_hist=64).channels[0]    # 1200 nodes
     grid = small.replace(hist_blocks=2, hist_block_len=8)
     inst = small.replace(law="instantaneous")
-    for chans, want in (([small], True), ([small, wide], False), ([small, grid], False),
-                        ([small, inst], False)):
-        with Solver(chans, precision="f32") as s:
+    damped = small.replace(law="strain_damping")
+    for chans, prec, want in (([small], "f32", 2), ([small], "f32p64", 1), ([small], "f64", 1),
+                              ([small, damped], "f32", 1), ([small, wide], "f32", 0),
+                              ([small, grid], "f32", 0), ([small, inst], "f32", 0)):
+        with Solver(chans, precision=prec) as s:
             s.set_block(8)
             assert s.fused == want
             s.set_block(1)
-            assert not s.fused          # no in-block steps to fuse
+            assert s.fused == 0         # no in-block steps to fuse
             s.set_block(8)
-            s.set_fused(False)
-            assert not s.fused
+            s.set_fused(2)
+            assert s.fused == min(want, 1)
+            s.set_fused(0)
+            assert s.fused == 0
