@@ -411,6 +411,74 @@ def bench_batched(steps: int = 2000):
             "plain_per_channel_f64": plain, "speedup_vs_plain_f64": batched / plain}
 
 
+def bench_adjoint(repeats: int = 3, oracle_steps: int = 200):
+    """Gradients of the differentiation run (1 x 128 channel, window 2048,
+    4000 steps, u_x sampled every 200, checkpoints every 256; LB_F32_P64,
+    8-step blocks): the forward run with its snapshots, then the adjoint sweep
+    (segment replay and the discrete adjoint), for dL/d(G_inf, tau, gamma_c,
+    g_x) of L = sum (u - u_target)^2 with the target from the true
+    parameters.  The oracle's central differences need 8 forward runs; their
+    cost is extrapolated from `oracle_steps` timed oracle steps."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads
+    from paper_1504_06123_amd import Solver, adjoint
+
+    wl = workloads.differentiation()
+    ch = wl.channels[0]
+    steps, every, seg = wl.steps, wl.sample_every, 256
+    with Solver([workloads.true_channel(ch)], precision="f32p64") as s:
+        s.set_block(8)
+        target, _ = adjoint.forward(s, steps, every, seg)
+    fw, bw = [], []
+    with Solver([ch], precision="f32p64") as s:
+        s.set_block(8)
+        init = s.save_state()
+        for _ in range(repeats + 1):      # the first round warms up
+            s.load_state(init)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, ckpts = adjoint.forward(s, steps, every, seg)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            g = adjoint.backward(s, ckpts, steps, every, seg, 2 * (u - target),
+                                 t_start=int(ckpts[0][0]))
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+            del ckpts
+    f_s, b_s = min(fw[1:]), min(bw[1:])
+    # the adjoint history transpose reads the FP64 adjoint ring once per
+    # node and step: n_hist x 8 B
+    alg = ch.nodes * ch.n_hist * 8 * steps
+    gbs = alg / b_s / 1e9
+    oc = oracle.OracleChannel(ch)
+    t0 = time.perf_counter()
+    oc.step(oracle_steps)
+    per_step = (time.perf_counter() - t0) / oracle_steps
+    oc.close()
+    fd_s = 8 * steps * per_step
+    log(f"bench: adjoint 1x{ch.ly} N_h={ch.n_hist} {steps} steps: forward {f_s*1e3:.1f} ms, "
+        f"sweep {b_s*1e3:.1f} ms ({b_s/steps*1e6:.1f} us per step); oracle FD ~{fd_s:.0f} s")
+    return {"workload": f"differentiation run, 1x{ch.ly} channel, N_h={ch.n_hist}, {steps} steps, "
+                        f"u_x sampled every {every}, checkpoints every {seg}",
+            "value": 1.0 / (f_s + b_s), "unit": "gradients/s", "dtype": "f32p64",
+            "forward_ms": f_s * 1e3, "sweep_ms": b_s * 1e3,
+            "sweep_us_per_step": b_s / steps * 1e6,
+            "gradient": [float(x) for x in np.asarray(g)[0]],
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "adjoint sweep (history transpose over the FP64 adjoint ring)",
+                         "alg_bytes": alg,
+                         "note": "128 nodes: a handful of wavefronts per launch, latency-bound"},
+            "oracle_fd": {"seconds_per_gradient": fd_s, "kind": "oracle",
+                          "sample": f"{oracle_steps} oracle steps timed, x 8 runs x {steps} steps",
+                          "cores": 1},
+            "speedup_vs_oracle_fd": fd_s / (f_s + b_s)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,7 +489,8 @@ def main():
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-finger", action="store_true")
     ap.add_argument("--no-laws", action="store_true")
-    ap.add_argument("--only", choices=("grid", "full_tensor", "laws", "batched"),
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--only", choices=("grid", "full_tensor", "laws", "batched", "adjoint"),
                     help="run one side leg alone and print its record")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--block", type=int, default=32, help="steps per pass without tuning")
@@ -460,7 +529,7 @@ def main():
     if args.only:
         # one side leg alone (for profiling); prints that leg's record
         legs = {"grid": bench_grid, "full_tensor": bench_finger, "laws": bench_laws,
-                "batched": bench_batched}
+                "batched": bench_batched, "adjoint": bench_adjoint}
         print(json.dumps({args.only: legs[args.only]()}), flush=True)
         return
 
@@ -485,6 +554,10 @@ def main():
     if not args.no_laws:
         log("bench: alternative constitutive laws on the large 2D channel")
         laws = bench_laws()
+    adj = None
+    if not args.no_adjoint:
+        log("bench: gradients of the differentiation run (adjoint)")
+        adj = bench_adjoint()
     batched = None
     if not args.no_batched:
         log("bench: batched 64-channel workload")
@@ -523,6 +596,7 @@ def main():
         "full_tensor": finger,
         "laws": laws,
         "batched": batched,
+        "adjoint": adj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

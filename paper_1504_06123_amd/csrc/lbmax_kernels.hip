@@ -2522,21 +2522,27 @@ __global__ __launch_bounds__(kBlock) void k_adj_record(char *__restrict__ ws,
     rec[9 * np + n] = reinterpret_cast<const R *>(ws + c->off_sig)[n];
 }
 
+// Workgroup of k_adj_a: 64 nodes (one per lane) x kAdjChunks age ranges of
+// the adjoint window (one per wavefront).
+constexpr int kAdjChunks = 16;
+
 template <typename R, typename RH>
-__global__ __launch_bounds__(kBlock) void k_adj_a(char *__restrict__ ws,
-                                                  const ChanDev *__restrict__ chans,
-                                                  const NodeTile *__restrict__ tiles,
-                                                  char *__restrict__ aws,
-                                                  const AdjChan *__restrict__ achans,
-                                                  int64_t t)
+__global__ __launch_bounds__(kWave * kAdjChunks) void k_adj_a(char *__restrict__ ws,
+                                                              const ChanDev *__restrict__ chans,
+                                                              const NodeTile *__restrict__ tiles,
+                                                              char *__restrict__ aws,
+                                                              const AdjChan *__restrict__ achans,
+                                                              int64_t t)
 {
-    const NodeTile tl = tiles[blockIdx.x];
+    __shared__ double part[2][kAdjChunks][kWave];
+    const NodeTile tl = tiles[blockIdx.x / (kBlock / kWave)];
     const ChanDev *c = chans + tl.ch;
     const AdjChan *a = achans + tl.ch;
-    const int y = tl.n0 + threadIdx.x;  // lx = 1: node index = y
+    const int lane = (int)(threadIdx.x % kWave), chunk = (int)(threadIdx.x / kWave);
+    // lx = 1: node index = y
+    const int y = tl.n0 + (int)(blockIdx.x % (kBlock / kWave)) * kWave + lane;
     const int ly = c->ly;
-    if (y >= ly)
-        return;
+    const bool own = y < ly && tl.n0 + (int)(blockIdx.x % (kBlock / kWave)) * kWave < ly;
     const size_t np = (size_t)c->np;
     const int H = c->n_hist;
     const int p = (int)(t % H);
@@ -2545,33 +2551,76 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(char *__restrict__ ws,
     const R *dbar = reinterpret_cast<const R *>(aws + a->off_dbar);
     R *nbar = reinterpret_cast<R *>(aws + a->off_nbar);
 
-    // sigma_bar^t: transpose of the divergence stencil applied to fbar(t+1)
-    R sb = R(0);
-    for (int yy = max(0, y - 2); yy <= min(ly - 1, y + 2); ++yy)
-        sb += coef_div<R>(yy, y, ly) * fbar[yy];
-    sring[(size_t)p * np + y] = sb;
+    if (own && chunk == 0) {
+        // sigma_bar^t: transpose of the divergence stencil applied to fbar(t+1)
+        R sb = R(0);
+        for (int yy = max(0, y - 2); yy <= min(ly - 1, y + 2); ++yy)
+            sb += coef_div<R>(yy, y, ly) * fbar[yy];
+        sring[(size_t)p * np + y] = sb;
 
-    // nbar(t): transpose of the pull-stream (the push map) applied to dbar(t+1)
+        // nbar(t): transpose of the pull-stream (the push map) applied to dbar(t+1)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const int yt = y + QY[q];
-        nbar[q * np + y] = (yt >= 0 && yt < ly) ? dbar[q * np + yt] : dbar[QOPP[q] * np + y];
+        for (int q = 0; q < 9; ++q) {
+            const int yt = y + QY[q];
+            nbar[q * np + y] = (yt >= 0 && yt < ly) ? dbar[q * np + yt] : dbar[QOPP[q] * np + y];
+        }
     }
+    __syncthreads();  // sigma_bar^t is in the ring before any range reads age 0
 
-    // history transpose for the entry of step t
-    const R s = (R)reinterpret_cast<const RH *>(ws + c->off_ring_s)[(size_t)p * np + y];
-    const R as = fabs(s);
-    const double rate = c->inv_tau + c->inv_gc * (double)as;
-    double S0 = 0.0, S1 = 0.0;
-    int slot = p;
-    for (int j = 0; j < H; ++j) {
-        const double w = (j == 0 || j == H - 1) ? 0.5 : 1.0;
-        const double e = exp(-(double)j * rate);
-        const double v = w * (double)sring[(size_t)slot * np + y] * e;
-        S0 += v;
-        S1 += v * (double)j;
-        slot = slot + 1 == H ? 0 : slot + 1;
+    // History transpose for the entry of step t over the ages j of this
+    // wavefront's range [j0, j1): S0 = sum w_j sbar^{t+j} E_j,
+    // S1 = sum w_j sbar^{t+j} E_j j, E_j = q^j with q = exp(-rate) carried from
+    // E_{j0} = exp(-j0 rate); the ranges combine in FP64 below.
+    R s = R(0);
+    double rate = 0.0, S0 = 0.0, S1 = 0.0;
+    const int j0 = (int)((int64_t)H * chunk / kAdjChunks);
+    const int j1 = (int)((int64_t)H * (chunk + 1) / kAdjChunks);
+    if (own) {
+        s = (R)reinterpret_cast<const RH *>(ws + c->off_ring_s)[(size_t)p * np + y];
+        rate = c->inv_tau + c->inv_gc * (double)fabs(s);
+        const double q = exp(-rate);
+        double e = exp(-(double)j0 * rate);
+        int slot = p + j0;
+        if (slot >= H)
+            slot -= H;
+        constexpr int L = 8;  // ring rows loaded ahead
+        for (int jb = j0; jb < j1; jb += L) {
+            R v[L];
+#pragma unroll
+            for (int u = 0; u < L; ++u) {
+                int sl = slot + u;
+                if (sl >= H)
+                    sl -= H;
+                v[u] = jb + u < j1 ? sring[(size_t)sl * np + y] : R(0);
+            }
+#pragma unroll
+            for (int u = 0; u < L; ++u) {
+                const int j = jb + u;
+                if (j < j1) {
+                    const double w = (j == 0 || j == H - 1) ? 0.5 : 1.0;
+                    const double x = w * (double)v[u] * e;
+                    S0 += x;
+                    S1 += x * (double)j;
+                    e *= q;
+                }
+            }
+            slot += L;
+            if (slot >= H)
+                slot -= H;
+        }
     }
+    part[0][chunk][lane] = S0;
+    part[1][chunk][lane] = S1;
+    __syncthreads();
+    if (!own || chunk != 0)
+        return;
+    S0 = 0.0;
+    S1 = 0.0;
+    for (int k = 0; k < kAdjChunks; ++k) {
+        S0 += part[0][k][lane];
+        S1 += part[1][k][lane];
+    }
+    const R as = fabs(s);
     const double G = c->g_inf;
     reinterpret_cast<R *>(aws + a->off_shbar)[y] = (R)(G * (S0 - (double)as * S1 * c->inv_gc));
     double *acc = reinterpret_cast<double *>(aws + a->off_acc);
@@ -2704,8 +2753,10 @@ void launch_adj_record(int prec, char *ws, const ChanDev *chans, const NodeTile 
 void launch_adj_a(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
                   char *aws, const AdjChan *achans, int64_t t, hipStream_t st)
 {
-    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_a<P, H>), dim3(n_tiles), dim3(kBlock), 0, st,
-                                           ws, chans, tiles, aws, achans, t));
+    // four workgroups of 64 nodes x kAdjChunks wavefronts per node tile
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_a<P, H>), dim3(n_tiles * (kBlock / kWave)),
+                                           dim3(kWave * kAdjChunks), 0, st, ws, chans, tiles,
+                                           aws, achans, t));
 }
 
 void launch_adj_b(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
