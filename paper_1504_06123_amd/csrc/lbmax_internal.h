@@ -62,6 +62,12 @@ struct alignas(256) ChanDev {
     int64_t off_grid_r;             // [qb][qc][np] |gamma_dot| of the averaged gradient (has_r)
     int64_t off_grid_d;             // [3][qb][qc][np] averaged D components (has_r)
     int64_t off_trace;              // [np] tr sigma two steps back (paper coupling)
+    // Adjoint replay: while rec != 0 (a device address), the lattice step t
+    // also records its input populations n*(t-1) and sigma_xy^{t-1} of each
+    // node at rec + (t - rec_t0) * 10 * np elements (the layout of the
+    // adjoint's step record).
+    int64_t rec;
+    int64_t rec_t0;
 };
 static_assert(sizeof(ChanDev) == 256, "ChanDev layout");
 
@@ -160,9 +166,6 @@ struct alignas(64) AdjChan {
     int64_t off_dldu;       // [seg_len][np] double  dL/du_x of each step
 };
 
-void launch_adj_record(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
-                       int n_tiles, const int64_t *tcount, char *aws, const AdjChan *achans,
-                       int slot, hipStream_t st);
 void launch_adj_a(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
                   int n_tiles, char *aws, const AdjChan *achans, int64_t t, hipStream_t st);
 void launch_adj_b(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,

@@ -333,6 +333,13 @@ __device__ __forceinline__ void lb_node(char *__restrict__ ws, const ChanDev *c,
     R *pop = reinterpret_cast<R *>(ws + c->off_pop);
     const R *__restrict__ src = pop + ((t + 1) & 1) * 9 * np;  // n*(t-1)
     R *__restrict__ dst = pop + (t & 1) * 9 * np;              // n*(t)
+    if (c->rec) {
+        R *rec = reinterpret_cast<R *>(c->rec) + (size_t)(t - c->rec_t0) * 10 * np;
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            rec[q * np + n] = src[q * np + n];
+        rec[9 * np + n] = reinterpret_cast<const R *>(ws + c->off_sig)[n];
+    }
     R d[9];
     lb_pull<R>(c, n, src, np, d);
     if (c->coupling) {
@@ -1685,6 +1692,13 @@ __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const Chan
         if (own) {
             A = blk[m * np + n];  // issued before the lattice phase
             B = blk[(kPlaneB + m) * np + n];
+            if (c->rec) {
+                P *rec = reinterpret_cast<P *>(c->rec) + (size_t)(t - c->rec_t0) * 10 * np;
+#pragma unroll
+                for (int q = 0; q < 9; ++q)
+                    rec[q * np + n] = s_pop[q * K + n];
+                rec[9 * np + n] = s_sig[n];
+            }
             P d[9];
             lb_pull<P>(c, n, s_pop, K, d);
             lb_collide_body<P>(c, n, d, s_sig, K, out, ux, uy, drho);
@@ -2497,52 +2511,30 @@ __device__ __forceinline__ R coef_div(int y, int yp, int ly)
     return yp == y + 1 ? R(0.5) : (yp == y - 1 ? R(-0.5) : R(0));
 }
 
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_adj_record(char *__restrict__ ws,
-                                                       const ChanDev *__restrict__ chans,
-                                                       const NodeTile *__restrict__ tiles,
-                                                       const int64_t *__restrict__ tcount,
-                                                       char *__restrict__ aws,
-                                                       const AdjChan *__restrict__ achans,
-                                                       int slot)
-{
-    const NodeTile tl = tiles[blockIdx.x];
-    const ChanDev *c = chans + tl.ch;
-    const AdjChan *a = achans + tl.ch;
-    const int n = tl.n0 + threadIdx.x;
-    if (n >= c->n)
-        return;
-    const size_t np = (size_t)c->np;
-    const int64_t t = *tcount;
-    const R *pop = reinterpret_cast<const R *>(ws + c->off_pop) + ((t + 1) & 1) * 9 * np;
-    R *rec = reinterpret_cast<R *>(aws + a->off_rec) + (size_t)slot * 10 * np;
-#pragma unroll
-    for (int q = 0; q < 9; ++q)
-        rec[q * np + n] = pop[q * np + n];
-    rec[9 * np + n] = reinterpret_cast<const R *>(ws + c->off_sig)[n];
-}
-
-// Workgroup of k_adj_a: 64 nodes (one per lane) x kAdjChunks age ranges of
-// the adjoint window (one per wavefront).
-constexpr int kAdjChunks = 16;
+// Workgroup of k_adj_a: kAdjNodes nodes x kAdjChunks age ranges of the
+// adjoint window; thread = node + kAdjNodes * range, so each wavefront reads
+// kAdjNodes consecutive nodes of 64 / kAdjNodes ranges.
+constexpr int kAdjNodes = 16;
+constexpr int kAdjChunks = 64;
 
 template <typename R, typename RH>
-__global__ __launch_bounds__(kWave * kAdjChunks) void k_adj_a(char *__restrict__ ws,
+__global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(char *__restrict__ ws,
                                                               const ChanDev *__restrict__ chans,
                                                               const NodeTile *__restrict__ tiles,
                                                               char *__restrict__ aws,
                                                               const AdjChan *__restrict__ achans,
                                                               int64_t t)
 {
-    __shared__ double part[2][kAdjChunks][kWave];
-    const NodeTile tl = tiles[blockIdx.x / (kBlock / kWave)];
+    __shared__ double part[2][kAdjChunks][kAdjNodes];
+    constexpr int kSub = kBlock / kAdjNodes;  // workgroups per node tile
+    const NodeTile tl = tiles[blockIdx.x / kSub];
     const ChanDev *c = chans + tl.ch;
     const AdjChan *a = achans + tl.ch;
-    const int lane = (int)(threadIdx.x % kWave), chunk = (int)(threadIdx.x / kWave);
+    const int lane = (int)(threadIdx.x % kAdjNodes), chunk = (int)(threadIdx.x / kAdjNodes);
     // lx = 1: node index = y
-    const int y = tl.n0 + (int)(blockIdx.x % (kBlock / kWave)) * kWave + lane;
+    const int y = tl.n0 + (int)(blockIdx.x % kSub) * kAdjNodes + lane;
     const int ly = c->ly;
-    const bool own = y < ly && tl.n0 + (int)(blockIdx.x % (kBlock / kWave)) * kWave < ly;
+    const bool own = y < ly;
     const size_t np = (size_t)c->np;
     const int H = c->n_hist;
     const int p = (int)(t % H);
@@ -2742,20 +2734,12 @@ __global__ void k_set_params(ChanDev *chans, int ch, double g_inf, double tau_m,
     }
 }
 
-void launch_adj_record(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
-                       int n_tiles, const int64_t *tcount, char *aws, const AdjChan *achans,
-                       int slot, hipStream_t st)
-{
-    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_adj_record<P>, dim3(n_tiles), dim3(kBlock), 0, st,
-                                           ws, chans, tiles, tcount, aws, achans, slot));
-}
-
 void launch_adj_a(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
                   char *aws, const AdjChan *achans, int64_t t, hipStream_t st)
 {
-    // four workgroups of 64 nodes x kAdjChunks wavefronts per node tile
-    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_a<P, H>), dim3(n_tiles * (kBlock / kWave)),
-                                           dim3(kWave * kAdjChunks), 0, st, ws, chans, tiles,
+    // workgroups of kAdjNodes nodes x kAdjChunks age ranges, kBlock / kAdjNodes per node tile
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_a<P, H>), dim3(n_tiles * (kBlock / kAdjNodes)),
+                                           dim3(kAdjNodes * kAdjChunks), 0, st, ws, chans, tiles,
                                            aws, achans, t));
 }
 

@@ -1269,17 +1269,30 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
         return fail(LB_ESTATE, "segment does not end where the previous one began; handle "
                                "poisoned");
     }
-    // replay the segment, recording each step's input populations and stress
-    for (int i = 0; i < n_steps; ++i) {
-        launch_adj_record(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles,
-                          h->d_tcount, h->aws, h->d_achans, i, h->stream);
-        s = check_launch(h, "adjoint record");
-        if (s != LB_OK)
-            return s;
-        s = lb_step(h, 1);
-        if (s != LB_OK)
-            return s;
-    }
+    // replay the segment; its lattice steps record their input populations
+    // and stress into the step records
+    auto set_record = [&](bool on) -> lb_status {
+        for (int ci = 0; ci < h->n_ch; ++ci) {
+            ChanDev &c = h->plan.chans[ci];
+            c.rec = on ? (int64_t)(uintptr_t)(h->aws + h->achans[ci].off_rec) : 0;
+            c.rec_t0 = on ? t0 : 0;
+        }
+        HIP_TRY(h, hipMemcpyAsync(h->d_chans, h->plan.chans.data(),
+                                  h->plan.chans.size() * sizeof(ChanDev), hipMemcpyHostToDevice,
+                                  h->stream));
+        // the host table is reused only after the copy
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        return LB_OK;
+    };
+    s = set_record(true);
+    if (s != LB_OK)
+        return s;
+    s = lb_step(h, n_steps);
+    lb_status s2 = set_record(false);
+    if (s != LB_OK)
+        return s;
+    if (s2 != LB_OK)
+        return s2;
     // dL/du_x of the segment: host [n_steps][sum of nodes]
     size_t total_nodes = 0;
     for (const ChanDev &c : h->plan.chans)
