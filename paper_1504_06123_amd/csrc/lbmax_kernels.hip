@@ -447,7 +447,7 @@ __device__ __forceinline__ void edge_entry(R s, R r, int k, int H, double loc,
 {
 #pragma clang fp contract(off)
     const R rate = decay_rate<R>(dec, r);
-    const R g2 = R(2) * (R)loc;
+    const R g = (R)loc;  // gamma; the factor 2 is applied to the finished B sums
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int a = k + m;
@@ -455,13 +455,13 @@ __device__ __forceinline__ void edge_entry(R s, R r, int k, int H, double loc,
             const R w = (a == 0 || a == H - 1) ? R(0.5) : R(1);
             const R se = w * s * decay_pow(R(a), rate);
             A[m].add(se);
-            B[m].add(se * g2);
+            B[m].add(se * g);
         }
     }
 }
 
 // One entry's terms for the M steps of a block: x q^m into pa[m][v] and
-// x q^m g2 into pb[m][v], m = 0..M-1 (SET: the first entry of a group sets
+// x q^m g2 into pb[m][v] (g2 the entry's strain factor), m = 0..M-1 (SET: the first entry of a group sets
 // them).  For M >= 16, q^m = q^{m mod 8} (q^8)^{m / 8}: eight carried low
 // powers, M/8 high powers (the second set also carries g2), one FMA per sum
 // and step; shorter blocks carry x q^m along m.
@@ -543,15 +543,16 @@ __device__ __forceinline__ void pass_rows(const R *__restrict__ ring_s,
             const R s = sv[u].v[v];
             const R rate = decay_rate<R>(dec, HAS_R ? rv[u].v[v] : fabs(s));
             loc[v] += (double)s;
-            const R g2 = R(2) * (R)loc[v];
+            // gamma (not 2 gamma): doubling the finished B sums is exact
+            const R g = (R)loc[v];
             R x = s * decay_pow(kf, rate);
             R q = R(1);
             if (M > 1)
                 q = decay_pow(R(1), rate);
             if (FIRST && u == 0)
-                add_powers<R, M, V, true>(x, q, g2, pa, pb, v);
+                add_powers<R, M, V, true>(x, q, g, pa, pb, v);
             else
-                add_powers<R, M, V, false>(x, q, g2, pa, pb, v);
+                add_powers<R, M, V, false>(x, q, g, pa, pb, v);
         }
     }
 }
@@ -712,20 +713,21 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
         const int node = first + v;
         if (node >= c->n)
             break;
+        // B was summed with gamma for 2 gamma: doubling is exact
         if (c->nchunks == 1) {
             sig[node] = (P)(c->g_inf * A[0][v].value());
-            sig[np + node] = (P)(c->g_inf * B[0][v].value());
+            sig[np + node] = (P)(c->g_inf * (2.0 * B[0][v].value()));
 #pragma unroll
             for (int m = 1; m < M; ++m) {
                 blk[m * np + node] = A[m][v].value();
-                blk[(kPlaneB + m) * np + node] = B[m][v].value();
+                blk[(kPlaneB + m) * np + node] = 2.0 * B[m][v].value();
             }
         } else {
             const size_t at = (size_t)tl.chunk * np + node;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 part[m * pplane + at] = A[m][v].value();
-                part[(kPlaneB + m) * pplane + at] = B[m][v].value();
+                part[(kPlaneB + m) * pplane + at] = 2.0 * B[m][v].value();
             }
             part[kPlaneT * pplane + at] = loc[v];
         }
