@@ -417,7 +417,7 @@ def bench_adjoint(repeats: int = 3, oracle_steps: int = 200):
     8-step blocks): the forward run with its snapshots, then the adjoint sweep
     (segment replay and the discrete adjoint), for dL/d(G_inf, tau, gamma_c,
     g_x) of L = sum (u - u_target)^2 with the target from the true
-    parameters.  The oracle's central differences need 8 forward runs; their
+    parameters; forward steps and replays in 64-step graphs.  The oracle's central differences need 8 forward runs; their
     cost is extrapolated from `oracle_steps` timed oracle steps."""
     import numpy as np
     import torch
@@ -434,6 +434,7 @@ def bench_adjoint(repeats: int = 3, oracle_steps: int = 200):
     fw, bw = [], []
     with Solver([ch], precision="f32p64") as s:
         s.set_block(8)
+        s.set_graph(64)
         init = s.save_state()
         for _ in range(repeats + 1):      # the first round warms up
             s.load_state(init)
