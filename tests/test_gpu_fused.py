@@ -146,3 +146,24 @@ def test_fused_only_when_every_channel_fits(Solver):
             assert s.fused == min(want, 1)
             s.set_fused(0)
             assert s.fused == 0
+
+
+def test_fused_set_params_and_force_mid_block(Solver):
+    """A parameter change inside a block restarts the block with a fresh pass
+    and a force change cuts a fused span: the LDS form and separate launches
+    stay identical across both."""
+    chans = workloads.batched().channels[:5]
+    say("case fused set_params / set_force mid-block, f32 block 16")
+    res = []
+    for mode in (0, 1):
+        with Solver(chans, precision="f32") as s:
+            s.set_block(16)
+            s.set_fused(mode)
+            s.step(21)                                  # 5 steps into a block
+            for ci in range(len(chans)):
+                s.lib.lb_set_params(s.h, ci, 3e-3, 80.0, 0.07)
+            s.step(11)
+            s.set_force(2, 0.0)
+            s.step(30)
+            res.append([s.fields(ci) + s.stress(ci) for ci in range(len(chans))])
+    _same(res[0], res[1])
