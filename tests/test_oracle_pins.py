@@ -490,6 +490,47 @@ def test_ucm_steady_centreline_maxwell_relation():
     assert errs[1] < errs[0] / 3
 
 
+def test_nlm_steady_channel_solves_the_pointwise_momentum_balance():
+    """Steady shear-thinning channel flow (Sec. IV, steady state): integrating
+    the momentum balance from the centre line gives, at each height,
+    nu s + sigma_ss(s) = -g (y - y_c), where sigma_ss(s) is the history sum of
+    Eq. (gitt) with the modulus of Eq. (nlmax) for a shear rate held at s over
+    the whole window (fixed trapezoid weights, n_hist entries).  Solved
+    pointwise with a root finder, independently of the coupled lattice /
+    history iteration; the oracle's steady shear rate must approach it at
+    second order in 1/ly (g scaled with 1/ly keeps the shear-rate profile,
+    here thinned to about half the Maxwell stress at the walls)."""
+    from scipy.optimize import brentq
+
+    errs = []
+    for ly, steps in ((16, 6000), (32, 20000)):
+        g, tau, Gm, gc, H = 1e-4 * 16 / ly, 12.0, 4e-3, 0.05, 400
+        ch = workloads.Channel(lx=1, ly=ly, tau_lb=1.0, g_inf=Gm, tau_m=tau, gamma_c=gc,
+                               n_hist=H, gx=g)
+        oc = oracle.OracleChannel(ch)
+        oc.step(steps)
+        s = oc.grad()[1][:, 0]
+        oc.close()
+        nu = 0.5 / 3
+        w = np.ones(H)
+        w[0] = w[-1] = 0.5
+        k = np.arange(H)
+
+        def sig(sv):
+            return Gm * sv * np.sum(w * np.exp(-k * (1.0 / tau + abs(sv) / gc)))
+
+        yc = (ly - 1) / 2
+        want = np.array([brentq(lambda sv: nu * sv + sig(sv) + g * (y - yc), -1.0, 1.0)
+                         for y in range(ly)])
+        # thinning is strong: sigma_ss / (G tau s) at the largest rate
+        smax = np.abs(want).max()
+        assert sig(smax) / (Gm * tau * smax) < 0.6
+        inner = slice(2, ly - 2)
+        errs.append(np.abs(s[inner] - want[inner]).max() / smax)
+    assert errs[0] < 3e-3, errs
+    assert errs[1] < errs[0] / 3, errs
+
+
 # --------------------------------------------------------------------------
 # Quasi-logarithmic history grid (Sec. III)
 # --------------------------------------------------------------------------
