@@ -55,6 +55,11 @@ MEASURED = {
                       ("f32p64", 1, 4): 8410395.0 * 1024 * 2 + 52509.82 * 1024},
     # SQ_INSTS_VALU x 64 / history entries
     "valu_instr_per_entry": {("f32p64", 32, 1): 95.64, ("f32p64", 1, 4): 10.54},
+    # the side legs' dominant kernels (profiles/history_variants_large_2d_1024x512.md),
+    # keyed by (leg, steps per pass), same calibration
+    "leg_traffic_bytes": {("grid", 16): 1606550.0 * 1024 * 2 + 211968.0 * 1024,
+                          ("full_tensor", 16): 33557310.0 * 1024 * 2 + 213072.0 * 1024,
+                          ("strain_damping", 32): 8395687.0 * 1024 * 2 + 266240.0 * 1024},
 }
 
 
@@ -278,7 +283,8 @@ def bench_grid(steps: int = 256, B: int = 6, C: int = 128, block: int = 16):
             "value": ch.nodes * steps / el, "unit": "node-steps/s", "ms_per_step": el / steps * 1e3,
             "dtype": "f32 history + f64 lattice", "steps_per_pass": block,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "frac": gbs / HBM_PEAK_GBS,
+                         "traffic": measured("leg_traffic_bytes", ("grid", block)),
                          "kernel": f"k_grid_pass ({block} steps per pass)",
                          "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg_bytes,
                          "in_block_step_avg_ms": edge_s * 1e3}}
@@ -313,7 +319,8 @@ def bench_finger(steps: int = 128):
             "ms_per_step": el / steps * 1e3, "dtype": "f32 history + f64 lattice",
             "config": cfg,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "frac": gbs / HBM_PEAK_GBS,
+                         "traffic": measured("leg_traffic_bytes", ("full_tensor", 16)),
                          "kernel": "k_finger_pass_persistent (16 steps per pass)",
                          "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg_bytes}}
 
@@ -349,7 +356,9 @@ def bench_laws(steps: int = 256):
             alg = ch.nodes * ch.n_hist * 8
             rec["roofline"] = {"bound": "hbm", "achieved": alg / pass_s / 1e9,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": alg / pass_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                               "frac": alg / pass_s / 1e9 / HBM_PEAK_GBS,
+                               "traffic": measured("leg_traffic_bytes",
+                                                   ("strain_damping", block)),
                                "kernel": "k_wm_pass (32 steps per pass)",
                                "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg}
         name = "nlm_paper_coupling" if coupled else law
