@@ -21,6 +21,14 @@ well for the 2D runs):
   batched_cheap8      the 8 batched channels of smallest ly*window, full
                       10000 steps, every 1000
   batched_all_1000    all 64 batched channels, 1000 steps, every 250
+  large_2d_first96    the full 1024 x 512 perturbed channel (the benchmark's
+                      workload) over its first 96 steps, sampled at steps 32,
+                      64 and 96 on 4096 seeded nodes (u_x, u_y, rho, sigma_xy,
+                      N1).  The ring starts zero-filled, so before step
+                      n_hist - 1 every entry past the pushed ones is zero and
+                      contributes nothing: the oracle runs it with a 128-entry
+                      window, identical to the 4096-entry one up to step 126
+                      (tests/test_oracle_pins.py checks this identity)
   differentiation     the 1 x 128 differentiation run: u_x samples (every 200
                       steps) at the true parameters (the target) and at the
                       evaluation point p0, the loss
@@ -89,7 +97,40 @@ def differentiation_fd(h_rel: float = 1e-6):
             "h_rel": h_rel}
 
 
+FIRST96_NODES = 4096
+FIRST96_SAMPLES = (32, 64, 96)
+
+
+def large_2d_first96():
+    ch = workloads.large_2d().channels[0]
+    assert max(FIRST96_SAMPLES) < 127
+    rng = np.random.default_rng(workloads.BASE_SEED + 20)
+    idx = np.sort(rng.choice(ch.nodes, size=FIRST96_NODES, replace=False))
+    oc = oracle.OracleChannel(ch.replace(n_hist=128))
+    out = {"nodes": idx, "t": np.array(FIRST96_SAMPLES), "n_hist_run": 128}
+    cols = {k: [] for k in ("ux", "uy", "rho", "sxy", "n1")}
+    done = 0
+    for t in FIRST96_SAMPLES:
+        oc.step(t - done)
+        done = t
+        rho, ux, uy = oc.fields()
+        sxy, n1 = oc.stress()
+        for k, v in (("ux", ux), ("uy", uy), ("rho", rho), ("sxy", sxy), ("n1", n1)):
+            cols[k].append(v.ravel()[idx])
+    oc.close()
+    for k, v in cols.items():
+        out[k] = np.array(v)
+    return out
+
+
 def make(name):
+    if name == "large_2d_first96":
+        t0 = time.time()
+        out = large_2d_first96()
+        path = os.path.join(HERE, f"{name}.npz")
+        np.savez_compressed(path, **out)
+        print(f"{name}: {time.time() - t0:.0f} s -> {path}", flush=True)
+        return
     if name == "differentiation":
         t0 = time.time()
         out = differentiation_fd()
@@ -116,6 +157,6 @@ def make(name):
 if __name__ == "__main__":
     names = sys.argv[1:] or ["all"]
     if names == ["all"]:
-        names = list(runs()) + ["differentiation"]
+        names = list(runs()) + ["large_2d_first96", "differentiation"]
     for n in names:
         make(n)

@@ -490,6 +490,23 @@ def test_ucm_steady_centreline_maxwell_relation():
     assert errs[1] < errs[0] / 3
 
 
+def test_short_window_equals_long_window_before_it_fills():
+    """The ring starts zero-filled (rest before t = 0), so before step
+    n_hist - 1 the entries past the pushed ones are exact zeros and the end
+    weight falls on a zero: a 128-entry window gives the same numbers as the
+    4096-entry one up to step 126, bit for bit (the identity the stored
+    full-size 96-step run relies on)."""
+    base = workloads.large_2d(lx=12, ly=10, n_hist=4096).channels[0]
+    outs = []
+    for h in (4096, 128):
+        oc = oracle.OracleChannel(base.replace(n_hist=h))
+        oc.step(126)
+        outs.append(oc.fields() + oc.stress() + (oc.grad(),))
+        oc.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
 def test_nlm_steady_channel_solves_the_pointwise_momentum_balance():
     """Steady shear-thinning channel flow (Sec. IV, steady state): integrating
     the momentum balance from the centre line gives, at each height,
