@@ -157,3 +157,36 @@ def test_batched_all_channels_1000_steps(lb, precision):
     got = run(lb, wl, BATCHED_LAUNCH, 1000, 250, precision=precision)
     for c in range(len(wl.channels)):
         check(got[c], gold, c, f"batched ch{c} ly={wl.channels[c].ly}", precision)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_large_2d_full_size_first_steps_in_the_bench_launch(lb, precision):
+    """The benchmark's own workload -- the perturbed 1024 x 512 channel with
+    the 4096-entry window -- in the launch it times (32 steps per pass,
+    persistent pass, 64-step graphs), against the oracle over its first 96
+    steps on 4096 seeded nodes (u_x, u_y, sigma_xy, N1 at steps 32 and 96;
+    the 64 steps in between run as one graph replay)."""
+    from paper_1504_06123_amd import autotune
+    gold = load("large_2d_first96")
+    nodes = gold["nodes"]
+    ch = workloads.large_2d().channels[0]
+    say(f"case large 2D full size first 96 steps, bench launch, {precision}")
+    got = {k: [] for k in ("ux", "uy", "sxy", "n1")}
+    with lb.Solver([ch], precision=precision) as s:
+        autotune.apply(s, LARGE_2D_LAUNCH)
+        for n in (32, 64):
+            s.step(n)
+            _, ux, uy = s.fields(0)
+            sxy, n1 = s.stress(0)
+            for k, v in (("ux", ux), ("uy", uy), ("sxy", sxy), ("n1", n1)):
+                got[k].append(v.ravel()[nodes])
+    rows = [0, 2]                                   # steps 32 and 96
+    vscale = max(np.abs(gold["ux"][rows]).max(), np.abs(gold["uy"][rows]).max())
+    errs = {}
+    for k in got:
+        ref = gold[k][rows]
+        scale = vscale if k in ("ux", "uy") else np.abs(ref).max()
+        errs[k] = float(np.abs(np.array(got[k]) - ref).max() / scale)
+    say("  errors: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= tolerance(precision, "ux" if k == "uy" else k, 96), (k, v)
