@@ -29,6 +29,14 @@ well for the 2D runs):
                       contributes nothing: the oracle runs it with a 128-entry
                       window, identical to the 4096-entry one up to step 126
                       (tests/test_oracle_pins.py checks this identity)
+  variants_first96    the same channel, nodes and identity for the variants
+                      the benchmark times beside it: the full Finger tensor,
+                      the accumulated-strain damping law, the paper's coupling
+                      (each with a 128-entry window, sampled at steps 32, 64
+                      and 96), the instantaneous law (no history, same steps)
+                      and the quasi-logarithmic grid with B = 6, C = 128
+                      (steps 32 and 64; all grid blocks combine within them);
+                      u_x, u_y, sigma_xy, N1
   differentiation     the 1 x 128 differentiation run: u_x samples (every 200
                       steps) at the true parameters (the target) and at the
                       evaluation point p0, the loss
@@ -123,7 +131,54 @@ def large_2d_first96():
     return out
 
 
+def _sample_full_size(ch, samples):
+    """u_x, u_y, rho, sigma_xy, N1 of a full-size channel at the given steps
+    on the FIRST96 nodes."""
+    rng = np.random.default_rng(workloads.BASE_SEED + 20)
+    idx = np.sort(rng.choice(ch.nodes, size=FIRST96_NODES, replace=False))
+    oc = oracle.OracleChannel(ch)
+    cols = {k: [] for k in ("ux", "uy", "rho", "sxy", "n1")}
+    done = 0
+    for t in samples:
+        oc.step(t - done)
+        done = t
+        rho, ux, uy = oc.fields()
+        sxy, n1 = oc.stress()
+        for k, v in (("ux", ux), ("uy", uy), ("rho", rho), ("sxy", sxy), ("n1", n1)):
+            cols[k].append(v.ravel()[idx])
+    oc.close()
+    return idx, {k: np.array(v) for k, v in cols.items()}
+
+
+def variants_first96():
+    base = workloads.large_2d().channels[0]
+    short = base.replace(n_hist=128)
+    cases = {"full_tensor": (short.replace(finger=True), FIRST96_SAMPLES),
+             "strain_damping": (short.replace(law="strain_damping"), FIRST96_SAMPLES),
+             "paper_coupling": (short.replace(paper_coupling=True), FIRST96_SAMPLES),
+             "instantaneous": (base.replace(law="instantaneous"), FIRST96_SAMPLES),
+             "grid": (base.replace(hist_blocks=6, hist_block_len=128), (32, 64))}
+    out = {}
+    for name, (ch, samples) in cases.items():
+        t0 = time.time()
+        idx, cols = _sample_full_size(ch, samples)
+        out["nodes"] = idx
+        out[f"{name}_t"] = np.array(samples)
+        for k, v in cols.items():
+            if k != "rho":
+                out[f"{name}_{k}"] = v
+        print(f"variants_first96: {name} {time.time() - t0:.0f} s", flush=True)
+    return out
+
+
 def make(name):
+    if name == "variants_first96":
+        t0 = time.time()
+        out = variants_first96()
+        path = os.path.join(HERE, f"{name}.npz")
+        np.savez_compressed(path, **out)
+        print(f"{name}: {time.time() - t0:.0f} s -> {path}", flush=True)
+        return
     if name == "large_2d_first96":
         t0 = time.time()
         out = large_2d_first96()
@@ -157,6 +212,6 @@ def make(name):
 if __name__ == "__main__":
     names = sys.argv[1:] or ["all"]
     if names == ["all"]:
-        names = list(runs()) + ["large_2d_first96", "differentiation"]
+        names = list(runs()) + ["large_2d_first96", "variants_first96", "differentiation"]
     for n in names:
         make(n)

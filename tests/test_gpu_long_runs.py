@@ -190,3 +190,69 @@ def test_large_2d_full_size_first_steps_in_the_bench_launch(lb, precision):
     say("  errors: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, v in errs.items():
         assert v <= tolerance(precision, "ux" if k == "uy" else k, 96), (k, v)
+
+
+# the benchmark's side legs: channel options and the launch each is timed in
+VARIANT_LAUNCHES = {
+    "full_tensor": (dict(finger=True),
+                    dict(block=16, vec=1, chunk_len=1 << 30, persistent=True, graph=0)),
+    "strain_damping": (dict(law="strain_damping"),
+                       dict(block=32, vec=1, chunk_len=1 << 30, persistent=False, graph=0)),
+    "paper_coupling": (dict(paper_coupling=True),
+                       dict(block=32, vec=1, chunk_len=1 << 30, persistent=False, graph=0)),
+    "instantaneous": (dict(law="instantaneous"),
+                      dict(block=1, vec=1, chunk_len=1 << 30, persistent=False, graph=0)),
+    "grid": (dict(hist_blocks=6, hist_block_len=128),
+             dict(block=16, vec=1, chunk_len=1 << 30, persistent=False, graph=64)),
+}
+
+
+@pytest.mark.parametrize("name", list(VARIANT_LAUNCHES))
+def test_variants_full_size_first_steps_in_the_bench_launch(lb, name):
+    """The benchmark's side legs on its full-size perturbed channel, in the
+    launches they are timed in, against the oracle's first steps on 4096
+    seeded nodes (u_x, u_y, sigma_xy, N1; LB_F32_P64).  With graphs, the
+    final sample is also taken from a run that reaches it in one graph
+    replay."""
+    from paper_1504_06123_amd import autotune
+    gold = load("variants_first96")
+    nodes = gold["nodes"]
+    ts = [int(t) for t in gold[f"{name}_t"]]
+    kw, launch = VARIANT_LAUNCHES[name]
+    ch = workloads.large_2d().channels[0].replace(**kw)
+    say(f"case {name} full size first {ts[-1]} steps, bench launch")
+
+    def sample(s, got):
+        _, ux, uy = s.fields(0)
+        sxy, n1 = s.stress(0)
+        for k, v in (("ux", ux), ("uy", uy), ("sxy", sxy), ("n1", n1)):
+            got[k].append(v.ravel()[nodes])
+
+    runs = []
+    got = {k: [] for k in ("ux", "uy", "sxy", "n1")}
+    with lb.Solver([ch], precision="f32p64") as s:
+        autotune.apply(s, launch)
+        done = 0
+        for t in ts:
+            s.step(t - done)
+            done = t
+            sample(s, got)
+    runs.append((got, list(range(len(ts)))))
+    if launch["graph"] and ts[-1] >= launch["graph"]:
+        got1 = {k: [] for k in ("ux", "uy", "sxy", "n1")}
+        with lb.Solver([ch], precision="f32p64") as s:
+            autotune.apply(s, launch)
+            s.step(ts[-1])
+            sample(s, got1)
+        runs.append((got1, [len(ts) - 1]))
+    for got, rows in runs:
+        vscale = max(np.abs(gold[f"{name}_ux"][rows]).max(),
+                     np.abs(gold[f"{name}_uy"][rows]).max())
+        errs = {}
+        for k in got:
+            ref = gold[f"{name}_{k}"][rows]
+            scale = vscale if k in ("ux", "uy") else np.abs(ref).max()
+            errs[k] = float(np.abs(np.array(got[k]) - ref).max() / scale) if scale > 0 else 0.0
+        say("  errors: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+        for k, v in errs.items():
+            assert v <= tolerance("f32p64", "ux" if k == "uy" else k, ts[-1]), (k, v)

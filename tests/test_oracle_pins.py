@@ -490,13 +490,17 @@ def test_ucm_steady_centreline_maxwell_relation():
     assert errs[1] < errs[0] / 3
 
 
-def test_short_window_equals_long_window_before_it_fills():
+@pytest.mark.parametrize("kw", [{}, {"finger": True}, {"law": "strain_damping"},
+                                {"paper_coupling": True}])
+def test_short_window_equals_long_window_before_it_fills(kw):
     """The ring starts zero-filled (rest before t = 0), so before step
-    n_hist - 1 the entries past the pushed ones are exact zeros and the end
-    weight falls on a zero: a 128-entry window gives the same numbers as the
-    4096-entry one up to step 126, bit for bit (the identity the stored
-    full-size 96-step run relies on)."""
-    base = workloads.large_2d(lx=12, ly=10, n_hist=4096).channels[0]
+    n_hist - 1 the entries past the pushed ones are exact zeros (zero shear
+    rate and gradient: no stress term, an identity deformation factor, no
+    accumulated strain) and the end weight falls on a zero: a 128-entry
+    window gives the same numbers as the 4096-entry one up to step 126, bit
+    for bit, for every law and tensor form (the identity the stored
+    full-size 96-step runs rely on)."""
+    base = workloads.large_2d(lx=12, ly=10, n_hist=4096).channels[0].replace(**kw)
     outs = []
     for h in (4096, 128):
         oc = oracle.OracleChannel(base.replace(n_hist=h))
