@@ -419,6 +419,45 @@ __device__ __forceinline__ Pack<R, V> load_pack(const R *row, uint32_t off)
     return *reinterpret_cast<const Pack<R, V> *>(reinterpret_cast<const char *>(row) + off);
 }
 
+typedef const __attribute__((address_space(1))) char *GlobalBytes;
+
+// The same load with the row address held in scalar registers: the empty asm
+// pins the (wave-uniform) row address to an SGPR pair, so it is not
+// reassociated with the lane offset, and with a 32-bit lane offset defined in
+// the same block (see pass_rows) the load takes the scalar-base form (row
+// address + 32-bit lane offset) instead of a 64-bit vector add per row.
+template <typename R, int V>
+__device__ __forceinline__ Pack<R, V> load_pack_sbase(const R *row, uint32_t off)
+{
+    uint64_t a = reinterpret_cast<uint64_t>(row);
+    asm volatile("" : "+s"(a));
+    const GlobalBytes p = reinterpret_cast<GlobalBytes>(a) + off;
+    Pack<R, V> r;
+    if constexpr (V == 1) {
+        r.v[0] = *reinterpret_cast<const __attribute__((address_space(1))) R *>(p);
+    } else {
+        typedef R Vec __attribute__((ext_vector_type(V)));
+        const Vec x = *reinterpret_cast<const __attribute__((address_space(1))) Vec *>(p);
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            r.v[v] = x[v];
+    }
+    return r;
+}
+
+// float(u) for a wave-uniform 0 <= u < 2^24 (exact), built from its bits with
+// integer operations in scalar registers, so it enters the vector
+// instructions as a scalar operand instead of a per-row vector conversion
+// (the empty asm keeps the compiler from turning it back into one).
+__device__ __forceinline__ float small_uniform_to_float(uint32_t u)
+{
+    const int e = 31 - __builtin_clz(u | 1u);  // u = 0 is selected below
+    uint32_t bits = ((uint32_t)(e + 127) << 23) | ((u << (23 - e)) & 0x7FFFFFu);
+    bits = u ? bits : 0u;
+    asm volatile("" : "+s"(bits));
+    return __builtin_bit_cast(float, bits);
+}
+
 __device__ __forceinline__ float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -462,9 +501,10 @@ __device__ __forceinline__ void edge_entry(R s, R r, int k, int H, double loc,
 
 // One entry's terms for the M steps of a block: x q^m into pa[m][v] and
 // x q^m g2 into pb[m][v] (g2 the entry's strain factor), m = 0..M-1 (SET: the first entry of a group sets
-// them).  For M >= 16, q^m = q^{m mod 8} (q^8)^{m / 8}: eight carried low
-// powers, M/8 high powers (the second set also carries g2), one FMA per sum
-// and step; shorter blocks carry x q^m along m.
+// them).  For M >= 16, x q^m = q^{m mod 8} (x q^{8 (m / 8)}): seven low
+// powers of q, M/8 high powers carrying x and M/8 carrying x g2, one FMA
+// (an add for m mod 8 = 0) per sum and step; shorter blocks carry x q^m
+// along m.
 template <typename R, int M, int V, bool SET>
 __device__ __forceinline__ void add_powers(R x, R q, R g2, R (&pa)[M][V], R (&pb)[M][V],
                                            int v)
@@ -472,30 +512,30 @@ __device__ __forceinline__ void add_powers(R x, R q, R g2, R (&pa)[M][V], R (&pb
 #pragma clang fp contract(off)
     if constexpr (M >= 16 && M % 8 == 0) {
         constexpr int MH = M / 8;
-        R lo[8], hi[MH], hg[MH];
-        lo[0] = x;
+        R lo[8], hx[MH], hg[MH];
+        lo[1] = q;
 #pragma unroll
-        for (int i = 1; i < 8; ++i)
+        for (int i = 2; i < 8; ++i)
             lo[i] = lo[i - 1] * q;
-        const R q2 = q * q, q4 = q2 * q2, q8 = q4 * q4;
-        hi[0] = R(1);
-        hg[0] = g2;
+        const R q8 = lo[4] * lo[4];
+        hx[0] = x;
 #pragma unroll
-        for (int j = 1; j < MH; ++j) {
-            hi[j] = j == 1 ? q8 : hi[j - 1] * q8;
-            hg[j] = hi[j] * g2;
-        }
+        for (int j = 1; j < MH; ++j)
+            hx[j] = hx[j - 1] * q8;
+#pragma unroll
+        for (int j = 0; j < MH; ++j)
+            hg[j] = hx[j] * g2;
 #pragma unroll
         for (int j = 0; j < MH; ++j)
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int m = 8 * j + i;
                 if (SET) {
-                    pa[m][v] = j == 0 ? lo[i] : lo[i] * hi[j];
-                    pb[m][v] = lo[i] * hg[j];
+                    pa[m][v] = i == 0 ? hx[j] : lo[i] * hx[j];
+                    pb[m][v] = i == 0 ? hg[j] : lo[i] * hg[j];
                 } else {
-                    pa[m][v] = j == 0 ? pa[m][v] + lo[i] : fused(lo[i], hi[j], pa[m][v]);
-                    pb[m][v] = fused(lo[i], hg[j], pb[m][v]);
+                    pa[m][v] = i == 0 ? pa[m][v] + hx[j] : fused(lo[i], hx[j], pa[m][v]);
+                    pb[m][v] = i == 0 ? pb[m][v] + hg[j] : fused(lo[i], hg[j], pb[m][v]);
                 }
             }
     } else {
@@ -528,16 +568,22 @@ __device__ __forceinline__ void pass_rows(const R *__restrict__ ring_s,
     // same operations the same way (the FMAs are written out).
 #pragma clang fp contract(off)
     Pack<R, V> sv[U], rv[U];
+    uint32_t off = lane_off;  // redefined here, so the loads below see a 32-bit offset
+    asm volatile("" : "+v"(off));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const size_t row = (size_t)(slot - u) * np;
-        sv[u] = load_pack<R, V>(ring_s + row, lane_off);
+        sv[u] = load_pack_sbase<R, V>(ring_s + row, off);
         if (HAS_R)
-            rv[u] = load_pack<R, V>(ring_r + row, lane_off);
+            rv[u] = load_pack_sbase<R, V>(ring_r + row, off);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const R kf = R(kf0 + u);
+        // ages stay below 2^24 in FP32 histories (the window is limited to
+        // that), where the scalar construction equals the vector conversion
+        const R kf = sizeof(R) == 4
+                         ? R(small_uniform_to_float((uint32_t)__builtin_amdgcn_readfirstlane(kf0 + u)))
+                         : R(kf0 + u);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const R s = sv[u].v[v];

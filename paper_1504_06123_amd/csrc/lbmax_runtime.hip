@@ -61,7 +61,7 @@ bool unidirectional(const lb_channel_desc &d)
     return true;
 }
 
-std::string check_desc(const lb_channel_desc *ch, int32_t n_ch)
+std::string check_desc(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
 {
     if (!ch)
         return "channel array is NULL";
@@ -84,6 +84,10 @@ std::string check_desc(const lb_channel_desc *ch, int32_t n_ch)
             return bad("hist_blocks must be >= 0");
         if (d.hist_blocks == 0 && d.law != 2 && d.n_hist < 2)
             return bad("n_hist must be >= 2");
+        // FP32 histories take the age of an entry as an FP32 number, exact
+        // below 2^24
+        if (prec != LB_F64 && d.hist_blocks == 0 && d.law != 2 && d.n_hist > (1 << 24))
+            return bad("n_hist must be <= 2^24 with FP32 histories");
         if (d.finger != 0 && d.finger != 1)
             return bad("finger must be 0 or 1");
         if (d.paper_coupling != 0 && d.paper_coupling != 1)
@@ -760,7 +764,7 @@ size_t lb_workspace_bytes(const lb_channel_desc *ch, int32_t n_ch, lb_precision 
         g_err = "unknown precision";
         return 0;
     }
-    std::string why = check_desc(ch, n_ch);
+    std::string why = check_desc(ch, n_ch, prec);
     if (!why.empty()) {
         g_err = why;
         return 0;
@@ -776,7 +780,7 @@ lb_status lb_init(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec, vo
     *out = nullptr;
     if (prec != LB_F64 && prec != LB_F32 && prec != LB_F32_P64)
         return fail(LB_EINVAL, "unknown precision");
-    std::string why = check_desc(ch, n_ch);
+    std::string why = check_desc(ch, n_ch, prec);
     if (!why.empty())
         return fail(LB_EINVAL, why);
     if (!d_ws)

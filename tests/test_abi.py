@@ -90,6 +90,18 @@ def test_invalid_descriptions_rejected(lib, field, value, msg):
     assert st == -1 and not h.value
 
 
+def test_fp32_window_limited_to_exact_ages(lib):
+    """FP32 histories take entry ages as FP32 numbers, exact below 2^24: a
+    longer window is rejected for them and accepted in FP64."""
+    arr, _ = _desc(n_hist=(1 << 24) + 1)
+    for prec in (1, 2):
+        assert lib.lb_workspace_bytes(arr, 1, prec) == 0
+        assert "2^24" in lib.lb_last_error().decode()
+    assert lib.lb_workspace_bytes(arr, 1, 0) > 0
+    arr, _ = _desc(n_hist=1 << 24)
+    assert lib.lb_workspace_bytes(arr, 1, 1) > 0
+
+
 def test_gamma_c_infinite_is_the_linear_limit(lib):
     arr, _ = _desc(gamma_c=math.inf)
     assert lib.lb_workspace_bytes(arr, 1, 1) > 0
