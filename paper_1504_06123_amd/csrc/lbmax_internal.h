@@ -155,12 +155,16 @@ void launch_readout(int prec, int which, char *ws, const ChanDev *chans,
 namespace lbmax {
 
 // Adjoint workspace of one channel (byte offsets into the adjoint workspace).
+// Workgroups over the age window per group of nodes in the adjoint's
+// history transpose.
+constexpr int kAdjGroups = 8;
+
 struct alignas(64) AdjChan {
     int64_t off_sbar_ring;  // [n_hist][np] R  adjoint of sigma_xy, row t mod n_hist
     int64_t off_nbar;       // [9][np] R  adjoint of the post-collision populations
     int64_t off_dbar;       // [9][np] R  adjoint of the pulled populations
     int64_t off_fbar;       // [np] R     adjoint of the force f_x
-    int64_t off_shbar;      // [np] R     adjoint of the pushed shear rate
+    int64_t off_part;       // [kAdjGroups][2][np] double  history-transpose partial sums
     int64_t off_acc;        // [4][np] double  per-node parameter gradients
     int64_t off_rec;        // [seg_len][10][np] R  n*(t-1) (9 planes), sigma_xy^{t-1}
     int64_t off_dldu;       // [seg_len][np] double  dL/du_x of each step
@@ -169,7 +173,8 @@ struct alignas(64) AdjChan {
 void launch_adj_a(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
                   int n_tiles, char *aws, const AdjChan *achans, int64_t t, hipStream_t st);
 void launch_adj_b(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
-                  int n_tiles, char *aws, const AdjChan *achans, int slot, hipStream_t st);
+                  int n_tiles, char *aws, const AdjChan *achans, int64_t t, int slot,
+                  hipStream_t st);
 void launch_adj_reduce(const ChanDev *chans, int n_ch, char *aws, const AdjChan *achans,
                        double *out, hipStream_t st);
 void launch_set_params(ChanDev *chans, int ch, double g_inf, double tau_m, double gamma_c,

@@ -2559,11 +2559,34 @@ __device__ __forceinline__ R coef_div(int y, int yp, int ly)
     return yp == y + 1 ? R(0.5) : (yp == y - 1 ? R(-0.5) : R(0));
 }
 
-// Workgroup of k_adj_a: kAdjNodes nodes x kAdjChunks age ranges of the
-// adjoint window; thread = node + kAdjNodes * range, so each wavefront reads
-// kAdjNodes consecutive nodes of 64 / kAdjNodes ranges.
+// Workgroup of k_adj_a: kAdjNodes nodes x kAdjChunks age ranges of one of
+// kAdjGroups parts of the adjoint window; thread = node + kAdjNodes * range,
+// so each wavefront reads kAdjNodes consecutive nodes of 64 / kAdjNodes
+// ranges.  The kAdjGroups x kAdjChunks ranges split [0, n_hist) with rounded-up
+// bounds, so the first range always holds age 0 (the entry pushed by the same
+// workgroup).
 constexpr int kAdjNodes = 16;
 constexpr int kAdjChunks = 64;
+constexpr int kAdjRanges = kAdjGroups * kAdjChunks;
+
+// Adjoint of the pushed shear rate at node y (the history transpose of step
+// t combined over the kAdjGroups partial sums in group order) and the two
+// sums themselves.
+template <typename RH>
+__device__ __forceinline__ double adj_sbar(const char *ws, const ChanDev *c, const double *part,
+                                           int64_t t, int y, double &S0, double &S1, double &s)
+{
+    const size_t np = (size_t)c->np;
+    S0 = 0.0;
+    S1 = 0.0;
+#pragma unroll
+    for (int g = 0; g < kAdjGroups; ++g) {
+        S0 += part[(size_t)(2 * g) * np + y];
+        S1 += part[(size_t)(2 * g + 1) * np + y];
+    }
+    s = (double)reinterpret_cast<const RH *>(ws + c->off_ring_s)[(size_t)(t % c->n_hist) * np + y];
+    return c->g_inf * (S0 - fabs(s) * S1 * c->inv_gc);
+}
 
 template <typename R, typename RH>
 __global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(char *__restrict__ ws,
@@ -2574,13 +2597,15 @@ __global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(char *__restri
                                                               int64_t t)
 {
     __shared__ double part[2][kAdjChunks][kAdjNodes];
-    constexpr int kSub = kBlock / kAdjNodes;  // workgroups per node tile
-    const NodeTile tl = tiles[blockIdx.x / kSub];
+    constexpr int kSub = kBlock / kAdjNodes;  // node groups per node tile
+    const int grp = (int)(blockIdx.x % kAdjGroups);
+    const int sub = (int)(blockIdx.x / kAdjGroups);
+    const NodeTile tl = tiles[sub / kSub];
     const ChanDev *c = chans + tl.ch;
     const AdjChan *a = achans + tl.ch;
     const int lane = (int)(threadIdx.x % kAdjNodes), chunk = (int)(threadIdx.x / kAdjNodes);
     // lx = 1: node index = y
-    const int y = tl.n0 + (int)(blockIdx.x % kSub) * kAdjNodes + lane;
+    const int y = tl.n0 + (sub % kSub) * kAdjNodes + lane;
     const int ly = c->ly;
     const bool own = y < ly;
     const size_t np = (size_t)c->np;
@@ -2591,7 +2616,7 @@ __global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(char *__restri
     const R *dbar = reinterpret_cast<const R *>(aws + a->off_dbar);
     R *nbar = reinterpret_cast<R *>(aws + a->off_nbar);
 
-    if (own && chunk == 0) {
+    if (own && chunk == 0 && grp == 0) {
         // sigma_bar^t: transpose of the divergence stencil applied to fbar(t+1)
         R sb = R(0);
         for (int yy = max(0, y - 2); yy <= min(ly - 1, y + 2); ++yy)
@@ -2613,9 +2638,10 @@ __global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(char *__restri
     // E_{j0} = exp(-j0 rate); the ranges combine in FP64 below.
     R s = R(0);
     double rate = 0.0, S0 = 0.0, S1 = 0.0;
-    const int j0 = (int)((int64_t)H * chunk / kAdjChunks);
-    const int j1 = (int)((int64_t)H * (chunk + 1) / kAdjChunks);
-    if (own) {
+    const int64_t rg = (int64_t)grp * kAdjChunks + chunk;
+    const int j0 = (int)(((int64_t)H * rg + kAdjRanges - 1) / kAdjRanges);
+    const int j1 = (int)(((int64_t)H * (rg + 1) + kAdjRanges - 1) / kAdjRanges);
+    if (own && j0 < j1) {
         s = (R)reinterpret_cast<const RH *>(ws + c->off_ring_s)[(size_t)p * np + y];
         rate = c->inv_tau + c->inv_gc * (double)fabs(s);
         const double q = exp(-rate);
@@ -2660,22 +2686,19 @@ __global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(char *__restri
         S0 += part[0][k][lane];
         S1 += part[1][k][lane];
     }
-    const R as = fabs(s);
-    const double G = c->g_inf;
-    reinterpret_cast<R *>(aws + a->off_shbar)[y] = (R)(G * (S0 - (double)as * S1 * c->inv_gc));
-    double *acc = reinterpret_cast<double *>(aws + a->off_acc);
-    acc[y] += (double)s * S0;
-    acc[np + y] += G * (double)s * S1 * c->inv_tau * c->inv_tau;
-    acc[2 * np + y] += G * (double)s * (double)as * S1 * c->inv_gc * c->inv_gc;
+    // this group's sums; k_adj_b combines the groups in group order
+    double *gpart = reinterpret_cast<double *>(aws + a->off_part);
+    gpart[(size_t)(2 * grp) * np + y] = S0;
+    gpart[(size_t)(2 * grp + 1) * np + y] = S1;
 }
 
-template <typename R>
+template <typename R, typename RH>
 __global__ __launch_bounds__(kBlock) void k_adj_b(char *__restrict__ ws,
                                                   const ChanDev *__restrict__ chans,
                                                   const NodeTile *__restrict__ tiles,
                                                   char *__restrict__ aws,
                                                   const AdjChan *__restrict__ achans,
-                                                  int slot)
+                                                  int64_t t, int slot)
 {
     const NodeTile tl = tiles[blockIdx.x];
     const ChanDev *c = chans + tl.ch;
@@ -2733,9 +2756,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(char *__restrict__ ws,
     }
     // the loss and the velocity-gradient transpose
     ux_b += (R)reinterpret_cast<const double *>(aws + a->off_dldu)[(size_t)slot * np + y];
-    const R *shbar = reinterpret_cast<const R *>(aws + a->off_shbar);
-    for (int yy = max(0, y - 1); yy <= min(ly - 1, y + 1); ++yy)
-        ux_b += coef_grad<R>(yy, y, ly) * shbar[yy];
+    const double *part = reinterpret_cast<const double *>(aws + a->off_part);
+    double *acc = reinterpret_cast<double *>(aws + a->off_acc);
+    for (int yy = max(0, y - 1); yy <= min(ly - 1, y + 1); ++yy) {
+        double S0, S1, s;
+        const R sbar = (R)adj_sbar<RH>(ws, c, part, t, yy, S0, S1, s);
+        ux_b += coef_grad<R>(yy, y, ly) * sbar;
+        if (yy == y) {
+            // parameter terms of the history transpose at this node
+            const double G = c->g_inf, as = fabs(s);
+            acc[y] += s * S0;
+            acc[np + y] += G * s * S1 * c->inv_tau * c->inv_tau;
+            acc[2 * np + y] += G * s * as * S1 * c->inv_gc * c->inv_gc;
+        }
+    }
     // u = (j + f/2) / rho
     const R jx_b = ux_b / rho;
     const R jy_b = uy_b / rho;
@@ -2743,7 +2777,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(char *__restrict__ ws,
     drho_b -= (ux * ux_b + uy * uy_b) / rho;
     // f_x = Dy sigma + rho g_x
     drho_b += fx_b * gx;
-    double *acc = reinterpret_cast<double *>(aws + a->off_acc);
     acc[3 * np + y] += (double)fx_b * (double)rho;
     // moments of the pulled populations
     R *dbar = reinterpret_cast<R *>(aws + a->off_dbar);
@@ -2785,17 +2818,19 @@ __global__ void k_set_params(ChanDev *chans, int ch, double g_inf, double tau_m,
 void launch_adj_a(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
                   char *aws, const AdjChan *achans, int64_t t, hipStream_t st)
 {
-    // workgroups of kAdjNodes nodes x kAdjChunks age ranges, kBlock / kAdjNodes per node tile
-    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_a<P, H>), dim3(n_tiles * (kBlock / kAdjNodes)),
+    // workgroups of kAdjNodes nodes x kAdjChunks age ranges: kBlock / kAdjNodes node
+    // groups per node tile, kAdjGroups parts of the window per node group
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_a<P, H>),
+                                           dim3(n_tiles * (kBlock / kAdjNodes) * kAdjGroups),
                                            dim3(kAdjNodes * kAdjChunks), 0, st, ws, chans, tiles,
                                            aws, achans, t));
 }
 
 void launch_adj_b(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
-                  char *aws, const AdjChan *achans, int slot, hipStream_t st)
+                  char *aws, const AdjChan *achans, int64_t t, int slot, hipStream_t st)
 {
-    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_adj_b<P>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
-                                           chans, tiles, aws, achans, slot));
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_b<P, H>), dim3(n_tiles), dim3(kBlock), 0, st,
+                                           ws, chans, tiles, aws, achans, t, slot));
 }
 
 void launch_adj_reduce(const ChanDev *chans, int n_ch, char *aws, const AdjChan *achans,

@@ -713,8 +713,8 @@ AdjPlan make_adj_plan(const lb_handle *h, int seg_len)
         off = align_up(off + 9 * plane, 256);
         a.off_fbar = (int64_t)off;
         off = align_up(off + plane, 256);
-        a.off_shbar = (int64_t)off;
-        off = align_up(off + plane, 256);
+        a.off_part = (int64_t)off;
+        off = align_up(off + (size_t)kAdjGroups * 2 * c.np * sizeof(double), 256);
         a.off_acc = (int64_t)off;
         off = align_up(off + 4 * (size_t)c.np * sizeof(double), 256);
         a.off_rec = (int64_t)off;
@@ -1315,7 +1315,7 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
         launch_adj_a(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
                      h->d_achans, t, h->stream);
         launch_adj_b(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
-                     h->d_achans, (int)(t - t0), h->stream);
+                     h->d_achans, t, (int)(t - t0), h->stream);
         s = check_launch(h, "adjoint step");
         if (s != LB_OK)
             return s;
