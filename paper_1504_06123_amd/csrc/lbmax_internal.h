@@ -170,11 +170,15 @@ struct alignas(64) AdjChan {
     int64_t off_dldu;       // [seg_len][np] double  dL/du_x of each step
 };
 
+// The adjoint kernels of step t = *t0 + slot (t0 in device memory, so one
+// captured sweep serves every segment of the same length).
 void launch_adj_a(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
-                  int n_tiles, char *aws, const AdjChan *achans, int64_t t, hipStream_t st);
-void launch_adj_b(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
-                  int n_tiles, char *aws, const AdjChan *achans, int64_t t, int slot,
+                  int n_tiles, char *aws, const AdjChan *achans, const int64_t *t0, int slot,
                   hipStream_t st);
+void launch_adj_b(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
+                  int n_tiles, char *aws, const AdjChan *achans, const int64_t *t0, int slot,
+                  hipStream_t st);
+void launch_store_i64(int64_t *p, int64_t v, hipStream_t st);
 void launch_adj_reduce(const ChanDev *chans, int n_ch, char *aws, const AdjChan *achans,
                        double *out, hipStream_t st);
 void launch_set_params(ChanDev *chans, int ch, double g_inf, double tau_m, double gamma_c,

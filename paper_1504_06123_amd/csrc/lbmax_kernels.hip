@@ -2594,8 +2594,10 @@ __global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(char *__restri
                                                               const NodeTile *__restrict__ tiles,
                                                               char *__restrict__ aws,
                                                               const AdjChan *__restrict__ achans,
-                                                              int64_t t)
+                                                              const int64_t *__restrict__ t0,
+                                                              int slot)
 {
+    const int64_t t = *t0 + slot;
     __shared__ double part[2][kAdjChunks][kAdjNodes];
     constexpr int kSub = kBlock / kAdjNodes;  // node groups per node tile
     const int grp = (int)(blockIdx.x % kAdjGroups);
@@ -2698,8 +2700,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(char *__restrict__ ws,
                                                   const NodeTile *__restrict__ tiles,
                                                   char *__restrict__ aws,
                                                   const AdjChan *__restrict__ achans,
-                                                  int64_t t, int slot)
+                                                  const int64_t *__restrict__ t0, int slot)
 {
+    const int64_t t = *t0 + slot;
     const NodeTile tl = tiles[blockIdx.x];
     const ChanDev *c = chans + tl.ch;
     const AdjChan *a = achans + tl.ch;
@@ -2816,21 +2819,32 @@ __global__ void k_set_params(ChanDev *chans, int ch, double g_inf, double tau_m,
 }
 
 void launch_adj_a(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
-                  char *aws, const AdjChan *achans, int64_t t, hipStream_t st)
+                  char *aws, const AdjChan *achans, const int64_t *t0, int slot, hipStream_t st)
 {
     // workgroups of kAdjNodes nodes x kAdjChunks age ranges: kBlock / kAdjNodes node
     // groups per node tile, kAdjGroups parts of the window per node group
     LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_a<P, H>),
                                            dim3(n_tiles * (kBlock / kAdjNodes) * kAdjGroups),
                                            dim3(kAdjNodes * kAdjChunks), 0, st, ws, chans, tiles,
-                                           aws, achans, t));
+                                           aws, achans, t0, slot));
 }
 
 void launch_adj_b(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
-                  char *aws, const AdjChan *achans, int64_t t, int slot, hipStream_t st)
+                  char *aws, const AdjChan *achans, const int64_t *t0, int slot, hipStream_t st)
 {
     LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_b<P, H>), dim3(n_tiles), dim3(kBlock), 0, st,
-                                           ws, chans, tiles, aws, achans, t, slot));
+                                           ws, chans, tiles, aws, achans, t0, slot));
+}
+
+__global__ void k_store_i64(int64_t *p, int64_t v)
+{
+    if (threadIdx.x == 0)
+        p[0] = v;
+}
+
+void launch_store_i64(int64_t *p, int64_t v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_store_i64, dim3(1), dim3(64), 0, st, p, v);
 }
 
 void launch_adj_reduce(const ChanDev *chans, int n_ch, char *aws, const AdjChan *achans,

@@ -293,6 +293,9 @@ struct lb_handle {
     AdjChan *d_achans = nullptr;
     double *d_adj_out = nullptr;
     std::vector<AdjChan> achans;
+    int64_t *d_adj_t0 = nullptr;
+    // captured reverse sweeps by segment length (for this adjoint workspace)
+    std::vector<std::pair<int, hipGraphExec_t>> adj_execs;
     int adj_seg_len = 0;
     int64_t adj_next = -1;  // the next segment must end at this step (-1: no sweep)
     // timing: event pairs recorded around launches, resolved on demand
@@ -687,7 +690,7 @@ size_t state_size(const lb_handle *h)
 // Adjoint sweep
 // ---------------------------------------------------------------------------
 struct AdjPlan {
-    size_t total = 0, off_table = 0, off_out = 0;
+    size_t total = 0, off_table = 0, off_out = 0, off_t0 = 0;
     std::vector<AdjChan> chans;
 };
 
@@ -700,6 +703,8 @@ AdjPlan make_adj_plan(const lb_handle *h, int seg_len)
     off = align_up(off + (size_t)h->n_ch * sizeof(AdjChan), 256);
     P.off_out = off;
     off = align_up(off + (size_t)h->n_ch * 4 * sizeof(double), 256);
+    P.off_t0 = off;  // first step of the segment being swept
+    off = align_up(off + sizeof(int64_t), 256);
     P.chans.resize(h->n_ch);
     for (int ci = 0; ci < h->n_ch; ++ci) {
         const ChanDev &c = h->plan.chans[ci];
@@ -752,6 +757,54 @@ std::string adjoint_unsupported(const lb_handle *h, int seg_len)
         return "seg_len must be >= 1";
     return "";
 }
+
+void drop_adj_graphs(lb_handle *h)
+{
+    for (auto &e : h->adj_execs)
+        (void)hipGraphExecDestroy(e.second);
+    h->adj_execs.clear();
+}
+
+// The reverse sweep of n_steps steps (k_adj_a then k_adj_b for slots
+// n_steps-1 .. 0), captured once per length and replayed for every segment.
+lb_status adj_sweep_graph(lb_handle *h, int n_steps, hipGraphExec_t *out)
+{
+    for (auto &e : h->adj_execs)
+        if (e.first == n_steps) {
+            *out = e.second;
+            return LB_OK;
+        }
+    if (!h->cap_stream)
+        HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = n_steps - 1; k >= 0; --k) {
+        launch_adj_a(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
+                     h->d_achans, h->d_adj_t0, k, h->cap_stream);
+        launch_adj_b(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
+                     h->d_achans, h->d_adj_t0, k, h->cap_stream);
+    }
+    const hipError_t cap = hipGetLastError();
+    hipGraph_t g = nullptr;
+    const hipError_t end = hipStreamEndCapture(h->cap_stream, &g);
+    if (cap != hipSuccess || end != hipSuccess || !g) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        h->poisoned = true;
+        return fail(LB_EDEVICE, std::string("adjoint sweep capture: ") +
+                                    hipGetErrorString(cap != hipSuccess ? cap : end));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t inst = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (inst != hipSuccess) {
+        h->poisoned = true;
+        return fail(LB_EDEVICE, std::string("adjoint sweep graph: ") + hipGetErrorString(inst));
+    }
+    h->adj_execs.push_back({n_steps, exec});
+    *out = exec;
+    return LB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1234,11 +1287,14 @@ lb_status lb_adjoint_begin(lb_handle *h, void *d_aws, size_t bytes, int32_t seg_
     AdjPlan P = make_adj_plan(h, seg_len);
     if (bytes < P.total)
         return fail(LB_ENOMEM, "adjoint workspace too small: need " + std::to_string(P.total));
+    if (h->aws != static_cast<char *>(d_aws) || h->adj_seg_len != seg_len)
+        drop_adj_graphs(h);  // they address the previous workspace
     h->aws = static_cast<char *>(d_aws);
     h->aws_bytes = bytes;
     h->achans = P.chans;
     h->d_achans = reinterpret_cast<AdjChan *>(h->aws + P.off_table);
     h->d_adj_out = reinterpret_cast<double *>(h->aws + P.off_out);
+    h->d_adj_t0 = reinterpret_cast<int64_t *>(h->aws + P.off_t0);
     h->adj_seg_len = seg_len;
     launch_fill_zero(h->aws, P.total, h->stream);
     s = check_launch(h, "adjoint zero fill");
@@ -1310,16 +1366,17 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
                                     hipMemcpyHostToDevice, h->stream));
         col += (size_t)c.n;
     }
-    // reverse sweep over the segment
-    for (int64_t t = t0 + n_steps - 1; t >= t0; --t) {
-        launch_adj_a(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
-                     h->d_achans, t, h->stream);
-        launch_adj_b(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
-                     h->d_achans, t, (int)(t - t0), h->stream);
-        s = check_launch(h, "adjoint step");
-        if (s != LB_OK)
-            return s;
-    }
+    // reverse sweep over the segment: one captured graph per segment length,
+    // the segment's first step passed in device memory
+    launch_store_i64(h->d_adj_t0, t0, h->stream);
+    s = check_launch(h, "adjoint segment start");
+    if (s != LB_OK)
+        return s;
+    hipGraphExec_t exec = nullptr;
+    s = adj_sweep_graph(h, n_steps, &exec);
+    if (s != LB_OK)
+        return s;
+    HIP_TRY(h, hipGraphLaunch(exec, h->stream));
     // the host buffer may be reused once this returns
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->adj_next = t0;
@@ -1354,6 +1411,7 @@ lb_status lb_destroy(lb_handle *h)
         (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph)
         (void)hipGraphDestroy(h->graph);
+    drop_adj_graphs(h);
     if (h->cap_stream)
         (void)hipStreamDestroy(h->cap_stream);
     for (int w = 0; w < 3; ++w)

@@ -150,3 +150,29 @@ def test_lbfunction_autograd(lb):
     rel = np.abs(g_auto - fd) / np.abs(fd)
     say(f"  rel {rel}")
     assert np.all(rel < 1e-5)
+
+
+def test_repeated_sweeps_on_one_handle(lb):
+    """The reverse sweep of a segment length is captured once and replayed for
+    every segment and every later sweep on the handle; a new segment length
+    (a new adjoint workspace layout) drops the captured sweeps.  Three
+    gradients on one handle, from the same initial state: the first two with
+    the same segment length, the third with another, all bitwise equal."""
+    import torch
+    from paper_1504_06123_amd import adjoint
+    ch = small_channel()
+    steps, every = 200, 20
+    target = torch.from_numpy(oracle_samples(ch.replace(gx=1.5e-5), steps, every))
+    say("case adjoint repeated sweeps on one handle")
+    grads = []
+    with lb.Solver([ch], precision="f64") as s:
+        init = s.save_state()
+        for seg in (50, 50, 23):
+            theta = torch.tensor([[ch.g_inf, ch.tau_m, ch.gamma_c, ch.gx]], dtype=torch.float64,
+                                 requires_grad=True)
+            u = adjoint.LBFunction.apply(theta, s, init, steps, every, seg)
+            ((u - target) ** 2).sum().backward()
+            grads.append(theta.grad.numpy()[0].copy())
+    say(f"  grads {grads}")
+    assert np.array_equal(grads[0], grads[1])
+    assert np.array_equal(grads[0], grads[2])
