@@ -49,17 +49,17 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernel
 # (precision, steps per pass, nodes per lane).  Valid only for the kernel source they
 # were taken from; otherwise reported as null.
 MEASURED = {
-    "source_sha256": "91803b3572c0c1201bb82b8d16f121d3945f42ae91484bab9ffaabedaf007e9e",
+    "source_sha256": "0d081fd0a8b6b68f10d0b545f87ace8fda6c0a9f63f3253ffa4e7cf3336c2b9c",
     # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated)
-    "traffic_bytes": {("f32p64", 32, 1): 8396179.0 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32p64", 1, 4): 8410395.0 * 1024 * 2 + 52509.82 * 1024},
+    "traffic_bytes": {("f32p64", 32, 1): 8395719.66 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32p64", 1, 4): 8408587.53 * 1024 * 2 + 48217.81 * 1024},
     # SQ_INSTS_VALU x 64 / history entries
-    "valu_instr_per_entry": {("f32p64", 32, 1): 95.64, ("f32p64", 1, 4): 10.54},
+    "valu_instr_per_entry": {("f32p64", 32, 1): 91.89, ("f32p64", 1, 4): 9.97},
     # the side legs' dominant kernels (profiles/history_variants_large_2d_1024x512.md),
     # keyed by (leg, steps per pass), same calibration
-    "leg_traffic_bytes": {("grid", 16): 1606550.0 * 1024 * 2 + 211968.0 * 1024,
-                          ("full_tensor", 16): 33557310.0 * 1024 * 2 + 213072.0 * 1024,
-                          ("strain_damping", 32): 8395687.0 * 1024 * 2 + 266240.0 * 1024},
+    "leg_traffic_bytes": {("grid", 16): 1606553.1 * 1024 * 2 + 211968.0 * 1024,
+                          ("full_tensor", 16): 33557411.66 * 1024 * 2 + 213072.0 * 1024,
+                          ("strain_damping", 32): 8395734.75 * 1024 * 2 + 266240.0 * 1024},
 }
 
 
@@ -162,11 +162,11 @@ def bench_large_2d(wl, args, precision: str):
     vpe = measured("valu_instr_per_entry", key)
     vpe_src = "rocprofv3 SQ_INSTS_VALU" if vpe else "model"
     if not vpe:
-        # Instruction model.  M >= 16: one FMA per sum and step plus the eight
-        # low and M/8 high powers and the per-entry decay, strain and flush
-        # work (the counted 32-step pass has 97).  Shorter blocks carry the
-        # decay factor along the steps: three instructions per step.
-        vpe = 2.25 * M + 24 if M >= 16 else 3.5 * M + 10
+        # Instruction model.  M >= 16: one FMA (or add) per sum and step plus
+        # the seven low and 2 M/8 high powers and the per-entry decay, strain
+        # and flush work (the counted 32-step pass has 92).  Shorter blocks
+        # carry the decay factor along the steps: three instructions per step.
+        vpe = 2.25 * M + 20 if M >= 16 else 3.5 * M + 10
     # Cycles each SIMD spends per wave-level VALU instruction; 4 is the
     # nominal wave64 issue interval (dependence-free FP32 chains measure 4.1).
     wave_instr = vpe * entries / 64
