@@ -767,6 +767,10 @@ void drop_adj_graphs(lb_handle *h)
 
 // The reverse sweep of n_steps steps (k_adj_a then k_adj_b for slots
 // n_steps-1 .. 0), captured once per length and replayed for every segment.
+// The graph holds the workspace, channel-table and node-tile pointers and the
+// node-tile count (fixed for the handle's life: node tiles depend on the
+// channels only) and the adjoint workspace (lb_adjoint_begin drops the
+// graphs when it changes).
 lb_status adj_sweep_graph(lb_handle *h, int n_steps, hipGraphExec_t *out)
 {
     for (auto &e : h->adj_execs)
