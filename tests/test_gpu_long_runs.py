@@ -159,6 +159,20 @@ def test_batched_all_channels_1000_steps(lb, precision):
         check(got[c], gold, c, f"batched ch{c} ly={wl.channels[c].ly}", precision)
 
 
+@pytest.mark.parametrize("persistent", [True, False])
+def test_batched_all_channels_in_the_tuned_launch(lb, persistent):
+    """The launch the benchmark's tuner keeps for the batched workload:
+    32-step passes over 512-entry age chunks (up to 64 chunks per channel,
+    combined in FP64), 64-step graphs, persistent pass or not; FP32."""
+    gold = load("batched_all_1000")
+    wl = workloads.batched()
+    launch = dict(block=32, vec=1, chunk_len=512, persistent=persistent, graph=64)
+    say(f"case batched 64 channels, 1000 steps, f32, {launch}")
+    got = run(lb, wl, launch, 1000, 250, precision="f32")
+    for c in range(len(wl.channels)):
+        check(got[c], gold, c, f"batched ch{c} ly={wl.channels[c].ly}", "f32")
+
+
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_large_2d_full_size_first_steps_in_the_bench_launch(lb, precision):
     """The benchmark's own workload -- the perturbed 1024 x 512 channel with
