@@ -49,17 +49,17 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernel
 # (precision, steps per pass, nodes per lane).  Valid only for the kernel source they
 # were taken from; otherwise reported as null.
 MEASURED = {
-    "source_sha256": "0d081fd0a8b6b68f10d0b545f87ace8fda6c0a9f63f3253ffa4e7cf3336c2b9c",
+    "source_sha256": "641b86dcebac45ed70677f29303c57292cca252411207868b932b09850116558",
     # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated)
-    "traffic_bytes": {("f32p64", 32, 1): 8395719.66 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32p64", 1, 4): 8408587.53 * 1024 * 2 + 48217.81 * 1024},
+    "traffic_bytes": {("f32p64", 32, 1): 8395878.86 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32p64", 1, 4): 8408529.74 * 1024 * 2 + 48238.28 * 1024},
     # SQ_INSTS_VALU x 64 / history entries
-    "valu_instr_per_entry": {("f32p64", 32, 1): 91.89, ("f32p64", 1, 4): 9.97},
+    "valu_instr_per_entry": {("f32p64", 32, 1): 91.18, ("f32p64", 1, 4): 9.97},
     # the side legs' dominant kernels (profiles/history_variants_large_2d_1024x512.md),
     # keyed by (leg, steps per pass), same calibration
-    "leg_traffic_bytes": {("grid", 16): 1606553.1 * 1024 * 2 + 211968.0 * 1024,
-                          ("full_tensor", 16): 33557411.66 * 1024 * 2 + 213072.0 * 1024,
-                          ("strain_damping", 32): 8395734.75 * 1024 * 2 + 266240.0 * 1024},
+    "leg_traffic_bytes": {("grid", 16): 1606553.36 * 1024 * 2 + 211968.0 * 1024,
+                          ("full_tensor", 16): 33557518.98 * 1024 * 2 + 213072.0 * 1024,
+                          ("strain_damping", 32): 8395712.95 * 1024 * 2 + 266240.0 * 1024},
 }
 
 
@@ -164,9 +164,9 @@ def bench_large_2d(wl, args, precision: str):
     if not vpe:
         # Instruction model.  M >= 16: one FMA (or add) per sum and step plus
         # the seven low and 2 M/8 high powers and the per-entry decay, strain
-        # and flush work (the counted 32-step pass has 92).  Shorter blocks
+        # and flush work (the counted 32-step pass has 91).  Shorter blocks
         # carry the decay factor along the steps: three instructions per step.
-        vpe = 2.25 * M + 20 if M >= 16 else 3.5 * M + 10
+        vpe = 2.25 * M + 19 if M >= 16 else 3.5 * M + 10
     # Cycles each SIMD spends per wave-level VALU instruction; 4 is the
     # nominal wave64 issue interval (dependence-free FP32 chains measure 4.1).
     wave_instr = vpe * entries / 64

@@ -2287,7 +2287,7 @@ void launch_lb(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, 
         } else if (block == 16) {                                                \
             X(1, 16, 8, 32);                                                     \
         } else {                                                                 \
-            X(1, 32, 8, 64);                                                       \
+            X(1, 32, 8, 128);                                                      \
         }                                                                        \
     } while (0)
 
