@@ -176,3 +176,25 @@ def test_repeated_sweeps_on_one_handle(lb):
     say(f"  grads {grads}")
     assert np.array_equal(grads[0], grads[1])
     assert np.array_equal(grads[0], grads[2])
+
+
+def test_channels_in_one_handle_match_single_channel_sweeps(lb):
+    """Channels of one handle are independent: the gradient of a loss summed
+    over two channels of different widths and parameters, swept together,
+    equals each channel's gradient swept alone, bit for bit (same arithmetic
+    in the same order per node, node-ordered reduction per channel)."""
+    from paper_1504_06123_amd import adjoint
+    c0 = small_channel()
+    c1 = workloads.Channel(lx=1, ly=23, tau_lb=0.9, g_inf=1e-3, tau_m=25.0, gamma_c=0.08,
+                           n_hist=48, gx=1.2e-5)
+    steps, every, seg = 200, 20, 40
+    say("case adjoint two channels in one handle")
+    targets = [oracle_samples(c.replace(gx=0.8 * c.gx), steps, every) for c in (c0, c1)]
+    with lb.Solver([c0, c1], precision="f64") as s:
+        u, ckpts = adjoint.forward(s, steps, every, seg)
+        g_both = adjoint.backward(s, ckpts, steps, every, seg,
+                                  2 * (u - np.concatenate(targets, axis=1)))
+    for i, c in enumerate((c0, c1)):
+        _, g_one = gpu_gradient(lb, c, "f64", steps, every, seg, targets[i])
+        say(f"  ch{i} together {g_both[i]}\n       alone    {g_one}")
+        assert np.array_equal(g_both[i], g_one)
