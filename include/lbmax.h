@@ -348,10 +348,11 @@ lb_status lb_set_params(lb_handle *h, int32_t ch, double g_inf, double tau_m,
  *       dL/dgamma_c, dL/dg_x, summed over the covered steps.
  * Accumulation is per node in FP64 and reduced in node order (bitwise
  * reproducible).  Arithmetic of the transposes: the handle's precision, with
- * the history gather in FP64.  The reverse sweep of a segment is captured
- * once per segment length as a HIP graph and replayed for later segments and
- * sweeps with the same adjoint workspace and seg_len (lb_adjoint_begin with
- * another buffer or seg_len drops the graphs; lb_destroy frees them).
+ * the history gather in FP64.  The reverse sweep of a segment of up to 1024
+ * steps is captured once per segment length as a HIP graph and replayed for
+ * later segments and sweeps with the same adjoint workspace and seg_len
+ * (lb_adjoint_begin with another buffer or seg_len drops the graphs;
+ * lb_destroy frees them); longer segments launch their kernels directly.
  */
 size_t lb_adjoint_workspace_bytes(const lb_handle *h, int32_t seg_len);
 lb_status lb_adjoint_begin(lb_handle *h, void *d_aws, size_t bytes, int32_t seg_len);

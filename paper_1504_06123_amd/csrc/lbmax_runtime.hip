@@ -758,6 +758,9 @@ std::string adjoint_unsupported(const lb_handle *h, int seg_len)
     return "";
 }
 
+// Segments up to this length replay a captured reverse sweep.
+constexpr int kAdjGraphMaxSteps = 1024;
+
 void drop_adj_graphs(lb_handle *h)
 {
     for (auto &e : h->adj_execs)
@@ -1376,11 +1379,25 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
     s = check_launch(h, "adjoint segment start");
     if (s != LB_OK)
         return s;
-    hipGraphExec_t exec = nullptr;
-    s = adj_sweep_graph(h, n_steps, &exec);
-    if (s != LB_OK)
-        return s;
-    HIP_TRY(h, hipGraphLaunch(exec, h->stream));
+    if (n_steps <= kAdjGraphMaxSteps) {
+        hipGraphExec_t exec = nullptr;
+        s = adj_sweep_graph(h, n_steps, &exec);
+        if (s != LB_OK)
+            return s;
+        HIP_TRY(h, hipGraphLaunch(exec, h->stream));
+    } else {
+        // longer segments launch directly (a graph of 2 n_steps nodes would
+        // cost more to build than it saves)
+        for (int k = n_steps - 1; k >= 0; --k) {
+            launch_adj_a(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
+                         h->d_achans, h->d_adj_t0, k, h->stream);
+            launch_adj_b(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
+                         h->d_achans, h->d_adj_t0, k, h->stream);
+            s = check_launch(h, "adjoint step");
+            if (s != LB_OK)
+                return s;
+        }
+    }
     // the host buffer may be reused once this returns
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->adj_next = t0;

@@ -198,3 +198,17 @@ def test_channels_in_one_handle_match_single_channel_sweeps(lb):
         _, g_one = gpu_gradient(lb, c, "f64", steps, every, seg, targets[i])
         say(f"  ch{i} together {g_both[i]}\n       alone    {g_one}")
         assert np.array_equal(g_both[i], g_one)
+
+
+def test_long_segments_launch_directly(lb):
+    """Segments longer than 1024 steps sweep with direct launches instead of a
+    captured graph; the gradient is the same, bit for bit, as with short
+    segments (the sweep's arithmetic does not depend on the segment length)."""
+    ch = small_channel().replace(n_hist=1200, tau_m=300.0)
+    steps, every = 1300, 100
+    say("case adjoint segments of 1100 steps (direct) and 100 (graphs)")
+    target = oracle_samples(ch.replace(gx=1.5e-5), steps, every)
+    _, g_long = gpu_gradient(lb, ch, "f64", steps, every, 1100, target)
+    _, g_short = gpu_gradient(lb, ch, "f64", steps, every, 100, target)
+    say(f"  long {g_long}\n  short {g_short}")
+    assert np.array_equal(g_long, g_short)
