@@ -167,8 +167,10 @@ def bench_large_2d(wl, args, precision: str):
         # and flush work (the counted 32-step pass has 91).  Shorter blocks
         # carry the decay factor along the steps: three instructions per step.
         vpe = 2.25 * M + 19 if M >= 16 else 3.5 * M + 10
-    # Cycles each SIMD spends per wave-level VALU instruction; 4 is the
-    # nominal wave64 issue interval (dependence-free FP32 chains measure 4.1).
+    # Cycles each SIMD spends per wave-level VALU instruction, counted at the
+    # nominal 2.4 GHz engine clock; 4 is the wave64 issue interval.  Under
+    # this load the engine runs below 2.4 GHz (rocprofv3 GRBM_GUI_ACTIVE
+    # counts 3.9 to 4.0 real cycles per instruction for the 32-step pass).
     wave_instr = vpe * entries / 64
     cycles_per_instr = 1024 * 2.4e9 * pass_s / wave_instr
     valu_bound = wave_instr / VALU_WAVE_INSTR_PER_S > alg_bytes / (HBM_PEAK_GBS * 1e9)
@@ -184,7 +186,7 @@ def bench_large_2d(wl, args, precision: str):
                  "alg_flops_per_launch": alg_flops, "hbm_GBs": gbs, "hbm_frac": hbm_frac,
                  "valu_TFLOPs": tflops, "valu_frac": alu_frac,
                  "valu_instr_per_entry": vpe, "valu_instr_source": vpe_src,
-                 "valu_cycles_per_instr": cycles_per_instr})
+                 "valu_cycles_per_instr_at_2p4ghz": cycles_per_instr})
     return {"el": el, "steps": steps, "cfg": cfg, "roof": roof,
             "node_steps_per_s": nodes * steps / el, "ms_per_step": el / steps * 1e3}
 
