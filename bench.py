@@ -37,7 +37,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-# FP32 vector arithmetic without packed instructions (the build disables
+# FP32 vector arithmetic without packed instructions (the library is built without
 # them): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # wave64 VALU instruction issue: 1024 SIMDs, 4 cycles per instruction
@@ -516,8 +516,9 @@ def main():
                     help="first copy this many MiB device-to-device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is a design note only)"}))
+        print(json.dumps({"error": "liblbmax runs on one GPU per process and bench.py "
+                                   "measures one GPU; --gpus must be 1 (sharding across "
+                                   "GPUs is described, not implemented)"}))
         sys.exit(2)
 
     import numpy as np
