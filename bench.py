@@ -123,6 +123,25 @@ def bench_large_2d(wl, args, precision: str):
     log(f"bench: {wl.name} nodes={nodes} N_h={H} precision={precision}")
     s = Solver(wl.channels, precision=precision, device="cuda:0")
     s.step(args.warmup)
+    # The pass in the default launch shape, one window reduction per step (no
+    # temporal blocking): the HBM-bound form of the history kernel, timed with
+    # HIP events over 8 steps (its time includes the chunk combine).
+    one_step = None
+    if s.block == 1:
+        s.profile(True)
+        s.step(8)
+        ms1, n1 = s.kernel_time(0)
+        s.profile(False)
+        vec1 = s.tiling(0)[1]
+        one_s = ms1 / n1 / 1e3
+        gbs1 = ch.nodes * ch.n_hist * hist_bytes_per_entry(ch) / one_s / 1e9
+        one_step = {"bound": "hbm", "achieved": gbs1, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs1 / HBM_PEAK_GBS,
+                    "traffic": measured("traffic_bytes", (precision, 1, vec1)),
+                    "kernel": f"k_hist_pass (one step per pass, {vec1} nodes per lane, "
+                              f"{s.tiling(0)[0]} age chunks; with the chunk combine)",
+                    "kernel_avg_ms": one_s * 1e3}
+        log(f"bench: {precision}: one-step pass {one_s*1e3:.3f} ms ({gbs1:.0f} GB/s)")
     if args.no_tune:
         cfg = dict(block=args.block, vec=1, chunk_len=1 << 30, persistent=args.persistent,
                    graph=args.graph)
@@ -187,7 +206,7 @@ def bench_large_2d(wl, args, precision: str):
                  "valu_TFLOPs": tflops, "valu_frac": alu_frac,
                  "valu_instr_per_entry": vpe, "valu_instr_source": vpe_src,
                  "valu_cycles_per_instr_at_2p4ghz": cycles_per_instr})
-    return {"el": el, "steps": steps, "cfg": cfg, "roof": roof,
+    return {"el": el, "steps": steps, "cfg": cfg, "roof": roof, "one_step": one_step,
             "node_steps_per_s": nodes * steps / el, "ms_per_step": el / steps * 1e3}
 
 
@@ -601,6 +620,9 @@ def main():
                    "history_entries_per_step": entries, "launch": cfg,
                    "precision": "f32p64"},
         "roofline": roof,
+        # the same history kernel run once per step (the shape the blocked
+        # pass replaces): HBM-bound
+        "history_pass_one_step": main["one_step"],
         "entry_updates_per_s": entries * steps / el,
         "all_f32": side and {"value": side["node_steps_per_s"],
                              "ms_per_step": side["ms_per_step"],
