@@ -49,17 +49,17 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernel
 # (precision, steps per pass, nodes per lane).  Valid only for the kernel source they
 # were taken from; otherwise reported as null.
 MEASURED = {
-    "source_sha256": "641b86dcebac45ed70677f29303c57292cca252411207868b932b09850116558",
+    "source_sha256": "bc7b26aa43a2973142e1595c4b0472abd3185e25590a9f340472f76340eb26b4",
     # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated)
-    "traffic_bytes": {("f32p64", 32, 1): 8395878.86 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32p64", 1, 4): 8408529.74 * 1024 * 2 + 48238.28 * 1024},
+    "traffic_bytes": {("f32p64", 32, 1): 8396190.39 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32p64", 1, 4): 8408567.93 * 1024 * 2 + 48194.03 * 1024},
     # SQ_INSTS_VALU x 64 / history entries
     "valu_instr_per_entry": {("f32p64", 32, 1): 91.18, ("f32p64", 1, 4): 9.97},
     # the side legs' dominant kernels (profiles/history_variants_large_2d_1024x512.md),
     # keyed by (leg, steps per pass), same calibration
-    "leg_traffic_bytes": {("grid", 16): 1606553.36 * 1024 * 2 + 211968.0 * 1024,
-                          ("full_tensor", 16): 33557518.98 * 1024 * 2 + 213072.0 * 1024,
-                          ("strain_damping", 32): 8395712.95 * 1024 * 2 + 266240.0 * 1024},
+    "leg_traffic_bytes": {("grid", 16): 1606550.61 * 1024 * 2 + 211968.0 * 1024,
+                          ("full_tensor", 16): 33557757.05 * 1024 * 2 + 213072.0 * 1024,
+                          ("strain_damping", 32): 8395696.69 * 1024 * 2 + 266240.0 * 1024},
 }
 
 

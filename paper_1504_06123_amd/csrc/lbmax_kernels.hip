@@ -2348,7 +2348,7 @@ int hist_pass_blocks_per_cu(int prec, int vec, int block)
         else if (block == 8)                                                     \
             X(8, 4, 16);                                                         \
         else                                                                     \
-            X(16, 2, 16);                                                        \
+            X(16, 4, 16);                                                        \
     } while (0)
 
 void launch_finger_pass(int prec, int block, char *ws, const ChanDev *chans,
