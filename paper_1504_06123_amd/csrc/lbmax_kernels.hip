@@ -1333,11 +1333,32 @@ __device__ __forceinline__ void wm_tile(char *__restrict__ ws, const ChanDev *c,
     };
     const int kb = max(1, H - M);  // ages [1, kb) stay inside with weight 1
     int slot = p;
-    // bulk ages: one sum, FP32 partials of 32 rows flushed into FP64
+    // bulk ages: one sum, FP32 partials of 32 rows flushed into FP64; rows
+    // are loaded 8 at a time before any is used (same order of operations)
     int k = 1;
     while (k < kb) {
         const int kend = min(kb, k + 32);
         R pa = R(0), pb = R(0);
+        for (; k + 8 <= kend; k += 8) {
+            R sv[8], rv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                slot = slot == 0 ? H - 1 : slot - 1;
+                const size_t row = (size_t)slot * np + node;
+                sv[u] = ring_s[row];
+                rv[u] = has_r ? ring_r[row] : R(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const R s = sv[u];
+                const R r = has_r ? rv[u] : fabs(s);
+                loc += (double)s;
+                racc += (double)r;
+                const R x = s * wm_damping<R>(dec, R(k + u), racc);
+                pa = pa + x;
+                pb = fused(x, R(2) * (R)loc, pb);
+            }
+        }
         for (; k < kend; ++k) {
             slot = slot == 0 ? H - 1 : slot - 1;
             const size_t row = (size_t)slot * np + node;
