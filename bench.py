@@ -49,17 +49,17 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernel
 # (precision, steps per pass, nodes per lane).  Valid only for the kernel source they
 # were taken from; otherwise reported as null.
 MEASURED = {
-    "source_sha256": "bc7b26aa43a2973142e1595c4b0472abd3185e25590a9f340472f76340eb26b4",
+    "source_sha256": "e7642656a2cfa6ac4aebc4ea655a2c221a31248cd42db30c119d01b49181370b",
     # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated)
-    "traffic_bytes": {("f32p64", 32, 1): 8396190.39 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32p64", 1, 4): 8408567.93 * 1024 * 2 + 48194.03 * 1024},
+    "traffic_bytes": {("f32p64", 32, 1): 8396150.41 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32p64", 1, 4): 8408579.65 * 1024 * 2 + 48205.17 * 1024},
     # SQ_INSTS_VALU x 64 / history entries
     "valu_instr_per_entry": {("f32p64", 32, 1): 91.18, ("f32p64", 1, 4): 9.97},
     # the side legs' dominant kernels (profiles/history_variants_large_2d_1024x512.md),
     # keyed by (leg, steps per pass), same calibration
-    "leg_traffic_bytes": {("grid", 16): 1606550.61 * 1024 * 2 + 211968.0 * 1024,
-                          ("full_tensor", 16): 33557757.05 * 1024 * 2 + 213072.0 * 1024,
-                          ("strain_damping", 32): 8395696.69 * 1024 * 2 + 266240.0 * 1024},
+    "leg_traffic_bytes": {("grid", 16): 1606547.78 * 1024 * 2 + 211968.0 * 1024,
+                          ("full_tensor", 16): 33557914.0 * 1024 * 2 + 213072.0 * 1024,
+                          ("strain_damping", 32): 8395975.89 * 1024 * 2 + 266240.0 * 1024},
 }
 
 

@@ -1436,17 +1436,35 @@ __device__ __forceinline__ void wm_step(char *__restrict__ ws, const ChanDev *c,
     const Decay<R> dec(c);
     double sxy = 0.5 * (double)s_new, sxx = 0.0, gam = 0.0, racc = 0.0;
     int slot = p;
-    for (int a = 1; a <= m; ++a) {
-        slot = slot == 0 ? H - 1 : slot - 1;
-        const R s = ring_s[(size_t)slot * np + n];
-        const R r = has_r ? ring_r[(size_t)slot * np + n] : fabs(s);
-        gam += (double)s;
-        racc += (double)r;
-        if (a < m && a <= H - 1) {
-            const double w = (a == H - 1) ? 0.5 : 1.0;
-            const double se = w * (double)(s * wm_damping<R>(dec, R(a), racc));
-            sxy += se;
-            sxx += 2.0 * gam * se;
+    // the m rows pushed since the pass, newest first, loaded 8 at a time
+    // before any is used (same order of operations)
+    for (int a0 = 1; a0 <= m; a0 += 8) {
+        R sv[8], rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sv[u] = rv[u] = R(0);
+            if (a0 + u <= m) {
+                slot = slot == 0 ? H - 1 : slot - 1;
+                sv[u] = ring_s[(size_t)slot * np + n];
+                if (has_r)
+                    rv[u] = ring_r[(size_t)slot * np + n];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int a = a0 + u;
+            if (a > m)
+                break;
+            const R s = sv[u];
+            const R r = has_r ? rv[u] : fabs(s);
+            gam += (double)s;
+            racc += (double)r;
+            if (a < m && a <= H - 1) {
+                const double w = (a == H - 1) ? 0.5 : 1.0;
+                const double se = w * (double)(s * wm_damping<R>(dec, R(a), racc));
+                sxy += se;
+                sxx += 2.0 * gam * se;
+            }
         }
     }
     // the pass's sums carried to this step: factor c_m
