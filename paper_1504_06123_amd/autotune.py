@@ -61,10 +61,12 @@ def time_config(solver, cfg: Dict, steps: int) -> float:
 
 
 def tune(solver, cands: Optional[List[Dict]] = None, min_steps: int = 32,
-         time_budget_s: float = 60.0, verbose: bool = False) -> Dict:
-    """Try the candidates on the solver's current state, restore the state,
-    apply and return the fastest configuration (with its ms/step and the
-    table of all timings)."""
+         time_budget_s: float = 60.0, verbose: bool = False, refine_top: int = 3) -> Dict:
+    """Try the candidates on the solver's current state, re-time the
+    `refine_top` fastest over four times as many steps (short trials are
+    noisy at the few-percent level that separates the best shapes), restore
+    the state, apply and return the fastest configuration (with its ms/step
+    and the table of all timings)."""
     cands = candidates(solver) if cands is None else cands
     solver.set_graph(0)
     solver.set_block(1)             # save at a block boundary
@@ -80,7 +82,19 @@ def tune(solver, cands: Optional[List[Dict]] = None, min_steps: int = 32,
             print(f"tune: {cfg} -> {ms:.4f} ms/step", flush=True)
         if time.perf_counter() - t_start > time_budget_s:
             break
-    best = min(results, key=lambda r: r["ms_per_step"])
+    if refine_top > 1:
+        for r in sorted(results, key=lambda r: r["ms_per_step"])[:refine_top]:
+            cfg = {k: r[k] for k in ("block", "vec", "chunk_len", "persistent", "graph")}
+            steps = 4 * max(min_steps, 2 * cfg["block"], cfg["graph"] or 0)
+            steps = int(math.ceil(steps / cfg["block"]) * cfg["block"])
+            r["ms_per_step_refined"] = time_config(solver, cfg, steps)
+            if verbose:
+                print(f"tune: refine {cfg} -> {r['ms_per_step_refined']:.4f} ms/step", flush=True)
+        refined = [r for r in results if "ms_per_step_refined" in r]
+        best = min(refined, key=lambda r: r["ms_per_step_refined"])
+        best = dict(best, ms_per_step=best["ms_per_step_refined"])
+    else:
+        best = min(results, key=lambda r: r["ms_per_step"])
     solver.set_graph(0)
     solver.set_block(1)
     solver.load_state(saved)
