@@ -382,6 +382,32 @@ def test_large_2d_full_size_first_steps(Solver):
         assert v <= TOL32[k], (k, v)
 
 
+@pytest.mark.parametrize("block", [1, 32])
+def test_fp32_longest_window(Solver, block):
+    """The longest window FP32 histories take, 2^24 entries (ages stay exact
+    in FP32), on a 1 x 32 channel (a 4 GiB ring split into 64 age chunks):
+    the zero-filled ring makes its first 40 steps equal to the oracle's with
+    a 64-entry window, unblocked and with 32 steps per pass."""
+    ch = workloads.startup_cessation().channels[0].replace(ly=32, n_hist=1 << 24,
+                                                            tau_m=200.0, gx=2e-5)
+    steps = 40
+    say(f"case longest FP32 window 2^24, 1 x 32, {steps} steps, block {block}")
+    with Solver([ch], precision="f32p64") as s:
+        assert s.max_chunks(0) == 64
+        s.set_block(block)
+        s.step(steps)
+        _, ux, _ = s.fields(0)
+        sxy, n1 = s.stress(0)
+    oc = oracle.OracleChannel(ch.replace(n_hist=64))
+    oc.step(steps)
+    _, rux, _ = oc.fields()
+    rsxy, rn1 = oc.stress()
+    errs = dict(ux=nerr(ux, rux), sxy=nerr(sxy, rsxy), n1=nerr(n1, rn1))
+    say(f"  errors {errs}")
+    for k, v in errs.items():
+        assert v <= TOL32[k], (k, v)
+
+
 def test_large_2d_full_size_synthetic_window(Solver):
     """Full-size ring with seeded random history at an arbitrary step (the
     window wraps): sigma at sampled nodes against the oracle's history sum
