@@ -204,6 +204,11 @@ def bench_large_2d(wl, args, precision: str):
                  "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg_bytes,
                  "alg_flops_per_launch": alg_flops, "hbm_GBs": gbs, "hbm_frac": hbm_frac,
                  "valu_TFLOPs": tflops, "valu_frac": alu_frac,
+                 # the packed-FP32 figure (two FP32 FMAs per lane and cycle), for
+                 # reference: the library is compiled without packed FP32
+                 # instructions, so the non-packed peak above is its ceiling
+                 "peak_packed_fp32_TFLOPs": 2 * VALU_PEAK_TFLOPS,
+                 "frac_of_packed_peak": tflops / (2 * VALU_PEAK_TFLOPS),
                  "valu_instr_per_entry": vpe, "valu_instr_source": vpe_src,
                  "valu_cycles_per_instr_at_2p4ghz": cycles_per_instr})
     return {"el": el, "steps": steps, "cfg": cfg, "roof": roof, "one_step": one_step,
