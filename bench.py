@@ -49,17 +49,17 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernel
 # (precision, steps per pass, nodes per lane).  Valid only for the kernel source they
 # were taken from; otherwise reported as null.
 MEASURED = {
-    "source_sha256": "e7642656a2cfa6ac4aebc4ea655a2c221a31248cd42db30c119d01b49181370b",
+    "source_sha256": "141082364c903bfa3c234e05852445f63ad9f1781a6fa5411450d378d1e3caf6",
     # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated)
-    "traffic_bytes": {("f32p64", 32, 1): 8396150.41 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32p64", 1, 4): 8408579.65 * 1024 * 2 + 48205.17 * 1024},
+    "traffic_bytes": {("f32p64", 32, 1): 8396634.33 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32p64", 1, 4): 8410779.95 * 1024 * 2 + 40928.69 * 1024},
     # SQ_INSTS_VALU x 64 / history entries
-    "valu_instr_per_entry": {("f32p64", 32, 1): 91.18, ("f32p64", 1, 4): 9.97},
+    "valu_instr_per_entry": {("f32p64", 32, 1): 88.38, ("f32p64", 1, 4): 9.97},
     # the side legs' dominant kernels (profiles/history_variants_large_2d_1024x512.md),
     # keyed by (leg, steps per pass), same calibration
-    "leg_traffic_bytes": {("grid", 16): 1606547.78 * 1024 * 2 + 211968.0 * 1024,
-                          ("full_tensor", 16): 33557914.0 * 1024 * 2 + 213072.0 * 1024,
-                          ("strain_damping", 32): 8395975.89 * 1024 * 2 + 266240.0 * 1024},
+    "leg_traffic_bytes": {("grid", 16): 1606549.86 * 1024 * 2 + 211968.0 * 1024,
+                          ("full_tensor", 16): 33557797.84 * 1024 * 2 + 213072.0 * 1024,
+                          ("strain_damping", 32): 8395958.26 * 1024 * 2 + 266240.0 * 1024},
 }
 
 
@@ -183,9 +183,9 @@ def bench_large_2d(wl, args, precision: str):
     if not vpe:
         # Instruction model.  M >= 16: one FMA (or add) per sum and step plus
         # the seven low and 2 M/8 high powers and the per-entry decay, strain
-        # and flush work (the counted 32-step pass has 91).  Shorter blocks
+        # and flush work (the counted 32-step pass has 88).  Shorter blocks
         # carry the decay factor along the steps: three instructions per step.
-        vpe = 2.25 * M + 19 if M >= 16 else 3.5 * M + 10
+        vpe = 2.25 * M + 16 if M >= 16 else 3.5 * M + 10
     # Cycles each SIMD spends per wave-level VALU instruction, counted at the
     # nominal 2.4 GHz engine clock; 4 is the wave64 issue interval.  Under
     # this load the engine runs below 2.4 GHz (rocprofv3 GRBM_GUI_ACTIVE

@@ -499,6 +499,31 @@ __device__ __forceinline__ void edge_entry(R s, R r, int k, int H, double loc,
     }
 }
 
+// The same terms for an entry near the far end of the window (some k + m
+// past it), into plain partial sums flushed once after the last such entry:
+// E(k + m) carried as E(k) q^m.
+template <typename R, int M>
+__device__ __forceinline__ void tail_entry(R s, R r, int k, int H, R g, const Decay<R> &dec,
+                                           R (&pa)[M], R (&pb)[M])
+{
+#pragma clang fp contract(off)
+    const R rate = decay_rate<R>(dec, r);
+    const R q = decay_pow(R(1), rate);
+    R e = decay_pow(R(k), rate);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int a = k + m;
+        if (a <= H - 1) {
+            const R w = a == H - 1 ? R(0.5) : R(1);
+            const R se = w * s * e;
+            pa[m] = pa[m] + se;
+            pb[m] = fused(se, g, pb[m]);
+        }
+        if (m + 1 < M)
+            e = e * q;
+    }
+}
+
 // One entry's terms for the M steps of a block: x q^m into pa[m][v] and
 // x q^m g2 into pb[m][v] (g2 the entry's strain factor), m = 0..M-1 (SET: the first entry of a group sets
 // them).  For M >= 16, x q^m = q^{m mod 8} (x q^{8 (m / 8)}): seven low
@@ -721,32 +746,37 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
     const int tail0 = max(k, H - M);
     pass_bulk<R, V, M, U, F, HAS_R>(ring_s, ring_r, np, lane_off, H, p, k, min(tl.k1, tail0),
                                  dec, A, B, loc);
-    for (int kk = max(k, tail0); kk < tl.k1; ++kk) {
-        int slot = p - kk;
-        if (slot < 0)
-            slot += H;
-        const size_t row = (size_t)slot * np;
-        const Pack<R, V> sv = load_pack<R, V>(ring_s + row, lane_off);
-        Pack<R, V> rv;
-        if (HAS_R)
-            rv = load_pack<R, V>(ring_r + row, lane_off);
+    if (max(k, tail0) < tl.k1) {
+        R ta[V][M], tb[V][M];
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const R s = sv.v[v];
-            loc[v] += (double)s;
-            Acc<R> a1[M], b1[M];
+        for (int v = 0; v < V; ++v)
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                a1[m] = A[m][v];
-                b1[m] = B[m][v];
-            }
-            edge_entry<R, M>(s, HAS_R ? rv.v[v] : fabs(s), kk, H, loc[v], dec, a1, b1);
+            for (int m = 0; m < M; ++m)
+                ta[v][m] = tb[v][m] = R(0);
+        for (int kk = max(k, tail0); kk < tl.k1; ++kk) {
+            int slot = p - kk;
+            if (slot < 0)
+                slot += H;
+            const size_t row = (size_t)slot * np;
+            const Pack<R, V> sv = load_pack<R, V>(ring_s + row, lane_off);
+            Pack<R, V> rv;
+            if (HAS_R)
+                rv = load_pack<R, V>(ring_r + row, lane_off);
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                A[m][v] = a1[m];
-                B[m][v] = b1[m];
+            for (int v = 0; v < V; ++v) {
+                const R s = sv.v[v];
+                loc[v] += (double)s;
+                tail_entry<R, M>(s, HAS_R ? rv.v[v] : fabs(s), kk, H, (R)loc[v], dec, ta[v],
+                                 tb[v]);
             }
         }
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                A[m][v].add(ta[v][m]);
+                B[m][v].add(tb[v][m]);
+            }
     }
     if (first >= c->n)
         return;
