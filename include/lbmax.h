@@ -50,23 +50,30 @@ typedef enum {
     LB_ENOMEM = -2,     /* workspace or buffer too small / misaligned        */
     LB_EDEVICE = -3,    /* a HIP call failed; the handle is now poisoned     */
     LB_ESTATE = -4,     /* call not valid in the handle's current state      */
-    LB_ENONFINITE = -5  /* reserved: non-finite values detected              */
+    LB_ENONFINITE = -5  /* a readout returned non-finite values (lb_set_checks) */
 } lb_status;
 
 /*
- * Arithmetic of the whole path.
- *  LB_F64: populations, velocities, history ring and sums in FP64.
- *  LB_F32: populations stored as deviations n_i - a_i in FP32, history ring
- *          in FP32, history sums as FP32 partial sums over groups of rows
- *          added into FP64 accumulators; the accumulated strain (prefix sum
- *          of the shear rate, Sec. III Eq. eeval) and the combination of
- *          partial sums in FP64.
- *  LB_F32_P64: the lattice state (populations as deviations, moments,
- *          stress planes) in FP64, the history ring and its window sums as
- *          in LB_F32.  The ring carries nearly all the bytes, so this costs
- *          little over LB_F32 and removes the drift of FP32 populations over
- *          long runs (a velocity that grows by a small amount per step loses
- *          part of each increment to FP32 rounding, coherently).
+ * Arithmetic of the whole path.  In every mode the stress, velocity and
+ * density planes are FP64, and so are the accumulated strain (prefix sum of
+ * the shear rate, Sec. III Eq. eeval) and the combination of partial sums.
+ *  LB_F64: populations, history ring and history sums in FP64.
+ *  LB_F32: FP32 populations in split storage, FP32 history.  A stored
+ *          post-collision population is the FP32 remainder
+ *          n*_i - n^eq_i(rho, u) against the second-order equilibrium
+ *          (Sec. III) of the moments its collision used, which are kept in
+ *          FP64 (rho - 1, u_x, u_y per node and step parity); a pulled
+ *          population is rebuilt in FP64 from its source node's moments and
+ *          remainder.  The remainder is the forcing term plus
+ *          (1 - 1/tau_LB) times the non-equilibrium part, so FP32 rounding
+ *          acts on that small part only and the conserved moments carry no
+ *          FP32 rounding from step to step (FP32 deviations n_i - a_i drift:
+ *          a velocity that grows by a small amount per step loses part of
+ *          each increment to FP32 rounding, coherently).  History ring in
+ *          FP32; history sums as FP32 partial sums over groups of rows added
+ *          into FP64 accumulators.
+ *  LB_F32_P64: populations as FP64 deviations n_i - a_i, history as in
+ *          LB_F32.
  */
 typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F32_P64 = 2 } lb_precision;
 
@@ -170,12 +177,35 @@ lb_status lb_step(lb_handle *h, int64_t n_steps);
 /* Number of completed steps (host-side counter). */
 int64_t lb_time(const lb_handle *h);
 
-/* Density, velocity u = (j + f/2)/rho of the last completed step.  Any
- * pointer may be NULL.  Synchronises the stream. */
+/*
+ * Failure detection at readouts.  flags (default: both):
+ *   LB_CHECK_FINITE: lb_fields, lb_stress and lb_grad return LB_ENONFINITE
+ *     when a value they return is NaN or infinite (the run has diverged);
+ *     the output arrays are still filled, and the handle stays usable.
+ *   LB_CHECK_MACH: lb_fields raises LB_WARN_MACH when the channel's largest
+ *     speed |u| exceeds 0.1 (lattice Mach number |u| / c_s above 0.17, with
+ *     c_s = 1/sqrt(3) the D2Q9 speed of sound of Sec. III; the BGK scheme
+ *     follows the incompressible equations of Sec. I only at small Mach
+ *     number).  It is a warning: the call still returns LB_OK.
+ * lb_warnings returns the warnings raised since its last call (bitmask) and
+ * clears them; 0 for a NULL handle.
+ */
+enum { LB_CHECK_FINITE = 1, LB_CHECK_MACH = 2 };
+enum { LB_WARN_MACH = 1 };
+lb_status lb_set_checks(lb_handle *h, int32_t flags);
+int32_t lb_warnings(lb_handle *h);
+
+/* Density rho = sum n_i and velocity u = (j + f/2)/rho of the last
+ * completed step (Sec. III Eq. hydrofields; with paper_coupling == 1, rho
+ * includes d_t delta rho / 2).  Any pointer may be NULL.  Synchronises the
+ * stream. */
 lb_status lb_fields(lb_handle *h, int32_t ch, double *rho, double *ux,
                     double *uy);
 
-/* sigma_xy and N1 = sigma_xx - sigma_yy of the last completed step. */
+/* sigma_xy and N1 = sigma_xx - sigma_yy of the last completed step: the
+ * structural stress, the history integral of Eq. gitt with the modulus of
+ * Eq. nlmax (or the law the channel takes), without the Newtonian background
+ * eta_inf D of Eq. nlM; N1 is the first normal-stress difference of Sec. IV. */
 lb_status lb_stress(lb_handle *h, int32_t ch, double *sxy, double *n1);
 
 /* Velocity gradient kappa_ab = d_b u_a (kappa = (grad v)^T, Sec. I) of the
@@ -187,21 +217,22 @@ lb_status lb_grad(lb_handle *h, int32_t ch, double *kappa);
  * State snapshot (checkpoint / resume).  lb_state_bytes gives the size of a
  * device buffer holding the full state; lb_save_state copies the state into
  * it (stream-ordered), lb_load_state restores it.  Layout (all sections
- * 256-byte aligned, R = the lattice type: double for LB_F64 and LB_F32_P64,
- * float for LB_F32; RH = the history type: double for LB_F64, float
+ * 256-byte aligned, R = double; RP = the population storage type: float for
+ * LB_F32, double otherwise; RH = the history type: double for LB_F64, float
  * otherwise):
- *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 5,
+ *   header, 256 bytes: uint64 magic 0x4C424D4158535431, uint32 version = 6,
  *     uint32 precision, int64 t (completed steps), int32 n_ch,
  *     int32 reserved, uint64 total bytes, int32 block length,
  *     int32 block position (steps of the current block already done);
  *   then per channel, in order, N = lx*ly:
- *     pop  [9][N] R  post-collision populations of step t-1 minus the
- *                    weights a_i (before the first step: the initial state
- *                    shifted back by one streaming step).  Direction order
- *                    q = 0..8: (0,0), (1,0), (-1,0), (0,1), (0,-1), (1,1),
- *                    (-1,-1), (1,-1), (-1,1).
+ *     pop  [9][N] RP post-collision populations of step t-1 minus the
+ *                    weights a_i (LB_F32: minus the equilibrium n^eq_i of the
+ *                    vel and drho sections instead); before the first step
+ *                    the initial state shifted back by one streaming step.
+ *                    Direction order q = 0..8: (0,0), (1,0), (-1,0), (0,1),
+ *                    (0,-1), (1,1), (-1,-1), (1,-1), (-1,1).
  *     sig  [3][N] R  sigma_xy, sigma_xx, sigma_yy of step t-1
- *     vel  [2][N] R  u_x, u_y of step t-1
+ *     vel  [2][N] R  u_x, u_y of step t-1 (before the first step: u0)
  *     drho [N]    R  rho - 1 of step t-1
  *     trp  [N]    R  tr sigma^{t-2} (used by the paper coupling; zero else)
  *     ring_s [n_hist][N] RH shear rate s(t') = kappa_xy, row t' mod n_hist
@@ -275,11 +306,11 @@ int32_t lb_get_block(const lb_handle *h);
  * block after its history pass run as one launch: one workgroup per channel
  * advances the lattice and the history of all those steps, with workgroup
  * barriers in place of kernel boundaries.  If moreover the handle is LB_F32
- * and every channel takes the simple-shear integral law (law == 0,
- * finger == 0) with the body-force coupling (paper_coupling == 0), the
- * workgroup keeps the channel's
- * populations, stress and velocity in LDS and the history rows pushed since
- * the pass in registers (the stencils then read no global memory).  mode: 0
+ * and every channel is unidirectional and takes the simple-shear integral law
+ * (law == 0, finger == 0) with the body-force coupling (paper_coupling == 0),
+ * the workgroup keeps the channel's stored populations, moments and stress
+ * in LDS and the history rows pushed since the pass in registers (the
+ * stencils then read no global memory).  mode: 0
  * separate launches, 1 fused (the LDS form where it applies; the default), 2
  * fused without the LDS form.  Results are identical in every mode.
  * lb_get_fused returns 0 when the steps are not fused (mode 0, a channel

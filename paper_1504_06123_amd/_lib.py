@@ -13,6 +13,8 @@ LIB_PATH = os.path.join(HERE, "liblbmax.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_ENONFINITE = 0, -1, -2, -3, -4, -5
 LB_F64, LB_F32, LB_F32_P64 = 0, 1, 2
+LB_CHECK_FINITE, LB_CHECK_MACH = 1, 2
+LB_WARN_MACH = 1
 STATUS_NAMES = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EDEVICE",
                 -4: "LB_ESTATE", -5: "LB_ENONFINITE"}
 
@@ -53,6 +55,8 @@ SIGNATURES = {
     "lb_set_force": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_double, ctypes.c_double]),
     "lb_step": (ctypes.c_int, [_H, ctypes.c_int64]),
     "lb_time": (ctypes.c_int64, [_H]),
+    "lb_set_checks": (ctypes.c_int, [_H, ctypes.c_int32]),
+    "lb_warnings": (ctypes.c_int32, [_H]),
     "lb_fields": (ctypes.c_int, [_H, ctypes.c_int32, _D, _D, _D]),
     "lb_stress": (ctypes.c_int, [_H, ctypes.c_int32, _D, _D]),
     "lb_grad": (ctypes.c_int, [_H, ctypes.c_int32, _D]),

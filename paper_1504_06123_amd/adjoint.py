@@ -72,7 +72,15 @@ def backward(solver, ckpts, steps: int, sample_every: int, seg_len: int, dL_dsam
     nbytes = solver.lib.lb_adjoint_workspace_bytes(solver.h, seg_len)
     if nbytes == 0:
         raise _lib.LBError(_lib.LB_EINVAL, "lb_adjoint_workspace_bytes", _lib.last_error())
-    aws = torch.empty(int(nbytes), dtype=torch.uint8, device=solver.device)
+    # One adjoint workspace per solver and segment length, kept between
+    # sweeps: the library keeps its captured reverse-sweep graphs only while
+    # the workspace address and segment length stay the same.
+    cached = getattr(solver, "_adjoint_ws", None)
+    if cached is not None and cached[0] == seg_len and cached[1].numel() == int(nbytes):
+        aws = cached[1]
+    else:
+        aws = torch.empty(int(nbytes), dtype=torch.uint8, device=solver.device)
+        solver._adjoint_ws = (seg_len, aws)
     _lib.check(solver.lib.lb_adjoint_begin(solver.h, ctypes.c_void_p(aws.data_ptr()),
                                            int(nbytes), seg_len), "lb_adjoint_begin")
     P = ctypes.POINTER(ctypes.c_double)
@@ -88,7 +96,6 @@ def backward(solver, ckpts, steps: int, sample_every: int, seg_len: int, dL_dsam
                    "lb_adjoint_segment")
     out = np.zeros((len(solver.channels), 4))
     _lib.check(solver.lib.lb_adjoint_end(solver.h, out.ctypes.data_as(P)), "lb_adjoint_end")
-    del aws
     return out
 
 

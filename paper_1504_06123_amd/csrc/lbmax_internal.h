@@ -50,7 +50,10 @@ struct alignas(256) ChanDev {
     double inv_tau, inv_gc;         // 1/tau, 1/gamma_c (0 for gamma_c = inf)
     double l2_tau, l2_gc;           // log2(e)/tau, log2(e)/gamma_c
     double gx, gy;                  // body-force acceleration
-    int64_t off_pop;                // [2][9][np] populations minus a_i
+    int64_t off_pop;                // [2][9][np] populations minus a_i (split storage:
+                                    // FP32 remainders n*_i - n^eq_i of the moments below)
+    int64_t off_mom;                // [2][3][np] FP64 rho - 1, u_x, u_y by step parity
+                                    // (split storage only; 0 otherwise)
     int64_t off_sig;                // [3][np]  sigma_xy, sigma_xx, sigma_yy
     int64_t off_vel;                // [2][np]  u_x, u_y
     int64_t off_rho;                // [np]     rho - 1
@@ -85,8 +88,10 @@ struct HistTile {
 };
 
 // Kernel launchers (lbmax_kernels.hip).  All launches go on `st`.  `prec`:
-// 0 = FP64 lattice and history, 1 = FP32 both, 2 = FP64 lattice (populations,
-// moments, stress planes) with FP32 history (ring and window sums).
+// 0 = FP64 lattice and history, 1 = split population storage (FP32 remainders
+// with FP64 moments) with FP32 history, 2 = FP64 lattice (populations,
+// moments, stress planes) with FP32 history (ring and window sums).  Stress,
+// velocity and density planes are FP64 in every mode.
 // `tcount` is the device step counter; a kernel works on step
 // t = *tcount + trel.
 void launch_init(int prec, char *ws, const ChanDev *chans, int ch,

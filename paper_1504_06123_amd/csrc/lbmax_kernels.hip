@@ -45,6 +45,15 @@ __device__ __forceinline__ R qweight(int q)
     return q == 0 ? R(4) / R(9) : (q < 5 ? R(1) / R(9) : R(1) / R(36));
 }
 
+// n^eq_q - a_q = a_q [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)] (Sec. III,
+// cs2 = 1/3), for direction weight w and cu = c_q.u.
+template <typename P>
+__device__ __forceinline__ P eq_dev(P w, P cu, P drho, P uu)
+{
+#pragma clang fp contract(off)
+    return w * (drho + (P(1) + drho) * (P(3) * cu + P(4.5) * cu * cu - P(1.5) * uu));
+}
+
 // ---------------------------------------------------------------------------
 // Window-sum accumulators.  FP32 entries are summed in plain FP32 partial
 // groups that are flushed into an FP64 sum (one conversion and one FP64 add
@@ -120,22 +129,26 @@ __device__ __forceinline__ R shear_rate(R kxx, R kxy, R kyx, R kyy)
 // ---------------------------------------------------------------------------
 // Initialisation: populations n*(-1) such that the first pull-stream yields
 // n(0) = n^eq(1, u0) (the streaming map inverted, bounce-back included), and
-// zero stress / moments.  One channel per launch.
+// zero stress.  The moments of step -1 are rho - 1 = 0 and u = u0 (in split
+// storage the remainders are taken against them).  One channel per launch.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename P, typename S>
 __global__ __launch_bounds__(kBlock) void k_init(char *__restrict__ ws,
                                                  const ChanDev *__restrict__ chans,
                                                  int ch,
                                                  const double *__restrict__ u0)
 {
+    constexpr bool kSplit = sizeof(S) < sizeof(P);
     const ChanDev *c = chans + ch;
     const int n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= c->n)
         return;
     const int lx = c->lx, ly = c->ly, np = c->np, N = c->n;
     const int y = n / lx, x = n - y * lx;
-    R *pop = reinterpret_cast<R *>(ws + c->off_pop);
-    R *read0 = pop + 9 * (size_t)np;  // buffer pulled from at t = 0
+    S *pop = reinterpret_cast<S *>(ws + c->off_pop);
+    S *read0 = pop + 9 * (size_t)np;  // buffer pulled from at t = 0
+    const double ux0 = u0 ? u0[n] : 0.0;
+    const double uy0 = u0 ? u0[N + n] : 0.0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int yt = y + QY[q];
@@ -152,17 +165,33 @@ __global__ __launch_bounds__(kBlock) void k_init(char *__restrict__ ws,
         const double uu = ux * ux + uy * uy;
         const double dev =
             qweight<double>(sq) * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        read0[q * (size_t)np + n] = (R)dev;
-        pop[q * (size_t)np + n] = R(0);
+        if constexpr (kSplit) {
+            const double cu_own = QX[q] * ux0 + QY[q] * uy0;
+            read0[q * (size_t)np + n] =
+                (S)(dev - eq_dev<double>(qweight<double>(q), cu_own, 0.0, ux0 * ux0 + uy0 * uy0));
+        } else {
+            read0[q * (size_t)np + n] = (S)dev;
+        }
+        pop[q * (size_t)np + n] = S(0);
     }
-    R *sig = reinterpret_cast<R *>(ws + c->off_sig);
-    R *vel = reinterpret_cast<R *>(ws + c->off_vel);
-    R *rho = reinterpret_cast<R *>(ws + c->off_rho);
-    sig[n] = R(0);
-    sig[np + n] = R(0);
-    vel[n] = R(0);
-    vel[np + n] = R(0);
-    rho[n] = R(0);
+    if constexpr (kSplit) {
+        P *mom = reinterpret_cast<P *>(ws + c->off_mom);
+        mom[n] = P(0);
+        mom[np + n] = P(0);
+        mom[2 * (size_t)np + n] = P(0);
+        P *m1 = mom + 3 * (size_t)np;  // step -1
+        m1[n] = P(0);
+        m1[np + n] = (P)ux0;
+        m1[2 * (size_t)np + n] = (P)uy0;
+    }
+    P *sig = reinterpret_cast<P *>(ws + c->off_sig);
+    P *vel = reinterpret_cast<P *>(ws + c->off_vel);
+    P *rho = reinterpret_cast<P *>(ws + c->off_rho);
+    sig[n] = P(0);
+    sig[np + n] = P(0);
+    vel[n] = (P)ux0;
+    vel[np + n] = (P)uy0;
+    rho[n] = P(0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_zero(uint4 *__restrict__ p,
@@ -190,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero(uint4 *__restrict__ p,
 template <typename R>
 __device__ __forceinline__ void lb_collide_paper(char *__restrict__ ws, const ChanDev *c, int n,
                                                  size_t np, const R (&d)[9], R drho, R jx,
-                                                 R jy, R *__restrict__ dst)
+                                                 R jy, R (&out)[9], R &ux, R &uy, R &drho_out)
 {
     const R *__restrict__ sxy = reinterpret_cast<const R *>(ws + c->off_sig);
     const R *__restrict__ sxx = sxy + np;
@@ -202,8 +231,8 @@ __device__ __forceinline__ void lb_collide_paper(char *__restrict__ ws, const Ch
     drho += R(0.5) * dr;
     const R rho = R(1) + drho;
     const R fx = rho * (R)c->gx, fy = rho * (R)c->gy;
-    const R ux = (jx + R(0.5) * fx) / rho;
-    const R uy = (jy + R(0.5) * fy) / rho;
+    ux = (jx + R(0.5) * fx) / rho;
+    uy = (jy + R(0.5) * fy) / rho;
     const R bxx = R(0.5) * (sxx[n] - syy), bxy = sxy[n];
     const R om = (R)c->omega;
     const R pf = R(1) - R(0.5) * om;
@@ -220,12 +249,9 @@ __device__ __forceinline__ void lb_collide_paper(char *__restrict__ ws, const Ch
         const R F = w * (R(-4.5) * om * st +
                          pf * (dr + R(3) * (cf - uf) + R(9) * cu * cf - R(4.5) * dr * cu * cu +
                                R(1.5) * dr * uu));
-        dst[q * np + n] = d[q] - om * (d[q] - deq) + F;
+        out[q] = d[q] - om * (d[q] - deq) + F;
     }
-    R *vel = reinterpret_cast<R *>(ws + c->off_vel);
-    vel[n] = ux;
-    vel[np + n] = uy;
-    reinterpret_cast<R *>(ws + c->off_rho)[n] = drho;
+    drho_out = drho;
 }
 
 // ---------------------------------------------------------------------------
@@ -324,43 +350,157 @@ __device__ __forceinline__ void lb_collide_body(const ChanDev *c, int n, const R
     }
 }
 
-// Lattice update of node n at step t from and to the workspace.
-template <typename R>
+// ---------------------------------------------------------------------------
+// Split population storage (LB_F32).  A post-collision population of node n
+// is kept as the moments its collision used -- rho - 1, u_x, u_y in FP64,
+// [2][3][np] by step parity -- and the FP32 remainder
+//   r_q = n*_q - n^eq_q(rho, u),
+// with n^eq the second-order equilibrium of Sec. III.  A pulled population is
+// rebuilt in FP64 as n^eq_q(rho, u of the source node) + r_q.  The remainder
+// is the forcing term plus (1 - 1/tau_LB) times the non-equilibrium part, some
+// 1e-3 of the deviation n_q - a_q in the channels here, so FP32 rounding acts
+// on that small part only, and the conserved moments carry no FP32 rounding
+// from step to step.
+// ---------------------------------------------------------------------------
+
+// Population Q arriving at a node by a pull: through (the population left
+// node na in direction Q) or bounced back (it left node nb in the opposite
+// direction).  mom: the moment planes of the step it left (plane stride ss).
+template <int Q, typename P>
+__device__ __forceinline__ P pull_split_one(bool through, int na, int nb,
+                                            const float *__restrict__ src,
+                                            const P *__restrict__ mom, size_t ss)
+{
+#pragma clang fp contract(off)
+    const int nd = through ? na : nb;
+    const size_t plane = through ? (size_t)Q : (size_t)QOPP[Q];
+    const P drho = mom[nd], ux = mom[ss + nd], uy = mom[2 * ss + nd];
+    // c_opp(Q) = -c_Q
+    const P cu0 = P(QX[Q]) * ux + P(QY[Q]) * uy;
+    const P cu = through ? cu0 : -cu0;
+    return eq_dev<P>(qweight<P>(Q), cu, drho, ux * ux + uy * uy) + (P)src[plane * ss + nd];
+}
+
+// Pull-stream of node n from split storage (the same sources as lb_pull).
+template <typename P>
+__device__ __forceinline__ void lb_pull_split(const ChanDev *c, int n,
+                                              const float *__restrict__ src,
+                                              const P *__restrict__ mom, size_t ss, P (&d)[9])
+{
+    const int lx = c->lx, ly = c->ly;
+    const int y = n / lx, x = n - y * lx;
+    const int xp = (x + 1 == lx) ? 0 : x + 1;
+    const int xm = (x == 0) ? lx - 1 : x - 1;
+    const bool lo = y > 0, hi = y < ly - 1;
+    const int rowm = (y - 1) * lx, row = y * lx, rowp = (y + 1) * lx;
+    d[0] = pull_split_one<0, P>(true, n, n, src, mom, ss);
+    d[1] = pull_split_one<1, P>(true, row + xm, n, src, mom, ss);
+    d[2] = pull_split_one<2, P>(true, row + xp, n, src, mom, ss);
+    d[3] = pull_split_one<3, P>(lo, rowm + x, n, src, mom, ss);
+    d[4] = pull_split_one<4, P>(hi, rowp + x, n, src, mom, ss);
+    d[5] = pull_split_one<5, P>(lo, rowm + xm, n, src, mom, ss);
+    d[6] = pull_split_one<6, P>(hi, rowp + xp, n, src, mom, ss);
+    d[7] = pull_split_one<7, P>(hi, rowp + xm, n, src, mom, ss);
+    d[8] = pull_split_one<8, P>(lo, rowm + xp, n, src, mom, ss);
+}
+
+// The node's own post-collision deviations n*_q - a_q rebuilt from split
+// storage (for the adjoint's step record).
+template <typename P>
+__device__ __forceinline__ void own_split(int n, const float *__restrict__ src,
+                                          const P *__restrict__ mom, size_t ss, P (&d)[9])
+{
+    d[0] = pull_split_one<0, P>(true, n, n, src, mom, ss);
+    d[1] = pull_split_one<1, P>(true, n, n, src, mom, ss);
+    d[2] = pull_split_one<2, P>(true, n, n, src, mom, ss);
+    d[3] = pull_split_one<3, P>(true, n, n, src, mom, ss);
+    d[4] = pull_split_one<4, P>(true, n, n, src, mom, ss);
+    d[5] = pull_split_one<5, P>(true, n, n, src, mom, ss);
+    d[6] = pull_split_one<6, P>(true, n, n, src, mom, ss);
+    d[7] = pull_split_one<7, P>(true, n, n, src, mom, ss);
+    d[8] = pull_split_one<8, P>(true, n, n, src, mom, ss);
+}
+
+// Remainders r_q = n*_q - n^eq_q(rho, u) of the post-collision deviations
+// `out` of a node whose collision used (drho, ux, uy).
+template <typename P>
+__device__ __forceinline__ void split_remainders(const P (&out)[9], P ux, P uy, P drho,
+                                                 float (&r)[9])
+{
+#pragma clang fp contract(off)
+    const P uu = ux * ux + uy * uy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const P cu = P(QX[q]) * ux + P(QY[q]) * uy;
+        r[q] = (float)(out[q] - eq_dev<P>(qweight<P>(q), cu, drho, uu));
+    }
+}
+
+// Lattice update of node n at step t from and to the workspace.  S is the
+// population storage type: P (plain deviations n_q - a_q) or float (split
+// storage, P = double).
+template <typename P, typename S>
 __device__ __forceinline__ void lb_node(char *__restrict__ ws, const ChanDev *c, int n,
                                         int64_t t)
 {
+    constexpr bool kSplit = sizeof(S) < sizeof(P);
     const size_t np = (size_t)c->np;
-    R *pop = reinterpret_cast<R *>(ws + c->off_pop);
-    const R *__restrict__ src = pop + ((t + 1) & 1) * 9 * np;  // n*(t-1)
-    R *__restrict__ dst = pop + (t & 1) * 9 * np;              // n*(t)
+    S *pop = reinterpret_cast<S *>(ws + c->off_pop);
+    const S *__restrict__ src = pop + ((t + 1) & 1) * 9 * np;  // n*(t-1)
+    S *__restrict__ dst = pop + (t & 1) * 9 * np;              // n*(t)
+    P *mom = reinterpret_cast<P *>(ws + c->off_mom);           // split storage only
+    const P *__restrict__ msrc = mom + ((t + 1) & 1) * 3 * np;
+    const P *__restrict__ sig = reinterpret_cast<const P *>(ws + c->off_sig);
     if (c->rec) {
-        R *rec = reinterpret_cast<R *>(c->rec) + (size_t)(t - c->rec_t0) * 10 * np;
+        P *rec = reinterpret_cast<P *>(c->rec) + (size_t)(t - c->rec_t0) * 10 * np;
+        if constexpr (kSplit) {
+            P own[9];
+            own_split<P>(n, src, msrc, np, own);
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                rec[q * np + n] = own[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                rec[q * np + n] = src[q * np + n];
+        }
+        rec[9 * np + n] = sig[n];
+    }
+    P d[9];
+    if constexpr (kSplit)
+        lb_pull_split<P>(c, n, src, msrc, np, d);
+    else
+        lb_pull<P>(c, n, src, np, d);
+    P out[9], ux, uy, drho;
+    if (c->coupling) {
+        P drho0, jx, jy;
+        lb_moments<P>(d, drho0, jx, jy);
+        lb_collide_paper<P>(ws, c, n, np, d, drho0, jx, jy, out, ux, uy, drho);
+    } else {
+        lb_collide_body<P>(c, n, d, sig, np, out, ux, uy, drho);
+    }
+    if constexpr (kSplit) {
+        float r[9];
+        split_remainders<P>(out, ux, uy, drho, r);
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-            rec[q * np + n] = src[q * np + n];
-        rec[9 * np + n] = reinterpret_cast<const R *>(ws + c->off_sig)[n];
-    }
-    R d[9];
-    lb_pull<R>(c, n, src, np, d);
-    if (c->coupling) {
-        R drho, jx, jy;
-        lb_moments<R>(d, drho, jx, jy);
-        lb_collide_paper<R>(ws, c, n, np, d, drho, jx, jy, dst);
-        return;
-    }
-    R out[9], ux, uy, drho;
-    lb_collide_body<R>(c, n, d, reinterpret_cast<const R *>(ws + c->off_sig), np, out, ux, uy,
-                       drho);
+            dst[q * np + n] = r[q];
+        P *mdst = mom + (t & 1) * 3 * np;
+        mdst[n] = drho;
+        mdst[np + n] = ux;
+        mdst[2 * np + n] = uy;
+    } else {
 #pragma unroll
-    for (int q = 0; q < 9; ++q)
-        dst[q * np + n] = out[q];
-    R *vel = reinterpret_cast<R *>(ws + c->off_vel);
+        for (int q = 0; q < 9; ++q)
+            dst[q * np + n] = out[q];
+    }
+    P *vel = reinterpret_cast<P *>(ws + c->off_vel);
     vel[n] = ux;
     vel[np + n] = uy;
-    reinterpret_cast<R *>(ws + c->off_rho)[n] = drho;
+    reinterpret_cast<P *>(ws + c->off_rho)[n] = drho;
 }
 
-template <typename R>
+template <typename P, typename S>
 __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
                                                const ChanDev *__restrict__ chans,
                                                const NodeTile *__restrict__ tiles,
@@ -376,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
         tile_counters[threadIdx.x] = 0;
     if (n >= c->n)
         return;
-    lb_node<R>(ws, c, n, *tcount + trel);
+    lb_node<P, S>(ws, c, n, *tcount + trel);
 }
 
 // ---------------------------------------------------------------------------
@@ -1701,7 +1841,7 @@ __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
 // the unfused path has a kernel boundary (every node a stencil of the channel
 // reads belongs to the workgroup).  Same per-node arithmetic as k_lb and
 // k_hist_step, so results are identical.
-template <typename P, typename R>
+template <typename P, typename R, typename S>
 __global__ __launch_bounds__(kFuseThreads) void k_fused_steps(char *__restrict__ ws,
                                                             const ChanDev *__restrict__ chans,
                                                             const int64_t *__restrict__ tcount,
@@ -1712,7 +1852,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_fused_steps(char *__restrict__
     for (int k = 0; k < count; ++k) {
         const int64_t t = t0 + k;
         for (int n = threadIdx.x; n < c->n; n += kFuseThreads)
-            lb_node<P>(ws, c, n, t);
+            lb_node<P, S>(ws, c, n, t);
         __syncthreads();
         for (int n = threadIdx.x; n < c->n; n += kFuseThreads)
             hist_step_node<P, R>(ws, c, n, t, m0 + k);
@@ -1721,15 +1861,15 @@ __global__ __launch_bounds__(kFuseThreads) void k_fused_steps(char *__restrict__
 }
 
 // Steps m0 .. m0 + count - 1 of a block with the channel's lattice state in
-// the workgroup, for handles whose channels all take the simple-shear integral
-// law with the body-force coupling on a uniform window (and fit one
-// workgroup).  LDS holds the post-collision populations, the stress and the
-// velocity of the channel, so the neighbours a stencil reads come from LDS;
-// each thread keeps the history rows of its node pushed since the pass in
-// registers.  Every result still goes to the workspace (populations of both
-// parities, velocity, rho, stress, ring rows) as the separate launches write
-// it, and the arithmetic is the same operations in the same order, so the
-// results are identical.
+// the workgroup, for handles in split population storage whose channels all
+// take the simple-shear integral law with the body-force coupling on a
+// uniform window (and fit one workgroup).  LDS holds the post-collision
+// remainders, the moments (rho - 1, u) and the stress of the channel, so the
+// neighbours a stencil reads come from LDS; each thread keeps the history rows
+// of its node pushed since the pass in registers.  Every result still goes to
+// the workspace (remainders and moments of both parities, velocity, rho,
+// stress, ring rows) as the separate launches write it, and the arithmetic is
+// the same operations in the same order, so the results are identical.
 //
 // In-block history of one node at step t0 + m from the rows in registers
 // (entry j pushed at t0 + j, s_new this step's): the ring walk of
@@ -1763,8 +1903,8 @@ __device__ __forceinline__ void hist_regs(const ChanDev *c, const Decay<R> &dec,
 
 template <typename P, typename R, bool HAS_R>
 __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const ChanDev *c,
-                                               int64_t t0s, int m0, int count, P *s_pop,
-                                               P *s_sig, P *s_vel)
+                                               int64_t t0s, int m0, int count, float *s_pop,
+                                               P *s_mom, P *s_sig)
 {
     constexpr int K = kFuseThreads;  // LDS plane stride
     const int n = threadIdx.x;
@@ -1772,7 +1912,8 @@ __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const Chan
     const size_t np = (size_t)c->np;
     const int H = c->n_hist;
     const int64_t tb = t0s - m0;  // step of the block's pass
-    P *pop = reinterpret_cast<P *>(ws + c->off_pop);
+    float *pop = reinterpret_cast<float *>(ws + c->off_pop);
+    P *mom = reinterpret_cast<P *>(ws + c->off_mom);
     P *vel = reinterpret_cast<P *>(ws + c->off_vel);
     P *rhop = reinterpret_cast<P *>(ws + c->off_rho);
     P *sig = reinterpret_cast<P *>(ws + c->off_sig);
@@ -1783,10 +1924,14 @@ __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const Chan
     // state of step t0s - 1, and the rows pushed since the pass
     R hs[kMaxBlock], hr[kMaxBlock];
     if (own) {
-        const P *src = pop + ((t0s + 1) & 1) * 9 * np;
+        const float *src = pop + ((t0s + 1) & 1) * 9 * np;
+        const P *msrc = mom + ((t0s + 1) & 1) * 3 * np;
 #pragma unroll
         for (int q = 0; q < 9; ++q)
             s_pop[q * K + n] = src[q * np + n];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            s_mom[i * K + n] = msrc[i * np + n];
         s_sig[n] = sig[n];
         s_sig[K + n] = sig[np + n];
 #pragma unroll
@@ -1805,31 +1950,40 @@ __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const Chan
         const int64_t t = t0s + k;
         const int m = m0 + k;
         double A = 0.0, B = 0.0;
-        P out[9], ux = P(0), uy = P(0), drho = P(0);
+        float r[9];
+        P ux = P(0), uy = P(0), drho = P(0);
         if (own) {
-            A = blk[m * np + n];  // issued before the lattice phase
-            B = blk[(kPlaneB + m) * np + n];
             if (c->rec) {
                 P *rec = reinterpret_cast<P *>(c->rec) + (size_t)(t - c->rec_t0) * 10 * np;
+                P od[9];
+                own_split<P>(n, s_pop, s_mom, K, od);
 #pragma unroll
                 for (int q = 0; q < 9; ++q)
-                    rec[q * np + n] = s_pop[q * K + n];
+                    rec[q * np + n] = od[q];
                 rec[9 * np + n] = s_sig[n];
             }
-            P d[9];
-            lb_pull<P>(c, n, s_pop, K, d);
+            P d[9], out[9];
+            lb_pull_split<P>(c, n, s_pop, s_mom, K, d);
             lb_collide_body<P>(c, n, d, s_sig, K, out, ux, uy, drho);
+            split_remainders<P>(out, ux, uy, drho, r);
         }
-        __syncthreads();  // every stencil read of the old populations and stress is done
+        __syncthreads();  // every stencil read of the old state and stress is done
         if (own) {
-            P *dst = pop + (t & 1) * 9 * np;
+            A = blk[m * np + n];
+            B = blk[(kPlaneB + m) * np + n];
+            float *dst = pop + (t & 1) * 9 * np;
+            P *mdst = mom + (t & 1) * 3 * np;
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
-                s_pop[q * K + n] = out[q];
-                dst[q * np + n] = out[q];
+                s_pop[q * K + n] = r[q];
+                dst[q * np + n] = r[q];
             }
-            s_vel[n] = ux;
-            s_vel[K + n] = uy;
+            s_mom[n] = drho;
+            s_mom[K + n] = ux;
+            s_mom[2 * K + n] = uy;
+            mdst[n] = drho;
+            mdst[np + n] = ux;
+            mdst[2 * np + n] = uy;
             vel[n] = ux;
             vel[np + n] = uy;
             rhop[n] = drho;
@@ -1838,7 +1992,8 @@ __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const Chan
         if (own) {
             const int y = n / c->lx, x = n - y * c->lx;
             P kxx, kxy, kyx, kyy;
-            velocity_gradient<P>(s_vel, s_vel + K, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
+            velocity_gradient<P>(s_mom + K, s_mom + 2 * K, c->lx, c->ly, x, y, kxx, kxy, kyx,
+                                 kyy);
             const R s_new = (R)kxy;
             const size_t o = (size_t)(t % H) * np + n;
             ring_s[o] = s_new;
@@ -1873,15 +2028,14 @@ __global__ __launch_bounds__(kFuseThreads) void k_fused_steps_lds(
     int trel, int m0, int count)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    P *s_pop = reinterpret_cast<P *>(lds_raw);  // [9][kFuseThreads]
-    P *s_sig = s_pop + 9 * kFuseThreads;        // [2][kFuseThreads]
-    P *s_vel = s_sig + 2 * kFuseThreads;        // [2][kFuseThreads]
+    P *s_mom = reinterpret_cast<P *>(lds_raw);             // [3][kFuseThreads]
+    P *s_sig = s_mom + 3 * kFuseThreads;                   // [2][kFuseThreads]
+    float *s_pop = reinterpret_cast<float *>(s_sig + 2 * kFuseThreads);  // [9][kFuseThreads]
     const ChanDev *c = chans + blockIdx.x;
     const int64_t t0s = *tcount + trel;
-    if (c->has_r)
-        fused_span_lds<P, R, true>(ws, c, t0s, m0, count, s_pop, s_sig, s_vel);
-    else
-        fused_span_lds<P, R, false>(ws, c, t0s, m0, count, s_pop, s_sig, s_vel);
+    // unidirectional channels only (|gamma_dot| = |s|: one row per entry in
+    // registers); the host selects this form only then
+    fused_span_lds<P, R, false>(ws, c, t0s, m0, count, s_pop, s_mom, s_sig);
 }
 
 // ---------------------------------------------------------------------------
@@ -2282,21 +2436,26 @@ __global__ __launch_bounds__(kBlock) void k_readout(int which, const char *__res
 // ---------------------------------------------------------------------------
 static inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
-// Precision codes: 0 FP64 lattice + FP64 history, 1 FP32 + FP32,
-// 2 FP64 lattice + FP32 history.  P is the lattice type, H the history type.
+// Precision codes: 0 FP64 lattice + FP64 history, 1 split population storage
+// (FP32 remainders, FP64 moments) + FP32 history, 2 FP64 lattice + FP32
+// history.  P is the lattice arithmetic and plane type, H the history type,
+// S the population storage type.
 #define LBMAX_BY_PREC(prec, BODY)                                                \
     do {                                                                         \
         if ((prec) == 0) {                                                       \
             typedef double P;                                                    \
             typedef double H;                                                    \
+            typedef double S;                                                    \
             BODY;                                                                \
         } else if ((prec) == 1) {                                                \
-            typedef float P;                                                     \
+            typedef double P;                                                    \
             typedef float H;                                                     \
+            typedef float S;                                                     \
             BODY;                                                                \
         } else {                                                                 \
             typedef double P;                                                    \
             typedef float H;                                                     \
+            typedef double S;                                                    \
             BODY;                                                                \
         }                                                                        \
     } while (0)
@@ -2304,7 +2463,7 @@ static inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 void launch_init(int prec, char *ws, const ChanDev *chans, int ch, const NodeTile *,
                  int n_tiles, const double *u0_dev, hipStream_t st)
 {
-    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_init<P>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_init<P, S>), dim3(n_tiles), dim3(kBlock), 0, st, ws,
                                            chans, ch, u0_dev));
 }
 
@@ -2323,7 +2482,7 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st)
 void launch_lb(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
                const int64_t *tcount, int trel, int *tile_counters, hipStream_t st)
 {
-    LBMAX_BY_PREC(prec, hipLaunchKernelGGL(k_lb<P>, dim3(n_tiles), dim3(kBlock), 0, st, ws,
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_lb<P, S>), dim3(n_tiles), dim3(kBlock), 0, st, ws,
                                            chans, tiles, tcount, trel, tile_counters));
 }
 
@@ -2510,26 +2669,29 @@ void launch_fused_steps(int prec, bool lds, char *ws, const ChanDev *chans, int 
     if (n_ch <= 0 || count <= 0)
         return;
     if (!lds) {
-        LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_fused_steps<P, H>), dim3(n_ch),
+        LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_fused_steps<P, H, S>), dim3(n_ch),
                                                dim3(kFuseThreads), 0, st, ws, chans, tcount,
                                                trel, m0, count));
         return;
     }
     if (prec == 1)
-        hipLaunchKernelGGL((k_fused_steps_lds<float, float>), dim3(n_ch), dim3(kFuseThreads),
+        hipLaunchKernelGGL((k_fused_steps_lds<double, float>), dim3(n_ch), dim3(kFuseThreads),
                            fused_lds_bytes(prec), st, ws, chans, tcount, trel, m0, count);
 }
 
-size_t fused_lds_bytes(int prec) { return prec == 1 ? (size_t)13 * kFuseThreads * sizeof(float) : 0; }
+// Moments and stress (FP64, 3 + 2 planes) and remainders (FP32, 9 planes).
+size_t fused_lds_bytes(int prec)
+{
+    return prec == 1 ? (size_t)kFuseThreads * (5 * sizeof(double) + 9 * sizeof(float)) : 0;
+}
 
 int prepare_fused_lds(int prec)
 {
-    // FP32 only: with FP64 lattice state the form does not fit the 128
-    // registers a 1024-thread workgroup leaves each thread
+    // Split storage only: with FP64 populations the state would not fit
     if (prec != 1)
         return -1;
     const hipError_t e =
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fused_steps_lds<float, float>),
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fused_steps_lds<double, float>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_lds_bytes(prec));
     return e == hipSuccess ? 0 : -1;
 }

@@ -3,6 +3,7 @@
 // workspace, builds the launch tile lists, enqueues steps (plain launches or
 // hipGraph replays), and implements readouts and state snapshots.
 #include "lbmax.h"
+#include "lbmax_checks.h"
 #include "lbmax_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -34,7 +35,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int blk_planes(const ChanDev &c) { return c.finger ? 3 * kMaxBlock : 2 * kMaxBlock + c.qb; }
 
 constexpr uint64_t kStateMagic = 0x4C424D4158535431ull;  // "LBMAXST1"
-constexpr uint32_t kStateVersion = 5;
+constexpr uint32_t kStateVersion = 6;
 constexpr size_t kStateHeader = 256;
 constexpr int64_t kMaxStepsPerBatch = int64_t(1) << 20;
 
@@ -145,8 +146,10 @@ int max_chunks_for(int n_hist, int np)
     return (int)std::min<int64_t>(m, cap);
 }
 
-// Element sizes of the lattice planes and of the history ring.
-size_t lattice_bytes(lb_precision prec) { return prec == LB_F32 ? 4 : 8; }
+// Element sizes of the lattice planes (stress, velocity, density), of the
+// stored populations and of the history ring.
+size_t lattice_bytes(lb_precision) { return 8; }
+size_t pop_bytes(lb_precision prec) { return prec == LB_F32 ? 4 : 8; }
 size_t history_bytes(lb_precision prec) { return prec == LB_F64 ? 8 : 4; }
 int prec_code(lb_precision prec) { return prec == LB_F64 ? 0 : (prec == LB_F32 ? 1 : 2); }
 
@@ -205,7 +208,12 @@ Plan make_plan(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec)
         ChanDev &c = P.chans[i];
         const size_t plane = (size_t)c.np * R;
         c.off_pop = (int64_t)off;
-        off = align_up(off + 18 * plane, 256);
+        off = align_up(off + 18 * (size_t)c.np * pop_bytes(prec), 256);
+        c.off_mom = 0;
+        if (prec == LB_F32) {
+            c.off_mom = (int64_t)off;
+            off = align_up(off + 6 * (size_t)c.np * sizeof(double), 256);
+        }
         c.off_sig = (int64_t)off;
         off = align_up(off + 3 * plane, 256);
         c.off_vel = (int64_t)off;
@@ -257,6 +265,8 @@ struct lb_handle {
     int block_pos = 0;      // steps done in the current block (0: next is a pass)
     bool has_out = false;   // readout planes belong to step t-1
     bool poisoned = false;
+    int checks = LB_CHECK_FINITE | LB_CHECK_MACH;  // lb_set_checks
+    int warnings = 0;                              // raised since the last lb_warnings
     // device pointers into the workspace
     int64_t *d_tcount = nullptr;
     int *d_tile_counters = nullptr;  // in the header block after the step counter
@@ -415,7 +425,7 @@ void build_tiles(lb_handle *h)
     for (const ChanDev &c : h->plan.chans) {
         if (c.n > kFuseMaxNodes)
             h->fuse_ok = h->fuse_lds_ok = false;
-        if (c.law != 0 || c.finger || c.coupling)
+        if (c.law != 0 || c.finger || c.coupling || c.has_r)
             h->fuse_lds_ok = false;
     }
     if (h->fuse_lds_ok && !h->fuse_lds_ready)
@@ -632,6 +642,17 @@ lb_status readout(lb_handle *h, int32_t ch, int which, int comps,
     for (int k = 0; k < comps; ++k)
         if (outs[k])
             std::memcpy(outs[k], host.data() + (size_t)k * N, N * sizeof(double));
+    // velocity readout: the lattice Mach guard (both components, requested or not)
+    if (which == 0 && (h->checks & LB_CHECK_MACH) &&
+        mach_guard_trips(max_speed(host.data() + N, host.data() + 2 * (size_t)N, N)))
+        h->warnings |= LB_WARN_MACH;
+    if (h->checks & LB_CHECK_FINITE) {
+        const ValueScan v = scan_values(host.data(), host.size());
+        if (v.nonfinite)
+            return fail(LB_ENONFINITE, "readout of channel " + std::to_string(ch) + ": " +
+                                           std::to_string(v.nonfinite) +
+                                           " non-finite values (the run has diverged)");
+    }
     return LB_OK;
 }
 
@@ -648,9 +669,10 @@ std::vector<Section> state_sections(const lb_handle *h, int ci, int64_t t)
     const size_t R = lattice_bytes(h->prec), RH = history_bytes(h->prec);
     const size_t rowb = (size_t)c.n * R, pitch = (size_t)c.np * R;
     const size_t hrowb = (size_t)c.n * RH, hpitch = (size_t)c.np * RH;
-    const int64_t cur = c.off_pop + (int64_t)(((t + 1) & 1) * 9 * pitch);
+    const size_t PB = pop_bytes(h->prec);
+    const int64_t cur = c.off_pop + (int64_t)(((t + 1) & 1) * 9 * (size_t)c.np * PB);
     std::vector<Section> v;
-    v.push_back({cur, 9, rowb, pitch});
+    v.push_back({cur, 9, (size_t)c.n * PB, (size_t)c.np * PB});
     v.push_back({c.off_sig, 3, rowb, pitch});
     v.push_back({c.off_vel, 2, rowb, pitch});
     v.push_back({c.off_rho, 1, rowb, pitch});
@@ -998,6 +1020,26 @@ lb_status lb_step(lb_handle *h, int64_t n_steps)
 
 int64_t lb_time(const lb_handle *h) { return h ? h->t : -1; }
 
+lb_status lb_set_checks(lb_handle *h, int32_t flags)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (flags & ~(LB_CHECK_FINITE | LB_CHECK_MACH))
+        return fail(LB_EINVAL, "unknown check flags");
+    h->checks = flags;
+    return LB_OK;
+}
+
+int32_t lb_warnings(lb_handle *h)
+{
+    if (!h)
+        return 0;
+    const int w = h->warnings;
+    h->warnings = 0;
+    return w;
+}
+
 lb_status lb_fields(lb_handle *h, int32_t ch, double *rho, double *ux, double *uy)
 {
     double *o[3] = {rho, ux, uy};
@@ -1086,6 +1128,18 @@ lb_status lb_load_state(lb_handle *h, const void *d_src)
         HIP_TRY(h, hipMemcpyAsync(&forces[2 * ci], src + off, 16, hipMemcpyDeviceToHost,
                                   h->stream));
         off = align_up(off + 2 * sizeof(double), 256);
+    }
+    // Split storage: the moments of step t-1 (the base of the stored
+    // remainders) are the loaded density and velocity planes.
+    for (int ci = 0; ci < h->n_ch; ++ci) {
+        const ChanDev &c = h->plan.chans[ci];
+        if (!c.off_mom)
+            continue;
+        const size_t pb = (size_t)c.np * sizeof(double);
+        char *m = h->ws + c.off_mom + (size_t)((hd.t + 1) & 1) * 3 * pb;
+        HIP_TRY(h, hipMemcpyAsync(m, h->ws + c.off_rho, pb, hipMemcpyDeviceToDevice, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(m + pb, h->ws + c.off_vel, 2 * pb, hipMemcpyDeviceToDevice,
+                                  h->stream));
     }
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     for (int ci = 0; ci < h->n_ch; ++ci) {

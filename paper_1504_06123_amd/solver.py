@@ -7,11 +7,16 @@ from __future__ import annotations
 
 import ctypes
 import math
+import warnings
 from typing import Optional, Sequence
 
 import numpy as np
 
 from . import _lib
+
+
+class MachWarning(UserWarning):
+    """A velocity readout found |u| above the lattice Mach guard (0.1)."""
 
 
 def _precision_code(precision: str) -> int:
@@ -69,8 +74,10 @@ class Solver:
     """A set of channels advanced together on one GPU.
 
     channels: sequence of channel descriptions (see make_descs).
-    precision: "f32" (FP32 populations and Kahan history sums, FP64 strain),
-    "f32p64" (FP64 lattice state, FP32 Kahan history) or "f64".
+    precision: "f32" (FP32 populations stored as remainders against the
+    equilibrium of FP64 moments; FP32 history with FP32 partial sums flushed
+    into FP64; FP64 strain), "f32p64" (FP64 populations, the same FP32
+    history) or "f64".
     """
 
     def __init__(self, channels: Sequence, precision: str = "f32",
@@ -102,6 +109,7 @@ class Solver:
         if getattr(self, "h", None):
             self.lib.lb_destroy(self.h)
             self.h = None
+        self._adjoint_ws = None
 
     def __del__(self):
         try:
@@ -179,7 +187,17 @@ class Solver:
         P = ctypes.POINTER(ctypes.c_double)
         _lib.check(self.lib.lb_fields(self.h, int(ch), rho.ctypes.data_as(P),
                                       ux.ctypes.data_as(P), uy.ctypes.data_as(P)), "lb_fields")
+        if self.lib.lb_warnings(self.h) & _lib.LB_WARN_MACH:
+            warnings.warn(MachWarning(
+                f"channel {ch}: |u| exceeds 0.1 (lattice Mach number above 0.17); the "
+                "lattice-Boltzmann step is accurate only at small Mach number"), stacklevel=2)
         return rho, ux, uy
+
+    def set_checks(self, finite: bool = True, mach: bool = True) -> None:
+        """Readout checks (lb_set_checks): non-finite values raise LBError
+        with status LB_ENONFINITE; speeds above 0.1 warn (MachWarning)."""
+        flags = (_lib.LB_CHECK_FINITE if finite else 0) | (_lib.LB_CHECK_MACH if mach else 0)
+        _lib.check(self.lib.lb_set_checks(self.h, flags), "lb_set_checks")
 
     def stress(self, ch: int = 0):
         sh = self._shape(ch)
@@ -222,7 +240,7 @@ class Solver:
 
 
 STATE_MAGIC = 0x4C424D4158535431
-STATE_VERSION = 5
+STATE_VERSION = 6
 
 
 def pack_state_header(t: int, n_ch: int, precision: str, total_bytes: int,
@@ -237,7 +255,8 @@ def pack_state_header(t: int, n_ch: int, precision: str, total_bytes: int,
 def state_layout(channels: Sequence, precision: str = "f32"):
     """Byte offsets of the sections of a state buffer (include/lbmax.h)."""
     code = _precision_code(precision)
-    R = 4 if code == _lib.LB_F32 else 8          # lattice planes
+    R = 8                                        # stress, velocity, density planes
+    RP = 4 if code == _lib.LB_F32 else 8         # stored populations
     RH = 8 if code == _lib.LB_F64 else 4         # history ring
 
     def up(x):
@@ -254,7 +273,7 @@ def state_layout(channels: Sequence, precision: str = "f32"):
         finger = bool(getattr(ch, "finger", False))
         for name, rows in (("pop", 9), ("sig", 3), ("vel", 2), ("drho", 1), ("trp", 1)):
             sec[name] = (off, rows, N)
-            off = up(off + rows * N * R)
+            off = up(off + rows * N * (RP if name == "pop" else R))
         B = int(getattr(ch, "hist_blocks", 0))
         if B:
             rows = B * int(ch.hist_block_len)

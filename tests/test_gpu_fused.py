@@ -53,43 +53,44 @@ def test_fused_equals_separate_launches_batched(Solver, precision, block):
 
 
 @pytest.mark.parametrize("block", [4, 32])
-def test_fused_lds_form_2d_channels_and_short_windows(Solver, block):
-    """The LDS form on 2D channels (|gamma_dot| rows kept too), windows
-    shorter than the block, a chunked window, and a channel at the 1024-node
-    limit."""
+def test_fused_lds_form_short_windows_and_limits(Solver, block):
+    """The LDS form (unidirectional channels) with a window shorter than the
+    block, a chunked window and a channel at the 1024-node limit; 2D channels
+    of the same sizes take the global-memory fused form.  Both equal the
+    separate launches bit for bit."""
+    def uni(ly, n_hist, tau_m):
+        return workloads.plain_f64().channels[0].replace(lx=1, ly=ly, n_hist=n_hist,
+                                                         tau_m=tau_m, gx=2e-5)
+
     def twod(lx, ly, n_hist, tau_m):
         return workloads.large_2d(lx=lx, ly=ly, n_hist=n_hist).channels[0].replace(tau_m=tau_m)
 
-    chans = [twod(8, 16, 300, 20.0),
-             twod(5, 13, 3, 15.0),      # window shorter than the block
-             twod(32, 32, 64, 30.0),    # 1024 nodes
-             workloads.plain_f64().channels[0].replace(lx=1, ly=40, n_hist=2000)]
-    say(f"case fused LDS form 2D + short windows, f32 block {block}")
-    a = _run(Solver, chans, "f32", block, 0, 150, want=0)
-    with Solver(chans, precision="f32") as s:
-        s.set_tiling(3, 4)     # the long window split into 4 age chunks
-        s.set_block(block)
-        out = []
-        done = 0
-        for k in (50, 55, 150):
-            s.step(k - done)
-            done = k
-            for ci in range(len(chans)):
-                out.append(s.fields(ci) + s.stress(ci))
-        assert s.fused == 2
-    with Solver(chans, precision="f32") as s:
-        s.set_tiling(3, 4)
-        s.set_block(block)
-        s.set_fused(0)
-        ref = []
-        done = 0
-        for k in (50, 55, 150):
-            s.step(k - done)
-            done = k
-            for ci in range(len(chans)):
-                ref.append(s.fields(ci) + s.stress(ci))
-    _same(ref, out)
-    assert len(a) == len(out)
+    for kind, chans, want in (
+            ("unidirectional", [uni(16, 300, 20.0),
+                                uni(13, 3, 15.0),       # window shorter than the block
+                                uni(1024, 64, 30.0),    # 1024 nodes
+                                uni(40, 2000, 100.0)], 2),
+            ("2D", [twod(8, 16, 300, 20.0),
+                    twod(5, 13, 3, 15.0),
+                    twod(32, 32, 64, 30.0),
+                    uni(40, 2000, 100.0)], 1)):
+        say(f"case fused form, {kind} channels, f32 block {block}")
+        runs = []
+        for mode in (1, 0):
+            with Solver(chans, precision="f32") as s:
+                s.set_tiling(3, 4)     # the long window split into 4 age chunks
+                s.set_block(block)
+                s.set_fused(mode)
+                assert s.fused == (want if mode else 0)
+                out = []
+                done = 0
+                for k in (50, 55, 150):
+                    s.step(k - done)
+                    done = k
+                    for ci in range(len(chans)):
+                        out.append(s.fields(ci) + s.stress(ci))
+                runs.append(out)
+        _same(runs[1], runs[0])
 
 
 def test_fused_equals_separate_launches_mixed_kinds(Solver):

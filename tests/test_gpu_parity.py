@@ -7,10 +7,11 @@ stays meaningful through zero crossings of the velocity during cessation).
 Both velocity components are divided by the speed scale max |u| of the
 reference.
 Tolerances: FP32 path 1e-5 for velocity and 1e-4 for sigma_xy and N1.  FP64
-path 1e-10: the oracle keeps whole populations (about 0.44, rounding unit
+path 1e-11: the oracle keeps whole populations (about 0.44, rounding unit
 5.6e-17) while the GPU keeps deviations from the weights, so the two differ
 by the oracle's own rounding floor, about 1e-16 absolute per step; for
-velocities of 1e-4 that random-walks to a few 1e-11 over 10^3 steps.
+velocities of 1e-4 that random-walks to a few 1e-12 over 10^3 steps (the
+largest seen is 3.1e-12).
 """
 import math
 import os
@@ -23,7 +24,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-TOL64 = 1e-10
+TOL64 = 1e-11
 TOL32 = {"ux": 1e-5, "uy": 1e-5, "sxy": 1e-4, "n1": 1e-4}
 
 
@@ -131,8 +132,15 @@ def test_f64_gradient_readout(Solver):
     oc = oracle.OracleChannel(ch)
     oc.step(37)
     kr = oc.grad()
+    _, uxr, uyr = oc.fields()
+    # kappa is a difference of velocities (stencil weights summing to at most
+    # 4/3 + 1 in magnitude): its error is bounded by that of the velocity, so
+    # it is measured on the velocity scale
+    vscale = max(np.abs(uxr).max(), np.abs(uyr).max())
     for i in range(4):
-        assert nerr(k[i], kr[i]) < TOL64
+        err = float(np.abs(k[i] - kr[i]).max() / vscale)
+        say(f"  kappa[{i}] error on the velocity scale {err:.2e}")
+        assert err < 3 * TOL64
 
 
 @pytest.mark.parametrize("name,kw", [
@@ -160,7 +168,8 @@ def test_f64_2d_perturbed(Solver):
 
 
 # ---------------------------------------------------------------------------
-# FP32 path (Kahan history sums, FP64 strain)
+# FP32 paths: split FP32 population storage ("f32") or FP64 populations
+# ("f32p64"); FP32 history with FP32 partial sums flushed into FP64; FP64 strain
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("precision", ["f32", "f32p64"])
@@ -199,14 +208,24 @@ def test_f32_batched_uneven_channels(Solver):
 # Launch-shape invariance, determinism, graphs, state
 # ---------------------------------------------------------------------------
 
-def test_chunk_split_invariance(Solver):
-    ch = workloads.startup_cessation().channels[0].replace(ly=40, n_hist=2048, tau_m=300.0, gx=5e-6)
-    say("case chunk invariance")
-    a = run_gpu(Solver, [ch], "f64", 500, 250, chunks=[1])[0]
+@pytest.mark.parametrize("block", [1, 32])
+def test_chunk_split_invariance(Solver, block):
+    """A window split into 2, 7 or 16 age chunks (combined in FP64) equals the
+    unsplit window to rounding order, past the first window fill (2048-entry
+    window, 2600 steps with cessation at 1800), so the window-end terms of
+    non-final chunks carry real entries; each run also matches the oracle."""
+    ch = workloads.startup_cessation().channels[0].replace(ly=40, n_hist=2048, tau_m=300.0,
+                                                            gx=5e-6)
+    steps, on = 2600, 1800
+    say(f"case chunk invariance, block {block}")
+    a = run_gpu(Solver, [ch], "f64", steps, 200, steps_on=on, chunks=[1], block=block)[0]
+    ref = run_oracle([ch], steps, 200, steps_on=on)[0]
+    compare(a, ref, TOL64, label="chunks=1")
     for nc in (2, 7, 16):
-        b = run_gpu(Solver, [ch], "f64", 500, 250, chunks=[nc])[0]
+        b = run_gpu(Solver, [ch], "f64", steps, 200, steps_on=on, chunks=[nc], block=block)[0]
         for k in ("ux", "sxy", "n1"):
             assert nerr(b[k], a[k]) < 1e-12, (nc, k)
+        compare(b, ref, TOL64, label=f"chunks={nc}")
 
 
 def test_lane_width_invariance(Solver):
@@ -450,6 +469,9 @@ def test_large_2d_full_size_synthetic_window(Solver):
             r_age[k] = cols_r[slot, j]
         rxy, rxx = oracle.history_sum_ages(s_age, r_age, ch.g_inf, ch.tau_m, ch.gamma_c)
         y, x = divmod(int(node), ch.lx)
+        # per node: relative 1e-4 (the stress bar) above an absolute floor
+        assert abs(sxy[y, x] - rxy) <= 1e-4 * abs(rxy) + 1e-12 * ch.g_inf, (node, sxy[y, x], rxy)
+        assert abs(n1[y, x] - rxx) <= 1e-4 * abs(rxx) + 1e-12 * ch.g_inf, (node, n1[y, x], rxx)
         got_xy.append(sxy[y, x])
         got_n1.append(n1[y, x])
         ref_xy.append(rxy)
