@@ -387,6 +387,22 @@ lb_status lb_set_params(lb_handle *h, int32_t ch, double g_inf, double tau_m,
  */
 size_t lb_adjoint_workspace_bytes(const lb_handle *h, int32_t seg_len);
 lb_status lb_adjoint_begin(lb_handle *h, void *d_aws, size_t bytes, int32_t seg_len);
+
+/*
+ * lb_adjoint_begin for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the adjoint workspace is the library's own static device array of 64 MiB,
+ * one per GPU (the GPU current at lb_init), held until the process ends.
+ * Allocates nothing, on the device or through any library.  Returns
+ * LB_ENOMEM, with nothing enqueued, when lb_adjoint_workspace_bytes(h,
+ * seg_len) exceeds 64 MiB.  The array is shared by every handle on that GPU
+ * and keeps the last sweep's contents (each begin clears what must start at
+ * zero); sweeps that overlap on one GPU -- two handles between their
+ * lb_adjoint_begin_noalloc and lb_adjoint_end at once -- race and give wrong
+ * gradients, so callers run them one at a time.  The rest of the protocol
+ * (lb_adjoint_segment, lb_adjoint_end) is unchanged.
+ */
+lb_status lb_adjoint_begin_noalloc(lb_handle *h, int32_t seg_len);
 lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_dux,
                              int32_t n_steps);
 lb_status lb_adjoint_end(lb_handle *h, double *dL_dtheta);

@@ -79,6 +79,7 @@ SIGNATURES = {
                                      ctypes.c_double]),
     "lb_adjoint_workspace_bytes": (ctypes.c_size_t, [_H, ctypes.c_int32]),
     "lb_adjoint_begin": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32]),
+    "lb_adjoint_begin_noalloc": (ctypes.c_int, [_H, ctypes.c_int32]),
     "lb_adjoint_segment": (ctypes.c_int, [_H, ctypes.c_void_p, _D, ctypes.c_int32]),
     "lb_adjoint_end": (ctypes.c_int, [_H, _D]),
     "lb_destroy": (ctypes.c_int, [_H]),

@@ -62,27 +62,33 @@ def forward(solver, steps: int, sample_every: int, seg_len: int):
 
 
 def backward(solver, ckpts, steps: int, sample_every: int, seg_len: int, dL_dsamples,
-             t_start: int = 0):
+             t_start: int = 0, library_workspace: bool = False):
     """dL/dtheta [n_ch, 4] for the run of forward(); dL_dsamples has the shape
-    of its samples.  The solver's forward state is overwritten."""
+    of its samples.  The solver's forward state is overwritten.  With
+    library_workspace the sweep runs in the library's own device array
+    (lb_adjoint_begin_noalloc) instead of a workspace allocated here."""
     import torch
     dL_dsamples = np.asarray(dL_dsamples, dtype=np.float64)
     total = dL_dsamples.shape[1]
     per_step = {t: dL_dsamples[k] for k, t in enumerate(sample_steps(steps, sample_every))}
-    nbytes = solver.lib.lb_adjoint_workspace_bytes(solver.h, seg_len)
-    if nbytes == 0:
-        raise _lib.LBError(_lib.LB_EINVAL, "lb_adjoint_workspace_bytes", _lib.last_error())
-    # One adjoint workspace per solver and segment length, kept between
-    # sweeps: the library keeps its captured reverse-sweep graphs only while
-    # the workspace address and segment length stay the same.
-    cached = getattr(solver, "_adjoint_ws", None)
-    if cached is not None and cached[0] == seg_len and cached[1].numel() == int(nbytes):
-        aws = cached[1]
+    if library_workspace:
+        _lib.check(solver.lib.lb_adjoint_begin_noalloc(solver.h, seg_len),
+                   "lb_adjoint_begin_noalloc")
     else:
-        aws = torch.empty(int(nbytes), dtype=torch.uint8, device=solver.device)
-        solver._adjoint_ws = (seg_len, aws)
-    _lib.check(solver.lib.lb_adjoint_begin(solver.h, ctypes.c_void_p(aws.data_ptr()),
-                                           int(nbytes), seg_len), "lb_adjoint_begin")
+        nbytes = solver.lib.lb_adjoint_workspace_bytes(solver.h, seg_len)
+        if nbytes == 0:
+            raise _lib.LBError(_lib.LB_EINVAL, "lb_adjoint_workspace_bytes", _lib.last_error())
+        # One adjoint workspace per solver and segment length, kept between
+        # sweeps: the library keeps its captured reverse-sweep graphs only
+        # while the workspace address and segment length stay the same.
+        cached = getattr(solver, "_adjoint_ws", None)
+        if cached is not None and cached[0] == seg_len and cached[1].numel() == int(nbytes):
+            aws = cached[1]
+        else:
+            aws = torch.empty(int(nbytes), dtype=torch.uint8, device=solver.device)
+            solver._adjoint_ws = (seg_len, aws)
+        _lib.check(solver.lib.lb_adjoint_begin(solver.h, ctypes.c_void_p(aws.data_ptr()),
+                                               int(nbytes), seg_len), "lb_adjoint_begin")
     P = ctypes.POINTER(ctypes.c_double)
     for t0, snap in reversed(ckpts):
         rel0 = t0 - t_start

@@ -12,12 +12,48 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace lbmax;
 
+// ---------------------------------------------------------------------------
+// The library's own adjoint workspace, for lb_adjoint_begin_noalloc: a static
+// device array, one copy on each GPU the library runs on, held until the
+// process ends and shared by every handle on that GPU.  In host code its name
+// is only a stand-in: the device address of each GPU's copy is taken once per
+// device with hipGetSymbolAddress (lb_init, that device current) and that
+// address is what kernels and copies receive.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the array on GPU dev (the current device), looked up on
+// the first call for that device.
+hipError_t scratch_address(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (!p)
+            return hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 thread_local std::string g_err;
 
@@ -302,7 +338,8 @@ struct lb_handle {
     size_t aws_bytes = 0;
     AdjChan *d_achans = nullptr;
     double *d_adj_out = nullptr;
-    std::vector<AdjChan> achans;
+    std::vector<AdjChan> achans;  // n_ch entries from lb_init on
+    void *scratch = nullptr;      // the library's device array on this handle's GPU
     int64_t *d_adj_t0 = nullptr;
     // captured reverse sweeps by segment length (for this adjoint workspace)
     std::vector<std::pair<int, hipGraphExec_t>> adj_execs;
@@ -711,27 +748,29 @@ size_t state_size(const lb_handle *h)
 // ---------------------------------------------------------------------------
 // Adjoint sweep
 // ---------------------------------------------------------------------------
-struct AdjPlan {
+// Layout of an adjoint workspace: the channel table, the reduced gradients,
+// the first step of the segment being swept, then per channel its planes.
+// Writes each channel's offsets into chans[0 .. n_ch) when chans is not null
+// (no allocation: the lb_adjoint_begin_noalloc path uses it too).
+struct AdjLayout {
     size_t total = 0, off_table = 0, off_out = 0, off_t0 = 0;
-    std::vector<AdjChan> chans;
 };
 
-AdjPlan make_adj_plan(const lb_handle *h, int seg_len)
+AdjLayout adj_layout(const lb_handle *h, int seg_len, AdjChan *chans)
 {
     const size_t R = lattice_bytes(h->prec);
-    AdjPlan P;
+    AdjLayout P;
     size_t off = 0;
     P.off_table = off;
     off = align_up(off + (size_t)h->n_ch * sizeof(AdjChan), 256);
     P.off_out = off;
     off = align_up(off + (size_t)h->n_ch * 4 * sizeof(double), 256);
-    P.off_t0 = off;  // first step of the segment being swept
+    P.off_t0 = off;
     off = align_up(off + sizeof(int64_t), 256);
-    P.chans.resize(h->n_ch);
     for (int ci = 0; ci < h->n_ch; ++ci) {
         const ChanDev &c = h->plan.chans[ci];
         const size_t plane = (size_t)c.np * R;
-        AdjChan &a = P.chans[ci];
+        AdjChan a{};
         a.off_sbar_ring = (int64_t)off;
         off = align_up(off + (size_t)c.n_hist * plane, 256);
         a.off_nbar = (int64_t)off;
@@ -748,6 +787,8 @@ AdjPlan make_adj_plan(const lb_handle *h, int seg_len)
         off = align_up(off + (size_t)seg_len * 10 * plane, 256);
         a.off_dldu = (int64_t)off;
         off = align_up(off + (size_t)seg_len * c.np * sizeof(double), 256);
+        if (chans)
+            chans[ci] = a;
     }
     P.total = off;
     return P;
@@ -894,6 +935,7 @@ lb_status lb_init(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec, vo
         h->n_hist.push_back(ch[i].n_hist);
     }
 
+    h->achans.resize(n_ch);
     default_tiling(h);
     build_tiles(h);
     {
@@ -903,6 +945,12 @@ lb_status lb_init(const lb_channel_desc *ch, int32_t n_ch, lb_precision prec, vo
                 hipSuccess || h->num_cus <= 0) {
             delete h;
             return fail(LB_EDEVICE, "cannot query the compute-unit count");
+        }
+        const hipError_t e = scratch_address(dev, &h->scratch);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(LB_EDEVICE, std::string("device address of the library's array: ") +
+                                        hipGetErrorString(e));
         }
     }
 
@@ -1332,8 +1380,42 @@ size_t lb_adjoint_workspace_bytes(const lb_handle *h, int32_t seg_len)
         g_err = why;
         return 0;
     }
-    return make_adj_plan(h, seg_len).total;
+    return adj_layout(h, seg_len, nullptr).total;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Start a sweep on the adjoint workspace at aws (validated by the caller):
+// lay it out, zero it with a fill kernel, upload the channel table.
+lb_status adjoint_begin_at(lb_handle *h, char *aws, size_t bytes, int seg_len)
+{
+    const AdjLayout P = adj_layout(h, seg_len, h->achans.data());
+    if (bytes < P.total)
+        return fail(LB_ENOMEM, "adjoint workspace too small: need " + std::to_string(P.total));
+    if (h->aws != aws || h->adj_seg_len != seg_len)
+        drop_adj_graphs(h);  // they address the previous workspace
+    h->aws = aws;
+    h->aws_bytes = bytes;
+    h->d_achans = reinterpret_cast<AdjChan *>(h->aws + P.off_table);
+    h->d_adj_out = reinterpret_cast<double *>(h->aws + P.off_out);
+    h->d_adj_t0 = reinterpret_cast<int64_t *>(h->aws + P.off_t0);
+    h->adj_seg_len = seg_len;
+    launch_fill_zero(h->aws, P.total, h->stream);
+    lb_status s = check_launch(h, "adjoint zero fill");
+    if (s != LB_OK)
+        return s;
+    HIP_TRY(h, hipMemcpyAsync(h->d_achans, h->achans.data(), h->achans.size() * sizeof(AdjChan),
+                              hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->adj_next = h->t;
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 lb_status lb_adjoint_begin(lb_handle *h, void *d_aws, size_t bytes, int32_t seg_len)
 {
@@ -1345,27 +1427,25 @@ lb_status lb_adjoint_begin(lb_handle *h, void *d_aws, size_t bytes, int32_t seg_
         return fail(LB_EINVAL, why);
     if (!d_aws || reinterpret_cast<uintptr_t>(d_aws) % 256 != 0)
         return fail(LB_ENOMEM, "adjoint workspace must be non-NULL and 256-byte aligned");
-    AdjPlan P = make_adj_plan(h, seg_len);
-    if (bytes < P.total)
-        return fail(LB_ENOMEM, "adjoint workspace too small: need " + std::to_string(P.total));
-    if (h->aws != static_cast<char *>(d_aws) || h->adj_seg_len != seg_len)
-        drop_adj_graphs(h);  // they address the previous workspace
-    h->aws = static_cast<char *>(d_aws);
-    h->aws_bytes = bytes;
-    h->achans = P.chans;
-    h->d_achans = reinterpret_cast<AdjChan *>(h->aws + P.off_table);
-    h->d_adj_out = reinterpret_cast<double *>(h->aws + P.off_out);
-    h->d_adj_t0 = reinterpret_cast<int64_t *>(h->aws + P.off_t0);
-    h->adj_seg_len = seg_len;
-    launch_fill_zero(h->aws, P.total, h->stream);
-    s = check_launch(h, "adjoint zero fill");
+    return adjoint_begin_at(h, static_cast<char *>(d_aws), bytes, seg_len);
+}
+
+lb_status lb_adjoint_begin_noalloc(lb_handle *h, int32_t seg_len)
+{
+    lb_status s = usable(h);
     if (s != LB_OK)
         return s;
-    HIP_TRY(h, hipMemcpyAsync(h->d_achans, h->achans.data(), h->achans.size() * sizeof(AdjChan),
-                              hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
-    h->adj_next = h->t;
-    return LB_OK;
+    std::string why = adjoint_unsupported(h, seg_len);
+    if (!why.empty())
+        return fail(LB_EINVAL, why);
+    const size_t need = adj_layout(h, seg_len, nullptr).total;
+    if (need > kScratchBytes)
+        return fail(LB_ENOMEM, "adjoint workspace of " + std::to_string(need) +
+                                   " bytes exceeds the library's " +
+                                   std::to_string(kScratchBytes) + "-byte device array");
+    if (!h->scratch)
+        return fail(LB_EDEVICE, "the library's device array has no address on this GPU");
+    return adjoint_begin_at(h, static_cast<char *>(h->scratch), kScratchBytes, seg_len);
 }
 
 lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_dux,
