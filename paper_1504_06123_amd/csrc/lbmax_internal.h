@@ -164,24 +164,31 @@ namespace lbmax {
 // history transpose.
 constexpr int kAdjGroups = 8;
 
-struct alignas(64) AdjChan {
+// The step records, loss gradients and recorded shear rates come in two
+// buffers (by segment parity), so the replay of one segment can fill one
+// while the reverse sweep of the next-later segment reads the other.
+struct alignas(128) AdjChan {
     int64_t off_sbar_ring;  // [n_hist][np] R  adjoint of sigma_xy, row t mod n_hist
     int64_t off_nbar;       // [9][np] R  adjoint of the post-collision populations
     int64_t off_dbar;       // [9][np] R  adjoint of the pulled populations
     int64_t off_fbar;       // [np] R     adjoint of the force f_x
     int64_t off_part;       // [kAdjGroups][2][np] double  history-transpose partial sums
     int64_t off_acc;        // [4][np] double  per-node parameter gradients
-    int64_t off_rec;        // [seg_len][10][np] R  n*(t-1) (9 planes), sigma_xy^{t-1}
-    int64_t off_dldu;       // [seg_len][np] double  dL/du_x of each step
+    int64_t off_rec[2];     // [seg_len][10][np] R  n*(t-1) (9 planes), sigma_xy^{t-1}
+    int64_t off_dldu[2];    // [seg_len][np] double  dL/du_x of each step
+    int64_t off_recs[2];    // [seg_len][np] RH  shear rate s_t pushed at each step
 };
 
 // The adjoint kernels of step t = *t0 + slot (t0 in device memory, so one
-// captured sweep serves every segment of the same length).
-void launch_adj_a(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
-                  int n_tiles, char *aws, const AdjChan *achans, const int64_t *t0, int slot,
+// captured sweep serves every segment of the same length) on record buffer
+// buf.  They read the forward state only through the records and a snapshot
+// of the channel table (chans), never the workspace, so the next replay may
+// run beside them.
+void launch_adj_a(int prec, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
+                  char *aws, const AdjChan *achans, const int64_t *t0, int slot, int buf,
                   hipStream_t st);
-void launch_adj_b(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles,
-                  int n_tiles, char *aws, const AdjChan *achans, const int64_t *t0, int slot,
+void launch_adj_b(int prec, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
+                  char *aws, const AdjChan *achans, const int64_t *t0, int slot, int buf,
                   hipStream_t st);
 void launch_store_i64(int64_t *p, int64_t v, hipStream_t st);
 void launch_adj_reduce(const ChanDev *chans, int n_ch, char *aws, const AdjChan *achans,

@@ -2802,10 +2802,10 @@ constexpr int kAdjRanges = kAdjGroups * kAdjChunks;
 
 // Adjoint of the pushed shear rate at node y (the history transpose of step
 // t combined over the kAdjGroups partial sums in group order) and the two
-// sums themselves.
+// sums themselves; s_t from the step's record (recs: the segment slot's row).
 template <typename RH>
-__device__ __forceinline__ double adj_sbar(const char *ws, const ChanDev *c, const double *part,
-                                           int64_t t, int y, double &S0, double &S1, double &s)
+__device__ __forceinline__ double adj_sbar(const RH *recs, const ChanDev *c, const double *part,
+                                           int y, double &S0, double &S1, double &s)
 {
     const size_t np = (size_t)c->np;
     S0 = 0.0;
@@ -2815,18 +2815,17 @@ __device__ __forceinline__ double adj_sbar(const char *ws, const ChanDev *c, con
         S0 += part[(size_t)(2 * g) * np + y];
         S1 += part[(size_t)(2 * g + 1) * np + y];
     }
-    s = (double)reinterpret_cast<const RH *>(ws + c->off_ring_s)[(size_t)(t % c->n_hist) * np + y];
+    s = (double)recs[y];
     return c->g_inf * (S0 - fabs(s) * S1 * c->inv_gc);
 }
 
 template <typename R, typename RH>
-__global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(char *__restrict__ ws,
-                                                              const ChanDev *__restrict__ chans,
+__global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(const ChanDev *__restrict__ chans,
                                                               const NodeTile *__restrict__ tiles,
                                                               char *__restrict__ aws,
                                                               const AdjChan *__restrict__ achans,
                                                               const int64_t *__restrict__ t0,
-                                                              int slot)
+                                                              int slot, int buf)
 {
     const int64_t t = *t0 + slot;
     __shared__ double part[2][kAdjChunks][kAdjNodes];
@@ -2875,7 +2874,7 @@ __global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(char *__restri
     const int j0 = (int)(((int64_t)H * rg + kAdjRanges - 1) / kAdjRanges);
     const int j1 = (int)(((int64_t)H * (rg + 1) + kAdjRanges - 1) / kAdjRanges);
     if (own && j0 < j1) {
-        s = (R)reinterpret_cast<const RH *>(ws + c->off_ring_s)[(size_t)p * np + y];
+        s = (R)reinterpret_cast<const RH *>(aws + a->off_recs[buf])[(size_t)slot * np + y];
         rate = c->inv_tau + c->inv_gc * (double)fabs(s);
         const double q = exp(-rate);
         double e = exp(-(double)j0 * rate);
@@ -2926,14 +2925,14 @@ __global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(char *__restri
 }
 
 template <typename R, typename RH>
-__global__ __launch_bounds__(kBlock) void k_adj_b(char *__restrict__ ws,
-                                                  const ChanDev *__restrict__ chans,
+__global__ __launch_bounds__(kBlock) void k_adj_b(const ChanDev *__restrict__ chans,
                                                   const NodeTile *__restrict__ tiles,
                                                   char *__restrict__ aws,
                                                   const AdjChan *__restrict__ achans,
-                                                  const int64_t *__restrict__ t0, int slot)
+                                                  const int64_t *__restrict__ t0, int slot,
+                                                  int buf)
 {
-    const int64_t t = *t0 + slot;
+    (void)t0;
     const NodeTile tl = tiles[blockIdx.x];
     const ChanDev *c = chans + tl.ch;
     const AdjChan *a = achans + tl.ch;
@@ -2942,7 +2941,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(char *__restrict__ ws,
     if (y >= ly)
         return;
     const size_t np = (size_t)c->np;
-    const R *rec = reinterpret_cast<const R *>(aws + a->off_rec) + (size_t)slot * 10 * np;
+    const R *rec = reinterpret_cast<const R *>(aws + a->off_rec[buf]) + (size_t)slot * 10 * np;
+    const RH *recs = reinterpret_cast<const RH *>(aws + a->off_recs[buf]) + (size_t)slot * np;
     const R *sig = rec + 9 * np;
 
     // forward quantities of the step, in the order and arithmetic of k_lb
@@ -2989,12 +2989,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(char *__restrict__ ws,
         fx_b += A[q] * w * pf * (R(3) * (cx - ux) + R(9) * cu * cx);
     }
     // the loss and the velocity-gradient transpose
-    ux_b += (R)reinterpret_cast<const double *>(aws + a->off_dldu)[(size_t)slot * np + y];
+    ux_b += (R)reinterpret_cast<const double *>(aws + a->off_dldu[buf])[(size_t)slot * np + y];
     const double *part = reinterpret_cast<const double *>(aws + a->off_part);
     double *acc = reinterpret_cast<double *>(aws + a->off_acc);
     for (int yy = max(0, y - 1); yy <= min(ly - 1, y + 1); ++yy) {
         double S0, S1, s;
-        const R sbar = (R)adj_sbar<RH>(ws, c, part, t, yy, S0, S1, s);
+        const R sbar = (R)adj_sbar<RH>(recs, c, part, yy, S0, S1, s);
         ux_b += coef_grad<R>(yy, y, ly) * sbar;
         if (yy == y) {
             // parameter terms of the history transpose at this node
@@ -3049,22 +3049,22 @@ __global__ void k_set_params(ChanDev *chans, int ch, double g_inf, double tau_m,
     }
 }
 
-void launch_adj_a(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
-                  char *aws, const AdjChan *achans, const int64_t *t0, int slot, hipStream_t st)
+void launch_adj_a(int prec, const ChanDev *chans, const NodeTile *tiles, int n_tiles, char *aws,
+                  const AdjChan *achans, const int64_t *t0, int slot, int buf, hipStream_t st)
 {
     // workgroups of kAdjNodes nodes x kAdjChunks age ranges: kBlock / kAdjNodes node
     // groups per node tile, kAdjGroups parts of the window per node group
     LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_a<P, H>),
                                            dim3(n_tiles * (kBlock / kAdjNodes) * kAdjGroups),
-                                           dim3(kAdjNodes * kAdjChunks), 0, st, ws, chans, tiles,
-                                           aws, achans, t0, slot));
+                                           dim3(kAdjNodes * kAdjChunks), 0, st, chans, tiles,
+                                           aws, achans, t0, slot, buf));
 }
 
-void launch_adj_b(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
-                  char *aws, const AdjChan *achans, const int64_t *t0, int slot, hipStream_t st)
+void launch_adj_b(int prec, const ChanDev *chans, const NodeTile *tiles, int n_tiles, char *aws,
+                  const AdjChan *achans, const int64_t *t0, int slot, int buf, hipStream_t st)
 {
     LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_b<P, H>), dim3(n_tiles), dim3(kBlock), 0, st,
-                                           ws, chans, tiles, aws, achans, t0, slot));
+                                           chans, tiles, aws, achans, t0, slot, buf));
 }
 
 __global__ void k_store_i64(int64_t *p, int64_t v)

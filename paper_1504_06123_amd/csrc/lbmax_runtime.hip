@@ -340,9 +340,17 @@ struct lb_handle {
     double *d_adj_out = nullptr;
     std::vector<AdjChan> achans;  // n_ch entries from lb_init on
     void *scratch = nullptr;      // the library's device array on this handle's GPU
-    int64_t *d_adj_t0 = nullptr;
+    int64_t *d_adj_t0 = nullptr;     // [2]: first step of the segment in each record buffer
+    ChanDev *d_adj_snap = nullptr;   // [2][n_ch]: channel table of the segment in each buffer
+    // the reverse sweeps run on their own stream, beside the next segment's
+    // replay on the handle's stream; events order the two
+    hipStream_t adj_stream = nullptr;
+    hipEvent_t adj_ev_replay = nullptr;
+    hipEvent_t adj_ev_sweep[2] = {nullptr, nullptr};
+    bool adj_sweep_pending[2] = {false, false};
+    int adj_segments = 0;            // segments swept since lb_adjoint_begin
     // captured reverse sweeps by segment length (for this adjoint workspace)
-    std::vector<std::pair<int, hipGraphExec_t>> adj_execs;
+    std::vector<std::pair<int, hipGraphExec_t>> adj_execs;  // key: 2 * n_steps + buffer
     int adj_seg_len = 0;
     int64_t adj_next = -1;  // the next segment must end at this step (-1: no sweep)
     // timing: event pairs recorded around launches, resolved on demand
@@ -749,16 +757,17 @@ size_t state_size(const lb_handle *h)
 // Adjoint sweep
 // ---------------------------------------------------------------------------
 // Layout of an adjoint workspace: the channel table, the reduced gradients,
-// the first step of the segment being swept, then per channel its planes.
-// Writes each channel's offsets into chans[0 .. n_ch) when chans is not null
-// (no allocation: the lb_adjoint_begin_noalloc path uses it too).
+// the first step of the segment being swept (per record buffer), a snapshot
+// of the forward channel table (per record buffer), then per channel its
+// planes.  Writes each channel's offsets into chans[0 .. n_ch) when chans is
+// not null (no allocation: the lb_adjoint_begin_noalloc path uses it too).
 struct AdjLayout {
-    size_t total = 0, off_table = 0, off_out = 0, off_t0 = 0;
+    size_t total = 0, off_table = 0, off_out = 0, off_t0 = 0, off_snap = 0;
 };
 
 AdjLayout adj_layout(const lb_handle *h, int seg_len, AdjChan *chans)
 {
-    const size_t R = lattice_bytes(h->prec);
+    const size_t R = lattice_bytes(h->prec), RH = history_bytes(h->prec);
     AdjLayout P;
     size_t off = 0;
     P.off_table = off;
@@ -766,7 +775,9 @@ AdjLayout adj_layout(const lb_handle *h, int seg_len, AdjChan *chans)
     P.off_out = off;
     off = align_up(off + (size_t)h->n_ch * 4 * sizeof(double), 256);
     P.off_t0 = off;
-    off = align_up(off + sizeof(int64_t), 256);
+    off = align_up(off + 2 * sizeof(int64_t), 256);
+    P.off_snap = off;
+    off = align_up(off + 2 * (size_t)h->n_ch * sizeof(ChanDev), 256);
     for (int ci = 0; ci < h->n_ch; ++ci) {
         const ChanDev &c = h->plan.chans[ci];
         const size_t plane = (size_t)c.np * R;
@@ -783,10 +794,14 @@ AdjLayout adj_layout(const lb_handle *h, int seg_len, AdjChan *chans)
         off = align_up(off + (size_t)kAdjGroups * 2 * c.np * sizeof(double), 256);
         a.off_acc = (int64_t)off;
         off = align_up(off + 4 * (size_t)c.np * sizeof(double), 256);
-        a.off_rec = (int64_t)off;
-        off = align_up(off + (size_t)seg_len * 10 * plane, 256);
-        a.off_dldu = (int64_t)off;
-        off = align_up(off + (size_t)seg_len * c.np * sizeof(double), 256);
+        for (int b = 0; b < 2; ++b) {
+            a.off_rec[b] = (int64_t)off;
+            off = align_up(off + (size_t)seg_len * 10 * plane, 256);
+            a.off_dldu[b] = (int64_t)off;
+            off = align_up(off + (size_t)seg_len * c.np * sizeof(double), 256);
+            a.off_recs[b] = (int64_t)off;
+            off = align_up(off + (size_t)seg_len * c.np * RH, 256);
+        }
         if (chans)
             chans[ci] = a;
     }
@@ -831,27 +846,29 @@ void drop_adj_graphs(lb_handle *h)
     h->adj_execs.clear();
 }
 
-// The reverse sweep of n_steps steps (k_adj_a then k_adj_b for slots
-// n_steps-1 .. 0), captured once per length and replayed for every segment.
-// The graph holds the workspace, channel-table and node-tile pointers and the
-// node-tile count (fixed for the handle's life: node tiles depend on the
-// channels only) and the adjoint workspace (lb_adjoint_begin drops the
-// graphs when it changes).
-lb_status adj_sweep_graph(lb_handle *h, int n_steps, hipGraphExec_t *out)
+// The reverse sweep of n_steps steps on record buffer buf (k_adj_a then
+// k_adj_b for slots n_steps-1 .. 0), captured once per length and buffer and
+// replayed for every segment.  The graph holds the adjoint workspace's
+// addresses and the node-tile pointer and count (fixed for the handle's life:
+// node tiles depend on the channels only); lb_adjoint_begin drops the graphs
+// when the adjoint workspace or segment length changes.
+lb_status adj_sweep_graph(lb_handle *h, int n_steps, int buf, hipGraphExec_t *out)
 {
+    const int key = 2 * n_steps + buf;
     for (auto &e : h->adj_execs)
-        if (e.first == n_steps) {
+        if (e.first == key) {
             *out = e.second;
             return LB_OK;
         }
     if (!h->cap_stream)
         HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    const ChanDev *snap = h->d_adj_snap + (size_t)buf * h->n_ch;
     for (int k = n_steps - 1; k >= 0; --k) {
-        launch_adj_a(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
-                     h->d_achans, h->d_adj_t0, k, h->cap_stream);
-        launch_adj_b(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
-                     h->d_achans, h->d_adj_t0, k, h->cap_stream);
+        launch_adj_a(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans,
+                     h->d_adj_t0 + buf, k, buf, h->cap_stream);
+        launch_adj_b(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans,
+                     h->d_adj_t0 + buf, k, buf, h->cap_stream);
     }
     const hipError_t cap = hipGetLastError();
     hipGraph_t g = nullptr;
@@ -870,8 +887,17 @@ lb_status adj_sweep_graph(lb_handle *h, int n_steps, hipGraphExec_t *out)
         h->poisoned = true;
         return fail(LB_EDEVICE, std::string("adjoint sweep graph: ") + hipGetErrorString(inst));
     }
-    h->adj_execs.push_back({n_steps, exec});
+    h->adj_execs.push_back({key, exec});
     *out = exec;
+    return LB_OK;
+}
+
+// Wait for every reverse sweep enqueued on the adjoint stream.
+lb_status adj_drain(lb_handle *h)
+{
+    if (h->adj_stream)
+        HIP_TRY(h, hipStreamSynchronize(h->adj_stream));
+    h->adj_sweep_pending[0] = h->adj_sweep_pending[1] = false;
     return LB_OK;
 }
 
@@ -1391,9 +1417,19 @@ namespace {
 // lay it out, zero it with a fill kernel, upload the channel table.
 lb_status adjoint_begin_at(lb_handle *h, char *aws, size_t bytes, int seg_len)
 {
+    const size_t need = adj_layout(h, seg_len, nullptr).total;
+    if (bytes < need)
+        return fail(LB_ENOMEM, "adjoint workspace too small: need " + std::to_string(need));
+    lb_status s = adj_drain(h);  // an earlier sweep still reading the workspace
+    if (s != LB_OK)
+        return s;
+    if (!h->adj_stream) {
+        HIP_TRY(h, hipStreamCreateWithFlags(&h->adj_stream, hipStreamNonBlocking));
+        HIP_TRY(h, hipEventCreateWithFlags(&h->adj_ev_replay, hipEventDisableTiming));
+        for (int b = 0; b < 2; ++b)
+            HIP_TRY(h, hipEventCreateWithFlags(&h->adj_ev_sweep[b], hipEventDisableTiming));
+    }
     const AdjLayout P = adj_layout(h, seg_len, h->achans.data());
-    if (bytes < P.total)
-        return fail(LB_ENOMEM, "adjoint workspace too small: need " + std::to_string(P.total));
     if (h->aws != aws || h->adj_seg_len != seg_len)
         drop_adj_graphs(h);  // they address the previous workspace
     h->aws = aws;
@@ -1401,9 +1437,11 @@ lb_status adjoint_begin_at(lb_handle *h, char *aws, size_t bytes, int seg_len)
     h->d_achans = reinterpret_cast<AdjChan *>(h->aws + P.off_table);
     h->d_adj_out = reinterpret_cast<double *>(h->aws + P.off_out);
     h->d_adj_t0 = reinterpret_cast<int64_t *>(h->aws + P.off_t0);
+    h->d_adj_snap = reinterpret_cast<ChanDev *>(h->aws + P.off_snap);
     h->adj_seg_len = seg_len;
+    h->adj_segments = 0;
     launch_fill_zero(h->aws, P.total, h->stream);
-    lb_status s = check_launch(h, "adjoint zero fill");
+    s = check_launch(h, "adjoint zero fill");
     if (s != LB_OK)
         return s;
     HIP_TRY(h, hipMemcpyAsync(h->d_achans, h->achans.data(), h->achans.size() * sizeof(AdjChan),
@@ -1470,12 +1508,17 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
         return fail(LB_ESTATE, "segment does not end where the previous one began; handle "
                                "poisoned");
     }
-    // replay the segment; its lattice steps record their input populations
-    // and stress into the step records
+    // Record buffer of this segment; the sweep two segments back read it last.
+    const int buf = h->adj_segments & 1;
+    if (h->adj_sweep_pending[buf])
+        HIP_TRY(h, hipStreamWaitEvent(h->stream, h->adj_ev_sweep[buf], 0));
+    // Replay the segment on the handle's stream (beside the sweep of the
+    // later segment on the adjoint stream); its lattice steps record their
+    // input populations and stress into the step records.
     auto set_record = [&](bool on) -> lb_status {
         for (int ci = 0; ci < h->n_ch; ++ci) {
             ChanDev &c = h->plan.chans[ci];
-            c.rec = on ? (int64_t)(uintptr_t)(h->aws + h->achans[ci].off_rec) : 0;
+            c.rec = on ? (int64_t)(uintptr_t)(h->aws + h->achans[ci].off_rec[buf]) : 0;
             c.rec_t0 = on ? t0 : 0;
         }
         HIP_TRY(h, hipMemcpyAsync(h->d_chans, h->plan.chans.data(),
@@ -1494,47 +1537,71 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
         return s;
     if (s2 != LB_OK)
         return s2;
-    // dL/du_x of the segment: host [n_steps][sum of nodes]
+    // The segment's shear rates (ring rows t0 .. t0 + n_steps - 1, wrapping),
+    // dL/du_x (host [n_steps][sum of nodes]) and the channel table into the
+    // buffer, so the sweep reads nothing the next replay overwrites.
+    const size_t RH = history_bytes(h->prec);
     size_t total_nodes = 0;
     for (const ChanDev &c : h->plan.chans)
         total_nodes += (size_t)c.n;
     size_t col = 0;
     for (int ci = 0; ci < h->n_ch; ++ci) {
         const ChanDev &c = h->plan.chans[ci];
-        HIP_TRY(h, hipMemcpy2DAsync(h->aws + h->achans[ci].off_dldu, (size_t)c.np * sizeof(double),
+        const AdjChan &a = h->achans[ci];
+        const size_t rowb = (size_t)c.np * RH;
+        const int H = c.n_hist;
+        const int first = (int)(t0 % H);
+        const int run1 = std::min(n_steps, H - first);
+        HIP_TRY(h, hipMemcpyAsync(h->aws + a.off_recs[buf], h->ws + c.off_ring_s + first * rowb,
+                                  (size_t)run1 * rowb, hipMemcpyDeviceToDevice, h->stream));
+        if (run1 < n_steps)
+            HIP_TRY(h, hipMemcpyAsync(h->aws + a.off_recs[buf] + (size_t)run1 * rowb,
+                                      h->ws + c.off_ring_s, (size_t)(n_steps - run1) * rowb,
+                                      hipMemcpyDeviceToDevice, h->stream));
+        HIP_TRY(h, hipMemcpy2DAsync(h->aws + a.off_dldu[buf], (size_t)c.np * sizeof(double),
                                     dL_dux + col, total_nodes * sizeof(double),
                                     (size_t)c.n * sizeof(double), (size_t)n_steps,
                                     hipMemcpyHostToDevice, h->stream));
         col += (size_t)c.n;
     }
-    // reverse sweep over the segment: one captured graph per segment length,
-    // the segment's first step passed in device memory
-    launch_store_i64(h->d_adj_t0, t0, h->stream);
+    ChanDev *snap = h->d_adj_snap + (size_t)buf * h->n_ch;
+    HIP_TRY(h, hipMemcpyAsync(snap, h->d_chans, (size_t)h->n_ch * sizeof(ChanDev),
+                              hipMemcpyDeviceToDevice, h->stream));
+    launch_store_i64(h->d_adj_t0 + buf, t0, h->stream);
     s = check_launch(h, "adjoint segment start");
     if (s != LB_OK)
         return s;
+    HIP_TRY(h, hipEventRecord(h->adj_ev_replay, h->stream));
+    // Reverse sweep of the segment on the adjoint stream, after the replay:
+    // one captured graph per segment length and buffer, the segment's first
+    // step in device memory.
+    HIP_TRY(h, hipStreamWaitEvent(h->adj_stream, h->adj_ev_replay, 0));
     if (n_steps <= kAdjGraphMaxSteps) {
         hipGraphExec_t exec = nullptr;
-        s = adj_sweep_graph(h, n_steps, &exec);
+        s = adj_sweep_graph(h, n_steps, buf, &exec);
         if (s != LB_OK)
             return s;
-        HIP_TRY(h, hipGraphLaunch(exec, h->stream));
+        HIP_TRY(h, hipGraphLaunch(exec, h->adj_stream));
     } else {
         // longer segments launch directly (a graph of 2 n_steps nodes would
         // cost more to build than it saves)
         for (int k = n_steps - 1; k >= 0; --k) {
-            launch_adj_a(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
-                         h->d_achans, h->d_adj_t0, k, h->stream);
-            launch_adj_b(h->pc, h->ws, h->d_chans, h->d_node_tiles, h->n_node_tiles, h->aws,
-                         h->d_achans, h->d_adj_t0, k, h->stream);
+            launch_adj_a(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans,
+                         h->d_adj_t0 + buf, k, buf, h->adj_stream);
+            launch_adj_b(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans,
+                         h->d_adj_t0 + buf, k, buf, h->adj_stream);
             s = check_launch(h, "adjoint step");
             if (s != LB_OK)
                 return s;
         }
     }
-    // the host buffer may be reused once this returns
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipEventRecord(h->adj_ev_sweep[buf], h->adj_stream));
+    h->adj_sweep_pending[buf] = true;
+    // The host buffer may be reused once this returns: wait for the replay
+    // and the copies (the sweep runs on).
+    HIP_TRY(h, hipEventSynchronize(h->adj_ev_replay));
     h->adj_next = t0;
+    h->adj_segments += 1;
     return LB_OK;
 }
 
@@ -1547,13 +1614,17 @@ lb_status lb_adjoint_end(lb_handle *h, double *dL_dtheta)
         return fail(LB_ESTATE, "no adjoint sweep in progress");
     if (!dL_dtheta)
         return fail(LB_EINVAL, "dL_dtheta is NULL");
-    launch_adj_reduce(h->d_chans, h->n_ch, h->aws, h->d_achans, h->d_adj_out, h->stream);
+    // after every sweep, on the adjoint stream
+    hipStream_t st = h->adj_stream ? h->adj_stream : h->stream;
+    launch_adj_reduce(h->d_chans, h->n_ch, h->aws, h->d_achans, h->d_adj_out, st);
     s = check_launch(h, "adjoint reduce");
     if (s != LB_OK)
         return s;
     HIP_TRY(h, hipMemcpyAsync(dL_dtheta, h->d_adj_out, (size_t)h->n_ch * 4 * sizeof(double),
-                              hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+                              hipMemcpyDeviceToHost, st));
+    s = adj_drain(h);
+    if (s != LB_OK)
+        return s;
     h->adj_next = -1;
     return LB_OK;
 }
@@ -1567,6 +1638,15 @@ lb_status lb_destroy(lb_handle *h)
     if (h->graph)
         (void)hipGraphDestroy(h->graph);
     drop_adj_graphs(h);
+    if (h->adj_stream) {
+        (void)hipStreamSynchronize(h->adj_stream);
+        (void)hipStreamDestroy(h->adj_stream);
+    }
+    if (h->adj_ev_replay)
+        (void)hipEventDestroy(h->adj_ev_replay);
+    for (int b = 0; b < 2; ++b)
+        if (h->adj_ev_sweep[b])
+            (void)hipEventDestroy(h->adj_ev_sweep[b]);
     if (h->cap_stream)
         (void)hipStreamDestroy(h->cap_stream);
     for (int w = 0; w < 3; ++w)
