@@ -308,9 +308,10 @@ int32_t lb_get_block(const lb_handle *h);
  * barriers in place of kernel boundaries.  If moreover the handle is LB_F32
  * and every channel is unidirectional and takes the simple-shear integral law
  * (law == 0, finger == 0) with the body-force coupling (paper_coupling == 0),
- * the workgroup keeps the channel's stored populations, moments and stress
- * in LDS and the history rows pushed since the pass in registers (the
- * stencils then read no global memory).  mode: 0
+ * the workgroup keeps the channel's populations (rebuilt in FP64 from the
+ * split storage once per node and step), velocity and stress in LDS and the
+ * history rows pushed since the pass in registers (the stencils then read no
+ * global memory).  mode: 0
  * separate launches, 1 fused (the LDS form where it applies; the default), 2
  * fused without the LDS form.  Results are identical in every mode.
  * lb_get_fused returns 0 when the steps are not fused (mode 0, a channel

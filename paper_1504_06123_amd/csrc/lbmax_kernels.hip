@@ -1901,10 +1901,32 @@ __device__ __forceinline__ void hist_regs(const ChanDev *c, const Decay<R> &dec,
     gam_out = gam;
 }
 
+// Remainders r_q = (float)(out_q - n^eq_q) of a collision, as
+// split_remainders forms them, and the populations a pull rebuilds from them,
+// n^eq_q + r_q (the same operations as pull_split_one, so bit for bit what a
+// neighbour pulling from split storage obtains).
+template <typename P>
+__device__ __forceinline__ void split_and_rebuild(const P (&out)[9], P ux, P uy, P drho,
+                                                  float (&r)[9], P (&full)[9])
+{
+#pragma clang fp contract(off)
+    const P uu = ux * ux + uy * uy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const P cu = P(QX[q]) * ux + P(QY[q]) * uy;
+        const P e = eq_dev<P>(qweight<P>(q), cu, drho, uu);
+        r[q] = (float)(out[q] - e);
+        full[q] = e + (P)r[q];
+    }
+}
+
+// LDS of the span: the channel's pulled-from populations as FP64 deviations
+// rebuilt from split storage ([9][K]), its velocity ([2][K]) and stress
+// ([2][K]); pulls read them without arithmetic.
 template <typename P, typename R, bool HAS_R>
 __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const ChanDev *c,
-                                               int64_t t0s, int m0, int count, float *s_pop,
-                                               P *s_mom, P *s_sig)
+                                               int64_t t0s, int m0, int count, P *s_full,
+                                               P *s_vel, P *s_sig)
 {
     constexpr int K = kFuseThreads;  // LDS plane stride
     const int n = threadIdx.x;
@@ -1926,12 +1948,11 @@ __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const Chan
     if (own) {
         const float *src = pop + ((t0s + 1) & 1) * 9 * np;
         const P *msrc = mom + ((t0s + 1) & 1) * 3 * np;
+        P full[9];
+        own_split<P>(n, src, msrc, np, full);
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-            s_pop[q * K + n] = src[q * np + n];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-            s_mom[i * K + n] = msrc[i * np + n];
+            s_full[q * K + n] = full[q];
         s_sig[n] = sig[n];
         s_sig[K + n] = sig[np + n];
 #pragma unroll
@@ -1950,37 +1971,29 @@ __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const Chan
         const int64_t t = t0s + k;
         const int m = m0 + k;
         double A = 0.0, B = 0.0;
-        float r[9];
-        P ux = P(0), uy = P(0), drho = P(0);
+        P full[9];
+        P ux = P(0), uy = P(0);
         if (own) {
+            A = blk[m * np + n];  // issued before the lattice phase
+            B = blk[(kPlaneB + m) * np + n];
             if (c->rec) {
                 P *rec = reinterpret_cast<P *>(c->rec) + (size_t)(t - c->rec_t0) * 10 * np;
-                P od[9];
-                own_split<P>(n, s_pop, s_mom, K, od);
 #pragma unroll
                 for (int q = 0; q < 9; ++q)
-                    rec[q * np + n] = od[q];
+                    rec[q * np + n] = s_full[q * K + n];
                 rec[9 * np + n] = s_sig[n];
             }
-            P d[9], out[9];
-            lb_pull_split<P>(c, n, s_pop, s_mom, K, d);
+            P d[9], out[9], drho;
+            lb_pull<P>(c, n, s_full, K, d);
             lb_collide_body<P>(c, n, d, s_sig, K, out, ux, uy, drho);
-            split_remainders<P>(out, ux, uy, drho, r);
-        }
-        __syncthreads();  // every stencil read of the old state and stress is done
-        if (own) {
-            A = blk[m * np + n];
-            B = blk[(kPlaneB + m) * np + n];
+            float r[9];
+            split_and_rebuild<P>(out, ux, uy, drho, r, full);
+            // the workspace state of this step (nothing here is read in the span)
             float *dst = pop + (t & 1) * 9 * np;
             P *mdst = mom + (t & 1) * 3 * np;
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                s_pop[q * K + n] = r[q];
+            for (int q = 0; q < 9; ++q)
                 dst[q * np + n] = r[q];
-            }
-            s_mom[n] = drho;
-            s_mom[K + n] = ux;
-            s_mom[2 * K + n] = uy;
             mdst[n] = drho;
             mdst[np + n] = ux;
             mdst[2 * np + n] = uy;
@@ -1988,12 +2001,19 @@ __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const Chan
             vel[np + n] = uy;
             rhop[n] = drho;
         }
+        __syncthreads();  // every stencil read of the old state and stress is done
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                s_full[q * K + n] = full[q];
+            s_vel[n] = ux;
+            s_vel[K + n] = uy;
+        }
         __syncthreads();  // this step's velocities are in LDS
         if (own) {
             const int y = n / c->lx, x = n - y * c->lx;
             P kxx, kxy, kyx, kyy;
-            velocity_gradient<P>(s_mom + K, s_mom + 2 * K, c->lx, c->ly, x, y, kxx, kxy, kyx,
-                                 kyy);
+            velocity_gradient<P>(s_vel, s_vel + K, c->lx, c->ly, x, y, kxx, kxy, kyx, kyy);
             const R s_new = (R)kxy;
             const size_t o = (size_t)(t % H) * np + n;
             ring_s[o] = s_new;
@@ -2028,14 +2048,14 @@ __global__ __launch_bounds__(kFuseThreads) void k_fused_steps_lds(
     int trel, int m0, int count)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    P *s_mom = reinterpret_cast<P *>(lds_raw);             // [3][kFuseThreads]
-    P *s_sig = s_mom + 3 * kFuseThreads;                   // [2][kFuseThreads]
-    float *s_pop = reinterpret_cast<float *>(s_sig + 2 * kFuseThreads);  // [9][kFuseThreads]
+    P *s_full = reinterpret_cast<P *>(lds_raw);  // [9][kFuseThreads]
+    P *s_vel = s_full + 9 * kFuseThreads;        // [2][kFuseThreads]
+    P *s_sig = s_vel + 2 * kFuseThreads;         // [2][kFuseThreads]
     const ChanDev *c = chans + blockIdx.x;
     const int64_t t0s = *tcount + trel;
     // unidirectional channels only (|gamma_dot| = |s|: one row per entry in
     // registers); the host selects this form only then
-    fused_span_lds<P, R, false>(ws, c, t0s, m0, count, s_pop, s_mom, s_sig);
+    fused_span_lds<P, R, false>(ws, c, t0s, m0, count, s_full, s_vel, s_sig);
 }
 
 // ---------------------------------------------------------------------------
@@ -2679,10 +2699,10 @@ void launch_fused_steps(int prec, bool lds, char *ws, const ChanDev *chans, int 
                            fused_lds_bytes(prec), st, ws, chans, tcount, trel, m0, count);
 }
 
-// Moments and stress (FP64, 3 + 2 planes) and remainders (FP32, 9 planes).
+// Rebuilt populations, velocity and stress: 13 FP64 planes.
 size_t fused_lds_bytes(int prec)
 {
-    return prec == 1 ? (size_t)kFuseThreads * (5 * sizeof(double) + 9 * sizeof(float)) : 0;
+    return prec == 1 ? (size_t)kFuseThreads * 13 * sizeof(double) : 0;
 }
 
 int prepare_fused_lds(int prec)
