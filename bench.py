@@ -5,9 +5,9 @@ history kernel and the FP64 oracle timed on the host beside it.
 Workload: the large 2D channel, 1024 x 512 nodes, window N_h = 4096, tau =
 1000, g = 5e-6, 1 % seeded velocity perturbation.  Precision of the headline
 number: FP32 populations in split storage (FP32 remainders against the
-equilibrium of FP64 moments), FP32 history ring with FP32 partial window sums
-flushed into FP64, FP64 accumulated strain; the mode with FP64 populations
-is timed beside it.  One step = the whole path for every node:
+equilibrium of FP64 moments), FP32 history ring whose window sums are FP32
+partial sums added into Kahan-compensated FP32 totals, FP64 accumulated
+strain; the mode with FP64 populations is timed beside it.  One step = the whole path for every node:
 pull-stream + collide with the stress-divergence force, velocity gradient,
 history push and the N_h-entry history integral.  The launch shape (steps
 per history pass, lanes, chunks, persistent pass) is chosen by the
@@ -39,14 +39,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-# MI355X published FP32 vector peak (packed FP32: two FMAs per lane and cycle)
+# MI355X published FP32 vector peak: 256 CUs x 4 SIMDs x 64 flops per cycle x
+# 2.4 GHz.  (The library is built without packed FP32 instructions; a plain FP32
+# FMA loop still issues a wave64 FMA every 2.4 to 3.3 cycles per SIMD with 8 to 2
+# waves per SIMD, so this peak, not half of it, bounds the vector arithmetic.)
 FP32_PEAK_TFLOPS = 157.3
-# FP32 vector arithmetic without packed instructions (the library is built without
-# them): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz -- an issue-rate
-# ceiling of this build, reported beside the published roofline.
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # the large 2D channel's own run length
 LARGE_2D_RUN_STEPS = 5000
+# replay length of the step graphs the legs use or tune over; --no-graphs sets it to 0
+GRAPH_LEN = 64
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernels.hip")
 # rocprofv3 counter results for the history pass on this workload (see
@@ -54,17 +55,20 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernel
 # (precision, steps per pass, nodes per lane).  Valid only for the kernel source they
 # were taken from; otherwise reported as null.
 MEASURED = {
-    "source_sha256": "141082364c903bfa3c234e05852445f63ad9f1781a6fa5411450d378d1e3caf6",
-    # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated)
-    "traffic_bytes": {("f32p64", 32, 1): 8396634.33 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32p64", 1, 4): 8410779.95 * 1024 * 2 + 40928.69 * 1024},
-    # SQ_INSTS_VALU x 64 / history entries
-    "valu_instr_per_entry": {("f32p64", 32, 1): 88.38, ("f32p64", 1, 4): 9.97},
-    # the side legs' dominant kernels (profiles/history_variants_large_2d_1024x512.md),
-    # keyed by (leg, steps per pass), same calibration
-    "leg_traffic_bytes": {("grid", 16): 1606549.86 * 1024 * 2 + 211968.0 * 1024,
-                          ("full_tensor", 16): 33557797.84 * 1024 * 2 + 213072.0 * 1024,
-                          ("strain_damping", 32): 8395958.26 * 1024 * 2 + 266240.0 * 1024},
+    "source_sha256": "126409aa93232d033174dabcc1cd24e81370c82d597378a90154041ddb3dc1d5",
+    # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated),
+    # from `bench.py --counter-run <leg>` under rocprofv3 --pmc
+    "traffic_bytes": {("f32", 32, 1): 8394760.0 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32", 1, 4): 8408870.0 * 1024 * 2 + 40872.0 * 1024,
+                      ("f32p64", 32, 1): 8394910.0 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32p64", 1, 4): 8408720.0 * 1024 * 2 + 40886.2 * 1024},
+    # SQ_INSTS_VALU x 64 / history entries (both modes run the same pass kernels)
+    "valu_instr_per_entry": {("f32", 32, 1): 90.78, ("f32p64", 32, 1): 90.78,
+                             ("f32", 1, 4): 11.49, ("f32p64", 1, 4): 11.49},
+    # the side legs' dominant kernels, keyed by (leg, steps per pass), same calibration
+    "leg_traffic_bytes": {("grid", 16): 1606570.0 * 1024 * 2 + 211968.0 * 1024,
+                          ("full_tensor", 16): 33558000.0 * 1024 * 2 + 213072.0 * 1024,
+                          ("strain_damping", 32): 8395920.0 * 1024 * 2 + 266240.0 * 1024},
 }
 
 
@@ -74,6 +78,11 @@ def measured(kind: str, key):
         if hashlib.sha256(f.read()).hexdigest() != MEASURED["source_sha256"]:
             return None
     return MEASURED[kind].get(key)
+
+
+def graph_lens():
+    """Graph replay lengths the autotuner tries (0: plain launches)."""
+    return (0, GRAPH_LEN) if GRAPH_LEN else (0,)
 
 
 def log(msg):
@@ -149,12 +158,12 @@ def bench_large_2d(wl, args, precision: str):
         log(f"bench: {precision}: one-step pass {one_s*1e3:.3f} ms ({gbs1:.0f} GB/s)")
     if args.no_tune:
         cfg = dict(block=args.block, vec=1, chunk_len=1 << 30, persistent=args.persistent,
-                   graph=args.graph)
+                   graph=args.graph if GRAPH_LEN else 0)
         autotune.apply(s, cfg)
     else:
         best = autotune.tune(s, autotune.candidates(s, blocks=(1, 8, 16, 32),
                                                     chunk_lens=(1024, 1 << 30),
-                                                    graphs=(0, 64)),
+                                                    graphs=graph_lens()),
                              min_steps=64)
         cfg = {k: best[k] for k in ("block", "vec", "chunk_len", "persistent", "graph")}
         log(f"bench: tuned {cfg} ({best['ms_per_step']:.4f} ms/step in tuning)")
@@ -183,7 +192,6 @@ def bench_large_2d(wl, args, precision: str):
     gbs = alg_bytes / pass_s / 1e9
     tflops = alg_flops / pass_s / 1e12
     hbm_frac = gbs / HBM_PEAK_GBS
-    alu_frac = tflops / VALU_PEAK_TFLOPS
     log(f"bench: {precision}: {steps} steps in {el:.3f} s ({el/steps*1e3:.4f} ms/step); "
         f"history pass {pass_s*1e3:.3f} ms x {n_pass} ({gbs:.0f} GB/s, {tflops:.1f} TFLOP/s); "
         f"lattice {kt[1][0]/max(kt[1][1],1):.4f} ms; block step "
@@ -195,13 +203,14 @@ def bench_large_2d(wl, args, precision: str):
     if not vpe:
         # Instruction model.  M >= 16: one FMA (or add) per sum and step plus
         # the seven low and 2 M/8 high powers and the per-entry decay, strain
-        # and flush work (the counted 32-step pass has 88).  Shorter blocks
-        # carry the decay factor along the steps: three instructions per step.
-        vpe = 2.25 * M + 16 if M >= 16 else 3.5 * M + 10
+        # and compensated-total work (the counted 32-step pass has 91).  Shorter
+        # blocks carry the decay factor along the steps: three instructions per
+        # step.
+        vpe = 2.25 * M + 19 if M >= 16 else 3.5 * M + 10
     # Cycles each SIMD spends per wave-level VALU instruction, counted at the
-    # nominal 2.4 GHz engine clock; 4 is the wave64 issue interval.  Under
-    # this load the engine runs below 2.4 GHz (rocprofv3 GRBM_GUI_ACTIVE
-    # counts 3.9 to 4.0 real cycles per instruction for the 32-step pass).
+    # nominal 2.4 GHz engine clock.  Under this load the engine runs below
+    # 2.4 GHz (rocprofv3 GRBM_GUI_ACTIVE counts about 3.7 real cycles per
+    # instruction for the 32-step pass, which holds 2 waves per SIMD).
     wave_instr = vpe * entries / 64
     cycles_per_instr = 1024 * 2.4e9 * pass_s / wave_instr
     # The binding published roof: the longer of the algorithmic bytes at the
@@ -218,9 +227,6 @@ def bench_large_2d(wl, args, precision: str):
                  "kernel_avg_ms": pass_s * 1e3, "alg_bytes_per_launch": alg_bytes,
                  "alg_flops_per_launch": alg_flops, "hbm_GBs": gbs, "hbm_frac": hbm_frac,
                  "fp32_TFLOPs": tflops, "fp32_frac": tflops / FP32_PEAK_TFLOPS,
-                 # the issue-rate ceiling of this build (no packed FP32 instructions)
-                 "peak_nonpacked_fp32_TFLOPs": VALU_PEAK_TFLOPS,
-                 "nonpacked_fp32_frac": alu_frac,
                  "valu_instr_per_entry": vpe, "valu_instr_source": vpe_src,
                  "valu_cycles_per_instr_at_2p4ghz": cycles_per_instr})
     return {"el": el, "steps": steps, "cfg": cfg, "roof": roof, "one_step": one_step,
@@ -302,7 +308,7 @@ def bench_grid(steps: int = 256, B: int = 6, C: int = 128, block: int = 16):
     ch = workloads.large_2d().channels[0].replace(hist_blocks=B, hist_block_len=C)
     s = Solver([ch], precision="f32p64")
     s.set_block(block)
-    s.set_graph(64)
+    s.set_graph(GRAPH_LEN)
     s.step(2 * C)
     el, kt = time_steps(s, steps)
     s.close()
@@ -419,7 +425,7 @@ def bench_batched(steps: int = 2000):
     s.step(64)
     best = autotune.tune(s, autotune.candidates(s, blocks=(8, 16, 32),
                                                 chunk_lens=(256, 512, 1024, 2048, 4096),
-                                                graphs=(0, 64)), min_steps=64)
+                                                graphs=graph_lens()), min_steps=64)
     M = best["block"]
     s.step(64)
     el, kt = time_steps(s, max(M, steps // M * M))
@@ -456,8 +462,7 @@ def bench_batched(steps: int = 2000):
                          "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS, "traffic": None,
                          "kernel": f"k_hist_pass + k_combine ({M} steps per pass)",
                          "kernel_avg_ms": pass_s * 1e3, "hbm_GBs": gbs,
-                         "hbm_frac": gbs / HBM_PEAK_GBS,
-                         "nonpacked_fp32_frac": tflops / VALU_PEAK_TFLOPS},
+                         "hbm_frac": gbs / HBM_PEAK_GBS},
             "plain_per_channel_f64": plain, "speedup_vs_plain_f64": batched / plain}
 
 
@@ -484,7 +489,7 @@ def bench_adjoint(repeats: int = 3, oracle_steps: int = 200):
     fw, bw = [], []
     with Solver([ch], precision="f32p64") as s:
         s.set_block(8)
-        s.set_graph(64)
+        s.set_graph(GRAPH_LEN)
         init = s.save_state()
         for _ in range(repeats + 1):      # the first round warms up
             s.load_state(init)
@@ -530,6 +535,53 @@ def bench_adjoint(repeats: int = 3, oracle_steps: int = 200):
             "speedup_vs_oracle_fd": fd_s / (f_s + b_s)}
 
 
+def counter_run(leg: str, copy_mib: int = 4096):
+    """A short plain-launch run for hardware-counter collection (no HIP
+    events, no graphs): `copy` copies `copy_mib` MiB device to device (the
+    calibration of FETCH_SIZE and WRITE_SIZE); the other legs build the
+    channel as their timed leg does, take 32 warm-up steps in the default
+    launch shape (one-step passes), then 4 blocks in the leg's shape."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1504_06123_amd import Solver, autotune
+
+    if leg == "copy":
+        n = copy_mib << 18
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        return {"counter_run": leg, "bytes": n * 4}
+    base = workloads.large_2d().channels[0]
+    prec, block, persistent = "f32p64", 32, True
+    if leg in ("f32", "f32p64"):
+        ch, prec = base, leg
+    elif leg == "grid":
+        ch, block = base.replace(hist_blocks=6, hist_block_len=128), 16
+    elif leg == "full_tensor":
+        ch, block = base.replace(finger=True), 16
+    elif leg == "strain_damping":
+        ch, persistent = base.replace(law="strain_damping"), False
+    else:
+        raise ValueError(f"unknown counter-run leg {leg}")
+    s = Solver([ch], precision=prec)
+    if leg == "grid":
+        s.set_block(block)
+        s.step(2 * 128)
+    else:
+        s.step(32)
+        autotune.apply(s, dict(block=block, vec=1, chunk_len=1 << 30,
+                               persistent=persistent, graph=0))
+    s.step(4 * block)
+    torch.cuda.synchronize()
+    _, ux, _ = s.fields(0)
+    assert np.isfinite(ux).all()
+    steps = s.t
+    s.close()
+    return {"counter_run": leg, "precision": prec, "steps_per_pass": block, "steps": steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -553,7 +605,16 @@ def main():
     ap.add_argument("--no-side-f32p64", dest="side", action="store_false")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (counter calibration)")
+    ap.add_argument("--counter-run", choices=("copy", "f32", "f32p64", "grid", "full_tensor",
+                                              "strain_damping"),
+                    help="a short plain-launch run of one leg for rocprofv3 --pmc")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="plain launches only, in every leg (for rocprofv3 counter runs, "
+                         "which have ended with a host segfault inside stream capture)")
     args = ap.parse_args()
+    if args.no_graphs:
+        global GRAPH_LEN
+        GRAPH_LEN = 0
     if args.gpus != 1:
         print(json.dumps({"error": "liblbmax runs on one GPU per process and bench.py "
                                    "measures one GPU; --gpus must be 1 (sharding across "
@@ -568,6 +629,11 @@ def main():
     if not os.path.exists(_lib.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
+
+    if args.counter_run:
+        print(json.dumps(counter_run(args.counter_run, args.copy_probe_mib or 4096)),
+              flush=True)
+        return
 
     if args.copy_probe_mib:
         n = args.copy_probe_mib << 18  # float32 elements
@@ -634,7 +700,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (populations: FP32 remainders on FP64 moments; history: FP32 ring, "
-                 "FP32 partial sums flushed into FP64; FP64 strain)",
+                 "FP32 partial sums into Kahan-compensated FP32 totals; FP64 strain)",
         "data": "synthetic",
         "config": {"workload": "large 2D channel 1024x512, N_h=4096, tau=1000 steps, "
                                "g=5e-6, 1% seeded velocity perturbation",

@@ -70,8 +70,9 @@ typedef enum {
  *          FP32 rounding from step to step (FP32 deviations n_i - a_i drift:
  *          a velocity that grows by a small amount per step loses part of
  *          each increment to FP32 rounding, coherently).  History ring in
- *          FP32; history sums as FP32 partial sums over groups of rows added
- *          into FP64 accumulators.
+ *          FP32; each window sum is formed as FP32 partial sums over groups
+ *          of up to 128 rows, each added into a Kahan-compensated FP32 total
+ *          (sum and compensation, read out as their FP64 difference).
  *  LB_F32_P64: populations as FP64 deviations n_i - a_i, history as in
  *          LB_F32.
  */
@@ -385,6 +386,21 @@ lb_status lb_set_params(lb_handle *h, int32_t ch, double g_inf, double tau_m,
  * later segments and sweeps with the same adjoint workspace and seg_len
  * (lb_adjoint_begin with another buffer or seg_len drops the graphs;
  * lb_destroy frees them); longer segments launch their kernels directly.
+ *
+ * Streams: lb_adjoint_segment returns once the segment's replay (and the
+ * copy of dL_dux) has finished on the handle's stream, so ckpt and dL_dux
+ * may be reused at once.  The segment's reverse sweep runs on a second
+ * stream that the handle creates at the first lb_adjoint_begin (default
+ * priority; destroyed by lb_destroy), ordered against the replays by events
+ * and reading records that are double-buffered in the adjoint workspace, so
+ * it overlaps the replay of the next segment.  lb_adjoint_end waits for the
+ * last sweep.  The workspace must stay allocated until lb_adjoint_end.
+ *
+ * Against a single call per segment that takes (t0, t1, sample_every) and
+ * returns the accumulated gradient: the segment's range follows from the
+ * call order and the checkpoint's step count, dL_dux holds every step of the
+ * segment (zeros where the loss does not sample, so any sampling pattern is
+ * expressed), and the gradient is reduced once, at lb_adjoint_end.
  */
 size_t lb_adjoint_workspace_bytes(const lb_handle *h, int32_t seg_len);
 lb_status lb_adjoint_begin(lb_handle *h, void *d_aws, size_t bytes, int32_t seg_len);

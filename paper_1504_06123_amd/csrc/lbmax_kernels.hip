@@ -14,14 +14,17 @@
 //             channel's window is split across workgroups.
 //
 // Data layout (per channel, all planes [np] with node = y*lx + x):
-//   populations: two buffers (step parity) x 9 planes of n_i - a_i
+//   populations: two buffers (step parity) x 9 planes of n_i - a_i in FP64;
+//   in FP32 storage, 9 planes of FP32 remainders against the equilibrium of
+//   the node's FP64 density and velocity, which two more buffers of 3 FP64
+//   planes hold
 //   history ring: row-major [n_hist][np]; row t' mod n_hist holds the entry
 //   of step t'.  A wavefront reads one row per age: 64 consecutive nodes,
-//   fully coalesced, streaming through HBM once per step.  Ages are walked
-//   newest to oldest, so the accumulated strain gamma_{t,t'} is a running
-//   FP64 sum of the shear rate over the window (Sec. III Eq. eeval with the
-//   simple-shear reduction of the Finger tensor) and no strain prefix has to
-//   be stored.
+//   fully coalesced, streaming through HBM once per pass (a pass serves a
+//   block of steps).  Ages are walked newest to oldest, so the accumulated
+//   strain gamma_{t,t'} is a running FP64 sum of the shear rate over the
+//   window (Sec. III Eq. eeval with the simple-shear reduction of the Finger
+//   tensor) and no strain prefix has to be stored.
 #include "lbmax_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -55,16 +58,34 @@ __device__ __forceinline__ P eq_dev(P w, P cu, P drho, P uu)
 }
 
 // ---------------------------------------------------------------------------
-// Window-sum accumulators.  FP32 entries are summed in plain FP32 partial
-// groups that are flushed into an FP64 sum (one conversion and one FP64 add
-// per flush: cheaper than a Kahan-compensated FP32 pair and no less
-// accurate); FP64 entries are summed plainly.  value() returns the sum.
+// Window-sum accumulators.  FP32 history entries are summed in plain FP32
+// partial groups (a few rows to 128 rows); each finished partial sum enters a
+// Kahan-compensated FP32 total: the sum s and the compensation c, the
+// negated low-order part that the additions so far have rounded away, which
+// the next addition feeds back.  value() returns s - c in FP64.  FP64 entries
+// are summed plainly.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Acc {
-    double s = 0.0;
-    __device__ __forceinline__ void add(R x) { s += (double)x; }
+    R s = R(0);
+    __device__ __forceinline__ void add(R x) { s += x; }
     __device__ __forceinline__ double value() const { return s; }
+};
+
+template <>
+struct Acc<float> {
+    float s = 0.0f, c = 0.0f;
+    __device__ __forceinline__ void add(float x)
+    {
+        // the order of these operations is the compensation; nothing here
+        // may be reassociated or contracted
+#pragma clang fp contract(off) reassociate(off)
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
 };
 
 // Rate constants of the memory decay exp(-k (1/tau + r/gamma_c)) of
@@ -585,6 +606,46 @@ __device__ __forceinline__ Pack<R, V> load_pack_sbase(const R *row, uint32_t off
     return r;
 }
 
+// The same load through a buffer resource whose base is the (wave-uniform)
+// row address: the lane's byte offset is a 32-bit VGPR operand that every row
+// shares, so a group of rows needs no per-row vector address arithmetic and no
+// per-row copy of the offset; lanes reading past the row's `row_bytes` get
+// zeros instead of touching memory.  Word 3 of the resource selects 32-bit
+// raw data, the gfx9 form.
+constexpr int kBufferWord3 = 0x00020000;
+
+template <typename R, int V>
+__device__ __forceinline__ Pack<R, V> load_pack_rsrc(const R *row, uint32_t row_bytes,
+                                                     uint32_t off)
+{
+    uint64_t a = reinterpret_cast<uint64_t>(row);
+    asm volatile("" : "+s"(a));  // uniform: the resource stays in scalar registers
+    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        reinterpret_cast<void *>(a), (short)0, (int)row_bytes, kBufferWord3);
+    constexpr int B = (int)sizeof(R) * V;
+    static_assert(B == 4 || B == 8 || B == 16 || B == 32, "pack size");
+    Pack<R, V> r;
+    if constexpr (B == 4) {
+        const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+        __builtin_memcpy(&r, &x, 4);
+    } else if constexpr (B == 8) {
+        typedef uint32_t U2 __attribute__((ext_vector_type(2)));
+        const U2 x = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+        __builtin_memcpy(&r, &x, 8);
+    } else if constexpr (B == 16) {
+        typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+        const U4 x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+        __builtin_memcpy(&r, &x, 16);
+    } else {
+        typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+        const U4 x0 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+        const U4 x1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off + 16, 0, 0);
+        __builtin_memcpy(&r, &x0, 16);
+        __builtin_memcpy(reinterpret_cast<char *>(&r) + 16, &x1, 16);
+    }
+    return r;
+}
+
 // float(u) for a wave-uniform 0 <= u < 2^24 (exact), built from its bits with
 // integer operations in scalar registers, so it enters the vector
 // instructions as a scalar operand instead of a per-row vector conversion
@@ -719,29 +780,36 @@ __device__ __forceinline__ void add_powers(R x, R q, R g2, R (&pa)[M][V], R (&pb
     }
 }
 
-// U rows of interior ages: entry k + j0 + u sits at ring slot `slot - j0 - u`.
-// The plain partial sums pa, pb take x = s E(k+m) (carried along m by the
-// per-entry factor q) and x * 2 gamma; FIRST starts them from these rows.
-template <typename R, int V, int M, int U, bool HAS_R, bool FIRST>
-__device__ __forceinline__ void pass_rows(const R *__restrict__ ring_s,
+// Loads of U ring rows, slots slot, slot - 1, ..., slot - U + 1, at the
+// lane's byte offset `off` (kept opaque by the caller, so that the loads take
+// it as a 32-bit offset to the scalar row address).
+template <typename R, int V, int U, bool HAS_R>
+__device__ __forceinline__ void load_rows(const R *__restrict__ ring_s,
                                           const R *__restrict__ ring_r, size_t np,
-                                          uint32_t lane_off, int slot, int kf0,
-                                          const Decay<R> &dec, R (&pa)[M][V], R (&pb)[M][V],
-                                          double (&loc)[V])
+                                          uint32_t off, int slot, Pack<R, V> (&sv)[U],
+                                          Pack<R, V> (&rv)[U])
+{
+    const uint32_t row_bytes = (uint32_t)(np * sizeof(R));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const size_t row = (size_t)(slot - u) * np;
+        sv[u] = load_pack_rsrc<R, V>(ring_s + row, row_bytes, off);
+        if (HAS_R)
+            rv[u] = load_pack_rsrc<R, V>(ring_r + row, row_bytes, off);
+    }
+}
+
+// The terms of U loaded rows of interior ages kf0, kf0 + 1, ...: the plain
+// partial sums pa, pb take x = s E(k+m) (carried along m by the per-entry
+// factor q) and x * gamma; FIRST starts them from these rows.
+template <typename R, int V, int M, int U, bool HAS_R, bool FIRST>
+__device__ __forceinline__ void sum_rows(const Pack<R, V> (&sv)[U], const Pack<R, V> (&rv)[U],
+                                         int kf0, const Decay<R> &dec, R (&pa)[M][V],
+                                         R (&pb)[M][V], double (&loc)[V])
 {
     // No implicit contraction: every lane width and group size rounds the
     // same operations the same way (the FMAs are written out).
 #pragma clang fp contract(off)
-    Pack<R, V> sv[U], rv[U];
-    uint32_t off = lane_off;  // redefined here, so the loads below see a 32-bit offset
-    asm volatile("" : "+v"(off));
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const size_t row = (size_t)(slot - u) * np;
-        sv[u] = load_pack_sbase<R, V>(ring_s + row, off);
-        if (HAS_R)
-            rv[u] = load_pack_sbase<R, V>(ring_r + row, off);
-    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         // ages stay below 2^24 in FP32 histories (the window is limited to
@@ -768,6 +836,21 @@ __device__ __forceinline__ void pass_rows(const R *__restrict__ ring_s,
     }
 }
 
+// U rows of interior ages: entry k + j0 + u sits at ring slot `slot - j0 - u`.
+template <typename R, int V, int M, int U, bool HAS_R, bool FIRST>
+__device__ __forceinline__ void pass_rows(const R *__restrict__ ring_s,
+                                          const R *__restrict__ ring_r, size_t np,
+                                          uint32_t lane_off, int slot, int kf0,
+                                          const Decay<R> &dec, R (&pa)[M][V], R (&pb)[M][V],
+                                          double (&loc)[V])
+{
+    uint32_t off = lane_off;  // redefined here, so the loads below see a 32-bit offset
+    asm volatile("" : "+v"(off));
+    Pack<R, V> sv[U], rv[U];
+    load_rows<R, V, U, HAS_R>(ring_s, ring_r, np, off, slot, sv, rv);
+    sum_rows<R, V, M, U, HAS_R, FIRST>(sv, rv, kf0, dec, pa, pb, loc);
+}
+
 template <typename R, int V, int M>
 __device__ __forceinline__ void flush(const R (&pa)[M][V], const R (&pb)[M][V],
                                       Acc<R> (&A)[M][V], Acc<R> (&B)[M][V])
@@ -782,10 +865,14 @@ __device__ __forceinline__ void flush(const R (&pa)[M][V], const R (&pb)[M][V],
 }
 
 // Interior ages [k, kend) of one chunk: every m has weight 1 and is in the
-// window.  Rows are visited newest to oldest, wrapping at row 0.  Rows are
-// loaded U at a time; the plain partial sums are flushed into the FP64
-// accumulators every F rows (F a multiple of U), then every U rows near the
-// end of a run, then row by row.
+// window.  Rows are visited newest to oldest, wrapping at row 0.  The plain
+// partial sums enter the compensated totals every F rows (F a multiple of
+// U), then every U/2 (or U) rows near the end of a run, then row by row.
+// In the F-row blocks the rows go in two halves of U/2 that alternate: the
+// loads of one half are issued before the terms of the other are summed, so
+// the load latency is hidden behind the arithmetic of the wavefront itself
+// (the register cost is that of U rows).  The half after a run's last F-row
+// block is loaded from clamped, in-bounds rows and not used.
 template <typename R, int V, int M, int U, int F, bool HAS_R>
 __device__ __forceinline__ void pass_bulk(const R *__restrict__ ring_s,
                                           const R *__restrict__ ring_r, size_t np,
@@ -794,6 +881,7 @@ __device__ __forceinline__ void pass_bulk(const R *__restrict__ ring_s,
                                           Acc<R> (&B)[M][V], double (&loc)[V])
 {
     static_assert(F % U == 0, "flush length must be a multiple of the row group");
+    constexpr int U2 = U / 2;
     int slot = p - k;
     if (slot < 0)
         slot += H;
@@ -801,20 +889,40 @@ __device__ __forceinline__ void pass_bulk(const R *__restrict__ ring_s,
         const int run = min(kend - k, slot + 1);  // rows down to 0 without wrap
         int j = 0;
         R pa[M][V], pb[M][V];
-        if (F > U) {
+        if constexpr (F > U && U % 2 == 0) {
+            // one opaque copy of the offset for all loads of the blocks
+            uint32_t off = lane_off;
+            asm volatile("" : "+v"(off));
+            Pack<R, V> as[U2], ar[U2], bs[U2], br[U2];
+            if (run >= F)
+                load_rows<R, V, U2, HAS_R>(ring_s, ring_r, np, off, slot, as, ar);
             for (; j + F <= run; j += F) {
-                pass_rows<R, V, M, U, HAS_R, true>(ring_s, ring_r, np, lane_off, slot - j,
-                                                   k + j, dec, pa, pb, loc);
-                for (int g = U; g < F; g += U)
-                    pass_rows<R, V, M, U, HAS_R, false>(ring_s, ring_r, np, lane_off,
-                                                        slot - j - g, k + j + g, dec, pa, pb,
-                                                        loc);
+                // inside the block every row index is >= slot - run + 1 >= 0
+                load_rows<R, V, U2, HAS_R>(ring_s, ring_r, np, off, slot - j - U2, bs,
+                                           br);
+                sum_rows<R, V, M, U2, HAS_R, true>(as, ar, k + j, dec, pa, pb, loc);
+                for (int g = U2; g < F; g += U) {
+                    // the next rows: past the block's end they belong to the
+                    // next block, or to no block (clamped to rows U2 - 1 .. 0)
+                    load_rows<R, V, U2, HAS_R>(ring_s, ring_r, np, off,
+                                               max(slot - j - g - U2, U2 - 1), as, ar);
+                    sum_rows<R, V, M, U2, HAS_R, false>(bs, br, k + j + g, dec, pa, pb, loc);
+                    if (g + U2 < F) {
+                        load_rows<R, V, U2, HAS_R>(ring_s, ring_r, np, off,
+                                                   slot - j - g - U, bs, br);
+                        sum_rows<R, V, M, U2, HAS_R, false>(as, ar, k + j + g + U2, dec, pa,
+                                                            pb, loc);
+                    }
+                }
                 flush<R, V, M>(pa, pb, A, B);
             }
         }
-        for (; j + U <= run; j += U) {
-            pass_rows<R, V, M, U, HAS_R, true>(ring_s, ring_r, np, lane_off, slot - j, k + j,
-                                               dec, pa, pb, loc);
+        // the rest of the run in groups of UR rows (the half group where the
+        // blocks above alternate halves: no more registers than they use)
+        constexpr int UR = (F > U && U % 2 == 0) ? U2 : U;
+        for (; j + UR <= run; j += UR) {
+            pass_rows<R, V, M, UR, HAS_R, true>(ring_s, ring_r, np, lane_off, slot - j, k + j,
+                                                dec, pa, pb, loc);
             flush<R, V, M>(pa, pb, A, B);
         }
         for (; j < run; ++j) {
@@ -954,16 +1062,16 @@ __device__ __forceinline__ void pass_tile(char *__restrict__ ws, const ChanDev *
 // whose lane width is V, one wavefront per tile (64 V nodes), so channels
 // narrower than a workgroup leave no wavefront idle.  Plain form: the four
 // wavefronts of workgroup b take tiles 4b .. 4b + 3.
-// FP32 histories fit two wavefronts per SIMD at every block length (the
-// 32-step pass needs the bound to get there); FP64 ones keep the default.
-template <typename R>
+// FP32 histories fit two wavefronts per SIMD at 32 steps per pass (the bound
+// is needed to get there) and three at 16; FP64 ones keep the default.
+template <typename R, int M>
 constexpr int pass_waves_per_simd()
 {
-    return sizeof(R) == 4 ? 2 : 1;
+    return sizeof(R) == 4 ? (M <= 16 ? 3 : 2) : 1;
 }
 
 template <typename P, typename R, int V, int M, int U, int F>
-__global__ __launch_bounds__(kBlock, pass_waves_per_simd<R>()) void k_hist_pass(char *__restrict__ ws,
+__global__ __launch_bounds__(kBlock, (pass_waves_per_simd<R, M>())) void k_hist_pass(char *__restrict__ ws,
                                                       const ChanDev *__restrict__ chans,
                                                       const HistTile *__restrict__ tiles,
                                                       int n_tiles,
@@ -989,7 +1097,7 @@ __global__ __launch_bounds__(kBlock, pass_waves_per_simd<R>()) void k_hist_pass(
 // until the list is exhausted.  The counter was zeroed by the lattice kernel
 // of this step.
 template <typename P, typename R, int V, int M, int U, int F>
-__global__ __launch_bounds__(kBlock, pass_waves_per_simd<R>()) void k_hist_pass_persistent(
+__global__ __launch_bounds__(kBlock, (pass_waves_per_simd<R, M>())) void k_hist_pass_persistent(
     char *__restrict__ ws, const ChanDev *__restrict__ chans,
     const HistTile *__restrict__ tiles, int n_tiles, const int64_t *__restrict__ tcount,
     int trel, int *__restrict__ counter)
@@ -1503,7 +1611,7 @@ __device__ __forceinline__ void wm_tile(char *__restrict__ ws, const ChanDev *c,
     };
     const int kb = max(1, H - M);  // ages [1, kb) stay inside with weight 1
     int slot = p;
-    // bulk ages: one sum, FP32 partials of 32 rows flushed into FP64; rows
+    // bulk ages: one sum, FP32 partials of 32 rows into the compensated total; rows
     // are loaded 8 at a time before any is used (same order of operations)
     int k = 1;
     while (k < kb) {
@@ -2245,7 +2353,7 @@ __device__ __forceinline__ void grid_walk(char *__restrict__ ws, const ChanDev *
                                           int64_t t)
 {
 #pragma clang fp contract(off)
-    constexpr int F = 64;  // FP32 partial sums flushed into FP64 every F entries
+    constexpr int F = 64;  // FP32 partial sums enter the totals every F entries
     const int B = c->qb, C = c->qc;
     const size_t np = (size_t)c->np;
     const bool has_r = c->has_r != 0;
@@ -2507,10 +2615,12 @@ void launch_lb(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, 
 }
 
 // Shapes of the history pass: (nodes per lane V, steps per pass M, rows
-// loaded per group U, rows per FP64 flush F) for each block length and
+// loaded per group U, rows per partial sum F) for each block length and
 // requested lane width.  Blocked passes use one node per lane (the M
-// accumulator pairs fill the registers); longer flush intervals save FP64
-// adds where the pass is bound by vector-ALU issue.
+// accumulator pairs fill the registers); longer partial sums save
+// compensated additions where the pass is bound by vector-ALU issue.  In the
+// F-row blocks the rows go in halves of U/2, the loads of one half issued
+// before the other half is summed.
 #define LBMAX_PASS_SHAPE_TABLE(block, vec, X)                                    \
     do {                                                                         \
         if (block == 1) {                                                        \
@@ -2535,7 +2645,7 @@ void launch_lb(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, 
         } else if (block == 16) {                                                \
             X(1, 16, 8, 32);                                                     \
         } else {                                                                 \
-            X(1, 32, 8, 128);                                                      \
+            X(1, 32, 16, 128);                                                      \
         }                                                                        \
     } while (0)
 
@@ -2584,7 +2694,7 @@ int hist_pass_blocks_per_cu(int prec, int vec, int block)
 }
 
 // Shapes of the full-tensor pass: (steps per pass M, rows per group U, rows
-// per FP64 flush F); three sums per step limit the block to 16 steps.
+// per partial sum F); three sums per step limit the block to 16 steps.
 #define LBMAX_FINGER_SHAPE_TABLE(block, X)                                      \
     do {                                                                         \
         if (block == 1)                                                          \

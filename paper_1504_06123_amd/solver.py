@@ -75,9 +75,9 @@ class Solver:
 
     channels: sequence of channel descriptions (see make_descs).
     precision: "f32" (FP32 populations stored as remainders against the
-    equilibrium of FP64 moments; FP32 history with FP32 partial sums flushed
-    into FP64; FP64 strain), "f32p64" (FP64 populations, the same FP32
-    history) or "f64".
+    equilibrium of FP64 moments; FP32 history whose window sums are FP32
+    partial sums added into Kahan-compensated FP32 totals; FP64 strain),
+    "f32p64" (FP64 populations, the same FP32 history) or "f64".
     """
 
     def __init__(self, channels: Sequence, precision: str = "f32",

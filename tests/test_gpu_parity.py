@@ -169,7 +169,8 @@ def test_f64_2d_perturbed(Solver):
 
 # ---------------------------------------------------------------------------
 # FP32 paths: split FP32 population storage ("f32") or FP64 populations
-# ("f32p64"); FP32 history with FP32 partial sums flushed into FP64; FP64 strain
+# ("f32p64"); FP32 history, FP32 partial sums into Kahan-compensated FP32
+# totals; FP64 strain
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("precision", ["f32", "f32p64"])
