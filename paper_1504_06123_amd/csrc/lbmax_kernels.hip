@@ -2625,27 +2625,27 @@ void launch_lb(int prec, char *ws, const ChanDev *chans, const NodeTile *tiles, 
     do {                                                                         \
         if (block == 1) {                                                        \
             if (vec == 4)                                                        \
-                X(4, 1, 4, 4);                                                    \
+                X(4, 1, 4, 32);                                                    \
             else if (vec == 2)                                                   \
-                X(2, 1, 8, 8);                                                    \
+                X(2, 1, 8, 32);                                                    \
             else                                                                 \
-                X(1, 1, 8, 8);                                                    \
+                X(1, 1, 8, 32);                                                    \
         } else if (block == 2) {                                                 \
             if (vec == 1)                                                        \
-                X(1, 2, 8, 8);                                                    \
+                X(1, 2, 8, 32);                                                    \
             else                                                                 \
-                X(2, 2, 4, 4);                                                    \
+                X(2, 2, 4, 32);                                                    \
         } else if (block == 4) {                                                 \
             if (vec == 1)                                                        \
-                X(1, 4, 8, 8);                                                    \
+                X(1, 4, 8, 32);                                                    \
             else                                                                 \
-                X(2, 4, 4, 4);                                                    \
+                X(2, 4, 4, 32);                                                    \
         } else if (block == 8) {                                                 \
-            X(1, 8, 8, 8);                                                      \
+            X(1, 8, 8, 32);                                                      \
         } else if (block == 16) {                                                \
             X(1, 16, 8, 32);                                                     \
         } else {                                                                 \
-            X(1, 32, 16, 128);                                                      \
+            X(1, 32, (sizeof(H) == 4 ? 16 : 8), 128);                               \
         }                                                                        \
     } while (0)
 
