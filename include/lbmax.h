@@ -80,7 +80,7 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F32_P64 = 2 } lb_precision;
 
 /*
  * One channel.  Requirements (checked, LB_EINVAL otherwise):
- *   lx >= 1, ly >= 3, tau_lb > 1/2, n_hist >= 2 (unless the grid or law 2
+ *   lx >= 1, ly >= 3, lx * ly <= 2^26 - 64, tau_lb > 1/2, n_hist >= 2 (unless the grid or law 2
  *   is used; with LB_F32 and LB_F32_P64 also n_hist <= 2^24, where entry
  *   ages are exact in FP32), g_inf >= 0, tau_m > 0,
  *   gamma_c > 0 (may be +INFINITY: the linear / UCM limit of Sec. II),

@@ -580,66 +580,47 @@ __device__ __forceinline__ Pack<R, V> load_pack(const R *row, uint32_t off)
     return *reinterpret_cast<const Pack<R, V> *>(reinterpret_cast<const char *>(row) + off);
 }
 
-typedef const __attribute__((address_space(1))) char *GlobalBytes;
-
-// The same load with the row address held in scalar registers: the empty asm
-// pins the (wave-uniform) row address to an SGPR pair, so it is not
-// reassociated with the lane offset, and with a 32-bit lane offset defined in
-// the same block (see pass_rows) the load takes the scalar-base form (row
-// address + 32-bit lane offset) instead of a 64-bit vector add per row.
-template <typename R, int V>
-__device__ __forceinline__ Pack<R, V> load_pack_sbase(const R *row, uint32_t off)
-{
-    uint64_t a = reinterpret_cast<uint64_t>(row);
-    asm volatile("" : "+s"(a));
-    const GlobalBytes p = reinterpret_cast<GlobalBytes>(a) + off;
-    Pack<R, V> r;
-    if constexpr (V == 1) {
-        r.v[0] = *reinterpret_cast<const __attribute__((address_space(1))) R *>(p);
-    } else {
-        typedef R Vec __attribute__((ext_vector_type(V)));
-        const Vec x = *reinterpret_cast<const __attribute__((address_space(1))) Vec *>(p);
-#pragma unroll
-        for (int v = 0; v < V; ++v)
-            r.v[v] = x[v];
-    }
-    return r;
-}
-
-// The same load through a buffer resource whose base is the (wave-uniform)
-// row address: the lane's byte offset is a 32-bit VGPR operand that every row
-// shares, so a group of rows needs no per-row vector address arithmetic and no
-// per-row copy of the offset; lanes reading past the row's `row_bytes` get
-// zeros instead of touching memory.  Word 3 of the resource selects 32-bit
-// raw data, the gfx9 form.
+// Loads through a buffer resource (gfx9 raw buffer: 32-bit offsets to a
+// base held in scalar registers).  A group of rows shares one resource whose
+// base is the group's lowest row: the row is selected by the scalar offset (a
+// multiple of the row length, the same for every group) and the lane by the
+// 32-bit VGPR offset that every row shares, so neither needs a vector
+// instruction per row and the scalar work per row is none.  Reads past the
+// resource's `bytes` return zeros instead of touching memory.  Word 3 selects
+// 32-bit raw data, the gfx9 form.
 constexpr int kBufferWord3 = 0x00020000;
 
-template <typename R, int V>
-__device__ __forceinline__ Pack<R, V> load_pack_rsrc(const R *row, uint32_t row_bytes,
-                                                     uint32_t off)
+template <typename R>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const R *base, uint32_t bytes)
 {
-    uint64_t a = reinterpret_cast<uint64_t>(row);
+    uint64_t a = reinterpret_cast<uint64_t>(base);
     asm volatile("" : "+s"(a));  // uniform: the resource stays in scalar registers
-    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        reinterpret_cast<void *>(a), (short)0, (int)row_bytes, kBufferWord3);
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(a), (short)0, (int)bytes,
+                                             kBufferWord3);
+}
+
+template <typename R, int V>
+__device__ __forceinline__ Pack<R, V> load_pack_rsrc(__amdgpu_buffer_rsrc_t rs, uint32_t off,
+                                                     uint32_t soff)
+{
     constexpr int B = (int)sizeof(R) * V;
     static_assert(B == 4 || B == 8 || B == 16 || B == 32, "pack size");
     Pack<R, V> r;
     if constexpr (B == 4) {
-        const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+        const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, (int)soff, 0);
         __builtin_memcpy(&r, &x, 4);
     } else if constexpr (B == 8) {
         typedef uint32_t U2 __attribute__((ext_vector_type(2)));
-        const U2 x = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+        const U2 x = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, (int)soff, 0);
         __builtin_memcpy(&r, &x, 8);
     } else if constexpr (B == 16) {
         typedef uint32_t U4 __attribute__((ext_vector_type(4)));
-        const U4 x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+        const U4 x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, (int)soff, 0);
         __builtin_memcpy(&r, &x, 16);
     } else {
         typedef uint32_t U4 __attribute__((ext_vector_type(4)));
-        const U4 x0 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
-        const U4 x1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off + 16, 0, 0);
+        const U4 x0 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, (int)soff, 0);
+        const U4 x1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off + 16, (int)soff, 0);
         __builtin_memcpy(&r, &x0, 16);
         __builtin_memcpy(reinterpret_cast<char *>(&r) + 16, &x1, 16);
     }
@@ -780,22 +761,29 @@ __device__ __forceinline__ void add_powers(R x, R q, R g2, R (&pa)[M][V], R (&pb
     }
 }
 
-// Loads of U ring rows, slots slot, slot - 1, ..., slot - U + 1, at the
-// lane's byte offset `off` (kept opaque by the caller, so that the loads take
-// it as a 32-bit offset to the scalar row address).
+// Loads of U ring rows, slots slot, slot - 1, ..., slot - U + 1 (all >= 0),
+// at the lane's byte offset `off`.  The rows lie (U - 1 - u) row lengths above
+// the group's lowest row; the host limits channels so that U rows of a ring
+// plane span less than 4 GiB.
 template <typename R, int V, int U, bool HAS_R>
 __device__ __forceinline__ void load_rows(const R *__restrict__ ring_s,
                                           const R *__restrict__ ring_r, size_t np,
                                           uint32_t off, int slot, Pack<R, V> (&sv)[U],
                                           Pack<R, V> (&rv)[U])
 {
+    static_assert(U <= 8, "the channel size limit keeps 8 rows of a plane below 4 GiB");
     const uint32_t row_bytes = (uint32_t)(np * sizeof(R));
+    const size_t low = (size_t)(slot - (U - 1)) * np;
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc<R>(ring_s + low, (uint32_t)U * row_bytes);
+    __amdgpu_buffer_rsrc_t rr = rs;
+    if (HAS_R)
+        rr = row_rsrc<R>(ring_r + low, (uint32_t)U * row_bytes);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const size_t row = (size_t)(slot - u) * np;
-        sv[u] = load_pack_rsrc<R, V>(ring_s + row, row_bytes, off);
+        const uint32_t soff = (uint32_t)(U - 1 - u) * row_bytes;
+        sv[u] = load_pack_rsrc<R, V>(rs, off, soff);
         if (HAS_R)
-            rv[u] = load_pack_rsrc<R, V>(ring_r + row, row_bytes, off);
+            rv[u] = load_pack_rsrc<R, V>(rr, off, soff);
     }
 }
 
@@ -844,10 +832,8 @@ __device__ __forceinline__ void pass_rows(const R *__restrict__ ring_s,
                                           const Decay<R> &dec, R (&pa)[M][V], R (&pb)[M][V],
                                           double (&loc)[V])
 {
-    uint32_t off = lane_off;  // redefined here, so the loads below see a 32-bit offset
-    asm volatile("" : "+v"(off));
     Pack<R, V> sv[U], rv[U];
-    load_rows<R, V, U, HAS_R>(ring_s, ring_r, np, off, slot, sv, rv);
+    load_rows<R, V, U, HAS_R>(ring_s, ring_r, np, lane_off, slot, sv, rv);
     sum_rows<R, V, M, U, HAS_R, FIRST>(sv, rv, kf0, dec, pa, pb, loc);
 }
 
@@ -890,9 +876,7 @@ __device__ __forceinline__ void pass_bulk(const R *__restrict__ ring_s,
         int j = 0;
         R pa[M][V], pb[M][V];
         if constexpr (F > U && U % 2 == 0) {
-            // one opaque copy of the offset for all loads of the blocks
-            uint32_t off = lane_off;
-            asm volatile("" : "+v"(off));
+            const uint32_t off = lane_off;
             Pack<R, V> as[U2], ar[U2], bs[U2], br[U2];
             if (run >= F)
                 load_rows<R, V, U2, HAS_R>(ring_s, ring_r, np, off, slot, as, ar);

@@ -115,8 +115,9 @@ std::string check_desc(const lb_channel_desc *ch, int32_t n_ch, lb_precision pre
             return bad("lx must be >= 1");
         if (d.ly < 3)
             return bad("ly must be >= 3");
-        if ((int64_t)d.lx * d.ly > (int64_t)1 << 30)
-            return bad("too many nodes");
+        // the history pass addresses 8 ring rows of a plane with 32-bit offsets
+        if ((int64_t)d.lx * d.ly > ((int64_t)1 << 26) - 64)
+            return bad("too many nodes (at most 2^26 - 64 per channel)");
         if (d.hist_blocks < 0)
             return bad("hist_blocks must be >= 0");
         if (d.hist_blocks == 0 && d.law != 2 && d.n_hist < 2)

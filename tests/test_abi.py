@@ -79,6 +79,7 @@ def test_workspace_bytes_large_2d_fits(lib):
     ("g_inf", -1e-3, "g_inf"), ("tau_m", 0.0, "tau_m"), ("tau_m", math.inf, "tau_m"),
     ("gamma_c", 0.0, "gamma_c"), ("gamma_c", math.nan, "gamma_c"),
     ("gx", math.inf, "force"),
+    ("lx", (1 << 22) + 1, "too many nodes"),
 ])
 def test_invalid_descriptions_rejected(lib, field, value, msg):
     arr, _ = _desc(**{field: value})
