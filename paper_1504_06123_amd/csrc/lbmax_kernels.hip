@@ -521,6 +521,20 @@ __device__ __forceinline__ void lb_node(char *__restrict__ ws, const ChanDev *c,
     reinterpret_cast<P *>(ws + c->off_rho)[n] = drho;
 }
 
+// Node tile of workgroup b in a launch of n workgroups (one per tile).  The
+// dispatcher deals the workgroups of a launch to the 8 XCDs in turn, so
+// consecutive workgroups land in different L2 caches; giving each XCD a
+// contiguous range of tiles (about n/8 of them, rows of a channel next to each
+// other) keeps a stencil's neighbouring rows in the L2 that reads them.  A
+// bijection of [0, n).
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int x = b % kXcds, i = b / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + min(x, r) + i;
+}
+
 template <typename P, typename S>
 __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
                                                const ChanDev *__restrict__ chans,
@@ -528,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
                                                const int64_t *__restrict__ tcount,
                                                int trel, int *__restrict__ tile_counters)
 {
-    const NodeTile tl = tiles[blockIdx.x];
+    const NodeTile tl = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
     const ChanDev *c = chans + tl.ch;
     const int n = tl.n0 + threadIdx.x;
     // The history pass of this step (if any) claims its tiles from these
@@ -564,9 +578,9 @@ __global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
 // age range [k0, k1) (a tile; four per workgroup); lane l owns nodes
 // n0 + V*l .. n0 + V*l + V-1 and reads them as one V-wide vector per ring row.  Ages are walked newest to
 // oldest (the running FP64 strain gamma is a sum over the rows already
-// read); U rows are loaded before any is used so each wavefront keeps U (2U
-// with |gamma_dot|) vector reads in flight.  In FP32 the terms of F rows
-// are added plainly and their sum enters the FP64 accumulator.
+// read); rows are read in halves of U/2, the next half's loads issued before
+// the current half is summed.  In FP32 the terms of F rows are added plainly
+// and their sum enters a Kahan-compensated FP32 total.
 // ---------------------------------------------------------------------------
 template <typename R, int V>
 struct alignas(sizeof(R) * V) Pack {
@@ -1745,7 +1759,7 @@ __global__ __launch_bounds__(kBlock) void k_inst_step(char *__restrict__ ws,
                                                       const ChanDev *__restrict__ chans,
                                                       const NodeTile *__restrict__ tiles)
 {
-    const NodeTile tl = tiles[blockIdx.x];
+    const NodeTile tl = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
     const ChanDev *c = chans + tl.ch;
     const int n = tl.n0 + threadIdx.x;
     if (c->law != 2 || n >= c->n)
@@ -1919,7 +1933,7 @@ __global__ __launch_bounds__(kBlock) void k_hist_step(char *__restrict__ ws,
                                                       const int64_t *__restrict__ tcount,
                                                       int trel, int m)
 {
-    const NodeTile tl = tiles[blockIdx.x];
+    const NodeTile tl = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
     const ChanDev *c = chans + tl.ch;
     const int n = tl.n0 + threadIdx.x;
     if (c->qb != 0 || n >= c->n)
@@ -2442,7 +2456,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_step(char *__restrict__ ws,
                                                       const int64_t *__restrict__ tcount,
                                                       int trel)
 {
-    const NodeTile tl = tiles[blockIdx.x];
+    const NodeTile tl = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
     const ChanDev *c = chans + tl.ch;
     const int n = tl.n0 + threadIdx.x;
     if (c->qb == 0 || n >= c->n)
@@ -2461,7 +2475,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_pass(char *__restrict__ ws,
                                                       const int64_t *__restrict__ tcount,
                                                       int trel)
 {
-    const NodeTile tl = tiles[blockIdx.x];
+    const NodeTile tl = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
     const ChanDev *c = chans + tl.ch;
     const int n = tl.n0 + threadIdx.x;
     if (c->qb == 0 || n >= c->n)
@@ -2482,7 +2496,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_edges(char *__restrict__ ws,
                                                        const int64_t *__restrict__ tcount,
                                                        int trel, int m, int M)
 {
-    const NodeTile tl = tiles[blockIdx.x];
+    const NodeTile tl = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
     const ChanDev *c = chans + tl.ch;
     const int n = tl.n0 + threadIdx.x;
     if (c->qb == 0 || n >= c->n)
