@@ -2094,18 +2094,22 @@ __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const Chan
             lb_collide_body<P>(c, n, d, s_sig, K, out, ux, uy, drho);
             float r[9];
             split_and_rebuild<P>(out, ux, uy, drho, r, full);
-            // the workspace state of this step (nothing here is read in the span)
-            float *dst = pop + (t & 1) * 9 * np;
-            P *mdst = mom + (t & 1) * 3 * np;
+            // The workspace state of the span's last step (nothing here is read
+            // in the span, and the next step reads only the last one); every
+            // step's while the lattice inputs are being recorded.
+            if (k == count - 1 || c->rec) {
+                float *dst = pop + (t & 1) * 9 * np;
+                P *mdst = mom + (t & 1) * 3 * np;
 #pragma unroll
-            for (int q = 0; q < 9; ++q)
-                dst[q * np + n] = r[q];
-            mdst[n] = drho;
-            mdst[np + n] = ux;
-            mdst[2 * np + n] = uy;
-            vel[n] = ux;
-            vel[np + n] = uy;
-            rhop[n] = drho;
+                for (int q = 0; q < 9; ++q)
+                    dst[q * np + n] = r[q];
+                mdst[n] = drho;
+                mdst[np + n] = ux;
+                mdst[2 * np + n] = uy;
+                vel[n] = ux;
+                vel[np + n] = uy;
+                rhop[n] = drho;
+            }
         }
         __syncthreads();  // every stencil read of the old state and stress is done
         if (own) {
@@ -2139,8 +2143,10 @@ __device__ __forceinline__ void fused_span_lds(char *__restrict__ ws, const Chan
                 }
             const P sxy_p = (P)(c->g_inf * (A + sxy));
             const P sxx_p = (P)(c->g_inf * (B + 2.0 * gam * A + sxx));
-            sig[n] = sxy_p;
-            sig[np + n] = sxx_p;
+            if (k == count - 1 || c->rec) {
+                sig[n] = sxy_p;
+                sig[np + n] = sxx_p;
+            }
             s_sig[n] = sxy_p;
             s_sig[K + n] = sxx_p;
         }
