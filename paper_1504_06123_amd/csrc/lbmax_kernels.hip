@@ -536,7 +536,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 }
 
 template <typename P, typename S>
-__global__ __launch_bounds__(kBlock) void k_lb(char *__restrict__ ws,
+__global__ __launch_bounds__(kBlock, 5) void k_lb(char *__restrict__ ws,
                                                const ChanDev *__restrict__ chans,
                                                const NodeTile *__restrict__ tiles,
                                                const int64_t *__restrict__ tcount,
