@@ -55,20 +55,20 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernel
 # (precision, steps per pass, nodes per lane).  Valid only for the kernel source they
 # were taken from; otherwise reported as null.
 MEASURED = {
-    "source_sha256": "126409aa93232d033174dabcc1cd24e81370c82d597378a90154041ddb3dc1d5",
+    "source_sha256": "28020c965c5cd20e1502ff54707b2793f704ea32e43d540b25232149db99aaeb",
     # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated),
     # from `bench.py --counter-run <leg>` under rocprofv3 --pmc
-    "traffic_bytes": {("f32", 32, 1): 8394760.0 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32", 1, 4): 8408870.0 * 1024 * 2 + 40872.0 * 1024,
-                      ("f32p64", 32, 1): 8394910.0 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32p64", 1, 4): 8408720.0 * 1024 * 2 + 40886.2 * 1024},
+    "traffic_bytes": {("f32", 32, 1): 8395010.0 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32", 1, 4): 8411360.0 * 1024 * 2 + 41266.0 * 1024,
+                      ("f32p64", 32, 1): 8395400.0 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32p64", 1, 4): 8411130.0 * 1024 * 2 + 41267.7 * 1024},
     # SQ_INSTS_VALU x 64 / history entries (both modes run the same pass kernels)
-    "valu_instr_per_entry": {("f32", 32, 1): 90.78, ("f32p64", 32, 1): 90.78,
-                             ("f32", 1, 4): 11.49, ("f32p64", 1, 4): 11.49},
+    "valu_instr_per_entry": {("f32", 32, 1): 90.77, ("f32p64", 32, 1): 90.77,
+                             ("f32", 1, 4): 9.53, ("f32p64", 1, 4): 9.53},
     # the side legs' dominant kernels, keyed by (leg, steps per pass), same calibration
-    "leg_traffic_bytes": {("grid", 16): 1606570.0 * 1024 * 2 + 211968.0 * 1024,
-                          ("full_tensor", 16): 33558000.0 * 1024 * 2 + 213072.0 * 1024,
-                          ("strain_damping", 32): 8395920.0 * 1024 * 2 + 266240.0 * 1024},
+    "leg_traffic_bytes": {("grid", 16): 1602530.0 * 1024 * 2 + 211968.0 * 1024,
+                          ("full_tensor", 16): 33557900.0 * 1024 * 2 + 213072.0 * 1024,
+                          ("strain_damping", 32): 8395980.0 * 1024 * 2 + 266240.0 * 1024},
 }
 
 
