@@ -2265,32 +2265,26 @@ __device__ __forceinline__ void grid_update(char *__restrict__ ws, const ChanDev
 // Running state of Eq. gitt on the grid, entries visited newest first:
 // trapezoid weights from the neighbours' ages, strain gamma = sum of (mean
 // s) x (step) over the entries from the newest-but-one down to the current.
+// Ages fit in 32 bits: the grid spans fewer than (C + 2) 2^B <= 2^30 + 2^21
+// steps.
 struct GridSums {
     double sxy = 0.0, sxx = 0.0, gam = 0.0;
-    int64_t a_prev = 0;
+    int a_prev = 0;
     bool first = true;
 };
 
-// Row of the i-th entry of block bi (node n).
-__device__ __forceinline__ size_t grid_row(const ChanDev *c, int n, int bi, int64_t i)
-{
-    return ((size_t)bi * c->qc + (size_t)(i % c->qc)) * (size_t)c->np + n;
-}
-
-
-// Visit the i-th entry of block bi at step t, with shear rate sv and
-// |gamma_dot| rv; returns its decay rate and E(age) in the history precision.
+// Visit an entry of block bi (time step `step`) of age `age` at the current
+// step, with shear rate sv and |gamma_dot| rv; `has_next`: the block holds an
+// older entry.  Returns its decay rate and E(age) in the history precision.
 // Without `direct` the entry's trapezoid terms are left to the caller.
 template <typename R>
-__device__ __forceinline__ void grid_visit(R sv, R rv, int C, int bi, int lg, int64_t i,
-                                           int64_t i_old, int64_t t, const Decay<R> &dec,
-                                           GridSums &g, R &rate, R &e, bool direct = true)
+__device__ __forceinline__ void grid_visit(R sv, R rv, int bi, int step, int age, bool has_next,
+                                           const Decay<R> &dec, GridSums &g, R &rate, R &e,
+                                           bool direct = true)
 {
-    const int64_t step = int64_t(1) << lg;
-    const int64_t age = grid_age(t, i, lg, C);
     // the older neighbour: the next entry of the block, or the newest of
     // block bi - 1 (2 steps back), or none for the oldest entry of all
-    const int64_t a_next = i > i_old ? age + step : (bi > 0 ? age + 2 * step : age);
+    const int a_next = has_next ? age + step : (bi > 0 ? age + 2 * step : age);
     if (!g.first)
         g.gam += (double)sv * (double)step;
     rate = decay_rate<R>(dec, rv);
@@ -2305,7 +2299,11 @@ __device__ __forceinline__ void grid_visit(R sv, R rv, int C, int bi, int lg, in
 }
 
 // Visit entries hi, hi - 1, ..., lo of block bi (newest first), loading L
-// entries ahead of their use; fn(i, sv, rate, e) after each visit.
+// entries ahead of their use; fn(i, sv, rate, e) after each visit.  Entries
+// sk_lo..sk_hi are visited without their trapezoid terms.  The row of entry
+// i is bi C + (i mod C): the slot and the age (which grows by the block's
+// step from one entry to the next older one) are carried along the range,
+// so that no entry needs a 64-bit division.
 template <typename R, int L, typename Fn>
 __device__ __forceinline__ void grid_range(const R *__restrict__ gs, const R *__restrict__ gr,
                                            bool has_r, const ChanDev *c, int n, int bi, int lg,
@@ -2313,23 +2311,37 @@ __device__ __forceinline__ void grid_range(const R *__restrict__ gs, const R *__
                                            const Decay<R> &dec, GridSums &g, Fn &&fn,
                                            int64_t sk_lo = 1, int64_t sk_hi = 0)
 {
-    for (int64_t i = hi; i >= lo; i -= L) {
+    if (hi < lo)
+        return;
+    const int C = c->qc;
+    const size_t np = (size_t)c->np;
+    const int step = 1 << lg;
+    const int count = (int)(hi - lo + 1);
+    const R *bs = gs + (size_t)bi * C * np;
+    const R *br = gr + (size_t)bi * C * np;
+    int slot = (int)(hi % C);
+    int age = (int)grid_age(t, hi, lg, C);
+    for (int k = 0; k < count; k += L) {
         R sv[L], rv[L];
 #pragma unroll
-        for (int u = 0; u < L; ++u)
-            if (i - u >= lo) {
-                const size_t o = grid_row(c, n, bi, i - u);
-                sv[u] = gs[o];
-                rv[u] = has_r ? gr[o] : fabs(sv[u]);
+        for (int u = 0; u < L; ++u) {
+            if (k + u < count) {
+                const size_t o = (size_t)slot * np + n;
+                sv[u] = bs[o];
+                rv[u] = has_r ? br[o] : fabs(sv[u]);
             }
+            slot = slot == 0 ? C - 1 : slot - 1;
+        }
 #pragma unroll
         for (int u = 0; u < L; ++u)
-            if (i - u >= lo) {
+            if (k + u < count) {
+                const int64_t i = hi - (k + u);
                 R rate, e;
-                grid_visit<R>(sv[u], rv[u], c->qc, bi, lg, i - u, i_old, t, dec, g, rate, e,
-                              i - u < sk_lo || i - u > sk_hi);
-                fn(i - u, sv[u], rate, e);
+                grid_visit<R>(sv[u], rv[u], bi, step, age + u * step, i > i_old, dec, g, rate, e,
+                              i < sk_lo || i > sk_hi);
+                fn(i, sv[u], rate, e);
             }
+        age += L * step;
     }
 }
 
@@ -2444,7 +2456,7 @@ __device__ __forceinline__ void grid_edges(char *__restrict__ ws, const ChanDev 
             delta = g.gam;  // entries C + t0 .. C + t - 1: the shear rates of steps t0..t-1
         if (i_old1 + 1 <= i_new0 - 1) {
             g.gam += blk[(kPlaneGrid + bi) * np + n];
-            g.a_prev = grid_age(t, i_old1 + 1, lg, C);
+            g.a_prev = (int)grid_age(t, i_old1 + 1, lg, C);
         }
         grid_range<R, 4>(gs, gr, has_r, c, n, bi, lg, i_old1, i_old, i_old, t, dec, g, none);
     }
