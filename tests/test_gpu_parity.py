@@ -480,3 +480,55 @@ def test_large_2d_full_size_synthetic_window(Solver):
     e_xy, e_n1 = nerr(got_xy, ref_xy), nerr(got_n1, ref_n1)
     say(f"  synthetic window errors: sxy={e_xy:.2e}, n1={e_n1:.2e}")
     assert e_xy <= TOL32["sxy"] and e_n1 <= TOL32["n1"]
+
+
+@pytest.mark.parametrize("precision,block,persistent", [
+    ("f64", 1, False), ("f64", 32, True), ("f32", 32, True)])
+def test_maximum_node_count(Solver, precision, block, persistent):
+    """The largest channels the library takes (lx * ly <= 2^26 - 64): 8192 x
+    8191 nodes, a 48-entry window that wraps twice in 100 steps.  Every
+    index of a node plane, a history row or a block-sum plane is at its
+    largest here; in FP64 one history row is 512 MiB, and the pass reads
+    groups of 4 rows (2 GiB) through 32-bit buffer offsets.  The start is
+    x-invariant (a seeded velocity profile in y, no force), so every column
+    must equal the oracle's 1 x 8191 column."""
+    import torch
+    lx, ly, steps = 8192, 8191, 100
+    rng = np.random.default_rng(workloads.BASE_SEED + 26)
+    prof = 1e-3 * rng.uniform(-1.0, 1.0, size=ly)
+    base = workloads.plain_f64().channels[0].replace(n_hist=48, tau_m=20.0, gx=0.0)
+    col = np.zeros((2, ly, 1))
+    col[0, :, 0] = prof
+    say(f"case maximum node count {lx}x{ly} ({lx * ly} nodes), {precision}, "
+        f"block {block}, persistent {persistent}")
+    u0 = np.zeros((2, ly, lx))
+    u0[0] = prof[:, None]
+    ch = base.replace(lx=lx, ly=ly, u0=u0)
+    del u0
+    with Solver([ch], precision=precision) as s:
+        if block != 1:
+            s.set_block(block)
+        if persistent:
+            s.set_persistent(True)
+        s.step(steps)
+        _, ux, uy = s.fields(0)
+        sxy, n1 = s.stress(0)
+    del ch
+    torch.cuda.empty_cache()
+    oc = oracle.OracleChannel(base.replace(lx=1, ly=ly, u0=col))
+    oc.step(steps)
+    _, rux, ruy = oc.fields()
+    rsxy, rn1 = oc.stress()
+    vscale = np.abs(rux).max()
+    errs = dict(ux=float(np.abs(ux - rux).max() / vscale),
+                sxy=nerr(sxy, np.broadcast_to(rsxy, sxy.shape)),
+                n1=nerr(n1, np.broadcast_to(rn1, n1.shape)))
+    # u_y is zero up to rounding on both sides (the oracle's whole
+    # populations leave about 1e-15, FP32 remainders about 1e-8 of the speed
+    # scale): a bound, not a comparison
+    uy_max = float(np.abs(uy).max() / vscale)
+    say(f"  errors {errs}, max |u_y| / max |u_x| = {uy_max:.1e}")
+    tol = TOL32 if precision == "f32" else {k: TOL64 for k in errs}
+    for k, v in errs.items():
+        assert v <= tol[k], (k, v)
+    assert uy_max <= (TOL32["uy"] if precision == "f32" else 1e-9), uy_max
