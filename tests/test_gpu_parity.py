@@ -367,6 +367,43 @@ def test_save_load_resume_bitwise(Solver, precision):
             assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("block,graph", [(1, 0), (32, 64)])
+def test_zero_and_negative_step_counts(Solver, block, graph):
+    """lb_step(0) is a no-op (state bit for bit, step counter and block
+    position unchanged, also in the middle of a block with graphs on);
+    lb_step(-1) fails with LB_EINVAL and leaves the handle usable."""
+    import torch
+    from paper_1504_06123_amd import LBError, _lib
+    ch = workloads.large_2d(lx=8, ly=12, n_hist=64).channels[0].replace(tau_m=30.0)
+    say(f"case zero and negative step counts, block {block}, graph {graph}")
+    with Solver([ch], precision="f32") as s:
+        s.set_block(block)
+        if graph:
+            s.set_graph(graph)
+        s.step(45)  # mid-block for block 32
+        before = s.save_state().clone()
+        s.step(0)
+        assert s.t == 45
+        assert torch.equal(s.save_state(), before)
+        with pytest.raises(LBError) as ei:
+            s.step(-1)
+        assert ei.value.status == _lib.LB_EINVAL
+        assert s.t == 45
+        assert torch.equal(s.save_state(), before)
+        s.step(19)
+        got = s.fields(0), s.stress(0)
+    with Solver([ch], precision="f32") as s:
+        s.set_block(block)
+        if graph:
+            s.set_graph(graph)
+        s.step(45)
+        s.step(19)
+        want = s.fields(0), s.stress(0)
+    for a, b in zip(want, got):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
 def test_readout_before_first_step_is_state_error(Solver):
     from paper_1504_06123_amd import LBError
     ch = workloads.plain_f64().channels[0]
