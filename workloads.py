@@ -218,6 +218,58 @@ def true_channel(ch: Channel) -> Channel:
     return ch.replace(**ADJOINT_TRUE)
 
 
+# --------------------------------------------------------------------------
+# Channels of the transient studies of Sec. IV (startup and cessation of
+# pressure-driven channel flow: Figs. Qall, QT, us, figtau, compModels,
+# uoffcut, ncut, noffcut)
+# --------------------------------------------------------------------------
+
+# The paper's BGK relaxation (Sec. III) and a channel of 2H = 32 nodes.
+SEC4_TAU_LB = 0.9
+SEC4_HALF_WIDTH = 16
+SEC4_MODELS = ("nlm", "ucm", "instantaneous", "newtonian")
+
+
+def sec4_wall_time(half_width: int = SEC4_HALF_WIDTH, tau_lb: float = SEC4_TAU_LB) -> float:
+    """Transverse momentum-diffusion time t_wall = 4 H^2 rho / (pi^2 eta_inf)
+    of Sec. IV in steps, with rho = 1 and eta_inf = (tau_LB - 1/2) / 3."""
+    eta = (tau_lb - 0.5) / 3.0
+    return 4.0 * half_width ** 2 / (math.pi ** 2 * eta)
+
+
+def sec4_channel(twall_over_tau0: float, theta: float = 10.0, model: str = "nlm",
+                 half_width: int = SEC4_HALF_WIDTH) -> Channel:
+    """One channel of the Sec. IV transient studies: 1 x 2H nodes, at rest.
+
+    The paper varies the channel width to set t_wall / tau_0; here H is fixed
+    and the ratio sets the background time tau_0 = t_wall / ratio instead
+    (G_inf = eta_inf / tau_0), which gives the same dimensionless problem.
+    The Maxwell time is tau = theta tau_0, gamma_c = 0.1, and the driving
+    force density g = G_inf / (2H) (the pressure drop over one channel width
+    equals G_inf, Fig. steadystate; the yield stress G_inf gamma_c then leaves
+    a plug |y| / H < 2 gamma_c).  The window holds 6 tau steps: history
+    older than that weighs at most e^-6 even where the fluid is unsheared.
+    Models: "nlm" the integral nonlinear Maxwell model (Eqs. gitt, nlmax);
+    "ucm" its linear limit gamma_c = inf; "instantaneous" Eq. inlM; and
+    "newtonian" G_inf = 0.  The last three keep the nlm channel's force.
+    """
+    if model not in SEC4_MODELS:
+        raise ValueError(f"unknown model {model!r}")
+    eta = (SEC4_TAU_LB - 0.5) / 3.0
+    tau0 = sec4_wall_time(half_width) / twall_over_tau0
+    g_inf = eta / tau0
+    tau = theta * tau0
+    ch = Channel(lx=1, ly=2 * half_width, tau_lb=SEC4_TAU_LB, g_inf=g_inf, tau_m=tau,
+                 gamma_c=0.1, n_hist=int(math.ceil(6.0 * tau)), gx=g_inf / (2 * half_width))
+    if model == "ucm":
+        ch = ch.replace(gamma_c=math.inf)
+    elif model == "instantaneous":
+        ch = ch.replace(law="instantaneous", n_hist=2)
+    elif model == "newtonian":
+        ch = ch.replace(g_inf=0.0, n_hist=2)
+    return ch
+
+
 ALL = {
     "plain_f64": plain_f64,
     "startup_cessation": startup_cessation,
