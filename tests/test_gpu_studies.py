@@ -21,6 +21,7 @@ import numpy as np
 import pytest
 
 import workloads
+from closed_forms import channel_node_positions, maxwell_channel_startup
 from test_gpu_parity import Solver, say  # noqa: F401
 
 pytestmark = pytest.mark.gpu
@@ -303,3 +304,28 @@ def test_cessation_centre_velocity_against_its_surroundings(runs):
                 assert first[0] < first.max()
             else:
                 assert first[0] == first.max()
+
+
+def test_ucm_matches_the_analytic_startup_and_stopping_flow(runs):
+    """Appendix, Fig. UCM: the UCM channel flow (with the background
+    viscosity) after applying and after removing the force, at the figure's
+    two widths, against its closed form (tests/closed_forms.py; stopping as
+    u_on(T + t) - u_on(t) by linearity), every node over the whole run; the
+    paper notes the same precision for stopping as for startup.  The bound
+    is the lattice's second-order error at 2H = 32 (the oracle shows it
+    shrinking fourfold per doubling of H)."""
+    n_on = T_ON // EVERY
+    for r in (0.1, 1.0):
+        run = runs[("ucm", r, 10.0)]
+        ch = workloads.sec4_channel(r, 10.0, "ucm")
+        eta = (ch.tau_lb - 0.5) / 3.0
+        t_on = EVERY * np.arange(1, n_on + 1)
+        ys = channel_node_positions(ch.ly)
+        ref_on = maxwell_channel_startup(ys, t_on, ch.ly / 2, 1.0, eta, ch.g_inf, ch.tau_m, ch.gx)
+        ref_cont = maxwell_channel_startup(ys, T_ON + t_on, ch.ly / 2, 1.0, eta, ch.g_inf,
+                                           ch.tau_m, ch.gx)
+        scale = np.abs(ref_on).max()
+        e_on = np.abs(run.pu[:n_on] - ref_on).max() / scale
+        e_off = np.abs(run.pu[n_on:] - (ref_cont - ref_on)).max() / scale
+        say(f"  t_wall/tau_0 = {r}: startup error {e_on:.2e}, stopping error {e_off:.2e}")
+        assert e_on <= 2.5e-3 and e_off <= 2.5e-3

@@ -490,6 +490,34 @@ def test_ucm_steady_centreline_maxwell_relation():
     assert errs[1] < errs[0] / 3
 
 
+@pytest.mark.parametrize("twall_over_tau0", [0.1, 1.0])
+def test_ucm_startup_matches_the_modal_solution_at_second_order(twall_over_tau0):
+    """Appendix, Fig. UCM: startup channel flow of the UCM with the background
+    viscosity (theta = 10, the figure's two widths) against its closed form
+    (the modal solution of tests/closed_forms.py, the problem Waters and King
+    solved), every node over six t_wall.  The oracle's error shrinks about
+    fourfold when the channel doubles: second order in 1/H."""
+    from closed_forms import channel_node_positions, maxwell_channel_startup
+    errs = []
+    for half in (4, 8):
+        ch = workloads.sec4_channel(twall_over_tau0, 10.0, "ucm", half_width=half)
+        eta = (ch.tau_lb - 0.5) / 3.0
+        steps = int(round(6 * workloads.sec4_wall_time(half)))
+        every = max(1, steps // 60)
+        oc = oracle.OracleChannel(ch)
+        ts, us, done = [], [], 0
+        while done < steps:
+            oc.step(every)
+            done += every
+            ts.append(done)
+            us.append(oc.fields()[1][:, 0].copy())
+        ref = maxwell_channel_startup(channel_node_positions(ch.ly), ts, half, 1.0, eta,
+                                      ch.g_inf, ch.tau_m, ch.gx)
+        errs.append(float(np.abs(np.array(us) - ref).max() / np.abs(ref).max()))
+    assert errs[0] < 2e-2 and errs[1] < 5e-3, errs
+    assert errs[0] / errs[1] > 3.5, errs
+
+
 @pytest.mark.parametrize("kw", [{}, {"finger": True}, {"law": "strain_damping"},
                                 {"paper_coupling": True}])
 def test_short_window_equals_long_window_before_it_fills(kw):

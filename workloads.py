@@ -248,7 +248,9 @@ def sec4_channel(twall_over_tau0: float, theta: float = 10.0, model: str = "nlm"
     force density g = G_inf / (2H) (the pressure drop over one channel width
     equals G_inf, Fig. steadystate; the yield stress G_inf gamma_c then leaves
     a plug |y| / H < 2 gamma_c).  The window holds 6 tau steps: history
-    older than that weighs at most e^-6 even where the fluid is unsheared.
+    older than that weighs at most e^-6 even where the fluid is unsheared;
+    10 tau for the UCM, whose memory decays with tau alone everywhere (and
+    which the tests hold to a closed form).
     Models: "nlm" the integral nonlinear Maxwell model (Eqs. gitt, nlmax);
     "ucm" its linear limit gamma_c = inf; "instantaneous" Eq. inlM; and
     "newtonian" G_inf = 0.  The last three keep the nlm channel's force.
@@ -262,7 +264,7 @@ def sec4_channel(twall_over_tau0: float, theta: float = 10.0, model: str = "nlm"
     ch = Channel(lx=1, ly=2 * half_width, tau_lb=SEC4_TAU_LB, g_inf=g_inf, tau_m=tau,
                  gamma_c=0.1, n_hist=int(math.ceil(6.0 * tau)), gx=g_inf / (2 * half_width))
     if model == "ucm":
-        ch = ch.replace(gamma_c=math.inf)
+        ch = ch.replace(gamma_c=math.inf, n_hist=int(math.ceil(10.0 * tau)))
     elif model == "instantaneous":
         ch = ch.replace(law="instantaneous", n_hist=2)
     elif model == "newtonian":
