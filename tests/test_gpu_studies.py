@@ -329,3 +329,37 @@ def test_ucm_matches_the_analytic_startup_and_stopping_flow(runs):
         e_off = np.abs(run.pu[n_on:] - (ref_cont - ref_on)).max() / scale
         say(f"  t_wall/tau_0 = {r}: startup error {e_on:.2e}, stopping error {e_off:.2e}")
         assert e_on <= 2.5e-3 and e_off <= 2.5e-3
+
+
+def test_wide_ucm_channels_track_the_closed_form(Solver):
+    """Appendix, Figs. fMvelstr and funnyMaxwell: very viscous UCM fluids in
+    wide channels (S2 = 0.05 and 0.01 << 1, S1 = 20 >> 1) respond almost
+    elastically (shear waves from the walls, overshoots of about 15 times
+    the steady speed) and reach their steady flow only on the scale of tau.
+    The run tracks the closed form over 40000 steps (about 6 tau at
+    theta = 400 and 2 tau at theta = 2000, in lattice units), and the error
+    shrinks fourfold when the channel doubles: second order in 1/H even in
+    this wave-dominated regime."""
+    cases = [(64, 400.0, 0.05), (128, 400.0, 0.05), (256, 2000.0, 0.01), (512, 2000.0, 0.01)]
+    chans = [workloads.appendix_ucm_channel(w, th, s2) for w, th, s2 in cases]
+    steps, every = 40000, 100
+    say(f"case appendix UCM: widths {[c.ly for c in chans]}, {steps} steps, f64")
+    us = [[] for _ in chans]
+    with Solver(chans, precision="f64") as s:
+        s.set_block(32)
+        s.set_graph(64)
+        for _ in range(steps // every):
+            s.step(every)
+            for i in range(len(chans)):
+                us[i].append(s.fields(i)[1][:, 0])
+    ts = every * np.arange(1, steps // every + 1)
+    errs = []
+    for (w, th, s2), ch, u in zip(cases, chans, us):
+        eta = (ch.tau_lb - 0.5) / 3.0
+        ref = maxwell_channel_startup(channel_node_positions(w), ts, w / 2, 1.0, eta, ch.g_inf,
+                                      ch.tau_m, ch.gx, n_modes=4000)
+        errs.append(float(np.abs(np.array(u) - ref).max() / np.abs(ref).max()))
+        say(f"  width {w}, theta {th:.0f}: peak / steady {np.abs(ref).max() / 1e-5:.0f}, "
+            f"error {errs[-1]:.2e}")
+    assert errs[1] <= 1.2e-2 and errs[3] <= 1e-2
+    assert errs[0] / errs[1] >= 3.5 and errs[2] / errs[3] >= 3.5

@@ -272,6 +272,27 @@ def sec4_channel(twall_over_tau0: float, theta: float = 10.0, model: str = "nlm"
     return ch
 
 
+def appendix_ucm_channel(width: int, theta: float, s2: float, u_steady: float = 1e-5) -> Channel:
+    """A wide UCM channel of the appendix (Figs. fMvelstr, funnyMaxwell):
+    1 x width nodes, theta = tau / tau_0, and the dimensionless retardation
+    time S2 = eta_max tau_0 / (rho L^2) with L = width and eta_max =
+    G_inf (tau + tau_0) = eta_inf (theta + 1); the relaxation time is then
+    S1 = S2 tau / tau_0.  tau_LB = 0.9, rho = 1.  The model is linear, so the
+    force only scales the flow: g gives the steady centreline speed
+    u_steady = g H^2 / (2 eta_max), small enough to keep the elastic
+    overshoots (about 15 to 20 times that) at small Mach number.  The window
+    holds 10 tau."""
+    eta = (SEC4_TAU_LB - 0.5) / 3.0
+    tau0 = s2 * width * width / (eta * (theta + 1.0))
+    g_inf = eta / tau0
+    tau = theta * tau0
+    half = width / 2.0
+    eta_max = eta * (theta + 1.0)
+    return Channel(lx=1, ly=width, tau_lb=SEC4_TAU_LB, g_inf=g_inf, tau_m=tau,
+                   gamma_c=math.inf, n_hist=int(math.ceil(10.0 * tau)),
+                   gx=2.0 * u_steady * eta_max / (half * half))
+
+
 ALL = {
     "plain_f64": plain_f64,
     "startup_cessation": startup_cessation,
