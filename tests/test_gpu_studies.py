@@ -184,6 +184,34 @@ def test_cessation_oscillates_for_the_integral_model_only(runs):
         assert low >= -1e-5
 
 
+def test_cessation_velocity_leads_the_shear_stress(runs):
+    """Figs. QT (right) and us: after cessation the velocity and the shear
+    stress decay with a phase shift, the velocity first: it reaches zero
+    while the stress, still dominated by past contributions, is positive;
+    that stress then drives the counter-flow and itself turns negative.  In
+    the instantaneous model the stress follows the velocity gradients and
+    does not oscillate (it dips by a few 1e-5 of its steady value as the
+    profile's shape relaxes; values at y/H = 0.51, each divided by its steady value:
+    the shear stress there is negative, the velocity falling towards the
+    wall)."""
+    n_on = T_ON // EVERY
+    for r in ALL_NLM:
+        run = runs[("nlm", r, 10.0)]
+        u, sxy = run.u[n_on:] / run.u_end, run.sxy[n_on:] / run.sxy[n_on - 1]
+        t_u = int(np.argmax(u <= 0))
+        t_s = int(np.argmax(sxy <= 0))
+        say(f"  integral t_wall/tau_0 = {r}: zero at step {(t_u + 1) * EVERY} (u), "
+            f"{(t_s + 1) * EVERY} (sigma_xy); min sigma_xy / steady {sxy.min():+.3f}")
+        assert (u <= 0).any() and (sxy <= 0).any()
+        assert t_u < t_s and sxy[t_u] > 0
+        assert sxy.min() <= -0.03
+    for r in (0.1, 1.0):
+        run = runs[("instantaneous", r, 10.0)]
+        s_low = (run.sxy[n_on:] / run.sxy[n_on - 1]).min()
+        say(f"  instantaneous t_wall/tau_0 = {r}: min sigma_xy / steady {s_low:+.1e}")
+        assert s_low >= -1e-3
+
+
 def test_cessation_normal_stress_decays_monotonically(runs):
     """Fig. Qall (bottom right), Fig. noffcut: after cessation N1 decays
     monotonically.  Checked at y/H = 0.51 until N1 has fallen to 1e-4 of its
