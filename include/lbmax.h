@@ -424,6 +424,30 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
                              int32_t n_steps);
 lb_status lb_adjoint_end(lb_handle *h, double *dL_dtheta);
 
+/*
+ * Form of the reverse sweep.  steps = 1: two launches per reverse step, the
+ * history transpose (for the entry of that step, a gather over all n_hist
+ * ages of the adjoint stresses) and the lattice part.  steps = M > 1
+ * (default 32, at most 32): the sweep goes in blocks of M reverse steps, the
+ * temporal blocking of the forward pass applied to the transpose.  Each
+ * entry's window is summed in fixed parts: ages 0 .. 31, then 16 ranges that
+ * split the rest.  One pass sums the far ranges for the M entries of a block
+ * (they reach adjoint stresses of later steps, all in the adjoint ring when
+ * the block starts); one launch of one workgroup per channel then runs the
+ * block's steps -- the near ages and the lattice part -- with workgroup
+ * barriers where the per-step form has launch boundaries.  Applies when
+ * every channel has at most 1024 nodes; otherwise the sweep runs per step.
+ * The gradients of the blocked form do not depend on M or on the segment
+ * lengths, bit for bit; they agree with the per-step form up to the order of
+ * the FP64 history sums.  Takes effect at the next lb_adjoint_segment; a
+ * change waits for the sweeps in flight and drops the captured sweeps.
+ * Returns LB_EINVAL for steps outside [1, 32].  lb_get_adjoint_block returns
+ * the form in effect (1 where the blocked form does not apply, 0 for a NULL
+ * handle).
+ */
+lb_status lb_set_adjoint_block(lb_handle *h, int32_t steps);
+int32_t lb_get_adjoint_block(const lb_handle *h);
+
 /* Release host-side handle memory.  Device memory stays the caller's. */
 lb_status lb_destroy(lb_handle *h);
 

@@ -72,6 +72,8 @@ SIGNATURES = {
     "lb_get_block": (ctypes.c_int32, [_H]),
     "lb_set_fused": (ctypes.c_int, [_H, ctypes.c_int32]),
     "lb_get_fused": (ctypes.c_int32, [_H]),
+    "lb_set_adjoint_block": (ctypes.c_int, [_H, ctypes.c_int32]),
+    "lb_get_adjoint_block": (ctypes.c_int32, [_H]),
     "lb_set_persistent": (ctypes.c_int, [_H, ctypes.c_int32]),
     "lb_profile": (ctypes.c_int, [_H, ctypes.c_int32]),
     "lb_kernel_time": (ctypes.c_int, [_H, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64)]),

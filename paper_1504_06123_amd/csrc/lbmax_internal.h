@@ -163,6 +163,10 @@ namespace lbmax {
 // Workgroups over the age window per group of nodes in the adjoint's
 // history transpose.
 constexpr int kAdjGroups = 8;
+// Most reverse steps one blocked launch pair (k_adj_bulk, k_adj_span) takes,
+// and the fixed age ranges the bulk pass splits each entry's window into.
+constexpr int kAdjMaxBlock = 32;
+constexpr int kAdjBulkRanges = 16;
 
 // The step records, loss gradients and recorded shear rates come in two
 // buffers (by segment parity), so the replay of one segment can fill one
@@ -177,6 +181,7 @@ struct alignas(128) AdjChan {
     int64_t off_rec[2];     // [seg_len][10][np] R  n*(t-1) (9 planes), sigma_xy^{t-1}
     int64_t off_dldu[2];    // [seg_len][np] double  dL/du_x of each step
     int64_t off_recs[2];    // [seg_len][np] RH  shear rate s_t pushed at each step
+    int64_t off_bulk;       // [kAdjBulkRanges][kAdjMaxBlock][2][np] double  bulk partial sums
 };
 
 // The adjoint kernels of step t = *t0 + slot (t0 in device memory, so one
@@ -190,6 +195,16 @@ void launch_adj_a(int prec, const ChanDev *chans, const NodeTile *tiles, int n_t
 void launch_adj_b(int prec, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
                   char *aws, const AdjChan *achans, const int64_t *t0, int slot, int buf,
                   hipStream_t st);
+// Blocked reverse sweep (channels of at most kFuseThreads nodes): the block of
+// reverse steps slot_hi, slot_hi - 1, ..., slot_hi - count + 1 (count <=
+// kAdjMaxBlock) as one bulk pass over the adjoint ring for the block's
+// entries and one launch of one workgroup per channel for the steps.
+void launch_adj_bulk(int prec, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
+                     char *aws, const AdjChan *achans, const int64_t *t0, int slot_hi,
+                     int count, int buf, hipStream_t st);
+void launch_adj_span(int prec, const ChanDev *chans, int n_ch, char *aws,
+                     const AdjChan *achans, const int64_t *t0, int slot_hi, int count,
+                     int buf, hipStream_t st);
 void launch_store_i64(int64_t *p, int64_t v, hipStream_t st);
 void launch_adj_reduce(const ChanDev *chans, int n_ch, char *aws, const AdjChan *achans,
                        double *out, hipStream_t st);

@@ -2936,6 +2936,31 @@ __device__ __forceinline__ R coef_div(int y, int yp, int ly)
     return yp == y + 1 ? R(0.5) : (yp == y - 1 ? R(-0.5) : R(0));
 }
 
+// sigma_bar^t of node y (the divergence stencil's transpose applied to
+// fbar(t+1)) into ring slot p = t mod n_hist of the adjoint ring, and nbar(t)
+// (the pull-stream's transpose, the push map, applied to dbar(t+1)).
+template <typename R>
+__device__ __forceinline__ R adj_push(const ChanDev *c, const AdjChan *a, char *aws, int p,
+                                      int y)
+{
+    const int ly = c->ly;
+    const size_t np = (size_t)c->np;
+    R *sring = reinterpret_cast<R *>(aws + a->off_sbar_ring);
+    const R *fbar = reinterpret_cast<const R *>(aws + a->off_fbar);
+    const R *dbar = reinterpret_cast<const R *>(aws + a->off_dbar);
+    R *nbar = reinterpret_cast<R *>(aws + a->off_nbar);
+    R sb = R(0);
+    for (int yy = max(0, y - 2); yy <= min(ly - 1, y + 2); ++yy)
+        sb += coef_div<R>(yy, y, ly) * fbar[yy];
+    sring[(size_t)p * np + y] = sb;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int yt = y + QY[q];
+        nbar[q * np + y] = (yt >= 0 && yt < ly) ? dbar[q * np + yt] : dbar[QOPP[q] * np + y];
+    }
+    return sb;
+}
+
 // Workgroup of k_adj_a: kAdjNodes nodes x kAdjChunks age ranges of one of
 // kAdjGroups parts of the adjoint window; thread = node + kAdjNodes * range,
 // so each wavefront reads kAdjNodes consecutive nodes of 64 / kAdjNodes
@@ -2989,25 +3014,10 @@ __global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(const ChanDev 
     const size_t np = (size_t)c->np;
     const int H = c->n_hist;
     const int p = (int)(t % H);
-    R *sring = reinterpret_cast<R *>(aws + a->off_sbar_ring);
-    const R *fbar = reinterpret_cast<const R *>(aws + a->off_fbar);
-    const R *dbar = reinterpret_cast<const R *>(aws + a->off_dbar);
-    R *nbar = reinterpret_cast<R *>(aws + a->off_nbar);
+    const R *sring = reinterpret_cast<const R *>(aws + a->off_sbar_ring);
 
-    if (own && chunk == 0 && grp == 0) {
-        // sigma_bar^t: transpose of the divergence stencil applied to fbar(t+1)
-        R sb = R(0);
-        for (int yy = max(0, y - 2); yy <= min(ly - 1, y + 2); ++yy)
-            sb += coef_div<R>(yy, y, ly) * fbar[yy];
-        sring[(size_t)p * np + y] = sb;
-
-        // nbar(t): transpose of the pull-stream (the push map) applied to dbar(t+1)
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const int yt = y + QY[q];
-            nbar[q * np + y] = (yt >= 0 && yt < ly) ? dbar[q * np + yt] : dbar[QOPP[q] * np + y];
-        }
-    }
+    if (own && chunk == 0 && grp == 0)
+        adj_push<R>(c, a, aws, p, y);
     __syncthreads();  // sigma_bar^t is in the ring before any range reads age 0
 
     // History transpose for the entry of step t over the ages j of this
@@ -3070,25 +3080,20 @@ __global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(const ChanDev 
     gpart[(size_t)(2 * grp + 1) * np + y] = S1;
 }
 
-template <typename R, typename RH>
-__global__ __launch_bounds__(kBlock) void k_adj_b(const ChanDev *__restrict__ chans,
-                                                  const NodeTile *__restrict__ tiles,
-                                                  char *__restrict__ aws,
-                                                  const AdjChan *__restrict__ achans,
-                                                  const int64_t *__restrict__ t0, int slot,
-                                                  int buf)
+// The lattice part of reverse step `slot` at node y: the step's moments,
+// force and collision recomputed from the recorded n*(t-1) and sigma^{t-1}
+// in the order and arithmetic of k_lb, their transposes (dbar(t), fbar(t)),
+// the loss, the velocity-gradient transpose of the pushed shear rates of y
+// and its neighbours (sbar_of(yy, S0, S1, s) gives sbar at node yy, and at yy
+// = y also the history sums and s for the parameter terms), and the parameter
+// gradients' per-node accumulators.
+template <typename R, typename RH, typename SbarOf>
+__device__ __forceinline__ void adj_lattice(const ChanDev *c, const AdjChan *a, char *aws,
+                                            int slot, int buf, int y, SbarOf &&sbar_of)
 {
-    (void)t0;
-    const NodeTile tl = tiles[blockIdx.x];
-    const ChanDev *c = chans + tl.ch;
-    const AdjChan *a = achans + tl.ch;
-    const int y = tl.n0 + threadIdx.x;
     const int ly = c->ly;
-    if (y >= ly)
-        return;
     const size_t np = (size_t)c->np;
     const R *rec = reinterpret_cast<const R *>(aws + a->off_rec[buf]) + (size_t)slot * 10 * np;
-    const RH *recs = reinterpret_cast<const RH *>(aws + a->off_recs[buf]) + (size_t)slot * np;
     const R *sig = rec + 9 * np;
 
     // forward quantities of the step, in the order and arithmetic of k_lb
@@ -3136,11 +3141,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(const ChanDev *__restrict__ ch
     }
     // the loss and the velocity-gradient transpose
     ux_b += (R)reinterpret_cast<const double *>(aws + a->off_dldu[buf])[(size_t)slot * np + y];
-    const double *part = reinterpret_cast<const double *>(aws + a->off_part);
     double *acc = reinterpret_cast<double *>(aws + a->off_acc);
     for (int yy = max(0, y - 1); yy <= min(ly - 1, y + 1); ++yy) {
         double S0, S1, s;
-        const R sbar = (R)adj_sbar<RH>(recs, c, part, yy, S0, S1, s);
+        const R sbar = (R)sbar_of(yy, S0, S1, s);
         ux_b += coef_grad<R>(yy, y, ly) * sbar;
         if (yy == y) {
             // parameter terms of the history transpose at this node
@@ -3164,6 +3168,233 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(const ChanDev *__restrict__ ch
     for (int q = 0; q < 9; ++q)
         dbar[q * np + y] = (R(1) - om) * A[q] + drho_b + R(QX[q]) * jx_b + R(QY[q]) * jy_b;
     reinterpret_cast<R *>(aws + a->off_fbar)[y] = fx_b;
+}
+
+template <typename R, typename RH>
+__global__ __launch_bounds__(kBlock) void k_adj_b(const ChanDev *__restrict__ chans,
+                                                  const NodeTile *__restrict__ tiles,
+                                                  char *__restrict__ aws,
+                                                  const AdjChan *__restrict__ achans,
+                                                  const int64_t *__restrict__ t0, int slot,
+                                                  int buf)
+{
+    (void)t0;
+    const NodeTile tl = tiles[blockIdx.x];
+    const ChanDev *c = chans + tl.ch;
+    const AdjChan *a = achans + tl.ch;
+    const int y = tl.n0 + threadIdx.x;
+    if (y >= c->ly)
+        return;
+    const RH *recs = reinterpret_cast<const RH *>(aws + a->off_recs[buf]) + (size_t)slot * c->np;
+    const double *part = reinterpret_cast<const double *>(aws + a->off_part);
+    adj_lattice<R, RH>(c, a, aws, slot, buf, y,
+                       [&](int yy, double &S0, double &S1, double &s) {
+                           return adj_sbar<RH>(recs, c, part, yy, S0, S1, s);
+                       });
+}
+
+// Blocked reverse sweep.  The history transpose of the entry pushed at step
+// t sums over the ages j of the window in fixed parts: the near ages [0,
+// kAdjMaxBlock) in order, then kAdjBulkRanges ranges that split [kAdjMaxBlock,
+// n_hist), each in order, added in range order.  For a block of reverse steps
+// t = t0 + slot, slot = slot_hi, slot_hi - 1, ..., slot_hi - count + 1 (count
+// <= kAdjMaxBlock), the far ranges reach adjoint stresses of steps after the
+// block, all in the ring before the block starts: k_adj_bulk sums them for
+// the whole block in one launch, and k_adj_span runs the block's steps one
+// by one with the near ages.  The parts do not depend on the block or the
+// segment a step falls in, so the gradients do not depend on the block size
+// or the segment length; the per-step kernels above split the window in
+// another way and agree up to the order of the FP64 sums.
+//
+// k_adj_bulk: one thread per node, entry of the block and far range
+// (workgroup = node tile x entry x range): B0 = sum w_j sbar^{t+j} E_j and
+// B1 = sum w_j sbar^{t+j} E_j j over the range, E_j = q^j carried from one
+// exp at the range's first age.
+template <typename R, typename RH>
+__global__ __launch_bounds__(kBlock) void k_adj_bulk(const ChanDev *__restrict__ chans,
+                                                     const NodeTile *__restrict__ tiles,
+                                                     int n_tiles, char *__restrict__ aws,
+                                                     const AdjChan *__restrict__ achans,
+                                                     const int64_t *__restrict__ t0, int slot_hi,
+                                                     int count, int buf)
+{
+    const NodeTile tl = tiles[blockIdx.x % n_tiles];
+    const int m = (int)((blockIdx.x / n_tiles) % count);
+    const int r = (int)(blockIdx.x / (n_tiles * count));
+    const ChanDev *c = chans + tl.ch;
+    const AdjChan *a = achans + tl.ch;
+    const int y = tl.n0 + threadIdx.x;
+    if (y >= c->ly)
+        return;
+    const size_t np = (size_t)c->np;
+    const int H = c->n_hist;
+    const int slot = slot_hi - m;
+    const int64_t t = *t0 + slot;
+    // far range r: ages [ja, jb)
+    const int lo = min(kAdjMaxBlock, H);
+    const int ja = lo + (int)((int64_t)(H - lo) * r / kAdjBulkRanges);
+    const int jb = lo + (int)((int64_t)(H - lo) * (r + 1) / kAdjBulkRanges);
+    double S0 = 0.0, S1 = 0.0;
+    if (ja < jb) {
+        const R *sring = reinterpret_cast<const R *>(aws + a->off_sbar_ring);
+        const R s = (R)reinterpret_cast<const RH *>(aws + a->off_recs[buf])[(size_t)slot * np + y];
+        const double rate = c->inv_tau + c->inv_gc * (double)fabs(s);
+        const double q = exp(-rate);
+        double e = exp(-(double)ja * rate);
+        int sl = (int)((t + ja) % H);
+        constexpr int L = 8;  // ring rows loaded ahead
+        for (int j0 = ja; j0 < jb; j0 += L) {
+            R v[L];
+#pragma unroll
+            for (int u = 0; u < L; ++u) {
+                int su = sl + u;
+                if (su >= H)
+                    su -= H;
+                v[u] = j0 + u < jb ? sring[(size_t)su * np + y] : R(0);
+            }
+#pragma unroll
+            for (int u = 0; u < L; ++u) {
+                const int j = j0 + u;
+                if (j < jb) {
+                    const double w = j == H - 1 ? 0.5 : 1.0;
+                    const double x = w * (double)v[u] * e;
+                    S0 += x;
+                    S1 += x * (double)j;
+                    e *= q;
+                }
+            }
+            sl += L;
+            if (sl >= H)
+                sl -= H;
+        }
+    }
+    double *bulk = reinterpret_cast<double *>(aws + a->off_bulk) +
+                   (size_t)r * kAdjMaxBlock * 2 * np;
+    bulk[(size_t)(2 * m) * np + y] = S0;
+    bulk[(size_t)(2 * m + 1) * np + y] = S1;
+}
+
+// k_adj_span: one workgroup per channel runs the block's steps in reverse
+// order; per step, for every node, the push of sigma_bar^t and nbar(t), the
+// near ages of the history transpose followed by the far range sums, with
+// sbar_t and the node's sums into LDS; a barrier; the lattice part with the
+// neighbours' sbar from LDS; and a barrier before the next step reads dbar
+// and fbar.  kAdjSpanThreads threads loop over the channel's nodes (the
+// lattice part needs about 180 registers a lane).  The near ages of the
+// block's entries reach the steps from kAdjMaxBlock - 1 before the block to
+// its end: channels of up to kAdjSpanLdsNodes nodes keep those adjoint
+// stresses in an LDS ring of 2 kAdjMaxBlock rows (indexed by step), filled
+// from the adjoint ring once at the start and by each push; wider channels
+// read the adjoint ring.  Both read the same values in the same order.
+constexpr int kAdjSpanThreads = 256;
+constexpr int kAdjSpanLdsNodes = 128;
+constexpr int kAdjNearRows = 2 * kAdjMaxBlock;
+
+template <typename R, typename RH>
+__global__ __launch_bounds__(kAdjSpanThreads) void k_adj_span(const ChanDev *__restrict__ chans,
+                                                              char *__restrict__ aws,
+                                                              const AdjChan *__restrict__ achans,
+                                                              const int64_t *__restrict__ t0,
+                                                              int slot_hi, int count, int buf)
+{
+    __shared__ double s_sbar[kFuseThreads], s_S0[kFuseThreads], s_S1[kFuseThreads],
+        s_s[kFuseThreads];
+    __shared__ R s_near[kAdjNearRows][kAdjSpanLdsNodes];
+    const ChanDev *c = chans + blockIdx.x;
+    const AdjChan *a = achans + blockIdx.x;
+    const int ly = c->ly;
+    const bool lds = ly <= kAdjSpanLdsNodes;
+    const size_t np = (size_t)c->np;
+    const int H = c->n_hist;
+    const int jn = min(kAdjMaxBlock, H) - 1;  // last near age
+    const R *sring = reinterpret_cast<const R *>(aws + a->off_sbar_ring);
+    const RH *recs = reinterpret_cast<const RH *>(aws + a->off_recs[buf]);
+    const double *bulk = reinterpret_cast<const double *>(aws + a->off_bulk);
+    const size_t rstride = (size_t)kAdjMaxBlock * 2 * np;
+    const int64_t t_hi = *t0 + slot_hi;
+    if (lds) {
+        // steps t_hi + 1 .. t_hi + jn, pushed before the block
+        for (int i = threadIdx.x; i < jn * ly; i += kAdjSpanThreads) {
+            const int k = 1 + i / ly, y = i % ly;
+            const int64_t u = t_hi + k;
+            s_near[u % kAdjNearRows][y] = sring[(size_t)(u % H) * np + y];
+        }
+        __syncthreads();
+    }
+    for (int m = 0; m < count; ++m) {
+        const int64_t t = t_hi - m;
+        const int p = (int)(t % H);
+        for (int y = threadIdx.x; y < ly; y += kAdjSpanThreads) {
+            // loads that do not wait for this step's push
+            const double s = (double)recs[(size_t)(slot_hi - m) * np + y];
+            double B0[kAdjBulkRanges], B1[kAdjBulkRanges];
+#pragma unroll
+            for (int r = 0; r < kAdjBulkRanges; ++r) {
+                B0[r] = bulk[r * rstride + (size_t)(2 * m) * np + y];
+                B1[r] = bulk[r * rstride + (size_t)(2 * m + 1) * np + y];
+            }
+            const R pushed = adj_push<R>(c, a, aws, p, y);
+            const double rate = c->inv_tau + c->inv_gc * fabs(s);
+            const double q = exp(-rate);
+            double S0 = 0.0, S1 = 0.0, e = 1.0;
+            if (lds) {
+                s_near[t % kAdjNearRows][y] = pushed;
+                for (int j = 0; j <= jn; ++j) {
+                    const double w = (j == 0 || j == H - 1) ? 0.5 : 1.0;
+                    const double x = w * (double)s_near[(t + j) % kAdjNearRows][y] * e;
+                    S0 += x;
+                    S1 += x * (double)j;
+                    e *= q;
+                }
+            } else {
+                int sl = p;
+                constexpr int L = 8;  // ring rows loaded together
+                for (int j0 = 0; j0 <= jn; j0 += L) {
+                    R v[L];
+#pragma unroll
+                    for (int u = 0; u < L; ++u) {
+                        int su = sl + u;
+                        if (su >= H)
+                            su -= H;
+                        v[u] = j0 + u <= jn ? sring[(size_t)su * np + y] : R(0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < L; ++u) {
+                        const int j = j0 + u;
+                        if (j <= jn) {
+                            const double w = (j == 0 || j == H - 1) ? 0.5 : 1.0;
+                            const double x = w * (double)v[u] * e;
+                            S0 += x;
+                            S1 += x * (double)j;
+                            e *= q;
+                        }
+                    }
+                    sl += L;
+                    if (sl >= H)
+                        sl -= H;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kAdjBulkRanges; ++r) {
+                S0 += B0[r];
+                S1 += B1[r];
+            }
+            s_S0[y] = S0;
+            s_S1[y] = S1;
+            s_s[y] = s;
+            s_sbar[y] = c->g_inf * (S0 - fabs(s) * S1 * c->inv_gc);
+        }
+        __syncthreads();  // every node's sbar_t is in LDS
+        for (int y = threadIdx.x; y < ly; y += kAdjSpanThreads)
+            adj_lattice<R, RH>(c, a, aws, slot_hi - m, buf, y,
+                               [&](int yy, double &S0, double &S1, double &s) {
+                                   S0 = s_S0[yy];
+                                   S1 = s_S1[yy];
+                                   s = s_s[yy];
+                                   return s_sbar[yy];
+                               });
+        __syncthreads();  // dbar(t), fbar(t) written before the next step reads them
+    }
 }
 
 // Sum the per-node parameter gradients of every channel in node order.
@@ -3211,6 +3442,25 @@ void launch_adj_b(int prec, const ChanDev *chans, const NodeTile *tiles, int n_t
 {
     LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_b<P, H>), dim3(n_tiles), dim3(kBlock), 0, st,
                                            chans, tiles, aws, achans, t0, slot, buf));
+}
+
+void launch_adj_bulk(int prec, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
+                     char *aws, const AdjChan *achans, const int64_t *t0, int slot_hi,
+                     int count, int buf, hipStream_t st)
+{
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_bulk<P, H>),
+                                           dim3(n_tiles * count * kAdjBulkRanges), dim3(kBlock),
+                                           0, st, chans, tiles, n_tiles, aws, achans, t0,
+                                           slot_hi, count, buf));
+}
+
+void launch_adj_span(int prec, const ChanDev *chans, int n_ch, char *aws,
+                     const AdjChan *achans, const int64_t *t0, int slot_hi, int count,
+                     int buf, hipStream_t st)
+{
+    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_span<P, H>), dim3(n_ch),
+                                           dim3(kAdjSpanThreads), 0, st, chans, aws, achans, t0,
+                                           slot_hi, count, buf));
 }
 
 __global__ void k_store_i64(int64_t *p, int64_t v)

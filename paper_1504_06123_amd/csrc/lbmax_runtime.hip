@@ -343,6 +343,7 @@ struct lb_handle {
     void *scratch = nullptr;      // the library's device array on this handle's GPU
     int64_t *d_adj_t0 = nullptr;     // [2]: first step of the segment in each record buffer
     ChanDev *d_adj_snap = nullptr;   // [2][n_ch]: channel table of the segment in each buffer
+    double *d_adj_stage[2] = {nullptr, nullptr};  // dL/du_x as given, per record buffer
     // the reverse sweeps run on their own stream, beside the next segment's
     // replay on the handle's stream; events order the two
     hipStream_t adj_stream = nullptr;
@@ -353,6 +354,7 @@ struct lb_handle {
     // captured reverse sweeps by segment length (for this adjoint workspace)
     std::vector<std::pair<int, hipGraphExec_t>> adj_execs;  // key: 2 * n_steps + buffer
     int adj_seg_len = 0;
+    int adj_block = kAdjMaxBlock;  // lb_set_adjoint_block
     int64_t adj_next = -1;  // the next segment must end at this step (-1: no sweep)
     // timing: event pairs recorded around launches, resolved on demand
     bool profile = false;
@@ -764,6 +766,7 @@ size_t state_size(const lb_handle *h)
 // not null (no allocation: the lb_adjoint_begin_noalloc path uses it too).
 struct AdjLayout {
     size_t total = 0, off_table = 0, off_out = 0, off_t0 = 0, off_snap = 0;
+    size_t off_stage[2] = {0, 0};  // [seg_len][sum of nodes] double: dL/du_x as the caller gives it
 };
 
 AdjLayout adj_layout(const lb_handle *h, int seg_len, AdjChan *chans)
@@ -779,6 +782,13 @@ AdjLayout adj_layout(const lb_handle *h, int seg_len, AdjChan *chans)
     off = align_up(off + 2 * sizeof(int64_t), 256);
     P.off_snap = off;
     off = align_up(off + 2 * (size_t)h->n_ch * sizeof(ChanDev), 256);
+    size_t total_nodes = 0;
+    for (const ChanDev &c : h->plan.chans)
+        total_nodes += (size_t)c.n;
+    for (int b = 0; b < 2; ++b) {
+        P.off_stage[b] = off;
+        off = align_up(off + (size_t)seg_len * total_nodes * sizeof(double), 256);
+    }
     for (int ci = 0; ci < h->n_ch; ++ci) {
         const ChanDev &c = h->plan.chans[ci];
         const size_t plane = (size_t)c.np * R;
@@ -795,6 +805,9 @@ AdjLayout adj_layout(const lb_handle *h, int seg_len, AdjChan *chans)
         off = align_up(off + (size_t)kAdjGroups * 2 * c.np * sizeof(double), 256);
         a.off_acc = (int64_t)off;
         off = align_up(off + 4 * (size_t)c.np * sizeof(double), 256);
+        a.off_bulk = (int64_t)off;
+        off = align_up(off + (size_t)kAdjBulkRanges * kAdjMaxBlock * 2 * c.np * sizeof(double),
+                       256);
         for (int b = 0; b < 2; ++b) {
             a.off_rec[b] = (int64_t)off;
             off = align_up(off + (size_t)seg_len * 10 * plane, 256);
@@ -840,6 +853,54 @@ std::string adjoint_unsupported(const lb_handle *h, int seg_len)
 // Segments up to this length replay a captured reverse sweep.
 constexpr int kAdjGraphMaxSteps = 1024;
 
+// Reverse steps per blocked launch pair in effect: the setting where every
+// channel fits one workgroup of the span, else 1 (the per-step kernels).
+int adj_block_in_effect(const lb_handle *h)
+{
+    if (h->adj_block <= 1)
+        return 1;
+    for (const ChanDev &c : h->plan.chans)
+        if (c.ly > kFuseThreads)
+            return 1;
+    return h->adj_block;
+}
+
+// Enqueue the reverse sweep of slots n_steps - 1 .. 0 on record buffer buf:
+// k_adj_a and k_adj_b per step, or per block of reverse steps one bulk pass
+// and one span launch.
+lb_status enqueue_adj_sweep(lb_handle *h, int n_steps, int buf, hipStream_t st, bool check)
+{
+    const ChanDev *snap = h->d_adj_snap + (size_t)buf * h->n_ch;
+    const int64_t *t0 = h->d_adj_t0 + buf;
+    const int blk = adj_block_in_effect(h);
+    if (blk > 1) {
+        for (int hi = n_steps - 1; hi >= 0; hi -= blk) {
+            const int count = std::min(blk, hi + 1);
+            launch_adj_bulk(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans,
+                            t0, hi, count, buf, st);
+            launch_adj_span(h->pc, snap, h->n_ch, h->aws, h->d_achans, t0, hi, count, buf, st);
+            if (check) {
+                lb_status s = check_launch(h, "adjoint block");
+                if (s != LB_OK)
+                    return s;
+            }
+        }
+        return LB_OK;
+    }
+    for (int k = n_steps - 1; k >= 0; --k) {
+        launch_adj_a(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans, t0, k,
+                     buf, st);
+        launch_adj_b(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans, t0, k,
+                     buf, st);
+        if (check) {
+            lb_status s = check_launch(h, "adjoint step");
+            if (s != LB_OK)
+                return s;
+        }
+    }
+    return LB_OK;
+}
+
 void drop_adj_graphs(lb_handle *h)
 {
     for (auto &e : h->adj_execs)
@@ -864,13 +925,7 @@ lb_status adj_sweep_graph(lb_handle *h, int n_steps, int buf, hipGraphExec_t *ou
     if (!h->cap_stream)
         HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    const ChanDev *snap = h->d_adj_snap + (size_t)buf * h->n_ch;
-    for (int k = n_steps - 1; k >= 0; --k) {
-        launch_adj_a(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans,
-                     h->d_adj_t0 + buf, k, buf, h->cap_stream);
-        launch_adj_b(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans,
-                     h->d_adj_t0 + buf, k, buf, h->cap_stream);
-    }
+    (void)enqueue_adj_sweep(h, n_steps, buf, h->cap_stream, false);
     const hipError_t cap = hipGetLastError();
     hipGraph_t g = nullptr;
     const hipError_t end = hipStreamEndCapture(h->cap_stream, &g);
@@ -1322,6 +1377,31 @@ lb_status lb_set_fused(lb_handle *h, int32_t mode)
     return LB_OK;
 }
 
+lb_status lb_set_adjoint_block(lb_handle *h, int32_t steps)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    if (steps < 1 || steps > kAdjMaxBlock)
+        return fail(LB_EINVAL, "adjoint block must be in [1, " + std::to_string(kAdjMaxBlock) +
+                                   "]");
+    if (steps != h->adj_block) {
+        // the captured sweeps hold the old launch sequence; none may be in
+        // flight when they are destroyed
+        s = adj_drain(h);
+        if (s != LB_OK)
+            return s;
+        drop_adj_graphs(h);
+        h->adj_block = steps;
+    }
+    return LB_OK;
+}
+
+int32_t lb_get_adjoint_block(const lb_handle *h)
+{
+    return h ? adj_block_in_effect(h) : 0;
+}
+
 int32_t lb_get_fused(const lb_handle *h)
 {
     if (!h || !h->fuse_ok || h->fuse_mode == 0 || h->block <= 1)
@@ -1439,6 +1519,8 @@ lb_status adjoint_begin_at(lb_handle *h, char *aws, size_t bytes, int seg_len)
     h->d_adj_out = reinterpret_cast<double *>(h->aws + P.off_out);
     h->d_adj_t0 = reinterpret_cast<int64_t *>(h->aws + P.off_t0);
     h->d_adj_snap = reinterpret_cast<ChanDev *>(h->aws + P.off_snap);
+    for (int b = 0; b < 2; ++b)
+        h->d_adj_stage[b] = reinterpret_cast<double *>(h->aws + P.off_stage[b]);
     h->adj_seg_len = seg_len;
     h->adj_segments = 0;
     launch_fill_zero(h->aws, P.total, h->stream);
@@ -1540,11 +1622,17 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
         return s2;
     // The segment's shear rates (ring rows t0 .. t0 + n_steps - 1, wrapping),
     // dL/du_x (host [n_steps][sum of nodes]) and the channel table into the
-    // buffer, so the sweep reads nothing the next replay overwrites.
+    // buffer, so the sweep reads nothing the next replay overwrites.  dL/du_x
+    // crosses to the device in one contiguous copy (a strided copy from
+    // pageable host memory goes row by row) and is spread over the channels'
+    // planes on the device.
     const size_t RH = history_bytes(h->prec);
     size_t total_nodes = 0;
     for (const ChanDev &c : h->plan.chans)
         total_nodes += (size_t)c.n;
+    HIP_TRY(h, hipMemcpyAsync(h->d_adj_stage[buf], dL_dux,
+                              (size_t)n_steps * total_nodes * sizeof(double),
+                              hipMemcpyHostToDevice, h->stream));
     size_t col = 0;
     for (int ci = 0; ci < h->n_ch; ++ci) {
         const ChanDev &c = h->plan.chans[ci];
@@ -1560,9 +1648,9 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
                                       h->ws + c.off_ring_s, (size_t)(n_steps - run1) * rowb,
                                       hipMemcpyDeviceToDevice, h->stream));
         HIP_TRY(h, hipMemcpy2DAsync(h->aws + a.off_dldu[buf], (size_t)c.np * sizeof(double),
-                                    dL_dux + col, total_nodes * sizeof(double),
+                                    h->d_adj_stage[buf] + col, total_nodes * sizeof(double),
                                     (size_t)c.n * sizeof(double), (size_t)n_steps,
-                                    hipMemcpyHostToDevice, h->stream));
+                                    hipMemcpyDeviceToDevice, h->stream));
         col += (size_t)c.n;
     }
     ChanDev *snap = h->d_adj_snap + (size_t)buf * h->n_ch;
@@ -1586,15 +1674,9 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
     } else {
         // longer segments launch directly (a graph of 2 n_steps nodes would
         // cost more to build than it saves)
-        for (int k = n_steps - 1; k >= 0; --k) {
-            launch_adj_a(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans,
-                         h->d_adj_t0 + buf, k, buf, h->adj_stream);
-            launch_adj_b(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans,
-                         h->d_adj_t0 + buf, k, buf, h->adj_stream);
-            s = check_launch(h, "adjoint step");
-            if (s != LB_OK)
-                return s;
-        }
+        s = enqueue_adj_sweep(h, n_steps, buf, h->adj_stream, true);
+        if (s != LB_OK)
+            return s;
     }
     HIP_TRY(h, hipEventRecord(h->adj_ev_sweep[buf], h->adj_stream));
     h->adj_sweep_pending[buf] = true;

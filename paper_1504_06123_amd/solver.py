@@ -147,6 +147,15 @@ class Solver:
         LDS-resident form where it applies, 2 fused without it."""
         _lib.check(self.lib.lb_set_fused(self.h, int(mode)), "lb_set_fused")
 
+    def set_adjoint_block(self, steps: int):
+        """Reverse steps per blocked launch pair of the adjoint sweep (1: the
+        per-step kernels); see lb_set_adjoint_block."""
+        _lib.check(self.lib.lb_set_adjoint_block(self.h, int(steps)), "lb_set_adjoint_block")
+
+    @property
+    def adjoint_block(self) -> int:
+        return int(self.lib.lb_get_adjoint_block(self.h))
+
     @property
     def fused(self) -> int:
         """0 not fused, 1 fused launch, 2 its LDS-resident form."""

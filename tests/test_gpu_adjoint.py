@@ -54,11 +54,13 @@ def oracle_fd(ch, target, steps, every, h_rel=1e-6):
     return np.array(grad)
 
 
-def gpu_gradient(lb, ch, precision, steps, every, seg_len, target, block=1):
+def gpu_gradient(lb, ch, precision, steps, every, seg_len, target, block=1, adjoint_block=None):
     from paper_1504_06123_amd import adjoint
     with lb.Solver([ch], precision=precision) as s:
         if block != 1:
             s.set_block(block)
+        if adjoint_block is not None:
+            s.set_adjoint_block(adjoint_block)
         u, ckpts = adjoint.forward(s, steps, every, seg_len)
         g = adjoint.backward(s, ckpts, steps, every, seg_len, 2 * (u - target))
     return u, g[0]
@@ -99,16 +101,104 @@ def test_adjoint_f64_tight(lb):
     assert np.all(rel < 1e-6), rel
 
 
-def test_adjoint_segment_length_and_blocking_invariance(lb):
+@pytest.mark.parametrize("adjoint_block", [32, 1])
+def test_adjoint_segment_length_and_blocking_invariance(lb, adjoint_block):
+    """Both forms of the reverse sweep give the same gradient, bit for bit,
+    for any segment length; the forward pass's temporal blocking changes it
+    only by rounding."""
     ch = small_channel()
     steps, every = 300, 25
-    say("case adjoint segment invariance")
+    say(f"case adjoint segment invariance, adjoint block {adjoint_block}")
     target = oracle_samples(ch.replace(gx=1.5e-5), steps, every)
-    _, g1 = gpu_gradient(lb, ch, "f64", steps, every, 64, target)
-    _, g2 = gpu_gradient(lb, ch, "f64", steps, every, 37, target)
+    _, g1 = gpu_gradient(lb, ch, "f64", steps, every, 64, target, adjoint_block=adjoint_block)
+    _, g2 = gpu_gradient(lb, ch, "f64", steps, every, 37, target, adjoint_block=adjoint_block)
     assert np.array_equal(g1, g2)
     _, g3 = gpu_gradient(lb, ch, "f64", steps, every, 64, target, block=4)
     assert np.all(np.abs(g3 - g1) <= 1e-10 * np.abs(g1))
+
+
+def _wide_channel():
+    return workloads.Channel(lx=1, ly=200, tau_lb=1.0, g_inf=2e-3, tau_m=40.0, gamma_c=0.05,
+                             n_hist=150, gx=2e-7)
+
+
+@pytest.mark.parametrize("case", ["1x16, window 64", "window 16, shorter than a block",
+                                  "two channels", "1x200, near ages from the ring"])
+def test_blocked_sweep_matches_the_per_step_sweep(lb, case):
+    """The blocked reverse sweep (the default) against the per-step one: the
+    same terms of the history transpose summed in another order, so equal to
+    a few FP64 roundings (bound 1e-12 relative per component); and the
+    blocked gradient is the same, bit for bit, for every block size and
+    segment length, since each entry's window is split at fixed ages."""
+    from paper_1504_06123_amd import adjoint
+    c0 = small_channel()
+    c1 = workloads.Channel(lx=1, ly=23, tau_lb=0.9, g_inf=1e-3, tau_m=25.0, gamma_c=0.08,
+                           n_hist=48, gx=1.2e-5)
+    chans, seg, seg2 = {
+        "1x16, window 64": ([c0], 64, 37),
+        "window 16, shorter than a block": ([c0.replace(n_hist=16)], 16, 11),
+        "two channels": ([c0, c1], 40, 23),
+        "1x200, near ages from the ring": ([_wide_channel()], 64, 37),
+    }[case]
+    steps, every = 300, 25
+    say(f"case blocked vs per-step adjoint sweep, {case}")
+    target = np.concatenate([oracle_samples(c.replace(gx=0.8 * c.gx), steps, every)
+                             for c in chans], axis=1)
+
+    def grad(ablock, seg_len):
+        with lb.Solver(chans, precision="f64") as s:
+            s.set_adjoint_block(ablock)
+            assert s.adjoint_block == ablock
+            u, ckpts = adjoint.forward(s, steps, every, seg_len)
+            return np.asarray(adjoint.backward(s, ckpts, steps, every, seg_len,
+                                               2 * (u - target)))
+
+    per_step = grad(1, seg)
+    blocked = grad(32, seg)
+    rel = np.abs(blocked - per_step) / np.abs(per_step)
+    say(f"  per-step {per_step}\n  blocked  {blocked}\n  rel {rel.max():.2e}")
+    assert np.all(rel <= 1e-12), rel
+    assert np.array_equal(grad(7, seg), blocked)
+    assert np.array_equal(grad(32, seg2), blocked)
+
+
+def test_adjoint_block_setting(lb):
+    """lb_set_adjoint_block takes 1 .. 32 and refuses the rest; channels
+    wider than 1024 nodes sweep per step whatever the setting."""
+    from paper_1504_06123_amd import _lib
+    say("case adjoint block setting")
+    with lb.Solver([small_channel()], precision="f64") as s:
+        assert s.adjoint_block == 32
+        for bad in (0, -1, 33):
+            assert s.lib.lb_set_adjoint_block(s.h, bad) == _lib.LB_EINVAL
+            assert "adjoint block" in _lib.last_error()
+        assert s.adjoint_block == 32
+        s.set_adjoint_block(5)
+        assert s.adjoint_block == 5
+    wide = workloads.Channel(lx=1, ly=1100, tau_lb=1.0, g_inf=1e-3, tau_m=10.0, gamma_c=0.1,
+                             n_hist=30, gx=1e-8)
+    with lb.Solver([small_channel(), wide], precision="f64") as s:
+        s.set_adjoint_block(32)
+        assert s.adjoint_block == 1
+
+
+def test_adjoint_dot_product_above_1024_nodes(lb):
+    """A 1 x 1100 channel (per-step sweep: too wide for the blocked one) in
+    the UCM limit, linear in the body force: <J e_gx, w> = <u, w> / g_x."""
+    from paper_1504_06123_amd import adjoint
+    ch = workloads.Channel(lx=1, ly=1100, tau_lb=1.0, g_inf=1e-3, tau_m=10.0,
+                           gamma_c=math.inf, n_hist=30, gx=1e-8)
+    steps, every, seg = 120, 10, 30
+    say("case adjoint dot product, 1x1100 UCM (per-step sweep)")
+    with lb.Solver([ch], precision="f64") as s:
+        assert s.adjoint_block == 1
+        u, ckpts = adjoint.forward(s, steps, every, seg)
+        w = _weights(u.shape, 1507)
+        g = adjoint.backward(s, ckpts, steps, every, seg, w)[0]
+    jv_w = float(np.sum(u * w) / ch.gx)
+    scale = float(np.sum(np.abs(u * w)) / ch.gx)
+    say(f"  <J e_gx, w> = {jv_w:.15e}, adjoint {g[3]:.15e}")
+    assert abs(g[3] - jv_w) <= 1e-10 * scale
 
 
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-5), ("f32", 1e-4), ("f32p64", 1e-4)])
