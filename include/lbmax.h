@@ -387,13 +387,16 @@ lb_status lb_set_params(lb_handle *h, int32_t ch, double g_inf, double tau_m,
  * (lb_adjoint_begin with another buffer or seg_len drops the graphs;
  * lb_destroy frees them); longer segments launch their kernels directly.
  *
- * Streams: lb_adjoint_segment returns once the segment's replay (and the
- * copy of dL_dux) has finished on the handle's stream, so ckpt and dL_dux
- * may be reused at once.  The segment's reverse sweep runs on a second
- * stream that the handle creates at the first lb_adjoint_begin (default
- * priority; destroyed by lb_destroy), ordered against the replays by events
- * and reading records that are double-buffered in the adjoint workspace, so
- * it overlaps the replay of the next segment.  lb_adjoint_end waits for the
+ * Streams: lb_adjoint_segment returns once dL_dux has been copied to the
+ * device, so dL_dux may be reused at once; the segment's replay runs on in
+ * the handle's stream, so ckpt must stay unchanged until lb_adjoint_end
+ * returns.  The checkpoint's header and forces are read over a third stream,
+ * so the next segment's state copies queue behind the replay in flight.
+ * The segment's reverse sweep runs on a second stream; both streams are
+ * created at the first lb_adjoint_begin (default priority; destroyed by
+ * lb_destroy).  The sweep is ordered against the replays by events and
+ * reads records that are double-buffered in the adjoint workspace, so it
+ * overlaps the replay of the next segment.  lb_adjoint_end waits for the
  * last sweep.  The workspace must stay allocated until lb_adjoint_end.
  *
  * Against a single call per segment that takes (t0, t1, sample_every) and

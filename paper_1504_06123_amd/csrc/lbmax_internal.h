@@ -181,7 +181,7 @@ struct alignas(128) AdjChan {
     int64_t off_rec[2];     // [seg_len][10][np] R  n*(t-1) (9 planes), sigma_xy^{t-1}
     int64_t off_dldu[2];    // [seg_len][np] double  dL/du_x of each step
     int64_t off_recs[2];    // [seg_len][np] RH  shear rate s_t pushed at each step
-    int64_t off_bulk;       // [kAdjBulkRanges][kAdjMaxBlock][2][np] double  bulk partial sums
+    int64_t off_bulk;       // [kAdjMaxBlock][2][np] double  far sums of a reverse block
 };
 
 // The adjoint kernels of step t = *t0 + slot (t0 in device memory, so one
@@ -198,14 +198,20 @@ void launch_adj_b(int prec, const ChanDev *chans, const NodeTile *tiles, int n_t
 // Blocked reverse sweep (channels of at most kFuseThreads nodes): the block of
 // reverse steps slot_hi, slot_hi - 1, ..., slot_hi - count + 1 (count <=
 // kAdjMaxBlock) as one bulk pass over the adjoint ring for the block's
-// entries and one launch of one workgroup per channel for the steps.
+// entries and one launch of one workgroup per channel for the steps (with
+// the block's adjoint state on chip when max_ly, the widest channel's ly, is
+// at most 128).
 void launch_adj_bulk(int prec, const ChanDev *chans, const NodeTile *tiles, int n_tiles,
                      char *aws, const AdjChan *achans, const int64_t *t0, int slot_hi,
                      int count, int buf, hipStream_t st);
-void launch_adj_span(int prec, const ChanDev *chans, int n_ch, char *aws,
+void launch_adj_span(int prec, const ChanDev *chans, int n_ch, int max_ly, char *aws,
                      const AdjChan *achans, const int64_t *t0, int slot_hi, int count,
                      int buf, hipStream_t st);
 void launch_store_i64(int64_t *p, int64_t v, hipStream_t st);
+// Step records on in the device channel table (each channel's record area of
+// buffer buf in the adjoint workspace aws, from step t0), or off (aws null).
+void launch_set_record(ChanDev *chans, const AdjChan *achans, int n_ch, char *aws, int buf,
+                       int64_t t0, hipStream_t st);
 void launch_adj_reduce(const ChanDev *chans, int n_ch, char *aws, const AdjChan *achans,
                        double *out, hipStream_t st);
 void launch_set_params(ChanDev *chans, int ch, double g_inf, double tau_m, double gamma_c,

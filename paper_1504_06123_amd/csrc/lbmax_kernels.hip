@@ -3086,34 +3086,62 @@ __global__ __launch_bounds__(kAdjNodes * kAdjChunks) void k_adj_a(const ChanDev 
 // the loss, the velocity-gradient transpose of the pushed shear rates of y
 // and its neighbours (sbar_of(yy, S0, S1, s) gives sbar at node yy, and at yy
 // = y also the history sums and s for the parameter terms), and the parameter
-// gradients' per-node accumulators.
-template <typename R, typename RH, typename SbarOf>
-__device__ __forceinline__ void adj_lattice(const ChanDev *c, const AdjChan *a, char *aws,
-                                            int slot, int buf, int y, SbarOf &&sbar_of)
+// gradients' per-node accumulators.  Split into the loads of the step's
+// records (adj_load_step), which do not depend on the sweep, and the
+// arithmetic (adj_lattice_core), which takes nbar(t) as A, adds to the
+// accumulators through acc_add(k, v) and hands out dbar(t) and fbar(t)
+// through put(q, v) (q = 9: fbar).
+template <typename R>
+struct AdjStepIn {
+    R d[9];     // pulled populations n*(t-1) at node y
+    R sg[3];    // sigma^{t-1} of the divergence stencil at node y
+    double dldu;  // dL/du_x(t) at node y
+};
+
+template <typename R>
+__device__ __forceinline__ void adj_load_step(const ChanDev *c, const AdjChan *a, const char *aws,
+                                              int slot, int buf, int y, AdjStepIn<R> &in)
 {
     const int ly = c->ly;
     const size_t np = (size_t)c->np;
     const R *rec = reinterpret_cast<const R *>(aws + a->off_rec[buf]) + (size_t)slot * 10 * np;
     const R *sig = rec + 9 * np;
-
-    // forward quantities of the step, in the order and arithmetic of k_lb
-    R d[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int ys = y - QY[q];
-        d[q] = (ys >= 0 && ys < ly) ? rec[q * np + ys] : rec[QOPP[q] * np + y];
+        in.d[q] = (ys >= 0 && ys < ly) ? rec[q * np + ys] : rec[QOPP[q] * np + y];
     }
+    // stencil nodes: (0, 1, 2) at the first node, (y, y - 1, y - 2) at the
+    // last, (y + 1, y - 1, -) inside; every load is issued (indices selected
+    // and clamped to the channel), so the loads of a step stay in one
+    // sequence for the wait counters
+    const int i0 = y == 0 ? 0 : (y == ly - 1 ? y : y + 1);
+    const int i1 = y == 0 ? min(1, ly - 1) : y - 1;
+    const int i2 = y == 0 ? min(2, ly - 1) : (y == ly - 1 ? max(y - 2, 0) : y);
+    in.sg[0] = sig[i0];
+    in.sg[1] = sig[i1];
+    in.sg[2] = sig[i2];
+    in.dldu = reinterpret_cast<const double *>(aws + a->off_dldu[buf])[(size_t)slot * np + y];
+}
+
+template <typename R, typename SbarOf, typename AccAdd, typename Put>
+__device__ __forceinline__ void adj_lattice_core(const ChanDev *c, int y, const AdjStepIn<R> &in,
+                                                 const R (&A)[9], SbarOf &&sbar_of,
+                                                 AccAdd &&acc_add, Put &&put)
+{
+    const int ly = c->ly;
+    const R *d = in.d;
     const R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
     const R jx = (d[1] - d[2]) + (d[5] - d[6]) + (d[7] - d[8]);
     const R jy = (d[3] - d[4]) + (d[5] - d[6]) + (d[8] - d[7]);
     const R rho = R(1) + drho;
     R dys;
     if (y == 0)
-        dys = R(0.5) * (R(-3) * sig[0] + R(4) * sig[1] - sig[2]);
+        dys = R(0.5) * (R(-3) * in.sg[0] + R(4) * in.sg[1] - in.sg[2]);
     else if (y == ly - 1)
-        dys = R(0.5) * (R(3) * sig[y] - R(4) * sig[y - 1] + sig[y - 2]);
+        dys = R(0.5) * (R(3) * in.sg[0] - R(4) * in.sg[1] + in.sg[2]);
     else
-        dys = R(0.5) * (sig[y + 1] - sig[y - 1]);
+        dys = R(0.5) * (in.sg[0] - in.sg[1]);
     const R gx = (R)c->gx;
     const R fx = dys + rho * gx;
     const R ux = (jx + R(0.5) * fx) / rho;
@@ -3122,12 +3150,9 @@ __device__ __forceinline__ void adj_lattice(const ChanDev *c, const AdjChan *a, 
     const R pf = R(1) - R(0.5) * om;
 
     // collision + forcing transpose
-    const R *nbar = reinterpret_cast<const R *>(aws + a->off_nbar);
-    R A[9];
     R drho_b = R(0), ux_b = R(0), uy_b = R(0), fx_b = R(0);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        A[q] = nbar[q * np + y];
         const R cx = R(QX[q]), cy = R(QY[q]);
         const R w = qweight<R>(q);
         const R cu = cx * ux + cy * uy;
@@ -3140,8 +3165,7 @@ __device__ __forceinline__ void adj_lattice(const ChanDev *c, const AdjChan *a, 
         fx_b += A[q] * w * pf * (R(3) * (cx - ux) + R(9) * cu * cx);
     }
     // the loss and the velocity-gradient transpose
-    ux_b += (R)reinterpret_cast<const double *>(aws + a->off_dldu[buf])[(size_t)slot * np + y];
-    double *acc = reinterpret_cast<double *>(aws + a->off_acc);
+    ux_b += (R)in.dldu;
     for (int yy = max(0, y - 1); yy <= min(ly - 1, y + 1); ++yy) {
         double S0, S1, s;
         const R sbar = (R)sbar_of(yy, S0, S1, s);
@@ -3149,9 +3173,9 @@ __device__ __forceinline__ void adj_lattice(const ChanDev *c, const AdjChan *a, 
         if (yy == y) {
             // parameter terms of the history transpose at this node
             const double G = c->g_inf, as = fabs(s);
-            acc[y] += s * S0;
-            acc[np + y] += G * s * S1 * c->inv_tau * c->inv_tau;
-            acc[2 * np + y] += G * s * as * S1 * c->inv_gc * c->inv_gc;
+            acc_add(0, s * S0);
+            acc_add(1, G * s * S1 * c->inv_tau * c->inv_tau);
+            acc_add(2, G * s * as * S1 * c->inv_gc * c->inv_gc);
         }
     }
     // u = (j + f/2) / rho
@@ -3161,13 +3185,37 @@ __device__ __forceinline__ void adj_lattice(const ChanDev *c, const AdjChan *a, 
     drho_b -= (ux * ux_b + uy * uy_b) / rho;
     // f_x = Dy sigma + rho g_x
     drho_b += fx_b * gx;
-    acc[3 * np + y] += (double)fx_b * (double)rho;
+    acc_add(3, (double)fx_b * (double)rho);
     // moments of the pulled populations
-    R *dbar = reinterpret_cast<R *>(aws + a->off_dbar);
 #pragma unroll
     for (int q = 0; q < 9; ++q)
-        dbar[q * np + y] = (R(1) - om) * A[q] + drho_b + R(QX[q]) * jx_b + R(QY[q]) * jy_b;
-    reinterpret_cast<R *>(aws + a->off_fbar)[y] = fx_b;
+        put(q, (R(1) - om) * A[q] + drho_b + R(QX[q]) * jx_b + R(QY[q]) * jy_b);
+    put(9, fx_b);
+}
+
+template <typename R, typename RH, typename SbarOf>
+__device__ __forceinline__ void adj_lattice(const ChanDev *c, const AdjChan *a, char *aws,
+                                            int slot, int buf, int y, SbarOf &&sbar_of)
+{
+    const size_t np = (size_t)c->np;
+    AdjStepIn<R> in;
+    adj_load_step<R>(c, a, aws, slot, buf, y, in);
+    const R *nbar = reinterpret_cast<const R *>(aws + a->off_nbar);
+    R A[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        A[q] = nbar[q * np + y];
+    double *acc = reinterpret_cast<double *>(aws + a->off_acc);
+    R *dbar = reinterpret_cast<R *>(aws + a->off_dbar);
+    R *fbar = reinterpret_cast<R *>(aws + a->off_fbar);
+    adj_lattice_core<R>(c, y, in, A, sbar_of,
+                        [&](int k, double v) { acc[k * np + y] += v; },
+                        [&](int q, R v) {
+                            if (q < 9)
+                                dbar[q * np + y] = v;
+                            else
+                                fbar[y] = v;
+                        });
 }
 
 template <typename R, typename RH>
@@ -3195,21 +3243,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(const ChanDev *__restrict__ ch
 
 // Blocked reverse sweep.  The history transpose of the entry pushed at step
 // t sums over the ages j of the window in fixed parts: the near ages [0,
-// kAdjMaxBlock) in order, then kAdjBulkRanges ranges that split [kAdjMaxBlock,
-// n_hist), each in order, added in range order.  For a block of reverse steps
-// t = t0 + slot, slot = slot_hi, slot_hi - 1, ..., slot_hi - count + 1 (count
-// <= kAdjMaxBlock), the far ranges reach adjoint stresses of steps after the
-// block, all in the ring before the block starts: k_adj_bulk sums them for
-// the whole block in one launch, and k_adj_span runs the block's steps one
-// by one with the near ages.  The parts do not depend on the block or the
-// segment a step falls in, so the gradients do not depend on the block size
-// or the segment length; the per-step kernels above split the window in
-// another way and agree up to the order of the FP64 sums.
+// kAdjMaxBlock) in order, then the far ages [kAdjMaxBlock, n_hist) as
+// kAdjBulkRanges ranges, each in order, whose sums are added in range order
+// and then to the near sum.  For a block of reverse steps t = t0 + slot, slot
+// = slot_hi, slot_hi - 1, ..., slot_hi - count + 1 (count <= kAdjMaxBlock),
+// the far ages reach adjoint stresses of steps after the block, all in the
+// ring before the block starts: k_adj_bulk sums them for the whole block in
+// one launch, and a span kernel runs the block's steps one by one with the
+// near ages.  The parts do not depend on the block or the segment a step
+// falls in, so the gradients do not depend on the block size or the segment
+// length; the per-step kernels above split the window in another way and
+// agree up to the order of the FP64 sums.
 //
-// k_adj_bulk: one thread per node, entry of the block and far range
-// (workgroup = node tile x entry x range): B0 = sum w_j sbar^{t+j} E_j and
-// B1 = sum w_j sbar^{t+j} E_j j over the range, E_j = q^j carried from one
-// exp at the range's first age.
+// k_adj_bulk: workgroup = kAdjBulkNodes nodes x kAdjBulkRanges far ranges of
+// one entry of the block; thread = node + kAdjBulkNodes * range.  Each thread
+// sums its range, B0 = sum w_j sbar^{t+j} E_j and B1 = sum w_j sbar^{t+j} E_j
+// j with E_j = q^j carried from one exp at the range's first age; the
+// ranges combine through LDS in range order.
+constexpr int kAdjBulkNodes = 16;
+static_assert(kAdjBulkNodes * kAdjBulkRanges == kBlock, "bulk workgroup shape");
+
 template <typename R, typename RH>
 __global__ __launch_bounds__(kBlock) void k_adj_bulk(const ChanDev *__restrict__ chans,
                                                      const NodeTile *__restrict__ tiles,
@@ -3218,14 +3271,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_bulk(const ChanDev *__restrict__
                                                      const int64_t *__restrict__ t0, int slot_hi,
                                                      int count, int buf)
 {
+    __shared__ double part[2][kAdjBulkRanges][kAdjBulkNodes];
+    constexpr int kSub = kBlock / kAdjBulkNodes;  // node groups per node tile
     const NodeTile tl = tiles[blockIdx.x % n_tiles];
-    const int m = (int)((blockIdx.x / n_tiles) % count);
-    const int r = (int)(blockIdx.x / (n_tiles * count));
+    const int sub = (int)((blockIdx.x / n_tiles) % kSub);
+    const int m = (int)(blockIdx.x / (n_tiles * kSub));
     const ChanDev *c = chans + tl.ch;
     const AdjChan *a = achans + tl.ch;
-    const int y = tl.n0 + threadIdx.x;
-    if (y >= c->ly)
-        return;
+    const int y0 = tl.n0 + sub * kAdjBulkNodes;
+    if (y0 >= c->ly || m >= count)
+        return;  // whole workgroup
+    const int lane = (int)(threadIdx.x % kAdjBulkNodes), r = (int)(threadIdx.x / kAdjBulkNodes);
+    const int y = y0 + lane;
+    const bool own = y < c->ly;
     const size_t np = (size_t)c->np;
     const int H = c->n_hist;
     const int slot = slot_hi - m;
@@ -3235,7 +3293,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_bulk(const ChanDev *__restrict__
     const int ja = lo + (int)((int64_t)(H - lo) * r / kAdjBulkRanges);
     const int jb = lo + (int)((int64_t)(H - lo) * (r + 1) / kAdjBulkRanges);
     double S0 = 0.0, S1 = 0.0;
-    if (ja < jb) {
+    if (own && ja < jb) {
         const R *sring = reinterpret_cast<const R *>(aws + a->off_sbar_ring);
         const R s = (R)reinterpret_cast<const RH *>(aws + a->off_recs[buf])[(size_t)slot * np + y];
         const double rate = c->inv_tau + c->inv_gc * (double)fabs(s);
@@ -3268,27 +3326,54 @@ __global__ __launch_bounds__(kBlock) void k_adj_bulk(const ChanDev *__restrict__
                 sl -= H;
         }
     }
-    double *bulk = reinterpret_cast<double *>(aws + a->off_bulk) +
-                   (size_t)r * kAdjMaxBlock * 2 * np;
+    part[0][r][lane] = S0;
+    part[1][r][lane] = S1;
+    __syncthreads();
+    if (!own || r != 0)
+        return;
+    S0 = 0.0;
+    S1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kAdjBulkRanges; ++k) {
+        S0 += part[0][k][lane];
+        S1 += part[1][k][lane];
+    }
+    double *bulk = reinterpret_cast<double *>(aws + a->off_bulk);
     bulk[(size_t)(2 * m) * np + y] = S0;
     bulk[(size_t)(2 * m + 1) * np + y] = S1;
 }
 
+// Near sum of the entry at node y: S0 = sum_{j <= jn} w_j sbar^{t+j} E_j,
+// S1 = sum w_j sbar^{t+j} E_j j in age order with E_j = q^j (w = 1/2 at the
+// window's ends); near(j) gives sbar^{t+j}.
+template <typename Near>
+__device__ __forceinline__ void adj_near_sum(int jn, int H, double q, Near &&near, double &S0,
+                                             double &S1)
+{
+    S0 = 0.0;
+    S1 = 0.0;
+    double e = 1.0;
+#pragma unroll
+    for (int j = 0; j < kAdjMaxBlock; ++j) {
+        if (j <= jn) {
+            const double w = (j == 0 || j == H - 1) ? 0.5 : 1.0;
+            const double x = w * near(j) * e;
+            S0 += x;
+            S1 += x * (double)j;
+            e *= q;
+        }
+    }
+}
+
 // k_adj_span: one workgroup per channel runs the block's steps in reverse
 // order; per step, for every node, the push of sigma_bar^t and nbar(t), the
-// near ages of the history transpose followed by the far range sums, with
-// sbar_t and the node's sums into LDS; a barrier; the lattice part with the
-// neighbours' sbar from LDS; and a barrier before the next step reads dbar
-// and fbar.  kAdjSpanThreads threads loop over the channel's nodes (the
-// lattice part needs about 180 registers a lane).  The near ages of the
-// block's entries reach the steps from kAdjMaxBlock - 1 before the block to
-// its end: channels of up to kAdjSpanLdsNodes nodes keep those adjoint
-// stresses in an LDS ring of 2 kAdjMaxBlock rows (indexed by step), filled
-// from the adjoint ring once at the start and by each push; wider channels
-// read the adjoint ring.  Both read the same values in the same order.
+// near sum plus the far sum of the bulk pass, with sbar_t and the node's
+// sums into LDS; a barrier; the lattice part with the neighbours' sbar from
+// LDS; and a barrier before the next step reads dbar and fbar.
+// kAdjSpanThreads threads loop over the channel's nodes (the lattice part
+// needs about 180 registers a lane); the near ages come from the adjoint
+// ring and the adjoint state from device memory.
 constexpr int kAdjSpanThreads = 256;
-constexpr int kAdjSpanLdsNodes = 128;
-constexpr int kAdjNearRows = 2 * kAdjMaxBlock;
 
 template <typename R, typename RH>
 __global__ __launch_bounds__(kAdjSpanThreads) void k_adj_span(const ChanDev *__restrict__ chans,
@@ -3299,86 +3384,37 @@ __global__ __launch_bounds__(kAdjSpanThreads) void k_adj_span(const ChanDev *__r
 {
     __shared__ double s_sbar[kFuseThreads], s_S0[kFuseThreads], s_S1[kFuseThreads],
         s_s[kFuseThreads];
-    __shared__ R s_near[kAdjNearRows][kAdjSpanLdsNodes];
     const ChanDev *c = chans + blockIdx.x;
     const AdjChan *a = achans + blockIdx.x;
     const int ly = c->ly;
-    const bool lds = ly <= kAdjSpanLdsNodes;
     const size_t np = (size_t)c->np;
     const int H = c->n_hist;
     const int jn = min(kAdjMaxBlock, H) - 1;  // last near age
     const R *sring = reinterpret_cast<const R *>(aws + a->off_sbar_ring);
     const RH *recs = reinterpret_cast<const RH *>(aws + a->off_recs[buf]);
     const double *bulk = reinterpret_cast<const double *>(aws + a->off_bulk);
-    const size_t rstride = (size_t)kAdjMaxBlock * 2 * np;
     const int64_t t_hi = *t0 + slot_hi;
-    if (lds) {
-        // steps t_hi + 1 .. t_hi + jn, pushed before the block
-        for (int i = threadIdx.x; i < jn * ly; i += kAdjSpanThreads) {
-            const int k = 1 + i / ly, y = i % ly;
-            const int64_t u = t_hi + k;
-            s_near[u % kAdjNearRows][y] = sring[(size_t)(u % H) * np + y];
-        }
-        __syncthreads();
-    }
     for (int m = 0; m < count; ++m) {
         const int64_t t = t_hi - m;
         const int p = (int)(t % H);
         for (int y = threadIdx.x; y < ly; y += kAdjSpanThreads) {
             // loads that do not wait for this step's push
             const double s = (double)recs[(size_t)(slot_hi - m) * np + y];
-            double B0[kAdjBulkRanges], B1[kAdjBulkRanges];
-#pragma unroll
-            for (int r = 0; r < kAdjBulkRanges; ++r) {
-                B0[r] = bulk[r * rstride + (size_t)(2 * m) * np + y];
-                B1[r] = bulk[r * rstride + (size_t)(2 * m + 1) * np + y];
-            }
-            const R pushed = adj_push<R>(c, a, aws, p, y);
-            const double rate = c->inv_tau + c->inv_gc * fabs(s);
-            const double q = exp(-rate);
-            double S0 = 0.0, S1 = 0.0, e = 1.0;
-            if (lds) {
-                s_near[t % kAdjNearRows][y] = pushed;
-                for (int j = 0; j <= jn; ++j) {
-                    const double w = (j == 0 || j == H - 1) ? 0.5 : 1.0;
-                    const double x = w * (double)s_near[(t + j) % kAdjNearRows][y] * e;
-                    S0 += x;
-                    S1 += x * (double)j;
-                    e *= q;
-                }
-            } else {
-                int sl = p;
-                constexpr int L = 8;  // ring rows loaded together
-                for (int j0 = 0; j0 <= jn; j0 += L) {
-                    R v[L];
-#pragma unroll
-                    for (int u = 0; u < L; ++u) {
-                        int su = sl + u;
-                        if (su >= H)
-                            su -= H;
-                        v[u] = j0 + u <= jn ? sring[(size_t)su * np + y] : R(0);
-                    }
-#pragma unroll
-                    for (int u = 0; u < L; ++u) {
-                        const int j = j0 + u;
-                        if (j <= jn) {
-                            const double w = (j == 0 || j == H - 1) ? 0.5 : 1.0;
-                            const double x = w * (double)v[u] * e;
-                            S0 += x;
-                            S1 += x * (double)j;
-                            e *= q;
-                        }
-                    }
-                    sl += L;
-                    if (sl >= H)
-                        sl -= H;
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < kAdjBulkRanges; ++r) {
-                S0 += B0[r];
-                S1 += B1[r];
-            }
+            const double b0 = bulk[(size_t)(2 * m) * np + y];
+            const double b1 = bulk[(size_t)(2 * m + 1) * np + y];
+            adj_push<R>(c, a, aws, p, y);
+            const double q = exp(-(c->inv_tau + c->inv_gc * fabs(s)));
+            double S0, S1;
+            adj_near_sum(jn, H, q,
+                         [&](int j) {
+                             int sl = p + j;
+                             if (sl >= H)
+                                 sl -= H;
+                             return (double)sring[(size_t)sl * np + y];
+                         },
+                         S0, S1);
+            S0 += b0;
+            S1 += b1;
             s_S0[y] = S0;
             s_S1[y] = S1;
             s_s[y] = s;
@@ -3394,6 +3430,153 @@ __global__ __launch_bounds__(kAdjSpanThreads) void k_adj_span(const ChanDev *__r
                                    return s_sbar[yy];
                                });
         __syncthreads();  // dbar(t), fbar(t) written before the next step reads them
+    }
+}
+
+// k_adj_span_lds: the same steps for channels of at most kAdjSpanLdsNodes
+// nodes, one thread per node, with the whole adjoint state of the block on
+// chip: dbar and fbar in LDS (read from device memory at the start, written
+// back at the end), nbar(t) in registers from the push to the lattice part,
+// the parameter accumulators in registers, and the near ages in an LDS ring
+// of kAdjNearRows rows indexed by step (filled from the adjoint ring at the
+// start and by each push: the block's entries reach from kAdjMaxBlock - 1
+// steps after the block to its first step; the block's pushes go to the
+// adjoint ring at the end).  Each step's records are loaded one step ahead,
+// so a step waits on no device memory.  Same values in the same order as
+// k_adj_span.
+constexpr int kAdjSpanLdsNodes = 128;
+constexpr int kAdjNearRows = 2 * kAdjMaxBlock;
+
+template <typename R, typename RH>
+__global__ __launch_bounds__(kAdjSpanLdsNodes) void k_adj_span_lds(
+    const ChanDev *__restrict__ chans, char *__restrict__ aws, const AdjChan *__restrict__ achans,
+    const int64_t *__restrict__ t0, int slot_hi, int count, int buf)
+{
+    constexpr int N = kAdjSpanLdsNodes;
+    __shared__ double s_sbar[N], s_S0[N], s_S1[N], s_s[N];
+    __shared__ R s_near[kAdjNearRows][N];
+    __shared__ R s_fbar[N], s_dbar[9][N];
+    const ChanDev *c = chans + blockIdx.x;
+    const AdjChan *a = achans + blockIdx.x;
+    const int ly = c->ly;
+    if (ly > N)
+        return;  // whole workgroup; the launcher takes this kernel only when no channel is wider
+    const size_t np = (size_t)c->np;
+    const int H = c->n_hist;
+    const int jn = min(kAdjMaxBlock, H) - 1;  // last near age
+    const int y = threadIdx.x;
+    const bool own = y < ly;
+    R *sring = reinterpret_cast<R *>(aws + a->off_sbar_ring);
+    const RH *recs = reinterpret_cast<const RH *>(aws + a->off_recs[buf]);
+    const double *bulk = reinterpret_cast<const double *>(aws + a->off_bulk);
+    R *g_fbar = reinterpret_cast<R *>(aws + a->off_fbar);
+    R *g_dbar = reinterpret_cast<R *>(aws + a->off_dbar);
+    double *g_acc = reinterpret_cast<double *>(aws + a->off_acc);
+    const int64_t t_hi = *t0 + slot_hi;
+
+    // steps t_hi + 1 .. t_hi + jn, pushed before the block
+    for (int i = threadIdx.x; i < jn * ly; i += N) {
+        const int k = 1 + i / ly, yy = i % ly;
+        const int64_t u = t_hi + k;
+        s_near[u % kAdjNearRows][yy] = sring[(size_t)(u % H) * np + yy];
+    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (own) {
+        s_fbar[y] = g_fbar[y];
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            s_dbar[q][y] = g_dbar[q * np + y];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            acc[k] = g_acc[k * np + y];
+    }
+    // A step's inputs: records, s (converted where used, so that its load
+    // stays in flight) and the far sums.
+    struct In {
+        AdjStepIn<R> rec;
+        RH s;
+        double b0, b1;
+    };
+    const auto load = [&](int m, In &in) {
+        const int slot = slot_hi - m;
+        adj_load_step<R>(c, a, aws, slot, buf, y, in.rec);
+        in.s = recs[(size_t)slot * np + y];
+        in.b0 = bulk[(size_t)(2 * m) * np + y];
+        in.b1 = bulk[(size_t)(2 * m + 1) * np + y];
+    };
+    // Step m with its inputs in `cur`; the next step's go to `nxt` while
+    // this one runs.
+    const auto run_step = [&](int m, const In &cur, In &nxt) {
+        const int64_t t = t_hi - m;
+        R A[9];
+        if (own) {
+            // push: sigma_bar^t = Dy^T fbar(t+1), nbar(t) = push map of dbar(t+1)
+            R sb = R(0);
+            for (int yy = max(0, y - 2); yy <= min(ly - 1, y + 2); ++yy)
+                sb += coef_div<R>(yy, y, ly) * s_fbar[yy];
+            s_near[t % kAdjNearRows][y] = sb;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int yt = y + QY[q];
+                A[q] = (yt >= 0 && yt < ly) ? s_dbar[q][yt] : s_dbar[QOPP[q]][y];
+            }
+            const double s = (double)cur.s;
+            const double q = exp(-(c->inv_tau + c->inv_gc * fabs(s)));
+            double S0, S1;
+            adj_near_sum(jn, H, q,
+                         [&](int j) { return (double)s_near[(t + j) % kAdjNearRows][y]; }, S0,
+                         S1);
+            S0 += cur.b0;
+            S1 += cur.b1;
+            s_S0[y] = S0;
+            s_S1[y] = S1;
+            s_s[y] = s;
+            s_sbar[y] = c->g_inf * (S0 - fabs(s) * S1 * c->inv_gc);
+        }
+        __syncthreads();  // every node's sbar_t is in LDS; every push has read dbar, fbar
+        if (own) {
+            // unconditional (the last step reloads its own inputs), so the
+            // loads of every step stay in one sequence for the wait counters
+            load(min(m + 1, count - 1), nxt);
+            adj_lattice_core<R>(c, y, cur.rec, A,
+                                [&](int yy, double &S0, double &S1, double &ss) {
+                                    S0 = s_S0[yy];
+                                    S1 = s_S1[yy];
+                                    ss = s_s[yy];
+                                    return s_sbar[yy];
+                                },
+                                [&](int k, double v) { acc[k] += v; },
+                                [&](int q, R v) {
+                                    if (q < 9)
+                                        s_dbar[q][y] = v;
+                                    else
+                                        s_fbar[y] = v;
+                                });
+        }
+        __syncthreads();  // dbar(t), fbar(t) in LDS before the next push reads them
+    };
+    In in0, in1;
+    if (own)
+        load(0, in0);
+    __syncthreads();
+    // two steps per trip, so that the inputs in flight stay in their registers
+    for (int m = 0; m < count; m += 2) {
+        run_step(m, in0, in1);
+        if (m + 1 < count)
+            run_step(m + 1, in1, in0);
+    }
+    if (own) {
+        for (int m = 0; m < count; ++m) {
+            const int64_t t = t_hi - m;
+            sring[(size_t)(t % H) * np + y] = s_near[t % kAdjNearRows][y];
+        }
+        g_fbar[y] = s_fbar[y];
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            g_dbar[q * np + y] = s_dbar[q][y];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            g_acc[k * np + y] = acc[k];
     }
 }
 
@@ -3448,19 +3631,25 @@ void launch_adj_bulk(int prec, const ChanDev *chans, const NodeTile *tiles, int 
                      char *aws, const AdjChan *achans, const int64_t *t0, int slot_hi,
                      int count, int buf, hipStream_t st)
 {
+    // node tiles x groups of kAdjBulkNodes nodes x entries of the block
     LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_bulk<P, H>),
-                                           dim3(n_tiles * count * kAdjBulkRanges), dim3(kBlock),
-                                           0, st, chans, tiles, n_tiles, aws, achans, t0,
-                                           slot_hi, count, buf));
+                                           dim3(n_tiles * (kBlock / kAdjBulkNodes) * count),
+                                           dim3(kBlock), 0, st, chans, tiles, n_tiles, aws,
+                                           achans, t0, slot_hi, count, buf));
 }
 
-void launch_adj_span(int prec, const ChanDev *chans, int n_ch, char *aws,
+void launch_adj_span(int prec, const ChanDev *chans, int n_ch, int max_ly, char *aws,
                      const AdjChan *achans, const int64_t *t0, int slot_hi, int count,
                      int buf, hipStream_t st)
 {
-    LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_span<P, H>), dim3(n_ch),
-                                           dim3(kAdjSpanThreads), 0, st, chans, aws, achans, t0,
-                                           slot_hi, count, buf));
+    if (max_ly <= kAdjSpanLdsNodes)
+        LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_span_lds<P, H>), dim3(n_ch),
+                                               dim3(kAdjSpanLdsNodes), 0, st, chans, aws,
+                                               achans, t0, slot_hi, count, buf));
+    else
+        LBMAX_BY_PREC(prec, hipLaunchKernelGGL((k_adj_span<P, H>), dim3(n_ch),
+                                               dim3(kAdjSpanThreads), 0, st, chans, aws, achans,
+                                               t0, slot_hi, count, buf));
 }
 
 __global__ void k_store_i64(int64_t *p, int64_t v)
@@ -3472,6 +3661,25 @@ __global__ void k_store_i64(int64_t *p, int64_t v)
 void launch_store_i64(int64_t *p, int64_t v, hipStream_t st)
 {
     hipLaunchKernelGGL(k_store_i64, dim3(1), dim3(64), 0, st, p, v);
+}
+
+// Step records on (aws: each channel's record area of buffer buf, from step
+// t0) or off (aws = nullptr) in the device channel table.
+__global__ void k_set_record(ChanDev *chans, const AdjChan *achans, int n_ch, char *aws, int buf,
+                             int64_t t0)
+{
+    const int ci = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (ci >= n_ch)
+        return;
+    chans[ci].rec = aws ? (int64_t)(uintptr_t)(aws + achans[ci].off_rec[buf]) : 0;
+    chans[ci].rec_t0 = aws ? t0 : 0;
+}
+
+void launch_set_record(ChanDev *chans, const AdjChan *achans, int n_ch, char *aws, int buf,
+                       int64_t t0, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_record, dim3((n_ch + 63) / 64), dim3(64), 0, st, chans, achans,
+                       n_ch, aws, buf, t0);
 }
 
 void launch_adj_reduce(const ChanDev *chans, int n_ch, char *aws, const AdjChan *achans,

@@ -347,7 +347,11 @@ struct lb_handle {
     // the reverse sweeps run on their own stream, beside the next segment's
     // replay on the handle's stream; events order the two
     hipStream_t adj_stream = nullptr;
+    // reads of a checkpoint's header and forces in lb_adjoint_segment, which
+    // must not wait for the replay in flight on the handle's stream
+    hipStream_t io_stream = nullptr;
     hipEvent_t adj_ev_replay = nullptr;
+    hipEvent_t adj_ev_input = nullptr;  // the segment's dL/du_x has left the caller's buffer
     hipEvent_t adj_ev_sweep[2] = {nullptr, nullptr};
     bool adj_sweep_pending[2] = {false, false};
     int adj_segments = 0;            // segments swept since lb_adjoint_begin
@@ -806,8 +810,7 @@ AdjLayout adj_layout(const lb_handle *h, int seg_len, AdjChan *chans)
         a.off_acc = (int64_t)off;
         off = align_up(off + 4 * (size_t)c.np * sizeof(double), 256);
         a.off_bulk = (int64_t)off;
-        off = align_up(off + (size_t)kAdjBulkRanges * kAdjMaxBlock * 2 * c.np * sizeof(double),
-                       256);
+        off = align_up(off + (size_t)kAdjMaxBlock * 2 * c.np * sizeof(double), 256);
         for (int b = 0; b < 2; ++b) {
             a.off_rec[b] = (int64_t)off;
             off = align_up(off + (size_t)seg_len * 10 * plane, 256);
@@ -874,11 +877,15 @@ lb_status enqueue_adj_sweep(lb_handle *h, int n_steps, int buf, hipStream_t st, 
     const int64_t *t0 = h->d_adj_t0 + buf;
     const int blk = adj_block_in_effect(h);
     if (blk > 1) {
+        int max_ly = 0;
+        for (const ChanDev &c : h->plan.chans)
+            max_ly = std::max(max_ly, c.ly);
         for (int hi = n_steps - 1; hi >= 0; hi -= blk) {
             const int count = std::min(blk, hi + 1);
             launch_adj_bulk(h->pc, snap, h->d_node_tiles, h->n_node_tiles, h->aws, h->d_achans,
                             t0, hi, count, buf, st);
-            launch_adj_span(h->pc, snap, h->n_ch, h->aws, h->d_achans, t0, hi, count, buf, st);
+            launch_adj_span(h->pc, snap, h->n_ch, max_ly, h->aws, h->d_achans, t0, hi, count, buf,
+                            st);
             if (check) {
                 lb_status s = check_launch(h, "adjoint block");
                 if (s != LB_OK)
@@ -1226,17 +1233,23 @@ lb_status lb_save_state(lb_handle *h, void *d_dst)
     return LB_OK;
 }
 
-lb_status lb_load_state(lb_handle *h, const void *d_src)
+namespace {
+
+// Restore a state: header and forces are read to the host on `meta` (and
+// that stream synchronised), the sections are copied on the handle's stream.
+// With meta = the handle's stream the call returns once the copies are done
+// (lb_load_state); with another stream they stay queued behind the handle's
+// stream work, and the source must stay unchanged until that work has run
+// (lb_adjoint_segment: a checkpoint the forward run finished, read while a
+// replay may still be running).
+lb_status load_state_impl(lb_handle *h, const void *d_src, hipStream_t meta)
 {
-    lb_status s = usable(h);
-    if (s != LB_OK)
-        return s;
     if (!d_src || reinterpret_cast<uintptr_t>(d_src) % 256 != 0)
         return fail(LB_EINVAL, "state buffer must be non-NULL and 256-byte aligned");
     const char *src = static_cast<const char *>(d_src);
     StateHeader hd{};
-    HIP_TRY(h, hipMemcpyAsync(&hd, src, sizeof hd, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpyAsync(&hd, src, sizeof hd, hipMemcpyDeviceToHost, meta));
+    HIP_TRY(h, hipStreamSynchronize(meta));
     if (hd.magic != kStateMagic || hd.version != kStateVersion)
         return fail(LB_EINVAL, "not a state buffer of this library version");
     if (hd.precision != (uint32_t)h->prec || hd.n_ch != h->n_ch || hd.bytes != state_size(h))
@@ -1255,8 +1268,7 @@ lb_status lb_load_state(lb_handle *h, const void *d_src)
                                         hipMemcpyDeviceToDevice, h->stream));
             off = align_up(off + sec.rows * sec.row_bytes, 256);
         }
-        HIP_TRY(h, hipMemcpyAsync(&forces[2 * ci], src + off, 16, hipMemcpyDeviceToHost,
-                                  h->stream));
+        HIP_TRY(h, hipMemcpyAsync(&forces[2 * ci], src + off, 16, hipMemcpyDeviceToHost, meta));
         off = align_up(off + 2 * sizeof(double), 256);
     }
     // Split storage: the moments of step t-1 (the base of the stored
@@ -1271,7 +1283,7 @@ lb_status lb_load_state(lb_handle *h, const void *d_src)
         HIP_TRY(h, hipMemcpyAsync(m + pb, h->ws + c.off_vel, 2 * pb, hipMemcpyDeviceToDevice,
                                   h->stream));
     }
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipStreamSynchronize(meta));
     for (int ci = 0; ci < h->n_ch; ++ci) {
         if (!std::isfinite(forces[2 * ci]) || !std::isfinite(forces[2 * ci + 1]) ||
             (!h->plan.chans[ci].has_r && forces[2 * ci + 1] != 0.0)) {
@@ -1283,13 +1295,23 @@ lb_status lb_load_state(lb_handle *h, const void *d_src)
         launch_set_force(h->d_chans, ci, forces[2 * ci], forces[2 * ci + 1], h->stream);
     }
     launch_tick(h->d_tcount, hd.t - h->t, h->stream);
-    s = check_launch(h, "load_state");
+    lb_status s = check_launch(h, "load_state");
     if (s != LB_OK)
         return s;
     h->t = hd.t;
     h->has_out = hd.t > 0;
     h->block_pos = hd.block_pos;
     return LB_OK;
+}
+
+}  // namespace
+
+lb_status lb_load_state(lb_handle *h, const void *d_src)
+{
+    lb_status s = usable(h);
+    if (s != LB_OK)
+        return s;
+    return load_state_impl(h, d_src, h->stream);
 }
 
 int32_t lb_max_chunks(const lb_handle *h, int32_t ch)
@@ -1506,7 +1528,9 @@ lb_status adjoint_begin_at(lb_handle *h, char *aws, size_t bytes, int seg_len)
         return s;
     if (!h->adj_stream) {
         HIP_TRY(h, hipStreamCreateWithFlags(&h->adj_stream, hipStreamNonBlocking));
+        HIP_TRY(h, hipStreamCreateWithFlags(&h->io_stream, hipStreamNonBlocking));
         HIP_TRY(h, hipEventCreateWithFlags(&h->adj_ev_replay, hipEventDisableTiming));
+        HIP_TRY(h, hipEventCreateWithFlags(&h->adj_ev_input, hipEventDisableTiming));
         for (int b = 0; b < 2; ++b)
             HIP_TRY(h, hipEventCreateWithFlags(&h->adj_ev_sweep[b], hipEventDisableTiming));
     }
@@ -1582,7 +1606,9 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
     if (!dL_dux)
         return fail(LB_EINVAL, "dL_dux is NULL");
     const int64_t want_end = h->adj_next;
-    s = lb_load_state(h, d_ckpt);
+    // the checkpoint's header and forces come over the io stream, so the
+    // state copies queue behind the replay still running
+    s = load_state_impl(h, d_ckpt, h->io_stream);
     if (s != LB_OK)
         return s;
     const int64_t t0 = h->t;
@@ -1595,44 +1621,41 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
     const int buf = h->adj_segments & 1;
     if (h->adj_sweep_pending[buf])
         HIP_TRY(h, hipStreamWaitEvent(h->stream, h->adj_ev_sweep[buf], 0));
-    // Replay the segment on the handle's stream (beside the sweep of the
-    // later segment on the adjoint stream); its lattice steps record their
-    // input populations and stress into the step records.
-    auto set_record = [&](bool on) -> lb_status {
-        for (int ci = 0; ci < h->n_ch; ++ci) {
-            ChanDev &c = h->plan.chans[ci];
-            c.rec = on ? (int64_t)(uintptr_t)(h->aws + h->achans[ci].off_rec[buf]) : 0;
-            c.rec_t0 = on ? t0 : 0;
-        }
-        HIP_TRY(h, hipMemcpyAsync(h->d_chans, h->plan.chans.data(),
-                                  h->plan.chans.size() * sizeof(ChanDev), hipMemcpyHostToDevice,
-                                  h->stream));
-        // the host table is reused only after the copy
-        HIP_TRY(h, hipStreamSynchronize(h->stream));
-        return LB_OK;
-    };
-    s = set_record(true);
-    if (s != LB_OK)
-        return s;
-    s = lb_step(h, n_steps);
-    lb_status s2 = set_record(false);
-    if (s != LB_OK)
-        return s;
-    if (s2 != LB_OK)
-        return s2;
-    // The segment's shear rates (ring rows t0 .. t0 + n_steps - 1, wrapping),
-    // dL/du_x (host [n_steps][sum of nodes]) and the channel table into the
-    // buffer, so the sweep reads nothing the next replay overwrites.  dL/du_x
-    // crosses to the device in one contiguous copy (a strided copy from
-    // pageable host memory goes row by row) and is spread over the channels'
-    // planes on the device.
-    const size_t RH = history_bytes(h->prec);
+    // dL/du_x (host [n_steps][sum of nodes]) crosses to the device first, in
+    // one contiguous copy (a strided copy from pageable host memory goes row
+    // by row); the call waits for this copy only, so the caller queues the
+    // next segment while this one replays.
     size_t total_nodes = 0;
     for (const ChanDev &c : h->plan.chans)
         total_nodes += (size_t)c.n;
     HIP_TRY(h, hipMemcpyAsync(h->d_adj_stage[buf], dL_dux,
                               (size_t)n_steps * total_nodes * sizeof(double),
                               hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipEventRecord(h->adj_ev_input, h->stream));
+    const auto leave = [&](lb_status st) {
+        (void)hipEventSynchronize(h->adj_ev_input);
+        return st;
+    };
+    // Replay the segment on the handle's stream (beside the sweep of the
+    // later segment on the adjoint stream); its lattice steps record their
+    // input populations and stress into the step records.  The record
+    // fields of the device channel table are set and cleared on the stream;
+    // the host table keeps them at zero.
+    launch_set_record(h->d_chans, h->d_achans, h->n_ch, h->aws, buf, t0, h->stream);
+    s = check_launch(h, "adjoint record on");
+    if (s != LB_OK)
+        return leave(s);
+    s = lb_step(h, n_steps);
+    launch_set_record(h->d_chans, h->d_achans, h->n_ch, nullptr, buf, 0, h->stream);
+    lb_status s2 = check_launch(h, "adjoint record off");
+    if (s != LB_OK)
+        return leave(s);
+    if (s2 != LB_OK)
+        return leave(s2);
+    // The segment's shear rates (ring rows t0 .. t0 + n_steps - 1, wrapping),
+    // dL/du_x spread over the channels' planes, and the channel table into
+    // the buffer, so the sweep reads nothing the next replay overwrites.
+    const size_t RH = history_bytes(h->prec);
     size_t col = 0;
     for (int ci = 0; ci < h->n_ch; ++ci) {
         const ChanDev &c = h->plan.chans[ci];
@@ -1659,7 +1682,7 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
     launch_store_i64(h->d_adj_t0 + buf, t0, h->stream);
     s = check_launch(h, "adjoint segment start");
     if (s != LB_OK)
-        return s;
+        return leave(s);
     HIP_TRY(h, hipEventRecord(h->adj_ev_replay, h->stream));
     // Reverse sweep of the segment on the adjoint stream, after the replay:
     // one captured graph per segment length and buffer, the segment's first
@@ -1669,20 +1692,20 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
         hipGraphExec_t exec = nullptr;
         s = adj_sweep_graph(h, n_steps, buf, &exec);
         if (s != LB_OK)
-            return s;
+            return leave(s);
         HIP_TRY(h, hipGraphLaunch(exec, h->adj_stream));
     } else {
         // longer segments launch directly (a graph of 2 n_steps nodes would
         // cost more to build than it saves)
         s = enqueue_adj_sweep(h, n_steps, buf, h->adj_stream, true);
         if (s != LB_OK)
-            return s;
+            return leave(s);
     }
     HIP_TRY(h, hipEventRecord(h->adj_ev_sweep[buf], h->adj_stream));
     h->adj_sweep_pending[buf] = true;
-    // The host buffer may be reused once this returns: wait for the replay
-    // and the copies (the sweep runs on).
-    HIP_TRY(h, hipEventSynchronize(h->adj_ev_replay));
+    // The host buffer may be reused once this returns: wait for its copy
+    // (the replay and the sweep run on).
+    HIP_TRY(h, hipEventSynchronize(h->adj_ev_input));
     h->adj_next = t0;
     h->adj_segments += 1;
     return LB_OK;
@@ -1725,8 +1748,12 @@ lb_status lb_destroy(lb_handle *h)
         (void)hipStreamSynchronize(h->adj_stream);
         (void)hipStreamDestroy(h->adj_stream);
     }
+    if (h->io_stream)
+        (void)hipStreamDestroy(h->io_stream);
     if (h->adj_ev_replay)
         (void)hipEventDestroy(h->adj_ev_replay);
+    if (h->adj_ev_input)
+        (void)hipEventDestroy(h->adj_ev_input);
     for (int b = 0; b < 2; ++b)
         if (h->adj_ev_sweep[b])
             (void)hipEventDestroy(h->adj_ev_sweep[b]);

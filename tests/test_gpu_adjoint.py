@@ -162,6 +162,27 @@ def test_blocked_sweep_matches_the_per_step_sweep(lb, case):
     assert np.array_equal(grad(32, seg2), blocked)
 
 
+def test_blocked_sweep_forms_agree_bit_for_bit(lb):
+    """A handle whose channels all have at most 128 nodes runs each block with
+    its adjoint state on chip; a wider channel in the handle sends every
+    channel through the form that keeps it in device memory.  Same values in
+    the same order: the 1 x 16 channel's gradient is the same, bit for bit,
+    swept alone and beside a 1 x 200 channel."""
+    from paper_1504_06123_amd import adjoint
+    c0, wide = small_channel(), _wide_channel()
+    steps, every, seg = 300, 25, 64
+    say("case blocked sweep, on-chip form vs device-memory form")
+    targets = [oracle_samples(c.replace(gx=0.8 * c.gx), steps, every) for c in (c0, wide)]
+    with lb.Solver([c0, wide], precision="f64") as s:
+        assert s.adjoint_block == 32
+        u, ckpts = adjoint.forward(s, steps, every, seg)
+        g_mixed = adjoint.backward(s, ckpts, steps, every, seg,
+                                   2 * (u - np.concatenate(targets, axis=1)))
+    _, g_alone = gpu_gradient(lb, c0, "f64", steps, every, seg, targets[0])
+    say(f"  beside 1x200 {g_mixed[0]}\n  alone        {g_alone}")
+    assert np.array_equal(g_mixed[0], g_alone)
+
+
 def test_adjoint_block_setting(lb):
     """lb_set_adjoint_block takes 1 .. 32 and refuses the rest; channels
     wider than 1024 nodes sweep per step whatever the setting."""
