@@ -55,20 +55,20 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernel
 # (precision, steps per pass, nodes per lane).  Valid only for the kernel source they
 # were taken from; otherwise reported as null.
 MEASURED = {
-    "source_sha256": "2957ae81ee4f783108f81491089deaad4b1797ac9f4b0316034b10e20febda78",
+    "source_sha256": "e7a28b061b05af360424e68dae98c81dfa434630eba86dd96d61ae644d17b553",
     # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated),
     # from `bench.py --counter-run <leg>` under rocprofv3 --pmc
-    "traffic_bytes": {("f32", 32, 1): 8395200.0 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32", 1, 4): 8411270.0 * 1024 * 2 + 41254.2 * 1024,
-                      ("f32p64", 32, 1): 8395220.0 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32p64", 1, 4): 8410990.0 * 1024 * 2 + 41256.9 * 1024},
+    "traffic_bytes": {("f32", 32, 1): 8395003.8 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32", 1, 4): 8412004.8 * 1024 * 2 + 41212.8 * 1024,
+                      ("f32p64", 32, 1): 8394869.1 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32p64", 1, 4): 8411952.6 * 1024 * 2 + 41215.0 * 1024},
     # SQ_INSTS_VALU x 64 / history entries (both modes run the same pass kernels)
     "valu_instr_per_entry": {("f32", 32, 1): 90.77, ("f32p64", 32, 1): 90.77,
                              ("f32", 1, 4): 9.53, ("f32p64", 1, 4): 9.53},
     # the side legs' dominant kernels, keyed by (leg, steps per pass), same calibration
-    "leg_traffic_bytes": {("grid", 16): 1602520.0 * 1024 * 2 + 211968.0 * 1024,
-                          ("full_tensor", 16): 33557900.0 * 1024 * 2 + 213072.0 * 1024,
-                          ("strain_damping", 32): 8396010.0 * 1024 * 2 + 266240.0 * 1024},
+    "leg_traffic_bytes": {("grid", 16): 1602531.9 * 1024 * 2 + 211968.0 * 1024,
+                          ("full_tensor", 16): 33557697.2 * 1024 * 2 + 213072.0 * 1024,
+                          ("strain_damping", 32): 8395976.4 * 1024 * 2 + 266240.0 * 1024},
 }
 
 
