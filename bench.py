@@ -468,8 +468,8 @@ def bench_batched(steps: int = 2000):
 
 def bench_adjoint(repeats: int = 3, oracle_steps: int = 200):
     """Gradients of the differentiation run (1 x 128 channel, window 2048,
-    4000 steps, u_x sampled every 200, checkpoints every 256; LB_F32_P64,
-    8-step blocks): the forward run with its snapshots, then the adjoint sweep
+    4000 steps, u_x sampled every 200, checkpoints every 256; LB_F32, 32-step
+    blocks): the forward run with its snapshots, then the adjoint sweep
     (segment replay and the discrete adjoint), for dL/d(G_inf, tau, gamma_c,
     g_x) of L = sum (u - u_target)^2 with the target from the true
     parameters; forward steps and replays in 64-step graphs.  The oracle's central differences need 8 forward runs; their
@@ -483,12 +483,13 @@ def bench_adjoint(repeats: int = 3, oracle_steps: int = 200):
     wl = workloads.differentiation()
     ch = wl.channels[0]
     steps, every, seg = wl.steps, wl.sample_every, 256
-    with Solver([workloads.true_channel(ch)], precision="f32p64") as s:
-        s.set_block(8)
+    prec, block = wl.precision, 32
+    with Solver([workloads.true_channel(ch)], precision=prec) as s:
+        s.set_block(block)
         target, _ = adjoint.forward(s, steps, every, seg)
     fw, bw = [], []
-    with Solver([ch], precision="f32p64") as s:
-        s.set_block(8)
+    with Solver([ch], precision=prec) as s:
+        s.set_block(block)
         s.set_graph(GRAPH_LEN)
         init = s.save_state()
         for _ in range(repeats + 1):      # the first round warms up
@@ -520,7 +521,8 @@ def bench_adjoint(repeats: int = 3, oracle_steps: int = 200):
         f"sweep {b_s*1e3:.1f} ms ({b_s/steps*1e6:.1f} us per step); oracle FD ~{fd_s:.0f} s")
     return {"workload": f"differentiation run, 1x{ch.ly} channel, N_h={ch.n_hist}, {steps} steps, "
                         f"u_x sampled every {every}, checkpoints every {seg}",
-            "value": 1.0 / (f_s + b_s), "unit": "gradients/s", "dtype": "f32p64",
+            "value": 1.0 / (f_s + b_s), "unit": "gradients/s", "dtype": prec,
+            "steps_per_pass": block,
             "forward_ms": f_s * 1e3, "sweep_ms": b_s * 1e3,
             "sweep_us_per_step": b_s / steps * 1e6,
             "gradient": [float(x) for x in np.asarray(g)[0]],

@@ -3353,6 +3353,18 @@ __device__ __forceinline__ void adj_near_sum(int jn, int H, double q, Near &&nea
     S0 = 0.0;
     S1 = 0.0;
     double e = 1.0;
+    if (H > kAdjMaxBlock) {
+        // every near age, the window's end beyond them: no bound to test
+#pragma unroll
+        for (int j = 0; j < kAdjMaxBlock; ++j) {
+            const double w = j == 0 ? 0.5 : 1.0;
+            const double x = w * near(j) * e;
+            S0 += x;
+            S1 += x * (double)j;
+            e *= q;
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < kAdjMaxBlock; ++j) {
         if (j <= jn) {
@@ -3446,6 +3458,7 @@ __global__ __launch_bounds__(kAdjSpanThreads) void k_adj_span(const ChanDev *__r
 // k_adj_span.
 constexpr int kAdjSpanLdsNodes = 128;
 constexpr int kAdjNearRows = 2 * kAdjMaxBlock;
+static_assert((kAdjNearRows & (kAdjNearRows - 1)) == 0, "the near ring is indexed with a mask");
 
 template <typename R, typename RH>
 __global__ __launch_bounds__(kAdjSpanLdsNodes) void k_adj_span_lds(
@@ -3508,13 +3521,14 @@ __global__ __launch_bounds__(kAdjSpanLdsNodes) void k_adj_span_lds(
     // this one runs.
     const auto run_step = [&](int m, const In &cur, In &nxt) {
         const int64_t t = t_hi - m;
+        const int r0 = (int)(t % kAdjNearRows);  // this step's row of the near ring
         R A[9];
         if (own) {
             // push: sigma_bar^t = Dy^T fbar(t+1), nbar(t) = push map of dbar(t+1)
             R sb = R(0);
             for (int yy = max(0, y - 2); yy <= min(ly - 1, y + 2); ++yy)
                 sb += coef_div<R>(yy, y, ly) * s_fbar[yy];
-            s_near[t % kAdjNearRows][y] = sb;
+            s_near[r0][y] = sb;
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const int yt = y + QY[q];
@@ -3524,8 +3538,8 @@ __global__ __launch_bounds__(kAdjSpanLdsNodes) void k_adj_span_lds(
             const double q = exp(-(c->inv_tau + c->inv_gc * fabs(s)));
             double S0, S1;
             adj_near_sum(jn, H, q,
-                         [&](int j) { return (double)s_near[(t + j) % kAdjNearRows][y]; }, S0,
-                         S1);
+                         [&](int j) { return (double)s_near[(r0 + j) & (kAdjNearRows - 1)][y]; },
+                         S0, S1);
             S0 += cur.b0;
             S1 += cur.b1;
             s_S0[y] = S0;
