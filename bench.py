@@ -55,20 +55,20 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_06123_amd", "csrc", "lbmax_kernel
 # (precision, steps per pass, nodes per lane).  Valid only for the kernel source they
 # were taken from; otherwise reported as null.
 MEASURED = {
-    "source_sha256": "e7a28b061b05af360424e68dae98c81dfa434630eba86dd96d61ae644d17b553",
+    "source_sha256": "4420735c938cc4f3a0b522dceeec0453bbaa654f000d4af98829c3c55b44b196",
     # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated),
     # from `bench.py --counter-run <leg>` under rocprofv3 --pmc
-    "traffic_bytes": {("f32", 32, 1): 8395003.8 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32", 1, 4): 8412004.8 * 1024 * 2 + 41212.8 * 1024,
-                      ("f32p64", 32, 1): 8394869.1 * 1024 * 2 + 266560.0 * 1024,
-                      ("f32p64", 1, 4): 8411952.6 * 1024 * 2 + 41215.0 * 1024},
+    "traffic_bytes": {("f32", 32, 1): 8395456.6 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32", 1, 4): 8411893.1 * 1024 * 2 + 41231.2 * 1024,
+                      ("f32p64", 32, 1): 8394923.6 * 1024 * 2 + 266560.0 * 1024,
+                      ("f32p64", 1, 4): 8411801.9 * 1024 * 2 + 41233.6 * 1024},
     # SQ_INSTS_VALU x 64 / history entries (both modes run the same pass kernels)
     "valu_instr_per_entry": {("f32", 32, 1): 90.77, ("f32p64", 32, 1): 90.77,
                              ("f32", 1, 4): 9.53, ("f32p64", 1, 4): 9.53},
     # the side legs' dominant kernels, keyed by (leg, steps per pass), same calibration
-    "leg_traffic_bytes": {("grid", 16): 1602531.9 * 1024 * 2 + 211968.0 * 1024,
-                          ("full_tensor", 16): 33557697.2 * 1024 * 2 + 213072.0 * 1024,
-                          ("strain_damping", 32): 8395976.4 * 1024 * 2 + 266240.0 * 1024},
+    "leg_traffic_bytes": {("grid", 16): 1602534.0 * 1024 * 2 + 211968.0 * 1024,
+                          ("full_tensor", 16): 33557838.6 * 1024 * 2 + 213072.0 * 1024,
+                          ("strain_damping", 32): 8395973.2 * 1024 * 2 + 266240.0 * 1024},
 }
 
 
