@@ -122,9 +122,12 @@ def _wide_channel():
                              n_hist=150, gx=2e-7)
 
 
-@pytest.mark.parametrize("case", ["1x16, window 64", "window 16, shorter than a block",
-                                  "two channels", "1x200, near ages from the ring"])
-def test_blocked_sweep_matches_the_per_step_sweep(lb, case):
+@pytest.mark.parametrize("case,precision", [
+    ("1x16, window 64", "f64"), ("window 16, shorter than a block", "f64"),
+    ("two channels", "f64"), ("1x200, near ages from the ring", "f64"),
+    ("windows 16 and 64 in one handle", "f64"), ("1x16, window 64", "f32"),
+])
+def test_blocked_sweep_matches_the_per_step_sweep(lb, case, precision):
     """The blocked reverse sweep (the default) against the per-step one: the
     same terms of the history transpose summed in another order, so equal to
     a few FP64 roundings (bound 1e-12 relative per component); and the
@@ -139,14 +142,15 @@ def test_blocked_sweep_matches_the_per_step_sweep(lb, case):
         "window 16, shorter than a block": ([c0.replace(n_hist=16)], 16, 11),
         "two channels": ([c0, c1], 40, 23),
         "1x200, near ages from the ring": ([_wide_channel()], 64, 37),
+        "windows 16 and 64 in one handle": ([c0.replace(n_hist=16), c0], 16, 11),
     }[case]
     steps, every = 300, 25
-    say(f"case blocked vs per-step adjoint sweep, {case}")
+    say(f"case blocked vs per-step adjoint sweep, {case}, {precision}")
     target = np.concatenate([oracle_samples(c.replace(gx=0.8 * c.gx), steps, every)
                              for c in chans], axis=1)
 
     def grad(ablock, seg_len):
-        with lb.Solver(chans, precision="f64") as s:
+        with lb.Solver(chans, precision=precision) as s:
             s.set_adjoint_block(ablock)
             assert s.adjoint_block == ablock
             u, ckpts = adjoint.forward(s, steps, every, seg_len)
@@ -181,6 +185,44 @@ def test_blocked_sweep_forms_agree_bit_for_bit(lb):
     _, g_alone = gpu_gradient(lb, c0, "f64", steps, every, seg, targets[0])
     say(f"  beside 1x200 {g_mixed[0]}\n  alone        {g_alone}")
     assert np.array_equal(g_mixed[0], g_alone)
+
+
+def test_sweep_form_switched_between_segments(lb):
+    """The two forms hand the adjoint state (ring, dbar, fbar, accumulators)
+    from one segment to the next in the same layout: a sweep whose segments
+    alternate between the blocked and the per-step form gives the per-step
+    gradient up to the order of the FP64 history sums (1e-12)."""
+    import ctypes
+    import torch
+    from paper_1504_06123_amd import _lib, adjoint
+    ch = small_channel()
+    steps, every, seg = 300, 25, 40
+    say("case adjoint sweep, form switched between segments")
+    target = oracle_samples(ch.replace(gx=1.5e-5), steps, every)
+    _, per_step = gpu_gradient(lb, ch, "f64", steps, every, seg, target, adjoint_block=1)
+    P = ctypes.POINTER(ctypes.c_double)
+    with lb.Solver([ch], precision="f64") as s:
+        u, ckpts = adjoint.forward(s, steps, every, seg)
+        dL = 2 * (u - target)
+        rows = {t: dL[k] for k, t in enumerate(adjoint.sample_steps(steps, every))}
+        nbytes = s.lib.lb_adjoint_workspace_bytes(s.h, seg)
+        aws = torch.empty(int(nbytes), dtype=torch.uint8, device=s.device)
+        _lib.check(s.lib.lb_adjoint_begin(s.h, ctypes.c_void_p(aws.data_ptr()), int(nbytes),
+                                          seg), "lb_adjoint_begin")
+        for i, (t0, snap) in enumerate(reversed(ckpts)):
+            s.set_adjoint_block(32 if i % 2 == 0 else 1)
+            n = min(seg, steps - t0)
+            g = np.zeros((n, ch.ly))
+            for j in range(n):
+                if t0 + j in rows:
+                    g[j] = rows[t0 + j]
+            _lib.check(s.lib.lb_adjoint_segment(s.h, ctypes.c_void_p(snap.data_ptr()),
+                                                g.ctypes.data_as(P), n), "lb_adjoint_segment")
+        out = np.zeros((1, 4))
+        _lib.check(s.lib.lb_adjoint_end(s.h, out.ctypes.data_as(P)), "lb_adjoint_end")
+    rel = np.abs(out[0] - per_step) / np.abs(per_step)
+    say(f"  alternating {out[0]}\n  per-step    {per_step}\n  rel {rel.max():.2e}")
+    assert np.all(rel <= 1e-12), rel
 
 
 def test_adjoint_block_setting(lb):
