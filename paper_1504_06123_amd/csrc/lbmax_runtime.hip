@@ -1593,6 +1593,86 @@ lb_status lb_adjoint_begin_noalloc(lb_handle *h, int32_t seg_len)
     return adjoint_begin_at(h, static_cast<char *>(h->scratch), kScratchBytes, seg_len);
 }
 
+namespace {
+
+// lb_adjoint_segment after its dL/du_x upload is queued: the replay with
+// step records on, the copies the sweep reads, and the sweep on the adjoint
+// stream.  Returns without waiting for the upload (the caller does).
+lb_status adjoint_segment_rest(lb_handle *h, int buf, int64_t t0, int n_steps,
+                               size_t total_nodes)
+{
+    // Replay the segment on the handle's stream (beside the sweep of the
+    // later segment on the adjoint stream); its lattice steps record their
+    // input populations and stress into the step records.  The record
+    // fields of the device channel table are set and cleared on the stream;
+    // the host table keeps them at zero.
+    launch_set_record(h->d_chans, h->d_achans, h->n_ch, h->aws, buf, t0, h->stream);
+    lb_status s = check_launch(h, "adjoint record on");
+    if (s != LB_OK)
+        return s;
+    s = lb_step(h, n_steps);
+    launch_set_record(h->d_chans, h->d_achans, h->n_ch, nullptr, buf, 0, h->stream);
+    lb_status s2 = check_launch(h, "adjoint record off");
+    if (s != LB_OK)
+        return s;
+    if (s2 != LB_OK)
+        return s2;
+    // The segment's shear rates (ring rows t0 .. t0 + n_steps - 1, wrapping),
+    // dL/du_x spread over the channels' planes, and the channel table into
+    // the buffer, so the sweep reads nothing the next replay overwrites.
+    const size_t RH = history_bytes(h->prec);
+    size_t col = 0;
+    for (int ci = 0; ci < h->n_ch; ++ci) {
+        const ChanDev &c = h->plan.chans[ci];
+        const AdjChan &a = h->achans[ci];
+        const size_t rowb = (size_t)c.np * RH;
+        const int H = c.n_hist;
+        const int first = (int)(t0 % H);
+        const int run1 = std::min(n_steps, H - first);
+        HIP_TRY(h, hipMemcpyAsync(h->aws + a.off_recs[buf], h->ws + c.off_ring_s + first * rowb,
+                                  (size_t)run1 * rowb, hipMemcpyDeviceToDevice, h->stream));
+        if (run1 < n_steps)
+            HIP_TRY(h, hipMemcpyAsync(h->aws + a.off_recs[buf] + (size_t)run1 * rowb,
+                                      h->ws + c.off_ring_s, (size_t)(n_steps - run1) * rowb,
+                                      hipMemcpyDeviceToDevice, h->stream));
+        HIP_TRY(h, hipMemcpy2DAsync(h->aws + a.off_dldu[buf], (size_t)c.np * sizeof(double),
+                                    h->d_adj_stage[buf] + col, total_nodes * sizeof(double),
+                                    (size_t)c.n * sizeof(double), (size_t)n_steps,
+                                    hipMemcpyDeviceToDevice, h->stream));
+        col += (size_t)c.n;
+    }
+    ChanDev *snap = h->d_adj_snap + (size_t)buf * h->n_ch;
+    HIP_TRY(h, hipMemcpyAsync(snap, h->d_chans, (size_t)h->n_ch * sizeof(ChanDev),
+                              hipMemcpyDeviceToDevice, h->stream));
+    launch_store_i64(h->d_adj_t0 + buf, t0, h->stream);
+    s = check_launch(h, "adjoint segment start");
+    if (s != LB_OK)
+        return s;
+    HIP_TRY(h, hipEventRecord(h->adj_ev_replay, h->stream));
+    // Reverse sweep of the segment on the adjoint stream, after the replay:
+    // one captured graph per segment length and buffer, the segment's first
+    // step in device memory.
+    HIP_TRY(h, hipStreamWaitEvent(h->adj_stream, h->adj_ev_replay, 0));
+    if (n_steps <= kAdjGraphMaxSteps) {
+        hipGraphExec_t exec = nullptr;
+        s = adj_sweep_graph(h, n_steps, buf, &exec);
+        if (s != LB_OK)
+            return s;
+        HIP_TRY(h, hipGraphLaunch(exec, h->adj_stream));
+    } else {
+        // longer segments launch directly (a graph of 2 n_steps nodes would
+        // cost more to build than it saves)
+        s = enqueue_adj_sweep(h, n_steps, buf, h->adj_stream, true);
+        if (s != LB_OK)
+            return s;
+    }
+    HIP_TRY(h, hipEventRecord(h->adj_ev_sweep[buf], h->adj_stream));
+    h->adj_sweep_pending[buf] = true;
+    return LB_OK;
+}
+
+}  // namespace
+
 lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_dux,
                              int32_t n_steps)
 {
@@ -1631,81 +1711,24 @@ lb_status lb_adjoint_segment(lb_handle *h, const void *d_ckpt, const double *dL_
     HIP_TRY(h, hipMemcpyAsync(h->d_adj_stage[buf], dL_dux,
                               (size_t)n_steps * total_nodes * sizeof(double),
                               hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(h, hipEventRecord(h->adj_ev_input, h->stream));
-    const auto leave = [&](lb_status st) {
-        (void)hipEventSynchronize(h->adj_ev_input);
+    const hipError_t rec = hipEventRecord(h->adj_ev_input, h->stream);
+    if (rec != hipSuccess) {
+        (void)hipStreamSynchronize(h->stream);  // the copy may still read dL_dux
+        h->poisoned = true;
+        return fail(LB_EDEVICE, std::string("adjoint segment input event: ") +
+                                    hipGetErrorString(rec));
+    }
+    // The rest of the segment; on every way out of it, the caller's buffer
+    // is released only once its copy has finished.
+    const lb_status st = adjoint_segment_rest(h, buf, t0, n_steps, total_nodes);
+    const hipError_t w = hipEventSynchronize(h->adj_ev_input);
+    if (st != LB_OK)
         return st;
-    };
-    // Replay the segment on the handle's stream (beside the sweep of the
-    // later segment on the adjoint stream); its lattice steps record their
-    // input populations and stress into the step records.  The record
-    // fields of the device channel table are set and cleared on the stream;
-    // the host table keeps them at zero.
-    launch_set_record(h->d_chans, h->d_achans, h->n_ch, h->aws, buf, t0, h->stream);
-    s = check_launch(h, "adjoint record on");
-    if (s != LB_OK)
-        return leave(s);
-    s = lb_step(h, n_steps);
-    launch_set_record(h->d_chans, h->d_achans, h->n_ch, nullptr, buf, 0, h->stream);
-    lb_status s2 = check_launch(h, "adjoint record off");
-    if (s != LB_OK)
-        return leave(s);
-    if (s2 != LB_OK)
-        return leave(s2);
-    // The segment's shear rates (ring rows t0 .. t0 + n_steps - 1, wrapping),
-    // dL/du_x spread over the channels' planes, and the channel table into
-    // the buffer, so the sweep reads nothing the next replay overwrites.
-    const size_t RH = history_bytes(h->prec);
-    size_t col = 0;
-    for (int ci = 0; ci < h->n_ch; ++ci) {
-        const ChanDev &c = h->plan.chans[ci];
-        const AdjChan &a = h->achans[ci];
-        const size_t rowb = (size_t)c.np * RH;
-        const int H = c.n_hist;
-        const int first = (int)(t0 % H);
-        const int run1 = std::min(n_steps, H - first);
-        HIP_TRY(h, hipMemcpyAsync(h->aws + a.off_recs[buf], h->ws + c.off_ring_s + first * rowb,
-                                  (size_t)run1 * rowb, hipMemcpyDeviceToDevice, h->stream));
-        if (run1 < n_steps)
-            HIP_TRY(h, hipMemcpyAsync(h->aws + a.off_recs[buf] + (size_t)run1 * rowb,
-                                      h->ws + c.off_ring_s, (size_t)(n_steps - run1) * rowb,
-                                      hipMemcpyDeviceToDevice, h->stream));
-        HIP_TRY(h, hipMemcpy2DAsync(h->aws + a.off_dldu[buf], (size_t)c.np * sizeof(double),
-                                    h->d_adj_stage[buf] + col, total_nodes * sizeof(double),
-                                    (size_t)c.n * sizeof(double), (size_t)n_steps,
-                                    hipMemcpyDeviceToDevice, h->stream));
-        col += (size_t)c.n;
+    if (w != hipSuccess) {
+        h->poisoned = true;
+        return fail(LB_EDEVICE, std::string("adjoint segment input copy: ") +
+                                    hipGetErrorString(w));
     }
-    ChanDev *snap = h->d_adj_snap + (size_t)buf * h->n_ch;
-    HIP_TRY(h, hipMemcpyAsync(snap, h->d_chans, (size_t)h->n_ch * sizeof(ChanDev),
-                              hipMemcpyDeviceToDevice, h->stream));
-    launch_store_i64(h->d_adj_t0 + buf, t0, h->stream);
-    s = check_launch(h, "adjoint segment start");
-    if (s != LB_OK)
-        return leave(s);
-    HIP_TRY(h, hipEventRecord(h->adj_ev_replay, h->stream));
-    // Reverse sweep of the segment on the adjoint stream, after the replay:
-    // one captured graph per segment length and buffer, the segment's first
-    // step in device memory.
-    HIP_TRY(h, hipStreamWaitEvent(h->adj_stream, h->adj_ev_replay, 0));
-    if (n_steps <= kAdjGraphMaxSteps) {
-        hipGraphExec_t exec = nullptr;
-        s = adj_sweep_graph(h, n_steps, buf, &exec);
-        if (s != LB_OK)
-            return leave(s);
-        HIP_TRY(h, hipGraphLaunch(exec, h->adj_stream));
-    } else {
-        // longer segments launch directly (a graph of 2 n_steps nodes would
-        // cost more to build than it saves)
-        s = enqueue_adj_sweep(h, n_steps, buf, h->adj_stream, true);
-        if (s != LB_OK)
-            return leave(s);
-    }
-    HIP_TRY(h, hipEventRecord(h->adj_ev_sweep[buf], h->adj_stream));
-    h->adj_sweep_pending[buf] = true;
-    // The host buffer may be reused once this returns: wait for its copy
-    // (the replay and the sweep run on).
-    HIP_TRY(h, hipEventSynchronize(h->adj_ev_input));
     h->adj_next = t0;
     h->adj_segments += 1;
     return LB_OK;
