@@ -518,6 +518,47 @@ def test_ucm_startup_matches_the_modal_solution_at_second_order(twall_over_tau0)
     assert errs[0] / errs[1] > 3.5, errs
 
 
+@pytest.mark.parametrize("twall_over_tau0", [0.1, 1.0])
+def test_nonlinear_startup_departs_from_ucm_at_first_order_in_the_driving(twall_over_tau0):
+    """Eq. nlmax with gamma_c large against the shear the driving produces:
+    the damping adds |s'|/gamma_c to each entry's decay rate, a correction of
+    first order in the shear rate, so the startup flow departs from the UCM
+    flow (gamma_c = inf, linear in the force) by a relative amount
+    proportional to the driving -- halving the force halves it -- and, since
+    damping only removes stress, the nonlinear flow is nowhere slower.  A
+    dropped damping term gives no departure; a wrong sign, a slower flow; a
+    damping of the wrong order in s, another ratio."""
+    base = workloads.sec4_channel(twall_over_tau0, 10.0, "ucm", half_width=4)
+    eta = (base.tau_lb - 0.5) / 3.0
+    steps = int(round(6 * workloads.sec4_wall_time(4)))
+    every = max(1, steps // 60)
+    # the steady wall shear rate of the linear flow sets gamma_c: a departure
+    # of about 1e-3 to 1e-2, far above rounding and with second-order terms
+    # near 1e-5
+    s_wall = base.gx * 4 / (eta + base.g_inf * base.tau_m)
+    gamma_c = 100.0 * s_wall * base.tau_m
+
+    def run(ch):
+        oc = oracle.OracleChannel(ch)
+        us = []
+        for _ in range(steps // every):
+            oc.step(every)
+            us.append(oc.fields()[1][:, 0].copy())
+        oc.close()
+        return np.array(us)
+
+    ucm = run(base)
+    dev = []
+    for amp in (1.0, 0.5):
+        nlm = run(base.replace(gx=amp * base.gx, gamma_c=gamma_c))
+        lin = amp * ucm
+        scale = np.abs(lin).max()
+        dev.append(np.abs(nlm - lin).max() / scale)
+        assert (nlm - lin).min() >= -1e-12 * scale
+    assert dev[0] > 1e-4, dev
+    assert 1.95 < dev[0] / dev[1] < 2.05, dev
+
+
 @pytest.mark.parametrize("kw", [{}, {"finger": True}, {"law": "strain_damping"},
                                 {"paper_coupling": True}])
 def test_short_window_equals_long_window_before_it_fills(kw):
