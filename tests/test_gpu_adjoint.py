@@ -126,6 +126,8 @@ def _wide_channel():
     ("1x16, window 64", "f64"), ("window 16, shorter than a block", "f64"),
     ("two channels", "f64"), ("1x200, near ages from the ring", "f64"),
     ("windows 16 and 64 in one handle", "f64"), ("1x16, window 64", "f32"),
+    ("window 32, the near ages exactly", "f64"), ("window 33, one far age", "f64"),
+    ("1x1024, the widest blocked channel", "f64"),
 ])
 def test_blocked_sweep_matches_the_per_step_sweep(lb, case, precision):
     """The blocked reverse sweep (the default) against the per-step one: the
@@ -143,6 +145,11 @@ def test_blocked_sweep_matches_the_per_step_sweep(lb, case, precision):
         "two channels": ([c0, c1], 40, 23),
         "1x200, near ages from the ring": ([_wide_channel()], 64, 37),
         "windows 16 and 64 in one handle": ([c0.replace(n_hist=16), c0], 16, 11),
+        "window 32, the near ages exactly": ([c0.replace(n_hist=32)], 32, 19),
+        "window 33, one far age": ([c0.replace(n_hist=33)], 33, 20),
+        "1x1024, the widest blocked channel": (
+            [workloads.Channel(lx=1, ly=1024, tau_lb=1.0, g_inf=2e-3, tau_m=20.0, gamma_c=0.05,
+                               n_hist=40, gx=1e-7)], 40, 23),
     }[case]
     steps, every = 300, 25
     say(f"case blocked vs per-step adjoint sweep, {case}, {precision}")
