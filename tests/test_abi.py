@@ -145,6 +145,9 @@ def test_null_handle_calls(lib):
     assert lib.lb_set_fused(None, 1) == -1
     assert lib.lb_set_fused(None, 3) == -1
     assert lib.lb_get_fused(None) == 0
+    assert lib.lb_set_adjoint_block(None, 32) == -1
+    assert lib.lb_get_adjoint_block(None) == 0
+    assert lib.lb_adjoint_workspace_bytes(None, 64) == 0
 
 
 def test_state_layout_sections_are_aligned():
