@@ -439,7 +439,8 @@ lb_status lb_adjoint_end(lb_handle *h, double *dL_dtheta);
  * the block starts); one launch of one workgroup per channel then runs the
  * block's steps -- the near ages and the lattice part -- with workgroup
  * barriers where the per-step form has launch boundaries.  Applies when
- * every channel has at most 1024 nodes; otherwise the sweep runs per step.
+ * every channel has at most 512 nodes (wider, the per-step kernels are
+ * faster); otherwise the sweep runs per step.
  * The gradients of the blocked form do not depend on M or on the segment
  * lengths, bit for bit; they agree with the per-step form up to the order of
  * the FP64 history sums.  Takes effect at the next lb_adjoint_segment; a

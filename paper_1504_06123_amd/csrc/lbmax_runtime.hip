@@ -857,13 +857,14 @@ std::string adjoint_unsupported(const lb_handle *h, int seg_len)
 constexpr int kAdjGraphMaxSteps = 1024;
 
 // Reverse steps per blocked launch pair in effect: the setting where every
-// channel fits one workgroup of the span, else 1 (the per-step kernels).
+// channel has at most kAdjBlockedMaxNodes nodes, else 1 (the per-step
+// kernels).
 int adj_block_in_effect(const lb_handle *h)
 {
     if (h->adj_block <= 1)
         return 1;
     for (const ChanDev &c : h->plan.chans)
-        if (c.ly > kFuseThreads)
+        if (c.ly > kAdjBlockedMaxNodes)
             return 1;
     return h->adj_block;
 }

@@ -127,7 +127,7 @@ def _wide_channel():
     ("two channels", "f64"), ("1x200, near ages from the ring", "f64"),
     ("windows 16 and 64 in one handle", "f64"), ("1x16, window 64", "f32"),
     ("window 32, the near ages exactly", "f64"), ("window 33, one far age", "f64"),
-    ("1x1024, the widest blocked channel", "f64"),
+    ("1x512, the widest blocked channel", "f64"),
 ])
 def test_blocked_sweep_matches_the_per_step_sweep(lb, case, precision):
     """The blocked reverse sweep (the default) against the per-step one: the
@@ -147,8 +147,8 @@ def test_blocked_sweep_matches_the_per_step_sweep(lb, case, precision):
         "windows 16 and 64 in one handle": ([c0.replace(n_hist=16), c0], 16, 11),
         "window 32, the near ages exactly": ([c0.replace(n_hist=32)], 32, 19),
         "window 33, one far age": ([c0.replace(n_hist=33)], 33, 20),
-        "1x1024, the widest blocked channel": (
-            [workloads.Channel(lx=1, ly=1024, tau_lb=1.0, g_inf=2e-3, tau_m=20.0, gamma_c=0.05,
+        "1x512, the widest blocked channel": (
+            [workloads.Channel(lx=1, ly=512, tau_lb=1.0, g_inf=2e-3, tau_m=20.0, gamma_c=0.05,
                                n_hist=40, gx=1e-7)], 40, 23),
     }[case]
     steps, every = 300, 25
@@ -234,7 +234,7 @@ def test_sweep_form_switched_between_segments(lb):
 
 def test_adjoint_block_setting(lb):
     """lb_set_adjoint_block takes 1 .. 32 and refuses the rest; channels
-    wider than 1024 nodes sweep per step whatever the setting."""
+    wider than 512 nodes sweep per step whatever the setting."""
     from paper_1504_06123_amd import _lib
     say("case adjoint block setting")
     with lb.Solver([small_channel()], precision="f64") as s:
@@ -245,11 +245,12 @@ def test_adjoint_block_setting(lb):
         assert s.adjoint_block == 32
         s.set_adjoint_block(5)
         assert s.adjoint_block == 5
-    wide = workloads.Channel(lx=1, ly=1100, tau_lb=1.0, g_inf=1e-3, tau_m=10.0, gamma_c=0.1,
-                             n_hist=30, gx=1e-8)
-    with lb.Solver([small_channel(), wide], precision="f64") as s:
-        s.set_adjoint_block(32)
-        assert s.adjoint_block == 1
+    for ly, form in ((512, 32), (513, 1), (1100, 1)):
+        wide = workloads.Channel(lx=1, ly=ly, tau_lb=1.0, g_inf=1e-3, tau_m=10.0, gamma_c=0.1,
+                                 n_hist=30, gx=1e-8)
+        with lb.Solver([small_channel(), wide], precision="f64") as s:
+            s.set_adjoint_block(32)
+            assert s.adjoint_block == form, (ly, s.adjoint_block)
 
 
 def test_adjoint_dot_product_above_1024_nodes(lb):
