@@ -313,8 +313,11 @@ int32_t lb_get_block(const lb_handle *h);
  * split storage once per node and step), velocity and stress in LDS and the
  * history rows pushed since the pass in registers (the stencils then read no
  * global memory).  mode: 0
- * separate launches, 1 fused (the LDS form where it applies; the default), 2
- * fused without the LDS form.  Results are identical in every mode.
+ * separate launches, 1 fused (the default: the LDS form where it applies,
+ * else the global-memory form when every channel has at most 512 nodes;
+ * wider, that form is slower than separate launches and the steps run
+ * separately), 2 fused without the LDS form whenever the channels fit.
+ * Results are identical in every mode.
  * lb_get_fused returns 0 when the steps are not fused (mode 0, a channel
  * that does not qualify, or blocks of one step), 1 for the fused launch, 2
  * for its LDS form.  Takes effect at the next lb_step.  For lb_kernel_time a

@@ -13,6 +13,11 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kWave = 64;          // threads per wavefront
 constexpr int kFuseThreads = 1024; // workgroup of the fused in-block steps
 constexpr int kFuseMaxNodes = 1024; // channels up to this size take them
+// Widest channel for which the default takes the global-memory fused form
+// (not the LDS one): FP64 populations, 1 x N channels, N_h 2048, 32-step
+// blocks measured 9.0 against 10.2 us per step unfused at 512 nodes, 11.8
+// against 10.4 at 1024.
+constexpr int kFuseGlobalMaxNodes = 512;
 constexpr int kNodeAlign = 64;     // node-plane stride is a multiple of this
 constexpr int kMinChunkLen = 128;  // shortest age range of one history chunk
 constexpr int kMaxChunks = 64;     // most age ranges per channel

@@ -322,6 +322,7 @@ struct lb_handle {
     bool any_grid = false, any_window = false;  // channels on the grid / the uniform window
     bool fuse_ok = false;      // every channel fits the fused in-block steps
     bool fuse_lds_ok = false;  // ... and takes the LDS-resident form
+    bool fuse_global_ok = false;  // ... and is narrow enough for the global-memory form to pay
     bool fuse_lds_ready = false;  // its dynamic LDS size is allowed
     int fuse_mode = 1;         // lb_set_fused
     // host mirrors kept alive for asynchronous uploads
@@ -474,9 +475,12 @@ void build_tiles(lb_handle *h)
     h->n_hist_tiles = (int)h->hist_tiles.size();
     h->fuse_ok = !h->any_grid && !h->any_inst;
     h->fuse_lds_ok = h->fuse_ok;
+    h->fuse_global_ok = h->fuse_ok;
     for (const ChanDev &c : h->plan.chans) {
         if (c.n > kFuseMaxNodes)
             h->fuse_ok = h->fuse_lds_ok = false;
+        if (c.n > kFuseGlobalMaxNodes)
+            h->fuse_global_ok = false;
         if (c.law != 0 || c.finger || c.coupling || c.has_r)
             h->fuse_lds_ok = false;
     }
@@ -611,13 +615,25 @@ lb_status enqueue_step(lb_handle *h, hipStream_t st, int trel, int m, bool timed
     return check_launch(h, "step launch");
 }
 
+// The in-block steps run fused: mode 2 whenever the channels fit a
+// workgroup; mode 1 (the default) in the LDS form where it applies, else in
+// the global-memory form only up to kFuseGlobalMaxNodes nodes per channel.
+bool fused_in_effect(const lb_handle *h)
+{
+    if (!h->fuse_ok || h->fuse_mode == 0 || h->block <= 1)
+        return false;
+    if (h->fuse_mode == 2)
+        return true;
+    return (h->fuse_lds_ok && h->fuse_lds_ready) || h->fuse_global_ok;
+}
+
 // Enqueue up to `left` steps starting at block position m: a fused launch
 // for the rest of the block when the handle allows it and m > 0, else one
 // step.  Sets *done to the steps enqueued.
 lb_status enqueue_span(lb_handle *h, hipStream_t st, int trel, int m, int64_t left, bool timed,
                        int *done)
 {
-    if (h->fuse_ok && h->fuse_mode != 0 && h->block > 1 && m > 0) {
+    if (fused_in_effect(h) && m > 0) {
         const int k = (int)std::min<int64_t>(left, h->block - m);
         hipEvent_t e[2] = {nullptr, nullptr};
         if (timed) {
@@ -1427,7 +1443,7 @@ int32_t lb_get_adjoint_block(const lb_handle *h)
 
 int32_t lb_get_fused(const lb_handle *h)
 {
-    if (!h || !h->fuse_ok || h->fuse_mode == 0 || h->block <= 1)
+    if (!h || !fused_in_effect(h))
         return 0;
     return (h->fuse_mode == 1 && h->fuse_lds_ok && h->fuse_lds_ready) ? 2 : 1;
 }

@@ -42,12 +42,15 @@ def _same(a, b):
 @pytest.mark.parametrize("precision", ["f64", "f32p64", "f32"])
 @pytest.mark.parametrize("block", [2, 8, 32])
 def test_fused_equals_separate_launches_batched(Solver, precision, block):
-    """Separate launches, the fused launch, and (LB_F32) its LDS form."""
+    """Separate launches, the fused launch, and (LB_F32) its LDS form.  With
+    FP64 populations the default (mode 1) runs these channels -- three are
+    wider than 512 nodes -- in separate launches; mode 2 forces the
+    global-memory fused form."""
     chans = workloads.batched().channels[:12]
     say(f"case fused batched 12 channels {precision} block {block}")
     a = _run(Solver, chans, precision, block, 0, 203, want=0)
     b = _run(Solver, chans, precision, block, 2, 203, want=1)
-    c = _run(Solver, chans, precision, block, 1, 203, want=2 if precision == "f32" else 1)
+    c = _run(Solver, chans, precision, block, 1, 203, want=2 if precision == "f32" else 0)
     _same(a, b)
     _same(a, c)
 
@@ -56,8 +59,9 @@ def test_fused_equals_separate_launches_batched(Solver, precision, block):
 def test_fused_lds_form_short_windows_and_limits(Solver, block):
     """The LDS form (unidirectional channels) with a window shorter than the
     block, a chunked window and a channel at the 1024-node limit; 2D channels
-    of the same sizes take the global-memory fused form.  Both equal the
-    separate launches bit for bit."""
+    of the same sizes take the global-memory fused form (mode 2: by default
+    it runs only up to 512 nodes per channel).  Both equal the separate
+    launches bit for bit."""
     def uni(ly, n_hist, tau_m):
         return workloads.plain_f64().channels[0].replace(lx=1, ly=ly, n_hist=n_hist,
                                                          tau_m=tau_m, gx=2e-5)
@@ -65,18 +69,18 @@ def test_fused_lds_form_short_windows_and_limits(Solver, block):
     def twod(lx, ly, n_hist, tau_m):
         return workloads.large_2d(lx=lx, ly=ly, n_hist=n_hist).channels[0].replace(tau_m=tau_m)
 
-    for kind, chans, want in (
+    for kind, chans, fused_mode, want in (
             ("unidirectional", [uni(16, 300, 20.0),
                                 uni(13, 3, 15.0),       # window shorter than the block
                                 uni(1024, 64, 30.0),    # 1024 nodes
-                                uni(40, 2000, 100.0)], 2),
+                                uni(40, 2000, 100.0)], 1, 2),
             ("2D", [twod(8, 16, 300, 20.0),
                     twod(5, 13, 3, 15.0),
                     twod(32, 32, 64, 30.0),
-                    uni(40, 2000, 100.0)], 1)):
+                    uni(40, 2000, 100.0)], 2, 1)):
         say(f"case fused form, {kind} channels, f32 block {block}")
         runs = []
-        for mode in (1, 0):
+        for mode in (fused_mode, 0):
             with Solver(chans, precision="f32") as s:
                 s.set_tiling(3, 4)     # the long window split into 4 age chunks
                 s.set_block(block)
@@ -147,6 +151,18 @@ def test_fused_only_when_every_channel_fits(Solver):
             assert s.fused == min(want, 1)
             s.set_fused(0)
             assert s.fused == 0
+    # FP64 populations above 512 nodes: separate launches by default (the
+    # global-memory fused form is slower there), fused on request
+    wide_uni = small.replace(ly=600)
+    for prec in ("f32p64", "f64"):
+        with Solver([small, wide_uni], precision=prec) as s:
+            s.set_block(8)
+            assert s.fused == 0
+            s.set_fused(2)
+            assert s.fused == 1
+    with Solver([small, wide_uni], precision="f32") as s:
+        s.set_block(8)
+        assert s.fused == 2
 
 
 def test_fused_set_params_and_force_mid_block(Solver):
