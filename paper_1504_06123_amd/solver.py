@@ -143,8 +143,10 @@ class Solver:
 
     def set_fused(self, mode=1):
         """Fused in-block steps for handles whose channels all fit one
-        workgroup: 0 (or False) separate launches, 1 (or True) fused with the
-        LDS-resident form where it applies, 2 fused without it."""
+        workgroup: 0 (or False) separate launches, 1 (or True, the default)
+        fused with the LDS-resident form where it applies, else in the
+        global-memory form up to 512 nodes per channel, 2 fused in the
+        global-memory form; see lb_set_fused."""
         _lib.check(self.lib.lb_set_fused(self.h, int(mode)), "lb_set_fused")
 
     def set_adjoint_block(self, steps: int):
